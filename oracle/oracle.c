@@ -1,0 +1,469 @@
+/*
+ * CPU oracle for the adaptive ray-tracing radiative-transfer hot path
+ * (De Ceuster et al., "Magritte II", arXiv 2011.14998).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * FP64 reference that the HIP library is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no code, header, table or constant generator with the HIP
+ * library.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * No FMA contraction, no fast-math: every floating-point operation below is a
+ * single IEEE-754 double operation, evaluated in the order written.
+ *
+ * What is computed, step by step, with the passage each step follows:
+ *   HEALPix ring-scheme pixel centres and pixel lookup, 12*4^l pixels of equal
+ *       area at level l (Section 2.1.3; Gorski et al. 2005 for the scheme).
+ *   Uniform direction set: antipodal pairs of level-l pixels (Section 2.1.3:
+ *       rays come in antipodal pairs), weight w = 1/(12*4^l) per ray (eq. 4).
+ *   Adaptive direction set (Section 2.1.3, Fig. 1): per origin, histogram the
+ *       directions to a sample of points at l_max, downgrade through the
+ *       hierarchy, refine the top half of the pairs per level.
+ *   Ray tracing (Section 2.1, Fig. 2): step from point to point along a
+ *       straight line; each step goes to the forward neighbour closest to the
+ *       ray axis; the distance increment is the projection of the edge.
+ *   Line assembly, Doppler-shifted optics, optical depth (Section 2.1.1 for the
+ *       velocity, eq. 1 for S and tau).
+ *   Second-order Feautrier equation (eq. 1) with second-order boundary
+ *       conditions (Section 2.1), solved for u at the origin by a two-sided
+ *       rescaled elimination.
+ *   Mean intensity J = sum over rays of w*u (eq. 3, eq. 4).
+ *
+ * Readings of what the paper leaves unstated are documented next to each step
+ * (boundary intensity, quadrature of tau, elimination form, tie rules).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_API __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------ HEALPix */
+
+static int64_t isqrt64(int64_t v) {
+    int64_t r = (int64_t)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+OR_API int64_t or_hp_npix(int64_t nside) { return 12 * nside * nside; }
+
+/* Ring index (1 .. 4*nside-1) of pixel p, and the z/phi of its centre. */
+static void hp_ring_centre(int64_t nside, int64_t p, int64_t* ring, double* z, double* phi) {
+    const int64_t npix = 12 * nside * nside;
+    const int64_t ncap = 2 * nside * (nside - 1);
+    if (p < ncap) {                       /* north polar cap */
+        int64_t i = (1 + isqrt64(1 + 2 * p)) >> 1;
+        int64_t j = p + 1 - 2 * i * (i - 1); /* 1 .. 4i */
+        *ring = i;
+        *z = 1.0 - (double)(i * i) / (double)(3 * nside * nside);
+        *phi = (double)(2 * j - 1) * M_PI / (double)(4 * i);
+    } else if (p < npix - ncap) {         /* equatorial belt */
+        int64_t q = p - ncap;
+        int64_t i = q / (4 * nside) + nside;
+        int64_t k = q % (4 * nside);      /* 0 .. 4nside-1 */
+        int64_t s = (i - nside + 1) & 1;
+        *ring = i;
+        *z = (double)(2 * (2 * nside - i)) / (double)(3 * nside);
+        *phi = (double)(2 * k + s) * M_PI / (double)(4 * nside);
+    } else {                              /* south polar cap */
+        int64_t q = npix - p;
+        int64_t i = (1 + isqrt64(2 * q - 1)) >> 1;
+        int64_t j = 4 * i + 1 - (q - 2 * i * (i - 1));
+        *ring = 4 * nside - i;
+        *z = -(1.0 - (double)(i * i) / (double)(3 * nside * nside));
+        *phi = (double)(2 * j - 1) * M_PI / (double)(4 * i);
+    }
+}
+
+/* Unit vector of the centre of ring-scheme pixel p at resolution nside. */
+OR_API void or_hp_pix2vec(int64_t nside, int64_t p, double* v) {
+    int64_t ring;
+    double z, phi;
+    hp_ring_centre(nside, p, &ring, &z, &phi);
+    double st = sqrt((1.0 - z) * (1.0 + z));
+    v[0] = st * cos(phi);
+    v[1] = st * sin(phi);
+    v[2] = z;
+}
+
+OR_API int64_t or_hp_ring_of(int64_t nside, int64_t p) {
+    int64_t ring;
+    double z, phi;
+    hp_ring_centre(nside, p, &ring, &z, &phi);
+    return ring;
+}
+
+/* Pixel lookup from (z, phi), phi in [0, 2 pi). */
+static int64_t hp_zphi2pix(int64_t nside, double z, double phi) {
+    const int64_t npix = 12 * nside * nside;
+    const int64_t ncap = 2 * nside * (nside - 1);
+    double za = fabs(z);
+    double tt = phi / (0.5 * M_PI);       /* [0, 4) */
+    if (tt >= 4.0) tt = 0.0;
+    if (za <= 2.0 / 3.0) {
+        double t1 = (double)nside * (0.5 + tt);
+        double t2 = (double)nside * z * 0.75;
+        int64_t jp = (int64_t)floor(t1 - t2);
+        int64_t jm = (int64_t)floor(t1 + t2);
+        int64_t ir = nside + 1 + jp - jm;          /* 1 .. 2nside+1 */
+        int64_t kshift = 1 - (ir & 1);
+        int64_t ip = (jp + jm - nside + kshift + 1) / 2;
+        ip = ((ip % (4 * nside)) + 4 * nside) % (4 * nside);
+        return ncap + (ir - 1) * 4 * nside + ip;
+    } else {
+        double tp = tt - floor(tt);
+        double tmp = (double)nside * sqrt(3.0 * (1.0 - za));
+        int64_t jp = (int64_t)floor(tp * tmp);
+        int64_t jm = (int64_t)floor((1.0 - tp) * tmp);
+        int64_t ir = jp + jm + 1;
+        int64_t ip = (int64_t)floor(tt * (double)ir);
+        ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
+        if (z > 0.0) return 2 * ir * (ir - 1) + ip;
+        return npix - 2 * ir * (ir + 1) + ip;
+    }
+}
+
+/* Pixel containing the direction of v (need not be normalised; v != 0).
+ * Uses the C library's atan2 for the azimuth. */
+OR_API int64_t or_hp_vec2pix(int64_t nside, const double* v) {
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double z = v[2] / r;
+    double phi = atan2(v[1], v[0]);
+    if (phi < 0.0) phi += 2.0 * M_PI;
+    return hp_zphi2pix(nside, z, phi);
+}
+
+/* Antipodal pixel: the pixel containing minus the centre of p. */
+static int64_t hp_antipode(int64_t nside, int64_t p) {
+    double v[3];
+    or_hp_pix2vec(nside, p, v);
+    v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2];
+    return or_hp_vec2pix(nside, v);
+}
+
+OR_API int64_t or_hp_antipode(int64_t nside, int64_t p) { return hp_antipode(nside, p); }
+
+/* Parent at nside/2 in the nested hierarchy: the coarse pixel containing the
+ * centre of p (each coarse pixel is the union of its 4 children). */
+OR_API int64_t or_hp_parent(int64_t nside, int64_t p) {
+    double v[3];
+    or_hp_pix2vec(nside, p, v);
+    return or_hp_vec2pix(nside / 2, v);
+}
+
+/* ---------------------------------------------------------- direction sets */
+
+/* Uniform set at resolution nside: every antipodal pair of pixels once, the
+ * member with the smaller ring-scheme index being canonical; pairs ascending
+ * in that index.  Ray direction of pair r is the centre of its canonical
+ * pixel; the partner ray is its exact negation.  w2[r] = 2 w, w = 1/(12 nside^2)
+ * (eq. 4, the pair carries both rays).  Returns the number of pairs. */
+OR_API int64_t or_dirset_uniform(int64_t nside, int64_t* pix, double* dirs, double* w2) {
+    int64_t npix = 12 * nside * nside, R = 0;
+    for (int64_t p = 0; p < npix; ++p) {
+        if (hp_antipode(nside, p) <= p) continue;
+        if (pix) pix[R] = p;
+        if (dirs) or_hp_pix2vec(nside, p, dirs + 3 * R);
+        if (w2) w2[R] = 2.0 / (double)npix;
+        ++R;
+    }
+    return R;
+}
+
+/* ---------------------------------------------------------------- tracing */
+
+/* Trace one ray from `origin` along unit direction d (Section 2.1, Fig. 2).
+ * From the current point c with projection Zc, every neighbour k with
+ *     Z_k = (R.x d.x + R.y d.y) + R.z d.z,  R = x_k - x_origin,
+ * strictly greater than Zc is a forward candidate; its squared distance to
+ * the ray axis is D_k = (q.x^2 + q.y^2) + q.z^2 with q = R - Z_k d.  The ray
+ * steps to the candidate of least D_k (equal D: smaller point id), records
+ * (k, Z_k), and continues from k with Zc = Z_k.  It ends where no neighbour
+ * is forward.  The origin is not recorded.  Returns the number of points;
+ * writes at most `cap` of them. */
+OR_API int64_t or_trace_ray(const double* pos, const int64_t* off, const int32_t* idx, int64_t P,
+                            int64_t origin, const double* d, int32_t* ids, double* Z, int64_t cap) {
+    const double ox = pos[3 * origin], oy = pos[3 * origin + 1], oz = pos[3 * origin + 2];
+    int64_t c = origin, n = 0;
+    double Zc = 0.0;
+    for (int64_t step = 0; step < P; ++step) {
+        int64_t best = -1;
+        double bestD = 0.0, bestZ = 0.0;
+        for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+            int64_t k = idx[e];
+            double Rx = pos[3 * k] - ox, Ry = pos[3 * k + 1] - oy, Rz = pos[3 * k + 2] - oz;
+            double Zk = (Rx * d[0] + Ry * d[1]) + Rz * d[2];
+            if (!(Zk > Zc)) continue;
+            double qx = Rx - Zk * d[0], qy = Ry - Zk * d[1], qz = Rz - Zk * d[2];
+            double Dk = (qx * qx + qy * qy) + qz * qz;
+            if (best < 0 || Dk < bestD || (Dk == bestD && k < best)) {
+                best = k; bestD = Dk; bestZ = Zk;
+            }
+        }
+        if (best < 0) break;
+        if (n < cap) { ids[n] = (int32_t)best; Z[n] = bestZ; }
+        ++n;
+        c = best;
+        Zc = bestZ;
+    }
+    return n;
+}
+
+/* Trace every ray of every listed origin.  Ray slot s = o*2R + 2r (+n_r) or
+ * 2r+1 (-n_r), o the position in `origins`.  ray_off[s+1]-ray_off[s] is the
+ * ray's length; lists are concatenated in slot order.  If ids/Z are NULL only
+ * ray_off is written.  Returns the total number of entries. */
+OR_API int64_t or_trace_all(const double* pos, const int64_t* off, const int32_t* idx, int64_t P,
+                            int64_t R, const double* dirs, int32_t per_origin_dirs,
+                            const int32_t* origins, int64_t n_origins,
+                            int64_t* ray_off, int32_t* ids, double* Z, int nthreads) {
+    const int64_t nr = n_origins * 2 * R;
+    int64_t* len = (int64_t*)calloc((size_t)nr, sizeof(int64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t o = 0; o < n_origins; ++o) {
+        const double* dv = per_origin_dirs ? dirs + 3 * R * o : dirs;
+        for (int64_t r = 0; r < R; ++r) {
+            double dp[3] = {dv[3 * r], dv[3 * r + 1], dv[3 * r + 2]};
+            double dm[3] = {-dp[0], -dp[1], -dp[2]};
+            len[o * 2 * R + 2 * r] = or_trace_ray(pos, off, idx, P, origins[o], dp, NULL, NULL, 0);
+            len[o * 2 * R + 2 * r + 1] = or_trace_ray(pos, off, idx, P, origins[o], dm, NULL, NULL, 0);
+        }
+    }
+    ray_off[0] = 0;
+    for (int64_t s = 0; s < nr; ++s) ray_off[s + 1] = ray_off[s] + len[s];
+    free(len);
+    if (ids && Z) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+        for (int64_t o = 0; o < n_origins; ++o) {
+            const double* dv = per_origin_dirs ? dirs + 3 * R * o : dirs;
+            for (int64_t r = 0; r < R; ++r) {
+                double dp[3] = {dv[3 * r], dv[3 * r + 1], dv[3 * r + 2]};
+                double dm[3] = {-dp[0], -dp[1], -dp[2]};
+                int64_t sp = o * 2 * R + 2 * r, sm = sp + 1;
+                or_trace_ray(pos, off, idx, P, origins[o], dp, ids + ray_off[sp], Z + ray_off[sp],
+                             ray_off[sp + 1] - ray_off[sp]);
+                or_trace_ray(pos, off, idx, P, origins[o], dm, ids + ray_off[sm], Z + ray_off[sm],
+                             ray_off[sm + 1] - ray_off[sm]);
+            }
+        }
+    }
+    return ray_off[nr];
+}
+
+/* --------------------------------------------------------- Feautrier solve */
+
+/* u at row m of the discrete second-order Feautrier system (eq. 1) on a line
+ * of N points with optical-depth increments dtau[0..N-2] and source S[0..N-1].
+ *
+ * Interior rows 0<d<N-1 (three-point second difference on a non-uniform grid):
+ *   -A_d u_{d-1} + (1 + A_d + C_d) u_d - C_d u_{d+1} = S_d,
+ *   A_d = 2/(dtau_{d-1}(dtau_{d-1}+dtau_d)),  C_d = 2/(dtau_d(dtau_{d-1}+dtau_d)).
+ * Boundary rows (second order, incoming intensity I at both ends):
+ *   (1 + 2/dt + 2/dt^2) u_0 - (2/dt^2) u_1 = S_0 + 2 I/dt,  dt = dtau_0, and the mirror
+ *   image at d = N-1 with dt = dtau_{N-2}.
+ * The system is eliminated from both ends towards m in the rescaled form
+ * u_{d} = u_{d+1}/(1+F_d) + Z_d (forward) and u_d = u_{d-1}/(1+G_d) + W_d
+ * (backward), where every F, G, Z, W is a sum and quotient of positive terms,
+ * so no cancellation occurs for small dtau.  N == 1 returns I. */
+OR_API double or_feautrier_u(int64_t N, int64_t m, const double* dtau, const double* S, double I) {
+    if (N == 1) return I;
+    double F = 0.0, Zf = 0.0, G = 0.0, W = 0.0;
+    /* forward sweep over rows 0 .. m-1 */
+    for (int64_t d = 0; d < m; ++d) {
+        if (d == 0) {
+            double dt = dtau[0];
+            double C0 = 2.0 / (dt * dt);
+            F = dt * (1.0 + 0.5 * dt);
+            Zf = (S[0] + 2.0 * I / dt) / (C0 * (1.0 + F));
+        } else {
+            double a = dtau[d - 1], b = dtau[d];
+            double A = 2.0 / (a * (a + b)), C = 2.0 / (b * (a + b));
+            double Fn = (1.0 + A * F / (1.0 + F)) / C;
+            Zf = (S[d] + A * Zf) / (C * (1.0 + Fn));
+            F = Fn;
+        }
+    }
+    /* backward sweep over rows N-1 .. m+1 */
+    for (int64_t d = N - 1; d > m; --d) {
+        if (d == N - 1) {
+            double dt = dtau[N - 2];
+            double AN = 2.0 / (dt * dt);
+            G = dt * (1.0 + 0.5 * dt);
+            W = (S[N - 1] + 2.0 * I / dt) / (AN * (1.0 + G));
+        } else {
+            double a = dtau[d - 1], b = dtau[d];
+            double A = 2.0 / (a * (a + b)), C = 2.0 / (b * (a + b));
+            double Gn = (1.0 + C * G / (1.0 + G)) / A;
+            W = (S[d] + C * W) / (A * (1.0 + Gn));
+            G = Gn;
+        }
+    }
+    if (m == 0) {
+        double dt = dtau[0];
+        double C0 = 2.0 / (dt * dt);
+        return (S[0] + 2.0 * I / dt + C0 * W) / (1.0 + 2.0 / dt + C0 * G / (1.0 + G));
+    }
+    if (m == N - 1) {
+        double dt = dtau[N - 2];
+        double AN = 2.0 / (dt * dt);
+        return (S[N - 1] + 2.0 * I / dt + AN * Zf) / (1.0 + 2.0 / dt + AN * F / (1.0 + F));
+    }
+    double a = dtau[m - 1], b = dtau[m];
+    double A = 2.0 / (a * (a + b)), C = 2.0 / (b * (a + b));
+    return (S[m] + A * Zf + C * W) / (1.0 + A * F / (1.0 + F) + C * G / (1.0 + G));
+}
+
+/* ------------------------------------------------------- full J at origins */
+
+typedef struct {
+    int64_t cap;
+    int32_t* idm; double* Zm;   /* backward ray (-n) */
+    int32_t* idp; double* Zp;   /* forward ray  (+n) */
+    int32_t* q;   double* s;    /* assembled line */
+    double* dtau; double* S; double* chi; double* eta;
+    int64_t* k; double* t;
+} or_ws;
+
+static void ws_grow(or_ws* w, int64_t n) {
+    if (n <= w->cap) return;
+    int64_t c = n * 2;
+    w->idm = realloc(w->idm, c * sizeof(int32_t)); w->Zm = realloc(w->Zm, c * sizeof(double));
+    w->idp = realloc(w->idp, c * sizeof(int32_t)); w->Zp = realloc(w->Zp, c * sizeof(double));
+    w->q = realloc(w->q, (2 * c + 1) * sizeof(int32_t)); w->s = realloc(w->s, (2 * c + 1) * sizeof(double));
+    w->dtau = realloc(w->dtau, (2 * c + 1) * sizeof(double)); w->S = realloc(w->S, (2 * c + 1) * sizeof(double));
+    w->chi = realloc(w->chi, (2 * c + 1) * sizeof(double)); w->eta = realloc(w->eta, (2 * c + 1) * sizeof(double));
+    w->k = realloc(w->k, (2 * c + 1) * sizeof(int64_t)); w->t = realloc(w->t, (2 * c + 1) * sizeof(double));
+    w->cap = c;
+}
+
+static void ws_free(or_ws* w) {
+    free(w->idm); free(w->Zm); free(w->idp); free(w->Zp); free(w->q); free(w->s);
+    free(w->dtau); free(w->S); free(w->chi); free(w->eta); free(w->k); free(w->t);
+}
+
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* J[o][f] at every listed origin (eq. 3, eq. 4).
+ *
+ * For each antipodal pair r (direction n_r and its negation) the two rays
+ * are traced, the line is assembled as reverse(backward list), origin,
+ * forward list, with coordinate s = (-Z_back reversed, 0, Z_fwd) and
+ * ds_d = s_{d+1} - s_d.  Optics in the comoving frame of the origin along
+ * +n_r (Section 2.1.1): the shift of line point q in block b is
+ *     delta_q = (n_r . (v_q - v_o)) / dx_b,  k = floor(delta_q), t = delta_q - k,
+ *     chi'_q[f] = (1-t) chi_q[clamp(f-k)] + t chi_q[clamp(f-k-1)]
+ * with indices clamped to the block; eta the same; S = eta'/chi'.  The
+ * optical-depth increment is the trapezoid dtau_d = (0.5 (chi'_d + chi'_{d+1})) ds_d.
+ * u at the origin comes from or_feautrier_u; J accumulates w2[r] u in ascending r.
+ *
+ * dirs: [R][3] shared, or [n_origins][R][3] when per_origin_dirs; w2 likewise.
+ * vel may be NULL (static).  u_out, if not NULL, receives u[o][r][f]. */
+OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const int32_t* idx,
+                        const float* vel, int64_t F, int32_t nblk, const int32_t* blk_len,
+                        const double* blk_dx, const double* chi, const double* eta, int64_t ld,
+                        const double* I_bc, int64_t R, const double* dirs, const double* w2,
+                        int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
+                        double* J, double* u_out, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int err = 0;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        or_ws w;
+        memset(&w, 0, sizeof(w));
+        ws_grow(&w, 256);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t oi = 0; oi < n_origins; ++oi) {
+            const int64_t o = origins[oi];
+            const double* dv = per_origin_dirs ? dirs + 3 * R * oi : dirs;
+            const double* wv = per_origin_dirs ? w2 + R * oi : w2;
+            double* Jo = J + oi * F;
+            for (int64_t f = 0; f < F; ++f) Jo[f] = 0.0;
+            for (int64_t r = 0; r < R; ++r) {
+                double dp[3] = {dv[3 * r], dv[3 * r + 1], dv[3 * r + 2]};
+                double dm[3] = {-dp[0], -dp[1], -dp[2]};
+                int64_t np_, nm;
+                for (;;) {
+                    np_ = or_trace_ray(pos, off, idx, P, o, dp, w.idp, w.Zp, w.cap);
+                    nm = or_trace_ray(pos, off, idx, P, o, dm, w.idm, w.Zm, w.cap);
+                    if (np_ <= w.cap && nm <= w.cap) break;
+                    ws_grow(&w, (np_ > nm ? np_ : nm));
+                }
+                /* line assembly */
+                const int64_t N = nm + 1 + np_, m = nm;
+                for (int64_t j = 0; j < nm; ++j) {
+                    w.q[j] = w.idm[nm - 1 - j];
+                    w.s[j] = -w.Zm[nm - 1 - j];
+                }
+                w.q[m] = (int32_t)o;
+                w.s[m] = 0.0;
+                for (int64_t j = 0; j < np_; ++j) {
+                    w.q[m + 1 + j] = w.idp[j];
+                    w.s[m + 1 + j] = w.Zp[j];
+                }
+                int64_t fb = 0;
+                for (int32_t b = 0; b < nblk; ++b) {
+                    const int64_t L = blk_len[b];
+                    /* per-point Doppler shift in this block's index units */
+                    for (int64_t d = 0; d < N; ++d) {
+                        if (vel) {
+                            const float* vq = vel + 3 * (int64_t)w.q[d];
+                            const float* vo = vel + 3 * o;
+                            double dvx = (double)vq[0] - (double)vo[0];
+                            double dvy = (double)vq[1] - (double)vo[1];
+                            double dvz = (double)vq[2] - (double)vo[2];
+                            double delta = ((dp[0] * dvx + dp[1] * dvy) + dp[2] * dvz) / blk_dx[b];
+                            double fl = floor(delta);
+                            w.k[d] = (int64_t)fl;
+                            w.t[d] = delta - fl;
+                        } else {
+                            w.k[d] = 0;
+                            w.t[d] = 0.0;
+                        }
+                    }
+                    for (int64_t j = 0; j < L; ++j) {
+                        const int64_t f = fb + j;
+                        for (int64_t d = 0; d < N; ++d) {
+                            const double* cr = chi + (int64_t)w.q[d] * ld + fb;
+                            const double* er = eta + (int64_t)w.q[d] * ld + fb;
+                            int64_t ia = clampi(j - w.k[d], 0, L - 1);
+                            int64_t ib = clampi(j - w.k[d] - 1, 0, L - 1);
+                            double t = w.t[d];
+                            w.chi[d] = (1.0 - t) * cr[ia] + t * cr[ib];
+                            w.eta[d] = (1.0 - t) * er[ia] + t * er[ib];
+                            w.S[d] = w.eta[d] / w.chi[d];
+                        }
+                        for (int64_t d = 0; d + 1 < N; ++d) {
+                            double ds = w.s[d + 1] - w.s[d];
+                            w.dtau[d] = (0.5 * (w.chi[d] + w.chi[d + 1])) * ds;
+                        }
+                        double u = or_feautrier_u(N, m, w.dtau, w.S, I_bc[f]);
+                        if (!(u == u)) err = 1;
+                        if (u_out) u_out[(oi * R + r) * F + f] = u;
+                        Jo[f] += wv[r] * u;
+                    }
+                    fb += L;
+                }
+            }
+        }
+        ws_free(&w);
+    }
+    return err ? -7 : 0;
+}

@@ -1,0 +1,147 @@
+"""Pins of the oracle's full J (eq. 3, eq. 4) on models with known answers."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def test_sphere_centre_closed_form(orc):
+    # homogeneous sphere, chi = 2, S = 1, no incident light:
+    # J(centre) = S (1 - exp(-chi R)) + I exp(-chi R)
+    m = synth.sphere_model()
+    _, dirs, w2 = orc.dirset_uniform(1)
+    J = orc.compute_J(m, dirs, w2, origins=[0])
+    exact = 1.0 - np.exp(-2.0)
+    assert abs(exact - 0.8646647167633873) < 1e-15
+    assert np.all(J[0] == J[0, 0])
+    assert abs(J[0, 0] - exact) < 2e-2
+
+
+def test_sphere_with_incident_light(orc):
+    m = synth.sphere_model(I_bc=0.5)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    J = orc.compute_J(m, dirs, w2, origins=[0])
+    exact = 1.0 * (1 - np.exp(-2.0)) + 0.5 * np.exp(-2.0)
+    assert abs(J[0, 0] - exact) < 2e-2
+
+
+def _chord_J6(p, dirs, chi, S):
+    """Exact mean over the direction pairs of the formal solution in a unit sphere."""
+    out = 0.0
+    for n in dirs:
+        pn = n @ p
+        root = np.sqrt(1.0 - (p @ p - pn * pn))
+        Lp, Lm = -pn + root, pn + root
+        out += (1.0 / len(dirs)) * 0.5 * ((1 - np.exp(-chi * Lp)) + (1 - np.exp(-chi * Lm))) * S
+    return out
+
+
+def test_sphere_interior_points_vs_chords(orc):
+    # Deep interior points only: a ray that reaches the hull keeps stepping
+    # along it while some hull neighbour lies further ahead, so near the
+    # surface the traced path is longer than the chord by construction.
+    m = synth.sphere_model()
+    _, dirs, w2 = orc.dirset_uniform(1)
+    r = np.linalg.norm(m.pos, axis=1)
+    origins = np.nonzero((r > 0) & (r < 0.3))[0]
+    assert len(origins) > 20
+    J = orc.compute_J(m, dirs, w2, origins=origins)
+    ref = np.array([_chord_J6(m.pos[o], dirs, 2.0, 1.0) for o in origins])
+    assert np.max(np.abs(J[:, 0] - ref)) < 1e-2
+    assert np.mean(np.abs(J[:, 0] - ref)) < 5e-3
+
+
+@pytest.mark.slow
+def test_sphere_convergence(orc):
+    _, dirs, w2 = orc.dirset_uniform(1)
+    exact = 1.0 - np.exp(-2.0)
+    errs = []
+    for k in (1, 8):
+        m = synth.sphere_model(n_inner=999 * k, n_surf=200 * int(round(k ** (2 / 3))), F=1)
+        errs.append(abs(orc.compute_J(m, dirs, w2, origins=[0])[0, 0] - exact))
+    assert errs[1] < errs[0]
+
+
+def test_uniform_source_equal_to_boundary_moving(orc):
+    # S uniform and equal to the incident intensity -> J == S for any chi, v
+    m = synth.tiny_model(8, P=50, F=12, moving=True)
+    S0 = 0.625
+    m.eta = m.chi * S0
+    m.I_bc = np.full(m.F, S0)
+    _, dirs, w2 = orc.dirset_uniform(2)
+    J = orc.compute_J(m, dirs, w2)
+    assert np.max(np.abs(J - S0)) < 1e-13
+
+
+def test_galilean_invariance(orc):
+    # a uniform velocity shifts nothing: bitwise identical to the static model
+    m = synth.tiny_model(9, P=40, F=10)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    J0 = orc.compute_J(m, dirs, w2)
+    m.vel = np.tile(np.array([[3.7, -1.2, 0.4]], np.float32), (m.P, 1))
+    J1 = orc.compute_J(m, dirs, w2)
+    assert np.array_equal(J0, J1)
+
+
+def test_integer_doppler_shift_is_index_shift(orc):
+    # One direction (+x); velocities along x in whole frequency steps (dx a
+    # power of two, so every shift is an exact integer).  The moving solve
+    # must equal a static solve whose tables are shifted per point by
+    # delta_q = (v_q - v_o).x / dx, i.e. read at index f - delta_q (clamped).
+    m = synth.tiny_model(10, P=40, F=16)
+    m.freq = synth.FreqGrid(np.array([16], np.int32), np.array([-4.0]), np.array([0.5]))
+    rng = np.random.default_rng(0)
+    kq = rng.integers(-5, 6, m.P)
+    vel = np.zeros((m.P, 3), np.float32)
+    vel[:, 0] = kq * 0.5
+    m.vel = vel
+    dirs = np.array([[1.0, 0.0, 0.0]])
+    w2 = np.array([1.0])
+    for o in (0, 7, 19):
+        Jm = orc.compute_J(m, dirs, w2, origins=[o])
+        delta = kq - kq[o]
+        fidx = np.clip(np.arange(m.F)[None, :] - delta[:, None], 0, m.F - 1)
+        ms = synth.tiny_model(10, P=40, F=16)
+        ms.chi = np.take_along_axis(m.chi, fidx, 1)
+        ms.eta = np.take_along_axis(m.eta, fidx, 1)
+        Js = orc.compute_J(ms, dirs, w2, origins=[o])
+        assert np.array_equal(Jm, Js)
+        # and a sign error would not pass: shifting the other way differs
+        fneg = np.clip(np.arange(m.F)[None, :] + delta[:, None], 0, m.F - 1)
+        ms.chi = np.take_along_axis(m.chi, fneg, 1)
+        ms.eta = np.take_along_axis(m.eta, fneg, 1)
+        assert not np.allclose(Jm, orc.compute_J(ms, dirs, w2, origins=[o]))
+
+
+def test_lattice_line_matches_slab(orc):
+    # 1D homogeneous line of the lattice: origin in the interior, ray along +x.
+    n = 41
+    m = synth.lattice_model(n=n, F=1, spacing=0.1)
+    chi = 1.5
+    m.chi[:] = chi
+    m.eta[:] = chi * 1.0
+    lin = lambda i, j, k: (i * n + j) * n + k  # noqa: E731
+    o = lin(10, 0, 0)
+    J = orc.compute_J(m, np.array([[1.0, 0.0, 0.0]]), np.array([1.0]), origins=[o])
+    T = chi * 0.1 * (n - 1)
+    tau = chi * 0.1 * 10
+    exact = 1 - 0.5 * (np.exp(-tau) + np.exp(-(T - tau)))
+    assert abs(J[0, 0] - exact) < 2e-3
+
+
+def test_pair_order_permutation(orc):
+    m = synth.tiny_model(12, P=40, F=6, moving=True)
+    _, dirs, w2 = orc.dirset_uniform(2)
+    J1 = orc.compute_J(m, dirs, w2)
+    J2 = orc.compute_J(m, dirs[::-1].copy(), w2[::-1].copy())
+    assert np.max(np.abs(J1 - J2) / np.abs(J1)) < 1e-14
+
+
+def test_want_u_consistent(orc):
+    m = synth.tiny_model(13, P=30, F=5, moving=True)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    J, u = orc.compute_J(m, dirs, w2, want_u=True)
+    Ju = np.zeros_like(J)
+    for r in range(len(w2)):
+        Ju += w2[r] * u[:, r, :]
+    assert np.array_equal(J, Ju)
