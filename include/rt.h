@@ -1,0 +1,230 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) ray-tracing radiative-transfer library.
+ *
+ * Given a point cloud with nearest-neighbour lists (Section 2.2: a point cloud
+ * plus nearest-neighbour information is all the method needs), per-point
+ * opacity chi(nu) and emissivity eta(nu) (Section 2.1: the ray tracer gathers
+ * emissivities and opacities along each ray), per-point velocities
+ * (Section 2.1.1) and a hierarchical HEALPix direction set (Section 2.1.3),
+ * the library returns the mean intensity J[point][nu], the directional
+ * integral of eq. 3 with the weights of eq. 4.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns rt_status: RT_OK (0) or a negative error code.
+ *    rt_last_error() then holds a message (thread-local).  No C++ exception
+ *    crosses this boundary.
+ *  - "device" pointers are HIP device memory (e.g. torch tensors on cuda:0);
+ *    "host" pointers are ordinary memory.  Buffers passed in are borrowed:
+ *    the caller owns them and keeps them alive while a call or a handle that
+ *    refers to them is in use.  Handles own only the small tables they build.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *    "async" only enqueue work on it; errors found by the kernels afterwards
+ *    are reported by rt_sync_status().
+ *  - Layouts: pos float64 [P][3]; nbr_off int64 [P+1] (CSR, off[0] = 0);
+ *    nbr_idx int32 [E]; vel float32 [P][3] in Doppler widths or NULL (static);
+ *    chi, eta [P][ld] row-major, frequency contiguous, dtype RT_F32 or RT_F64;
+ *    J [n_origins][F] of the same dtype.
+ *  - Ray slots: ray s = o*2R + 2r (+n_r) or o*2R + 2r + 1 (-n_r) for origin
+ *    position o in the origin list and pair r of R; ray_off[s] .. ray_off[s+1]
+ *    delimits ray s in ray_ids / ray_Z.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+enum {
+    RT_OK = 0,
+    RT_ERR_ARG = -1,         /* bad argument, size or NULL pointer */
+    RT_ERR_MESH = -2,        /* neighbour list out of range, self, duplicate or asymmetric */
+    RT_ERR_OPACITY = -3,     /* chi <= 0 or non-finite */
+    RT_ERR_CAPACITY = -4,    /* workspace or list capacity too small */
+    RT_ERR_HIP = -5,         /* a HIP runtime call failed */
+    RT_ERR_UNSUPPORTED = -6, /* nside not a power of two, level > 13, too many blocks */
+    RT_ERR_NONFINITE = -7,   /* the solve produced a non-finite u */
+    RT_ERR_STATE = -8        /* handle used in the wrong state */
+};
+
+enum { RT_F32 = 1, RT_F64 = 2 };
+
+#define RT_MAX_FREQ_BLOCKS 8
+#define RT_MAX_LEVEL 13
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rt_last_error(void);
+rt_status rt_version(int32_t* major, int32_t* minor);
+
+/* ------------------------------------------------------------------ direction sets
+ * HEALPix ring-scheme pixels at level l (nside = 2^l) have equal area, 12*4^l of
+ * them (Section 2.1.3).  Rays come in antipodal pairs (Section 2.1.3); the pair
+ * member with the smaller ring index is canonical, its centre is the pair's
+ * direction n_r, the partner ray is exactly -n_r.  A pair at level l carries
+ * weight 2w, w = 1/(12*4^l) (eq. 4).  Sets are built on the host; the handle
+ * uploads its tables to the current device on first use. */
+typedef struct rt_dirset rt_dirset;
+
+/* Every pair at level log2(nside), ascending canonical ring index (6*nside^2 pairs).
+ * nside must be a power of two <= 2^RT_MAX_LEVEL. */
+rt_status rt_dirset_uniform(int32_t nside, rt_dirset** out);
+
+/* Adaptive per-origin sets (Section 2.1.3, Fig. 1): for each origin, the
+ * directions to the sample points (sample_ids, host, n_sample ids) are
+ * histogrammed at level lmax; pair counts are downgraded through the nested
+ * hierarchy; starting from every pair at lmin, the top half of the active
+ * pairs of each level (by count, ties to the smaller ring index) is refined.
+ * The same number of pairs results for every origin: 6*4^lmin*((2^K-1)/2 + 2^K),
+ * K = lmax-lmin (552 rays for lmin=1, lmax=4).  Built on the GPU (async on
+ * `stream`); model positions and origins are device pointers. */
+typedef struct rt_model rt_model;
+rt_status rt_dirset_adaptive(const rt_model* model, int32_t lmin, int32_t lmax,
+                             const int32_t* sample_ids_dev, int64_t n_sample,
+                             const int32_t* origins_dev, int64_t n_origins,
+                             void* stream, rt_dirset** out);
+
+/* Pairs per origin, number of origins the set is specific to (0 = shared by all
+ * origins), and levels. */
+rt_status rt_dirset_info(const rt_dirset* set, int64_t* pairs, int64_t* n_origins,
+                         int32_t* lmin, int32_t* lmax);
+
+/* Copy the set to host: pix [n][R] canonical pixel ids at their level,
+ * level [n][R], dirs [n][R][3], w2 [n][R], n = max(1, n_origins).  Any output
+ * pointer may be NULL.  For adaptive sets this synchronises `stream`. */
+rt_status rt_dirset_export(const rt_dirset* set, int64_t* pix, int32_t* level, double* dirs,
+                           double* w2, void* stream);
+rt_status rt_dirset_destroy(rt_dirset* set);
+
+/* ------------------------------------------------------------------ model
+ * Borrows the caller's device arrays for the handle's lifetime.  Validates the
+ * neighbour lists on the device (indices in range, no self entries) and
+ * synchronises once on `stream` to read the verdict.  Builds a neighbour-
+ * position table (24 bytes per neighbour entry) that the tracer reads instead
+ * of chasing nbr_idx into pos. */
+rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
+                          int64_t E, const float* vel, void* stream, rt_model** out);
+rt_status rt_model_destroy(rt_model* model);
+
+/* Host-side checks of a model (for callers holding host copies, and tests):
+ * offsets monotone from 0 to E, indices in range, no self or duplicate entries,
+ * symmetric lists, finite positions, chi finite and > 0 over [P][F] with row
+ * stride ld (chi may be NULL).  Returns the first error found. */
+rt_status rt_validate_host(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
+                           int64_t E, const void* chi, int32_t dtype, int64_t F, int64_t ld);
+
+/* ------------------------------------------------------------------ tracing
+ * Every ray of every listed origin walks the neighbour graph (Section 2.1,
+ * Fig. 2): from the current point it steps to the forward neighbour closest to
+ * the ray axis.  With R = x_k - x_origin and d the ray direction,
+ *   Z_k = (R.x d.x + R.y d.y) + R.z d.z           (projection, FP64)
+ *   forward:  Z_k > Z_current (strict)
+ *   D_k = (q.x^2 + q.y^2) + q.z^2, q = R - Z_k d  (squared distance to the axis)
+ * the least D_k wins, equal D_k go to the smaller point id; the ray records
+ * (k, Z_k) and continues from k; it ends where no neighbour is forward.  The
+ * origin itself is not recorded.  All geometry is IEEE FP64 without FMA
+ * contraction, so lists are bit-exact and independent of launch shape.
+ *
+ * origins: device int32 [n_origins], or NULL for 0..n_origins-1. */
+
+/* Ray lengths and offsets: ray_off (device int64 [n_origins*2R + 1]) receives
+ * the exclusive scan of the lengths, ray_off[n_rays] the total.  Async.
+ * ws: device scratch of at least rt_trace_count_workspace() bytes. */
+rt_status rt_trace_count_workspace(const rt_dirset* set, int64_t n_origins, size_t* bytes);
+rt_status rt_trace_count(const rt_model* model, const rt_dirset* set, const int32_t* origins,
+                         int64_t n_origins, int64_t* ray_off, void* ws, size_t ws_bytes, void* stream);
+
+/* Writes ray_ids (int32) and ray_Z (float64) of every ray at the offsets from
+ * rt_trace_count; `capacity` is the length of both arrays.  A ray that would
+ * write past capacity is truncated and RT_ERR_CAPACITY is latched for
+ * rt_sync_status().  Async. */
+rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int32_t* origins,
+                         int64_t n_origins, const int64_t* ray_off, int32_t* ray_ids, double* ray_Z,
+                         int64_t capacity, void* stream);
+
+/* ------------------------------------------------------------------ solve
+ * Frequency grid: n_blocks blocks, block b holding len[b] consecutive
+ * frequencies uniformly spaced by dx[b] Doppler widths (host arrays).
+ * F = sum(len) <= ld.
+ *
+ * For every origin o and pair r, the line reverse(ray -n_r), o, ray +n_r is
+ * assembled with coordinates s = (-Z reversed, 0, Z).  Optics are taken in the
+ * frame of o along +n_r (Section 2.1.1): point q is shifted by
+ * delta_q = n_r.(v_q - v_o)/dx_b frequency steps, chi'_q[f] is the linear
+ * interpolation of chi_q at index f - delta_q within the block (indices clamped
+ * to the block), eta' likewise, S = eta'/chi'.  dtau_d = (chi'_d + chi'_{d+1})/2 * ds_d.
+ * The second-order Feautrier equation (eq. 1) with second-order boundary
+ * conditions and incoming intensity I_bc[f] at both ends of every line is
+ * eliminated from both ends towards o in rescaled form; u at o is kept.
+ * J[o][f] = sum_r w2_r u_r[f], summed in ascending r (eq. 3, eq. 4).
+ *
+ * precision RT_F64: all FP64 (tables must be RT_F64).  RT_F32: tables RT_F32,
+ * sweep in FP32, except that rows where min(dtau_{d-1}, dtau_d) < dtau_fp64_below
+ * are eliminated in FP64; ds is always formed in FP64 from the FP64 Z. */
+typedef struct {
+    int32_t n_blocks;
+    const int32_t* len; /* host [n_blocks] */
+    const double* dx;   /* host [n_blocks] */
+} rt_freq_grid;
+
+enum { RT_SCHED_DIRECT = 0, RT_SCHED_BINNED = 1 };
+
+typedef struct {
+    int32_t precision;        /* RT_F32 or RT_F64 */
+    int32_t schedule;         /* RT_SCHED_DIRECT: one wave per (origin, pair, 64-frequency chunk) in
+                                 slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
+                                 queue, longest lines first */
+    double dtau_fp64_below;   /* FP32 path: rows with a smaller dtau are eliminated in FP64 (e.g. 1e-4) */
+    int32_t waves_per_cu;     /* persistent grid size (0 = default) */
+    int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default) */
+} rt_solve_opts;
+
+/* Scratch needed by rt_solve (u per (origin, pair, frequency), bins). */
+rt_status rt_solve_workspace(const rt_dirset* set, int64_t n_origins, int64_t F, const rt_solve_opts* opts,
+                             size_t* bytes);
+
+/* J for every listed origin from precomputed ray lists.  u_out, if not NULL,
+ * receives u[n_origins][R][F] (dtype of the precision).  Async. */
+rt_status rt_solve(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                   const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z,
+                   const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                   const double* I_bc, void* J, void* u_out, const rt_solve_opts* opts,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ plans
+ * A plan owns the ray-list buffers for a fixed (model, set, origins) and replays
+ * the whole hot path -- count, scan, write, bin, sweep, reduce -- as one HIP
+ * graph on the caller's stream.  Creation runs the count pass once to size the
+ * lists (synchronises) and allocates; rt_plan_run allocates nothing. */
+typedef struct rt_plan rt_plan;
+rt_status rt_plan_create(const rt_model* model, const rt_dirset* set, const int32_t* origins,
+                         int64_t n_origins, const void* chi, const void* eta, int32_t dtype, int64_t ld,
+                         const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* opts,
+                         void* stream, rt_plan** out);
+/* Replay the plan (async).  use_graph = 0 launches the kernels one by one. */
+rt_status rt_plan_run(rt_plan* plan, int32_t use_graph, void* stream);
+/* Run the plan eagerly n_runs times on `stream` with HIP events between its
+ * stages and return the mean time per stage in ms: stage_ms[6] = {count, scan,
+ * write, bin, sweep, reduce} (bin is ~0 for RT_SCHED_DIRECT).  Synchronises. */
+rt_status rt_plan_profile(rt_plan* plan, int32_t n_runs, double* stage_ms, void* stream);
+/* Total ray-list entries, and the plan's device ray lists (borrowed views). */
+rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_t** ray_off,
+                       const int32_t** ray_ids, const double** ray_Z);
+/* Copy the plan's current ray lists into caller buffers (device; sizes
+ * n_origins*2R+1, total, total).  Async. */
+rt_status rt_plan_copy_rays(const rt_plan* plan, int64_t* ray_off, int32_t* ray_ids, double* ray_Z, void* stream);
+rt_status rt_plan_destroy(rt_plan* plan);
+
+/* Synchronise `stream` and return the error latched by kernels since the last
+ * call (RT_ERR_CAPACITY; RT_ERR_NONFINITE; RT_ERR_ARG for an origin id outside
+ * 0 .. P-1, whose rays are then empty and whose J row is undefined), then
+ * clear it. */
+rt_status rt_sync_status(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

@@ -8,7 +8,8 @@
  * it.  It shares no code, header, table or constant generator with the HIP
  * library.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * Build: gcc -O2 -std=gnu11 -ffp-contract=off -fno-fast-math -fno-builtin-sin
+ *        -fno-builtin-cos -fopenmp -shared -fPIC
  * No FMA contraction, no fast-math: every floating-point operation below is a
  * single IEEE-754 double operation, evaluated in the order written.
  *
@@ -82,7 +83,9 @@ static void hp_ring_centre(int64_t nside, int64_t p, int64_t* ring, double* z, d
     }
 }
 
-/* Unit vector of the centre of ring-scheme pixel p at resolution nside. */
+/* Unit vector of the centre of ring-scheme pixel p at resolution nside.
+ * sin and cos are called separately (the build keeps the compiler from
+ * fusing them into sincos, which may round differently). */
 OR_API void or_hp_pix2vec(int64_t nside, int64_t p, double* v) {
     int64_t ring;
     double z, phi;

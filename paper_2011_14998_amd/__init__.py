@@ -1,0 +1,25 @@
+"""MI355X (gfx950) adaptive ray-tracing radiative transfer.
+
+Thin Python binding of the C ABI in include/rt.h (librtmi.so, built from
+csrc/ by build.py).  Every step of the computation runs in the library's HIP
+kernels; this module only marshals torch device tensors (memory and streams)
+into the C calls.  There is no CPU fallback: if the library is not built, or
+no GPU is present, the calls raise.
+"""
+from .binding import (  # noqa: F401
+    RT_F32,
+    RT_F64,
+    SCHED_BINNED,
+    SCHED_DIRECT,
+    DirSet,
+    Model,
+    Plan,
+    RtError,
+    compute_J,
+    load,
+    solve,
+    sync_status,
+    trace,
+    validate_host,
+    version,
+)

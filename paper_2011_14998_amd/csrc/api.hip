@@ -1,0 +1,659 @@
+// C ABI of the library (declared in include/rt.h): handles, validation,
+// workspace planning, launches and HIP-graph plans.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+namespace {
+thread_local std::string g_last_error;
+
+__device__ int32_t g_err_word;
+
+constexpr int MAX_DEVICES = 64;
+int32_t* g_err_ptr[MAX_DEVICES] = {nullptr};
+int g_cus[MAX_DEVICES] = {0};
+std::mutex g_mu;
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+rt_status fail(rt_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+rt_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return RT_ERR_HIP;
+}
+
+int32_t* error_word() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_err_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_word)) != hipSuccess) return nullptr;
+        if (hipMemset(p, 0, sizeof(int32_t)) != hipSuccess) return nullptr;
+        g_err_ptr[dev] = (int32_t*)p;
+    }
+    return g_err_ptr[dev];
+}
+
+int num_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 256;
+    if (!g_cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        g_cus[dev] = v;
+    }
+    return g_cus[dev];
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+// ------------------------------------------------------------------ basics
+
+extern "C" const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" rt_status rt_version(int32_t* major, int32_t* minor) {
+    if (!major || !minor) return fail(RT_ERR_ARG, "rt_version: NULL output");
+    *major = 0;
+    *minor = 1;
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ direction sets
+
+rt_status rt_dirset::ensure_device() {
+    int d = 0;
+    RT_HIP(hipGetDevice(&d));
+    if (dev.dirs && dev.device == d) return RT_OK;
+    if (n_origins > 0) return fail(RT_ERR_STATE, "adaptive direction set used on another device");
+    if (dev.dirs) {
+        (void)hipFree(dev.dirs);
+        (void)hipFree(dev.w2);
+        dev.dirs = dev.w2 = nullptr;
+    }
+    RT_HIP(hipMalloc((void**)&dev.dirs, sizeof(double) * dirs.size()));
+    RT_HIP(hipMalloc((void**)&dev.w2, sizeof(double) * w2.size()));
+    RT_HIP(hipMemcpy(dev.dirs, dirs.data(), sizeof(double) * dirs.size(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(dev.w2, w2.data(), sizeof(double) * w2.size(), hipMemcpyHostToDevice));
+    dev.device = d;
+    return RT_OK;
+}
+
+static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+static int32_t log2i(int64_t v) {
+    int32_t l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+extern "C" rt_status rt_dirset_uniform(int32_t nside, rt_dirset** out) {
+    if (!out) return fail(RT_ERR_ARG, "rt_dirset_uniform: NULL output");
+    *out = nullptr;
+    if (!is_pow2(nside) || log2i(nside) > RT_MAX_LEVEL)
+        return fail(RT_ERR_UNSUPPORTED, "rt_dirset_uniform: nside must be a power of two <= 2^13");
+    auto* s = new rt_dirset();
+    s->lmin = s->lmax = log2i(nside);
+    const int64_t npix = 12 * (int64_t)nside * nside;
+    s->R = 6 * (int64_t)nside * nside;
+    s->pix.reserve(s->R);
+    for (int64_t p = 0; p < npix; ++p) {
+        if (hp_antipode(nside, p) <= p) continue;
+        double v[3];
+        hp_centre(nside, p, v, nullptr);
+        s->pix.push_back(p);
+        s->level.push_back(s->lmax);
+        s->dirs.insert(s->dirs.end(), v, v + 3);
+        s->w2.push_back(2.0 / (double)npix);
+    }
+    if ((int64_t)s->pix.size() != s->R) {
+        delete s;
+        return fail(RT_ERR_STATE, "rt_dirset_uniform: internal pair count mismatch");
+    }
+    *out = s;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_dirset_info(const rt_dirset* set, int64_t* pairs, int64_t* n_origins, int32_t* lmin,
+                                    int32_t* lmax) {
+    if (!set) return fail(RT_ERR_ARG, "rt_dirset_info: NULL set");
+    if (pairs) *pairs = set->R;
+    if (n_origins) *n_origins = set->n_origins;
+    if (lmin) *lmin = set->lmin;
+    if (lmax) *lmax = set->lmax;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_dirset_export(const rt_dirset* set, int64_t* pix, int32_t* level, double* dirs, double* w2,
+                                      void* stream) {
+    if (!set) return fail(RT_ERR_ARG, "rt_dirset_export: NULL set");
+    if (set->n_origins == 0) {
+        if (pix) std::memcpy(pix, set->pix.data(), sizeof(int64_t) * set->R);
+        if (level) std::memcpy(level, set->level.data(), sizeof(int32_t) * set->R);
+        if (dirs) std::memcpy(dirs, set->dirs.data(), sizeof(double) * 3 * set->R);
+        if (w2) std::memcpy(w2, set->w2.data(), sizeof(double) * set->R);
+        return RT_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)set->n_origins * set->R;
+    RT_HIP(hipStreamSynchronize(s));
+    if (pix) RT_HIP(hipMemcpy(pix, set->dev_pix, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+    if (level) RT_HIP(hipMemcpy(level, set->dev_level, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (dirs) RT_HIP(hipMemcpy(dirs, set->dev.dirs, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+    if (w2) RT_HIP(hipMemcpy(w2, set->dev.w2, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_dirset_destroy(rt_dirset* set) {
+    if (!set) return RT_OK;
+    if (set->dev.dirs) (void)hipFree(set->dev.dirs);
+    if (set->dev.w2) (void)hipFree(set->dev.w2);
+    if (set->dev_pix) (void)hipFree(set->dev_pix);
+    if (set->dev_level) (void)hipFree(set->dev_level);
+    delete set;
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ model
+
+extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
+                                     int64_t E, const float* vel, void* stream, rt_model** out) {
+    if (!out) return fail(RT_ERR_ARG, "rt_model_create: NULL output");
+    *out = nullptr;
+    if (!pos || !nbr_off || (E > 0 && !nbr_idx) || P <= 0 || E < 0)
+        return fail(RT_ERR_ARG, "rt_model_create: NULL array or non-positive size");
+    if (P > INT32_MAX || E > INT32_MAX)
+        return fail(RT_ERR_UNSUPPORTED, "rt_model_create: more than 2^31-1 points or neighbour entries");
+    hipStream_t s = (hipStream_t)stream;
+    auto* m = new rt_model();
+    m->pos = pos;
+    m->P = P;
+    m->off = nbr_off;
+    m->idx = nbr_idx;
+    m->E = E;
+    m->vel = vel;
+    RT_HIP(hipGetDevice(&m->device));
+    int32_t* bad = nullptr;
+    hipError_t e = hipMalloc((void**)&m->nbr, sizeof(NbrRec) * (size_t)std::max<int64_t>(E, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&bad, sizeof(int32_t));
+    if (e == hipSuccess) e = launch_fill_i32(bad, 1, 0, s);
+    if (e == hipSuccess) e = launch_build_nbr(m, bad, s);
+    int32_t hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (bad) (void)hipFree(bad);
+    if (e != hipSuccess) {
+        rt_status st = hip_fail(e, "rt_model_create");
+        if (m->nbr) (void)hipFree(m->nbr);
+        delete m;
+        return st;
+    }
+    if (hbad) {
+        if (m->nbr) (void)hipFree(m->nbr);
+        delete m;
+        return fail(RT_ERR_MESH, std::string("rt_model_create: invalid neighbour lists (") +
+                                     ((hbad & 1) ? "index out of range " : "") + ((hbad & 2) ? "bad offsets " : "") +
+                                     ((hbad & 4) ? "self neighbour" : "") + ")");
+    }
+    *out = m;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_model_destroy(rt_model* m) {
+    if (!m) return RT_OK;
+    if (m->nbr) (void)hipFree(m->nbr);
+    delete m;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_validate_host(const double* pos, int64_t P, const int64_t* off, const int32_t* idx, int64_t E,
+                                      const void* chi, int32_t dtype, int64_t F, int64_t ld) {
+    if (!pos || !off || (E > 0 && !idx) || P <= 0 || E < 0) return fail(RT_ERR_ARG, "rt_validate_host: bad arguments");
+    for (int64_t i = 0; i < 3 * P; ++i)
+        if (!std::isfinite(pos[i])) return fail(RT_ERR_MESH, "rt_validate_host: non-finite position");
+    if (off[0] != 0 || off[P] != E) return fail(RT_ERR_MESH, "rt_validate_host: offsets must run from 0 to E");
+    std::vector<std::pair<int32_t, int32_t>> edges;
+    edges.reserve((size_t)E);
+    for (int64_t p = 0; p < P; ++p) {
+        if (off[p + 1] < off[p]) return fail(RT_ERR_MESH, "rt_validate_host: offsets not monotone");
+        for (int64_t e = off[p]; e < off[p + 1]; ++e) {
+            int32_t k = idx[e];
+            if (k < 0 || k >= P) return fail(RT_ERR_MESH, "rt_validate_host: neighbour index out of range");
+            if (k == p) return fail(RT_ERR_MESH, "rt_validate_host: self neighbour");
+            edges.emplace_back((int32_t)p, k);
+        }
+    }
+    std::sort(edges.begin(), edges.end());
+    for (size_t i = 1; i < edges.size(); ++i)
+        if (edges[i] == edges[i - 1]) return fail(RT_ERR_MESH, "rt_validate_host: duplicate neighbour");
+    for (auto& pr : edges)
+        if (!std::binary_search(edges.begin(), edges.end(), std::make_pair(pr.second, pr.first)))
+            return fail(RT_ERR_MESH, "rt_validate_host: neighbour lists are not symmetric");
+    if (chi) {
+        if (F <= 0 || ld < F) return fail(RT_ERR_ARG, "rt_validate_host: need 0 < F <= ld");
+        if (F > 4096) return fail(RT_ERR_UNSUPPORTED, "rt_validate_host: more than 4096 frequencies");
+        for (int64_t p = 0; p < P; ++p)
+            for (int64_t f = 0; f < F; ++f) {
+                double c = dtype == RT_F32 ? (double)((const float*)chi)[p * ld + f] : ((const double*)chi)[p * ld + f];
+                if (!(c > 0.0) || !std::isfinite(c)) return fail(RT_ERR_OPACITY, "rt_validate_host: chi must be finite and > 0");
+            }
+    }
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ tracing
+
+static rt_status check_trace_args(const rt_model* m, rt_dirset* set, int64_t n_origins, const char* who) {
+    if (!m || !set) return fail(RT_ERR_ARG, std::string(who) + ": NULL model or set");
+    if (n_origins < 0) return fail(RT_ERR_ARG, std::string(who) + ": negative origin count");
+    if (set->n_origins > 0 && set->n_origins != n_origins)
+        return fail(RT_ERR_ARG, std::string(who) + ": adaptive set built for a different number of origins");
+    return set->ensure_device();
+}
+
+extern "C" rt_status rt_trace_count_workspace(const rt_dirset* set, int64_t n_origins, size_t* bytes) {
+    if (!set || !bytes || n_origins < 0) return fail(RT_ERR_ARG, "rt_trace_count_workspace: bad arguments");
+    const int64_t n = n_origins * 2 * set->R;
+    *bytes = align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1)) + align_up(scan_workspace(n));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_trace_count(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
+                                    int64_t* ray_off, void* ws, size_t ws_bytes, void* stream) {
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_status st = check_trace_args(m, set, n_origins, "rt_trace_count");
+    if (st) return st;
+    if (!ray_off) return fail(RT_ERR_ARG, "rt_trace_count: NULL ray_off");
+    size_t need = 0;
+    rt_trace_count_workspace(set, n_origins, &need);
+    if (!ws || ws_bytes < need) return fail(RT_ERR_CAPACITY, "rt_trace_count: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = n_origins * 2 * set->R;
+    int32_t* lens = (int32_t*)ws;
+    void* scan_ws = (char*)ws + align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    RT_HIP(launch_trace_count(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, lens, s));
+    RT_HIP(launch_scan(lens, n, ray_off, scan_ws, s));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_trace_write(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
+                                    const int64_t* ray_off, int32_t* ray_ids, double* ray_Z, int64_t capacity,
+                                    void* stream) {
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_status st = check_trace_args(m, set, n_origins, "rt_trace_write");
+    if (st) return st;
+    if (!ray_off || (capacity > 0 && (!ray_ids || !ray_Z)) || capacity < 0)
+        return fail(RT_ERR_ARG, "rt_trace_write: NULL list or negative capacity");
+    if (!error_word()) return fail(RT_ERR_HIP, "rt_trace_write: no device error word");
+    RT_HIP(launch_trace_write(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, ray_off, ray_ids,
+                              ray_Z, capacity, (hipStream_t)stream));
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ solve
+
+static rt_solve_opts default_opts() {
+    rt_solve_opts o;
+    o.precision = RT_F32;
+    o.schedule = RT_SCHED_DIRECT;
+    o.dtau_fp64_below = 1e-4;
+    o.waves_per_cu = 0;
+    o.n_bins = 0;
+    return o;
+}
+
+static int32_t opts_bins(const rt_solve_opts& o) { return o.n_bins > 0 ? o.n_bins : 64; }
+
+static size_t solve_ws_bytes(int64_t n_origins, int64_t R, int64_t F, const rt_solve_opts& o, bool need_u) {
+    const size_t es = o.precision == RT_F64 ? 8 : 4;
+    const int64_t n_items = n_origins * R * ((F + 63) / 64);
+    size_t b = 0;
+    if (need_u) b += align_up(es * (size_t)std::max<int64_t>(n_origins * R * F, 1));
+    if (o.schedule == RT_SCHED_BINNED) b += align_up(bin_workspace(n_items, opts_bins(o))) + 256;
+    return b;
+}
+
+extern "C" rt_status rt_solve_workspace(const rt_dirset* set, int64_t n_origins, int64_t F, const rt_solve_opts* opts,
+                                        size_t* bytes) {
+    if (!set || !bytes || n_origins < 0 || F <= 0) return fail(RT_ERR_ARG, "rt_solve_workspace: bad arguments");
+    rt_solve_opts o = opts ? *opts : default_opts();
+    *bytes = solve_ws_bytes(n_origins, set->R, F, o, true);
+    return RT_OK;
+}
+
+static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                             const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
+                             const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid, const double* I_bc,
+                             void* J, const rt_solve_opts& o, SolveLaunch& a) {
+    if (!m || !set || !ray_off || !chi || !eta || !grid || !I_bc || (!J && n_origins > 0))
+        return fail(RT_ERR_ARG, "solve: NULL argument");
+    if (o.precision != RT_F32 && o.precision != RT_F64) return fail(RT_ERR_ARG, "solve: precision must be RT_F32 or RT_F64");
+    if (dtype != o.precision) return fail(RT_ERR_ARG, "solve: table dtype must match the precision");
+    if (grid->n_blocks < 1 || grid->n_blocks > RT_MAX_FREQ_BLOCKS || !grid->len || !grid->dx)
+        return fail(RT_ERR_UNSUPPORTED, "solve: 1 .. 8 frequency blocks required");
+    std::memset(&a, 0, sizeof(a));
+    int64_t F = 0;
+    for (int b = 0; b < grid->n_blocks; ++b) {
+        if (grid->len[b] <= 0 || !(grid->dx[b] > 0.0)) return fail(RT_ERR_ARG, "solve: block lengths and dx must be > 0");
+        a.blk_start[b] = (int32_t)F;
+        a.inv_dx[b] = 1.0 / grid->dx[b];
+        F += grid->len[b];
+    }
+    for (int b = grid->n_blocks; b <= RT_MAX_FREQ_BLOCKS; ++b) a.blk_start[b] = (int32_t)F;
+    if (F > 4096) return fail(RT_ERR_UNSUPPORTED, "solve: more than 4096 frequencies");
+    if (ld < F) return fail(RT_ERR_ARG, "solve: ld < F");
+    if (set->n_origins > 0 && set->n_origins != n_origins)
+        return fail(RT_ERR_ARG, "solve: adaptive set built for a different number of origins");
+    rt_status st = set->ensure_device();
+    if (st) return st;
+    a.origins = origins;
+    a.n_origins = n_origins;
+    a.R = set->R;
+    a.dirs = set->d_dirs();
+    a.w2 = set->d_w2();
+    a.per_origin = set->n_origins > 0;
+    a.ray_off = ray_off;
+    a.ray_ids = ray_ids;
+    a.ray_Z = ray_Z;
+    a.chi = chi;
+    a.eta = eta;
+    a.ld = ld;
+    a.F = (int32_t)F;
+    a.n_blocks = grid->n_blocks;
+    a.vel = m->vel;
+    a.P = m->P;
+    a.I_bc = I_bc;
+    a.J = J;
+    a.dtau_fp64_below = o.dtau_fp64_below;
+    a.schedule = o.schedule;
+    a.n_bins = opts_bins(o);
+    int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;
+    a.grid_waves = num_cus() * wpc;
+    a.err = error_word();
+    if (!a.err) return fail(RT_ERR_HIP, "solve: no device error word");
+    return RT_OK;
+}
+
+// Carve the solve scratch out of ws: u (unless given), then bins and the queue counter.
+static rt_status carve_solve_ws(SolveLaunch& a, const rt_solve_opts& o, void* u_out, void* ws, size_t ws_bytes,
+                                void** bin_ws) {
+    const bool need_u = u_out == nullptr;
+    size_t need = solve_ws_bytes(a.n_origins, a.R, a.F, o, need_u);
+    if (need > 0 && (!ws || ws_bytes < need)) return fail(RT_ERR_CAPACITY, "solve: workspace too small");
+    char* p = (char*)ws;
+    const size_t es = o.precision == RT_F64 ? 8 : 4;
+    if (need_u) {
+        a.u = p;
+        p += align_up(es * (size_t)std::max<int64_t>(a.n_origins * a.R * a.F, 1));
+    } else {
+        a.u = u_out;
+    }
+    *bin_ws = nullptr;
+    if (o.schedule == RT_SCHED_BINNED) {
+        a.queue = (int32_t*)p;
+        p += 256;
+        *bin_ws = p;
+    }
+    return RT_OK;
+}
+
+static hipError_t enqueue_solve(SolveLaunch& a, int precision, void* bin_ws, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (a.schedule == RT_SCHED_BINNED) {
+        int32_t* items = nullptr;
+        e = launch_bin(a, bin_ws, &items, s);
+        if (e != hipSuccess) return e;
+        a.items = items;
+        e = launch_fill_i32(a.queue, 1, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_solve(a, precision, s);
+    if (e != hipSuccess) return e;
+    return launch_reduce(a, precision, s);
+}
+
+extern "C" rt_status rt_solve(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
+                              const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
+                              const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid, const double* I_bc,
+                              void* J, void* u_out, const rt_solve_opts* opts, void* ws, size_t ws_bytes,
+                              void* stream) {
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_solve_opts o = opts ? *opts : default_opts();
+    if (o.schedule != RT_SCHED_DIRECT && o.schedule != RT_SCHED_BINNED) return fail(RT_ERR_ARG, "rt_solve: bad schedule");
+    SolveLaunch a;
+    rt_status st = fill_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid, I_bc, J,
+                               o, a);
+    if (st) return st;
+    if (n_origins * a.R * ((a.F + 63) / 64) > INT32_MAX) return fail(RT_ERR_UNSUPPORTED, "rt_solve: too many work items");
+    void* bin_ws = nullptr;
+    st = carve_solve_ws(a, o, u_out, ws, ws_bytes, &bin_ws);
+    if (st) return st;
+    RT_HIP(enqueue_solve(a, o.precision, bin_ws, (hipStream_t)stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_sync_status(void* stream) {
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int32_t* w = error_word();
+    if (!w) return fail(RT_ERR_HIP, "rt_sync_status: no device error word");
+    int32_t h = 0;
+    RT_HIP(hipMemcpy(&h, w, sizeof(int32_t), hipMemcpyDeviceToHost));
+    RT_HIP(hipMemset(w, 0, sizeof(int32_t)));
+    if (h & ERRBIT_CAPACITY) return fail(RT_ERR_CAPACITY, "a ray list exceeded its capacity");
+    if (h & ERRBIT_NONFINITE) return fail(RT_ERR_NONFINITE, "the solve produced a non-finite u");
+    if (h & ERRBIT_ORIGIN) return fail(RT_ERR_ARG, "an origin id was outside 0 .. P-1");
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ plans
+
+struct rt_plan {
+    const rt_model* m = nullptr;
+    rt_dirset* set = nullptr;
+    const int32_t* origins = nullptr;
+    int64_t n_origins = 0;
+    int64_t n_rays = 0;
+    int64_t total = 0;
+    rt_solve_opts o;
+    SolveLaunch a;
+    int32_t* lens = nullptr;
+    int64_t* ray_off = nullptr;
+    int32_t* ids = nullptr;
+    double* Z = nullptr;
+    void* scan_ws = nullptr;
+    void* solve_ws = nullptr;
+    void* bin_ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Stages: 0 count, 1 scan, 2 write, 3 bin (+ queue reset), 4 sweep, 5 reduce.
+// With `ev` (7 events) each stage is bracketed by event records.
+static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullptr) {
+    hipError_t e = hipSuccess;
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], s);
+    };
+    mark(0);
+    if (e == hipSuccess)
+        e = launch_trace_count(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), p->set->n_origins > 0,
+                               p->lens, s);
+    mark(1);
+    if (e == hipSuccess) e = launch_scan(p->lens, p->n_rays, p->ray_off, p->scan_ws, s);
+    mark(2);
+    if (e == hipSuccess)
+        e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), p->set->n_origins > 0,
+                               p->ray_off, p->ids, p->Z, p->total, s);
+    mark(3);
+    SolveLaunch a = p->a;
+    if (e == hipSuccess && a.schedule == RT_SCHED_BINNED) {
+        int32_t* items = nullptr;
+        e = launch_bin(a, p->bin_ws, &items, s);
+        a.items = items;
+        if (e == hipSuccess) e = launch_fill_i32(a.queue, 1, 0, s);
+    }
+    mark(4);
+    if (e == hipSuccess) e = launch_solve(a, p->o.precision, s);
+    mark(5);
+    if (e == hipSuccess) e = launch_reduce(a, p->o.precision, s);
+    mark(6);
+    return e;
+}
+
+static void plan_free(rt_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (void* q : {(void*)p->lens, (void*)p->ray_off, (void*)p->ids, (void*)p->Z, p->scan_ws, p->solve_ws})
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
+                                    const void* chi, const void* eta, int32_t dtype, int64_t ld,
+                                    const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* opts,
+                                    void* stream, rt_plan** out) {
+    if (!out) return fail(RT_ERR_ARG, "rt_plan_create: NULL output");
+    *out = nullptr;
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_status st = check_trace_args(m, set, n_origins, "rt_plan_create");
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    auto* p = new rt_plan();
+    p->m = m;
+    p->set = set;
+    p->origins = origins;
+    p->n_origins = n_origins;
+    p->n_rays = n_origins * 2 * set->R;
+    p->o = opts ? *opts : default_opts();
+    hipError_t e = hipMalloc((void**)&p->lens, sizeof(int32_t) * (size_t)std::max<int64_t>(p->n_rays, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->ray_off, sizeof(int64_t) * (size_t)(p->n_rays + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->scan_ws, scan_workspace(p->n_rays));
+    if (e == hipSuccess)
+        e = launch_trace_count(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, p->lens, s);
+    if (e == hipSuccess) e = launch_scan(p->lens, p->n_rays, p->ray_off, p->scan_ws, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&p->total, p->ray_off + p->n_rays, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->ids, sizeof(int32_t) * (size_t)std::max<int64_t>(p->total, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->Z, sizeof(double) * (size_t)std::max<int64_t>(p->total, 1));
+    if (e != hipSuccess) {
+        st = hip_fail(e, "rt_plan_create");
+        plan_free(p);
+        return st;
+    }
+    st = fill_launch(m, set, origins, n_origins, p->ray_off, p->ids, p->Z, chi, eta, dtype, ld, grid, I_bc, J, p->o,
+                     p->a);
+    if (!st && solve_items(p->a) > INT32_MAX) st = fail(RT_ERR_UNSUPPORTED, "rt_plan_create: too many work items");
+    if (st) {
+        plan_free(p);
+        return st;
+    }
+    size_t wsb = solve_ws_bytes(n_origins, set->R, p->a.F, p->o, true);
+    e = hipMalloc(&p->solve_ws, std::max<size_t>(wsb, 256));
+    if (e != hipSuccess) {
+        st = hip_fail(e, "rt_plan_create: solve workspace");
+        plan_free(p);
+        return st;
+    }
+    st = carve_solve_ws(p->a, p->o, nullptr, p->solve_ws, wsb, &p->bin_ws);
+    if (st) {
+        plan_free(p);
+        return st;
+    }
+    // Capture the whole step as one graph on a private stream (the caller's
+    // stream may be the legacy default stream, which cannot be captured).
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = plan_enqueue(p, cap);
+        e = hipStreamEndCapture(cap, &p->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "rt_plan_create: graph capture");
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_run(rt_plan* p, int32_t use_graph, void* stream) {
+    if (!p) return fail(RT_ERR_ARG, "rt_plan_run: NULL plan");
+    hipStream_t s = (hipStream_t)stream;
+    if (use_graph) {
+        RT_HIP(hipGraphLaunch(p->exec, s));
+    } else {
+        RT_HIP(plan_enqueue(p, s));
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_profile(rt_plan* p, int32_t n_runs, double* stage_ms, void* stream) {
+    if (!p || !stage_ms || n_runs <= 0) return fail(RT_ERR_ARG, "rt_plan_profile: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[7] = {};
+    for (auto& x : ev) RT_HIP(hipEventCreate(&x));
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < n_runs && e == hipSuccess; ++r) {
+        e = plan_enqueue(p, s, ev);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+        for (int i = 0; i < 6 && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            acc[i] += ms;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "rt_plan_profile");
+    for (int i = 0; i < 6; ++i) stage_ms[i] = acc[i] / n_runs;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_info(const rt_plan* p, int64_t* total, const int64_t** ray_off, const int32_t** ray_ids,
+                                  const double** ray_Z) {
+    if (!p) return fail(RT_ERR_ARG, "rt_plan_info: NULL plan");
+    if (total) *total = p->total;
+    if (ray_off) *ray_off = p->ray_off;
+    if (ray_ids) *ray_ids = p->ids;
+    if (ray_Z) *ray_Z = p->Z;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_copy_rays(const rt_plan* p, int64_t* ray_off, int32_t* ray_ids, double* ray_Z,
+                                       void* stream) {
+    if (!p || !ray_off || (p->total > 0 && (!ray_ids || !ray_Z))) return fail(RT_ERR_ARG, "rt_plan_copy_rays: NULL");
+    hipStream_t s = (hipStream_t)stream;
+    RT_HIP(hipMemcpyAsync(ray_off, p->ray_off, sizeof(int64_t) * (size_t)(p->n_rays + 1), hipMemcpyDeviceToDevice, s));
+    if (p->total > 0) {
+        RT_HIP(hipMemcpyAsync(ray_ids, p->ids, sizeof(int32_t) * (size_t)p->total, hipMemcpyDeviceToDevice, s));
+        RT_HIP(hipMemcpyAsync(ray_Z, p->Z, sizeof(double) * (size_t)p->total, hipMemcpyDeviceToDevice, s));
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_destroy(rt_plan* p) {
+    if (p) plan_free(p);
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ adaptive sets (see dirset.hip)

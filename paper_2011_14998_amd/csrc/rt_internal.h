@@ -1,0 +1,132 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+
+namespace rt {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+rt_status fail(rt_status code, const std::string& msg);
+rt_status hip_fail(hipError_t e, const char* what);
+#define RT_HIP(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return ::rt::hip_fail(e_, #call);  \
+    } while (0)
+
+// Device-side error word (per device), written by kernels with atomicOr.
+enum : int32_t { ERRBIT_CAPACITY = 1, ERRBIT_NONFINITE = 2, ERRBIT_ORIGIN = 4 };
+int32_t* error_word();  // device address for the current device, nullptr on failure
+int num_cus();
+
+// ---------------------------------------------------------------- HEALPix (host)
+// Centre of ring-scheme pixel p at resolution nside (unit vector) and its ring.
+void hp_centre(int64_t nside, int64_t p, double v[3], int64_t* ring);
+// Antipodal pixel (exact integer map: opposite ring, half a turn along it).
+int64_t hp_antipode(int64_t nside, int64_t p);
+
+// ---------------------------------------------------------------- handles
+struct DevTables {
+    int device = -1;
+    double* dirs = nullptr;  // [n][R][3]
+    double* w2 = nullptr;    // [n][R]
+};
+
+}  // namespace rt
+
+struct rt_dirset {
+    int32_t lmin = 0, lmax = 0;
+    int64_t R = 0;          // pairs per origin
+    int64_t n_origins = 0;  // 0: shared set
+    // shared sets: host tables
+    std::vector<int64_t> pix;
+    std::vector<int32_t> level;
+    std::vector<double> dirs, w2;
+    // device tables (uploaded lazily for shared sets, owned for adaptive sets)
+    rt::DevTables dev;
+    int64_t* dev_pix = nullptr;   // adaptive only
+    int32_t* dev_level = nullptr; // adaptive only
+    rt_status ensure_device();
+    const double* d_dirs() const { return dev.dirs; }
+    const double* d_w2() const { return dev.w2; }
+};
+
+struct NbrRec {
+    double x, y, z;
+    int32_t id;
+    int32_t pad;
+};
+
+struct rt_model {
+    const double* pos = nullptr;
+    int64_t P = 0;
+    const int64_t* off = nullptr;
+    const int32_t* idx = nullptr;
+    int64_t E = 0;
+    const float* vel = nullptr;
+    NbrRec* nbr = nullptr;  // owned: neighbour records in CSR order
+    int device = -1;
+};
+
+namespace rt {
+
+// ---------------------------------------------------------------- kernels (launchers)
+// trace.hip
+hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s);
+hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                              const double* dirs, int per_origin, int32_t* lens, hipStream_t s);
+hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                              const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
+                              double* Z, int64_t capacity, hipStream_t s);
+size_t scan_workspace(int64_t n);
+hipError_t launch_scan(const int32_t* lens, int64_t n, int64_t* off, void* ws, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// solve.hip
+struct SolveLaunch {
+    const int32_t* origins;
+    int64_t n_origins;
+    int64_t R;
+    const double* dirs;
+    const double* w2;
+    int per_origin;
+    const int64_t* ray_off;
+    const int32_t* ray_ids;
+    const double* ray_Z;
+    const void* chi;
+    const void* eta;
+    int64_t ld;
+    int32_t F;
+    int32_t n_blocks;
+    int32_t blk_start[RT_MAX_FREQ_BLOCKS + 1];
+    double inv_dx[RT_MAX_FREQ_BLOCKS];
+    const float* vel;
+    const double* I_bc;
+    void* u;
+    void* J;
+    double dtau_fp64_below;
+    // scheduling
+    int32_t schedule;
+    const int32_t* items;  // binned order, or nullptr
+    int32_t* queue;        // persistent counter, or nullptr
+    int32_t grid_waves;    // persistent grid size in waves
+    int32_t n_bins;
+    int32_t* bin_counts;   // [n_bins+1] scratch
+    int32_t* bin_cursor;   // [n_bins] scratch
+    int32_t* err;          // device error word
+    int64_t P;             // number of points (origin ids are checked against it)
+};
+int64_t solve_items(const SolveLaunch& a);
+size_t bin_workspace(int64_t n_items, int32_t n_bins);
+hipError_t launch_bin(const SolveLaunch& a, void* ws, int32_t** items_out, hipStream_t s);
+hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s);
+hipError_t launch_reduce(const SolveLaunch& a, int precision, hipStream_t s);
+
+}  // namespace rt

@@ -1,0 +1,118 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and
+its host-side logic (direction tables, validation, argument errors) behaves."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "rt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2011_14998_amd import binding
+    return binding
+
+
+def test_every_declared_symbol_is_exported(lib):
+    L = lib.load()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding declares exactly what the header declares
+    assert sorted(lib.declared_symbols()) == names
+
+
+def test_version(lib):
+    assert lib.version() == (0, 1)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 16])
+def test_uniform_dirset_bitwise_equal_to_oracle(lib, orc, nside):
+    d = lib.DirSet.uniform(nside)
+    pix, lev, dirs, w2 = d.export()
+    op, od, ow = orc.dirset_uniform(nside)
+    assert np.array_equal(pix, op)
+    assert np.array_equal(dirs, od)  # bit-exact: same closed form, same IEEE order
+    assert np.array_equal(w2, ow)
+    assert np.all(lev == int(np.log2(nside)))
+    assert d.info() == dict(R=6 * nside * nside, n_origins=0, lmin=int(np.log2(nside)), lmax=int(np.log2(nside)))
+
+
+@pytest.mark.parametrize("nside", [0, 3, 6, -4, 2 ** 14])
+def test_dirset_rejects_bad_nside(lib, nside):
+    with pytest.raises(lib.RtError) as e:
+        lib.DirSet.uniform(nside)
+    assert e.value.code == -6
+
+
+def test_validate_host_accepts_generated_models(lib):
+    for m in (synth.tiny_model(1), synth.sphere_model(), synth.lattice_model(4)):
+        lib.validate_host(m.pos, m.nbr_off, m.nbr_idx, m.chi)
+        lib.validate_host(m.pos, m.nbr_off, m.nbr_idx, m.chi.astype(np.float32))
+
+
+def _err(lib, fn):
+    with pytest.raises(lib.RtError) as e:
+        fn()
+    return e.value.code
+
+
+def test_validate_host_error_codes(lib):
+    m = synth.tiny_model(2, P=20)
+    off, idx = m.nbr_off.copy(), m.nbr_idx.copy()
+    bad = idx.copy()
+    bad[3] = m.P + 5
+    assert _err(lib, lambda: lib.validate_host(m.pos, off, bad)) == -2   # out of range
+    bad = idx.copy()
+    bad[off[4]] = 4
+    assert _err(lib, lambda: lib.validate_host(m.pos, off, bad)) == -2   # self
+    # drop one direction of an edge -> asymmetric
+    keep = np.ones(len(idx), bool)
+    keep[off[0]] = False
+    off2 = off.copy()
+    off2[1:] -= 1
+    assert _err(lib, lambda: lib.validate_host(m.pos, off2, idx[keep])) == -2
+    chi = m.chi.copy()
+    chi[2, 3] = 0.0
+    assert _err(lib, lambda: lib.validate_host(m.pos, off, idx, chi)) == -3
+    chi[2, 3] = np.nan
+    assert _err(lib, lambda: lib.validate_host(m.pos, off, idx, chi)) == -3
+    pos = m.pos.copy()
+    pos[1, 1] = np.inf
+    assert _err(lib, lambda: lib.validate_host(pos, off, idx)) == -2
+
+
+def test_null_arguments_rejected(lib):
+    L = lib.load()
+    assert L.rt_dirset_uniform(4, None) == -1
+    assert L.rt_dirset_info(None, None, None, None, None) == -1
+    assert L.rt_model_create(None, 10, None, None, 0, None, None, None) == -1
+    assert L.rt_trace_count_workspace(None, 10, None) == -1
+    assert L.rt_plan_run(None, 1, None) == -1
+    assert L.rt_dirset_destroy(None) == 0
+
+
+def test_workspace_queries(lib):
+    import ctypes as C
+    L = lib.load()
+    d = lib.DirSet.uniform(2)
+    sz = C.c_size_t()
+    assert L.rt_trace_count_workspace(d._h, 1000, C.byref(sz)) == 0
+    assert sz.value >= 1000 * 2 * 24 * 4
+    o = lib.SolveOptsC(lib.RT_F32, lib.SCHED_DIRECT, 1e-4, 0, 0)
+    assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
+    assert sz.value >= 1000 * 24 * 64 * 4
+    o = lib.SolveOptsC(lib.RT_F64, lib.SCHED_BINNED, 1e-4, 0, 0)
+    assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
+    assert sz.value >= 1000 * 24 * 64 * 8 + 1000 * 24 * 4

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Bars: ray lists (ids and Z) bit-exact; J within 1e-12 relative on the FP64 path
+and within 1e-4 relative on the FP32 sweep (both against the FP64 oracle fed the
+same table values); schedules and graph replays bit-identical to each other.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _gpu_model(rt, m):
+    return rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
+
+
+def _t(a, dtype=None):
+    torch = _torch()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _trace_both(rt, orc, m, nside, origins):
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(nside)
+    _, dirs, w2 = orc.dirset_uniform(nside)
+    org = None if origins is None else _t(origins.astype(np.int32))
+    n_o = m.P if origins is None else len(origins)
+    off, ids, Z = rt.trace(model, ds, origins=org, n_origins=n_o)
+    oo = np.arange(m.P, dtype=np.int32) if origins is None else origins.astype(np.int32)
+    e_off, e_ids, e_Z = orc.trace_all(m, dirs, oo)
+    return model, ds, (off, ids, Z), (e_off, e_ids, e_Z), dirs, w2, org, oo
+
+
+def _assert_rays_equal(g, e):
+    off, ids, Z = (x.cpu().numpy() for x in g)
+    assert np.array_equal(off, e[0])
+    assert np.array_equal(ids, e[1])
+    assert np.array_equal(Z.view(np.uint64), e[2].view(np.uint64))
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+# ----------------------------------------------------------------------------- tracing
+
+@pytest.mark.parametrize("nside", [1, 2])
+def test_trace_sphere_all_origins(rt, orc, nside):
+    m = synth.sphere_model()
+    _, _, g, e, *_ = _trace_both(rt, orc, m, nside, None)
+    _assert_rays_equal(g, e)
+
+
+def test_trace_lattice_ties(rt, orc):
+    # exact distance ties and the exact +x direction at nside 1
+    m = synth.lattice_model(7)
+    _, _, g, e, *_ = _trace_both(rt, orc, m, 1, np.arange(m.P))
+    _assert_rays_equal(g, e)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_trace_tiny(rt, orc, seed):
+    m = synth.tiny_model(seed, P=60)
+    _, _, g, e, *_ = _trace_both(rt, orc, m, 4, None)
+    _assert_rays_equal(g, e)
+
+
+@pytest.mark.parametrize("nside,n_org", [(2, 3000), (4, 700)])
+def test_trace_wind_sampled(rt, orc, wind, nside, n_org):
+    rng = np.random.default_rng(nside)
+    origins = rng.choice(wind.P, n_org, replace=False)
+    _, _, g, e, *_ = _trace_both(rt, orc, wind, nside, origins)
+    _assert_rays_equal(g, e)
+
+
+def test_trace_degenerate_meshes(rt, orc):
+    # two points, three collinear points: lines of length 1..3, empty rays
+    for pos in (np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]]),
+                np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [2.0, 0.0, 0.0]])):
+        P = len(pos)
+        a = np.arange(P - 1)
+        off, idx = synth.models.csr_from_edges(P, a, a + 1)
+        m = synth.Model("line", pos, off, idx, None, np.ones((P, 3)), np.ones((P, 3)) * 0.5,
+                        synth.FreqGrid.uniform(1, 3), np.zeros(3))
+        _, _, g, e, *_ = _trace_both(rt, orc, m, 1, None)
+        _assert_rays_equal(g, e)
+
+
+def test_trace_capacity_error_is_reported(rt):
+    import ctypes as C
+    torch = _torch()
+    m = synth.tiny_model(4, P=30)
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(1)
+    off, ids, Z = rt.trace(model, ds)
+    total = ids.numel()
+    small = total // 2
+    ids2 = torch.empty(small, dtype=torch.int32, device="cuda")
+    Z2 = torch.empty(small, dtype=torch.float64, device="cuda")
+    L = rt.binding.load()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.rt_trace_write(model._h, ds._h, None, m.P, off.data_ptr(), ids2.data_ptr(), Z2.data_ptr(), small, s) == 0
+    with pytest.raises(rt.RtError) as ex:
+        rt.sync_status()
+    assert ex.value.code == -4
+    rt.sync_status()  # cleared
+
+
+def test_model_rejects_bad_indices(rt):
+    m = synth.tiny_model(5, P=20)
+    idx = m.nbr_idx.copy()
+    idx[7] = 1000
+    with pytest.raises(rt.RtError) as ex:
+        rt.Model.from_numpy(m.pos, m.nbr_off, idx)
+    assert ex.value.code == -2
+
+
+# ----------------------------------------------------------------------------- solve, FP64
+
+def _solve_gpu(rt, m, model, ds, rays, org, n_o, precision, chi=None, eta=None, **kw):
+    torch = _torch()
+    dt = np.float64 if precision == rt.RT_F64 else np.float32
+    chi = m.chi if chi is None else chi
+    eta = m.eta if eta is None else eta
+    return rt.solve(model, ds, rays, _t(chi.astype(dt)), _t(eta.astype(dt)), m.freq.len, m.freq.dx,
+                    _t(m.I_bc, torch.float64), origins=org, n_origins=n_o, precision=precision, **kw)
+
+
+@pytest.mark.parametrize("case", ["sphere", "tiny_moving", "tiny_2blocks", "tiny_F70", "lattice"])
+def test_J_fp64(rt, orc, case):
+    if case == "sphere":
+        m, nside = synth.sphere_model(), 1
+    elif case == "tiny_moving":
+        m, nside = synth.tiny_model(6, P=60, F=8, moving=True), 2
+    elif case == "tiny_2blocks":
+        m, nside = synth.tiny_model(7, P=50, F=20, moving=True), 2
+        m.freq = synth.FreqGrid(np.array([12, 8], np.int32), np.array([-3.0, -2.0]), np.array([0.5, 0.6]))
+    elif case == "tiny_F70":
+        m, nside = synth.tiny_model(8, P=40, F=70, moving=True), 1
+    else:
+        m, nside = synth.lattice_model(5, F=5), 1
+        m.chi = np.random.default_rng(0).uniform(0.5, 2, m.chi.shape)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, nside, None)
+    J, u = _solve_gpu(rt, m, model, ds, g, org, m.P, rt.RT_F64, want_u=True)
+    Je, ue = orc.compute_J(m, dirs, w2, origins=oo, want_u=True)
+    assert _rel(u.cpu().numpy(), ue) <= TOL64
+    assert _rel(J.cpu().numpy(), Je) <= TOL64
+
+
+@pytest.fixture(scope="module")
+def wind():
+    return synth.wind_model()
+
+
+@pytest.mark.parametrize("nside", [2, 4])
+def test_J_wind_fp64_and_fp32(rt, orc, wind, nside):
+    rng = np.random.default_rng(10 + nside)
+    origins = rng.choice(wind.P, 400, replace=False)
+    c32, e32, c64, e64 = synth.to_fp32_tables(wind.chi, wind.eta)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, wind, nside, origins)
+    Je = orc.compute_J(wind, dirs, w2, origins=oo, chi=c64, eta=e64)
+    J64 = _solve_gpu(rt, wind, model, ds, g, org, len(oo), rt.RT_F64, chi=c64, eta=e64)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    J32 = _solve_gpu(rt, wind, model, ds, g, org, len(oo), rt.RT_F32, chi=c32, eta=e32)
+    err32 = _rel(J32.cpu().numpy().astype(np.float64), Je)
+    assert err32 <= TOL32, err32
+
+
+def test_fp32_error_on_optically_thin_and_thick_lines(rt, orc):
+    # dtau spanning 1e-7 .. 1e3: the FP64 coefficient rows keep the FP32 sweep within 1e-4
+    m = synth.tiny_model(9, P=60, F=16, moving=True)
+    rng = np.random.default_rng(1)
+    scale = 10.0 ** rng.uniform(-6, 3, (m.P, 1))
+    m.chi = m.chi * scale
+    m.eta = m.eta * scale
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, 2, None)
+    Je = orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64)
+    J32 = _solve_gpu(rt, m, model, ds, g, org, m.P, rt.RT_F32, chi=c32, eta=e32)
+    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
+
+
+# ----------------------------------------------------------------------------- closed forms through the GPU
+
+def test_sphere_centre_gpu(rt, orc):
+    m = synth.sphere_model()
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, 1, np.array([0]))
+    J = _solve_gpu(rt, m, model, ds, g, org, 1, rt.RT_F64).cpu().numpy()
+    assert abs(J[0, 0] - (1 - np.exp(-2.0))) < 2e-2
+    assert np.all(J[0] == J[0, 0])
+
+
+@pytest.mark.parametrize("prec,tol", [(2, 1e-13), (1, 1e-5)])
+def test_uniform_source_gives_J_equal_S(rt, orc, prec, tol):
+    m = synth.tiny_model(11, P=60, F=12, moving=True)
+    S0 = 0.625
+    m.eta = m.chi * S0
+    m.I_bc = np.full(m.F, S0)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, 2, None)
+    J = _solve_gpu(rt, m, model, ds, g, org, m.P, prec).cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(J - S0)) <= tol
+
+
+def test_galilean_invariance_gpu(rt, orc):
+    m = synth.tiny_model(12, P=50, F=10)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, 2, None)
+    J0 = _solve_gpu(rt, m, model, ds, g, org, m.P, rt.RT_F64).cpu().numpy()
+    m.vel = np.tile(np.array([[3.7, -1.2, 0.4]], np.float32), (m.P, 1))
+    model_v = _gpu_model(rt, m)
+    J1 = _solve_gpu(rt, m, model_v, ds, g, org, m.P, rt.RT_F64).cpu().numpy()
+    assert np.array_equal(J0, J1)
+
+
+# ----------------------------------------------------------------------------- schedules, plans, graphs
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_binned_schedule_bitwise_equal_direct(rt, orc, wind, prec):
+    origins = np.arange(0, wind.P, 25)
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, wind, 2, origins)
+    Jd = _solve_gpu(rt, wind, model, ds, g, org, len(oo), prec, schedule=rt.SCHED_DIRECT).cpu().numpy()
+    for wpc, nb in ((0, 0), (4, 16), (64, 64)):
+        Jb = _solve_gpu(rt, wind, model, ds, g, org, len(oo), prec, schedule=rt.SCHED_BINNED,
+                        waves_per_cu=wpc, n_bins=nb).cpu().numpy()
+        assert np.array_equal(Jd, Jb)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_plan_graph_replays(rt, orc, wind, schedule):
+    torch = _torch()
+    origins = np.arange(0, wind.P, 50).astype(np.int32)
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(2)
+    c32, e32, c64, e64 = synth.to_fp32_tables(wind.chi, wind.eta)
+    chi, eta = _t(c32), _t(e32)
+    I_bc = _t(wind.I_bc, torch.float64)
+    org = _t(origins)
+    J = torch.empty((len(origins), wind.F), dtype=torch.float32, device="cuda")
+    plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=org,
+                   precision=rt.RT_F32, schedule=schedule)
+    ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
+                       precision=rt.RT_F32).cpu().numpy()
+    plan.run(use_graph=False)
+    rt.sync_status()
+    assert np.array_equal(J.cpu().numpy(), ref)
+    for _ in range(3):
+        J.zero_()
+        plan.run(use_graph=True)
+        rt.sync_status()
+        assert np.array_equal(J.cpu().numpy(), ref)
+        torch.cuda.synchronize()
+    # the plan's lists are the oracle's
+    off, ids, Z = plan.rays()
+    _, dirs, _ = orc.dirset_uniform(2)
+    e = orc.trace_all(wind, dirs, origins)
+    _assert_rays_equal((off, ids, Z), e)
+    prof = plan.profile(2)
+    assert prof["sweep"] > 0 and prof["count"] > 0
+
+
+def test_empty_origin_list(rt):
+    torch = _torch()
+    m = synth.tiny_model(13, P=30, F=4)
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(1)
+    org = torch.empty(0, dtype=torch.int32, device="cuda")
+    off, ids, Z = rt.trace(model, ds, origins=org)
+    assert off.numel() == 1 and int(off[0]) == 0 and ids.numel() == 0
+    J = _solve_gpu(rt, m, model, ds, (off, ids, Z), org, 0, rt.RT_F64)
+    assert J.shape == (0, m.F)
