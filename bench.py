@@ -86,9 +86,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--schedule", choices=["direct", "binned"], default="binned")
+    ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial")
     ap.add_argument("--cpu-sample", type=int, default=4000, help="origins timed on the CPU oracle (0 = skip)")
     ap.add_argument("--nside", type=int, default=NSIDE)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (for scaling HBM counters) and exit")
+    ap.add_argument("--two-pass-trace", action="store_true",
+                    help="walk every ray twice (count, then write) instead of once into padded slots")
+    ap.add_argument("--fp64-below", type=float, default=1e-4,
+                    help="FP32 sweep: rows with an optical-depth step below this are eliminated in FP64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -104,6 +110,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
     rt.load()
 
     _log("generating the wind model ...")
@@ -116,10 +131,11 @@ def main():
     eta = torch.as_tensor(e32, device=dev)
     I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device=dev)
     J = torch.empty((m.P, F), dtype=torch.float32, device=dev)
-    sched = rt.SCHED_BINNED if args.schedule == "binned" else rt.SCHED_DIRECT
+    sched = {"direct": rt.SCHED_DIRECT, "binned": rt.SCHED_BINNED, "spatial": rt.SCHED_SPATIAL}[args.schedule]
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   schedule=sched, dtau_fp64_below=1e-4)
+                   schedule=sched, dtau_fp64_below=args.fp64_below,
+                   padded_trace_budget=-1 if args.two_pass_trace else 0)
     total = plan.info()["total"]
 
     for _ in range(args.warmup):
@@ -170,6 +186,7 @@ def main():
                         f"({R} pairs), F={F}, moving (v_inf 20 Doppler widths), FP32 sweep",
             "points": m.P, "pairs_per_point": R, "freqs": F, "ray_list_entries": total,
             "mean_line_length": (total + m.P * R) / (m.P * R), "schedule": args.schedule,
+            "fp64_rows_below_dtau": args.fp64_below,
         },
         "roofline": {
             "kernel": "feautrier sweep",

@@ -170,16 +170,22 @@ typedef struct {
     const double* dx;   /* host [n_blocks] */
 } rt_freq_grid;
 
-enum { RT_SCHED_DIRECT = 0, RT_SCHED_BINNED = 1 };
+enum { RT_SCHED_DIRECT = 0, RT_SCHED_BINNED = 1, RT_SCHED_SPATIAL = 2 };
 
 typedef struct {
     int32_t precision;        /* RT_F32 or RT_F64 */
     int32_t schedule;         /* RT_SCHED_DIRECT: one wave per (origin, pair, 64-frequency chunk) in
                                  slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
-                                 queue, longest lines first */
+                                 queue, longest lines first; RT_SCHED_SPATIAL (plans only): rays and
+                                 sweep items direction by direction, origins in Morton order of their
+                                 positions, each XCD on a contiguous range -- concurrent waves then read
+                                 mostly the same rows and the L2s hold them */
     double dtau_fp64_below;   /* FP32 path: rows with a smaller dtau are eliminated in FP64 (e.g. 1e-4) */
     int32_t waves_per_cu;     /* persistent grid size (0 = default) */
-    int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default) */
+    int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
+    int64_t padded_trace_budget; /* plans only: bytes allowed for single-pass tracing into padded
+                                    per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB,
+                                    < 0 = always trace in two passes (count, then write) */
 } rt_solve_opts;
 
 /* Scratch needed by rt_solve (u per (origin, pair, frequency), bins). */
@@ -196,9 +202,14 @@ rt_status rt_solve(const rt_model* model, const rt_dirset* set, const int32_t* o
 
 /* ------------------------------------------------------------------ plans
  * A plan owns the ray-list buffers for a fixed (model, set, origins) and replays
- * the whole hot path -- count, scan, write, bin, sweep, reduce -- as one HIP
- * graph on the caller's stream.  Creation runs the count pass once to size the
- * lists (synchronises) and allocates; rt_plan_run allocates nothing. */
+ * the whole hot path -- trace, scan, list output, bin, sweep, reduce -- as one
+ * HIP graph on the caller's stream.  Creation runs the count pass once to size
+ * the lists (synchronises) and allocates; rt_plan_run allocates nothing.  When
+ * the padded budget allows, each run walks every ray once into per-ray slots
+ * sized by the longest ray found at creation and then compacts the slots into
+ * the lists; otherwise it walks twice (count, then write).  A ray longer than
+ * its slot (the model's positions changed after creation) latches
+ * RT_ERR_CAPACITY. */
 typedef struct rt_plan rt_plan;
 rt_status rt_plan_create(const rt_model* model, const rt_dirset* set, const int32_t* origins,
                          int64_t n_origins, const void* chi, const void* eta, int32_t dtype, int64_t ld,
@@ -207,8 +218,9 @@ rt_status rt_plan_create(const rt_model* model, const rt_dirset* set, const int3
 /* Replay the plan (async).  use_graph = 0 launches the kernels one by one. */
 rt_status rt_plan_run(rt_plan* plan, int32_t use_graph, void* stream);
 /* Run the plan eagerly n_runs times on `stream` with HIP events between its
- * stages and return the mean time per stage in ms: stage_ms[6] = {count, scan,
- * write, bin, sweep, reduce} (bin is ~0 for RT_SCHED_DIRECT).  Synchronises. */
+ * stages and return the mean time per stage in ms: stage_ms[6] = {walk (count or
+ * padded), scan, list output (write walk or compaction), bin, sweep, reduce}
+ * (bin is ~0 for RT_SCHED_DIRECT).  Synchronises. */
 rt_status rt_plan_profile(rt_plan* plan, int32_t n_runs, double* stage_ms, void* stream);
 /* Total ray-list entries, and the plan's device ray lists (borrowed views). */
 rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_t** ray_off,

@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     RT_F64,
     SCHED_BINNED,
     SCHED_DIRECT,
+    SCHED_SPATIAL,
     DirSet,
     Model,
     Plan,

@@ -14,6 +14,7 @@ RT_F32 = 1
 RT_F64 = 2
 SCHED_DIRECT = 0
 SCHED_BINNED = 1
+SCHED_SPATIAL = 2
 MAX_FREQ_BLOCKS = 8
 
 _i32, _i64, _vp, _sz, _dbl = C.c_int32, C.c_int64, C.c_void_p, C.c_size_t, C.c_double
@@ -32,7 +33,7 @@ class FreqGridC(C.Structure):
 
 class SolveOptsC(C.Structure):
     _fields_ = [("precision", _i32), ("schedule", _i32), ("dtau_fp64_below", _dbl),
-                ("waves_per_cu", _i32), ("n_bins", _i32)]
+                ("waves_per_cu", _i32), ("n_bins", _i32), ("padded_trace_budget", _i64)]
 
 
 # name -> (restype, argtypes)
@@ -254,8 +255,8 @@ def _grid(freq_len: Sequence[int], freq_dx: Sequence[float]):
     return g, (ln, dx)
 
 
-def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins):
-    return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins)
+def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget=0):
+    return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget)
 
 
 def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
@@ -301,7 +302,8 @@ class Plan:
 
     def __init__(self, model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None,
                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT,
-                 dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0, stream=None):
+                 dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0,
+                 padded_trace_budget: int = 0, stream=None):
         torch = _torch()
         dt = torch.float64 if precision == RT_F64 else torch.float32
         self.chi, self.eta, self.J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
@@ -314,7 +316,7 @@ class Plan:
         self.origins, self.n_origins = origins, n_origins
         self.model, self.dirset = model, dirset
         g, self._keep = _grid(freq_len, freq_dx)
-        o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins)
+        o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget)
         h = _vp()
         _check(load().rt_plan_create(model._h, dirset._h, _ptr(origins), n_origins, _ptr(self.chi),
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),
@@ -324,7 +326,7 @@ class Plan:
     def run(self, use_graph: bool = True, stream=None):
         _check(load().rt_plan_run(self._h, 1 if use_graph else 0, _stream(stream)))
 
-    STAGES = ("count", "scan", "write", "bin", "sweep", "reduce")
+    STAGES = ("walk", "scan", "lists", "bin", "sweep", "reduce")
 
     def profile(self, n_runs: int, stream=None) -> dict:
         """Mean per-stage times (ms) over n_runs eager runs, from HIP events on the stream."""

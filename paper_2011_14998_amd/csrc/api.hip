@@ -19,6 +19,7 @@ __device__ int32_t g_err_word;
 constexpr int MAX_DEVICES = 64;
 int32_t* g_err_ptr[MAX_DEVICES] = {nullptr};
 int g_cus[MAX_DEVICES] = {0};
+int g_xcds[MAX_DEVICES] = {0};
 std::mutex g_mu;
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
@@ -58,6 +59,17 @@ int num_cus() {
         g_cus[dev] = v;
     }
     return g_cus[dev];
+}
+
+int num_xcds() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 1;
+    if (!g_xcds[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || v <= 0) v = 1;
+        g_xcds[dev] = v;
+    }
+    return g_xcds[dev];
 }
 
 }  // namespace rt
@@ -190,6 +202,7 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
     RT_HIP(hipGetDevice(&m->device));
     int32_t* bad = nullptr;
     hipError_t e = hipMalloc((void**)&m->nbr, sizeof(NbrRec) * (size_t)std::max<int64_t>(E, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&m->rows, sizeof(int2) * (size_t)P);
     if (e == hipSuccess) e = hipMalloc((void**)&bad, sizeof(int32_t));
     if (e == hipSuccess) e = launch_fill_i32(bad, 1, 0, s);
     if (e == hipSuccess) e = launch_build_nbr(m, bad, s);
@@ -200,11 +213,13 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
     if (e != hipSuccess) {
         rt_status st = hip_fail(e, "rt_model_create");
         if (m->nbr) (void)hipFree(m->nbr);
+        if (m->rows) (void)hipFree(m->rows);
         delete m;
         return st;
     }
     if (hbad) {
         if (m->nbr) (void)hipFree(m->nbr);
+        if (m->rows) (void)hipFree(m->rows);
         delete m;
         return fail(RT_ERR_MESH, std::string("rt_model_create: invalid neighbour lists (") +
                                      ((hbad & 1) ? "index out of range " : "") + ((hbad & 2) ? "bad offsets " : "") +
@@ -217,6 +232,7 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
 extern "C" rt_status rt_model_destroy(rt_model* m) {
     if (!m) return RT_OK;
     if (m->nbr) (void)hipFree(m->nbr);
+    if (m->rows) (void)hipFree(m->rows);
     delete m;
     return RT_OK;
 }
@@ -314,10 +330,11 @@ static rt_solve_opts default_opts() {
     o.dtau_fp64_below = 1e-4;
     o.waves_per_cu = 0;
     o.n_bins = 0;
+    o.padded_trace_budget = 0;
     return o;
 }
 
-static int32_t opts_bins(const rt_solve_opts& o) { return o.n_bins > 0 ? o.n_bins : 64; }
+static int32_t opts_bins(const rt_solve_opts& o) { return o.n_bins > 0 ? std::min(o.n_bins, 128) : 64; }
 
 static size_t solve_ws_bytes(int64_t n_origins, int64_t R, int64_t F, const rt_solve_opts& o, bool need_u) {
     const size_t es = o.precision == RT_F64 ? 8 : 4;
@@ -384,6 +401,7 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.n_bins = opts_bins(o);
     int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;
     a.grid_waves = num_cus() * wpc;
+    a.n_xcd = num_xcds();
     a.err = error_word();
     if (!a.err) return fail(RT_ERR_HIP, "solve: no device error word");
     return RT_OK;
@@ -434,7 +452,8 @@ extern "C" rt_status rt_solve(const rt_model* m, const rt_dirset* set_, const in
                               void* stream) {
     rt_dirset* set = const_cast<rt_dirset*>(set_);
     rt_solve_opts o = opts ? *opts : default_opts();
-    if (o.schedule != RT_SCHED_DIRECT && o.schedule != RT_SCHED_BINNED) return fail(RT_ERR_ARG, "rt_solve: bad schedule");
+    if (o.schedule != RT_SCHED_DIRECT && o.schedule != RT_SCHED_BINNED)
+        return fail(RT_ERR_ARG, "rt_solve: schedule must be RT_SCHED_DIRECT or RT_SCHED_BINNED (spatial: plans only)");
     SolveLaunch a;
     rt_status st = fill_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid, I_bc, J,
                                o, a);
@@ -478,6 +497,13 @@ struct rt_plan {
     void* scan_ws = nullptr;
     void* solve_ws = nullptr;
     void* bin_ws = nullptr;
+    // single-pass tracing into padded slots (cap per ray), then compaction
+    int64_t cap = 0;
+    int32_t* pids = nullptr;
+    double* pZ = nullptr;
+    // spatial schedule: origin order (Morton) and sweep item order
+    int32_t* order = nullptr;
+    int32_t* items = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -489,16 +515,26 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
     auto mark = [&](int i) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[i], s);
     };
+    const int per = p->set->n_origins > 0;
     mark(0);
-    if (e == hipSuccess)
-        e = launch_trace_count(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), p->set->n_origins > 0,
-                               p->lens, s);
+    if (e == hipSuccess) {
+        if (p->pids)
+            e = launch_trace_padded(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->lens, p->pids,
+                                    p->pZ, p->cap, s, p->order);
+        else
+            e = launch_trace_count(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->lens, s,
+                                   p->order);
+    }
     mark(1);
     if (e == hipSuccess) e = launch_scan(p->lens, p->n_rays, p->ray_off, p->scan_ws, s);
     mark(2);
-    if (e == hipSuccess)
-        e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), p->set->n_origins > 0,
-                               p->ray_off, p->ids, p->Z, p->total, s);
+    if (e == hipSuccess) {
+        if (p->pids)
+            e = launch_compact(p->pids, p->pZ, p->cap, p->ray_off, p->n_rays, p->ids, p->Z, s);
+        else
+            e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->ray_off,
+                                   p->ids, p->Z, p->total, s, p->order);
+    }
     mark(3);
     SolveLaunch a = p->a;
     if (e == hipSuccess && a.schedule == RT_SCHED_BINNED) {
@@ -518,9 +554,58 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
 static void plan_free(rt_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    for (void* q : {(void*)p->lens, (void*)p->ray_off, (void*)p->ids, (void*)p->Z, p->scan_ws, p->solve_ws})
+    for (void* q : {(void*)p->lens, (void*)p->ray_off, (void*)p->ids, (void*)p->Z, p->scan_ws, p->solve_ws,
+                    (void*)p->pids, (void*)p->pZ, (void*)p->order, (void*)p->items})
         if (q) (void)hipFree(q);
     delete p;
+}
+
+// Origin positions in the order of the Morton (Z-order) code of their points:
+// 21 bits per axis over the bounding box of the origins.
+static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
+                               std::vector<int32_t>& order) {
+    std::vector<double> pos((size_t)m->P * 3);
+    std::vector<int32_t> org;
+    hipError_t e = hipMemcpyAsync(pos.data(), m->pos, sizeof(double) * pos.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && origins) {
+        org.resize((size_t)n_o);
+        e = hipMemcpyAsync(org.data(), origins, sizeof(int32_t) * org.size(), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    auto pt = [&](int64_t k) -> int64_t {
+        int64_t o = origins ? (int64_t)org[(size_t)k] : k;
+        return (o < 0 || o >= m->P) ? 0 : o;
+    };
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = 0; k < n_o; ++k)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], pos[(size_t)(3 * pt(k) + c)]);
+            hi[c] = std::max(hi[c], pos[(size_t)(3 * pt(k) + c)]);
+        }
+    auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffULL;
+        v = (v | v << 16) & 0x1f0000ff0000ffULL;
+        v = (v | v << 8) & 0x100f00f00f00f00fULL;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+        v = (v | v << 2) & 0x1249249249249249ULL;
+        return v;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n_o);
+    for (int64_t k = 0; k < n_o; ++k) {
+        uint64_t code = 0;
+        for (int c = 0; c < 3; ++c) {
+            double w = hi[c] > lo[c] ? (pos[(size_t)(3 * pt(k) + c)] - lo[c]) / (hi[c] - lo[c]) : 0.0;
+            uint64_t qv = (uint64_t)std::min(std::max(w * 2097151.0, 0.0), 2097151.0);
+            code |= spread(qv) << c;
+        }
+        key[(size_t)k] = {code, (int32_t)k};
+    }
+    std::sort(key.begin(), key.end());
+    order.resize((size_t)n_o);
+    for (int64_t k = 0; k < n_o; ++k) order[(size_t)k] = key[(size_t)k].second;
+    return hipSuccess;
 }
 
 extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
@@ -532,6 +617,8 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     rt_dirset* set = const_cast<rt_dirset*>(set_);
     rt_status st = check_trace_args(m, set, n_origins, "rt_plan_create");
     if (st) return st;
+    if (opts && (opts->schedule < RT_SCHED_DIRECT || opts->schedule > RT_SCHED_SPATIAL))
+        return fail(RT_ERR_ARG, "rt_plan_create: bad schedule");
     hipStream_t s = (hipStream_t)stream;
     auto* p = new rt_plan();
     p->m = m;
@@ -551,6 +638,22 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMalloc((void**)&p->ids, sizeof(int32_t) * (size_t)std::max<int64_t>(p->total, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&p->Z, sizeof(double) * (size_t)std::max<int64_t>(p->total, 1));
+    // Longest ray: the padded single-pass walk is used when its slots fit the budget.
+    int32_t longest = 0;
+    if (e == hipSuccess && p->n_rays > 0) {
+        std::vector<int32_t> hl((size_t)p->n_rays);
+        e = hipMemcpyAsync(hl.data(), p->lens, sizeof(int32_t) * hl.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (int32_t v : hl) longest = std::max(longest, v);
+    }
+    const size_t pad_bytes = (size_t)p->n_rays * (size_t)std::max(longest, 1) * 12;
+    const size_t budget = opts && opts->padded_trace_budget > 0 ? (size_t)opts->padded_trace_budget
+                                                               : (size_t)32 << 30;
+    if (e == hipSuccess && p->n_rays > 0 && !(opts && opts->padded_trace_budget < 0) && pad_bytes <= budget) {
+        p->cap = std::max(longest, 1);
+        e = hipMalloc((void**)&p->pids, sizeof(int32_t) * (size_t)p->n_rays * p->cap);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->pZ, sizeof(double) * (size_t)p->n_rays * p->cap);
+    }
     if (e != hipSuccess) {
         st = hip_fail(e, "rt_plan_create");
         plan_free(p);
@@ -562,6 +665,31 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (st) {
         plan_free(p);
         return st;
+    }
+    if (p->o.schedule == RT_SCHED_SPATIAL && n_origins > 0) {
+        std::vector<int32_t> ord;
+        e = morton_order(m, origins, n_origins, s, ord);
+        const int nfc = (p->a.F + 63) / 64;
+        std::vector<int32_t> it;
+        if (e == hipSuccess) {
+            it.reserve((size_t)solve_items(p->a));
+            for (int64_t r = 0; r < set->R; ++r)
+                for (int c = 0; c < nfc; ++c)
+                    for (int64_t k = 0; k < n_origins; ++k)
+                        it.push_back((int32_t)(((int64_t)ord[(size_t)k] * set->R + r) * nfc + c));
+            e = hipMalloc((void**)&p->order, sizeof(int32_t) * ord.size());
+        }
+        if (e == hipSuccess) e = hipMalloc((void**)&p->items, sizeof(int32_t) * it.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->items, it.data(), sizeof(int32_t) * it.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "rt_plan_create: spatial order");
+            plan_free(p);
+            return st;
+        }
+        p->a.items = p->items;
+        p->a.schedule = RT_SCHED_DIRECT;  // the sweep itself is a direct launch over the ordered items
     }
     size_t wsb = solve_ws_bytes(n_origins, set->R, p->a.F, p->o, true);
     e = hipMalloc(&p->solve_ws, std::max<size_t>(wsb, 256));

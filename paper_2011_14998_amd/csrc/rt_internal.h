@@ -25,6 +25,18 @@ rt_status hip_fail(hipError_t e, const char* what);
 enum : int32_t { ERRBIT_CAPACITY = 1, ERRBIT_NONFINITE = 2, ERRBIT_ORIGIN = 4 };
 int32_t* error_word();  // device address for the current device, nullptr on failure
 int num_cus();
+int num_xcds();
+
+// Workgroups are dispatched to the XCDs round-robin (workgroup b runs on XCD
+// b mod n).  This renumbering gives XCD x the contiguous range of logical
+// blocks [start_x, start_x + count_x), a bijection of [0, nb), so work that is
+// adjacent in the logical order shares an L2.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb, int n) {
+    if (n <= 1) return b;
+    const int64_t q = nb / n, rem = nb % n;
+    const int64_t x = b % n, i = b / n;
+    return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+}
 
 // ---------------------------------------------------------------- HEALPix (host)
 // Centre of ring-scheme pixel p at resolution nside (unit vector) and its ring.
@@ -72,6 +84,7 @@ struct rt_model {
     int64_t E = 0;
     const float* vel = nullptr;
     NbrRec* nbr = nullptr;  // owned: neighbour records in CSR order
+    int2* rows = nullptr;   // owned: per point {row start, degree}
     int device = -1;
 };
 
@@ -80,11 +93,19 @@ namespace rt {
 // ---------------------------------------------------------------- kernels (launchers)
 // trace.hip
 hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s);
+// `order` (optional): spatially sorted permutation of origin positions; the
+// rays are then walked direction-major in that origin order.
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
-                              const double* dirs, int per_origin, int32_t* lens, hipStream_t s);
+                              const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
+                              const int32_t* order = nullptr);
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
-                              double* Z, int64_t capacity, hipStream_t s);
+                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order = nullptr);
+hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                               const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
+                               int64_t cap, hipStream_t s, const int32_t* order = nullptr);
+hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
+                          int32_t* ids, double* Z, hipStream_t s);
 size_t scan_workspace(int64_t n);
 hipError_t launch_scan(const int32_t* lens, int64_t n, int64_t* off, void* ws, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -122,6 +143,7 @@ struct SolveLaunch {
     int32_t* bin_cursor;   // [n_bins] scratch
     int32_t* err;          // device error word
     int64_t P;             // number of points (origin ids are checked against it)
+    int n_xcd;             // XCDs for the block renumbering of the direct launch
 };
 int64_t solve_items(const SolveLaunch& a);
 size_t bin_workspace(int64_t n_items, int32_t n_bins);

@@ -46,6 +46,15 @@ __device__ inline double readlane_d(double v, int j) {
 
 __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 
+template <typename T>
+__device__ inline T readlane_t(T v, int j);
+template <>
+__device__ inline float readlane_t<float>(float v, int j) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+}
+template <>
+__device__ inline double readlane_t<double>(double v, int j) { return readlane_d(v, j); }
+
 struct LaneFreq {
     int f;       // global frequency index of this lane (clamped to F-1 when inactive)
     bool active;
@@ -80,156 +89,268 @@ __device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) {
     return lf;
 }
 
-// One row of the rescaled elimination (see the file header).
-template <typename T>
-__device__ inline void row_update(bool far_end, T a, T b, T S, T I, T& F, T& Z) {
-    if (far_end) {
-        F = b * ((T)1 + (T)0.5 * b);
-        Z = ((T)0.5 * b * b * S + b * I) / ((T)1 + F);
-    } else {
-        T hb = (T)0.5 * b * (a + b);
-        T ba = b / a;
-        T Fn = hb + ba * (F / ((T)1 + F));
-        Z = (hb * S + ba * Z) / ((T)1 + Fn);
-        F = Fn;
-    }
+// Reciprocals.  FP32: the hardware reciprocal (1 ulp).  FP64: the hardware
+// estimate refined by two Newton steps r <- r + r(1 - x r), within about 1 ulp
+// (an IEEE division costs several times more and is not needed for 1e-12).
+__device__ inline double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
+}
+
+// FP64 reciprocal seeded by the FP32 one (relative error ~1e-7) and refined by
+// one Newton step to ~1e-14: the FP64 rows of the FP32 sweep.
+__device__ inline double rcp64_from32(double x) {
+    double r = (double)__builtin_amdgcn_rcpf((float)x);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
 template <typename T>
-__device__ inline void row_update_policy(bool far_end, T a, T b, T S, T I, T& F, T& Z, double thr) {
-    row_update<T>(far_end, a, b, S, I, F, Z);
-}
-
-// FP32 sweep: rows whose optical-depth steps fall below the threshold are
-// eliminated in FP64 (the coefficients b(a+b)/2 and b/a lose relative
-// accuracy to rounding of the tiny steps first).
+__device__ inline T rcp(T x);
 template <>
-__device__ inline void row_update_policy<float>(bool far_end, float a, float b, float S, float I, float& F,
-                                                float& Z, double thr) {
-    float m = far_end ? b : fminf(a, b);
-    if ((double)m < thr) {
-        double Fd = F, Zd = Z;
-        row_update<double>(far_end, (double)a, (double)b, (double)S, (double)I, Fd, Zd);
-        F = (float)Fd;
-        Z = (float)Zd;
+__device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ inline double rcp<double>(double x) { return rcp64(x); }
+
+// Running state of one side's elimination.  r1 = 1/(1+F) and ra = 1/a are
+// carried so that every row costs three reciprocals: 1/(1+F_new), 1/dtau and
+// 1/chi' (for S).
+template <typename T>
+struct SweepState {
+    T F, Z, r1;   // rescaled pivot, right-hand side, 1/(1+F)
+    T a, ra;      // outer optical-depth step of the pending row and its reciprocal
+};
+
+// Row d of the elimination, given its outer step a (ra = 1/a), inner step b and S_d.
+template <typename T>
+__device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
+    if (far_end) {
+        st.F = b * ((T)1 + (T)0.5 * b);
+        st.r1 = rcp<T>((T)1 + st.F);
+        st.Z = ((T)0.5 * b * b * S + b * I) * st.r1;
     } else {
-        row_update<float>(far_end, a, b, S, I, F, Z);
+        const T hb = (T)0.5 * b * (st.a + b);
+        const T ba = b * st.ra;
+        st.F = hb + ba * (st.F * st.r1);
+        const T Zn = hb * S + ba * st.Z;
+        st.r1 = rcp<T>((T)1 + st.F);
+        st.Z = Zn * st.r1;
     }
+    st.a = b;
+    st.ra = rcp<T>(b);
 }
 
+// The same row with its coefficients and update in FP64 (FP32 state in and out).
+__device__ inline void row_fp64(SweepState<float>& st, bool far_end, float b, float S, float I) {
+    const double bd = b, ad = st.a;
+    double F, Z, r1;
+    if (far_end) {
+        F = bd * (1.0 + 0.5 * bd);
+        r1 = rcp64_from32(1.0 + F);
+        Z = (0.5 * bd * bd * (double)S + bd * (double)I) * r1;
+    } else {
+        const double F0 = st.F;
+        const double hb = 0.5 * bd * (ad + bd);
+        const double ba = bd * rcp64_from32(ad);
+        F = hb + ba * (F0 * rcp64_from32(1.0 + F0));
+        r1 = rcp64_from32(1.0 + F);
+        Z = (hb * (double)S + ba * (double)st.Z) * r1;
+    }
+    st.F = (float)F;
+    st.Z = (float)Z;
+    st.r1 = (float)r1;
+    st.a = b;
+    st.ra = __builtin_amdgcn_rcpf(b);
+}
+
+// Precision policy.  FP64 sweep: plain rows.  FP32 sweep: when any lane of the
+// wave has a step below the threshold (min(a, b), or b at the far end) the
+// whole wave eliminates this row in FP64 -- the row is the same for every lane
+// of the chunk, so a wave-uniform choice costs one path instead of two.
 template <typename T>
-__device__ inline T origin_u(int64_t nm, int64_t np, T a, T b, T Fm, T Zm, T Fp, T Zp, T S, T I) {
-    if (nm > 0 && np > 0) {
-        T h = (T)0.5 * a * b * (a + b);
-        return (h * S + b * Zm + a * Zp) / (h + b * (Fm / ((T)1 + Fm)) + a * (Fp / ((T)1 + Fp)));
+__device__ inline void row_policy(SweepState<T>& st, bool far_end, T b, T S, T I, float thr) {
+    row<T>(st, far_end, b, S, I);
+}
+
+template <>
+__device__ inline void row_policy<float>(SweepState<float>& st, bool far_end, float b, float S, float I,
+                                         float thr) {
+    const float m = far_end ? b : fminf(st.a, b);
+    if (__builtin_amdgcn_ballot_w64(m < thr)) row_fp64(st, far_end, b, S, I);
+    else row<float>(st, far_end, b, S, I);
+}
+
+// u at the origin from the two sides' states (file header).
+template <typename T>
+__device__ inline T origin_u(bool hm, bool hp, const SweepState<T>& m, const SweepState<T>& p, T S, T I) {
+    const T a = m.a, b = p.a;
+    if (hm && hp) {
+        const T h = (T)0.5 * a * b * (a + b);
+        return (h * S + b * m.Z + a * p.Z) * rcp<T>(h + b * (m.F * m.r1) + a * (p.F * p.r1));
     }
-    if (np > 0) {
-        T h = (T)0.5 * b * b;
-        return (h * S + b * I + Zp) / (h + b + Fp / ((T)1 + Fp));
+    if (hp) {
+        const T h = (T)0.5 * b * b;
+        return (h * S + b * I + p.Z) * rcp<T>(h + b + p.F * p.r1);
     }
-    if (nm > 0) {
-        T h = (T)0.5 * a * a;
-        return (h * S + a * I + Zm) / (h + a + Fm / ((T)1 + Fm));
+    if (hm) {
+        const T h = (T)0.5 * a * a;
+        return (h * S + a * I + m.Z) * rcp<T>(h + a + m.F * m.r1);
     }
     return I;
 }
 
+__device__ inline float origin_u_fp64(bool hm, bool hp, const SweepState<float>& m, const SweepState<float>& p,
+                                      float S, float I) {
+    const double a = m.a, b = p.a, Sd = S, Id = I;
+    const double Fm = m.F, Fp = p.F, Zm = m.Z, Zp = p.Z;
+    if (hm && hp) {
+        const double h = 0.5 * a * b * (a + b);
+        return (float)((h * Sd + b * Zm + a * Zp) *
+                       rcp64(h + b * (Fm * rcp64(1.0 + Fm)) + a * (Fp * rcp64(1.0 + Fp))));
+    }
+    if (hp) return (float)((0.5 * b * b * Sd + b * Id + Zp) * rcp64(0.5 * b * b + b + Fp * rcp64(1.0 + Fp)));
+    if (hm) return (float)((0.5 * a * a * Sd + a * Id + Zm) * rcp64(0.5 * a * a + a + Fm * rcp64(1.0 + Fm)));
+    return I;
+}
+
 template <typename T>
-__device__ inline T origin_u_policy(int64_t nm, int64_t np, T a, T b, T Fm, T Zm, T Fp, T Zp, T S, T I,
-                                    double thr) {
-    return origin_u<T>(nm, np, a, b, Fm, Zm, Fp, Zp, S, I);
+__device__ inline T origin_policy(bool hm, bool hp, const SweepState<T>& m, const SweepState<T>& p, T S, T I,
+                                  float thr) {
+    return origin_u<T>(hm, hp, m, p, S, I);
 }
 
 template <>
-__device__ inline float origin_u_policy<float>(int64_t nm, int64_t np, float a, float b, float Fm, float Zm,
-                                               float Fp, float Zp, float S, float I, double thr) {
-    float m = (nm > 0 && np > 0) ? fminf(a, b) : (np > 0 ? b : a);
-    if ((nm > 0 || np > 0) && (double)m < thr)
-        return (float)origin_u<double>(nm, np, a, b, Fm, Zm, Fp, Zp, S, I);
-    return origin_u<float>(nm, np, a, b, Fm, Zm, Fp, Zp, S, I);
+__device__ inline float origin_policy<float>(bool hm, bool hp, const SweepState<float>& m,
+                                             const SweepState<float>& p, float S, float I, float thr) {
+    const float mn = (hm && hp) ? fminf(m.a, p.a) : (hp ? p.a : m.a);
+    if ((hm || hp) && __builtin_amdgcn_ballot_w64(mn < thr)) return origin_u_fp64(hm, hp, m, p, S, I);
+    return origin_u<float>(hm, hp, m, p, S, I);
 }
 
-struct Side {
-    int64_t base;
-    int64_t n;
+constexpr int GROUP = 8;  // line points whose loads are issued together
+
+// Per-wave constants of one item.
+struct ItemCtx {
+    const char* chi;   // table bases (bytes)
+    const char* eta;
+    int64_t ld_bytes;  // row stride in bytes
+    const int32_t* ids;
+    const double* Zr;
+    const float* vel;
+    double nx, ny, nz, inv_dx0;
+    float vox, voy, voz;
+    float thr;
 };
 
-// Eliminate one side of the line, far end first, up to the origin.
-template <typename T, bool MOVING>
-__device__ inline void sweep(const SolveLaunch& a, const T* __restrict__ chi, const T* __restrict__ eta,
-                             const Side sd, const LaneFreq& lf, int lane, double nx, double ny, double nz,
-                             float vox, float voy, float voz, T chi_o, T I, T& Fs, T& Zs, T& dt_last) {
-    const int32_t* __restrict__ ids = a.ray_ids;
-    const double* __restrict__ Zr = a.ray_Z;
-    const int64_t ld = a.ld;
-    T c_prev = (T)0, S_prev = (T)0, dt_out = (T)0;
-    double ds_prev = 0.0;
-    int64_t done = 0;
-    for (int64_t hi = sd.n - 1; hi >= 0; hi -= 64) {
-        const int cnt = (int)(hi + 1 < 64 ? hi + 1 : 64);
-        const int64_t e = hi - lane;
+// Eliminate one side of the line (entries base .. base+n-1 of a ray list,
+// walked from the far end inwards), up to the origin; on return st holds the
+// row next to the origin and st.a the step between that row and the origin.
+//
+// UDX: every frequency block has the same dx, so the Doppler shift of a point
+// (whole steps k and fraction t) is the same in every lane and is computed
+// once per point while the 64-point segment is staged.
+template <typename T, bool MOVING, bool UDX>
+__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
+                             SweepState<T>& st) {
+    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
+    int done = 0;
+    const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
+    for (int hi = n - 1; hi >= 0; hi -= 64) {
+        const int cnt = hi + 1 < 64 ? hi + 1 : 64;
+        // staging: lane j holds entry hi-j
+        const int e = hi - lane;
         const bool v = lane < cnt;
-        int q_l = 0;
-        double ds_l = 0.0, dot_l = 0.0;
+        int q_l = 0, k_l = 0;
+        T ds_l = (T)0, t_l = (T)0;
+        double dot_l = 0.0;
         if (v) {
-            q_l = ids[sd.base + e];
-            double z = Zr[sd.base + e];
-            double zi = e > 0 ? Zr[sd.base + e - 1] : 0.0;
-            ds_l = z - zi;
+            q_l = c.ids[base + e];
+            const double z = c.Zr[base + e];
+            const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
+            ds_l = (T)(z - zi);  // difference of FP64 projections, rounded once
             if (MOVING) {
-                const float* vq = a.vel + 3 * (int64_t)q_l;
-                double dvx = (double)vq[0] - (double)vox;
-                double dvy = (double)vq[1] - (double)voy;
-                double dvz = (double)vq[2] - (double)voz;
-                dot_l = (nx * dvx + ny * dvy) + nz * dvz;
+                const float* vq = c.vel + 3 * (int64_t)q_l;
+                const double dvx = (double)vq[0] - (double)c.vox;
+                const double dvy = (double)vq[1] - (double)c.voy;
+                const double dvz = (double)vq[2] - (double)c.voz;
+                dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
+                if (UDX) {
+                    const double delta = dot_l * c.inv_dx0;
+                    const double kf = floor(delta);
+                    k_l = (int)kf;
+                    t_l = (T)(delta - kf);
+                }
             }
         }
-        for (int j = 0; j < cnt; ++j) {
-            const int q = readlane_i(q_l, j);
-            const double ds = readlane_d(ds_l, j);
-            const T* cr = chi + (int64_t)q * ld;
-            const T* er = eta + (int64_t)q * ld;
-            T c, et;
-            if (MOVING) {
-                const double dot = readlane_d(dot_l, j);
-                const double delta = dot * lf.inv_dx;
-                const double kf = floor(delta);
-                const T t = (T)(delta - kf);
-                const int k = (int)kf;
-                int ia = lf.fl - k, ib = lf.fl - k - 1;
-                ia = ia < 0 ? 0 : (ia > lf.L - 1 ? lf.L - 1 : ia);
-                ib = ib < 0 ? 0 : (ib > lf.L - 1 ? lf.L - 1 : ib);
-                const T ca = cr[lf.fb + ia], cb = cr[lf.fb + ib];
-                const T ea = er[lf.fb + ia], eb = er[lf.fb + ib];
-                c = ((T)1 - t) * ca + t * cb;
-                et = ((T)1 - t) * ea + t * eb;
-            } else {
-                c = cr[lf.f];
-                et = er[lf.f];
+        for (int j = 0; j < cnt; j += GROUP) {
+            T ca[GROUP], cb[GROUP], ea[GROUP], eb[GROUP], tt[GROUP], dsv[GROUP];
+#pragma unroll
+            for (int g = 0; g < GROUP; ++g) {
+                if (j + g < cnt) {
+                    const int q = readlane_i(q_l, j + g);
+                    const char* cr = c.chi + (int64_t)q * c.ld_bytes;
+                    const char* er = c.eta + (int64_t)q * c.ld_bytes;
+                    dsv[g] = readlane_t<T>(ds_l, j + g);
+                    if (MOVING) {
+                        int k;
+                        T t;
+                        if (UDX) {
+                            k = readlane_i(k_l, j + g);
+                            t = readlane_t<T>(t_l, j + g);
+                        } else {
+                            const double delta = readlane_d(dot_l, j + g) * lf.inv_dx;
+                            const double kf = floor(delta);
+                            k = (int)kf;
+                            t = (T)(delta - kf);
+                        }
+                        const int ia = min(max(lf.fl - k, 0), lf.L - 1);
+                        const int ib = min(max(lf.fl - k - 1, 0), lf.L - 1);
+                        const uint32_t oa = (uint32_t)(lf.fb + ia) * (uint32_t)sizeof(T);
+                        const uint32_t ob = (uint32_t)(lf.fb + ib) * (uint32_t)sizeof(T);
+                        ca[g] = *(const T*)(cr + oa);
+                        cb[g] = *(const T*)(cr + ob);
+                        ea[g] = *(const T*)(er + oa);
+                        eb[g] = *(const T*)(er + ob);
+                        tt[g] = t;
+                    } else {
+                        ca[g] = *(const T*)(cr + lane_off);
+                        ea[g] = *(const T*)(er + lane_off);
+                    }
+                }
             }
-            const T S = et / c;
-            if (done > 0) {
-                const T dt = ((T)0.5 * (c_prev + c)) * (T)ds_prev;
-                row_update_policy<T>(done == 1, dt_out, dt, S_prev, I, Fs, Zs, a.dtau_fp64_below);
-                dt_out = dt;
+#pragma unroll
+            for (int g = 0; g < GROUP; ++g) {
+                if (j + g < cnt) {
+                    T cc, et;
+                    if (MOVING) {
+                        cc = ca[g] + tt[g] * (cb[g] - ca[g]);
+                        et = ea[g] + tt[g] * (eb[g] - ea[g]);
+                    } else {
+                        cc = ca[g];
+                        et = ea[g];
+                    }
+                    const T S = et * rcp<T>(cc);
+                    if (done > 0) {
+                        const T dt = ((T)0.5 * (c_prev + cc)) * ds_prev;
+                        row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
+                    }
+                    c_prev = cc;
+                    S_prev = S;
+                    ds_prev = dsv[g];
+                    ++done;
+                }
             }
-            c_prev = c;
-            S_prev = S;
-            ds_prev = ds;
-            ++done;
         }
     }
-    if (sd.n > 0) {
-        const T dt = ((T)0.5 * (c_prev + chi_o)) * (T)ds_prev;
-        row_update_policy<T>(sd.n == 1, dt_out, dt, S_prev, I, Fs, Zs, a.dtau_fp64_below);
-        dt_last = dt;
+    if (n > 0) {
+        const T dt = ((T)0.5 * (c_prev + chi_o)) * ds_prev;
+        row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
     }
 }
 
-template <typename T, bool MOVING>
+template <typename T, bool MOVING, bool UDX>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane) {
-    const T* __restrict__ chi = (const T*)a.chi;
-    const T* __restrict__ eta = (const T*)a.eta;
     const int fc = (int)(w % nfc);
     const int64_t pr = w / nfc;
     const int64_t r = pr % a.R;
@@ -241,47 +362,56 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
         return;
     }
     const int64_t slot_p = oi * 2 * a.R + 2 * r;
-    Side sp, sm;
-    sp.base = a.ray_off[slot_p];
-    sp.n = a.ray_off[slot_p + 1] - sp.base;
-    sm.base = a.ray_off[slot_p + 1];
-    sm.n = a.ray_off[slot_p + 2] - sm.base;
+    const int64_t bp = a.ray_off[slot_p], bm = a.ray_off[slot_p + 1], be = a.ray_off[slot_p + 2];
+    const int np = (int)(bm - bp), nm = (int)(be - bm);
+    ItemCtx c;
+    c.chi = (const char*)a.chi;
+    c.eta = (const char*)a.eta;
+    c.ld_bytes = a.ld * (int64_t)sizeof(T);
+    c.ids = a.ray_ids;
+    c.Zr = a.ray_Z;
+    c.vel = a.vel;
     const double* dv = a.dirs + 3 * ((a.per_origin ? oi * a.R : 0) + r);
-    const double nx = dv[0], ny = dv[1], nz = dv[2];
-    float vox = 0.f, voy = 0.f, voz = 0.f;
+    c.nx = dv[0];
+    c.ny = dv[1];
+    c.nz = dv[2];
+    c.inv_dx0 = a.inv_dx[0];
+    c.vox = c.voy = c.voz = 0.f;
     if (MOVING) {
-        vox = a.vel[3 * o];
-        voy = a.vel[3 * o + 1];
-        voz = a.vel[3 * o + 2];
+        c.vox = a.vel[3 * o];
+        c.voy = a.vel[3 * o + 1];
+        c.voz = a.vel[3 * o + 2];
     }
+    c.thr = (float)a.dtau_fp64_below;
     const T I = (T)a.I_bc[lf.f];
-    const T chi_o = chi[o * a.ld + lf.f];
-    const T S_o = eta[o * a.ld + lf.f] / chi_o;
-    T Fm = 0, Zm = 0, dm = 0, Fp = 0, Zp = 0, dp = 0;
-    sweep<T, MOVING>(a, chi, eta, sm, lf, lane, nx, ny, nz, vox, voy, voz, chi_o, I, Fm, Zm, dm);
-    sweep<T, MOVING>(a, chi, eta, sp, lf, lane, nx, ny, nz, vox, voy, voz, chi_o, I, Fp, Zp, dp);
-    const T u = origin_u_policy<T>(sm.n, sp.n, dm, dp, Fm, Zm, Fp, Zp, S_o, I, a.dtau_fp64_below);
+    const T chi_o = ((const T*)a.chi)[o * a.ld + lf.f];
+    const T S_o = ((const T*)a.eta)[o * a.ld + lf.f] * rcp<T>(chi_o);
+    SweepState<T> m{}, p{};
+    sweep<T, MOVING, UDX>(c, bm, nm, lf, lane, chi_o, I, m);
+    sweep<T, MOVING, UDX>(c, bp, np, lf, lane, chi_o, I, p);
+    const T u = origin_policy<T>(nm > 0, np > 0, m, p, S_o, I, c.thr);
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
         if (!(u == u) || u - u != (T)0) atomicOr(a.err, ERRBIT_NONFINITE);
     }
 }
 
-template <typename T, bool MOVING>
+template <typename T, bool MOVING, bool UDX>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
-    const int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.n_xcd);
+    const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
     if (it >= n_items) return;
     const int64_t w = a.items ? (int64_t)a.items[it] : it;
-    solve_item<T, MOVING>(a, w, nfc, lane);
+    solve_item<T, MOVING, UDX>(a, w, nfc, lane);
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
 // takes the next item with one atomic and exits when the queue is empty, so
 // every wave reaches the end.
-template <typename T, bool MOVING>
+template <typename T, bool MOVING, bool UDX>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -292,7 +422,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX>(a, w, nfc, lane);
     }
 }
 
@@ -324,12 +454,22 @@ __device__ inline int bin_of(int64_t N, int n_bins) {
     return b;
 }
 
+// Block-local histograms in LDS; one global atomic per non-empty bin per block.
+constexpr int MAX_BINS = 128;
+
 __global__ __launch_bounds__(256) void k_bin_count(const SolveLaunch a) {
+    __shared__ int h[MAX_BINS];
+    for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= a.n_origins * a.R) return;
-    const int64_t s = 2 * p;  // slot of the +ray: origin*2R + 2r = 2*(origin*R + r)
-    const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
-    atomicAdd(&a.bin_counts[bin_of(N, a.n_bins)], 1);
+    if (p < a.n_origins * a.R) {
+        const int64_t s = 2 * p;  // slot of the +ray: origin*2R + 2r = 2*(origin*R + r)
+        const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
+        atomicAdd(&h[bin_of(N, a.n_bins)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x)
+        if (h[i]) atomicAdd(&a.bin_counts[i], h[i]);
 }
 
 __global__ void k_bin_offsets(const SolveLaunch a) {
@@ -343,13 +483,28 @@ __global__ void k_bin_offsets(const SolveLaunch a) {
 }
 
 __global__ __launch_bounds__(256) void k_bin_scatter(const SolveLaunch a, int32_t* __restrict__ items) {
+    __shared__ int h[MAX_BINS];
+    __shared__ int base[MAX_BINS];
+    for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= a.n_origins * a.R) return;
-    const int64_t s = 2 * p;
-    const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
-    const int nfc = (a.F + 63) / 64;
-    const int pos = atomicAdd(&a.bin_cursor[bin_of(N, a.n_bins)], 1);
-    for (int c = 0; c < nfc; ++c) items[(int64_t)pos * nfc + c] = (int32_t)(p * nfc + c);
+    const bool live = p < a.n_origins * a.R;
+    int b = 0, local = 0;
+    if (live) {
+        const int64_t s = 2 * p;
+        const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
+        b = bin_of(N, a.n_bins);
+        local = atomicAdd(&h[b], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x)
+        base[i] = h[i] ? atomicAdd(&a.bin_cursor[i], h[i]) : 0;
+    __syncthreads();
+    if (live) {
+        const int nfc = (a.F + 63) / 64;
+        const int pos = base[b] + local;
+        for (int c = 0; c < nfc; ++c) items[(int64_t)pos * nfc + c] = (int32_t)(p * nfc + c);
+    }
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -381,29 +536,33 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
+template <typename T>
+static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
+    const bool moving = a.vel != nullptr;
+    // the shift of a point is lane-independent when every block has the same dx
+    bool udx = true;
+    for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+    if (persist) {
+        if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
+        else if (moving) RT_LAUNCH(k_solve_persist, true, false);
+        else RT_LAUNCH(k_solve_persist, false, true);
+    } else {
+        if (moving && udx) RT_LAUNCH(k_solve_direct, true, true);
+        else if (moving) RT_LAUNCH(k_solve_direct, true, false);
+        else RT_LAUNCH(k_solve_direct, false, true);
+    }
+#undef RT_LAUNCH
+}
+
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s) {
     const int64_t n_items = solve_items(a);
     if (n_items == 0) return hipSuccess;
-    const bool moving = a.vel != nullptr;
-    if (a.schedule == RT_SCHED_BINNED) {
-        dim3 grid((unsigned)((a.grid_waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
-        if (precision == RT_F64) {
-            if (moving) hipLaunchKernelGGL((k_solve_persist<double, true>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((k_solve_persist<double, false>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-        } else {
-            if (moving) hipLaunchKernelGGL((k_solve_persist<float, true>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((k_solve_persist<float, false>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-        }
-    } else {
-        dim3 grid(nblocks(n_items, WAVES_PER_BLOCK));
-        if (precision == RT_F64) {
-            if (moving) hipLaunchKernelGGL((k_solve_direct<double, true>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((k_solve_direct<double, false>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-        } else {
-            if (moving) hipLaunchKernelGGL((k_solve_direct<float, true>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((k_solve_direct<float, false>), grid, dim3(SOLVE_BLOCK), 0, s, a);
-        }
-    }
+    const bool persist = a.schedule == RT_SCHED_BINNED;
+    dim3 grid = persist ? dim3((unsigned)((a.grid_waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK))
+                        : dim3(nblocks(n_items, WAVES_PER_BLOCK));
+    if (precision == RT_F64) solve_dispatch<double>(a, persist, grid, s);
+    else solve_dispatch<float>(a, persist, grid, s);
     return hipGetLastError();
 }
 

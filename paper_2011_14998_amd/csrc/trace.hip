@@ -1,17 +1,19 @@
 // Ray tracing through the neighbour graph (Section 2.1, Fig. 2) and the
 // device-wide scan that turns ray lengths into list offsets.
 //
-// One lane walks one ray: from the current point it takes the forward neighbour
-// (projection on the ray axis strictly beyond the current one) that lies
-// closest to the axis, equal distances going to the smaller point id.  The
+// From the current point a ray takes the forward neighbour (projection on the
+// ray axis strictly beyond the current one) that lies closest to the axis,
+// equal distances going to the smaller point id.  The
 // geometry is IEEE FP64 in a fixed operation order with FMA contraction off
 // (this file is compiled with -ffp-contract=off as well), so every list is
 // bit-identical to any other evaluation of the same rule.
 //
-// Data layout: neighbour records {x, y, z, id} (32 bytes) in CSR order, built
-// once per model, so a step reads one record per neighbour instead of an index
-// and then a position.  The whole table of a 50k-point Delaunay mesh (~25 MB)
-// stays in the L2/Infinity-cache hierarchy; the walk is latency bound.
+// Data layout: neighbour records {x, y, z, id} (32 bytes) in CSR order and a
+// per-point {row start, degree} table, both built once per model, so a step
+// reads one record per neighbour instead of an index and then a position; a
+// group of 8 lanes reads a point's whole row (~15 records, ~500 contiguous
+// bytes) per step.  The tables of a 50k-point Delaunay mesh (~25 MB) stay in
+// the Infinity cache; the walk is latency bound.
 #include "rt_internal.h"
 
 #pragma clang fp contract(off)
@@ -55,24 +57,88 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
         if (idx[e] == p) atomicOr(bad, 4);
 }
 
-template <bool WRITE>
-__global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict__ pos, const int64_t* __restrict__ off,
+// Eight lanes walk one ray (eight rays per wavefront).  At every step lane s
+// takes neighbours s, s+8, ... of the current point's row (contiguous records,
+// so a group reads whole cache lines), keeps its best forward candidate
+// together with that candidate's own CSR row (start, degree; loaded at the same
+// time, so no load depends on the step's outcome), and the group reduces to
+// the lexicographic minimum of (D, id) with DPP lane permutations inside each
+// 8-lane half-row: mirror, then swap neighbours, then swap pairs.  The result
+// equals a sequential scan of the row.
+enum TraceMode { TRACE_COUNT = 0, TRACE_WRITE = 1, TRACE_PADDED = 2 };
+
+constexpr int TRACE_GL = 8;
+
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = dpp_i<CTRL>(p.x);
+    p.y = dpp_i<CTRL>(p.y);
+    return __builtin_bit_cast(double, p);
+}
+
+struct Cand {
+    double D, Z;
+    int32_t id, start, deg;
+};
+
+template <int CTRL>
+__device__ inline void cand_merge(Cand& b) {
+    Cand o;
+    o.D = dpp_d<CTRL>(b.D);
+    o.Z = dpp_d<CTRL>(b.Z);
+    o.id = dpp_i<CTRL>(b.id);
+    o.start = dpp_i<CTRL>(b.start);
+    o.deg = dpp_i<CTRL>(b.deg);
+    if (o.D < b.D || (o.D == b.D && o.id < b.id)) b = o;
+}
+
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
+constexpr int DPP_SWAP1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_SWAP2 = 0x4E;         // quad_perm [2,3,0,1]
+
+// Work order.  Without `order`, ray L is slot L (origin-major).  With `order`
+// (a permutation of origin positions, spatially sorted) ray L is direction
+// L / n_origins of origin order[L % n_origins]: concurrent waves walk nearby
+// origins in the same direction and share most of the rows they read.  Blocks
+// are renumbered so that each XCD (own L2) gets a contiguous range of rays.
+template <int MODE>
+__global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict__ pos,
+                                                        const int2* __restrict__ rows,
                                                         const NbrRec* __restrict__ nbr, int64_t P,
                                                         const int32_t* __restrict__ origins, int64_t n_origins,
                                                         int64_t R, const double* __restrict__ dirs, int per_origin,
                                                         int32_t* __restrict__ lens, const int64_t* __restrict__ ray_off,
                                                         int32_t* __restrict__ ids, double* __restrict__ Zout,
-                                                        int64_t capacity, int32_t* __restrict__ err) {
-    const int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+                                                        int64_t capacity, int32_t* __restrict__ err,
+                                                        const int32_t* __restrict__ order, int n_xcd) {
+    const int sub = threadIdx.x & (TRACE_GL - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd);
+    const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / TRACE_GL;
     const int64_t two_r = 2 * R;
-    if (ray >= n_origins * two_r) return;
-    const int64_t oi = ray / two_r;
-    const int64_t rr = ray - oi * two_r;
+    if (L >= n_origins * two_r) return;  // whole groups leave together
+    int64_t oi, rr;
+    if (order) {
+        const int64_t dslot = L / n_origins;
+        oi = order[L - dslot * n_origins];
+        rr = dslot;
+    } else {
+        oi = L / two_r;
+        rr = L - oi * two_r;
+    }
+    const int64_t ray = oi * two_r + rr;
     const int64_t r = rr >> 1;
     const int64_t o = origins ? (int64_t)origins[oi] : oi;
     if (o < 0 || o >= P) {  // invalid origin id: empty ray, error latched
-        if (!WRITE) lens[ray] = 0;
-        else atomicOr(err, ERRBIT_ORIGIN);
+        if (sub == 0) {
+            if (MODE != TRACE_WRITE) lens[ray] = 0;
+            if (MODE != TRACE_COUNT) atomicOr(err, ERRBIT_ORIGIN);
+        }
         return;
     }
     const double* dv = dirs + 3 * ((per_origin ? oi * R : 0) + r);
@@ -84,45 +150,84 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     }
     const double ox = pos[3 * o], oy = pos[3 * o + 1], oz = pos[3 * o + 2];
     int64_t base = 0, room = 0;
-    if (WRITE) {
+    if (MODE == TRACE_WRITE) {
         base = ray_off[ray];
         room = ray_off[ray + 1] - base;
         if (base + room > capacity) room = capacity - base;
+    } else if (MODE == TRACE_PADDED) {
+        base = ray * capacity;  // capacity = slots per ray
+        room = capacity;
     }
-    int64_t c = o, n = 0;
+    const int2 row0 = rows[o];
+    int32_t e0 = row0.x, deg = row0.y;
+    int32_t n = 0;
     double Zc = 0.0;
     for (int64_t step = 0; step < P; ++step) {
-        const int64_t e0 = off[c], e1 = off[c + 1];
-        int32_t best = -1;
-        double bestD = 0.0, bestZ = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const NbrRec rec = nbr[e];
+        Cand b;
+        b.D = __builtin_inf();
+        b.Z = 0.0;
+        b.id = INT32_MAX;
+        b.start = 0;
+        b.deg = 0;
+        for (int i = sub; i < deg; i += TRACE_GL) {
+            const NbrRec rec = nbr[e0 + i];
+            const int2 nrow = rows[rec.id];
             const double Rx = rec.x - ox, Ry = rec.y - oy, Rz = rec.z - oz;
             const double Zk = (Rx * dx + Ry * dy) + Rz * dz;
             if (!(Zk > Zc)) continue;
             const double qx = Rx - Zk * dx, qy = Ry - Zk * dy, qz = Rz - Zk * dz;
             const double Dk = (qx * qx + qy * qy) + qz * qz;
-            if (best < 0 || Dk < bestD || (Dk == bestD && rec.id < best)) {
-                best = rec.id;
-                bestD = Dk;
-                bestZ = Zk;
+            if (Dk < b.D || (Dk == b.D && rec.id < b.id)) {
+                b.D = Dk;
+                b.Z = Zk;
+                b.id = rec.id;
+                b.start = nrow.x;
+                b.deg = nrow.y;
             }
         }
-        if (best < 0) break;
-        if (WRITE) {
+        cand_merge<DPP_HALF_MIRROR>(b);
+        cand_merge<DPP_SWAP1>(b);
+        cand_merge<DPP_SWAP2>(b);
+        if (b.id == INT32_MAX) break;
+        if (MODE != TRACE_COUNT) {
             if (n < room) {
-                ids[base + n] = best;
-                Zout[base + n] = bestZ;
+                if (sub == 0) {
+                    ids[base + n] = b.id;
+                    Zout[base + n] = b.Z;
+                }
             } else {
-                atomicOr(err, ERRBIT_CAPACITY);
+                if (sub == 0) atomicOr(err, ERRBIT_CAPACITY);
                 break;
             }
         }
         ++n;
-        c = best;
-        Zc = bestZ;
+        e0 = b.start;
+        deg = b.deg;
+        Zc = b.Z;
     }
-    if (!WRITE) lens[ray] = (int32_t)n;
+    if (MODE != TRACE_WRITE && sub == 0) lens[ray] = n;
+}
+
+// Padded slots (ray * cap) -> compacted lists at ray_off.  Eight lanes per ray.
+__global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ pids, const double* __restrict__ pZ,
+                                                  int64_t cap, const int64_t* __restrict__ ray_off, int64_t n_rays,
+                                                  int32_t* __restrict__ ids, double* __restrict__ Z) {
+    const int sub = threadIdx.x & 7;
+    const int64_t ray = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 3;
+    if (ray >= n_rays) return;
+    const int64_t b = ray_off[ray], n = ray_off[ray + 1] - b;
+    const int64_t src = ray * cap;
+    for (int64_t j = sub; j < n && j < cap; j += 8) {
+        ids[b + j] = pids[src + j];
+        Z[b + j] = pZ[src + j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_build_rows(const int64_t* __restrict__ off, int64_t P,
+                                                     int2* __restrict__ rows) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    rows[p] = make_int2((int)off[p], (int)(off[p + 1] - off[p]));
 }
 
 // ---------------------------------------------------------------- scan
@@ -212,6 +317,7 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 }  // namespace
 
 hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_rows, dim3(blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
     if (m->E > 0)
         hipLaunchKernelGGL(k_build_nbr, dim3(blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
                            m->E, m->nbr, bad);
@@ -219,24 +325,44 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
-                              const double* dirs, int per_origin, int32_t* lens, hipStream_t s) {
-    int64_t n = n_origins * 2 * R;
+template <int MODE>
+static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                               const double* dirs, int per_origin, int32_t* lens, const int64_t* ray_off,
+                               int32_t* ids, double* Z, int64_t capacity, const int32_t* order, hipStream_t s) {
+    const int64_t n = n_origins * 2 * R;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trace<false>, dim3(blocks_for(n, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos, m->off,
-                       m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, nullptr, nullptr, nullptr,
-                       (int64_t)0, nullptr);
+    hipLaunchKernelGGL((k_trace<MODE>), dim3(blocks_for(n * TRACE_GL, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+                       m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z, capacity,
+                       MODE == TRACE_COUNT ? nullptr : error_word(), order, num_xcds());
     return hipGetLastError();
+}
+
+hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                              const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
+                              const int32_t* order) {
+    return trace_launch<TRACE_COUNT>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, nullptr, nullptr, 0,
+                                     order, s);
 }
 
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
-                              double* Z, int64_t capacity, hipStream_t s) {
-    int64_t n = n_origins * 2 * R;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trace<true>, dim3(blocks_for(n, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos, m->off,
-                       m->nbr, m->P, origins, n_origins, R, dirs, per_origin, nullptr, ray_off, ids, Z, capacity,
-                       error_word());
+                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order) {
+    return trace_launch<TRACE_WRITE>(m, origins, n_origins, R, dirs, per_origin, nullptr, ray_off, ids, Z, capacity,
+                                     order, s);
+}
+
+hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
+                               const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
+                               int64_t cap, hipStream_t s, const int32_t* order) {
+    return trace_launch<TRACE_PADDED>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, pids, pZ, cap, order,
+                                      s);
+}
+
+hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
+                          int32_t* ids, double* Z, hipStream_t s) {
+    if (n_rays == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_rays * 8, 256)), dim3(256), 0, s, pids, pZ, cap, ray_off, n_rays,
+                       ids, Z);
     return hipGetLastError();
 }
 

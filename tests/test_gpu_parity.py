@@ -234,8 +234,8 @@ def test_binned_schedule_bitwise_equal_direct(rt, orc, wind, prec):
         assert np.array_equal(Jd, Jb)
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
-def test_plan_graph_replays(rt, orc, wind, schedule):
+@pytest.mark.parametrize("schedule,padded", [(0, 0), (1, 0), (1, -1), (2, 0), (2, -1)])
+def test_plan_graph_replays(rt, orc, wind, schedule, padded):
     torch = _torch()
     origins = np.arange(0, wind.P, 50).astype(np.int32)
     model = _gpu_model(rt, wind)
@@ -246,7 +246,7 @@ def test_plan_graph_replays(rt, orc, wind, schedule):
     org = _t(origins)
     J = torch.empty((len(origins), wind.F), dtype=torch.float32, device="cuda")
     plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=org,
-                   precision=rt.RT_F32, schedule=schedule)
+                   precision=rt.RT_F32, schedule=schedule, padded_trace_budget=padded)
     ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
                        precision=rt.RT_F32).cpu().numpy()
     plan.run(use_graph=False)
@@ -264,7 +264,7 @@ def test_plan_graph_replays(rt, orc, wind, schedule):
     e = orc.trace_all(wind, dirs, origins)
     _assert_rays_equal((off, ids, Z), e)
     prof = plan.profile(2)
-    assert prof["sweep"] > 0 and prof["count"] > 0
+    assert prof["sweep"] > 0 and prof["walk"] > 0
 
 
 def test_empty_origin_list(rt):
