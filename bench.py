@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--nside", type=int, default=NSIDE)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (for scaling HBM counters) and exit")
+    ap.add_argument("--group", type=int, default=0, help="sweep load-group size (4 or 8; 0 = library default)")
+    ap.add_argument("--trace-lanes", type=int, default=0, help="lanes per ray in the walk (4 or 8; 0 = default)")
     ap.add_argument("--two-pass-trace", action="store_true",
                     help="walk every ray twice (count, then write) instead of once into padded slots")
     ap.add_argument("--fp64-below", type=float, default=1e-4,
@@ -135,7 +137,8 @@ def main():
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
                    schedule=sched, dtau_fp64_below=args.fp64_below,
-                   padded_trace_budget=-1 if args.two_pass_trace else 0)
+                   padded_trace_budget=-1 if args.two_pass_trace else 0, group=args.group,
+                   trace_lanes=args.trace_lanes)
     total = plan.info()["total"]
 
     for _ in range(args.warmup):

@@ -103,8 +103,9 @@ rt_status rt_dirset_destroy(rt_dirset* set);
  * Borrows the caller's device arrays for the handle's lifetime.  Validates the
  * neighbour lists on the device (indices in range, no self entries) and
  * synchronises once on `stream` to read the verdict.  Builds a neighbour-
- * position table (24 bytes per neighbour entry) that the tracer reads instead
- * of chasing nbr_idx into pos. */
+ * record table (48 bytes per neighbour entry: position, id, the neighbour's
+ * own row) that the tracer reads instead of chasing nbr_idx into pos and
+ * nbr_off.  The positions and lists must not change while the handle lives. */
 rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
                           int64_t E, const float* vel, void* stream, rt_model** out);
 rt_status rt_model_destroy(rt_model* model);
@@ -162,8 +163,10 @@ rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int3
  * J[o][f] = sum_r w2_r u_r[f], summed in ascending r (eq. 3, eq. 4).
  *
  * precision RT_F64: all FP64 (tables must be RT_F64).  RT_F32: tables RT_F32,
- * sweep in FP32, except that rows where min(dtau_{d-1}, dtau_d) < dtau_fp64_below
- * are eliminated in FP64; ds is always formed in FP64 from the FP64 Z. */
+ * sweep in FP32, except that for rows where some frequency of the 64-wide
+ * chunk has min(dtau_{d-1}, dtau_d) < dtau_fp64_below the elimination
+ * coefficients are evaluated in FP64; ds is always formed in FP64 from the
+ * FP64 Z. */
 typedef struct {
     int32_t n_blocks;
     const int32_t* len; /* host [n_blocks] */
@@ -183,6 +186,8 @@ typedef struct {
     double dtau_fp64_below;   /* FP32 path: rows with a smaller dtau are eliminated in FP64 (e.g. 1e-4) */
     int32_t waves_per_cu;     /* persistent grid size (0 = default) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
+    int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 4) */
+    int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */
     int64_t padded_trace_budget; /* plans only: bytes allowed for single-pass tracing into padded
                                     per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB,
                                     < 0 = always trace in two passes (count, then write) */

@@ -330,6 +330,8 @@ static rt_solve_opts default_opts() {
     o.dtau_fp64_below = 1e-4;
     o.waves_per_cu = 0;
     o.n_bins = 0;
+    o.group = 0;
+    o.trace_lanes = 0;
     o.padded_trace_budget = 0;
     return o;
 }
@@ -402,6 +404,8 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;
     a.grid_waves = num_cus() * wpc;
     a.n_xcd = num_xcds();
+    if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
+    a.group = o.group ? o.group : 4;
     a.err = error_word();
     if (!a.err) return fail(RT_ERR_HIP, "solve: no device error word");
     return RT_OK;
@@ -520,10 +524,10 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
     if (e == hipSuccess) {
         if (p->pids)
             e = launch_trace_padded(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->lens, p->pids,
-                                    p->pZ, p->cap, s, p->order);
+                                    p->pZ, p->cap, s, p->order, p->o.trace_lanes);
         else
             e = launch_trace_count(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->lens, s,
-                                   p->order);
+                                   p->order, p->o.trace_lanes);
     }
     mark(1);
     if (e == hipSuccess) e = launch_scan(p->lens, p->n_rays, p->ray_off, p->scan_ws, s);
@@ -533,7 +537,7 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
             e = launch_compact(p->pids, p->pZ, p->cap, p->ray_off, p->n_rays, p->ids, p->Z, s);
         else
             e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->ray_off,
-                                   p->ids, p->Z, p->total, s, p->order);
+                                   p->ids, p->Z, p->total, s, p->order, p->o.trace_lanes);
     }
     mark(3);
     SolveLaunch a = p->a;

@@ -70,9 +70,14 @@ struct rt_dirset {
     const double* d_w2() const { return dev.w2; }
 };
 
-struct NbrRec {
+// One neighbour entry as the tracer reads it: the neighbour's position, its
+// id, and its own CSR row (start, degree), so a step needs no further load to
+// continue from the chosen neighbour.
+struct alignas(16) NbrRec {
     double x, y, z;
     int32_t id;
+    int32_t start;
+    int32_t deg;
     int32_t pad;
 };
 
@@ -97,13 +102,14 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s);
 // rays are then walked direction-major in that origin order.
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
-                              const int32_t* order = nullptr);
+                              const int32_t* order = nullptr, int gl = 8);
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
-                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order = nullptr);
+                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order = nullptr,
+                              int gl = 8);
 hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
-                               int64_t cap, hipStream_t s, const int32_t* order = nullptr);
+                               int64_t cap, hipStream_t s, const int32_t* order = nullptr, int gl = 8);
 hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
                           int32_t* ids, double* Z, hipStream_t s);
 size_t scan_workspace(int64_t n);
@@ -144,6 +150,7 @@ struct SolveLaunch {
     int32_t* err;          // device error word
     int64_t P;             // number of points (origin ids are checked against it)
     int n_xcd;             // XCDs for the block renumbering of the direct launch
+    int group;             // sweep load-group size (4 or 8)
 };
 int64_t solve_items(const SolveLaunch& a);
 size_t bin_workspace(int64_t n_items, int32_t n_bins);

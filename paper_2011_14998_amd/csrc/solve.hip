@@ -46,6 +46,23 @@ __device__ inline double readlane_d(double v, int j) {
 
 __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 
+__device__ inline int64_t readlane_64(int64_t v, int j) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_readlane(p.x, j);
+    p.y = __builtin_amdgcn_readlane(p.y, j);
+    return __builtin_bit_cast(int64_t, p);
+}
+
+// Values every lane holds identically, moved to scalar registers so that the
+// compiler keeps loop bounds and branches on them scalar.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni64(int64_t v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_readfirstlane(p.x);
+    p.y = __builtin_amdgcn_readfirstlane(p.y);
+    return __builtin_bit_cast(int64_t, p);
+}
+
 template <typename T>
 __device__ inline T readlane_t(T v, int j);
 template <>
@@ -99,13 +116,6 @@ __device__ inline double rcp64(double x) {
     return r;
 }
 
-// FP64 reciprocal seeded by the FP32 one (relative error ~1e-7) and refined by
-// one Newton step to ~1e-14: the FP64 rows of the FP32 sweep.
-__device__ inline double rcp64_from32(double x) {
-    double r = (double)__builtin_amdgcn_rcpf((float)x);
-    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
-}
-
 template <typename T>
 __device__ inline T rcp(T x);
 template <>
@@ -141,33 +151,34 @@ __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
     st.ra = rcp<T>(b);
 }
 
-// The same row with its coefficients and update in FP64 (FP32 state in and out).
-__device__ inline void row_fp64(SweepState<float>& st, bool far_end, float b, float S, float I) {
-    const double bd = b, ad = st.a;
-    double F, Z, r1;
+// The same row with its elimination coefficients -- b(a+b)/2 and b/a, or at the
+// far end b(1+b/2) and b^2/2 -- evaluated in FP64 and rounded once; the
+// recurrence itself stays FP32.  Used for rows with tiny optical-depth steps.
+__device__ inline void row_coef64(SweepState<float>& st, bool far_end, float b, float S, float I) {
+    const double bd = b;
     if (far_end) {
-        F = bd * (1.0 + 0.5 * bd);
-        r1 = rcp64_from32(1.0 + F);
-        Z = (0.5 * bd * bd * (double)S + bd * (double)I) * r1;
+        st.F = (float)(bd * (1.0 + 0.5 * bd));
+        const float h = (float)(0.5 * bd * bd);
+        st.r1 = __builtin_amdgcn_rcpf(1.0f + st.F);
+        st.Z = (h * S + b * I) * st.r1;
     } else {
-        const double F0 = st.F;
-        const double hb = 0.5 * bd * (ad + bd);
-        const double ba = bd * rcp64_from32(ad);
-        F = hb + ba * (F0 * rcp64_from32(1.0 + F0));
-        r1 = rcp64_from32(1.0 + F);
-        Z = (hb * (double)S + ba * (double)st.Z) * r1;
+        const double ad = st.a;
+        const double ra = __builtin_fma((double)st.ra, __builtin_fma(-ad, (double)st.ra, 1.0), (double)st.ra);
+        const float hb = (float)(0.5 * bd * (ad + bd));
+        const float ba = (float)(bd * ra);
+        st.F = hb + ba * (st.F * st.r1);
+        const float Zn = hb * S + ba * st.Z;
+        st.r1 = __builtin_amdgcn_rcpf(1.0f + st.F);
+        st.Z = Zn * st.r1;
     }
-    st.F = (float)F;
-    st.Z = (float)Z;
-    st.r1 = (float)r1;
     st.a = b;
     st.ra = __builtin_amdgcn_rcpf(b);
 }
 
 // Precision policy.  FP64 sweep: plain rows.  FP32 sweep: when any lane of the
 // wave has a step below the threshold (min(a, b), or b at the far end) the
-// whole wave eliminates this row in FP64 -- the row is the same for every lane
-// of the chunk, so a wave-uniform choice costs one path instead of two.
+// wave computes this row's coefficients in FP64 -- one path per wave instead of
+// two divergent ones.
 template <typename T>
 __device__ inline void row_policy(SweepState<T>& st, bool far_end, T b, T S, T I, float thr) {
     row<T>(st, far_end, b, S, I);
@@ -176,9 +187,15 @@ __device__ inline void row_policy(SweepState<T>& st, bool far_end, T b, T S, T I
 template <>
 __device__ inline void row_policy<float>(SweepState<float>& st, bool far_end, float b, float S, float I,
                                          float thr) {
-    const float m = far_end ? b : fminf(st.a, b);
-    if (__builtin_amdgcn_ballot_w64(m < thr)) row_fp64(st, far_end, b, S, I);
-    else row<float>(st, far_end, b, S, I);
+    // far_end is the same in every lane: a scalar branch
+    if (far_end) {
+        if (__builtin_amdgcn_ballot_w64(b < thr)) row_coef64(st, true, b, S, I);
+        else row<float>(st, true, b, S, I);
+    } else {
+        const float m = st.a < b ? st.a : b;
+        if (__builtin_amdgcn_ballot_w64(m < thr)) row_coef64(st, false, b, S, I);
+        else row<float>(st, false, b, S, I);
+    }
 }
 
 // u at the origin from the two sides' states (file header).
@@ -200,17 +217,23 @@ __device__ inline T origin_u(bool hm, bool hp, const SweepState<T>& m, const Swe
     return I;
 }
 
-__device__ inline float origin_u_fp64(bool hm, bool hp, const SweepState<float>& m, const SweepState<float>& p,
-                                      float S, float I) {
-    const double a = m.a, b = p.a, Sd = S, Id = I;
-    const double Fm = m.F, Fp = p.F, Zm = m.Z, Zp = p.Z;
+// Origin row with its coefficients h = ab(a+b)/2 (or t^2/2) in FP64, rounded once.
+__device__ inline float origin_u_coef64(bool hm, bool hp, const SweepState<float>& m, const SweepState<float>& p,
+                                        float S, float I) {
+    const double a = m.a, b = p.a;
     if (hm && hp) {
-        const double h = 0.5 * a * b * (a + b);
-        return (float)((h * Sd + b * Zm + a * Zp) *
-                       rcp64(h + b * (Fm * rcp64(1.0 + Fm)) + a * (Fp * rcp64(1.0 + Fp))));
+        const float h = (float)(0.5 * a * b * (a + b));
+        return (h * S + p.a * m.Z + m.a * p.Z) *
+               __builtin_amdgcn_rcpf(h + p.a * (m.F * m.r1) + m.a * (p.F * p.r1));
     }
-    if (hp) return (float)((0.5 * b * b * Sd + b * Id + Zp) * rcp64(0.5 * b * b + b + Fp * rcp64(1.0 + Fp)));
-    if (hm) return (float)((0.5 * a * a * Sd + a * Id + Zm) * rcp64(0.5 * a * a + a + Fm * rcp64(1.0 + Fm)));
+    if (hp) {
+        const float h = (float)(0.5 * b * b);
+        return (h * S + p.a * I + p.Z) * __builtin_amdgcn_rcpf(h + p.a + p.F * p.r1);
+    }
+    if (hm) {
+        const float h = (float)(0.5 * a * a);
+        return (h * S + m.a * I + m.Z) * __builtin_amdgcn_rcpf(h + m.a + m.F * m.r1);
+    }
     return I;
 }
 
@@ -224,11 +247,10 @@ template <>
 __device__ inline float origin_policy<float>(bool hm, bool hp, const SweepState<float>& m,
                                              const SweepState<float>& p, float S, float I, float thr) {
     const float mn = (hm && hp) ? fminf(m.a, p.a) : (hp ? p.a : m.a);
-    if ((hm || hp) && __builtin_amdgcn_ballot_w64(mn < thr)) return origin_u_fp64(hm, hp, m, p, S, I);
+    if ((hm || hp) && __builtin_amdgcn_ballot_w64(mn < thr)) return origin_u_coef64(hm, hp, m, p, S, I);
     return origin_u<float>(hm, hp, m, p, S, I);
 }
 
-constexpr int GROUP = 8;  // line points whose loads are issued together
 
 // Per-wave constants of one item.
 struct ItemCtx {
@@ -250,7 +272,10 @@ struct ItemCtx {
 // UDX: every frequency block has the same dx, so the Doppler shift of a point
 // (whole steps k and fraction t) is the same in every lane and is computed
 // once per point while the 64-point segment is staged.
-template <typename T, bool MOVING, bool UDX>
+// GROUP line points have their loads issued together before the recurrence
+// consumes them (a tuning parameter: more points in flight per wave against
+// more registers, i.e. fewer waves).
+template <typename T, bool MOVING, bool UDX, int GROUP>
 __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
                              SweepState<T>& st) {
     T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
@@ -262,10 +287,12 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
         const int e = hi - lane;
         const bool v = lane < cnt;
         int q_l = 0, k_l = 0;
+        int64_t row_l = 0;
         T ds_l = (T)0, t_l = (T)0;
         double dot_l = 0.0;
         if (v) {
             q_l = c.ids[base + e];
+            row_l = (int64_t)q_l * c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
             ds_l = (T)(z - zi);  // difference of FP64 projections, rounded once
@@ -288,9 +315,9 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
 #pragma unroll
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
-                    const int q = readlane_i(q_l, j + g);
-                    const char* cr = c.chi + (int64_t)q * c.ld_bytes;
-                    const char* er = c.eta + (int64_t)q * c.ld_bytes;
+                    const int64_t row = readlane_64(row_l, j + g);
+                    const char* cr = c.chi + row;
+                    const char* er = c.eta + row;
                     dsv[g] = readlane_t<T>(ds_l, j + g);
                     if (MOVING) {
                         int k;
@@ -349,20 +376,23 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     }
 }
 
-template <typename T, bool MOVING, bool UDX>
+template <typename T, bool MOVING, bool UDX, int GROUP>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane) {
+    // w is the same in every lane of the wave
+    w = uni64(w);
     const int fc = (int)(w % nfc);
     const int64_t pr = w / nfc;
     const int64_t r = pr % a.R;
     const int64_t oi = pr / a.R;
     const LaneFreq lf = lane_freq(a, fc, lane);
-    const int64_t o = a.origins ? (int64_t)a.origins[oi] : oi;
+    const int64_t o = a.origins ? (int64_t)uni(a.origins[oi]) : oi;
     if (o < 0 || o >= a.P) {
         if (lane == 0) atomicOr(a.err, ERRBIT_ORIGIN);
         return;
     }
     const int64_t slot_p = oi * 2 * a.R + 2 * r;
-    const int64_t bp = a.ray_off[slot_p], bm = a.ray_off[slot_p + 1], be = a.ray_off[slot_p + 2];
+    const int64_t bp = uni64(a.ray_off[slot_p]), bm = uni64(a.ray_off[slot_p + 1]);
+    const int64_t be = uni64(a.ray_off[slot_p + 2]);
     const int np = (int)(bm - bp), nm = (int)(be - bm);
     ItemCtx c;
     c.chi = (const char*)a.chi;
@@ -387,8 +417,8 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     const T chi_o = ((const T*)a.chi)[o * a.ld + lf.f];
     const T S_o = ((const T*)a.eta)[o * a.ld + lf.f] * rcp<T>(chi_o);
     SweepState<T> m{}, p{};
-    sweep<T, MOVING, UDX>(c, bm, nm, lf, lane, chi_o, I, m);
-    sweep<T, MOVING, UDX>(c, bp, np, lf, lane, chi_o, I, p);
+    sweep<T, MOVING, UDX, GROUP>(c, bm, nm, lf, lane, chi_o, I, m);
+    sweep<T, MOVING, UDX, GROUP>(c, bp, np, lf, lane, chi_o, I, p);
     const T u = origin_policy<T>(nm > 0, np > 0, m, p, S_o, I, c.thr);
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
@@ -396,7 +426,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
 }
 
-template <typename T, bool MOVING, bool UDX>
+template <typename T, bool MOVING, bool UDX, int GROUP>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -405,13 +435,13 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
     const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
     if (it >= n_items) return;
     const int64_t w = a.items ? (int64_t)a.items[it] : it;
-    solve_item<T, MOVING, UDX>(a, w, nfc, lane);
+    solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
 // takes the next item with one atomic and exits when the queue is empty, so
 // every wave reaches the end.
-template <typename T, bool MOVING, bool UDX>
+template <typename T, bool MOVING, bool UDX, int GROUP>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -422,7 +452,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
     }
 }
 
@@ -536,13 +566,13 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
-template <typename T>
-static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
+template <typename T, int G>
+static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     const bool moving = a.vel != nullptr;
     // the shift of a point is lane-independent when every block has the same dx
     bool udx = true;
     for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
-#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G>), grid, dim3(SOLVE_BLOCK), 0, s, a)
     if (persist) {
         if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
         else if (moving) RT_LAUNCH(k_solve_persist, true, false);
@@ -553,6 +583,12 @@ static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStr
         else RT_LAUNCH(k_solve_direct, false, true);
     }
 #undef RT_LAUNCH
+}
+
+template <typename T>
+static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
+    if (a.group == 4) solve_dispatch_g<T, 4>(a, persist, grid, s);
+    else solve_dispatch_g<T, 8>(a, persist, grid, s);
 }
 
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s) {

@@ -8,12 +8,13 @@
 // (this file is compiled with -ffp-contract=off as well), so every list is
 // bit-identical to any other evaluation of the same rule.
 //
-// Data layout: neighbour records {x, y, z, id} (32 bytes) in CSR order and a
-// per-point {row start, degree} table, both built once per model, so a step
-// reads one record per neighbour instead of an index and then a position; a
-// group of 8 lanes reads a point's whole row (~15 records, ~500 contiguous
-// bytes) per step.  The tables of a 50k-point Delaunay mesh (~25 MB) stay in
-// the Infinity cache; the walk is latency bound.
+// Data layout: neighbour records {x, y, z, id, row start, degree} (48 bytes)
+// in CSR order and a per-point {row start, degree} table, both built once per
+// model, so a step reads one record per neighbour instead of an index, a
+// position and the next row's offsets; a group of 8 lanes reads a point's whole
+// row (~15 records, ~740 contiguous bytes) per step.  The tables of a
+// 50k-point Delaunay mesh (~37 MB) stay in the Infinity cache; the walk is
+// latency bound.
 #include "rt_internal.h"
 
 #pragma clang fp contract(off)
@@ -40,6 +41,8 @@ __global__ __launch_bounds__(256) void k_build_nbr(const double* __restrict__ po
     r.y = pos[3 * (int64_t)k + 1];
     r.z = pos[3 * (int64_t)k + 2];
     r.id = k;
+    r.start = (int32_t)off[k];
+    r.deg = (int32_t)(off[k + 1] - off[k]);
     r.pad = 0;
     nbr[e] = r;
 }
@@ -57,17 +60,17 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
         if (idx[e] == p) atomicOr(bad, 4);
 }
 
-// Eight lanes walk one ray (eight rays per wavefront).  At every step lane s
-// takes neighbours s, s+8, ... of the current point's row (contiguous records,
-// so a group reads whole cache lines), keeps its best forward candidate
-// together with that candidate's own CSR row (start, degree; loaded at the same
-// time, so no load depends on the step's outcome), and the group reduces to
-// the lexicographic minimum of (D, id) with DPP lane permutations inside each
-// 8-lane half-row: mirror, then swap neighbours, then swap pairs.  The result
+// GL lanes (4, 8 or 16) walk one ray.  At every step lane s takes neighbours s,
+// s+GL, ... of the current point's row (contiguous records, so a group reads
+// whole cache lines; a lane's loads are issued four at a time), keeps its best
+// forward candidate together with that candidate's own CSR row (start,
+// degree, held in the record, so the next step's loads depend on nothing
+// else), and the group reduces to the lexicographic minimum of (D, id) with
+// DPP lane permutations: (16 lanes: mirror within the row; 8 or 16: mirror
+// within the half-row), then swap neighbours, then swap pairs.  The result
 // equals a sequential scan of the row.
 enum TraceMode { TRACE_COUNT = 0, TRACE_WRITE = 1, TRACE_PADDED = 2 };
 
-constexpr int TRACE_GL = 8;
 
 template <int CTRL>
 __device__ inline int dpp_i(int v) {
@@ -98,6 +101,7 @@ __device__ inline void cand_merge(Cand& b) {
     if (o.D < b.D || (o.D == b.D && o.id < b.id)) b = o;
 }
 
+constexpr int DPP_ROW_MIRROR = 0x140;   // lane i <-> 15-i within each 16 lanes
 constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
 constexpr int DPP_SWAP1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int DPP_SWAP2 = 0x4E;         // quad_perm [2,3,0,1]
@@ -107,7 +111,7 @@ constexpr int DPP_SWAP2 = 0x4E;         // quad_perm [2,3,0,1]
 // L / n_origins of origin order[L % n_origins]: concurrent waves walk nearby
 // origins in the same direction and share most of the rows they read.  Blocks
 // are renumbered so that each XCD (own L2) gets a contiguous range of rays.
-template <int MODE>
+template <int MODE, int GL>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
                                                         const NbrRec* __restrict__ nbr, int64_t P,
@@ -117,9 +121,11 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                                                         int32_t* __restrict__ ids, double* __restrict__ Zout,
                                                         int64_t capacity, int32_t* __restrict__ err,
                                                         const int32_t* __restrict__ order, int n_xcd) {
-    const int sub = threadIdx.x & (TRACE_GL - 1);
+    static_assert(GL == 4 || GL == 8 || GL == 16, "4, 8 or 16 lanes per ray");
+    constexpr int U = 32 / GL;  // candidates per lane per pass: a whole row of up to 32 in one round of loads
+    const int sub = threadIdx.x & (GL - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd);
-    const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / TRACE_GL;
+    const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
     const int64_t two_r = 2 * R;
     if (L >= n_origins * two_r) return;  // whole groups leave together
     int64_t oi, rr;
@@ -149,43 +155,56 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
         dz = -dz;
     }
     const double ox = pos[3 * o], oy = pos[3 * o + 1], oz = pos[3 * o + 2];
-    int64_t base = 0, room = 0;
+    int64_t base = 0;
+    int32_t room = 0;
     if (MODE == TRACE_WRITE) {
         base = ray_off[ray];
-        room = ray_off[ray + 1] - base;
-        if (base + room > capacity) room = capacity - base;
+        int64_t rm = ray_off[ray + 1] - base;
+        if (base + rm > capacity) rm = capacity - base;
+        room = (int32_t)(rm < 0 ? 0 : rm);
     } else if (MODE == TRACE_PADDED) {
         base = ray * capacity;  // capacity = slots per ray
-        room = capacity;
+        room = (int32_t)capacity;
     }
     const int2 row0 = rows[o];
     int32_t e0 = row0.x, deg = row0.y;
     int32_t n = 0;
     double Zc = 0.0;
-    for (int64_t step = 0; step < P; ++step) {
+    for (int32_t step = 0; step < (int32_t)P; ++step) {
         Cand b;
         b.D = __builtin_inf();
         b.Z = 0.0;
         b.id = INT32_MAX;
         b.start = 0;
         b.deg = 0;
-        for (int i = sub; i < deg; i += TRACE_GL) {
-            const NbrRec rec = nbr[e0 + i];
-            const int2 nrow = rows[rec.id];
-            const double Rx = rec.x - ox, Ry = rec.y - oy, Rz = rec.z - oz;
-            const double Zk = (Rx * dx + Ry * dy) + Rz * dz;
-            if (!(Zk > Zc)) continue;
-            const double qx = Rx - Zk * dx, qy = Ry - Zk * dy, qz = Rz - Zk * dz;
-            const double Dk = (qx * qx + qy * qy) + qz * qz;
-            if (Dk < b.D || (Dk == b.D && rec.id < b.id)) {
-                b.D = Dk;
-                b.Z = Zk;
-                b.id = rec.id;
-                b.start = nrow.x;
-                b.deg = nrow.y;
+        // GL lanes x U candidates per pass (32 entries); a lane's U loads are issued together
+        for (int32_t i0 = 0; i0 < deg; i0 += U * GL) {
+            NbrRec rec[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t i = i0 + u * GL + sub;
+                if (i < deg) rec[u] = nbr[e0 + i];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t i = i0 + u * GL + sub;
+                if (i >= deg) continue;
+                const double Rx = rec[u].x - ox, Ry = rec[u].y - oy, Rz = rec[u].z - oz;
+                const double Zk = (Rx * dx + Ry * dy) + Rz * dz;
+                if (!(Zk > Zc)) continue;
+                const double qx = Rx - Zk * dx, qy = Ry - Zk * dy, qz = Rz - Zk * dz;
+                const double Dk = (qx * qx + qy * qy) + qz * qz;
+                if (Dk < b.D || (Dk == b.D && rec[u].id < b.id)) {
+                    b.D = Dk;
+                    b.Z = Zk;
+                    b.id = rec[u].id;
+                    b.start = rec[u].start;
+                    b.deg = rec[u].deg;
+                }
             }
         }
-        cand_merge<DPP_HALF_MIRROR>(b);
+        if (GL == 16) cand_merge<DPP_ROW_MIRROR>(b);
+        if (GL >= 8) cand_merge<DPP_HALF_MIRROR>(b);
         cand_merge<DPP_SWAP1>(b);
         cand_merge<DPP_SWAP2>(b);
         if (b.id == INT32_MAX) break;
@@ -328,34 +347,45 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
 template <int MODE>
 static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, const int64_t* ray_off,
-                               int32_t* ids, double* Z, int64_t capacity, const int32_t* order, hipStream_t s) {
+                               int32_t* ids, double* Z, int64_t capacity, const int32_t* order, int gl, hipStream_t s) {
     const int64_t n = n_origins * 2 * R;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_trace<MODE>), dim3(blocks_for(n * TRACE_GL, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
-                       m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z, capacity,
-                       MODE == TRACE_COUNT ? nullptr : error_word(), order, num_xcds());
+    if (gl != 4 && gl != 16) gl = 8;
+    int32_t* ew = MODE == TRACE_COUNT ? nullptr : error_word();
+    if (gl == 16)
+        hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(blocks_for(n * 16, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           capacity, ew, order, num_xcds());
+    else if (gl == 8)
+        hipLaunchKernelGGL((k_trace<MODE, 8>), dim3(blocks_for(n * 8, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           capacity, ew, order, num_xcds());
+    else
+        hipLaunchKernelGGL((k_trace<MODE, 4>), dim3(blocks_for(n * 4, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           capacity, ew, order, num_xcds());
     return hipGetLastError();
 }
 
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
-                              const int32_t* order) {
+                              const int32_t* order, int gl) {
     return trace_launch<TRACE_COUNT>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, nullptr, nullptr, 0,
-                                     order, s);
+                                     order, gl, s);
 }
 
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
-                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order) {
+                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order, int gl) {
     return trace_launch<TRACE_WRITE>(m, origins, n_origins, R, dirs, per_origin, nullptr, ray_off, ids, Z, capacity,
-                                     order, s);
+                                     order, gl, s);
 }
 
 hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
-                               int64_t cap, hipStream_t s, const int32_t* order) {
+                               int64_t cap, hipStream_t s, const int32_t* order, int gl) {
     return trace_launch<TRACE_PADDED>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, pids, pZ, cap, order,
-                                      s);
+                                      gl, s);
 }
 
 hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,

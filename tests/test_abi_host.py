@@ -110,9 +110,9 @@ def test_workspace_queries(lib):
     sz = C.c_size_t()
     assert L.rt_trace_count_workspace(d._h, 1000, C.byref(sz)) == 0
     assert sz.value >= 1000 * 2 * 24 * 4
-    o = lib.SolveOptsC(lib.RT_F32, lib.SCHED_DIRECT, 1e-4, 0, 0, 0)
+    o = lib.SolveOptsC(lib.RT_F32, lib.SCHED_DIRECT, 1e-4, 0, 0, 0, 0, 0)
     assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
     assert sz.value >= 1000 * 24 * 64 * 4
-    o = lib.SolveOptsC(lib.RT_F64, lib.SCHED_BINNED, 1e-4, 0, 0, 0)
+    o = lib.SolveOptsC(lib.RT_F64, lib.SCHED_BINNED, 1e-4, 0, 0, 0, 0, 0)
     assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
     assert sz.value >= 1000 * 24 * 64 * 8 + 1000 * 24 * 4

@@ -234,8 +234,9 @@ def test_binned_schedule_bitwise_equal_direct(rt, orc, wind, prec):
         assert np.array_equal(Jd, Jb)
 
 
-@pytest.mark.parametrize("schedule,padded", [(0, 0), (1, 0), (1, -1), (2, 0), (2, -1)])
-def test_plan_graph_replays(rt, orc, wind, schedule, padded):
+@pytest.mark.parametrize("schedule,padded,lanes,group", [(0, 0, 4, 8), (1, 0, 8, 4), (1, -1, 16, 8), (2, 0, 8, 4),
+                                                        (2, -1, 4, 4), (2, 0, 16, 8)])
+def test_plan_graph_replays(rt, orc, wind, schedule, padded, lanes, group):
     torch = _torch()
     origins = np.arange(0, wind.P, 50).astype(np.int32)
     model = _gpu_model(rt, wind)
@@ -246,7 +247,8 @@ def test_plan_graph_replays(rt, orc, wind, schedule, padded):
     org = _t(origins)
     J = torch.empty((len(origins), wind.F), dtype=torch.float32, device="cuda")
     plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=org,
-                   precision=rt.RT_F32, schedule=schedule, padded_trace_budget=padded)
+                   precision=rt.RT_F32, schedule=schedule, padded_trace_budget=padded, trace_lanes=lanes,
+                   group=group)
     ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
                        precision=rt.RT_F32).cpu().numpy()
     plan.run(use_graph=False)
