@@ -52,6 +52,96 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
+KERNEL_KEYS = {"sweep": ("k_solve_direct", "k_solve_persist"), "walk": ("k_trace<2",),
+               "compact": ("k_compact",), "reduce": ("k_reduce",)}
+
+
+def _counter_means(csv_path, counter):
+    """Mean per dispatch of `counter` for each kernel family in a rocprofv3 counter CSV."""
+    import csv
+    acc = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            for fam, keys in list(KERNEL_KEYS.items()) + [("copy", ("copyBuffer",))]:
+                if any(k in r["Kernel_Name"] for k in keys):
+                    acc.setdefault(fam, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_counters(d, out_json, out_md):
+    """Write the counter summary of one profiling session (directory d holding the
+    rocprofv3 outputs fetch/, write/, copyf/, copyw/, stats/) to profiles/."""
+    import csv
+    import glob
+    f = _counter_means(glob.glob(os.path.join(d, "fetch", "*counter_collection.csv"))[0], "FETCH_SIZE")
+    w = _counter_means(glob.glob(os.path.join(d, "write", "*counter_collection.csv"))[0], "WRITE_SIZE")
+    cf = _counter_means(glob.glob(os.path.join(d, "copyf", "*counter_collection.csv"))[0], "FETCH_SIZE")
+    cw = _counter_means(glob.glob(os.path.join(d, "copyw", "*counter_collection.csv"))[0], "WRITE_SIZE")
+    # the calibration copy moves exactly 1 GiB each way per dispatch (KiB units)
+    kib = 1 << 20
+    fscale = kib / cf["copy"]
+    wscale = kib / cw["copy"]
+    res = {"kernel_src_hash": src_hash("solve.hip", "rt_internal.h"),
+           "calibration": {"copy_bytes": 1 << 30, "FETCH_SIZE_KiB": cf["copy"], "WRITE_SIZE_KiB": cw["copy"],
+                           "fetch_scale": fscale, "write_scale": wscale},
+           "per_launch": {}}
+    for fam in ("sweep", "walk", "compact", "reduce"):
+        if fam in f and fam in w:
+            rb = f[fam] * 1024 * fscale
+            wb = w[fam] * 1024 * wscale
+            res["per_launch"][fam] = {"FETCH_SIZE_KiB": f[fam], "WRITE_SIZE_KiB": w[fam],
+                                      "hbm_read_bytes": rb, "hbm_write_bytes": wb, "hbm_bytes": rb + wb}
+    res["hbm_bytes_per_launch"] = res["per_launch"]["sweep"]["hbm_bytes"]
+    with open(out_json, "w") as fo:
+        json.dump(res, fo, indent=1)
+    stats = glob.glob(os.path.join(d, "stats", "*kernel_stats.csv"))
+    sq = glob.glob(os.path.join(d, "sq", "*counter_collection.csv"))
+    if stats and out_md:
+        rows = list(csv.DictReader(open(stats[0])))
+        B = "python3 bench.py --steps 5 --warmup 1 --cpu-sample 0"
+        with open(out_md, "w") as fo:
+            fo.write("# Kernel times and HBM traffic: analytic wind, 50 000 points, nside 4, F = 64, FP32 sweep\n\n")
+            fo.write("Session (run from /tmp with TMPDIR=/tmp; every command runs committed files only):\n\n")
+            fo.write(f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats -o bench -- {B}\n")
+            fo.write(f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {B}\n")
+            fo.write(f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {B}\n")
+            fo.write("    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/copyf -o run -- "
+                     "python3 bench.py --copy-calibration 1073741824\n")
+            fo.write("    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/copyw -o run -- "
+                     "python3 bench.py --copy-calibration 1073741824\n")
+            fo.write("    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES "
+                     f"SQ_BUSY_CYCLES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE --output-format csv -d <dir>/sq -o run -- {B}\n")
+            fo.write("    python3 bench.py --summarize-counters <dir> profiles/sweep_wind50k_nside4_counters.json "
+                     "profiles/wind50k_nside4_kernel_stats.md\n\n")
+            fo.write("## rocprofv3 --stats (kernel trace)\n\n")
+            fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
+            for r in rows:
+                fo.write(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |\n")
+            fo.write("\n## HBM traffic per launch (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale)\n\n")
+            c = res["calibration"]
+            fo.write(f"Calibration: a plain 1 GiB device copy reads as FETCH_SIZE {c['FETCH_SIZE_KiB']:.0f} KiB and "
+                     f"WRITE_SIZE {c['WRITE_SIZE_KiB']:.0f} KiB, so fetch_scale = {c['fetch_scale']:.4f}, "
+                     f"write_scale = {c['write_scale']:.4f}.\n\n")
+            fo.write("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read GB | HBM write GB | total GB |\n"
+                     "|---|---|---|---|---|---|\n")
+            for fam, v in res["per_launch"].items():
+                fo.write(f"| {fam} | {v['FETCH_SIZE_KiB']:.0f} | {v['WRITE_SIZE_KiB']:.0f} | "
+                         f"{v['hbm_read_bytes'] / 1e9:.2f} | {v['hbm_write_bytes'] / 1e9:.2f} | "
+                         f"{v['hbm_bytes'] / 1e9:.2f} |\n")
+            if sq:
+                fo.write("\n## SQ counters per launch (sums over the device)\n\n")
+                names = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_BUSY_CYCLES",
+                         "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE"]
+                fo.write("| kernel | " + " | ".join(names) + " |\n|" + "---|" * (len(names) + 1) + "\n")
+                for fam in ("sweep", "walk", "compact"):
+                    vals = [_counter_means(sq[0], n).get(fam, float("nan")) for n in names]
+                    fo.write(f"| {fam} | " + " | ".join(f"{x:.3g}" for x in vals) + " |\n")
+    return res
+
+
 def load_traffic(kernel_hash, launch_bytes_alg):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source."""
@@ -89,6 +179,8 @@ def main():
     ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial")
     ap.add_argument("--cpu-sample", type=int, default=4000, help="origins timed on the CPU oracle (0 = skip)")
     ap.add_argument("--nside", type=int, default=NSIDE)
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("DIR", "OUT_JSON", "OUT_MD"),
+                    help="summarise a rocprofv3 session directory into the profiles/ files and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (for scaling HBM counters) and exit")
     ap.add_argument("--group", type=int, default=0, help="sweep load-group size (4 or 8; 0 = library default)")
@@ -98,6 +190,9 @@ def main():
     ap.add_argument("--fp64-below", type=float, default=1e-4,
                     help="FP32 sweep: rows with an optical-depth step below this are eliminated in FP64")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
                                    "this build (the path shards by origins, see the design notes)",
