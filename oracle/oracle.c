@@ -180,6 +180,222 @@ OR_API int64_t or_dirset_uniform(int64_t nside, int64_t* pix, double* dirs, doub
     return R;
 }
 
+/* ------------------------------------------- pixel lookup for adaptive sets
+ *
+ * The adaptive direction set classifies the directions to sample points into
+ * pixels, so CPU and GPU must classify boundary directions identically.  The
+ * lookup therefore uses a square root and an arctangent built only from IEEE
+ * +, -, *, / in a fixed order (no library transcendental), evaluated
+ * identically by the HIP library:
+ *   fx_sqrt(x):    seed from the exponent bits (bits/2 + bias), then six
+ *                  Newton steps y <- 0.5 (y + x / y).
+ *   fx_atan2(y,x): reduce to t = min/max in [0,1]; if t > tan(pi/8), use
+ *                  t' = (t - 1)/(t + 1) and add pi/4; atan(t') by its Taylor
+ *                  series to t'^43 (Horner in t'^2, coefficient (-1)^k/(2k+1)
+ *                  formed by one division); then undo the octant.
+ * Both agree with the C library to a few ulp (pinned by the tests). */
+static double fx_sqrt(double x) {
+    if (!(x > 0.0)) return 0.0;
+    union { double d; uint64_t u; } b;
+    b.d = x;
+    b.u = (b.u >> 1) + 0x1FF8000000000000ULL;
+    double y = b.d;
+    for (int i = 0; i < 6; ++i) y = 0.5 * (y + x / y);
+    return y;
+}
+
+static double fx_atan2(double y, double x) {
+    double ax = fabs(x), ay = fabs(y);
+    if (ax == 0.0 && ay == 0.0) return 0.0;
+    int swap = ay > ax;
+    double mx = swap ? ay : ax, mn = swap ? ax : ay;
+    double t = mn / mx, base = 0.0;
+    if (t > 0.41421356237309503) {
+        t = (t - 1.0) / (t + 1.0);
+        base = 0.78539816339744831;
+    }
+    double t2 = t * t, p = 0.0;
+    for (int k = 21; k >= 0; --k) {
+        double c = (k & 1 ? -1.0 : 1.0) / (double)(2 * k + 1);
+        p = p * t2 + c;
+    }
+    double r = base + t * p;
+    if (swap) r = 1.5707963267948966 - r;
+    if (x < 0.0) r = 3.1415926535897931 - r;
+    if (y < 0.0) r = -r;
+    return r;
+}
+
+/* Pixel of the direction of (vx, vy, vz) with the fixed-arithmetic lookup. */
+static int64_t fx_vec2pix(int64_t nside, double vx, double vy, double vz) {
+    const int64_t npix = 12 * nside * nside;
+    const int64_t ncap = 2 * nside * (nside - 1);
+    double r = fx_sqrt((vx * vx + vy * vy) + vz * vz);
+    double z = vz / r;
+    double phi = fx_atan2(vy, vx);
+    if (phi < 0.0) phi = phi + 6.2831853071795862;
+    double za = fabs(z);
+    double tt = phi / 1.5707963267948966;
+    if (tt >= 4.0) tt = 0.0;
+    if (za <= 2.0 / 3.0) {
+        double t1 = (double)nside * (0.5 + tt);
+        double t2 = (double)nside * z * 0.75;
+        int64_t jp = (int64_t)floor(t1 - t2);
+        int64_t jm = (int64_t)floor(t1 + t2);
+        int64_t ir = nside + 1 + jp - jm;
+        int64_t kshift = 1 - (ir & 1);
+        int64_t ip = (jp + jm - nside + kshift + 1) / 2;
+        ip = ((ip % (4 * nside)) + 4 * nside) % (4 * nside);
+        return ncap + (ir - 1) * 4 * nside + ip;
+    } else {
+        double tp = tt - floor(tt);
+        double tmp = (double)nside * fx_sqrt(3.0 * (1.0 - za));
+        int64_t jp = (int64_t)floor(tp * tmp);
+        int64_t jm = (int64_t)floor((1.0 - tp) * tmp);
+        int64_t ir = jp + jm + 1;
+        int64_t ip = (int64_t)floor(tt * (double)ir);
+        ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
+        if (z > 0.0) return 2 * ir * (ir - 1) + ip;
+        return npix - 2 * ir * (ir + 1) + ip;
+    }
+}
+
+OR_API double or_fx_sqrt(double x) { return fx_sqrt(x); }
+OR_API double or_fx_atan2(double y, double x) { return fx_atan2(y, x); }
+OR_API int64_t or_fx_vec2pix(int64_t nside, const double* v) { return fx_vec2pix(nside, v[0], v[1], v[2]); }
+
+/* --------------------------------------------------- adaptive direction sets */
+
+typedef struct { int64_t cnt; int64_t pix; } or_key;
+
+static int key_cmp(const void* a, const void* b) {
+    const or_key* x = (const or_key*)a;
+    const or_key* y = (const or_key*)b;
+    if (x->cnt != y->cnt) return x->cnt > y->cnt ? -1 : 1;   /* count descending */
+    return x->pix < y->pix ? -1 : (x->pix > y->pix ? 1 : 0); /* then ring index ascending */
+}
+
+typedef struct { int32_t level; int64_t pix; } or_leaf;
+
+static int leaf_cmp(const void* a, const void* b) {
+    const or_leaf* x = (const or_leaf*)a;
+    const or_leaf* y = (const or_leaf*)b;
+    if (x->level != y->level) return x->level < y->level ? -1 : 1;
+    return x->pix < y->pix ? -1 : (x->pix > y->pix ? 1 : 0);
+}
+
+/* Number of pairs per origin of the adaptive set (lmin, lmax). */
+OR_API int64_t or_dirset_adaptive_R(int32_t lmin, int32_t lmax) {
+    int64_t R = 0, act = 6LL << (2 * lmin);
+    for (int32_t l = lmin; l < lmax; ++l) {
+        R += act / 2;
+        act = 4 * (act / 2);
+    }
+    return R + act;
+}
+
+/* Adaptive direction set per origin (Section 2.1.3, Fig. 1).
+ * For origin i: every sample point s != i with x_s != x_i adds one to the
+ * level-lmax pixel containing x_s - x_i (fixed-arithmetic lookup above).  The
+ * pixel histogram is downgraded to every coarser level by summing the four
+ * children of each pixel (the nested hierarchy).  The count of an antipodal
+ * pair is the sum over both of its pixels.  Starting from every pair at lmin,
+ * at each level the active pairs are ranked by count (descending, ties to the
+ * smaller canonical index) and the first half is refined into the pairs of
+ * their children; the rest become leaves at that level; all active pairs at
+ * lmax are leaves.  Leaves are written ordered by (level, canonical index):
+ * pix, level, direction (centre of the canonical pixel at its level) and pair
+ * weight 2/(12*4^level).  Returns R (pairs per origin). */
+OR_API int64_t or_dirset_adaptive(const double* pos, int64_t P, const int32_t* origins, int64_t n_origins,
+                                  const int32_t* sample, int64_t n_sample, int32_t lmin, int32_t lmax,
+                                  int64_t* pix_out, int32_t* level_out, double* dirs_out, double* w2_out,
+                                  int nthreads) {
+    const int64_t R = or_dirset_adaptive_R(lmin, lmax);
+    const int32_t L = lmax - lmin + 1;
+    int64_t* npix = (int64_t*)malloc(sizeof(int64_t) * L);
+    int64_t** anti = (int64_t**)malloc(sizeof(int64_t*) * L);
+    int64_t** par = (int64_t**)malloc(sizeof(int64_t*) * L);
+    for (int32_t k = 0; k < L; ++k) {
+        int64_t ns = 1LL << (lmin + k);
+        npix[k] = 12 * ns * ns;
+        anti[k] = (int64_t*)malloc(sizeof(int64_t) * npix[k]);
+        par[k] = (int64_t*)malloc(sizeof(int64_t) * npix[k]);
+        for (int64_t p = 0; p < npix[k]; ++p) {
+            anti[k][p] = hp_antipode(ns, p);
+            par[k][p] = k > 0 ? or_hp_parent(ns, p) : -1;
+        }
+    }
+    (void)P;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t oi = 0; oi < n_origins; ++oi) {
+        const int64_t o = origins[oi];
+        int64_t** h = (int64_t**)malloc(sizeof(int64_t*) * L);
+        for (int32_t k = 0; k < L; ++k) h[k] = (int64_t*)calloc((size_t)npix[k], sizeof(int64_t));
+        const int64_t nsm = 1LL << lmax;
+        for (int64_t j = 0; j < n_sample; ++j) {
+            const int64_t s = sample[j];
+            if (s == o) continue;
+            double vx = pos[3 * s] - pos[3 * o], vy = pos[3 * s + 1] - pos[3 * o + 1];
+            double vz = pos[3 * s + 2] - pos[3 * o + 2];
+            if (vx == 0.0 && vy == 0.0 && vz == 0.0) continue;
+            h[L - 1][fx_vec2pix(nsm, vx, vy, vz)] += 1;
+        }
+        for (int32_t k = L - 1; k > 0; --k)
+            for (int64_t p = 0; p < npix[k]; ++p) h[k - 1][par[k][p]] += h[k][p];
+        or_leaf* leaves = (or_leaf*)malloc(sizeof(or_leaf) * (size_t)R);
+        int64_t nl = 0;
+        int64_t nact = npix[0] / 2;
+        or_key* act = (or_key*)malloc(sizeof(or_key) * (size_t)(npix[L - 1]));
+        int64_t a = 0;
+        for (int64_t p = 0; p < npix[0]; ++p)
+            if (anti[0][p] > p) { act[a].pix = p; act[a].cnt = h[0][p] + h[0][anti[0][p]]; ++a; }
+        for (int32_t k = 0; k < L; ++k) {
+            if (k == L - 1) {
+                for (int64_t i = 0; i < nact; ++i) { leaves[nl].level = lmin + k; leaves[nl].pix = act[i].pix; ++nl; }
+                break;
+            }
+            qsort(act, (size_t)nact, sizeof(or_key), key_cmp);
+            int64_t nref = nact / 2;
+            for (int64_t i = nref; i < nact; ++i) { leaves[nl].level = lmin + k; leaves[nl].pix = act[i].pix; ++nl; }
+            /* children of the refined pairs: the level-(k+1) pixels whose parent is the canonical pixel */
+            or_key* nxt = (or_key*)malloc(sizeof(or_key) * (size_t)(4 * nref));
+            int64_t b = 0;
+            for (int64_t c = 0; c < npix[k + 1]; ++c) {
+                int64_t pc = par[k + 1][c];
+                for (int64_t i = 0; i < nref; ++i)
+                    if (act[i].pix == pc) {
+                        int64_t cc = c < anti[k + 1][c] ? c : anti[k + 1][c];
+                        nxt[b].pix = cc;
+                        nxt[b].cnt = h[k + 1][cc] + h[k + 1][anti[k + 1][cc]];
+                        ++b;
+                        break;
+                    }
+            }
+            memcpy(act, nxt, sizeof(or_key) * (size_t)b);
+            free(nxt);
+            nact = b;
+        }
+        qsort(leaves, (size_t)nl, sizeof(or_leaf), leaf_cmp);
+        for (int64_t r = 0; r < nl && r < R; ++r) {
+            int64_t ns = 1LL << leaves[r].level;
+            if (pix_out) pix_out[oi * R + r] = leaves[r].pix;
+            if (level_out) level_out[oi * R + r] = leaves[r].level;
+            if (dirs_out) or_hp_pix2vec(ns, leaves[r].pix, dirs_out + 3 * (oi * R + r));
+            if (w2_out) w2_out[oi * R + r] = 2.0 / (double)(12 * ns * ns);
+        }
+        free(leaves);
+        free(act);
+        for (int32_t k = 0; k < L; ++k) free(h[k]);
+        free(h);
+    }
+    for (int32_t k = 0; k < L; ++k) { free(anti[k]); free(par[k]); }
+    free(anti); free(par); free(npix);
+    return R;
+}
+
 /* ---------------------------------------------------------------- tracing */
 
 /* Trace one ray from `origin` along unit direction d (Section 2.1, Fig. 2).

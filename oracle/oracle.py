@@ -57,6 +57,16 @@ def lib():
         L.or_trace_all.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp, i64, vp, vp, vp, C.c_int]
         L.or_feautrier_u.restype = C.c_double
         L.or_feautrier_u.argtypes = [i64, i64, vp, vp, C.c_double]
+        L.or_fx_sqrt.restype = C.c_double
+        L.or_fx_sqrt.argtypes = [C.c_double]
+        L.or_fx_atan2.restype = C.c_double
+        L.or_fx_atan2.argtypes = [C.c_double, C.c_double]
+        L.or_fx_vec2pix.restype = i64
+        L.or_fx_vec2pix.argtypes = [i64, vp]
+        L.or_dirset_adaptive_R.restype = i64
+        L.or_dirset_adaptive_R.argtypes = [i32, i32]
+        L.or_dirset_adaptive.restype = i64
+        L.or_dirset_adaptive.argtypes = [vp, i64, vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, C.c_int]
         L.or_compute_J.restype = C.c_int
         L.or_compute_J.argtypes = [i64, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, i64, vp, i64, vp,
                                    vp, i32, vp, i64, vp, vp, C.c_int]
@@ -111,6 +121,40 @@ def dirset_uniform(nside: int):
     w2 = np.zeros(R)
     L.or_dirset_uniform(nside, _p(pix), _p(dirs), _p(w2))
     return pix, dirs, w2
+
+
+def fx_sqrt(x: float) -> float:
+    return lib().or_fx_sqrt(float(x))
+
+
+def fx_atan2(y: float, x: float) -> float:
+    return lib().or_fx_atan2(float(y), float(x))
+
+
+def fx_vec2pix(nside: int, v) -> int:
+    v = _c(v, np.float64)
+    return lib().or_fx_vec2pix(nside, _p(v))
+
+
+def dirset_adaptive_R(lmin: int, lmax: int) -> int:
+    return lib().or_dirset_adaptive_R(lmin, lmax)
+
+
+def dirset_adaptive(model, lmin: int, lmax: int, sample, origins=None, nthreads: int = 0):
+    """Adaptive sets: (pix [n][R] int64, level [n][R] int32, dirs [n][R][3], w2 [n][R])."""
+    L = lib()
+    pos = _c(model.pos, np.float64)
+    origins = np.arange(model.P, dtype=np.int32) if origins is None else _c(origins, np.int32)
+    sample = _c(sample, np.int32)
+    R = L.or_dirset_adaptive_R(lmin, lmax)
+    n = len(origins)
+    pix = np.zeros((n, R), np.int64)
+    lev = np.zeros((n, R), np.int32)
+    dirs = np.zeros((n, R, 3))
+    w2 = np.zeros((n, R))
+    L.or_dirset_adaptive(_p(pos), model.P, _p(origins), n, _p(sample), len(sample), lmin, lmax, _p(pix),
+                         _p(lev), _p(dirs), _p(w2), nthreads)
+    return pix, lev, dirs, w2
 
 
 # ----------------------------------------------------------------- tracing
