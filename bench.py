@@ -177,7 +177,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial")
-    ap.add_argument("--cpu-sample", type=int, default=4000, help="origins timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
     ap.add_argument("--nside", type=int, default=NSIDE)
     ap.add_argument("--summarize-counters", nargs=3, metavar=("DIR", "OUT_JSON", "OUT_MD"),
                     help="summarise a rocprofv3 session directory into the profiles/ files and exit")

@@ -279,3 +279,55 @@ def test_empty_origin_list(rt):
     assert off.numel() == 1 and int(off[0]) == 0 and ids.numel() == 0
     J = _solve_gpu(rt, m, model, ds, (off, ids, Z), org, 0, rt.RT_F64)
     assert J.shape == (0, m.F)
+
+
+# ----------------------------------------------------------------------------- adaptive direction sets
+
+@pytest.mark.parametrize("lmin,lmax", [(1, 4), (0, 3), (2, 3)])
+def test_adaptive_sets_bitwise(rt, orc, wind, lmin, lmax):
+    torch = _torch()
+    rng = np.random.default_rng(lmin * 10 + lmax)
+    sample = rng.choice(wind.P, 10_000, replace=False).astype(np.int32)
+    origins = rng.choice(wind.P, 300, replace=False).astype(np.int32)
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.adaptive(model, lmin, lmax, _t(sample), origins=_t(origins))
+    pix, lev, dirs, w2 = ds.export()
+    e_pix, e_lev, e_dirs, e_w2 = orc.dirset_adaptive(wind, lmin, lmax, sample, origins=origins)
+    assert np.array_equal(lev, e_lev)
+    assert np.array_equal(pix, e_pix)
+    assert np.array_equal(dirs.view(np.uint64), e_dirs.view(np.uint64))
+    assert np.array_equal(w2, e_w2)
+    assert ds.info()["R"] == orc.dirset_adaptive_R(lmin, lmax)
+    del torch
+
+
+def test_adaptive_J_and_lmax_identity(rt, orc, wind):
+    torch = _torch()
+    rng = np.random.default_rng(77)
+    sample = rng.choice(wind.P, 10_000, replace=False).astype(np.int32)
+    origins = rng.choice(wind.P, 120, replace=False).astype(np.int32)
+    model = _gpu_model(rt, wind)
+    org = _t(origins)
+    ds = rt.DirSet.adaptive(model, 1, 3, _t(sample), origins=org)
+    pix, lev, dirs, w2 = ds.export()
+    rays = rt.trace(model, ds, origins=org)
+    e = orc.trace_all(wind, dirs, origins)
+    _assert_rays_equal(rays, e)
+    c32, e32, c64, e64 = synth.to_fp32_tables(wind.chi, wind.eta)
+    J64, u64 = _solve_gpu(rt, wind, model, ds, rays, org, len(origins), rt.RT_F64, chi=c64, eta=e64, want_u=True)
+    Je = orc.compute_J(wind, dirs, w2, origins=origins, chi=c64, eta=e64)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    # Section 3.2.1: the maximally refined directions are the dense regular ones, with the same u
+    du = rt.DirSet.uniform(8)
+    upix = du.export()[0]
+    where = {int(p): i for i, p in enumerate(upix)}
+    rays_u = rt.trace(model, du, origins=org)
+    J_u, u_u = _solve_gpu(rt, wind, model, du, rays_u, org, len(origins), rt.RT_F64, chi=c64, eta=e64, want_u=True)
+    u64, u_u = u64.cpu().numpy(), u_u.cpu().numpy()
+    n = 0
+    for o in range(len(origins)):
+        for r in np.nonzero(lev[o] == 3)[0]:
+            assert u64[o, r].tobytes() == u_u[o, where[int(pix[o, r])]].tobytes()
+            n += 1
+    assert n == len(origins) * 96
+    del torch
