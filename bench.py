@@ -176,9 +176,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial")
+    ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial",
+                    help="plan schedule when the autotuner is skipped")
     ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
-    ap.add_argument("--nside", type=int, default=NSIDE)
+    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch"], default="wind",
+                    help="wind: the headline 50k-point wind (default); octree: ~500k-leaf AMR-like cloud, 2x48 "
+                         "frequencies; octree_reduced: the same field with ~50k leaves; sph_batch: 64 SPH-like "
+                         "clouds as one disjoint union (size scaled by --batch-scale)")
+    ap.add_argument("--batch-scale", type=float, default=0.25)
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner and use the library defaults")
+    ap.add_argument("--nside", type=int, default=0, help="HEALPix nside (0 = the workload's own)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("DIR", "OUT_JSON", "OUT_MD"),
                     help="summarise a rocprofv3 session directory into the profiles/ files and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -218,22 +225,48 @@ def main():
         return
     rt.load()
 
-    _log("generating the wind model ...")
-    m = synth.wind_model(seed=2, P=50_000, F=F)
+    t_gen = time.perf_counter()
+    if args.workload == "wind":
+        m = synth.wind_model(seed=2, P=50_000, F=F)
+        nside = args.nside or NSIDE
+        desc = "analytic spherical wind, 50000 points (Delaunay), moving (v_inf 20 Doppler widths)"
+    elif args.workload in ("octree", "octree_reduced"):
+        target = 500_000 if args.workload == "octree" else 50_000
+        m = synth.octree_model(seed=3, target=target)
+        nside = args.nside or 4
+        desc = (f"AMR-octree-like cloud, {m.P} leaves (levels 5-8, touching-leaf neighbours), 2 lines x 48 "
+                "frequencies, turbulent velocity 3 Doppler widths rms")
+    else:
+        ms = synth.sph_batch_models(n_models=64, scale=args.batch_scale, workers=16)
+        m = synth.concat_models(ms)
+        nside = args.nside or 2
+        desc = (f"64 SPH-like clouds (Plummer + spiral arm, Keplerian), {m.P} particles in one disjoint union "
+                f"(sizes x{args.batch_scale})")
+    _log(f"generated {args.workload}: {m.P} points, {m.E} neighbour entries in {time.perf_counter() - t_gen:.1f} s")
+    Fw = m.F
     c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
     model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
-    ds = rt.DirSet.uniform(args.nside)
+    ds = rt.DirSet.uniform(nside)
     R = ds.R
     chi = torch.as_tensor(c32, device=dev)
     eta = torch.as_tensor(e32, device=dev)
     I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device=dev)
-    J = torch.empty((m.P, F), dtype=torch.float32, device=dev)
+    J = torch.empty((m.P, Fw), dtype=torch.float32, device=dev)
     sched = {"direct": rt.SCHED_DIRECT, "binned": rt.SCHED_BINNED, "spatial": rt.SCHED_SPATIAL}[args.schedule]
+    opts = dict(schedule=sched, group=args.group, trace_lanes=args.trace_lanes)
+    tuned = None
+    if not args.no_autotune:
+        _log("autotuning (schedule, sweep load group, walk lanes, persistent grid) ...")
+        t0 = time.perf_counter()
+        opts, tuned_ms = rt.autotune(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P,
+                                     precision=rt.RT_F32, dtau_fp64_below=args.fp64_below, n_runs=2,
+                                     verbose=True)
+        tuned = dict(opts, ms_per_step=tuned_ms, seconds=time.perf_counter() - t0)
+        _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   schedule=sched, dtau_fp64_below=args.fp64_below,
-                   padded_trace_budget=-1 if args.two_pass_trace else 0, group=args.group,
-                   trace_lanes=args.trace_lanes)
+                   dtau_fp64_below=args.fp64_below, padded_trace_budget=-1 if args.two_pass_trace else 0,
+                   **opts)
     total = plan.info()["total"]
 
     for _ in range(args.warmup):
@@ -254,17 +287,18 @@ def main():
     wall = time.perf_counter() - t0
     rt.sync_status()
     ms_step = ev0.elapsed_time(ev1) / args.steps
-    solves = m.P * R * F
+    solves = m.P * R * Fw
     value = solves / (ms_step * 1e-3)
     _log(f"step {ms_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall)")
 
     # per-stage times from HIP events on the same stream, eager launches
     stages = plan.profile(max(3, min(args.steps, 10)))
     _log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
-    alg = sweep_bytes(m.P, R, total, F, moving=True)
+    nfc = (Fw + 63) // 64
+    alg = sweep_bytes(m.P, R, total, Fw, moving=m.vel is not None)
     achieved = alg / (stages["sweep"] * 1e-3) / 1e9
     khash = src_hash("solve.hip", "rt_internal.h")
-    traffic = load_traffic(khash, alg)
+    traffic = load_traffic(khash, alg) if args.workload == "wind" and nside == NSIDE else None
 
     rec = {
         "metric": "point-ray-freq solves/s (one solve = one origin x antipodal ray pair x frequency)",
@@ -280,11 +314,10 @@ def main():
         "dtype": "f32 sweep, f64 geometry",
         "data": "synthetic (seeded analytic wind)",
         "config": {
-            "workload": f"analytic spherical wind, 50000 points (Delaunay), nside {args.nside} "
-                        f"({R} pairs), F={F}, moving (v_inf 20 Doppler widths), FP32 sweep",
-            "points": m.P, "pairs_per_point": R, "freqs": F, "ray_list_entries": total,
-            "mean_line_length": (total + m.P * R) / (m.P * R), "schedule": args.schedule,
-            "fp64_rows_below_dtau": args.fp64_below,
+            "workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep",
+            "points": m.P, "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
+            "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "autotune": tuned,
+            "fp64_rows_below_dtau": args.fp64_below, "frequency_chunks_per_pair": nfc,
         },
         "roofline": {
             "kernel": "feautrier sweep",
@@ -298,11 +331,13 @@ def main():
             "sweep_ms": stages["sweep"],
         },
         "stages_ms": stages,
-        "line_point_freq_updates_per_s": (total + m.P * R) * F / (ms_step * 1e-3),
+        "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms_step * 1e-3),
     }
     if args.cpu_sample > 0:
         from oracle import dirset_uniform
-        _, dirs, w2 = dirset_uniform(args.nside)
+        _, dirs, w2 = dirset_uniform(nside)
+        if args.workload != "wind" and args.cpu_sample == ap.get_default("cpu_sample"):
+            args.cpu_sample = 3000  # longer lines and more frequencies: keep the CPU leg to tens of seconds
         _log(f"timing the CPU oracle on {args.cpu_sample} origins ...")
         rec["cpu_baseline"] = cpu_baseline(m, dirs, w2, args.cpu_sample)
     print(json.dumps(rec), flush=True)

@@ -179,10 +179,11 @@ typedef struct {
     int32_t precision;        /* RT_F32 or RT_F64 */
     int32_t schedule;         /* RT_SCHED_DIRECT: one wave per (origin, pair, 64-frequency chunk) in
                                  slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
-                                 queue, longest lines first; RT_SCHED_SPATIAL (plans only): rays and
-                                 sweep items direction by direction, origins in Morton order of their
-                                 positions, each XCD on a contiguous range -- concurrent waves then read
-                                 mostly the same rows and the L2s hold them */
+                                 queue, longest lines first; RT_SCHED_SPATIAL (plans only): sweep items
+                                 direction by direction, origins in Morton order of their positions,
+                                 each XCD on a contiguous range -- concurrent waves then read mostly the
+                                 same rows and the L2s hold them.  A plan's walk always uses that
+                                 order. */
     double dtau_fp64_below;   /* FP32 path: rows with a smaller dtau are eliminated in FP64 (e.g. 1e-4) */
     int32_t waves_per_cu;     /* persistent grid size (0 = default) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
@@ -234,6 +235,29 @@ rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_
  * n_origins*2R+1, total, total).  Async. */
 rt_status rt_plan_copy_rays(const rt_plan* plan, int64_t* ray_off, int32_t* ray_ids, double* ray_Z, void* stream);
 rt_status rt_plan_destroy(rt_plan* plan);
+
+/* Re-capture a plan's graph with other scheduling options (schedule, group,
+ * trace_lanes, waves_per_cu, n_bins; precision and threshold stay), reusing its
+ * lists and buffers; builds the spatial order or bin workspace on first use.
+ * Synchronises `stream`. */
+rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream);
+
+/* Autotuner.  On the caller's data, one plan is built and re-captured for six
+ * candidate runs; each run varies the walk's lanes per ray (8, 16, 4) and the
+ * sweep's schedule / load group / persistent grid (spatial 4 and 8; binned 4 and
+ * 8 at 32 waves per CU; binned 4 at 16; direct 4), and the HIP-event stage times
+ * (one warm-up, n_runs timed, rt_plan_profile) credit the walk and the sweep
+ * separately.  The fastest of each goes to *best (other fields from *base, or
+ * defaults) and the sum of the stage times to *best_ms.  With cache_path, a line
+ * "<signature> <schedule> <group> <lanes> <waves_per_cu> <bins> <ms>" is
+ * appended, and a later call with the same signature (device, P, E, R, origins,
+ * F, precision, moving, adaptive) returns the cached choice without timing.
+ * verbose != 0 prints one line per candidate to stderr.  Synchronises, allocates. */
+rt_status rt_autotune(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                      const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                      const double* I_bc, void* J, const rt_solve_opts* base, int32_t n_runs,
+                      const char* cache_path, int32_t verbose, void* stream, rt_solve_opts* best,
+                      double* best_ms);
 
 /* Synchronise `stream` and return the error latched by kernels since the last
  * call (RT_ERR_CAPACITY; RT_ERR_NONFINITE; RT_ERR_ARG for an origin id outside

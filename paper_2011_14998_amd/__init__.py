@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     Model,
     Plan,
     RtError,
+    autotune,
     compute_J,
     load,
     solve,

@@ -62,6 +62,10 @@ _SIGS = {
     "rt_plan_copy_rays": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rt_plan_profile": (_i32, [_vp, _i32, _vp, _vp]),
     "rt_plan_destroy": (_i32, [_vp]),
+    "rt_autotune": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC), _vp, _vp,
+                           C.POINTER(SolveOptsC), _i32, C.c_char_p, _i32, _vp, C.POINTER(SolveOptsC),
+                           C.POINTER(_dbl)]),
+    "rt_plan_retune": (_i32, [_vp, C.POINTER(SolveOptsC), _vp]),
     "rt_sync_status": (_i32, [_vp]),
 }
 
@@ -300,6 +304,33 @@ def compute_J(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, o
     return solve(model, dirset, rays, chi, eta, freq_len, freq_dx, I_bc, origins=origins, **kw)
 
 
+def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None, n_origins=None,
+             precision: int = RT_F32, dtau_fp64_below: float = 1e-4, n_runs: int = 2, cache_path: str = None,
+             verbose: bool = False, stream=None):
+    """Fastest plan options for this workload (see rt_autotune); returns (options dict, ms per step)."""
+    torch = _torch()
+    dt = torch.float64 if precision == RT_F64 else torch.float32
+    chi, eta, J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
+    I_bc = _dev(I_bc, torch.float64)
+    if origins is not None:
+        origins = _dev(origins, torch.int32)
+        n_origins = origins.numel()
+    elif n_origins is None:
+        n_origins = model.P
+    g, keep = _grid(freq_len, freq_dx)
+    base = _opts(precision, SCHED_SPATIAL, dtau_fp64_below, 0, 0)
+    best = SolveOptsC()
+    ms = _dbl()
+    _check(load().rt_autotune(model._h, dirset._h, _ptr(origins), n_origins, _ptr(chi), _ptr(eta), precision,
+                              chi.shape[1], C.byref(g), _ptr(I_bc), _ptr(J), C.byref(base), n_runs,
+                              None if cache_path is None else cache_path.encode(), 1 if verbose else 0,
+                              _stream(stream), C.byref(best), C.byref(ms)))
+    del keep
+    opts = dict(schedule=best.schedule, group=best.group, trace_lanes=best.trace_lanes,
+                waves_per_cu=best.waves_per_cu, n_bins=best.n_bins)
+    return opts, ms.value
+
+
 class Plan:
     """The whole hot path (count, scan, write, bin, sweep, reduce) as one replayable HIP graph."""
 
@@ -325,6 +356,12 @@ class Plan:
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),
                                      _ptr(self.J), C.byref(o), _stream(stream), C.byref(h)))
         self._h = h
+
+    def retune(self, schedule: int = SCHED_SPATIAL, group: int = 0, trace_lanes: int = 0, waves_per_cu: int = 0,
+               n_bins: int = 0, stream=None):
+        """Re-capture the plan's graph with other scheduling options."""
+        o = _opts(RT_F32, schedule, 1e-4, waves_per_cu, n_bins, 0, group, trace_lanes)
+        _check(load().rt_plan_retune(self._h, C.byref(o), _stream(stream)))
 
     def run(self, use_graph: bool = True, stream=None):
         _check(load().rt_plan_run(self._h, 1 if use_graph else 0, _stream(stream)))

@@ -2,6 +2,7 @@
 // workspace planning, launches and HIP-graph plans.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -505,9 +506,13 @@ struct rt_plan {
     int64_t cap = 0;
     int32_t* pids = nullptr;
     double* pZ = nullptr;
-    // spatial schedule: origin order (Morton) and sweep item order
+    // spatial schedule: origin order (Morton), built on first use
     int32_t* order = nullptr;
-    int32_t* items = nullptr;
+    // the solve launch as filled from the caller's arguments, before any schedule is applied
+    SolveLaunch base;
+    void* u_buf = nullptr;
+    void* bin_buf = nullptr;   // binned schedule: queue counter + bins, allocated on first use
+    hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -559,7 +564,7 @@ static void plan_free(rt_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     for (void* q : {(void*)p->lens, (void*)p->ray_off, (void*)p->ids, (void*)p->Z, p->scan_ws, p->solve_ws,
-                    (void*)p->pids, (void*)p->pZ, (void*)p->order, (void*)p->items})
+                    (void*)p->pids, (void*)p->pZ, (void*)p->order, p->u_buf, p->bin_buf})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -610,6 +615,84 @@ static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_
     order.resize((size_t)n_o);
     for (int64_t k = 0; k < n_o; ++k) order[(size_t)k] = key[(size_t)k].second;
     return hipSuccess;
+}
+
+// Apply scheduling options to a plan whose lists and u buffer exist: build what
+// the schedule needs on first use (spatial origin order, bin workspace) and
+// re-capture the whole step as one graph on a private stream (the caller's
+// stream may be the legacy default stream, which cannot be captured).
+static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
+    if (o.schedule < RT_SCHED_DIRECT || o.schedule > RT_SCHED_SPATIAL) return fail(RT_ERR_ARG, "plan: bad schedule");
+    if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "plan: group must be 4 or 8");
+    if (o.trace_lanes != 0 && o.trace_lanes != 4 && o.trace_lanes != 8 && o.trace_lanes != 16)
+        return fail(RT_ERR_ARG, "plan: trace_lanes must be 4, 8 or 16");
+    hipError_t e = hipSuccess;
+    const rt_solve_opts prev = p->o;
+    p->o.schedule = o.schedule;
+    p->o.group = o.group;
+    p->o.trace_lanes = o.trace_lanes;
+    p->o.waves_per_cu = o.waves_per_cu;
+    p->o.n_bins = o.n_bins;
+    SolveLaunch a = p->base;
+    a.u = p->u_buf;
+    a.schedule = o.schedule == RT_SCHED_BINNED ? RT_SCHED_BINNED : RT_SCHED_DIRECT;
+    a.group = o.group ? o.group : 4;
+    a.n_bins = opts_bins(o);
+    a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? o.waves_per_cu : 32);
+    a.items = nullptr;
+    a.order = nullptr;
+    a.queue = nullptr;
+    p->bin_ws = nullptr;
+    // The walk always runs direction-major over Morton-ordered origins (best L2
+    // reuse whatever the sweep's schedule); the spatial schedule applies the same
+    // order to the sweep's items.
+    if (p->n_origins > 0 && !p->order) {
+        std::vector<int32_t> ord;
+        e = morton_order(p->m, p->origins, p->n_origins, p->stream, ord);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->order, sizeof(int32_t) * ord.size());
+        if (e == hipSuccess) e = hipMemcpy(p->order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            p->o = prev;
+            return hip_fail(e, "plan: spatial order");
+        }
+    }
+    if (o.schedule == RT_SCHED_SPATIAL) a.order = p->order;
+    if (o.schedule == RT_SCHED_BINNED) {
+        const size_t need = align_up(bin_workspace(solve_items(a), 128)) + 256;
+        if (!p->bin_buf) {
+            e = hipMalloc(&p->bin_buf, need);
+            if (e != hipSuccess) {
+                p->o = prev;
+                return hip_fail(e, "plan: bin workspace");
+            }
+        }
+        a.queue = (int32_t*)p->bin_buf;
+        p->bin_ws = (char*)p->bin_buf + 256;
+    }
+    p->a = a;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = plan_enqueue(p, cap);
+        e = hipStreamEndCapture(cap, &p->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "plan: graph capture");
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_retune(rt_plan* p, const rt_solve_opts* opts, void* stream) {
+    if (!p || !opts) return fail(RT_ERR_ARG, "rt_plan_retune: NULL argument");
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    p->stream = (hipStream_t)stream;
+    return plan_configure(p, *opts);
 }
 
 extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
@@ -670,57 +753,17 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
         plan_free(p);
         return st;
     }
-    if (p->o.schedule == RT_SCHED_SPATIAL && n_origins > 0) {
-        std::vector<int32_t> ord;
-        e = morton_order(m, origins, n_origins, s, ord);
-        const int nfc = (p->a.F + 63) / 64;
-        std::vector<int32_t> it;
-        if (e == hipSuccess) {
-            it.reserve((size_t)solve_items(p->a));
-            for (int64_t r = 0; r < set->R; ++r)
-                for (int c = 0; c < nfc; ++c)
-                    for (int64_t k = 0; k < n_origins; ++k)
-                        it.push_back((int32_t)(((int64_t)ord[(size_t)k] * set->R + r) * nfc + c));
-            e = hipMalloc((void**)&p->order, sizeof(int32_t) * ord.size());
-        }
-        if (e == hipSuccess) e = hipMalloc((void**)&p->items, sizeof(int32_t) * it.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(p->order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(p->items, it.data(), sizeof(int32_t) * it.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "rt_plan_create: spatial order");
-            plan_free(p);
-            return st;
-        }
-        p->a.items = p->items;
-        p->a.schedule = RT_SCHED_DIRECT;  // the sweep itself is a direct launch over the ordered items
-    }
-    size_t wsb = solve_ws_bytes(n_origins, set->R, p->a.F, p->o, true);
-    e = hipMalloc(&p->solve_ws, std::max<size_t>(wsb, 256));
+    p->base = p->a;
+    const size_t es = p->o.precision == RT_F64 ? 8 : 4;
+    e = hipMalloc(&p->u_buf, es * (size_t)std::max<int64_t>(n_origins * set->R * p->a.F, 1));
     if (e != hipSuccess) {
-        st = hip_fail(e, "rt_plan_create: solve workspace");
+        st = hip_fail(e, "rt_plan_create: u buffer");
         plan_free(p);
         return st;
     }
-    st = carve_solve_ws(p->a, p->o, nullptr, p->solve_ws, wsb, &p->bin_ws);
+    p->stream = s;
+    st = plan_configure(p, p->o);
     if (st) {
-        plan_free(p);
-        return st;
-    }
-    // Capture the whole step as one graph on a private stream (the caller's
-    // stream may be the legacy default stream, which cannot be captured).
-    hipStream_t cap = nullptr;
-    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t e2 = plan_enqueue(p, cap);
-        e = hipStreamEndCapture(cap, &p->graph);
-        if (e2 != hipSuccess) e = e2;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    if (cap) (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) {
-        st = hip_fail(e, "rt_plan_create: graph capture");
         plan_free(p);
         return st;
     }
@@ -785,6 +828,120 @@ extern "C" rt_status rt_plan_copy_rays(const rt_plan* p, int64_t* ray_off, int32
 
 extern "C" rt_status rt_plan_destroy(rt_plan* p) {
     if (p) plan_free(p);
+    return RT_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+static std::string tune_signature(const rt_model* m, const rt_dirset* set, int64_t n_origins, int64_t F,
+                                  int32_t precision) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s_P%lld_E%lld_R%lld_n%lld_F%lld_p%d_v%d_a%d", arch.c_str(), (long long)m->P,
+                  (long long)m->E, (long long)set->R, (long long)n_origins, (long long)F, (int)precision,
+                  m->vel ? 1 : 0, set->n_origins > 0 ? 1 : 0);
+    return buf;
+}
+
+extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                                 const void* chi, const void* eta, int32_t dtype, int64_t ld,
+                                 const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* base,
+                                 int32_t n_runs, const char* cache_path, int32_t verbose, void* stream,
+                                 rt_solve_opts* best, double* best_ms) {
+    if (!m || !set || !grid || !best) return fail(RT_ERR_ARG, "rt_autotune: NULL argument");
+    rt_solve_opts b0 = base ? *base : default_opts();
+    int64_t F = 0;
+    for (int i = 0; i < grid->n_blocks && grid->len; ++i) F += grid->len[i];
+    const std::string sig = tune_signature(m, set, n_origins, F, b0.precision);
+    if (cache_path && *cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char key[256];
+            int sc, gr, la, wpc, nb;
+            double ms;
+            while (std::fscanf(f, "%255s %d %d %d %d %d %lf", key, &sc, &gr, &la, &wpc, &nb, &ms) == 7) {
+                if (sig == key) {
+                    *best = b0;
+                    best->schedule = sc;
+                    best->group = gr;
+                    best->trace_lanes = la;
+                    best->waves_per_cu = wpc;
+                    best->n_bins = nb;
+                    if (best_ms) *best_ms = ms;
+                    std::fclose(f);
+                    return RT_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    if (n_runs <= 0) n_runs = 2;
+    // The walk's lanes per ray and the sweep's (schedule, load group, grid) act on
+    // different stages, so each candidate run varies both and the stage times
+    // (HIP events between stages) are credited separately.
+    const int lanes[3] = {8, 16, 4};
+    struct SweepCand { int sc, gr, wpc; };
+    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 4, 0}, {RT_SCHED_SPATIAL, 8, 0}, {RT_SCHED_BINNED, 4, 32},
+                             {RT_SCHED_BINNED, 8, 32}, {RT_SCHED_BINNED, 4, 16}, {RT_SCHED_DIRECT, 4, 0}};
+    rt_plan* p = nullptr;
+    rt_solve_opts o = b0;
+    o.schedule = RT_SCHED_SPATIAL;
+    o.group = 4;
+    o.trace_lanes = 8;
+    rt_status st = rt_plan_create(m, set, origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J, &o, stream, &p);
+    if (st) return st;
+    double walk_best = 1e300, sweep_best = 1e300, other = 0.0;
+    int lane_best = 8;
+    SweepCand sw_best = sw[0];
+    for (int i = 0; i < 6 && !st; ++i) {
+        o.schedule = sw[i].sc;
+        o.group = sw[i].gr;
+        o.waves_per_cu = sw[i].wpc;
+        o.n_bins = sw[i].sc == RT_SCHED_BINNED ? 64 : 0;
+        o.trace_lanes = lanes[i % 3];
+        st = plan_configure(p, o);
+        if (st) break;
+        double ms[6];
+        st = rt_plan_profile(p, 1, ms, stream);  // warm-up
+        if (!st) st = rt_plan_profile(p, n_runs, ms, stream);
+        if (st) break;
+        const double walk = ms[0] + ms[2], sweep = ms[3] + ms[4];
+        if (i < 3 && walk < walk_best) {
+            walk_best = walk;
+            lane_best = lanes[i];
+        }
+        if (sweep < sweep_best) {
+            sweep_best = sweep;
+            sw_best = sw[i];
+        }
+        other = ms[1] + ms[5];
+        if (verbose)
+            std::fprintf(stderr, "autotune: lanes %d schedule %d group %d waves/CU %d -> walk %.3f ms, sweep %.3f ms\n",
+                         o.trace_lanes, o.schedule, o.group, o.waves_per_cu, walk, sweep);
+    }
+    rt_plan_destroy(p);
+    if (st) return st;
+    *best = b0;
+    best->schedule = sw_best.sc;
+    best->group = sw_best.gr;
+    best->waves_per_cu = sw_best.wpc;
+    best->n_bins = sw_best.sc == RT_SCHED_BINNED ? 64 : 0;
+    best->trace_lanes = lane_best;
+    const double bms = walk_best + sweep_best + other;
+    if (best_ms) *best_ms = bms;
+    if (cache_path && *cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%s %d %d %d %d %d %.6f\n", sig.c_str(), best->schedule, best->group, best->trace_lanes,
+                         best->waves_per_cu, best->n_bins, bms);
+            std::fclose(f);
+        }
+    }
     return RT_OK;
 }
 

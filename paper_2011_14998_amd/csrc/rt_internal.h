@@ -27,6 +27,14 @@ int32_t* error_word();  // device address for the current device, nullptr on fai
 int num_cus();
 int num_xcds();
 
+// A dispatch covers at most 2^32 - 1 work-items per dimension; kernels whose
+// logical index space can be larger loop over it in rounds of at most
+// MAX_GRID_BLOCKS workgroups.
+constexpr int64_t MAX_GRID_BLOCKS = (int64_t)1 << 22;
+inline unsigned capped_blocks(int64_t n_blocks) {
+    return (unsigned)(n_blocks < 1 ? 1 : (n_blocks > MAX_GRID_BLOCKS ? MAX_GRID_BLOCKS : n_blocks));
+}
+
 // Workgroups are dispatched to the XCDs round-robin (workgroup b runs on XCD
 // b mod n).  This renumbering gives XCD x the contiguous range of logical
 // blocks [start_x, start_x + count_x), a bijection of [0, nb), so work that is
@@ -142,6 +150,7 @@ struct SolveLaunch {
     // scheduling
     int32_t schedule;
     const int32_t* items;  // binned order, or nullptr
+    const int32_t* order;  // spatial order of origin positions (direct launch, direction-major), or nullptr
     int32_t* queue;        // persistent counter, or nullptr
     int32_t grid_waves;    // persistent grid size in waves
     int32_t n_bins;

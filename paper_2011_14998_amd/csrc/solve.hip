@@ -431,11 +431,20 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.n_xcd);
-    const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (it >= n_items) return;
-    const int64_t w = a.items ? (int64_t)a.items[it] : it;
-    solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
+    const int64_t nb = (n_items + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.n_xcd); blk < nb; blk += gridDim.x) {
+        const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+        if (it >= n_items) continue;
+        int64_t w;
+        if (a.order) {  // direction-major over spatially ordered origins
+            const int64_t rc = it / a.n_origins;
+            const int64_t oi = a.order[it - rc * a.n_origins];
+            w = oi * a.R * nfc + rc;  // rc = r * nfc + chunk
+        } else {
+            w = a.items ? (int64_t)a.items[it] : it;
+        }
+        solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
+    }
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
@@ -459,8 +468,8 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
 // J[o][f] = sum over pairs, ascending, of w2_r u_r[f] (eq. 3, eq. 4).
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce(const SolveLaunch a) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.n_origins * a.F) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n_origins * a.F;
+         i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t oi = i / a.F;
     const int f = (int)(i - oi * a.F);
     const T* __restrict__ u = (const T*)a.u + oi * a.R * a.F + f;
@@ -468,6 +477,7 @@ __global__ __launch_bounds__(256) void k_reduce(const SolveLaunch a) {
     T acc = (T)0;
     for (int64_t r = 0; r < a.R; ++r) acc += (T)w2[r] * u[r * a.F];
     ((T*)a.J)[i] = acc;
+    }
 }
 
 // ---------------------------------------------------------------- length binning
@@ -596,7 +606,7 @@ hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const bool persist = a.schedule == RT_SCHED_BINNED;
     dim3 grid = persist ? dim3((unsigned)((a.grid_waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK))
-                        : dim3(nblocks(n_items, WAVES_PER_BLOCK));
+                        : dim3(capped_blocks((n_items + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
     if (precision == RT_F64) solve_dispatch<double>(a, persist, grid, s);
     else solve_dispatch<float>(a, persist, grid, s);
     return hipGetLastError();
@@ -606,9 +616,9 @@ hipError_t launch_reduce(const SolveLaunch& a, int precision, hipStream_t s) {
     const int64_t n = a.n_origins * a.F;
     if (n == 0) return hipSuccess;
     if (precision == RT_F64)
-        hipLaunchKernelGGL(k_reduce<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reduce<double>, dim3(capped_blocks((n + 255) / 256)), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_reduce<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reduce<float>, dim3(capped_blocks((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

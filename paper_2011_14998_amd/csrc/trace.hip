@@ -124,10 +124,12 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     static_assert(GL == 4 || GL == 8 || GL == 16, "4, 8 or 16 lanes per ray");
     constexpr int U = 32 / GL;  // candidates per lane per pass: a whole row of up to 32 in one round of loads
     const int sub = threadIdx.x & (GL - 1);
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd);
-    const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
     const int64_t two_r = 2 * R;
-    if (L >= n_origins * two_r) return;  // whole groups leave together
+    const int64_t n_rays = n_origins * two_r;
+    const int64_t nb = (n_rays * GL + blockDim.x - 1) / blockDim.x;  // logical blocks
+    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd); blk < nb; blk += gridDim.x) {
+    const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
+    if (L >= n_rays) continue;  // whole groups leave together
     int64_t oi, rr;
     if (order) {
         const int64_t dslot = L / n_origins;
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
             if (MODE != TRACE_WRITE) lens[ray] = 0;
             if (MODE != TRACE_COUNT) atomicOr(err, ERRBIT_ORIGIN);
         }
-        return;
+        continue;
     }
     const double* dv = dirs + 3 * ((per_origin ? oi * R : 0) + r);
     double dx = dv[0], dy = dv[1], dz = dv[2];
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
         Zc = b.Z;
     }
     if (MODE != TRACE_WRITE && sub == 0) lens[ray] = n;
+    }
 }
 
 // Padded slots (ray * cap) -> compacted lists at ray_off.  Eight lanes per ray.
@@ -232,13 +235,16 @@ __global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ pid
                                                   int64_t cap, const int64_t* __restrict__ ray_off, int64_t n_rays,
                                                   int32_t* __restrict__ ids, double* __restrict__ Z) {
     const int sub = threadIdx.x & 7;
-    const int64_t ray = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 3;
-    if (ray >= n_rays) return;
-    const int64_t b = ray_off[ray], n = ray_off[ray + 1] - b;
-    const int64_t src = ray * cap;
-    for (int64_t j = sub; j < n && j < cap; j += 8) {
-        ids[b + j] = pids[src + j];
-        Z[b + j] = pZ[src + j];
+    const int64_t nb = (n_rays * 8 + blockDim.x - 1) / blockDim.x;
+    for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+        const int64_t ray = (blk * (int64_t)blockDim.x + threadIdx.x) >> 3;
+        if (ray >= n_rays) continue;
+        const int64_t b = ray_off[ray], n = ray_off[ray + 1] - b;
+        const int64_t src = ray * cap;
+        for (int64_t j = sub; j < n && j < cap; j += 8) {
+            ids[b + j] = pids[src + j];
+            Z[b + j] = pZ[src + j];
+        }
     }
 }
 
@@ -327,20 +333,20 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t* __rest
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
-inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+inline int64_t blocks_for(int64_t n, int b) { return (n + b - 1) / b; }
 
 }  // namespace
 
 hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_build_rows, dim3(blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
+    hipLaunchKernelGGL(k_build_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
     if (m->E > 0)
-        hipLaunchKernelGGL(k_build_nbr, dim3(blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
+        hipLaunchKernelGGL(k_build_nbr, dim3((unsigned)blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
                            m->E, m->nbr, bad);
-    hipLaunchKernelGGL(k_check_off, dim3(blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->P, m->E, bad);
+    hipLaunchKernelGGL(k_check_off, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->P, m->E, bad);
     return hipGetLastError();
 }
 
@@ -353,15 +359,15 @@ static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_
     if (gl != 4 && gl != 16) gl = 8;
     int32_t* ew = MODE == TRACE_COUNT ? nullptr : error_word();
     if (gl == 16)
-        hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(blocks_for(n * 16, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+        hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(capped_blocks(blocks_for(n * 16, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     else if (gl == 8)
-        hipLaunchKernelGGL((k_trace<MODE, 8>), dim3(blocks_for(n * 8, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+        hipLaunchKernelGGL((k_trace<MODE, 8>), dim3(capped_blocks(blocks_for(n * 8, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     else
-        hipLaunchKernelGGL((k_trace<MODE, 4>), dim3(blocks_for(n * 4, TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, s, m->pos,
+        hipLaunchKernelGGL((k_trace<MODE, 4>), dim3(capped_blocks(blocks_for(n * 4, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     return hipGetLastError();
@@ -391,7 +397,7 @@ hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_
 hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
                           int32_t* ids, double* Z, hipStream_t s) {
     if (n_rays == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_rays * 8, 256)), dim3(256), 0, s, pids, pZ, cap, ray_off, n_rays,
+    hipLaunchKernelGGL(k_compact, dim3(capped_blocks(blocks_for(n_rays * 8, 256))), dim3(256), 0, s, pids, pZ, cap, ray_off, n_rays,
                        ids, Z);
     return hipGetLastError();
 }
@@ -414,7 +420,7 @@ hipError_t launch_scan(const int32_t* lens, int64_t n, int64_t* off, void* ws, h
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_fill_i32, dim3(capped_blocks(blocks_for(n, 256))), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@ library consume what it produces, and neither depends on the other.
 from .models import (  # noqa: F401
     Model,
     FreqGrid,
+    concat_models,
     delaunay_csr,
     lattice_model,
     sphere_model,

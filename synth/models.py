@@ -362,12 +362,48 @@ def sph_cloud_model(seed: int, P: int, F: int = 64, chi0: float = 1.0, v0: float
                  meta=dict(seed=seed))
 
 
+def _sph_one(args):
+    seed, P, F = args
+    return sph_cloud_model(seed, P, F=F)
+
+
 def sph_batch_models(n_models: int = 64, seed0: int = 400, lo: int = 10_000, hi: int = 200_000,
-                     F: int = 64, scale: float = 1.0) -> List[Model]:
-    """n_models independent SPH-like clouds with log-uniform sizes in [lo, hi] (times scale)."""
-    out = []
+                     F: int = 64, scale: float = 1.0, workers: int = 0) -> List[Model]:
+    """n_models independent SPH-like clouds with log-uniform sizes in [lo, hi] (times scale).
+    workers > 1 builds the clouds in that many processes (same result)."""
+    jobs = []
     for k in range(n_models):
         rng = np.random.default_rng(seed0 + k)
         P = int(np.exp(rng.uniform(np.log(lo), np.log(hi))) * scale)
-        out.append(sph_cloud_model(seed0 + k, max(P, 64), F=F))
-    return out
+        jobs.append((seed0 + k, max(P, 64), F))
+    if workers and workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(_sph_one, jobs))
+    return [_sph_one(j) for j in jobs]
+
+
+def concat_models(models: List[Model], spacing: float = 100.0) -> Model:
+    """Disjoint union of models with the same frequency grid: neighbour ids are
+    offset so no ray crosses from one model into another, and model k is
+    translated to cell k of a cubic grid of the given spacing so the models also
+    occupy disjoint regions of space.  meta["offsets"] gives each model's first
+    point."""
+    n = len(models)
+    side = int(np.ceil(n ** (1.0 / 3.0)))
+    pos, off, idx, vel, chi, eta = [], [np.zeros(1, np.int64)], [], [], [], []
+    base_p, base_e, starts = 0, 0, []
+    for k, m in enumerate(models):
+        cell = np.array([k % side, (k // side) % side, k // (side * side)], np.float64)
+        pos.append(m.pos + spacing * cell)
+        off.append(m.nbr_off[1:] + base_e)
+        idx.append(m.nbr_idx.astype(np.int64) + base_p)
+        vel.append(m.vel if m.vel is not None else np.zeros((m.P, 3), np.float32))
+        chi.append(m.chi)
+        eta.append(m.eta)
+        starts.append(base_p)
+        base_p += m.P
+        base_e += m.E
+    return Model("batch", np.concatenate(pos), np.concatenate(off), np.concatenate(idx).astype(np.int32),
+                 np.concatenate(vel).astype(np.float32), np.concatenate(chi), np.concatenate(eta), models[0].freq,
+                 models[0].I_bc.copy(), meta=dict(offsets=np.array(starts + [base_p]), n_models=n))

@@ -331,3 +331,79 @@ def test_adaptive_J_and_lmax_identity(rt, orc, wind):
             n += 1
     assert n == len(origins) * 96
     del torch
+
+
+# ----------------------------------------------------------------------------- batching, octree, autotuner
+
+def test_octree_cloud_parity(rt, orc):
+    # touching-leaf adjacency: many exact distance ties, two frequency blocks
+    m = synth.octree_model(seed=31, lmin=3, lmax=5, target=3000)
+    rng = np.random.default_rng(8)
+    origins = rng.choice(m.P, 200, replace=False)
+    model, ds, g, e, dirs, w2, org, oo = _trace_both(rt, orc, m, 2, origins)
+    _assert_rays_equal(g, e)
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    Je = orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64)
+    J64 = _solve_gpu(rt, m, model, ds, g, org, len(oo), rt.RT_F64, chi=c64, eta=e64)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    J32 = _solve_gpu(rt, m, model, ds, g, org, len(oo), rt.RT_F32, chi=c32, eta=e32)
+    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
+
+
+def test_batched_union(rt, orc):
+    torch = _torch()
+    ms = synth.sph_batch_models(n_models=5, lo=800, hi=3000, seed0=900)
+    u = synth.concat_models(ms)
+    model = _gpu_model(rt, u)
+    ds = rt.DirSet.uniform(2)
+    c32, e32, c64, e64 = synth.to_fp32_tables(u.chi, u.eta)
+    J = torch.empty((u.P, u.F), dtype=torch.float32, device="cuda")
+    plan = rt.Plan(model, ds, _t(c32), _t(e32), u.freq.len, u.freq.dx, _t(u.I_bc, torch.float64), J,
+                   n_origins=u.P, precision=rt.RT_F32, schedule=rt.SCHED_BINNED)
+    plan.run()
+    rt.sync_status()
+    off, ids, Z = (x.cpu().numpy() for x in plan.rays())
+    # no ray leaves its own model
+    starts = u.meta["offsets"]
+    owner = np.searchsorted(starts, np.arange(u.P), side="right") - 1
+    ray_origin = np.repeat(np.arange(u.P), 2 * ds.R)
+    ray_of_entry = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    assert np.array_equal(owner[ids], owner[ray_origin[ray_of_entry]])
+    # sampled origins of every model against the oracle on the union
+    rng = np.random.default_rng(9)
+    origins = np.concatenate([rng.choice(np.arange(starts[k], starts[k + 1]), 20, replace=False)
+                              for k in range(len(ms))]).astype(np.int32)
+    _, dirs, w2 = orc.dirset_uniform(2)
+    Je = orc.compute_J(u, dirs, w2, origins=origins, chi=c64, eta=e64)
+    assert _rel(J.cpu().numpy()[origins].astype(np.float64), Je) <= TOL32
+
+
+def test_autotune_and_cache(rt, wind, tmp_path):
+    torch = _torch()
+    origins = np.arange(0, wind.P, 20).astype(np.int32)
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(2)
+    c32, e32, _, _ = synth.to_fp32_tables(wind.chi, wind.eta)
+    chi, eta = _t(c32), _t(e32)
+    I_bc = _t(wind.I_bc, torch.float64)
+    J = torch.empty((len(origins), wind.F), dtype=torch.float32, device="cuda")
+    cache = str(tmp_path / "tune.txt")
+    opts, ms = rt.autotune(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=_t(origins),
+                           n_runs=1, cache_path=cache)
+    assert opts["schedule"] in (0, 1, 2) and opts["group"] in (4, 8) and opts["trace_lanes"] in (4, 8, 16)
+    assert ms > 0 and open(cache).read().count("\n") == 1
+    opts2, ms2 = rt.autotune(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=_t(origins),
+                             n_runs=1, cache_path=cache)
+    assert opts2 == opts and abs(ms2 - ms) < 1e-3 and open(cache).read().count("\n") == 1
+    plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=_t(origins), **opts)
+    plan.run()
+    rt.sync_status()
+    ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=_t(origins))
+    assert np.array_equal(J.cpu().numpy(), ref.cpu().numpy())
+    # re-captured with every schedule and tile option: the same result, bit for bit
+    for sc, g, la, wpc in ((2, 8, 16, 0), (1, 4, 4, 16), (0, 8, 8, 0), (2, 4, 8, 0)):
+        J.zero_()
+        plan.retune(schedule=sc, group=g, trace_lanes=la, waves_per_cu=wpc, n_bins=64 if sc == 1 else 0)
+        plan.run()
+        rt.sync_status()
+        assert np.array_equal(J.cpu().numpy(), ref.cpu().numpy())
