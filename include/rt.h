@@ -259,6 +259,96 @@ rt_status rt_autotune(const rt_model* model, const rt_dirset* set, const int32_t
                       const char* cache_path, int32_t verbose, void* stream, rt_solve_opts* best,
                       double* best_ms);
 
+/* ------------------------------------------------------------------ learned closure
+ * A cheap J from the nside = 1 set (6 pairs, Section 2.1.3) plus local optical
+ * properties is mapped by a small network to the J of the nside = 8 set (384
+ * pairs); points whose predicted error exceeds a bound are re-solved by the
+ * plain method (rt_plan_* over the flagged origins) and merged back.  Two
+ * features come from the paper's re-meshing section: the relative-difference
+ * indicator of eq. 6 and the local element size of eq. 8.
+ *
+ * Network, fixed shape: 16 inputs (12 features, 4 zero) -> 256 -> 256 -> 256 -> 2,
+ * SiLU (z / (1 + exp(-z))) after the three hidden layers, outputs y = (m, s):
+ * m predicts log(J_fine / J_coarse), s the log variance of that prediction.
+ * Products run on the matrix cores in BF16 with FP32 accumulation: inputs,
+ * weights, stored pre-activations z and activations silu(z) are BF16; biases
+ * and outputs FP32; the backward signal dz is rounded to BF16 before each
+ * product.  FP32 master parameters (layout W1[16][256], b1[256], W2[256][256],
+ * b2, W3[256][256], b3, W4[256][2], b4[2], row-major, RT_MLP_NPARAM floats)
+ * and Adam moments are owned by the handle; BF16 copies are refreshed after
+ * every change of the parameters. */
+#define RT_MLP_D_IN 16
+#define RT_MLP_WIDTH 256
+#define RT_MLP_D_OUT 2
+#define RT_MLP_NPARAM 136450
+#define RT_CLOSURE_STAT_BLOCKS 1024
+typedef struct rt_mlp rt_mlp;
+rt_status rt_mlp_num_params(int64_t* n);
+/* New network: weights N(0, 2/fan_in) (N(0, 1/fan_in) for the output layer,
+ * fan_in 12 for the first), biases 0, Adam state 0.  Synchronises. */
+rt_status rt_mlp_create(uint64_t seed, void* stream, rt_mlp** out);
+rt_status rt_mlp_destroy(rt_mlp* mlp);
+/* Parameters / accumulated gradients as RT_MLP_NPARAM host floats.  Synchronise. */
+rt_status rt_mlp_get_params(const rt_mlp* mlp, float* host, void* stream);
+rt_status rt_mlp_set_params(rt_mlp* mlp, const float* host, void* stream);
+rt_status rt_mlp_get_grads(const rt_mlp* mlp, float* host, void* stream);
+rt_status rt_mlp_zero_grad(rt_mlp* mlp, void* stream); /* async */
+/* Workspace bytes for n samples: 0 for inference, else the stored
+ * pre-activations (3*n*256 BF16) plus per-64-sample-tile gradient partials. */
+rt_status rt_mlp_workspace(int64_t n, int32_t training, size_t* bytes);
+/* Y[i][2] (device f32) = network(X[rows[i]]) for i < n; X device BF16 [*][16]
+ * (bit patterns as uint16), rows device int32 or NULL (identity).  keep != 0
+ * stores the pre-activations in ws for rt_mlp_backward.  n < 2^31.  Async. */
+rt_status rt_mlp_forward(rt_mlp* mlp, const uint16_t* X, const int32_t* rows, int64_t n, float* Y, int32_t keep,
+                         void* ws, size_t ws_bytes, void* stream);
+/* Adds to the gradients d(sum_i dY[i] . Y[i])/d(params) for the samples of the
+ * last keep-forward with the same X, rows, n and ws (dY device f32 [n][2]).
+ * The per-tile partials are summed in tile order (deterministic).  Async. */
+rt_status rt_mlp_backward(rt_mlp* mlp, const uint16_t* X, const int32_t* rows, int64_t n, const float* dY,
+                          void* ws, size_t ws_bytes, void* stream);
+/* Mean Gaussian negative log-likelihood over n samples, per sample
+ * 0.5 (exp(-s) (t - m)^2 + s) with t = T[rows[i]] (T device f32, rows as in
+ * rt_mlp_forward): dY[i] = its gradient w.r.t. Y[i]; *loss_sum (device f32, may
+ * be NULL; caller zeroes it) += the sum of the per-sample losses.  Async. */
+rt_status rt_mlp_nll(const float* Y, const float* T, const int32_t* rows, int64_t n, float* dY, float* loss_sum,
+                     void* stream);
+/* One Adam step on the accumulated gradients (bias-corrected moments,
+ * decoupled weight decay wd: w -= lr (m_hat / (sqrt(v_hat) + eps) + wd w)),
+ * then the BF16 copies are refreshed.  Gradients are left as they are.  Async. */
+rt_status rt_mlp_adam_step(rt_mlp* mlp, float lr, float b1, float b2, float eps, float wd, void* stream);
+/* Features feat[(k*F + f)][16] (device f32) for points p = points[k] (device
+ * int32, or NULL for p = k) at frequency f < F: 0 log J1[k][f], 1 log chi,
+ * 2 log S (S = eta/chi), 3 and 4 neighbour means of log chi and log S, 5 the
+ * neighbour standard deviation of log chi, 6 and 7 max over neighbours n of
+ * |(f_p - f_n)/(f_p + f_n)| for chi and S (eq. 6), 8 log L_p with L_p the mean
+ * distance to the neighbours (eq. 8), 9 log(chi L_p), 10 freq_x[f] / 5,
+ * 11 log(neighbour count), 12..15 zero.  chi, eta device f32 [P][ld]; J1 device
+ * f32 [n_points][F]; freq_x device f32 [F] in Doppler widths.  An id outside
+ * 0..P-1 gives a zero row and latches RT_ERR_ARG (rt_sync_status).  Async. */
+rt_status rt_closure_features(const rt_model* model, const float* chi, const float* eta, int64_t ld, int64_t F,
+                              const float* freq_x, const float* J1, const int32_t* points, int64_t n_points,
+                              float* feat, void* stream);
+/* sums[0..15] = column sums of feat[n][16], sums[16..31] = sums of squares
+ * (device f64), summed in a fixed order; partial: device f64 scratch of
+ * RT_CLOSURE_STAT_BLOCKS*32.  Async. */
+rt_status rt_closure_feature_stats(const float* feat, int64_t n, double* sums, double* partial, void* stream);
+/* X[i][c] = bf16((feat[i][c] - mean[c]) * inv_std[c]); mean, inv_std host f32 [16]. Async. */
+rt_status rt_closure_normalize(const float* feat, int64_t n, const float* mean, const float* inv_std, uint16_t* X,
+                               void* stream);
+/* Closure and fallback flags: J[p][f] = J1[p][f] exp(Y[p*F+f][0]) for p < n_points;
+ * p is flagged when 0.5 Y[p*F+f][1] > log_bound for some f (log_bound = -inf
+ * flags every point, +inf none).  flagged (device int32 [n_points]) receives the
+ * flagged positions in unspecified order, *n_flagged (device int32) their count.
+ * Async. */
+rt_status rt_closure_apply(const float* J1, const float* Y, int64_t n_points, int64_t F, float log_bound, float* J,
+                           int32_t* flagged, int32_t* n_flagged, void* stream);
+/* Training targets T[i] = log(J_fine[i] / J1[i]) (device f32, n values).  Async. */
+rt_status rt_closure_targets(const float* J1, const float* J_fine, int64_t n, float* T, void* stream);
+/* J[flagged[k]][f] = J_fine[k][f] for k < n_flagged (J [n_points][F]); a
+ * position outside 0..n_points-1 is skipped and latches RT_ERR_ARG.  Async. */
+rt_status rt_closure_merge(const float* J_fine, const int32_t* flagged, int64_t n_flagged, int64_t F,
+                           int64_t n_points, float* J, void* stream);
+
 /* Synchronise `stream` and return the error latched by kernels since the last
  * call (RT_ERR_CAPACITY; RT_ERR_NONFINITE; RT_ERR_ARG for an origin id outside
  * 0 .. P-1, whose rays are then empty and whose J row is undefined), then

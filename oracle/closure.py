@@ -74,12 +74,19 @@ def dsilu(z):
 
 
 class MLP:
-    """Parameters as a dict of float64 arrays: W1 [16,256], b1, W2, b2, W3, b3, W4 [256,2], b4."""
+    """Parameters as a dict of float64 arrays: W1 [16,256], b1, W2, b2, W3, b3, W4 [256,2], b4.
+
+    rnd (optional) is applied where a reduced-precision implementation stores a
+    value: the pre-activations z, the activations silu(z) and the backward
+    signals dz (pass bf16_round to mirror a BF16 matrix-core implementation; the
+    weights and inputs are rounded by the caller).  The default stores exactly.
+    """
 
     SHAPES = (("W1", (D_IN, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (256, 256)), ("b3", (256,)), ("W4", (256, 2)), ("b4", (2,)))
 
-    def __init__(self, flat: np.ndarray):
+    def __init__(self, flat: np.ndarray, rnd=None):
+        self.rnd = rnd if rnd is not None else (lambda a: a)
         self.p = {}
         o = 0
         for name, shp in self.SHAPES:
@@ -97,30 +104,30 @@ class MLP:
         return np.concatenate([d[n].ravel() for n, _ in self.SHAPES])
 
     def forward(self, X):
-        p = self.p
-        z1 = X @ p["W1"] + p["b1"]
-        h1 = silu(z1)
-        z2 = h1 @ p["W2"] + p["b2"]
-        h2 = silu(z2)
-        z3 = h2 @ p["W3"] + p["b3"]
-        h3 = silu(z3)
+        p, r = self.p, self.rnd
+        z1 = r(X @ p["W1"] + p["b1"])
+        h1 = r(silu(z1))
+        z2 = r(h1 @ p["W2"] + p["b2"])
+        h2 = r(silu(z2))
+        z3 = r(h2 @ p["W3"] + p["b3"])
+        h3 = r(silu(z3))
         y = h3 @ p["W4"] + p["b4"]
         return y, (X, z1, h1, z2, h2, z3, h3)
 
     def backward(self, cache, dy):
         """Gradients of sum(dy * y) with respect to every parameter."""
         X, z1, h1, z2, h2, z3, h3 = cache
-        p = self.p
+        p, r = self.p, self.rnd
         g = {}
         g["W4"] = h3.T @ dy
         g["b4"] = dy.sum(0)
-        dz3 = (dy @ p["W4"].T) * dsilu(z3)
+        dz3 = r((dy @ p["W4"].T) * dsilu(z3))
         g["W3"] = h2.T @ dz3
         g["b3"] = dz3.sum(0)
-        dz2 = (dz3 @ p["W3"].T) * dsilu(z2)
+        dz2 = r((dz3 @ p["W3"].T) * dsilu(z2))
         g["W2"] = h1.T @ dz2
         g["b2"] = dz2.sum(0)
-        dz1 = (dz2 @ p["W2"].T) * dsilu(z1)
+        dz1 = r((dz2 @ p["W2"].T) * dsilu(z1))
         g["W1"] = X.T @ dz1
         g["b1"] = dz1.sum(0)
         return g

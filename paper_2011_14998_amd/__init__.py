@@ -12,13 +12,21 @@ from .binding import (  # noqa: F401
     SCHED_BINNED,
     SCHED_DIRECT,
     SCHED_SPATIAL,
+    MLP,
     DirSet,
     Model,
     Plan,
     RtError,
     autotune,
+    closure_apply,
+    closure_feature_stats,
+    closure_features,
+    closure_merge,
+    closure_normalize,
+    closure_targets,
     compute_J,
     load,
+    mlp_nll,
     solve,
     sync_status,
     trace,

@@ -67,6 +67,24 @@ _SIGS = {
                            C.POINTER(_dbl)]),
     "rt_plan_retune": (_i32, [_vp, C.POINTER(SolveOptsC), _vp]),
     "rt_sync_status": (_i32, [_vp]),
+    "rt_mlp_num_params": (_i32, [C.POINTER(_i64)]),
+    "rt_mlp_create": (_i32, [C.c_uint64, _vp, C.POINTER(_vp)]),
+    "rt_mlp_destroy": (_i32, [_vp]),
+    "rt_mlp_get_params": (_i32, [_vp, _vp, _vp]),
+    "rt_mlp_set_params": (_i32, [_vp, _vp, _vp]),
+    "rt_mlp_get_grads": (_i32, [_vp, _vp, _vp]),
+    "rt_mlp_zero_grad": (_i32, [_vp, _vp]),
+    "rt_mlp_workspace": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "rt_mlp_forward": (_i32, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _sz, _vp]),
+    "rt_mlp_backward": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "rt_mlp_nll": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "rt_mlp_adam_step": (_i32, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "rt_closure_feature_stats": (_i32, [_vp, _i64, _vp, _vp, _vp]),
+    "rt_closure_normalize": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "rt_closure_apply": (_i32, [_vp, _vp, _i64, _i64, C.c_float, _vp, _vp, _vp, _vp]),
+    "rt_closure_merge": (_i32, [_vp, _vp, _i64, _i64, _i64, _vp, _vp]),
+    "rt_closure_targets": (_i32, [_vp, _vp, _i64, _vp, _vp]),
 }
 
 
@@ -396,3 +414,184 @@ class Plan:
         if _lib is not None and getattr(self, "_h", None):
             _lib.rt_plan_destroy(self._h)
             self._h = None
+
+
+# ---------------------------------------------------------------- learned closure
+
+MLP_D_IN = 16
+MLP_NPARAM = 136450
+CLOSURE_STAT_BLOCKS = 1024
+
+
+class MLP:
+    """The closure network (rt_mlp): FP32 master parameters, Adam state, BF16 copies on the device."""
+
+    def __init__(self, seed: int = 0, stream=None):
+        h = _vp()
+        _check(load().rt_mlp_create(seed, _stream(stream), C.byref(h)))
+        self._h = h
+        self._ws = None
+
+    @staticmethod
+    def n_params() -> int:
+        n = _i64()
+        _check(load().rt_mlp_num_params(C.byref(n)))
+        return n.value
+
+    def get_params(self, stream=None) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, np.float32)
+        _check(load().rt_mlp_get_params(self._h, out.ctypes.data, _stream(stream)))
+        return out
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == MLP_NPARAM
+        _check(load().rt_mlp_set_params(self._h, p.ctypes.data, _stream(stream)))
+
+    def get_grads(self, stream=None) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, np.float32)
+        _check(load().rt_mlp_get_grads(self._h, out.ctypes.data, _stream(stream)))
+        return out
+
+    def zero_grad(self, stream=None):
+        _check(load().rt_mlp_zero_grad(self._h, _stream(stream)))
+
+    def workspace(self, n: int, device="cuda"):
+        """A training workspace for up to n samples (kept by the handle)."""
+        torch = _torch()
+        b = _sz()
+        _check(load().rt_mlp_workspace(n, 1, C.byref(b)))
+        if self._ws is None or self._ws.numel() < b.value:
+            self._ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def forward(self, X, n=None, rows=None, Y=None, keep=False, stream=None):
+        """Y [n][2] f32 for the BF16 inputs X [*][16] (int16 bit patterns), rows optional int32 gather list."""
+        torch = _torch()
+        if rows is not None:
+            rows = _dev(rows, torch.int32)
+            n = rows.numel() if n is None else n
+        elif n is None:
+            n = X.shape[0]
+        X = _dev(X, torch.int16)
+        if Y is None:
+            Y = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+        ws = self.workspace(n, X.device) if keep else None
+        _check(load().rt_mlp_forward(self._h, _ptr(X), _ptr(rows), n, _ptr(_dev(Y, torch.float32)), 1 if keep else 0,
+                                     _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)))
+        return Y
+
+    def backward(self, X, dY, n=None, rows=None, stream=None):
+        """Accumulate the gradients of sum(dY * Y) for the last keep-forward over the same samples."""
+        torch = _torch()
+        if rows is not None:
+            rows = _dev(rows, torch.int32)
+            n = rows.numel() if n is None else n
+        elif n is None:
+            n = X.shape[0]
+        ws = self.workspace(n, X.device)
+        _check(load().rt_mlp_backward(self._h, _ptr(_dev(X, torch.int16)), _ptr(rows), n,
+                                      _ptr(_dev(dY, torch.float32)), _ptr(ws), ws.numel(), _stream(stream)))
+
+    def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, wd: float = 0.0,
+                  stream=None):
+        _check(load().rt_mlp_adam_step(self._h, lr, b1, b2, eps, wd, _stream(stream)))
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None):
+            _lib.rt_mlp_destroy(self._h)
+            self._h = None
+
+
+def mlp_nll(Y, T, rows=None, n=None, dY=None, loss_sum=None, stream=None):
+    """Gaussian NLL gradient dY (and, with loss_sum, the summed loss) for targets T[rows[i]]."""
+    torch = _torch()
+    if rows is not None:
+        rows = _dev(rows, torch.int32)
+        n = rows.numel() if n is None else n
+    elif n is None:
+        n = Y.shape[0]
+    if dY is None:
+        dY = torch.empty((n, 2), dtype=torch.float32, device=Y.device)
+    _check(load().rt_mlp_nll(_ptr(_dev(Y, torch.float32)), _ptr(_dev(T, torch.float32)), _ptr(rows), n,
+                             _ptr(dY), _ptr(loss_sum), _stream(stream)))
+    return dY
+
+
+def closure_features(model: Model, chi, eta, freq_x, J1, points=None, feat=None, stream=None):
+    """Features [n_points*F][16] f32 of rt_closure_features (J1 [n_points][F] f32)."""
+    torch = _torch()
+    chi, eta = _dev(chi, torch.float32), _dev(eta, torch.float32)
+    J1 = _dev(J1, torch.float32)
+    freq_x = _dev(freq_x, torch.float32)
+    n_points, F = J1.shape
+    if points is not None:
+        points = _dev(points, torch.int32)
+        assert points.numel() == n_points
+    if feat is None:
+        feat = torch.empty((n_points * F, MLP_D_IN), dtype=torch.float32, device=J1.device)
+    _check(load().rt_closure_features(model._h, _ptr(chi), _ptr(eta), chi.shape[1], F, _ptr(freq_x), _ptr(J1),
+                                      _ptr(points), n_points, _ptr(_dev(feat, torch.float32)), _stream(stream)))
+    return feat
+
+
+def closure_feature_stats(feat, stream=None):
+    """Column sums and sums of squares (device f64 [32]) of feat [n][16]."""
+    torch = _torch()
+    feat = _dev(feat, torch.float32)
+    sums = torch.empty(2 * MLP_D_IN, dtype=torch.float64, device=feat.device)
+    part = torch.empty(CLOSURE_STAT_BLOCKS * 2 * MLP_D_IN, dtype=torch.float64, device=feat.device)
+    _check(load().rt_closure_feature_stats(_ptr(feat), feat.shape[0], _ptr(sums), _ptr(part), _stream(stream)))
+    return sums
+
+
+def closure_normalize(feat, mean, inv_std, X=None, stream=None):
+    """BF16 (int16 bit patterns) X = (feat - mean) * inv_std; mean, inv_std host arrays of 16."""
+    torch = _torch()
+    feat = _dev(feat, torch.float32)
+    m = np.ascontiguousarray(mean, np.float32)
+    s = np.ascontiguousarray(inv_std, np.float32)
+    assert m.size == MLP_D_IN and s.size == MLP_D_IN
+    if X is None:
+        X = torch.empty((feat.shape[0], MLP_D_IN), dtype=torch.int16, device=feat.device)
+    _check(load().rt_closure_normalize(_ptr(feat), feat.shape[0], m.ctypes.data, s.ctypes.data,
+                                       _ptr(_dev(X, torch.int16)), _stream(stream)))
+    return X
+
+
+def closure_apply(J1, Y, log_bound: float, J=None, flagged=None, n_flagged=None, stream=None):
+    """J = J1 exp(m) and the fallback list; returns (J, flagged, n_flagged device int32 [1])."""
+    torch = _torch()
+    J1 = _dev(J1, torch.float32)
+    n_points, F = J1.shape
+    dev = J1.device
+    if J is None:
+        J = torch.empty_like(J1)
+    if flagged is None:
+        flagged = torch.empty(max(n_points, 1), dtype=torch.int32, device=dev)
+    if n_flagged is None:
+        n_flagged = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(load().rt_closure_apply(_ptr(J1), _ptr(_dev(Y, torch.float32)), n_points, F, float(log_bound),
+                                   _ptr(_dev(J, torch.float32)), _ptr(flagged), _ptr(n_flagged), _stream(stream)))
+    return J, flagged, n_flagged
+
+
+def closure_merge(J_fine, flagged, n_flagged: int, J, stream=None):
+    """J[flagged[k]] = J_fine[k] for k < n_flagged."""
+    torch = _torch()
+    J = _dev(J, torch.float32)
+    _check(load().rt_closure_merge(_ptr(_dev(J_fine, torch.float32)), _ptr(_dev(flagged, torch.int32)), n_flagged,
+                                   J.shape[1], J.shape[0], _ptr(J), _stream(stream)))
+    return J
+
+
+def closure_targets(J1, J_fine, T=None, stream=None):
+    """T = log(J_fine / J1) elementwise (f32)."""
+    torch = _torch()
+    J1, J_fine = _dev(J1, torch.float32), _dev(J_fine, torch.float32)
+    assert J1.shape == J_fine.shape
+    if T is None:
+        T = torch.empty(J1.numel(), dtype=torch.float32, device=J1.device)
+    _check(load().rt_closure_targets(_ptr(J1), _ptr(J_fine), J1.numel(), _ptr(_dev(T, torch.float32)),
+                                     _stream(stream)))
+    return T

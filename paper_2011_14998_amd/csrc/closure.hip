@@ -1,0 +1,826 @@
+// Learned closure: features of the coarse (nside 1) solution, a 4-layer MLP in
+// BF16 on the matrix cores with FP32 accumulation (forward, backward, Adam),
+// and the closure/fallback assembly.
+//
+// Network: h1 = silu(x W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
+// y = h3 W4 + b4; x has 16 inputs (12 features, 4 zero), hidden width 256,
+// y = (m, s): m predicts log(J_fine/J_coarse), s the log variance of its error.
+// Parameters live as FP32 master weights (layout W1[16][256], b1, W2[256][256],
+// b2, W3[256][256], b3, W4[256][2], b4); BF16 copies are published after every
+// update: transposed [N][K] for the forward products and [K][N] for the
+// backward ones.
+//
+// Rounding points (mirrored by the FP64 reference in the tests): x, weights,
+// stored pre-activations z and activations h = silu(z) are BF16; products
+// accumulate in FP32 (MFMA); biases and the head are FP32; the backward signal
+// dz = dh * silu'(z) is rounded to BF16 before it enters the matrix cores.
+//
+// Tiles: one workgroup (4 waves) takes 64 samples.  Forward: each wave owns 64
+// of the 256 output columns, 4x4 tiles of v_mfma_f32_16x16x16_bf16, activations
+// stay in LDS between layers.  Backward: weight gradients are formed per tile
+// (H^T dZ on the matrix cores) into a per-tile partial buffer and summed by a
+// separate pass in tile order (deterministic).
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+namespace {
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+constexpr int DIN = 16;
+constexpr int HW = 256;   // hidden width
+constexpr int DOUT = 2;
+constexpr int MT = 64;    // samples per workgroup
+constexpr int LDH = HW + 8;  // LDS row stride (bf16 elements) of activation tiles
+constexpr int LDX = DIN + 4;
+
+// master-parameter offsets
+constexpr int64_t OFF_W1 = 0;
+constexpr int64_t OFF_B1 = OFF_W1 + DIN * HW;
+constexpr int64_t OFF_W2 = OFF_B1 + HW;
+constexpr int64_t OFF_B2 = OFF_W2 + HW * HW;
+constexpr int64_t OFF_W3 = OFF_B2 + HW;
+constexpr int64_t OFF_B3 = OFF_W3 + HW * HW;
+constexpr int64_t OFF_W4 = OFF_B3 + HW;
+constexpr int64_t OFF_B4 = OFF_W4 + HW * DOUT;
+constexpr int64_t NPARAM = OFF_B4 + DOUT;
+static_assert(NPARAM == RT_MLP_NPARAM, "parameter count");
+constexpr int64_t MAX_SAMPLES = ((int64_t)1 << 31) - 1;  // sample indices are int32
+
+// BF16 copies: forward (transposed [N][K]) and backward ([K][N]) layouts
+constexpr int64_t WT1 = 0;                 // [256][16]
+constexpr int64_t WT2 = WT1 + HW * DIN;    // [256][256]
+constexpr int64_t WT3 = WT2 + HW * HW;     // [256][256]
+constexpr int64_t WT4 = WT3 + HW * HW;     // [16][256], rows >= 2 zero
+constexpr int64_t NWT = WT4 + 16 * HW;
+constexpr int64_t WB2 = 0;                 // [256][256]
+constexpr int64_t WB3 = WB2 + HW * HW;
+constexpr int64_t NWB = WB3 + HW * HW;
+
+__host__ __device__ inline uint16_t f2bf(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ inline v4i16 ld4(const uint16_t* p) {  // 4 consecutive bf16 (8-byte aligned)
+    return *(const v4i16*)p;
+}
+__device__ inline v4i16 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+    v4i16 r;
+    r[0] = (short)a;
+    r[1] = (short)b;
+    r[2] = (short)c;
+    r[3] = (short)d;
+    return r;
+}
+__device__ inline v4f32 mfma(v4i16 a, v4i16 b, v4f32 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- publish / init
+
+__global__ void k_publish(const float* __restrict__ w, uint16_t* __restrict__ wt, uint16_t* __restrict__ wb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < HW * DIN) {  // W1t[n][k] = W1[k][n]
+        const int n = (int)(i / DIN), k = (int)(i % DIN);
+        wt[WT1 + i] = f2bf(w[OFF_W1 + (int64_t)k * HW + n]);
+    }
+    if (i < HW * HW) {
+        const int n = (int)(i / HW), k = (int)(i % HW);
+        wt[WT2 + i] = f2bf(w[OFF_W2 + (int64_t)k * HW + n]);
+        wt[WT3 + i] = f2bf(w[OFF_W3 + (int64_t)k * HW + n]);
+        wb[WB2 + i] = f2bf(w[OFF_W2 + i]);
+        wb[WB3 + i] = f2bf(w[OFF_W3 + i]);
+    }
+    if (i < 16 * HW) {  // W4t[c][k] = W4[k][c], c < 2
+        const int c = (int)(i / HW), k = (int)(i % HW);
+        wt[WT4 + i] = c < DOUT ? f2bf(w[OFF_W4 + (int64_t)k * DOUT + c]) : (uint16_t)0;
+    }
+}
+
+// ---------------------------------------------------------------- forward
+
+// out[64][256] = silu(bf16(in[64][K] * W + b)), W given as Wt[256][K] (bf16).
+// Wave w owns columns [64w, 64w+64): 4 row tiles x 4 column tiles.
+__device__ inline void fwd_layer(const uint16_t* in, int ldin, int K, const uint16_t* __restrict__ Wt,
+                                 const float* __restrict__ bias, uint16_t* out, uint16_t* __restrict__ zout,
+                                 int64_t row0, int nvalid) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    v4f32 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        v4i16 a[4], b[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = ld4(in + (mt * 16 + r) * ldin + k0 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) b[nt] = ld4(Wt + (int64_t)(64 * w + 16 * nt + r) * K + k0 + 4 * g);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int col = 64 * w + 16 * nt + r;
+            const float bb = bias[col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * g + i;
+                const uint16_t zb = f2bf(acc[mt][nt][i] + bb);
+                if (zout && row < nvalid) zout[(row0 + row) * HW + col] = zb;
+                out[row * LDH + col] = f2bf(silu(bf2f(zb)));
+            }
+        }
+}
+
+template <bool KEEP>
+__global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ wt, const float* __restrict__ w,
+                                                  const uint16_t* __restrict__ X, const int32_t* __restrict__ rows,
+                                                  int64_t n, float* __restrict__ Y, uint16_t* __restrict__ Z) {
+    __shared__ __attribute__((aligned(16))) uint16_t sx[MT * LDX];
+    __shared__ __attribute__((aligned(16))) uint16_t sa[MT * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[MT * LDH];
+    const int64_t row0 = (int64_t)blockIdx.x * MT;
+    const int nvalid = (int)(n - row0 < MT ? n - row0 : MT);
+    {   // 64 x 16 inputs: thread t loads 4 of row t/4
+        const int t = threadIdx.x, m = t >> 2, q = t & 3;
+        v4i16 v = (v4i16){0, 0, 0, 0};
+        if (m < nvalid) {
+            const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
+            v = ld4(X + src * DIN + 4 * q);
+        }
+        *(v4i16*)(sx + m * LDX + 4 * q) = v;
+    }
+    __syncthreads();
+    uint16_t* Z1 = KEEP ? Z : nullptr;
+    uint16_t* Z2 = KEEP ? Z + n * HW : nullptr;
+    uint16_t* Z3 = KEEP ? Z + 2 * n * HW : nullptr;
+    fwd_layer(sx, LDX, DIN, wt + WT1, w + OFF_B1, sa, Z1, row0, nvalid);
+    __syncthreads();
+    fwd_layer(sa, LDH, HW, wt + WT2, w + OFF_B2, sb, Z2, row0, nvalid);
+    __syncthreads();
+    fwd_layer(sb, LDH, HW, wt + WT3, w + OFF_B3, sa, Z3, row0, nvalid);
+    __syncthreads();
+    // head: wave w takes rows [16w, 16w+16); columns 0..15 of W4t, 0 and 1 used
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < HW; k0 += 16)
+        acc = mfma(ld4(sa + (16 * wv + r) * LDH + k0 + 4 * g), ld4(wt + WT4 + (int64_t)r * HW + k0 + 4 * g), acc);
+    if (r < DOUT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * wv + 4 * g + i;
+            if (row < nvalid) Y[(row0 + row) * DOUT + r] = acc[i] + w[OFF_B4 + r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward
+
+// part[wofs + j*Ncols + n] = sum over the 64 samples of H[m][j] dZ[m][n]:
+// wave w takes rows j in [64w, 64w+64), in column strips of 64.
+__device__ inline void grad_HtdZ(const uint16_t* H, int ldh, const uint16_t* dZ, float* __restrict__ part,
+                                 int64_t wofs, int Ncols) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int jbase = 64 * w;
+    for (int nh = 0; nh < HW; nh += 64) {
+        v4f32 acc[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int m0 = 0; m0 < MT; m0 += 16) {
+            v4i16 a[4], b[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const uint16_t* p = H + (m0 + 4 * g) * ldh + jbase + 16 * mt + r;
+                a[mt] = pack4(p[0], p[ldh], p[2 * ldh], p[3 * ldh]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const uint16_t* p = dZ + (m0 + 4 * g) * LDH + nh + 16 * nt + r;
+                b[nt] = pack4(p[0], p[LDH], p[2 * LDH], p[3 * LDH]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = jbase + 16 * mt + 4 * g + i;
+                    part[wofs + (int64_t)j * Ncols + nh + 16 * nt + r] = acc[mt][nt][i];
+                }
+    }
+}
+
+// dH[64][256] = dZ[64][256] * W^T (W as [K][N] row-major = B operand [n][k]);
+// then dZ_prev = bf16(dH * silu'(z_prev)) into out, rows >= nvalid zero.
+__device__ inline void bwd_dH(const uint16_t* dZ, const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ zprev,
+                              uint16_t* out, int64_t row0, int nvalid) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    v4f32 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < HW; k0 += 16) {
+        v4i16 a[4], b[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = ld4(dZ + (mt * 16 + r) * LDH + k0 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) b[nt] = ld4(Wb + (int64_t)(64 * w + 16 * nt + r) * HW + k0 + 4 * g);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+    }
+    __syncthreads();  // every wave has read dZ before it is overwritten
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int col = 64 * w + 16 * nt + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * g + i;
+                float v = 0.f;
+                if (row < nvalid) v = acc[mt][nt][i] * dsilu(bf2f(zprev[(row0 + row) * HW + col]));
+                out[row * LDH + col] = f2bf(v);
+            }
+        }
+}
+
+// h[m][j] = bf16(silu(z[m][j])) for the 64 rows of the tile (zero beyond nvalid).
+__device__ inline void load_h(const uint16_t* __restrict__ z, uint16_t* h, int64_t row0, int nvalid) {
+    const int j = threadIdx.x;
+    for (int m = 0; m < MT; ++m)
+        h[m * LDH + j] = m < nvalid ? f2bf(silu(bf2f(z[(row0 + m) * HW + j]))) : (uint16_t)0;
+}
+
+// column sums of dZ (bias gradient) into the partial row
+__device__ inline void bias_grad(const uint16_t* dZ, float* __restrict__ part, int64_t ofs) {
+    const int j = threadIdx.x;
+    float s = 0.f;
+    for (int m = 0; m < MT; ++m) s += bf2f(dZ[m * LDH + j]);
+    part[ofs + j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t* __restrict__ wt, const uint16_t* __restrict__ wb,
+                                                  const float* __restrict__ w, const uint16_t* __restrict__ X,
+                                                  const int32_t* __restrict__ rows, int64_t n,
+                                                  const uint16_t* __restrict__ Z, const float* __restrict__ dY,
+                                                  float* __restrict__ partial) {
+    __shared__ __attribute__((aligned(16))) uint16_t sx[MT * LDH];  // inputs (16 columns used), then reused
+    __shared__ __attribute__((aligned(16))) uint16_t sd[MT * LDH];  // dZ of the current layer
+    __shared__ __attribute__((aligned(16))) uint16_t sh[MT * LDH];  // activations feeding the current layer
+    __shared__ float sdy[MT * DOUT];
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * MT;
+    const int nvalid = (int)(n - row0 < MT ? n - row0 : MT);
+    float* part = partial + tile * NPARAM;
+    const uint16_t* Z1 = Z;
+    const uint16_t* Z2 = Z + n * HW;
+    const uint16_t* Z3 = Z + 2 * n * HW;
+    const int t = threadIdx.x;
+    if (t < MT * DOUT) {
+        const int m = t / DOUT;
+        sdy[t] = m < nvalid ? dY[(row0 + m) * DOUT + (t % DOUT)] : 0.f;
+    }
+    {
+        const int m = t >> 2, q = t & 3;
+        v4i16 v = (v4i16){0, 0, 0, 0};
+        if (m < nvalid) {
+            const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
+            v = ld4(X + src * DIN + 4 * q);
+        }
+        *(v4i16*)(sx + m * LDH + 4 * q) = v;
+    }
+    __syncthreads();
+    // head: dW4[j][c] = sum_m h3[m][j] dY[m][c];  dZ3 = bf16((dY W4^T) * silu'(z3))
+    {
+        const int j = t;
+        const float w40 = bf2f(f2bf(w[OFF_W4 + j * DOUT])), w41 = bf2f(f2bf(w[OFF_W4 + j * DOUT + 1]));
+        float g0 = 0.f, g1 = 0.f, db = 0.f;
+        for (int m = 0; m < MT; ++m) {
+            float z = m < nvalid ? bf2f(Z3[(row0 + m) * HW + j]) : 0.f;
+            const float h = m < nvalid ? bf2f(f2bf(silu(z))) : 0.f;
+            g0 += h * sdy[m * DOUT];
+            g1 += h * sdy[m * DOUT + 1];
+            const float dz = (sdy[m * DOUT] * w40 + sdy[m * DOUT + 1] * w41) * dsilu(z);
+            const uint16_t dzb = m < nvalid ? f2bf(dz) : (uint16_t)0;
+            sd[m * LDH + j] = dzb;
+            db += bf2f(dzb);
+        }
+        part[OFF_W4 + j * DOUT] = g0;
+        part[OFF_W4 + j * DOUT + 1] = g1;
+        part[OFF_B3 + j] = db;
+        if (j < DOUT) {
+            float s = 0.f;
+            for (int m = 0; m < MT; ++m) s += sdy[m * DOUT + j];
+            part[OFF_B4 + j] = s;
+        }
+    }
+    load_h(Z2, sh, row0, nvalid);
+    __syncthreads();
+    // layer 3: dW3 = H2^T dZ3; dZ2 = bf16((dZ3 W3^T) * silu'(z2))
+    grad_HtdZ(sh, LDH, sd, part, OFF_W3, HW);
+    __syncthreads();
+    bwd_dH(sd, wb + WB3, Z2, sd, row0, nvalid);
+    __syncthreads();
+    bias_grad(sd, part, OFF_B2);
+    load_h(Z1, sh, row0, nvalid);
+    __syncthreads();
+    // layer 2: dW2 = H1^T dZ2; dZ1 = bf16((dZ2 W2^T) * silu'(z1))
+    grad_HtdZ(sh, LDH, sd, part, OFF_W2, HW);
+    __syncthreads();
+    bwd_dH(sd, wb + WB2, Z1, sd, row0, nvalid);
+    __syncthreads();
+    bias_grad(sd, part, OFF_B1);
+    __syncthreads();
+    // layer 1: dW1 = X^T dZ1 (16 x 256): wave w takes columns [64w, 64w+64)
+    {
+        const int lane = t & 63, wv = t >> 6;
+        const int g = lane >> 4, r = lane & 15;
+        v4f32 acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int m0 = 0; m0 < MT; m0 += 16) {
+            const uint16_t* pa = sx + (m0 + 4 * g) * LDH + r;
+            const v4i16 a = pack4(pa[0], pa[LDH], pa[2 * LDH], pa[3 * LDH]);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const uint16_t* pb = sd + (m0 + 4 * g) * LDH + 64 * wv + 16 * nt + r;
+                acc[nt] = mfma(a, pack4(pb[0], pb[LDH], pb[2 * LDH], pb[3 * LDH]), acc[nt]);
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[OFF_W1 + (int64_t)(4 * g + i) * HW + 64 * wv + 16 * nt + r] = acc[nt][i];
+    }
+}
+
+// grad[p] += sum over tiles, in tile order, of partial[tile][p]
+__global__ void k_grad_reduce(const float* __restrict__ partial, int64_t n_tiles, float* __restrict__ grad) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    float s = 0.f;
+    for (int64_t t = 0; t < n_tiles; ++t) s += partial[t * NPARAM + p];
+    grad[p] += s;
+}
+
+// mean Gaussian NLL: 0.5 (exp(-s) (t - m)^2 + s); dY for the mean over n samples
+__global__ void k_nll(const float* __restrict__ Y, const float* __restrict__ T, const int32_t* __restrict__ rows,
+                      int64_t n, float* __restrict__ dY, float* __restrict__ loss_sum) {
+    __shared__ float red[256];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (i < n) {
+        const float m = Y[2 * i], s = Y[2 * i + 1];
+        const float t = T[rows ? (int64_t)rows[i] : i];
+        const float e = __expf(-s), d = t - m;
+        l = 0.5f * (e * d * d + s);
+        dY[2 * i] = -(e * d) / (float)n;
+        dY[2 * i + 1] = 0.5f * (1.f - e * d * d) / (float)n;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0]);
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
+}
+
+// ---------------------------------------------------------------- features
+
+// feat[(k*F + f)*16 + c] for point p = points[k] (or p = k) at frequency f;
+// J1 is [n_points][F] in the same order.  Features (c): 0 log J1, 1 log chi,
+// 2 log S, 3/4 neighbour mean of log chi / log S, 5 neighbour standard
+// deviation of log chi, 6/7 the eq. 6 indicator max_n |(f_p - f_n)/(f_p + f_n)|
+// of chi and S, 8 log L_p with L_p the mean neighbour distance (eq. 8),
+// 9 log(chi L_p), 10 x_f / 5, 11 log(number of neighbours), 12..15 zero.
+__global__ void k_features(const double* __restrict__ pos, const int64_t* __restrict__ off,
+                           const int32_t* __restrict__ idx, const float* __restrict__ chi,
+                           const float* __restrict__ eta, int64_t ld, int64_t F, const float* __restrict__ fx,
+                           const float* __restrict__ J1, const int32_t* __restrict__ points, int64_t n_points,
+                           int64_t P, float* __restrict__ feat, int32_t* __restrict__ err) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_points * F) return;
+    const int64_t k = i / F;
+    const int64_t f = i - k * F;
+    const int64_t p = points ? (int64_t)points[k] : k;
+    if (p < 0 || p >= P) {
+        if (err) atomicOr(err, ERRBIT_ORIGIN);
+        for (int c = 0; c < DIN; ++c) feat[i * DIN + c] = 0.f;
+        return;
+    }
+    const float cp = chi[p * ld + f], sp = eta[p * ld + f] / cp;
+    const int64_t e0 = off[p], e1 = off[p + 1];
+    const double px = pos[3 * p], py = pos[3 * p + 1], pz = pos[3 * p + 2];
+    float s_lc = 0.f, s_ls = 0.f, gc = 0.f, gs = 0.f;
+    double L = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t q = idx[e];
+        const float cq = chi[q * ld + f], sq = eta[q * ld + f] / cq;
+        s_lc += logf(cq);
+        s_ls += logf(sq);
+        gc = fmaxf(gc, fabsf((cp - cq) / (cp + cq)));
+        gs = fmaxf(gs, fabsf((sp - sq) / (sp + sq)));
+        const double dx = pos[3 * q] - px, dy = pos[3 * q + 1] - py, dz = pos[3 * q + 2] - pz;
+        L += sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    const float nd = (float)(e1 - e0);
+    const float mlc = s_lc / nd;
+    float var = 0.f;
+    for (int64_t e = e0; e < e1; ++e) {
+        const float d = logf(chi[(int64_t)idx[e] * ld + f]) - mlc;
+        var += d * d;
+    }
+    const float Lp = (float)(L / (double)(e1 - e0));
+    float* o = feat + i * DIN;
+    o[0] = logf(J1[k * F + f]);
+    o[1] = logf(cp);
+    o[2] = logf(sp);
+    o[3] = mlc;
+    o[4] = s_ls / nd;
+    o[5] = sqrtf(var / nd);
+    o[6] = gc;
+    o[7] = gs;
+    o[8] = logf(Lp);
+    o[9] = logf(cp * Lp);
+    o[10] = fx[f] / 5.f;
+    o[11] = logf(nd);
+    o[12] = o[13] = o[14] = o[15] = 0.f;
+}
+
+// Column sums and sums of squares of feat[n][16]: block b accumulates rows
+// b*256 + t + k*STAT_BLOCKS*256 per thread, reduces in a fixed order and
+// writes part[b][32]; k_feature_stats_final sums the blocks in order.
+constexpr int STAT_BLOCKS = RT_CLOSURE_STAT_BLOCKS;
+
+__global__ __launch_bounds__(256) void k_feature_stats(const float* __restrict__ feat, int64_t n,
+                                                        double* __restrict__ part) {
+    __shared__ double sw[4][2 * DIN];
+    double acc[2 * DIN];
+#pragma unroll
+    for (int c = 0; c < 2 * DIN; ++c) acc[c] = 0.0;
+    for (int64_t r = blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)STAT_BLOCKS * 256) {
+#pragma unroll
+        for (int c = 0; c < DIN; ++c) {
+            const double v = feat[r * DIN + c];
+            acc[c] += v;
+            acc[DIN + c] += v * v;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2 * DIN; ++c)
+        for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 2 * DIN; ++c) sw[w][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 2 * DIN)
+        part[blockIdx.x * 2 * DIN + threadIdx.x] =
+            ((sw[0][threadIdx.x] + sw[1][threadIdx.x]) + sw[2][threadIdx.x]) + sw[3][threadIdx.x];
+}
+
+__global__ void k_feature_stats_final(const double* __restrict__ part, double* __restrict__ sums) {
+    const int c = threadIdx.x;
+    if (c >= 2 * DIN) return;
+    double s = 0.0;
+    for (int b = 0; b < STAT_BLOCKS; ++b) s += part[b * 2 * DIN + c];
+    sums[c] = s;
+}
+
+struct Norm {
+    float mean[DIN], istd[DIN];
+};
+
+__global__ void k_normalize(const float* __restrict__ feat, int64_t n, const Norm nm, uint16_t* __restrict__ X) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * DIN;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % DIN);
+        X[i] = f2bf((feat[i] - nm.mean[c]) * nm.istd[c]);
+    }
+}
+
+// ---------------------------------------------------------------- closure assembly
+
+__global__ void k_closure_apply(const float* __restrict__ J1, const float* __restrict__ Y, int64_t n_points,
+                                int64_t F, float log_bound, float* __restrict__ J, int32_t* __restrict__ flagged,
+                                int32_t* __restrict__ n_flagged) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n_points) return;
+    bool fl = false;
+    for (int64_t f = 0; f < F; ++f) {
+        const int64_t i = p * F + f;
+        J[i] = J1[i] * __expf(Y[2 * i]);
+        fl = fl || (0.5f * Y[2 * i + 1] > log_bound);
+    }
+    if (fl) flagged[atomicAdd(n_flagged, 1)] = (int32_t)p;
+}
+
+__global__ void k_closure_merge(const float* __restrict__ Jf, const int32_t* __restrict__ flagged, int64_t n_flagged,
+                                int64_t F, int64_t n_points, float* __restrict__ J, int32_t* __restrict__ err) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_flagged * F;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = i / F, f = i - k * F;
+        const int64_t p = flagged[k];
+        if (p < 0 || p >= n_points) {
+            if (err) atomicOr(err, ERRBIT_ORIGIN);
+            continue;
+        }
+        J[p * F + f] = Jf[i];
+    }
+}
+
+__global__ void k_targets(const float* __restrict__ J1, const float* __restrict__ Jf, int64_t n,
+                          float* __restrict__ T) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        T[i] = logf(Jf[i] / J1[i]);
+}
+
+inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+}  // namespace rt
+
+using namespace rt;
+
+struct rt_mlp {
+    float* w = nullptr;     // master parameters
+    float* g = nullptr;     // gradients
+    float* m = nullptr;     // Adam moments
+    float* v = nullptr;
+    uint16_t* wt = nullptr; // BF16 forward copies
+    uint16_t* wb = nullptr; // BF16 backward copies
+    int64_t step = 0;
+};
+
+static rt_status mlp_publish(rt_mlp* h, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(nb(HW * HW, 256)), dim3(256), 0, s, h->w, h->wt, h->wb);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_num_params(int64_t* n) {
+    if (!n) return fail(RT_ERR_ARG, "rt_mlp_num_params: NULL");
+    *n = NPARAM;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_create(uint64_t seed, void* stream, rt_mlp** out) {
+    if (!out) return fail(RT_ERR_ARG, "rt_mlp_create: NULL output");
+    *out = nullptr;
+    auto* h = new rt_mlp();
+    hipError_t e = hipMalloc((void**)&h->w, sizeof(float) * NPARAM);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->g, sizeof(float) * NPARAM);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->m, sizeof(float) * NPARAM);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->v, sizeof(float) * NPARAM);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->wt, sizeof(uint16_t) * NWT);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->wb, sizeof(uint16_t) * NWB);
+    // He-style initialisation: weights N(0, 2/fan_in) for the SiLU layers, N(0, 1/fan_in) for the head; biases 0
+    std::vector<float> p((size_t)NPARAM, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    auto fill = [&](int64_t ofs, int64_t cnt, float sd) {
+        for (int64_t i = 0; i < cnt; ++i) p[(size_t)(ofs + i)] = sd * nd(rng);
+    };
+    fill(OFF_W1, DIN * HW, std::sqrt(2.f / 12.f));
+    fill(OFF_W2, HW * HW, std::sqrt(2.f / HW));
+    fill(OFF_W3, HW * HW, std::sqrt(2.f / HW));
+    fill(OFF_W4, HW * DOUT, std::sqrt(1.f / HW));
+    hipStream_t s = (hipStream_t)stream;
+    if (e == hipSuccess) e = hipMemcpyAsync(h->w, p.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, sizeof(float) * NPARAM, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->m, 0, sizeof(float) * NPARAM, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->v, 0, sizeof(float) * NPARAM, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rt_status st = hip_fail(e, "rt_mlp_create");
+        rt_mlp_destroy(h);
+        return st;
+    }
+    rt_status st = mlp_publish(h, s);
+    if (st) {
+        rt_mlp_destroy(h);
+        return st;
+    }
+    *out = h;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_destroy(rt_mlp* h) {
+    if (!h) return RT_OK;
+    for (void* q : {(void*)h->w, (void*)h->g, (void*)h->m, (void*)h->v, (void*)h->wt, (void*)h->wb})
+        if (q) (void)hipFree(q);
+    delete h;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_get_params(const rt_mlp* h, float* host, void* stream) {
+    if (!h || !host) return fail(RT_ERR_ARG, "rt_mlp_get_params: NULL");
+    RT_HIP(hipMemcpyAsync(host, h->w, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_set_params(rt_mlp* h, const float* host, void* stream) {
+    if (!h || !host) return fail(RT_ERR_ARG, "rt_mlp_set_params: NULL");
+    hipStream_t s = (hipStream_t)stream;
+    RT_HIP(hipMemcpyAsync(h->w, host, sizeof(float) * NPARAM, hipMemcpyHostToDevice, s));
+    RT_HIP(hipStreamSynchronize(s));
+    return mlp_publish(h, s);
+}
+
+extern "C" rt_status rt_mlp_get_grads(const rt_mlp* h, float* host, void* stream) {
+    if (!h || !host) return fail(RT_ERR_ARG, "rt_mlp_get_grads: NULL");
+    RT_HIP(hipMemcpyAsync(host, h->g, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_zero_grad(rt_mlp* h, void* stream) {
+    if (!h) return fail(RT_ERR_ARG, "rt_mlp_zero_grad: NULL");
+    RT_HIP(hipMemsetAsync(h->g, 0, sizeof(float) * NPARAM, (hipStream_t)stream));
+    return RT_OK;
+}
+
+// Training workspace: the BF16 pre-activations Z[3][n][256], then (256-byte
+// aligned) the per-tile weight-gradient partials [tiles][NPARAM] in FP32.
+static size_t z_bytes(int64_t n) { return (((size_t)(3 * n * HW) * sizeof(uint16_t)) + 255) & ~(size_t)255; }
+static size_t ws_bytes_for(int64_t n) {
+    const int64_t tiles = (n + MT - 1) / MT;
+    return z_bytes(n) + (size_t)(tiles * NPARAM) * sizeof(float);
+}
+
+extern "C" rt_status rt_mlp_workspace(int64_t n, int32_t training, size_t* bytes) {
+    if (!bytes || n < 0) return fail(RT_ERR_ARG, "rt_mlp_workspace: bad arguments");
+    *bytes = training ? ws_bytes_for(n) : 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_forward(rt_mlp* h, const uint16_t* X, const int32_t* rows, int64_t n, float* Y,
+                                    int32_t keep, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || (n > 0 && (!X || !Y)) || n < 0 || n > MAX_SAMPLES)
+        return fail(RT_ERR_ARG, "rt_mlp_forward: bad arguments");
+    if (n == 0) return RT_OK;
+    if (keep && (!ws || ws_bytes < ws_bytes_for(n))) return fail(RT_ERR_CAPACITY, "rt_mlp_forward: workspace too small");
+    const unsigned grid = nb(n, MT);
+    hipStream_t s = (hipStream_t)stream;
+    if (keep)
+        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y, (uint16_t*)ws);
+    else
+        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y, nullptr);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_backward(rt_mlp* h, const uint16_t* X, const int32_t* rows, int64_t n, const float* dY,
+                                     void* ws, size_t ws_bytes, void* stream) {
+    if (!h || (n > 0 && (!X || !dY)) || n < 0 || n > MAX_SAMPLES)
+        return fail(RT_ERR_ARG, "rt_mlp_backward: bad arguments");
+    if (n == 0) return RT_OK;
+    if (!ws || ws_bytes < ws_bytes_for(n)) return fail(RT_ERR_CAPACITY, "rt_mlp_backward: workspace too small");
+    const int64_t tiles = (n + MT - 1) / MT;
+    const uint16_t* Z = (const uint16_t*)ws;
+    float* partial = (float*)((char*)ws + z_bytes(n));
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)tiles), dim3(256), 0, s, h->wt, h->wb, h->w, X, rows, n, Z, dY,
+                       partial);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(nb(NPARAM, 256)), dim3(256), 0, s, partial, tiles, h->g);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_nll(const float* Y, const float* T, const int32_t* rows, int64_t n, float* dY,
+                                float* loss_sum, void* stream) {
+    if ((n > 0 && (!Y || !T || !dY)) || n < 0 || n > MAX_SAMPLES) return fail(RT_ERR_ARG, "rt_mlp_nll: bad arguments");
+    if (n == 0) return RT_OK;
+    hipLaunchKernelGGL(k_nll, dim3(nb(n, 256)), dim3(256), 0, (hipStream_t)stream, Y, T, rows, n, dY, loss_sum);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_adam_step(rt_mlp* h, float lr, float b1, float b2, float eps, float wd, void* stream) {
+    if (!h) return fail(RT_ERR_ARG, "rt_mlp_adam_step: NULL");
+    h->step += 1;
+    const float c1 = 1.f - std::pow(b1, (float)h->step), c2 = 1.f - std::pow(b2, (float)h->step);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_adam, dim3(nb(NPARAM, 256)), dim3(256), 0, s, h->w, h->g, h->m, h->v, lr, b1, b2, eps, wd,
+                       c1, c2);
+    RT_HIP(hipGetLastError());
+    return mlp_publish(h, s);
+}
+
+extern "C" rt_status rt_closure_features(const rt_model* m, const float* chi, const float* eta, int64_t ld, int64_t F,
+                                         const float* freq_x, const float* J1, const int32_t* points,
+                                         int64_t n_points, float* feat, void* stream) {
+    if (!m || !chi || !eta || !freq_x || !J1 || (n_points > 0 && !feat) || F <= 0 || ld < F || n_points < 0 ||
+        n_points * F > MAX_SAMPLES || (!points && n_points > m->P))
+        return fail(RT_ERR_ARG, "rt_closure_features: bad arguments");
+    if (n_points == 0) return RT_OK;
+    hipLaunchKernelGGL(k_features, dim3(nb(n_points * F, 256)), dim3(256), 0, (hipStream_t)stream, m->pos, m->off,
+                       m->idx, chi, eta, ld, F, freq_x, J1, points, n_points, m->P, feat, error_word());
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_feature_stats(const float* feat, int64_t n, double* sums, double* partial,
+                                              void* stream) {
+    if (!sums || !partial || (n > 0 && !feat) || n < 0)
+        return fail(RT_ERR_ARG, "rt_closure_feature_stats: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_feature_stats, dim3(STAT_BLOCKS), dim3(256), 0, s, feat, n, partial);
+    hipLaunchKernelGGL(k_feature_stats_final, dim3(1), dim3(64), 0, s, partial, sums);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_normalize(const float* feat, int64_t n, const float* mean, const float* inv_std,
+                                          uint16_t* X, void* stream) {
+    if (!mean || !inv_std || (n > 0 && (!feat || !X)) || n < 0)
+        return fail(RT_ERR_ARG, "rt_closure_normalize: bad arguments");
+    if (n == 0) return RT_OK;
+    Norm nm;
+    std::memcpy(nm.mean, mean, sizeof(nm.mean));
+    std::memcpy(nm.istd, inv_std, sizeof(nm.istd));
+    hipLaunchKernelGGL(k_normalize, dim3(capped_blocks(nb(n * DIN, 256))), dim3(256), 0, (hipStream_t)stream, feat, n, nm, X);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_apply(const float* J1, const float* Y, int64_t n_points, int64_t F, float log_bound,
+                                      float* J, int32_t* flagged, int32_t* n_flagged, void* stream) {
+    if ((n_points > 0 && (!J1 || !Y || !J || !flagged)) || !n_flagged || F <= 0 || n_points < 0)
+        return fail(RT_ERR_ARG, "rt_closure_apply: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RT_HIP(launch_fill_i32(n_flagged, 1, 0, s));
+    if (n_points == 0) return RT_OK;
+    hipLaunchKernelGGL(k_closure_apply, dim3(nb(n_points, 256)), dim3(256), 0, s, J1, Y,
+                       n_points, F, log_bound, J, flagged, n_flagged);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_merge(const float* J_fine, const int32_t* flagged, int64_t n_flagged, int64_t F,
+                                      int64_t n_points, float* J, void* stream) {
+    if ((n_flagged > 0 && (!J_fine || !flagged || !J)) || F <= 0 || n_flagged < 0)
+        return fail(RT_ERR_ARG, "rt_closure_merge: bad arguments");
+    if (n_flagged == 0) return RT_OK;
+    hipLaunchKernelGGL(k_closure_merge, dim3(capped_blocks(nb(n_flagged * F, 256))), dim3(256), 0, (hipStream_t)stream, J_fine,
+                       flagged, n_flagged, F, n_points, J, error_word());
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_targets(const float* J1, const float* J_fine, int64_t n, float* T, void* stream) {
+    if ((n > 0 && (!J1 || !J_fine || !T)) || n < 0) return fail(RT_ERR_ARG, "rt_closure_targets: bad arguments");
+    if (n == 0) return RT_OK;
+    hipLaunchKernelGGL(k_targets, dim3(capped_blocks(nb(n, 256))), dim3(256), 0, (hipStream_t)stream, J1, J_fine, n, T);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}

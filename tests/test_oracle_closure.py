@@ -116,3 +116,21 @@ def test_bf16_rounding():
     assert r[2] == 1.0078125            # rounds up
     assert abs(r[3] + 3.140625) < 1e-12
     assert np.all(np.abs(r - a) <= np.abs(a) * 2 ** -8)
+
+
+def test_storage_rounding_hook():
+    """With BF16 storage the stored values are representable and the output moves
+    by no more than a few BF16 ulps relative; the identity hook changes nothing."""
+    net = _mlp(6, scale=1.0)
+    rng = np.random.default_rng(7)
+    X = rng.normal(size=(33, 16))
+    y, _ = net.forward(X)
+    r = oc.MLP(net.flat(), rnd=oc.bf16_round)
+    yr, cache = r.forward(X)
+    for a in cache[1:]:
+        assert np.array_equal(oc.bf16_round(a), a)
+    assert np.linalg.norm(yr - y) <= 3 * 2.0 ** -8 * np.linalg.norm(y) * 4
+    g = r.backward(cache, rng.normal(size=(33, 2)))
+    assert all(np.all(np.isfinite(v)) for v in g.values())
+    y_id, _ = oc.MLP(net.flat(), rnd=lambda a: a).forward(X)
+    assert np.array_equal(y_id, y)
