@@ -179,10 +179,13 @@ def main():
     ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial",
                     help="plan schedule when the autotuner is skipped")
     ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
-    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch"], default="wind",
+    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure"],
+                    default="wind",
                     help="wind: the headline 50k-point wind (default); octree: ~500k-leaf AMR-like cloud, 2x48 "
                          "frequencies; octree_reduced: the same field with ~50k leaves; sph_batch: 64 SPH-like "
-                         "clouds as one disjoint union (size scaled by --batch-scale)")
+                         "clouds as one disjoint union (size scaled by --batch-scale); closure: the learned "
+                         "closure trained on winds of seeds 500-503 and judged on 510-511 against the plain "
+                         "nside-8 solve (--closure-points each)")
     ap.add_argument("--batch-scale", type=float, default=0.25)
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner and use the library defaults")
     ap.add_argument("--nside", type=int, default=0, help="HEALPix nside (0 = the workload's own)")
@@ -194,6 +197,12 @@ def main():
     ap.add_argument("--trace-lanes", type=int, default=0, help="lanes per ray in the walk (4 or 8; 0 = default)")
     ap.add_argument("--two-pass-trace", action="store_true",
                     help="walk every ray twice (count, then write) instead of once into padded slots")
+    ap.add_argument("--closure-points", type=int, default=2_000_000, help="points per closure model")
+    ap.add_argument("--closure-train", type=int, default=4, help="closure training models (seeds 500..)")
+    ap.add_argument("--closure-test", type=int, default=2, help="closure test models (seeds 510..)")
+    ap.add_argument("--closure-steps", type=int, default=20000, help="closure training steps")
+    ap.add_argument("--closure-batch", type=int, default=8192)
+    ap.add_argument("--closure-lr", type=float, default=2e-3)
     ap.add_argument("--fp64-below", type=float, default=1e-4,
                     help="FP32 sweep: rows with an optical-depth step below this are eliminated in FP64")
     args = ap.parse_args()
@@ -224,6 +233,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
         return
     rt.load()
+    if args.workload == "closure":
+        run_closure(args)
+        return
 
     t_gen = time.perf_counter()
     if args.workload == "wind":
@@ -340,6 +352,96 @@ def main():
             args.cpu_sample = 3000  # longer lines and more frequencies: keep the CPU leg to tens of seconds
         _log(f"timing the CPU oracle on {args.cpu_sample} origins ...")
         rec["cpu_baseline"] = cpu_baseline(m, dirs, w2, args.cpu_sample)
+    print(json.dumps(rec), flush=True)
+
+
+def _gen_wind(seed_P):
+    import synth
+    seed, P = seed_P
+    t0 = time.perf_counter()
+    m = synth.wind_model(seed=seed, P=P)
+    return m, time.perf_counter() - t0
+
+
+def run_closure(args):
+    """Learned closure vs the plain nside-8 solve: label, train, judge; one JSON line."""
+    import math
+    from concurrent.futures import ProcessPoolExecutor, as_completed
+
+    import torch
+
+    import paper_2011_14998_amd as rt
+    from paper_2011_14998_amd import closure as cl
+
+    P = args.closure_points
+    seeds_train = [500 + i for i in range(args.closure_train)]
+    seeds_test = [510 + i for i in range(args.closure_test)]
+    models = {}
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(8, len(seeds_train) + len(seeds_test))) as ex:
+        futs = [ex.submit(_gen_wind, (s, P)) for s in seeds_train + seeds_test]
+        for f in as_completed(futs):
+            m, sec = f.result()
+            models[m.meta["seed"]] = m
+            _log(f"generated wind seed {m.meta['seed']}: {m.P} points, {m.E} entries ({sec:.0f} s)")
+    gen_s = time.perf_counter() - t0
+    ds1, ds2, ds8 = rt.DirSet.uniform(1), rt.DirSet.uniform(2), rt.DirSet.uniform(8)
+    labs = []
+    t0 = time.perf_counter()
+    for sd in seeds_train:
+        dm = cl.DeviceModel.from_synth(models.pop(sd))
+        labs.append(cl.label(dm, ds1, ds8, verbose=True))
+        _log(f"labelled seed {sd}: nside-1 {labs[-1].coarse.ms:.0f} ms, nside-8 {labs[-1].fine.ms:.0f} ms")
+    label_s = time.perf_counter() - t0
+    X, T, norm = cl.dataset(labs)
+    del labs
+    _log(f"training set: {X.shape[0]} samples")
+    t0 = time.perf_counter()
+    net = cl.train(X, T, norm, steps=args.closure_steps, batch=args.closure_batch, lr=args.closure_lr, seed=7,
+                   log_every=max(1, args.closure_steps // 10))
+    train_s = time.perf_counter() - t0
+    del X, T
+    torch.cuda.empty_cache()
+    fractions = [0.0, 0.1, 0.25, 0.5, 1.0]
+    results = []
+    for sd in seeds_test:
+        dm = cl.DeviceModel.from_synth(models.pop(sd))
+        lab = cl.label(dm, ds1, ds8, verbose=True)
+        # warm timing of both paths: the labelling runs above include first-launch costs
+        r = cl.evaluate(net, lab, ds8, fractions, mid_set=ds2, verbose=True)
+        results.append(r)
+        del lab, dm
+        torch.cuda.empty_cache()
+    # headline: per target fallback fraction, error and time over the test models
+    summary = []
+    for i, q in enumerate(fractions):
+        runs = [r["closure"][i] for r in results]
+        plain = sum(r["plain_ms"] for r in results)
+        tot = sum(c["total_ms"] for c in runs)
+        summary.append(dict(target_fraction=q, median=float(np.median([c["median"] for c in runs])),
+                            median_unflagged=float(np.median([c["median_unflagged"] for c in runs])),
+                            p99=float(np.median([c["p99"] for c in runs])),
+                            flagged_fraction=float(np.mean([c["flagged_fraction"] for c in runs])),
+                            closure_ms=tot, plain_ms=plain, speedup=plain / tot))
+    ok = [s for s in summary if s["median"] <= 1e-3 and s["target_fraction"] < 1.0]
+    head = max(ok, key=lambda s: s["speedup"]) if ok else summary[0]
+    rec = {
+        "metric": "learned closure vs plain nside-8 solve: speedup at the smallest fallback fraction with median "
+                  "J rel err <= 1e-3 (if none reaches it: without fallback, with its error)",
+        "value": head["speedup"],
+        "unit": "x (plain time / closure time)",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": head["closure_ms"] / len(results),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 mfma / f32 accumulate (network), f32 sweep, f64 geometry",
+        "data": "synthetic (seeded analytic winds)",
+        "config": {"workload": f"learned closure, winds of {P} points, train seeds {seeds_train}, test seeds "
+                               f"{seeds_test}; coarse nside 1, fine nside 8, F=64",
+                   "points": P, "train_models": len(seeds_train), "test_models": len(seeds_test),
+                   "steps": args.closure_steps, "batch": args.closure_batch, "lr": args.closure_lr},
+        "headline": head, "fallback_sweep": summary, "per_model": results,
+        "training": {"loss_history": net.history, "train_s": train_s, "label_s": label_s, "generate_s": gen_s},
+    }
     print(json.dumps(rec), flush=True)
 
 

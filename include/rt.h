@@ -234,6 +234,10 @@ rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_
 /* Copy the plan's current ray lists into caller buffers (device; sizes
  * n_origins*2R+1, total, total).  Async. */
 rt_status rt_plan_copy_rays(const rt_plan* plan, int64_t* ray_off, int32_t* ray_ids, double* ray_Z, void* stream);
+/* Copy the per-pair mean intensities of the plan's last run, u[n_origins][R][F]
+ * (eq. 3 before the weighted sum; dtype of the precision), into a caller device
+ * buffer.  Async. */
+rt_status rt_plan_copy_u(const rt_plan* plan, void* u, void* stream);
 rt_status rt_plan_destroy(rt_plan* plan);
 
 /* Re-capture a plan's graph with other scheduling options (schedule, group,
@@ -322,12 +326,15 @@ rt_status rt_mlp_adam_step(rt_mlp* mlp, float lr, float b1, float b2, float eps,
  * neighbour standard deviation of log chi, 6 and 7 max over neighbours n of
  * |(f_p - f_n)/(f_p + f_n)| for chi and S (eq. 6), 8 log L_p with L_p the mean
  * distance to the neighbours (eq. 8), 9 log(chi L_p), 10 freq_x[f] / 5,
- * 11 log(neighbour count), 12..15 zero.  chi, eta device f32 [P][ld]; J1 device
- * f32 [n_points][F]; freq_x device f32 [F] in Doppler widths.  An id outside
- * 0..P-1 gives a zero row and latches RT_ERR_ARG (rt_sync_status).  Async. */
+ * 11 log(neighbour count); with u (device f32 [n_points][R][F], the coarse
+ * solve's per-pair mean intensities, rt_plan_copy_u) 12, 13 and 14 the max,
+ * min and standard deviation over the R pairs of log(u_r / J1), else zero;
+ * 15 zero.  chi, eta device f32 [P][ld]; J1 device f32 [n_points][F]; freq_x
+ * device f32 [F] in Doppler widths.  An id outside 0..P-1 gives a zero row and
+ * latches RT_ERR_ARG (rt_sync_status).  Async. */
 rt_status rt_closure_features(const rt_model* model, const float* chi, const float* eta, int64_t ld, int64_t F,
-                              const float* freq_x, const float* J1, const int32_t* points, int64_t n_points,
-                              float* feat, void* stream);
+                              const float* freq_x, const float* J1, const float* u, int64_t R,
+                              const int32_t* points, int64_t n_points, float* feat, void* stream);
 /* sums[0..15] = column sums of feat[n][16], sums[16..31] = sums of squares
  * (device f64), summed in a fixed order; partial: device f64 scratch of
  * RT_CLOSURE_STAT_BLOCKS*32.  Async. */

@@ -21,7 +21,11 @@ features (in this order; computed from the model, J1 = J at nside 1):
    9  log(chi[p,f] L_p)
   10  x_f / 5                (frequency in Doppler widths)
   11  log(number of neighbours)
-  12..15  zero (padding to 16)
+  12  max over the R coarse pairs r of log(u_r[p,f] / J1[p,f])   (u: per-pair mean
+  13  min over r of the same                                    intensities of the
+  14  standard deviation over r of the same                    coarse solve; zero
+                                                                when not given)
+  15  zero (padding to 16)
 
 network: h1 = silu(x W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
          y = h3 W4 + b4, y = (m, s): m predicts log(J8/J1), s the log variance of
@@ -38,8 +42,8 @@ D_IN = 16
 N_FEAT = 12
 
 
-def features(model, J1: np.ndarray, freq_x: np.ndarray) -> np.ndarray:
-    """[P*F][16] features, sample index p*F + f."""
+def features(model, J1: np.ndarray, freq_x: np.ndarray, u: np.ndarray = None) -> np.ndarray:
+    """[P*F][16] features, sample index p*F + f; u optional [P][R][F]."""
     P, F = model.P, J1.shape[1]
     chi = np.asarray(model.chi, np.float64)
     S = np.asarray(model.eta, np.float64) / chi
@@ -61,6 +65,11 @@ def features(model, J1: np.ndarray, freq_x: np.ndarray) -> np.ndarray:
         X[p, :, 9] = np.log(chi[p] * L)
         X[p, :, 10] = np.asarray(freq_x) / 5.0
         X[p, :, 11] = np.log(len(nb))
+        if u is not None:
+            a = np.log(u[p]) - np.log(J1[p])[None, :]   # [R][F]
+            X[p, :, 12] = a.max(0)
+            X[p, :, 13] = a.min(0)
+            X[p, :, 14] = a.std(0)
     return X.reshape(P * F, D_IN)
 
 

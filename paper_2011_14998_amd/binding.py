@@ -79,7 +79,8 @@ _SIGS = {
     "rt_mlp_backward": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "rt_mlp_nll": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "rt_mlp_adam_step": (_i32, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
-    "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "rt_plan_copy_u": (_i32, [_vp, _vp, _vp]),
     "rt_closure_feature_stats": (_i32, [_vp, _i64, _vp, _vp, _vp]),
     "rt_closure_normalize": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "rt_closure_apply": (_i32, [_vp, _vp, _i64, _i64, C.c_float, _vp, _vp, _vp, _vp]),
@@ -392,6 +393,14 @@ class Plan:
         _check(load().rt_plan_profile(self._h, n_runs, out.ctypes.data, _stream(stream)))
         return dict(zip(self.STAGES, out.tolist()))
 
+    def copy_u(self, u=None, stream=None):
+        """Per-pair mean intensities u [n_origins][R][F] of the last run (device tensor)."""
+        torch = _torch()
+        if u is None:
+            u = torch.empty((self.n_origins, self.dirset.R, self.J.shape[1]), dtype=self.J.dtype, device=self.J.device)
+        _check(load().rt_plan_copy_u(self._h, _ptr(u), _stream(stream)))
+        return u
+
     def info(self):
         tot = _i64()
         off, ids, Z = _vp(), _vp(), _vp()
@@ -518,20 +527,27 @@ def mlp_nll(Y, T, rows=None, n=None, dY=None, loss_sum=None, stream=None):
     return dY
 
 
-def closure_features(model: Model, chi, eta, freq_x, J1, points=None, feat=None, stream=None):
-    """Features [n_points*F][16] f32 of rt_closure_features (J1 [n_points][F] f32)."""
+def closure_features(model: Model, chi, eta, freq_x, J1, u=None, points=None, feat=None, stream=None):
+    """Features [n_points*F][16] f32 of rt_closure_features (J1 [n_points][F] f32; u optional
+    [n_points][R][F] f32 per-pair coarse intensities)."""
     torch = _torch()
     chi, eta = _dev(chi, torch.float32), _dev(eta, torch.float32)
     J1 = _dev(J1, torch.float32)
     freq_x = _dev(freq_x, torch.float32)
     n_points, F = J1.shape
+    R = 0
+    if u is not None:
+        u = _dev(u, torch.float32)
+        assert u.dim() == 3 and u.shape[0] == n_points and u.shape[2] == F
+        R = u.shape[1]
     if points is not None:
         points = _dev(points, torch.int32)
         assert points.numel() == n_points
     if feat is None:
         feat = torch.empty((n_points * F, MLP_D_IN), dtype=torch.float32, device=J1.device)
     _check(load().rt_closure_features(model._h, _ptr(chi), _ptr(eta), chi.shape[1], F, _ptr(freq_x), _ptr(J1),
-                                      _ptr(points), n_points, _ptr(_dev(feat, torch.float32)), _stream(stream)))
+                                      _ptr(u), R, _ptr(points), n_points, _ptr(_dev(feat, torch.float32)),
+                                      _stream(stream)))
     return feat
 
 

@@ -1,0 +1,324 @@
+"""Learned closure driver: coarse solve, features, network, fallback.
+
+Every arithmetic step runs in the library's kernels (rt_plan_* for the
+solves, rt_closure_* and rt_mlp_* for features, network and assembly); this
+module only sequences the calls, owns the device buffers and draws the
+minibatch indices.
+
+Closure (an addition to the method, which computes J from the direction set
+alone): J at nside = 1 (6 pairs, Section 2.1.3) plus local optical properties
+are mapped to the J of the nside = 8 set (384 pairs).  The network predicts
+m = log(J8/J1) and s, the log variance of that prediction; a point whose
+predicted standard deviation exp(s/2) exceeds the bound for some frequency is
+re-solved at nside = 8 (the fallback) and merged back.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import binding as rt
+
+COARSE_NSIDE = 1
+FINE_NSIDE = 8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class DeviceModel:
+    """One model resident on the device: mesh handle, FP32 tables, frequency grid."""
+
+    def __init__(self, pos, nbr_off, nbr_idx, vel, chi, eta, freq_len, freq_dx, freq_x, I_bc, name="model"):
+        torch = _torch()
+        self.name = name
+        self.P, self.F = chi.shape
+        self.model = rt.Model.from_numpy(pos, nbr_off, nbr_idx, vel)
+        dev = "cuda"
+        self.chi = torch.as_tensor(np.ascontiguousarray(chi, np.float32), device=dev)
+        self.eta = torch.as_tensor(np.ascontiguousarray(eta, np.float32), device=dev)
+        self.freq_len = list(freq_len)
+        self.freq_dx = list(freq_dx)
+        self.x = torch.as_tensor(np.ascontiguousarray(freq_x, np.float32), device=dev)
+        self.I_bc = torch.as_tensor(np.ascontiguousarray(I_bc, np.float64), device=dev)
+        self.mean_len = None  # mean ray length (entries), learnt from the first solve
+
+    @classmethod
+    def from_synth(cls, m):
+        return cls(m.pos, m.nbr_off, m.nbr_idx, m.vel, m.chi, m.eta, m.freq.len, m.freq.dx, m.freq.x(), m.I_bc,
+                   name=f"{m.name}{m.meta.get('seed', '')}")
+
+
+@dataclass
+class SolveResult:
+    J: object
+    ms: float                  # summed HIP-event time of the plan replays
+    build_s: float             # wall time of plan creation (count walk, allocation, capture)
+    entries: int               # ray-list entries walked
+    u: object = None           # per-pair mean intensities [n][R][F] when asked for
+
+
+def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: float = 3.0e9, J=None,
+            schedule: int = rt.SCHED_SPATIAL, keep_u: bool = False, verbose: bool = False) -> SolveResult:
+    """J [n][F] (f32) for the listed origins (device int32, or all points) by plans over origin chunks
+    sized to about max_entries ray-list entries each; keep_u also returns the per-pair u."""
+    torch = _torch()
+    n = dm.P if origins is None else int(origins.numel())
+    if J is None:
+        J = torch.empty((max(n, 1), dm.F), dtype=torch.float32, device="cuda")[:n]
+    U = torch.empty((max(n, 1), dirset.R, dm.F), dtype=torch.float32, device="cuda")[:n] if keep_u else None
+    if n == 0:
+        return SolveResult(J, 0.0, 0.0, 0, U)
+    all_ids = origins if origins is not None else torch.arange(n, dtype=torch.int32, device="cuda")
+    per_origin = 2 * dirset.R * (dm.mean_len or 64.0)
+    chunk = min(n, 2048) if dm.mean_len is None else max(1, int(max_entries // per_origin))
+    ms, build_s, entries, c0 = 0.0, 0.0, 0, 0
+    while c0 < n:
+        c1 = min(n, c0 + chunk)
+        t0 = time.time()
+        plan = rt.Plan(dm.model, dirset, dm.chi, dm.eta, dm.freq_len, dm.freq_dx, dm.I_bc, J[c0:c1],
+                       origins=all_ids[c0:c1], precision=rt.RT_F32, schedule=schedule)
+        torch.cuda.synchronize()
+        build_s += time.time() - t0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run()
+        e1.record()
+        e1.synchronize()
+        ms += e0.elapsed_time(e1)
+        if keep_u:
+            plan.copy_u(U[c0:c1])
+        tot = plan.info()["total"]
+        entries += tot
+        if dm.mean_len is None:
+            dm.mean_len = max(1.0, tot / ((c1 - c0) * 2 * dirset.R))
+            per_origin = 2 * dirset.R * dm.mean_len
+        del plan
+        if verbose:
+            print(f"  [{dm.name}] nside-{int(round(math.sqrt(dirset.R / 6)))} solve {c1}/{n} origins, "
+                  f"{ms:.0f} ms", flush=True)
+        c0 = c1
+        chunk = max(1, int(max_entries // per_origin))
+    rt.sync_status()
+    return SolveResult(J, ms, build_s, entries, U)
+
+
+@dataclass
+class Normalizer:
+    mean: np.ndarray
+    inv_std: np.ndarray
+
+    @classmethod
+    def from_sums(cls, sums: np.ndarray, n: int) -> "Normalizer":
+        mean = sums[:16] / n
+        var = np.maximum(sums[16:] / n - mean * mean, 0.0)
+        inv = np.where(var > 1e-12 * np.maximum(1.0, mean * mean), 1.0 / np.sqrt(np.maximum(var, 1e-300)), 0.0)
+        return cls(mean.astype(np.float32), inv.astype(np.float32))
+
+
+def features(dm: DeviceModel, J1, u=None, points=None):
+    return rt.closure_features(dm.model, dm.chi, dm.eta, dm.x, J1, u=u, points=points)
+
+
+@dataclass
+class ClosureNet:
+    mlp: "rt.MLP"
+    norm: Normalizer
+    history: List[float] = field(default_factory=list)
+
+
+def train(X, T, norm: Normalizer, steps: int = 20000, batch: int = 8192, lr: float = 1e-3,
+          lr_final: float = 1e-5, wd: float = 0.0, seed: int = 0, log_every: int = 2000,
+          verbose: bool = True) -> ClosureNet:
+    """Adam on the mean Gaussian NLL over minibatches drawn with replacement (seeded) from
+    the samples X (BF16 bits, [N][16]) with targets T ([N]); cosine learning-rate decay."""
+    torch = _torch()
+    N = X.shape[0]
+    net = rt.MLP(seed=seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dY = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
+    Y = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
+    hist = []
+    t0 = time.time()
+    for step in range(steps):
+        rows = torch.randint(0, N, (batch,), generator=gen, device="cuda", dtype=torch.int32)
+        a = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(1, steps)))
+        net.forward(X, rows=rows, Y=Y, keep=True)
+        rt.mlp_nll(Y, T, rows=rows, dY=dY, loss_sum=loss)
+        net.zero_grad()
+        net.backward(X, dY, rows=rows)
+        net.adam_step(lr=a, wd=wd)
+        if (step + 1) % log_every == 0 or step + 1 == steps:
+            avg = loss.item() / (log_every * batch)
+            loss.zero_()
+            hist.append(avg)
+            if verbose:
+                print(f"  train step {step + 1}/{steps}: mean NLL {avg:.4f}, lr {a:.2e}, "
+                      f"{time.time() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    return ClosureNet(net, norm, hist)
+
+
+@dataclass
+class ClosureResult:
+    J: object
+    n_flagged: int
+    coarse_ms: float
+    infer_ms: float
+    fallback_ms: float
+    fallback_build_s: float
+    flagged: object = None     # device int32, the first n_flagged entries are the flagged positions
+
+    @property
+    def total_ms(self):
+        return self.coarse_ms + self.infer_ms + self.fallback_ms + 1e3 * self.fallback_build_s
+
+
+def infer(net: ClosureNet, dm: DeviceModel, coarse: SolveResult, fine_set: "rt.DirSet", log_bound: float,
+          fallback: bool = True, verbose: bool = False) -> ClosureResult:
+    """Closure J for every point of dm from its coarse solve: features, network, flags, fallback, merge."""
+    torch = _torch()
+    J1, coarse_ms = coarse.J, coarse.ms
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    feat = features(dm, J1, coarse.u)
+    X = rt.closure_normalize(feat, net.norm.mean, net.norm.inv_std)
+    del feat
+    Y = net.mlp.forward(X)
+    J, flagged, nf = rt.closure_apply(J1, Y, log_bound)
+    e1.record()
+    n_flag = int(nf.item())  # synchronises
+    infer_ms = e0.elapsed_time(e1)
+    del X, Y
+    fb_ms, fb_build = 0.0, 0.0
+    if fallback and n_flag > 0:
+        res = solve_J(dm, fine_set, origins=flagged[:n_flag], verbose=verbose)
+        e0.record()
+        rt.closure_merge(res.J, flagged, n_flag, J)
+        e1.record()
+        e1.synchronize()
+        fb_ms = res.ms + e0.elapsed_time(e1)
+        fb_build = res.build_s
+        del res
+    rt.sync_status()
+    return ClosureResult(J, n_flag, coarse_ms, infer_ms, fb_ms, fb_build, flagged)
+
+
+def rel_errors(J, J_ref) -> np.ndarray:
+    """|J - J_ref| / J_ref per (point, f), on the host (float64)."""
+    a = J.double().cpu().numpy()
+    b = J_ref.double().cpu().numpy()
+    return (np.abs(a - b) / np.abs(b)).ravel()
+
+
+def flagged_mask(flagged, n_flagged: int, P: int) -> np.ndarray:
+    mask = np.zeros(P, bool)
+    mask[flagged[:n_flagged].cpu().numpy()] = True
+    return mask
+
+
+def error_summary(J, J_ref, flagged_mask: Optional[np.ndarray], F: int) -> dict:
+    e = rel_errors(J, J_ref)
+    out = dict(median=float(np.median(e)), p99=float(np.quantile(e, 0.99)), max=float(e.max()))
+    if flagged_mask is not None:
+        keep = np.repeat(~flagged_mask, F)
+        ek = e[keep]
+        out.update(median_unflagged=float(np.median(ek)) if ek.size else 0.0,
+                   p99_unflagged=float(np.quantile(ek, 0.99)) if ek.size else 0.0,
+                   flagged_fraction=float(flagged_mask.mean()))
+    return out
+
+
+# ---------------------------------------------------------------- experiment: train on some models, judge on others
+
+@dataclass
+class Labelled:
+    dm: DeviceModel
+    coarse: SolveResult    # nside 1
+    fine: SolveResult      # nside 8 (the label, and the plain method the closure is judged against)
+
+
+def label(dm: DeviceModel, coarse_set, fine_set, verbose: bool = False) -> Labelled:
+    c = solve_J(dm, coarse_set, keep_u=True, verbose=verbose)
+    f = solve_J(dm, fine_set, verbose=verbose)
+    return Labelled(dm, c, f)
+
+
+def dataset(labelled: List[Labelled]):
+    """Normalised BF16 inputs X [N][16], targets T [N] = log(J8/J1) and the normaliser, over all samples."""
+    torch = _torch()
+    feats = [features(lab.dm, lab.coarse.J, lab.coarse.u) for lab in labelled]
+    n = sum(f.shape[0] for f in feats)
+    sums = np.zeros(32)
+    for f in feats:
+        sums += rt.closure_feature_stats(f).cpu().numpy()
+    norm = Normalizer.from_sums(sums, n)
+    X = torch.empty((n, 16), dtype=torch.int16, device="cuda")
+    T = torch.empty(n, dtype=torch.float32, device="cuda")
+    o = 0
+    for f, lab in zip(feats, labelled):
+        k = f.shape[0]
+        rt.closure_normalize(f, norm.mean, norm.inv_std, X=X[o:o + k])
+        rt.closure_targets(lab.coarse.J, lab.fine.J, T=T[o:o + k])
+        o += k
+    del feats
+    torch.cuda.synchronize()
+    return X, T, norm
+
+
+def predicted_sd(net: ClosureNet, dm: DeviceModel, coarse: SolveResult) -> np.ndarray:
+    """Per point, the largest predicted standard deviation exp(s/2) over its frequencies (host)."""
+    X = rt.closure_normalize(features(dm, coarse.J, coarse.u), net.norm.mean, net.norm.inv_std)
+    Y = net.mlp.forward(X)
+    s = Y[:, 1].reshape(dm.P, dm.F).max(1).values
+    return np.exp(0.5 * s.double().cpu().numpy())
+
+
+def evaluate(net: ClosureNet, lab: Labelled, fine_set, flag_fractions=(0.0,), mid_set=None,
+             verbose: bool = False) -> dict:
+    """Closure against the plain nside-8 solve on one model.  For each target fallback fraction q
+    the bound is the (1 - q) quantile of the predicted per-point deviation (q = 0: no fallback;
+    q = 1: every point).  Baselines: J1 alone, and J at mid_set's nside."""
+    dm = lab.dm
+    F = dm.F
+    out = dict(model=dm.name, points=dm.P, F=F, plain_ms=lab.fine.ms, coarse_ms=lab.coarse.ms,
+               coarse_alone=error_summary(lab.coarse.J, lab.fine.J, None, F))
+    if mid_set is not None:
+        mid = solve_J(dm, mid_set)
+        out["mid_alone"] = dict(error_summary(mid.J, lab.fine.J, None, F), ms=mid.ms,
+                                nside=int(round(math.sqrt(mid_set.R / 6))))
+        del mid
+    sd = predicted_sd(net, dm, lab.coarse)
+    out["predicted_sd_quantiles"] = {str(q): float(np.quantile(sd, q)) for q in (0.1, 0.25, 0.5, 0.75, 0.9)}
+    runs = []
+    for q in flag_fractions:
+        if q <= 0:
+            b = math.inf
+        elif q >= 1:
+            b = 0.0
+        else:
+            b = float(np.quantile(sd, 1.0 - q))
+        lb = math.log(b) if b > 0 else -math.inf
+        res = infer(net, dm, lab.coarse, fine_set, lb, verbose=verbose)
+        mask = flagged_mask(res.flagged, res.n_flagged, dm.P)
+        e = error_summary(res.J, lab.fine.J, mask, F)
+        e.update(target_fraction=q, bound=b, n_flagged=res.n_flagged, coarse_ms=res.coarse_ms,
+                 infer_ms=res.infer_ms, fallback_ms=res.fallback_ms, fallback_build_s=res.fallback_build_s,
+                 total_ms=res.total_ms, replay_ms=res.coarse_ms + res.infer_ms + res.fallback_ms,
+                 speedup_vs_plain=lab.fine.ms / res.total_ms if res.total_ms > 0 else None)
+        runs.append(e)
+        if verbose:
+            print(f"  [{dm.name}] fallback {e['flagged_fraction']:.3f} (bound {b:.3g}): median "
+                  f"{e['median']:.2e} (unflagged {e['median_unflagged']:.2e}), closure {res.total_ms:.0f} ms "
+                  f"vs plain {lab.fine.ms:.0f} ms", flush=True)
+        del res
+    out["closure"] = runs
+    return out

@@ -826,6 +826,14 @@ extern "C" rt_status rt_plan_copy_rays(const rt_plan* p, int64_t* ray_off, int32
     return RT_OK;
 }
 
+extern "C" rt_status rt_plan_copy_u(const rt_plan* p, void* u, void* stream) {
+    if (!p || (!u && p->n_origins > 0)) return fail(RT_ERR_ARG, "rt_plan_copy_u: NULL");
+    const size_t es = p->o.precision == RT_F64 ? 8 : 4;
+    const size_t n = (size_t)p->n_origins * (size_t)p->set->R * (size_t)p->a.F;
+    if (n > 0) RT_HIP(hipMemcpyAsync(u, p->u_buf, es * n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return RT_OK;
+}
+
 extern "C" rt_status rt_plan_destroy(rt_plan* p) {
     if (p) plan_free(p);
     return RT_OK;

@@ -439,12 +439,15 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
 // 2 log S, 3/4 neighbour mean of log chi / log S, 5 neighbour standard
 // deviation of log chi, 6/7 the eq. 6 indicator max_n |(f_p - f_n)/(f_p + f_n)|
 // of chi and S, 8 log L_p with L_p the mean neighbour distance (eq. 8),
-// 9 log(chi L_p), 10 x_f / 5, 11 log(number of neighbours), 12..15 zero.
+// 9 log(chi L_p), 10 x_f / 5, 11 log(number of neighbours); 12, 13, 14 the
+// max, min and standard deviation over the R coarse pairs of log(u_r / J1)
+// when u [n_points][R][F] is given (else zero); 15 zero.
 __global__ void k_features(const double* __restrict__ pos, const int64_t* __restrict__ off,
                            const int32_t* __restrict__ idx, const float* __restrict__ chi,
                            const float* __restrict__ eta, int64_t ld, int64_t F, const float* __restrict__ fx,
-                           const float* __restrict__ J1, const int32_t* __restrict__ points, int64_t n_points,
-                           int64_t P, float* __restrict__ feat, int32_t* __restrict__ err) {
+                           const float* __restrict__ J1, const float* __restrict__ u, int64_t R,
+                           const int32_t* __restrict__ points, int64_t n_points, int64_t P,
+                           float* __restrict__ feat, int32_t* __restrict__ err) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n_points * F) return;
     const int64_t k = i / F;
@@ -491,7 +494,29 @@ __global__ void k_features(const double* __restrict__ pos, const int64_t* __rest
     o[9] = logf(cp * Lp);
     o[10] = fx[f] / 5.f;
     o[11] = logf(nd);
-    o[12] = o[13] = o[14] = o[15] = 0.f;
+    float amax = 0.f, amin = 0.f, asd = 0.f;
+    if (u) {
+        const float lj = logf(J1[k * F + f]);
+        float s1 = 0.f;
+        amax = -INFINITY;
+        amin = INFINITY;
+        for (int64_t r = 0; r < R; ++r) {
+            const float a = logf(fmaxf(u[(k * R + r) * F + f], 1e-30f)) - lj;
+            amax = fmaxf(amax, a);
+            amin = fminf(amin, a);
+            s1 += a;
+        }
+        const float ma = s1 / (float)R;
+        for (int64_t r = 0; r < R; ++r) {
+            const float d = logf(fmaxf(u[(k * R + r) * F + f], 1e-30f)) - lj - ma;
+            asd += d * d;
+        }
+        asd = sqrtf(asd / (float)R);
+    }
+    o[12] = amax;
+    o[13] = amin;
+    o[14] = asd;
+    o[15] = 0.f;
 }
 
 // Column sums and sums of squares of feat[n][16]: block b accumulates rows
@@ -757,14 +782,14 @@ extern "C" rt_status rt_mlp_adam_step(rt_mlp* h, float lr, float b1, float b2, f
 }
 
 extern "C" rt_status rt_closure_features(const rt_model* m, const float* chi, const float* eta, int64_t ld, int64_t F,
-                                         const float* freq_x, const float* J1, const int32_t* points,
-                                         int64_t n_points, float* feat, void* stream) {
+                                         const float* freq_x, const float* J1, const float* u, int64_t R,
+                                         const int32_t* points, int64_t n_points, float* feat, void* stream) {
     if (!m || !chi || !eta || !freq_x || !J1 || (n_points > 0 && !feat) || F <= 0 || ld < F || n_points < 0 ||
-        n_points * F > MAX_SAMPLES || (!points && n_points > m->P))
+        n_points * F > MAX_SAMPLES || (!points && n_points > m->P) || (u && R <= 0))
         return fail(RT_ERR_ARG, "rt_closure_features: bad arguments");
     if (n_points == 0) return RT_OK;
     hipLaunchKernelGGL(k_features, dim3(nb(n_points * F, 256)), dim3(256), 0, (hipStream_t)stream, m->pos, m->off,
-                       m->idx, chi, eta, ld, F, freq_x, J1, points, n_points, m->P, feat, error_word());
+                       m->idx, chi, eta, ld, F, freq_x, J1, u, R, points, n_points, m->P, feat, error_word());
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -194,22 +194,25 @@ def test_training_reduces_error(rt):
     assert e1 < 0.1 * T.var() and e1 < 0.2 * e0
 
 
-@pytest.mark.parametrize("subset", [False, True])
-def test_features(rt, orc, subset):
+@pytest.mark.parametrize("subset,with_u", [(False, False), (True, False), (False, True), (True, True)])
+def test_features(rt, orc, subset, with_u):
     m = synth.tiny_model(21, P=200, F=8)
     chi32, eta32 = m.chi.astype(np.float32), m.eta.astype(np.float32)
     m.chi, m.eta = chi32.astype(np.float64), eta32.astype(np.float64)
     rng = np.random.default_rng(13)
     J1 = rng.uniform(0.05, 2.0, (m.P, m.F)).astype(np.float32)
+    u = rng.uniform(0.05, 2.0, (m.P, 6, m.F)).astype(np.float32) if with_u else None
     x = m.freq.x().astype(np.float32)
-    e = oc.features(m, J1.astype(np.float64), x.astype(np.float64)).reshape(m.P, m.F, 16)
+    e = oc.features(m, J1.astype(np.float64), x.astype(np.float64),
+                    None if u is None else u.astype(np.float64)).reshape(m.P, m.F, 16)
     model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
     if subset:
         pts = rng.permutation(m.P)[:77].astype(np.int32)
-        got = rt.closure_features(model, _t(chi32), _t(eta32), _t(x), _t(J1[pts]), points=_t(pts))
+        got = rt.closure_features(model, _t(chi32), _t(eta32), _t(x), _t(J1[pts]),
+                                  u=None if u is None else _t(u[pts]), points=_t(pts))
         e = e[pts]
     else:
-        got = rt.closure_features(model, _t(chi32), _t(eta32), _t(x), _t(J1))
+        got = rt.closure_features(model, _t(chi32), _t(eta32), _t(x), _t(J1), u=None if u is None else _t(u))
     got = got.cpu().numpy().reshape(e.shape)
     assert np.allclose(got, e, rtol=1e-5, atol=5e-5), float(np.max(np.abs(got - e)))
     rt.sync_status()

@@ -1,0 +1,88 @@
+"""The learned closure end to end on small winds: what the trained network gains
+over the coarse solve alone, that its predicted deviation ranks its errors, and
+the fallback rule's two limits.
+
+Training and test models use different seeds.  The plain nside-8 solve is the
+judge.  Bound 0 (every point falls back) must reproduce the plain solve bit for
+bit; an infinite bound must leave every point to the network.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+P = 12000
+
+
+@pytest.fixture(scope="module")
+def trained(rt):
+    import torch
+    from paper_2011_14998_amd import closure as cl
+    ds1, ds8 = rt.DirSet.uniform(1), rt.DirSet.uniform(8)
+    labs = []
+    for seed in (500, 501):
+        dm = cl.DeviceModel.from_synth(synth.wind_model(seed=seed, P=P))
+        labs.append(cl.label(dm, ds1, ds8))
+    X, T, norm = cl.dataset(labs)
+    net = cl.train(X, T, norm, steps=1500, batch=4096, lr=2e-3, seed=1, log_every=500, verbose=True)
+    test = cl.label(cl.DeviceModel.from_synth(synth.wind_model(seed=510, P=P)), ds1, ds8)
+    torch.cuda.synchronize()
+    return cl, net, test, ds8
+
+
+def test_closure_gain_over_coarse(trained):
+    cl, net, test, ds8 = trained
+    r = cl.evaluate(net, test, ds8, flag_fractions=[0.0])
+    c = r["closure"][0]
+    base = r["coarse_alone"]["median"]
+    print(f"median rel err: coarse alone {base:.3e}, closure {c['median']:.3e}")
+    assert c["n_flagged"] == 0
+    assert c["median"] < 0.85 * base
+    assert c["p99"] < r["coarse_alone"]["p99"]
+
+
+def test_predicted_deviation_ranks_errors(trained):
+    """Points the network is least sure of carry larger errors than those it is surest of,
+    which is what makes the fallback worth its cost."""
+    cl, net, test, ds8 = trained
+    sd = cl.predicted_sd(net, test.dm, test.coarse)
+    res = cl.infer(net, test.dm, test.coarse, ds8, math.inf)
+    e = np.median(np.abs(res.J.double().cpu().numpy() / test.fine.J.double().cpu().numpy() - 1.0), axis=1)
+    lo, hi = np.quantile(sd, [0.25, 0.75])
+    e_lo, e_hi = np.median(e[sd <= lo]), np.median(e[sd >= hi])
+    print(f"median error: surest quarter {e_lo:.3e}, least sure quarter {e_hi:.3e}")
+    assert e_lo < 0.7 * e_hi
+
+
+def test_fallback_everywhere_is_the_plain_solve(trained):
+    cl, net, test, ds8 = trained
+    res = cl.infer(net, test.dm, test.coarse, ds8, -math.inf)
+    assert res.n_flagged == test.dm.P
+    got = res.J.cpu().numpy()
+    want = test.fine.J.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_finite_bound_flags_the_predicted_worst(trained):
+    """Points flagged at a bound are exactly those whose predicted deviation exceeds it,
+    and every unflagged point keeps the network's value."""
+    cl, net, test, ds8 = trained
+    rt = cl.rt
+    X = rt.closure_normalize(cl.features(test.dm, test.coarse.J, test.coarse.u), net.norm.mean, net.norm.inv_std)
+    Y = net.mlp.forward(X).cpu().numpy().reshape(test.dm.P, test.dm.F, 2)
+    sd = np.exp(0.5 * Y[:, :, 1].astype(np.float64)).max(1)
+    b = float(np.quantile(sd, 0.8))
+    res = cl.infer(net, test.dm, test.coarse, ds8, math.log(b))
+    mask = cl.flagged_mask(res.flagged, res.n_flagged, test.dm.P)
+    # the kernel compares 0.5 s > log b in FP32; away from the boundary both agree
+    clear = np.abs(np.log(sd) - math.log(b)) > 1e-5
+    assert np.array_equal(mask[clear], (sd > b)[clear])
+    J = res.J.cpu().numpy()
+    J8 = test.fine.J.cpu().numpy()
+    J1 = test.coarse.J.cpu().numpy()
+    assert np.array_equal(J[mask], J8[mask])
+    assert np.allclose(J[~mask], J1[~mask] * np.exp(Y[~mask][:, :, 0].astype(np.float64)), rtol=2e-6)

@@ -89,6 +89,14 @@ def test_features_definitions():
     assert np.isclose(X[p, f, 5], np.std([np.log(m.chi[n, f]) for n in nb]))
     assert np.isclose(X[p, f, 4], np.mean([np.log(S[n, f]) for n in nb]))
     assert np.isclose(X[p, f, 10], x[f] / 5) and np.all(X[:, :, 12:] == 0)
+    # coarse per-pair intensities: an isotropic field has no spread; one bright pair of six
+    u = np.repeat(J1[:, None, :], 6, axis=1)
+    Xi = oc.features(m, J1, x, u).reshape(m.P, m.F, 16)
+    assert np.allclose(Xi[:, :, 12:15], 0.0, atol=1e-15)
+    u[p, 2, f] = 7.0 * J1[p, f]
+    Xa = oc.features(m, J1, x, u).reshape(m.P, m.F, 16)
+    assert np.isclose(Xa[p, f, 12], np.log(7.0)) and np.isclose(Xa[p, f, 13], 0.0)
+    assert np.isclose(Xa[p, f, 14], np.log(7.0) * np.sqrt(5.0) / 6.0)   # one of six at log 7
     # a uniform medium has no gradients
     m.chi[:] = 2.0
     m.eta[:] = 3.0
