@@ -64,15 +64,22 @@ constexpr int64_t WB2 = 0;                 // [256][256]
 constexpr int64_t WB3 = WB2 + HW * HW;
 constexpr int64_t NWB = WB3 + HW * HW;
 
-__host__ __device__ inline uint16_t f2bf(float x) {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (the hardware conversion)
+__device__ inline uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ inline uint32_t f2bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
-__host__ __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
-__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+__device__ inline float bf_lo(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
+__device__ inline float bf_hi(uint32_t v) { return __builtin_bit_cast(float, v & 0xFFFF0000u); }
+// logistic function with the hardware reciprocal; silu(z) = z sigma(z)
+__device__ inline float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigm(z); }
 __device__ inline float dsilu(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -114,56 +121,65 @@ __global__ void k_publish(const float* __restrict__ w, uint16_t* __restrict__ wt
 
 // ---------------------------------------------------------------- forward
 
-// out[64][256] = silu(bf16(in[64][K] * W + b)), W given as Wt[256][K] (bf16).
-// Wave w owns columns [64w, 64w+64): 4 row tiles x 4 column tiles.
-__device__ inline void fwd_layer(const uint16_t* in, int ldin, int K, const uint16_t* __restrict__ Wt,
-                                 const float* __restrict__ bias, uint16_t* out, uint16_t* __restrict__ zout,
-                                 int64_t row0, int nvalid) {
+// out[m][n] = bf16(silu(z)), z = bf16(sum_k in[m][k] W[k][n] + b[n]) for the
+// 16*MTW samples m of the tile, W given as Wt[256][K].  The product is formed
+// transposed (Z^T = Wt in^T: weights as the A operand, samples as B) so that a
+// lane's four accumulators are four consecutive n of one sample and go out as
+// one 8-byte store.  Wave w owns n in [64w, 64w+64).
+template <int MTW, int K, int ldin, bool KEEP>
+__device__ __attribute__((always_inline)) inline void fwd_layer(const uint16_t* in, const uint16_t* __restrict__ Wt,
+                                                                const float* __restrict__ bias, uint16_t* out,
+                                                                uint16_t* __restrict__ zout, int64_t row0,
+                                                                int nvalid) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
-    v4f32 acc[4][4];
+    v4f32 acc[4][MTW];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < MTW; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 16) {
-        v4i16 a[4], b[4];
+        v4i16 a[4], b[MTW];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = ld4(in + (mt * 16 + r) * ldin + k0 + 4 * g);
+        for (int nt = 0; nt < 4; ++nt) a[nt] = ld4(Wt + (int64_t)(64 * w + 16 * nt + r) * K + k0 + 4 * g);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = ld4(Wt + (int64_t)(64 * w + 16 * nt + r) * K + k0 + 4 * g);
+        for (int mt = 0; mt < MTW; ++mt) b[mt] = ld4(in + (mt * 16 + r) * ldin + k0 + 4 * g);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+            for (int mt = 0; mt < MTW; ++mt) acc[nt][mt] = mfma(a[nt], b[mt], acc[nt][mt]);
     }
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n0 = 64 * w + 16 * nt + 4 * g;
+        const float4 bb = *(const float4*)(bias + n0);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int col = 64 * w + 16 * nt + r;
-            const float bb = bias[col];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = mt * 16 + 4 * g + i;
-                const uint16_t zb = f2bf(acc[mt][nt][i] + bb);
-                if (zout && row < nvalid) zout[(row0 + row) * HW + col] = zb;
-                out[row * LDH + col] = f2bf(silu(bf2f(zb)));
-            }
+        for (int mt = 0; mt < MTW; ++mt) {
+            const int m = mt * 16 + r;
+            const uint32_t z01 = f2bf2(acc[nt][mt][0] + bb.x, acc[nt][mt][1] + bb.y);
+            const uint32_t z23 = f2bf2(acc[nt][mt][2] + bb.z, acc[nt][mt][3] + bb.w);
+            const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
+            const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
+            *(uint2*)(out + m * LDH + n0) = make_uint2(h01, h23);
+            if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
         }
+    }
 }
 
-template <bool KEEP>
-__global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ wt, const float* __restrict__ w,
-                                                  const uint16_t* __restrict__ X, const int32_t* __restrict__ rows,
-                                                  int64_t n, float* __restrict__ Y, uint16_t* __restrict__ Z) {
-    __shared__ __attribute__((aligned(16))) uint16_t sx[MT * LDX];
-    __shared__ __attribute__((aligned(16))) uint16_t sa[MT * LDH];
-    __shared__ __attribute__((aligned(16))) uint16_t sb[MT * LDH];
-    const int64_t row0 = (int64_t)blockIdx.x * MT;
-    const int nvalid = (int)(n - row0 < MT ? n - row0 : MT);
-    {   // 64 x 16 inputs: thread t loads 4 of row t/4
-        const int t = threadIdx.x, m = t >> 2, q = t & 3;
+// Forward over tiles of 16*MTW samples (rows[i] selects the input row of
+// sample i when given); KEEP stores the BF16 pre-activations Z[3][n][256].
+template <bool KEEP, int MTW>
+__global__ __launch_bounds__(256, MTW == 4 ? 2 : 1) void k_mlp_fwd(
+    const uint16_t* __restrict__ wt, const float* __restrict__ w, const uint16_t* __restrict__ X,
+    const int32_t* __restrict__ rows, int64_t n, float* __restrict__ Y, uint16_t* __restrict__ Z) {
+    constexpr int TS = 16 * MTW;
+    __shared__ __attribute__((aligned(16))) uint16_t sx[TS * LDX];
+    __shared__ __attribute__((aligned(16))) uint16_t sa[TS * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[TS * LDH];
+    const int64_t row0 = (int64_t)blockIdx.x * TS;
+    const int nvalid = (int)(n - row0 < TS ? n - row0 : TS);
+    for (int t = threadIdx.x; t < TS * 4; t += 256) {  // TS x 16 inputs, 4 per thread
+        const int m = t >> 2, q = t & 3;
         v4i16 v = (v4i16){0, 0, 0, 0};
         if (m < nvalid) {
             const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
@@ -175,24 +191,25 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ wt
     uint16_t* Z1 = KEEP ? Z : nullptr;
     uint16_t* Z2 = KEEP ? Z + n * HW : nullptr;
     uint16_t* Z3 = KEEP ? Z + 2 * n * HW : nullptr;
-    fwd_layer(sx, LDX, DIN, wt + WT1, w + OFF_B1, sa, Z1, row0, nvalid);
+    fwd_layer<MTW, DIN, LDX, KEEP>(sx, wt + WT1, w + OFF_B1, sa, Z1, row0, nvalid);
     __syncthreads();
-    fwd_layer(sa, LDH, HW, wt + WT2, w + OFF_B2, sb, Z2, row0, nvalid);
+    fwd_layer<MTW, HW, LDH, KEEP>(sa, wt + WT2, w + OFF_B2, sb, Z2, row0, nvalid);
     __syncthreads();
-    fwd_layer(sb, LDH, HW, wt + WT3, w + OFF_B3, sa, Z3, row0, nvalid);
+    fwd_layer<MTW, HW, LDH, KEEP>(sb, wt + WT3, w + OFF_B3, sa, Z3, row0, nvalid);
     __syncthreads();
-    // head: wave w takes rows [16w, 16w+16); columns 0..15 of W4t, 0 and 1 used
+    // head, transposed as the hidden layers: wave w takes the 16-sample groups
+    // w, w+4, ...; the A operand is W4t (rows 0 and 1 used), so lanes with
+    // g = 0 hold y[m][0..1]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
-    v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < HW; k0 += 16)
-        acc = mfma(ld4(sa + (16 * wv + r) * LDH + k0 + 4 * g), ld4(wt + WT4 + (int64_t)r * HW + k0 + 4 * g), acc);
-    if (r < DOUT) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * wv + 4 * g + i;
-            if (row < nvalid) Y[(row0 + row) * DOUT + r] = acc[i] + w[OFF_B4 + r];
-        }
+    for (int grp = wv; grp < MTW; grp += 4) {
+        v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < HW; k0 += 16)
+            acc = mfma(ld4(wt + WT4 + (int64_t)r * HW + k0 + 4 * g), ld4(sa + (16 * grp + r) * LDH + k0 + 4 * g),
+                       acc);
+        const int m = 16 * grp + r;
+        if (g == 0 && m < nvalid)
+            *(float2*)(Y + (row0 + m) * DOUT) = make_float2(acc[0] + w[OFF_B4], acc[1] + w[OFF_B4 + 1]);
     }
 }
 
@@ -200,7 +217,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ wt
 
 // part[wofs + j*Ncols + n] = sum over the 64 samples of H[m][j] dZ[m][n]:
 // wave w takes rows j in [64w, 64w+64), in column strips of 64.
-__device__ inline void grad_HtdZ(const uint16_t* H, int ldh, const uint16_t* dZ, float* __restrict__ part,
+__device__ __attribute__((always_inline)) inline void grad_HtdZ(const uint16_t* H, int ldh, const uint16_t* dZ, float* __restrict__ part,
                                  int64_t wofs, int Ncols) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
@@ -242,7 +259,7 @@ __device__ inline void grad_HtdZ(const uint16_t* H, int ldh, const uint16_t* dZ,
 
 // dH[64][256] = dZ[64][256] * W^T (W as [K][N] row-major = B operand [n][k]);
 // then dZ_prev = bf16(dH * silu'(z_prev)) into out, rows >= nvalid zero.
-__device__ inline void bwd_dH(const uint16_t* dZ, const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ zprev,
+__device__ __attribute__((always_inline)) inline void bwd_dH(const uint16_t* dZ, const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ zprev,
                               uint16_t* out, int64_t row0, int nvalid) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
@@ -734,12 +751,23 @@ extern "C" rt_status rt_mlp_forward(rt_mlp* h, const uint16_t* X, const int32_t*
         return fail(RT_ERR_ARG, "rt_mlp_forward: bad arguments");
     if (n == 0) return RT_OK;
     if (keep && (!ws || ws_bytes < ws_bytes_for(n))) return fail(RT_ERR_CAPACITY, "rt_mlp_forward: workspace too small");
-    const unsigned grid = nb(n, MT);
     hipStream_t s = (hipStream_t)stream;
-    if (keep)
-        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y, (uint16_t*)ws);
-    else
-        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y, nullptr);
+    // small batches (training) in 64-sample tiles to fill the chip, large ones in 128
+    if (n < (int64_t)num_cus() * 256) {
+        if (keep)
+            hipLaunchKernelGGL((k_mlp_fwd<true, 4>), dim3(nb(n, 64)), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y,
+                               (uint16_t*)ws);
+        else
+            hipLaunchKernelGGL((k_mlp_fwd<false, 4>), dim3(nb(n, 64)), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y,
+                               nullptr);
+    } else {
+        if (keep)
+            hipLaunchKernelGGL((k_mlp_fwd<true, 8>), dim3(nb(n, 128)), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y,
+                               (uint16_t*)ws);
+        else
+            hipLaunchKernelGGL((k_mlp_fwd<false, 8>), dim3(nb(n, 128)), dim3(256), 0, s, h->wt, h->w, X, rows, n, Y,
+                               nullptr);
+    }
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
