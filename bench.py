@@ -100,7 +100,7 @@ def summarize_counters(d, out_json, out_md):
     sq = glob.glob(os.path.join(d, "sq", "*counter_collection.csv"))
     if stats and out_md:
         rows = list(csv.DictReader(open(stats[0])))
-        B = "python3 bench.py --steps 5 --warmup 1 --cpu-sample 0"
+        B = "python3 bench.py --steps 5 --warmup 1 --cpu-sample 0 --no-autotune"
         with open(out_md, "w") as fo:
             fo.write("# Kernel times and HBM traffic: analytic wind, 50 000 points, nside 4, F = 64, FP32 sweep\n\n")
             fo.write("Session (run from /tmp with TMPDIR=/tmp; every command runs committed files only):\n\n")
@@ -115,6 +115,8 @@ def summarize_counters(d, out_json, out_md):
                      f"SQ_BUSY_CYCLES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE --output-format csv -d <dir>/sq -o run -- {B}\n")
             fo.write("    python3 bench.py --summarize-counters <dir> profiles/sweep_wind50k_nside4_counters.json "
                      "profiles/wind50k_nside4_kernel_stats.md\n\n")
+            fo.write("`--no-autotune` runs the plan options the autotuner picks for this workload (spatial schedule, "
+                     "load group 4, 8 lanes per ray), without its candidate runs in the trace.\n\n")
             fo.write("## rocprofv3 --stats (kernel trace)\n\n")
             fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
             for r in rows:
@@ -179,13 +181,14 @@ def main():
     ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial",
                     help="plan schedule when the autotuner is skipped")
     ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
-    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure"],
+    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure", "precision"],
                     default="wind",
                     help="wind: the headline 50k-point wind (default); octree: ~500k-leaf AMR-like cloud, 2x48 "
                          "frequencies; octree_reduced: the same field with ~50k leaves; sph_batch: 64 SPH-like "
                          "clouds as one disjoint union (size scaled by --batch-scale); closure: the learned "
                          "closure trained on winds of seeds 500-503 and judged on 510-511 against the plain "
-                         "nside-8 solve (--closure-points each)")
+                         "nside-8 solve (--closure-points each); precision: the FP32 sweep's error against the "
+                         "FP64 oracle, model by model")
     ap.add_argument("--batch-scale", type=float, default=0.25)
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner and use the library defaults")
     ap.add_argument("--nside", type=int, default=0, help="HEALPix nside (0 = the workload's own)")
@@ -235,6 +238,9 @@ def main():
     rt.load()
     if args.workload == "closure":
         run_closure(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
         return
 
     t_gen = time.perf_counter()
@@ -355,9 +361,63 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def run_precision(args):
+    """FP32 sweep (FP64 geometry, FP64 rows below the threshold) and FP64 sweep against the FP64
+    oracle fed the same FP32 table values, on seeded origin samples of each model; one JSON line."""
+    import torch
+
+    import oracle
+    import paper_2011_14998_amd as rt
+    import synth
+
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    cases = [
+        ("homogeneous sphere, 1200 points, nside 1, F=31", lambda: synth.sphere_model(), 1, None),
+        ("analytic wind, 50000 points, nside 4, F=64", lambda: synth.wind_model(seed=2, P=50_000), 4, 1500),
+        ("AMR-octree-like cloud, ~50000 leaves, nside 4, 2x48 freqs",
+         lambda: synth.octree_model(seed=3, target=50_000), 4, 400),
+        ("SPH-like cloud (Plummer + spiral arm), 20000 particles, nside 2, F=64",
+         lambda: synth.sph_cloud_model(seed=400, P=20_000), 2, 1500),
+    ]
+    out = []
+    for name, make, nside, n_sample in cases:
+        m = make()
+        rng = np.random.default_rng(11)
+        org = (np.arange(m.P) if n_sample is None or n_sample >= m.P
+               else np.sort(rng.choice(m.P, n_sample, replace=False))).astype(np.int32)
+        c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+        _, dirs, w2 = oracle.dirset_uniform(nside)
+        t0 = time.perf_counter()
+        Jo = oracle.compute_J(m, dirs, w2, origins=org, chi=c64, eta=e64, nthreads=threads)
+        t_or = time.perf_counter() - t0
+        model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
+        ds = rt.DirSet.uniform(nside)
+        o_t = torch.as_tensor(org, device="cuda")
+        I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device="cuda")
+        rec = dict(model=name, points=m.P, origins=len(org), freqs=m.F, pairs=ds.R, oracle_s=t_or)
+        for prec, tab, dt in ((rt.RT_F32, (c32, e32), torch.float32), (rt.RT_F64, (c64, e64), torch.float64)):
+            chi = torch.as_tensor(tab[0], device="cuda")
+            eta = torch.as_tensor(tab[1], device="cuda")
+            J = torch.empty((len(org), m.F), dtype=dt, device="cuda")
+            plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, origins=o_t, precision=prec,
+                           schedule=rt.SCHED_SPATIAL)
+            plan.run()
+            rt.sync_status()
+            e = np.abs(J.double().cpu().numpy() - Jo) / np.abs(Jo)
+            key = "fp32" if prec == rt.RT_F32 else "fp64"
+            rec[key] = dict(max_rel=float(e.max()), median_rel=float(np.median(e)),
+                            p99_rel=float(np.quantile(e, 0.99)))
+            del plan
+        _log(f"{name}: fp32 max {rec['fp32']['max_rel']:.2e}, fp64 max {rec['fp64']['max_rel']:.2e}")
+        out.append(rec)
+    print(json.dumps({"metric": "relative error of J against the FP64 oracle, per model", "per_model": out,
+                      "fp64_rows_below_dtau": args.fp64_below}), flush=True)
+
+
 def _gen_wind(seed_P):
     import synth
     seed, P = seed_P
+    _log(f"generating wind seed {seed} ({P} points) ...")
     t0 = time.perf_counter()
     m = synth.wind_model(seed=seed, P=P)
     return m, time.perf_counter() - t0

@@ -356,6 +356,14 @@ rt_status rt_closure_targets(const float* J1, const float* J_fine, int64_t n, fl
 rt_status rt_closure_merge(const float* J_fine, const int32_t* flagged, int64_t n_flagged, int64_t F,
                            int64_t n_points, float* J, void* stream);
 
+/* Spatial order of an origin list (device int32 [n], or NULL for 0..n-1):
+ * order (host int32 [n]) receives the list positions sorted by the Morton code
+ * of the origins' positions on a 2^21 grid over their bounding box.  Splitting
+ * a large origin list into chunks along this order keeps each chunk's rays
+ * in one region of the model.  Synchronises (reads the positions back). */
+rt_status rt_spatial_order(const rt_model* model, const int32_t* origins, int64_t n_origins, int32_t* order,
+                           void* stream);
+
 /* Synchronise `stream` and return the error latched by kernels since the last
  * call (RT_ERR_CAPACITY; RT_ERR_NONFINITE; RT_ERR_ARG for an origin id outside
  * 0 .. P-1, whose rays are then empty and whose J row is undefined), then

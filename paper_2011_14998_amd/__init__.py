@@ -28,6 +28,7 @@ from .binding import (  # noqa: F401
     load,
     mlp_nll,
     solve,
+    spatial_order,
     sync_status,
     trace,
     validate_host,

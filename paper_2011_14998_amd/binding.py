@@ -81,6 +81,7 @@ _SIGS = {
     "rt_mlp_adam_step": (_i32, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rt_plan_copy_u": (_i32, [_vp, _vp, _vp]),
+    "rt_spatial_order": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "rt_closure_feature_stats": (_i32, [_vp, _i64, _vp, _vp, _vp]),
     "rt_closure_normalize": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "rt_closure_apply": (_i32, [_vp, _vp, _i64, _i64, C.c_float, _vp, _vp, _vp, _vp]),
@@ -240,6 +241,19 @@ def validate_host(pos, nbr_off, nbr_idx, chi=None, F=0, ld=0):
         cp = chi.ctypes.data
     _check(load().rt_validate_host(pos.ctypes.data, pos.shape[0], off.ctypes.data, idx.ctypes.data, idx.size,
                                    cp, dt, F, ld))
+
+
+def spatial_order(model: Model, origins=None, n_origins=None, stream=None) -> np.ndarray:
+    """Positions of the origin list in Morton order of the origins' coordinates (host int32)."""
+    torch = _torch()
+    if origins is not None:
+        origins = _dev(origins, torch.int32)
+        n_origins = origins.numel()
+    elif n_origins is None:
+        n_origins = model.P
+    out = np.empty(max(n_origins, 1), np.int32)
+    _check(load().rt_spatial_order(model._h, _ptr(origins), n_origins, out.ctypes.data, _stream(stream)))
+    return out[:n_origins]
 
 
 def sync_status(stream=None):

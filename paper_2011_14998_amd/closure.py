@@ -64,10 +64,13 @@ class SolveResult:
     u: object = None           # per-pair mean intensities [n][R][F] when asked for
 
 
-def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: float = 3.0e9, J=None,
-            schedule: int = rt.SCHED_SPATIAL, keep_u: bool = False, verbose: bool = False) -> SolveResult:
+def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: float = 1.0e9, J=None,
+            schedule: int = rt.SCHED_SPATIAL, keep_u: bool = False, spatial_chunks: bool = True,
+            padded_budget: int = 0, verbose: bool = False) -> SolveResult:
     """J [n][F] (f32) for the listed origins (device int32, or all points) by plans over origin chunks
-    sized to about max_entries ray-list entries each; keep_u also returns the per-pair u."""
+    of about max_entries ray-list entries each; keep_u also returns the per-pair u.  With
+    spatial_chunks the list is cut along the Morton order of the origins' positions, so each chunk
+    walks one region of the model, and the rows are scattered back to list order."""
     torch = _torch()
     n = dm.P if origins is None else int(origins.numel())
     if J is None:
@@ -76,14 +79,26 @@ def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: flo
     if n == 0:
         return SolveResult(J, 0.0, 0.0, 0, U)
     all_ids = origins if origins is not None else torch.arange(n, dtype=torch.int32, device="cuda")
+    perm = None
+    if spatial_chunks and n > 4096:
+        order = rt.spatial_order(dm.model, origins=all_ids)
+        ids_host = all_ids.cpu().numpy()[order]
+        all_ids = torch.as_tensor(ids_host, device="cuda")
+        perm = torch.as_tensor(order, device="cuda")
+        Jw = torch.empty_like(J)
+        Uw = torch.empty_like(U) if keep_u else None
+    else:
+        Jw, Uw = J, U
     per_origin = 2 * dirset.R * (dm.mean_len or 64.0)
     chunk = min(n, 2048) if dm.mean_len is None else max(1, int(max_entries // per_origin))
     ms, build_s, entries, c0 = 0.0, 0.0, 0, 0
+    first_estimate = dm.mean_len is None
     while c0 < n:
         c1 = min(n, c0 + chunk)
         t0 = time.time()
-        plan = rt.Plan(dm.model, dirset, dm.chi, dm.eta, dm.freq_len, dm.freq_dx, dm.I_bc, J[c0:c1],
-                       origins=all_ids[c0:c1], precision=rt.RT_F32, schedule=schedule)
+        plan = rt.Plan(dm.model, dirset, dm.chi, dm.eta, dm.freq_len, dm.freq_dx, dm.I_bc, Jw[c0:c1],
+                       origins=all_ids[c0:c1], precision=rt.RT_F32, schedule=schedule,
+                       padded_trace_budget=padded_budget)
         torch.cuda.synchronize()
         build_s += time.time() - t0
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -93,11 +108,11 @@ def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: flo
         e1.synchronize()
         ms += e0.elapsed_time(e1)
         if keep_u:
-            plan.copy_u(U[c0:c1])
+            plan.copy_u(Uw[c0:c1])
         tot = plan.info()["total"]
         entries += tot
-        if dm.mean_len is None:
-            dm.mean_len = max(1.0, tot / ((c1 - c0) * 2 * dirset.R))
+        if first_estimate:  # running mean ray length over the chunks walked so far
+            dm.mean_len = max(1.0, entries / (c1 * 2 * dirset.R))
             per_origin = 2 * dirset.R * dm.mean_len
         del plan
         if verbose:
@@ -105,6 +120,16 @@ def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: flo
                   f"{ms:.0f} ms", flush=True)
         c0 = c1
         chunk = max(1, int(max_entries // per_origin))
+    if perm is not None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rt.closure_merge(Jw, perm, n, J)
+        if keep_u:
+            rt.closure_merge(Uw.view(n, -1), perm, n, U.view(n, -1))
+        e1.record()
+        e1.synchronize()
+        ms += e0.elapsed_time(e1)
+        del Jw, Uw
     rt.sync_status()
     return SolveResult(J, ms, build_s, entries, U)
 

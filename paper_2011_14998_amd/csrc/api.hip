@@ -617,6 +617,16 @@ static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_
     return hipSuccess;
 }
 
+extern "C" rt_status rt_spatial_order(const rt_model* m, const int32_t* origins, int64_t n_origins, int32_t* order,
+                                      void* stream) {
+    if (!m || n_origins < 0 || (n_origins > 0 && !order)) return fail(RT_ERR_ARG, "rt_spatial_order: bad arguments");
+    if (n_origins == 0) return RT_OK;
+    std::vector<int32_t> ord;
+    RT_HIP(morton_order(m, origins, n_origins, (hipStream_t)stream, ord));
+    std::memcpy(order, ord.data(), sizeof(int32_t) * ord.size());
+    return RT_OK;
+}
+
 // Apply scheduling options to a plan whose lists and u buffer exist: build what
 // the schedule needs on first use (spatial origin order, bin workspace) and
 // re-capture the whole step as one graph on a private stream (the caller's

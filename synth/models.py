@@ -218,7 +218,7 @@ def _grf(n: int, rng: np.random.Generator, slope: float = -11.0 / 3.0) -> np.nda
     amp = K2 ** (slope / 4.0)
     amp[0, 0, 0] = 0.0
     wn = rng.normal(size=(n, n, n))
-    f = np.fft.irfftn(np.fft.rfftn(wn) * amp, s=(n, n, n))
+    f = np.fft.irfftn(np.fft.rfftn(wn) * amp, s=(n, n, n), axes=(0, 1, 2))
     f -= f.mean()
     f /= f.std()
     return f
