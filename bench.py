@@ -52,7 +52,7 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
-KERNEL_KEYS = {"sweep": ("k_solve_direct", "k_solve_persist"), "walk": ("k_trace<2",),
+KERNEL_KEYS = {"sweep": ("k_solve_direct", "k_solve_persist"), "walk": ("k_trace<1", "k_trace<2"),
                "compact": ("k_compact",), "reduce": ("k_reduce",)}
 
 
@@ -198,8 +198,9 @@ def main():
                     help="only run a plain device copy of BYTES bytes (for scaling HBM counters) and exit")
     ap.add_argument("--group", type=int, default=0, help="sweep load-group size (4 or 8; 0 = library default)")
     ap.add_argument("--trace-lanes", type=int, default=0, help="lanes per ray in the walk (4 or 8; 0 = default)")
-    ap.add_argument("--two-pass-trace", action="store_true",
-                    help="walk every ray twice (count, then write) instead of once into padded slots")
+    ap.add_argument("--walk", choices=["exact", "padded", "two-pass"], default="exact",
+                    help="plan walk: once into the creation-time slots (default), once into padded slots plus "
+                         "compaction, or count + write")
     ap.add_argument("--closure-points", type=int, default=2_000_000, help="points per closure model")
     ap.add_argument("--closure-train", type=int, default=4, help="closure training models (seeds 500..)")
     ap.add_argument("--closure-test", type=int, default=2, help="closure test models (seeds 510..)")
@@ -283,7 +284,8 @@ def main():
         _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   dtau_fp64_below=args.fp64_below, padded_trace_budget=-1 if args.two_pass_trace else 0,
+                   dtau_fp64_below=args.fp64_below,
+                   walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
                    **opts)
     total = plan.info()["total"]
 
@@ -334,7 +336,7 @@ def main():
         "config": {
             "workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep",
             "points": m.P, "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
-            "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "autotune": tuned,
+            "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "walk": args.walk, "autotune": tuned,
             "fp64_rows_below_dtau": args.fp64_below, "frequency_chunks_per_pair": nfc,
         },
         "roofline": {

@@ -140,7 +140,8 @@ rt_status rt_trace_count(const rt_model* model, const rt_dirset* set, const int3
 
 /* Writes ray_ids (int32) and ray_Z (float64) of every ray at the offsets from
  * rt_trace_count; `capacity` is the length of both arrays.  A ray that would
- * write past capacity is truncated and RT_ERR_CAPACITY is latched for
+ * write past its slot or past capacity is truncated, and a ray shorter than its
+ * slot leaves the rest unwritten; both latch RT_ERR_CAPACITY for
  * rt_sync_status().  Async. */
 rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int32_t* origins,
                          int64_t n_origins, const int64_t* ray_off, int32_t* ray_ids, double* ray_Z,
@@ -189,10 +190,16 @@ typedef struct {
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
     int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 4) */
     int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */
-    int64_t padded_trace_budget; /* plans only: bytes allowed for single-pass tracing into padded
-                                    per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB,
-                                    < 0 = always trace in two passes (count, then write) */
+    int64_t padded_trace_budget; /* plans, RT_WALK_PADDED: bytes allowed for single-pass tracing into
+                                    padded per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB;
+                                    beyond it, or < 0, the walk takes two passes (count, then write) */
+    int32_t walk;             /* plans: RT_WALK_EXACT (0): every run walks each ray once straight into
+                                 its slot of the lists sized by the count pass at creation; a ray whose
+                                 length then differs from its slot latches RT_ERR_CAPACITY.
+                                 RT_WALK_PADDED: once into padded slots, then scan and compaction.
+                                 RT_WALK_TWO_PASS: count, scan, write on every run. */
 } rt_solve_opts;
+enum { RT_WALK_EXACT = 0, RT_WALK_PADDED = 1, RT_WALK_TWO_PASS = 2 };
 
 /* Scratch needed by rt_solve (u per (origin, pair, frequency), bins). */
 rt_status rt_solve_workspace(const rt_dirset* set, int64_t n_origins, int64_t F, const rt_solve_opts* opts,
@@ -208,14 +215,15 @@ rt_status rt_solve(const rt_model* model, const rt_dirset* set, const int32_t* o
 
 /* ------------------------------------------------------------------ plans
  * A plan owns the ray-list buffers for a fixed (model, set, origins) and replays
- * the whole hot path -- trace, scan, list output, bin, sweep, reduce -- as one
+ * the whole hot path -- trace, (scan, list output), bin, sweep, reduce -- as one
  * HIP graph on the caller's stream.  Creation runs the count pass once to size
- * the lists (synchronises) and allocates; rt_plan_run allocates nothing.  When
- * the padded budget allows, each run walks every ray once into per-ray slots
- * sized by the longest ray found at creation and then compacts the slots into
- * the lists; otherwise it walks twice (count, then write).  A ray longer than
- * its slot (the model's positions changed after creation) latches
- * RT_ERR_CAPACITY. */
+ * the lists (synchronises) and allocates; rt_plan_run allocates nothing.  The
+ * walk of each run follows opts->walk: by default every ray is walked once and
+ * written straight into its slot (the lists' offsets come from the creation-time
+ * count); RT_WALK_PADDED walks once into per-ray slots sized by the longest ray
+ * and compacts them (when the padded budget allows); RT_WALK_TWO_PASS counts,
+ * scans and writes.  A ray that no longer fits its slot (the model's positions
+ * changed after creation) latches RT_ERR_CAPACITY. */
 typedef struct rt_plan rt_plan;
 rt_status rt_plan_create(const rt_model* model, const rt_dirset* set, const int32_t* origins,
                          int64_t n_origins, const void* chi, const void* eta, int32_t dtype, int64_t ld,
@@ -224,9 +232,10 @@ rt_status rt_plan_create(const rt_model* model, const rt_dirset* set, const int3
 /* Replay the plan (async).  use_graph = 0 launches the kernels one by one. */
 rt_status rt_plan_run(rt_plan* plan, int32_t use_graph, void* stream);
 /* Run the plan eagerly n_runs times on `stream` with HIP events between its
- * stages and return the mean time per stage in ms: stage_ms[6] = {walk (count or
- * padded), scan, list output (write walk or compaction), bin, sweep, reduce}
- * (bin is ~0 for RT_SCHED_DIRECT).  Synchronises. */
+ * stages and return the mean time per stage in ms: stage_ms[6] = {walk (exact
+ * write, padded or count), scan, list output (write walk or compaction), bin,
+ * sweep, reduce} (scan and list output are ~0 for RT_WALK_EXACT, bin for
+ * RT_SCHED_DIRECT).  Synchronises. */
 rt_status rt_plan_profile(rt_plan* plan, int32_t n_runs, double* stage_ms, void* stream);
 /* Total ray-list entries, and the plan's device ray lists (borrowed views). */
 rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_t** ray_off,

@@ -12,6 +12,9 @@ from .binding import (  # noqa: F401
     SCHED_BINNED,
     SCHED_DIRECT,
     SCHED_SPATIAL,
+    WALK_EXACT,
+    WALK_PADDED,
+    WALK_TWO_PASS,
     MLP,
     DirSet,
     Model,

@@ -15,6 +15,9 @@ RT_F64 = 2
 SCHED_DIRECT = 0
 SCHED_BINNED = 1
 SCHED_SPATIAL = 2
+WALK_EXACT = 0
+WALK_PADDED = 1
+WALK_TWO_PASS = 2
 MAX_FREQ_BLOCKS = 8
 
 _i32, _i64, _vp, _sz, _dbl = C.c_int32, C.c_int64, C.c_void_p, C.c_size_t, C.c_double
@@ -34,7 +37,7 @@ class FreqGridC(C.Structure):
 class SolveOptsC(C.Structure):
     _fields_ = [("precision", _i32), ("schedule", _i32), ("dtau_fp64_below", _dbl),
                 ("waves_per_cu", _i32), ("n_bins", _i32), ("group", _i32), ("trace_lanes", _i32),
-                ("padded_trace_budget", _i64)]
+                ("padded_trace_budget", _i64), ("walk", _i32)]
 
 
 # name -> (restype, argtypes)
@@ -294,9 +297,9 @@ def _grid(freq_len: Sequence[int], freq_dx: Sequence[float]):
 
 
 def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget=0, group=0,
-          trace_lanes=0):
+          trace_lanes=0, walk=0):
     return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group, trace_lanes,
-                      padded_trace_budget)
+                      padded_trace_budget, walk)
 
 
 def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
@@ -370,7 +373,8 @@ class Plan:
     def __init__(self, model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None,
                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT,
                  dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0,
-                 padded_trace_budget: int = 0, group: int = 0, trace_lanes: int = 0, stream=None):
+                 padded_trace_budget: int = 0, group: int = 0, trace_lanes: int = 0, walk: int = WALK_EXACT,
+                 stream=None):
         torch = _torch()
         dt = torch.float64 if precision == RT_F64 else torch.float32
         self.chi, self.eta, self.J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
@@ -383,7 +387,8 @@ class Plan:
         self.origins, self.n_origins = origins, n_origins
         self.model, self.dirset = model, dirset
         g, self._keep = _grid(freq_len, freq_dx)
-        o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes)
+        o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes,
+                  walk)
         h = _vp()
         _check(load().rt_plan_create(model._h, dirset._h, _ptr(origins), n_origins, _ptr(self.chi),
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),

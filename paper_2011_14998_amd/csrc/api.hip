@@ -334,6 +334,7 @@ static rt_solve_opts default_opts() {
     o.group = 0;
     o.trace_lanes = 0;
     o.padded_trace_budget = 0;
+    o.walk = RT_WALK_EXACT;
     return o;
 }
 
@@ -515,6 +516,7 @@ struct rt_plan {
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool exact = false;  // RT_WALK_EXACT: walk straight into the creation-time slots
 };
 
 // Stages: 0 count, 1 scan, 2 write, 3 bin (+ queue reset), 4 sweep, 5 reduce.
@@ -526,6 +528,13 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
     };
     const int per = p->set->n_origins > 0;
     mark(0);
+    if (p->exact) {  // one walk straight into the creation-time slots
+        if (e == hipSuccess)
+            e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->ray_off,
+                                   p->ids, p->Z, p->total, s, p->order, p->o.trace_lanes);
+        mark(1);
+        mark(2);
+    } else {
     if (e == hipSuccess) {
         if (p->pids)
             e = launch_trace_padded(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->lens, p->pids,
@@ -543,6 +552,7 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
         else
             e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->ray_off,
                                    p->ids, p->Z, p->total, s, p->order, p->o.trace_lanes);
+    }
     }
     mark(3);
     SolveLaunch a = p->a;
@@ -716,6 +726,8 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (st) return st;
     if (opts && (opts->schedule < RT_SCHED_DIRECT || opts->schedule > RT_SCHED_SPATIAL))
         return fail(RT_ERR_ARG, "rt_plan_create: bad schedule");
+    if (opts && (opts->walk < RT_WALK_EXACT || opts->walk > RT_WALK_TWO_PASS))
+        return fail(RT_ERR_ARG, "rt_plan_create: bad walk mode");
     hipStream_t s = (hipStream_t)stream;
     auto* p = new rt_plan();
     p->m = m;
@@ -735,9 +747,10 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMalloc((void**)&p->ids, sizeof(int32_t) * (size_t)std::max<int64_t>(p->total, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&p->Z, sizeof(double) * (size_t)std::max<int64_t>(p->total, 1));
+    p->exact = p->o.walk == RT_WALK_EXACT;
     // Longest ray: the padded single-pass walk is used when its slots fit the budget.
     int32_t longest = 0;
-    if (e == hipSuccess && p->n_rays > 0) {
+    if (e == hipSuccess && p->n_rays > 0 && p->o.walk == RT_WALK_PADDED) {
         std::vector<int32_t> hl((size_t)p->n_rays);
         e = hipMemcpyAsync(hl.data(), p->lens, sizeof(int32_t) * hl.size(), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -746,7 +759,8 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     const size_t pad_bytes = (size_t)p->n_rays * (size_t)std::max(longest, 1) * 12;
     const size_t budget = opts && opts->padded_trace_budget > 0 ? (size_t)opts->padded_trace_budget
                                                                : (size_t)32 << 30;
-    if (e == hipSuccess && p->n_rays > 0 && !(opts && opts->padded_trace_budget < 0) && pad_bytes <= budget) {
+    if (e == hipSuccess && p->n_rays > 0 && p->o.walk == RT_WALK_PADDED && !(opts && opts->padded_trace_budget < 0) &&
+        pad_bytes <= budget) {
         p->cap = std::max(longest, 1);
         e = hipMalloc((void**)&p->pids, sizeof(int32_t) * (size_t)p->n_rays * p->cap);
         if (e == hipSuccess) e = hipMalloc((void**)&p->pZ, sizeof(double) * (size_t)p->n_rays * p->cap);

@@ -227,6 +227,8 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
         Zc = b.Z;
     }
     if (MODE != TRACE_WRITE && sub == 0) lens[ray] = n;
+    // a ray shorter than its slot leaves entries unwritten: the offsets do not match this walk
+    if (MODE == TRACE_WRITE && sub == 0 && n < room) atomicOr(err, ERRBIT_CAPACITY);
     }
 }
 

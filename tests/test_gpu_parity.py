@@ -234,9 +234,11 @@ def test_binned_schedule_bitwise_equal_direct(rt, orc, wind, prec):
         assert np.array_equal(Jd, Jb)
 
 
-@pytest.mark.parametrize("schedule,padded,lanes,group", [(0, 0, 4, 8), (1, 0, 8, 4), (1, -1, 16, 8), (2, 0, 8, 4),
-                                                        (2, -1, 4, 4), (2, 0, 16, 8)])
-def test_plan_graph_replays(rt, orc, wind, schedule, padded, lanes, group):
+# walk 0: exact slots (default), 1: padded slots + compaction, 2: two passes
+@pytest.mark.parametrize("schedule,walk,padded,lanes,group", [(0, 0, 0, 4, 8), (1, 1, 0, 8, 4), (1, 2, 0, 16, 8),
+                                                             (2, 0, 0, 8, 4), (2, 1, -1, 4, 4), (2, 1, 0, 16, 8),
+                                                             (2, 2, 0, 8, 8)])
+def test_plan_graph_replays(rt, orc, wind, schedule, walk, padded, lanes, group):
     torch = _torch()
     origins = np.arange(0, wind.P, 50).astype(np.int32)
     model = _gpu_model(rt, wind)
@@ -248,7 +250,7 @@ def test_plan_graph_replays(rt, orc, wind, schedule, padded, lanes, group):
     J = torch.empty((len(origins), wind.F), dtype=torch.float32, device="cuda")
     plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=org,
                    precision=rt.RT_F32, schedule=schedule, padded_trace_budget=padded, trace_lanes=lanes,
-                   group=group)
+                   group=group, walk=walk)
     ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
                        precision=rt.RT_F32).cpu().numpy()
     plan.run(use_graph=False)
@@ -267,6 +269,30 @@ def test_plan_graph_replays(rt, orc, wind, schedule, padded, lanes, group):
     _assert_rays_equal((off, ids, Z), e)
     prof = plan.profile(2)
     assert prof["sweep"] > 0 and prof["walk"] > 0
+    rt.sync_status()
+
+
+def test_trace_write_flags_mismatched_offsets(rt, wind):
+    """Writing at offsets that do not match the walk (here: every slot one entry too long)
+    latches a capacity error instead of leaving the mismatch unnoticed."""
+    torch = _torch()
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(1)
+    org = _t(np.arange(0, 200, dtype=np.int32))
+    off, ids, Z = rt.trace(model, ds, origins=org)
+    rt.sync_status()
+    lens = torch.diff(off)
+    off2 = torch.zeros_like(off)
+    off2[1:] = torch.cumsum(lens + 1, 0)
+    tot = int(off2[-1])
+    ids2 = torch.empty(tot, dtype=torch.int32, device="cuda")
+    Z2 = torch.empty(tot, dtype=torch.float64, device="cuda")
+    rt.binding._check(rt.load().rt_trace_write(model._h, ds._h, org.data_ptr(), org.numel(), off2.data_ptr(),
+                                               ids2.data_ptr(), Z2.data_ptr(), tot, rt.binding._stream(None)))
+    with pytest.raises(rt.RtError) as ei:
+        rt.sync_status()
+    assert ei.value.code == -4
+    rt.sync_status()
 
 
 def test_empty_origin_list(rt):
