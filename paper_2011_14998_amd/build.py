@@ -17,7 +17,9 @@ SOURCES = ["healpix.cpp", "trace.hip", "solve.hip", "dirset.hip", "api.hip", "cl
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-    # IEEE arithmetic without contraction: bit-exact tracing and direction tables.
+    # IEEE arithmetic without contraction: bit-exact tracing and direction tables,
+    # and the same bits from every instance of a kernel (fused multiply-adds are
+    # written out where they are wanted)
     "-ffp-contract=off",
     # host direction tables call the C library's sin and cos, never a fused sincos
     "-fno-builtin-sin", "-fno-builtin-cos",

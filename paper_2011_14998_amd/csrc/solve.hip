@@ -117,6 +117,11 @@ __device__ inline double rcp64(double x) {
 }
 
 template <typename T>
+__device__ inline T fma_(T a, T b, T c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ inline float fma_<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
 __device__ inline T rcp(T x);
 template <>
 __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -142,8 +147,8 @@ __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
     } else {
         const T hb = (T)0.5 * b * (st.a + b);
         const T ba = b * st.ra;
-        st.F = hb + ba * (st.F * st.r1);
-        const T Zn = hb * S + ba * st.Z;
+        st.F = fma_<T>(ba, st.F * st.r1, hb);
+        const T Zn = fma_<T>(hb, S, ba * st.Z);
         st.r1 = rcp<T>((T)1 + st.F);
         st.Z = Zn * st.r1;
     }
@@ -166,8 +171,8 @@ __device__ inline void row_coef64(SweepState<float>& st, bool far_end, float b, 
         const double ra = __builtin_fma((double)st.ra, __builtin_fma(-ad, (double)st.ra, 1.0), (double)st.ra);
         const float hb = (float)(0.5 * bd * (ad + bd));
         const float ba = (float)(bd * ra);
-        st.F = hb + ba * (st.F * st.r1);
-        const float Zn = hb * S + ba * st.Z;
+        st.F = __builtin_fmaf(ba, st.F * st.r1, hb);
+        const float Zn = __builtin_fmaf(hb, S, ba * st.Z);
         st.r1 = __builtin_amdgcn_rcpf(1.0f + st.F);
         st.Z = Zn * st.r1;
     }
@@ -281,6 +286,10 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
+    // the lane's own frequency and its block's first and last, in bytes
+    const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
+    const int lo_bytes = lf.fb * (int)sizeof(T);
+    const int hi_bytes = (lf.fb + lf.L - 1) * (int)sizeof(T);
     for (int hi = n - 1; hi >= 0; hi -= 64) {
         const int cnt = hi + 1 < 64 ? hi + 1 : 64;
         // staging: lane j holds entry hi-j
@@ -295,7 +304,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
             row_l = (int64_t)q_l * c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
-            ds_l = (T)(z - zi);  // difference of FP64 projections, rounded once
+            ds_l = (T)0.5 * (T)(z - zi);  // half the difference of FP64 projections, rounded once
             if (MOVING) {
                 const float* vq = c.vel + 3 * (int64_t)q_l;
                 const double dvx = (double)vq[0] - (double)c.vox;
@@ -331,10 +340,10 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                             k = (int)kf;
                             t = (T)(delta - kf);
                         }
-                        const int ia = min(max(lf.fl - k, 0), lf.L - 1);
-                        const int ib = min(max(lf.fl - k - 1, 0), lf.L - 1);
-                        const uint32_t oa = (uint32_t)(lf.fb + ia) * (uint32_t)sizeof(T);
-                        const uint32_t ob = (uint32_t)(lf.fb + ib) * (uint32_t)sizeof(T);
+                        // byte offsets of rows fl - k and fl - k - 1, clamped to the block
+                        const int ks = k * (int)sizeof(T);
+                        const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
+                        const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
                         ca[g] = *(const T*)(cr + oa);
                         cb[g] = *(const T*)(cr + ob);
                         ea[g] = *(const T*)(er + oa);
@@ -351,15 +360,15 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                 if (j + g < cnt) {
                     T cc, et;
                     if (MOVING) {
-                        cc = ca[g] + tt[g] * (cb[g] - ca[g]);
-                        et = ea[g] + tt[g] * (eb[g] - ea[g]);
+                        cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
+                        et = fma_<T>(tt[g], eb[g] - ea[g], ea[g]);
                     } else {
                         cc = ca[g];
                         et = ea[g];
                     }
                     const T S = et * rcp<T>(cc);
                     if (done > 0) {
-                        const T dt = ((T)0.5 * (c_prev + cc)) * ds_prev;
+                        const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
                         row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
                     }
                     c_prev = cc;
@@ -371,7 +380,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
         }
     }
     if (n > 0) {
-        const T dt = ((T)0.5 * (c_prev + chi_o)) * ds_prev;
+        const T dt = (c_prev + chi_o) * ds_prev;
         row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
     }
 }
