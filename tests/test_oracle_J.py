@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import synth
+from exact_feautrier import exact_u
 
 
 def test_sphere_centre_closed_form(orc):
@@ -145,3 +146,61 @@ def test_want_u_consistent(orc):
     for r in range(len(w2)):
         Ju += w2[r] * u[:, r, :]
     assert np.array_equal(J, Ju)
+
+
+def _exact_line_u(trace_ray, m, o, d, f, I):
+    """u at origin o for pair direction d and frequency f, built independently:
+    trace both rays, assemble the line, shift and interpolate every point's
+    tables in the origin's frame along +d (exact rationals), trapezoid optical
+    depths, exact rational Feautrier solve."""
+    from fractions import Fraction as Fr
+    import math
+    ids_p, Z_p = trace_ray(m, o, d)
+    ids_m, Z_m = trace_ray(m, o, -d)
+    q = list(ids_m[::-1]) + [o] + list(ids_p)
+    s = [-Fr(float(z)) for z in Z_m[::-1]] + [Fr(0)] + [Fr(float(z)) for z in Z_p]
+    mi = len(ids_m)
+    # frequency f sits in block b at index j
+    starts = np.concatenate([[0], np.cumsum(m.freq.len)])
+    b = int(np.searchsorted(starts, f, side="right") - 1)
+    fb, L, dx = int(starts[b]), int(m.freq.len[b]), Fr(float(m.freq.dx[b]))
+    j = f - fb
+    vo = [Fr(float(v)) for v in m.vel[o]]
+    dd = [Fr(float(c)) for c in d]
+    chi, S = [], []
+    for p in q:
+        dv = [Fr(float(v)) - w for v, w in zip(m.vel[p], vo)]
+        delta = sum(a * c for a, c in zip(dd, dv)) / dx
+        k = math.floor(delta)
+        t = delta - k
+        ia = min(max(j - k, 0), L - 1)
+        ib = min(max(j - k - 1, 0), L - 1)
+        c = (1 - t) * Fr(float(m.chi[p, fb + ia])) + t * Fr(float(m.chi[p, fb + ib]))
+        e = (1 - t) * Fr(float(m.eta[p, fb + ia])) + t * Fr(float(m.eta[p, fb + ib]))
+        chi.append(c)
+        S.append(e / c)
+    dtau = [(chi[i] + chi[i + 1]) / 2 * (s[i + 1] - s[i]) for i in range(len(q) - 1)]
+    return exact_u(dtau, S, mi, Fr(float(I)))
+
+
+def test_general_doppler_shift_exact(orc):
+    """Moving medium with non-integer shifts in two blocks of different widths: the
+    oracle's per-pair u against an independent exact-rational construction."""
+    m = synth.tiny_model(31, P=45, F=10, moving=True)
+    m.freq = synth.FreqGrid(np.array([6, 4], np.int32), np.array([-3.0, -1.0]), np.array([0.7, 0.45]))
+    rng = np.random.default_rng(8)
+    m.I_bc = rng.uniform(0.0, 0.4, m.F)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    origins = np.array([3, 17, 30], np.int32)
+    J, u = orc.compute_J(m, dirs, w2, origins=origins, want_u=True)
+    checked = 0
+    for oi, o in enumerate(origins):
+        for r in (0, 2, 5):
+            for f in (0, 4, 5, 6, 9):
+                ue = _exact_line_u(orc.trace_ray, m, int(o), dirs[r], f, m.I_bc[f])
+                assert abs(u[oi, r, f] - float(ue)) <= 1e-12 * abs(float(ue)), (o, r, f)
+                checked += 1
+    assert checked == 45
+    # the shifts are not all integers and not all zero: the interpolation is exercised
+    dv = m.vel[origins[0]] - m.vel
+    assert np.any(np.abs(dv @ dirs[0] / 0.7 - np.round(dv @ dirs[0] / 0.7)) > 0.1)
