@@ -553,6 +553,9 @@ typedef struct {
     int32_t* q;   double* s;    /* assembled line */
     double* dtau; double* S; double* chi; double* eta;
     int64_t* k; double* t;
+    int64_t* nsub;              /* optical-depth sub-steps per interval */
+    int64_t rcap;               /* line refined by optical-depth sub-steps */
+    double* rdtau; double* rS; double* rchi;
 } or_ws;
 
 static void ws_grow(or_ws* w, int64_t n) {
@@ -564,12 +567,75 @@ static void ws_grow(or_ws* w, int64_t n) {
     w->dtau = realloc(w->dtau, (2 * c + 1) * sizeof(double)); w->S = realloc(w->S, (2 * c + 1) * sizeof(double));
     w->chi = realloc(w->chi, (2 * c + 1) * sizeof(double)); w->eta = realloc(w->eta, (2 * c + 1) * sizeof(double));
     w->k = realloc(w->k, (2 * c + 1) * sizeof(int64_t)); w->t = realloc(w->t, (2 * c + 1) * sizeof(double));
+    w->nsub = realloc(w->nsub, (2 * c + 1) * sizeof(int64_t));
     w->cap = c;
 }
 
 static void ws_free(or_ws* w) {
     free(w->idm); free(w->Zm); free(w->idp); free(w->Zp); free(w->q); free(w->s);
-    free(w->dtau); free(w->S); free(w->chi); free(w->eta); free(w->k); free(w->t);
+    free(w->dtau); free(w->S); free(w->chi); free(w->eta); free(w->k); free(w->t); free(w->nsub);
+    free(w->rdtau); free(w->rS); free(w->rchi);
+}
+
+static void ws_grow_refined(or_ws* w, int64_t n) {
+    if (n <= w->rcap) return;
+    int64_t c = n * 2;
+    w->rdtau = realloc(w->rdtau, c * sizeof(double));
+    w->rS = realloc(w->rS, c * sizeof(double));
+    w->rchi = realloc(w->rchi, c * sizeof(double));
+    w->rcap = c;
+}
+
+/* Adaptive optical-depth increments (Section 2.1.2, eq. 2).  The interval
+ * between line points d and d+1 is split into
+ *     n_d = ceil(max(chi_d, chi_{d+1}) ds_d / dtau_max)
+ * equal parts (computed as (max * ds) * (1/dtau_max), the reciprocal rounded
+ * once; n_d clamped to 1 .. max_sub), and chi and eta are interpolated
+ * linearly on the sub-intervals: at w = i/n_d, chi = (1-w) chi_d + w chi_{d+1},
+ * eta likewise, S = eta/chi.  Every sub-interval gets the trapezoid
+ * dtau = (0.5 (chi_j + chi_{j+1})) (ds_d / n_d).  Writes the refined line into
+ * w->rdtau / w->rS and returns its length; *m_out receives the refined index of
+ * line point m.  dtau_max <= 0 leaves every interval whole. */
+static int64_t refine_line(or_ws* w, int64_t N, int64_t m, double dtau_max, int64_t max_sub, int64_t* m_out) {
+    const double rdt = dtau_max > 0.0 ? 1.0 / dtau_max : 0.0;
+    int64_t total = 1;
+    for (int64_t d = 0; d + 1 < N; ++d) {
+        int64_t n = 1;
+        if (dtau_max > 0.0) {
+            const double ds = w->s[d + 1] - w->s[d];
+            const double cm = w->chi[d] > w->chi[d + 1] ? w->chi[d] : w->chi[d + 1];
+            double c = ceil((cm * ds) * rdt);
+            if (c > (double)max_sub) c = (double)max_sub;
+            n = c < 1.0 ? 1 : (int64_t)c;
+        }
+        w->nsub[d] = n;
+        total += n;
+    }
+    ws_grow_refined(w, total);
+    int64_t j = 0;
+    for (int64_t d = 0; d < N; ++d) {
+        if (d == m) *m_out = j;
+        w->rS[j] = w->S[d];
+        w->rchi[j] = w->chi[d];
+        ++j;
+        if (d + 1 == N) break;
+        const int64_t n = w->nsub[d];
+        for (int64_t i = 1; i < n; ++i) {
+            const double wt = (double)i / (double)n;
+            const double c = (1.0 - wt) * w->chi[d] + wt * w->chi[d + 1];
+            const double e = (1.0 - wt) * w->eta[d] + wt * w->eta[d + 1];
+            w->rS[j] = e / c;
+            w->rchi[j] = c;
+            ++j;
+        }
+    }
+    j = 0;
+    for (int64_t d = 0; d + 1 < N; ++d) {
+        const int64_t n = w->nsub[d];
+        const double h = (w->s[d + 1] - w->s[d]) / (double)n;
+        for (int64_t i = 0; i < n; ++i, ++j) w->rdtau[j] = (0.5 * (w->rchi[j] + w->rchi[j + 1])) * h;
+    }
+    return total;
 }
 
 static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -589,12 +655,12 @@ static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : 
  *
  * dirs: [R][3] shared, or [n_origins][R][3] when per_origin_dirs; w2 likewise.
  * vel may be NULL (static).  u_out, if not NULL, receives u[o][r][f]. */
-OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const int32_t* idx,
-                        const float* vel, int64_t F, int32_t nblk, const int32_t* blk_len,
-                        const double* blk_dx, const double* chi, const double* eta, int64_t ld,
-                        const double* I_bc, int64_t R, const double* dirs, const double* w2,
-                        int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
-                        double* J, double* u_out, int nthreads) {
+OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, const int32_t* idx,
+                            const float* vel, int64_t F, int32_t nblk, const int32_t* blk_len,
+                            const double* blk_dx, const double* chi, const double* eta, int64_t ld,
+                            const double* I_bc, int64_t R, const double* dirs, const double* w2,
+                            int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
+                            double dtau_max, int64_t max_sub, double* J, double* u_out, int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -669,11 +735,18 @@ OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const 
                             w.eta[d] = (1.0 - t) * er[ia] + t * er[ib];
                             w.S[d] = w.eta[d] / w.chi[d];
                         }
-                        for (int64_t d = 0; d + 1 < N; ++d) {
-                            double ds = w.s[d + 1] - w.s[d];
-                            w.dtau[d] = (0.5 * (w.chi[d] + w.chi[d + 1])) * ds;
+                        double u;
+                        if (dtau_max > 0.0) {
+                            int64_t mr = 0;
+                            const int64_t Nr = refine_line(&w, N, m, dtau_max, max_sub, &mr);
+                            u = or_feautrier_u(Nr, mr, w.rdtau, w.rS, I_bc[f]);
+                        } else {
+                            for (int64_t d = 0; d + 1 < N; ++d) {
+                                double ds = w.s[d + 1] - w.s[d];
+                                w.dtau[d] = (0.5 * (w.chi[d] + w.chi[d + 1])) * ds;
+                            }
+                            u = or_feautrier_u(N, m, w.dtau, w.S, I_bc[f]);
                         }
-                        double u = or_feautrier_u(N, m, w.dtau, w.S, I_bc[f]);
                         if (!(u == u)) err = 1;
                         if (u_out) u_out[(oi * R + r) * F + f] = u;
                         Jo[f] += wv[r] * u;
@@ -685,4 +758,15 @@ OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const 
         ws_free(&w);
     }
     return err ? -7 : 0;
+}
+
+/* J without optical-depth sub-steps (every interval whole). */
+OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const int32_t* idx,
+                        const float* vel, int64_t F, int32_t nblk, const int32_t* blk_len,
+                        const double* blk_dx, const double* chi, const double* eta, int64_t ld,
+                        const double* I_bc, int64_t R, const double* dirs, const double* w2,
+                        int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
+                        double* J, double* u_out, int nthreads) {
+    return or_compute_J_sub(P, pos, off, idx, vel, F, nblk, blk_len, blk_dx, chi, eta, ld, I_bc, R, dirs, w2,
+                            per_origin_dirs, origins, n_origins, 0.0, 1, J, u_out, nthreads);
 }
