@@ -198,6 +198,13 @@ typedef struct {
                                  length then differs from its slot latches RT_ERR_CAPACITY.
                                  RT_WALK_PADDED: once into padded slots, then scan and compaction.
                                  RT_WALK_TWO_PASS: count, scan, write on every run. */
+    double dtau_max;          /* > 0: adaptive optical-depth increments (Section 2.1.2, eq. 2): the
+                                 interval between line points d, d+1 is split into
+                                 n = ceil(max(chi'_d, chi'_{d+1}) ds_d / dtau_max) equal parts
+                                 (chi' Doppler-shifted, evaluated in FP64 as (1-t) chi_a + t chi_b;
+                                 the product times the reciprocal of dtau_max rounded once), chi'
+                                 and eta' interpolated linearly between the end points; 0 = off */
+    int32_t max_substeps;     /* cap on n per interval (0 = 1024) */
 } rt_solve_opts;
 enum { RT_WALK_EXACT = 0, RT_WALK_PADDED = 1, RT_WALK_TWO_PASS = 2 };
 

@@ -606,7 +606,7 @@ static int64_t refine_line(or_ws* w, int64_t N, int64_t m, double dtau_max, int6
             const double cm = w->chi[d] > w->chi[d + 1] ? w->chi[d] : w->chi[d + 1];
             double c = ceil((cm * ds) * rdt);
             if (c > (double)max_sub) c = (double)max_sub;
-            n = c < 1.0 ? 1 : (int64_t)c;
+            n = c >= 1.0 ? (int64_t)c : 1;
         }
         w->nsub[d] = n;
         total += n;

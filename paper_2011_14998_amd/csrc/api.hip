@@ -335,6 +335,8 @@ static rt_solve_opts default_opts() {
     o.trace_lanes = 0;
     o.padded_trace_budget = 0;
     o.walk = RT_WALK_EXACT;
+    o.dtau_max = 0.0;
+    o.max_substeps = 0;
     return o;
 }
 
@@ -401,6 +403,9 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.I_bc = I_bc;
     a.J = J;
     a.dtau_fp64_below = o.dtau_fp64_below;
+    if (!(o.dtau_max >= 0.0) || o.max_substeps < 0) return fail(RT_ERR_ARG, "solve: dtau_max and max_substeps must be >= 0");
+    a.dtau_max_rcp = o.dtau_max > 0.0 ? 1.0 / o.dtau_max : 0.0;
+    a.max_sub = o.max_substeps > 0 ? o.max_substeps : 1024;
     a.schedule = o.schedule;
     a.n_bins = opts_bins(o);
     int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;

@@ -147,6 +147,8 @@ struct SolveLaunch {
     void* u;
     void* J;
     double dtau_fp64_below;
+    double dtau_max_rcp;   // 1/dtau_max (adaptive optical-depth increments), 0 = off
+    int32_t max_sub;       // cap on the sub-steps of one interval
     // scheduling
     int32_t schedule;
     const int32_t* items;  // binned order, or nullptr

@@ -192,7 +192,8 @@ __device__ inline void row_policy(SweepState<T>& st, bool far_end, T b, T S, T I
 template <>
 __device__ inline void row_policy<float>(SweepState<float>& st, bool far_end, float b, float S, float I,
                                          float thr) {
-    // far_end is the same in every lane: a scalar branch
+    // far_end is the same in every lane (a scalar branch) except with optical-depth
+    // sub-steps, where lanes split the first interval differently
     if (far_end) {
         if (__builtin_amdgcn_ballot_w64(b < thr)) row_coef64(st, true, b, S, I);
         else row<float>(st, true, b, S, I);
@@ -268,7 +269,44 @@ struct ItemCtx {
     double nx, ny, nz, inv_dx0;
     float vox, voy, voz;
     float thr;
+    double dtau_rcp;   // adaptive optical-depth increments: 1/dtau_max
+    int max_sub;
 };
+
+// Adaptive optical-depth increments (Section 2.1.2, eq. 2) for the interval
+// from the far point (chi cf, eta ef, S Sf) to the near point (cn, en, Sn) of
+// one side of the line; hds is half the interval's length.  The split count
+// n = ceil(max(chi'_far, chi'_near) ds / dtau_max), clamped to 1 .. max_sub, is
+// decided in FP64 from chi' evaluated as (1-t) chi_a + t chi_b (c64f, c64n) and
+// the FP64 length ds64, so every precision takes the same decision.  The n-1
+// interior points interpolate chi' and eta' linearly from the far point; the
+// rows are emitted far to near, each with its inner step, and the last row is
+// that of the sub-point next to the near point.  `first` marks the far end of
+// the line (its row is the boundary row).
+template <typename T>
+__device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
+                                        T hds, double c64f, double c64n, double ds64, T I) {
+    const double cm = c64f > c64n ? c64f : c64n;
+    double q = ceil((cm * ds64) * c.dtau_rcp);
+    if (q > (double)c.max_sub) q = (double)c.max_sub;
+    const int n = q >= 1.0 ? (int)q : 1;  // also 1 for a NaN
+    const T rn = rcp<T>((T)n);
+    const T hh = hds * rn;  // half a sub-interval
+    T cp = cf, Sp = Sf;
+    bool fr = first;
+    for (int k = 1; __builtin_amdgcn_ballot_w64(k < n); ++k) {
+        if (k < n) {
+            const T w = (T)k * rn;
+            const T ck = fma_<T>(w, cn - cf, cf);
+            const T ek = fma_<T>(w, en - ef, ef);
+            row_policy<T>(st, fr, (cp + ck) * hh, Sp, I, c.thr);
+            cp = ck;
+            Sp = ek * rcp<T>(ck);
+            fr = false;
+        }
+    }
+    row_policy<T>(st, fr, (cp + cn) * hh, Sp, I, c.thr);
+}
 
 // Eliminate one side of the line (entries base .. base+n-1 of a ray list,
 // walked from the far end inwards), up to the origin; on return st holds the
@@ -280,10 +318,12 @@ struct ItemCtx {
 // GROUP line points have their loads issued together before the recurrence
 // consumes them (a tuning parameter: more points in flight per wave against
 // more registers, i.e. fewer waves).
-template <typename T, bool MOVING, bool UDX, int GROUP>
-__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
-                             SweepState<T>& st) {
-    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
+// SUB: adaptive optical-depth increments between consecutive points.
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
+__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T eta_o,
+                             T I, SweepState<T>& st) {
+    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0, e_prev = (T)0;
+    double c64_prev = 0.0, ds64_prev = 0.0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
@@ -298,13 +338,14 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
         int q_l = 0, k_l = 0;
         int64_t row_l = 0;
         T ds_l = (T)0, t_l = (T)0;
-        double dot_l = 0.0;
+        double dot_l = 0.0, t64_l = 0.0, ds64_l = 0.0;
         if (v) {
             q_l = c.ids[base + e];
             row_l = (int64_t)q_l * c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
-            ds_l = (T)0.5 * (T)(z - zi);  // half the difference of FP64 projections, rounded once
+            ds64_l = z - zi;
+            ds_l = (T)0.5 * (T)ds64_l;  // half the difference of FP64 projections, rounded once
             if (MOVING) {
                 const float* vq = c.vel + 3 * (int64_t)q_l;
                 const double dvx = (double)vq[0] - (double)c.vox;
@@ -315,12 +356,14 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     const double delta = dot_l * c.inv_dx0;
                     const double kf = floor(delta);
                     k_l = (int)kf;
-                    t_l = (T)(delta - kf);
+                    t64_l = delta - kf;
+                    t_l = (T)t64_l;
                 }
             }
         }
         for (int j = 0; j < cnt; j += GROUP) {
             T ca[GROUP], cb[GROUP], ea[GROUP], eb[GROUP], tt[GROUP], dsv[GROUP];
+            double t64[GROUP], ds64v[GROUP];
 #pragma unroll
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
@@ -328,17 +371,22 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     const char* cr = c.chi + row;
                     const char* er = c.eta + row;
                     dsv[g] = readlane_t<T>(ds_l, j + g);
+                    if (SUB) ds64v[g] = readlane_d(ds64_l, j + g);
                     if (MOVING) {
                         int k;
                         T t;
                         if (UDX) {
                             k = readlane_i(k_l, j + g);
                             t = readlane_t<T>(t_l, j + g);
+                            if (SUB) t64[g] = readlane_d(t64_l, j + g);
                         } else {
+                            // the oracle divides by dx_b; the product with its reciprocal can
+                            // differ in the last bit, which only moves t by an ulp
                             const double delta = readlane_d(dot_l, j + g) * lf.inv_dx;
                             const double kf = floor(delta);
                             k = (int)kf;
                             t = (T)(delta - kf);
+                            if (SUB) t64[g] = delta - kf;
                         }
                         // byte offsets of rows fl - k and fl - k - 1, clamped to the block
                         const int ks = k * (int)sizeof(T);
@@ -359,33 +407,51 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
                     T cc, et;
+                    double c64 = 0.0;
                     if (MOVING) {
                         cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
                         et = fma_<T>(tt[g], eb[g] - ea[g], ea[g]);
+                        if (SUB) c64 = (1.0 - t64[g]) * (double)ca[g] + t64[g] * (double)cb[g];
                     } else {
                         cc = ca[g];
                         et = ea[g];
+                        if (SUB) c64 = (double)ca[g];
                     }
                     const T S = et * rcp<T>(cc);
                     if (done > 0) {
-                        const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
-                        row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
+                        if (SUB) {
+                            substep_interval<T>(c, st, done == 1, c_prev, e_prev, S_prev, cc, et, ds_prev, c64_prev,
+                                                c64, ds64_prev, I);
+                        } else {
+                            const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
+                            row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
+                        }
                     }
                     c_prev = cc;
                     S_prev = S;
                     ds_prev = dsv[g];
+                    if (SUB) {
+                        e_prev = et;
+                        c64_prev = c64;
+                        ds64_prev = ds64v[g];
+                    }
                     ++done;
                 }
             }
         }
     }
     if (n > 0) {
-        const T dt = (c_prev + chi_o) * ds_prev;
-        row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
+        if (SUB) {
+            substep_interval<T>(c, st, n == 1, c_prev, e_prev, S_prev, chi_o, eta_o, ds_prev, c64_prev, (double)chi_o,
+                                ds64_prev, I);
+        } else {
+            const T dt = (c_prev + chi_o) * ds_prev;
+            row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
+        }
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane) {
     // w is the same in every lane of the wave
     w = uni64(w);
@@ -422,12 +488,15 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
         c.voz = a.vel[3 * o + 2];
     }
     c.thr = (float)a.dtau_fp64_below;
+    c.dtau_rcp = a.dtau_max_rcp;
+    c.max_sub = a.max_sub;
     const T I = (T)a.I_bc[lf.f];
     const T chi_o = ((const T*)a.chi)[o * a.ld + lf.f];
-    const T S_o = ((const T*)a.eta)[o * a.ld + lf.f] * rcp<T>(chi_o);
+    const T eta_o = ((const T*)a.eta)[o * a.ld + lf.f];
+    const T S_o = eta_o * rcp<T>(chi_o);
     SweepState<T> m{}, p{};
-    sweep<T, MOVING, UDX, GROUP>(c, bm, nm, lf, lane, chi_o, I, m);
-    sweep<T, MOVING, UDX, GROUP>(c, bp, np, lf, lane, chi_o, I, p);
+    sweep<T, MOVING, UDX, GROUP, SUB>(c, bm, nm, lf, lane, chi_o, eta_o, I, m);
+    sweep<T, MOVING, UDX, GROUP, SUB>(c, bp, np, lf, lane, chi_o, eta_o, I, p);
     const T u = origin_policy<T>(nm > 0, np > 0, m, p, S_o, I, c.thr);
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
@@ -435,7 +504,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -452,14 +521,14 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
         }
-        solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, SUB>(a, w, nfc, lane);
     }
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
 // takes the next item with one atomic and exits when the queue is empty, so
 // every wave reaches the end.
-template <typename T, bool MOVING, bool UDX, int GROUP>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -470,7 +539,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX, GROUP>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, SUB>(a, w, nfc, lane);
     }
 }
 
@@ -585,13 +654,13 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
-template <typename T, int G>
+template <typename T, int G, bool SUB>
 static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     const bool moving = a.vel != nullptr;
     // the shift of a point is lane-independent when every block has the same dx
     bool udx = true;
     for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
-#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, SUB>), grid, dim3(SOLVE_BLOCK), 0, s, a)
     if (persist) {
         if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
         else if (moving) RT_LAUNCH(k_solve_persist, true, false);
@@ -606,8 +675,10 @@ static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipS
 
 template <typename T>
 static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
-    if (a.group == 4) solve_dispatch_g<T, 4>(a, persist, grid, s);
-    else solve_dispatch_g<T, 8>(a, persist, grid, s);
+    // optical-depth sub-steps are built with load group 4 only
+    if (a.dtau_max_rcp > 0.0) solve_dispatch_g<T, 4, true>(a, persist, grid, s);
+    else if (a.group == 4) solve_dispatch_g<T, 4, false>(a, persist, grid, s);
+    else solve_dispatch_g<T, 8, false>(a, persist, grid, s);
 }
 
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s) {
