@@ -274,18 +274,33 @@ struct ItemCtx {
 };
 
 // Adaptive optical-depth increments (Section 2.1.2, eq. 2) for the interval
-// from the far point (chi cf, eta ef, S Sf) to the near point (cn, en, Sn) of
-// one side of the line; hds is half the interval's length.  The split count
+// from the far point (chi cf, eta ef, S Sf) to the near point (cn, en) of one
+// side of the line; hds is half the interval's length.  The split count
 // n = ceil(max(chi'_far, chi'_near) ds / dtau_max), clamped to 1 .. max_sub, is
-// decided in FP64 from chi' evaluated as (1-t) chi_a + t chi_b (c64f, c64n) and
-// the FP64 length ds64, so every precision takes the same decision.  The n-1
-// interior points interpolate chi' and eta' linearly from the far point; the
-// rows are emitted far to near, each with its inner step, and the last row is
-// that of the sub-point next to the near point.  `first` marks the far end of
-// the line (its row is the boundary row).
+// decided in FP64 from chi' evaluated as (1-t) chi_a + t chi_b from the point's
+// two table values and shift fraction (Pt64) and the FP64 length ds64, so every
+// precision takes the same decision.  When the kernel-precision estimate is
+// below 1 - 1e-4 in every lane (it is within a few ulps of the FP64 value), n is
+// 1 everywhere and the FP64 evaluation is skipped.  The n-1 interior points
+// interpolate chi' and eta' linearly from the far point; rows are emitted far
+// to near, each with its inner step, the last being the sub-point next to the
+// near point.  `first` marks the far end of the line (its row is the boundary row).
+template <typename T>
+struct Pt64 {
+    T ca, cb;    // table values at rows f - k and f - k - 1
+    double t;    // shift fraction
+};
+
 template <typename T>
 __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
-                                        T hds, double c64f, double c64n, double ds64, T I) {
+                                        T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I) {
+    const T est = (cf > cn ? cf : cn) * (hds + hds) * (T)c.dtau_rcp;
+    if (!__builtin_amdgcn_ballot_w64(est > (T)0.9999)) {
+        row_policy<T>(st, first, (cf + cn) * hds, Sf, I, c.thr);
+        return;
+    }
+    const double c64f = (1.0 - pf.t) * (double)pf.ca + pf.t * (double)pf.cb;
+    const double c64n = (1.0 - pn.t) * (double)pn.ca + pn.t * (double)pn.cb;
     const double cm = c64f > c64n ? c64f : c64n;
     double q = ceil((cm * ds64) * c.dtau_rcp);
     if (q > (double)c.max_sub) q = (double)c.max_sub;
@@ -323,7 +338,8 @@ template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
 __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T eta_o,
                              T I, SweepState<T>& st) {
     T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0, e_prev = (T)0;
-    double c64_prev = 0.0, ds64_prev = 0.0;
+    Pt64<T> p_prev{(T)0, (T)0, 0.0};
+    double ds64_prev = 0.0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
@@ -407,21 +423,21 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
                     T cc, et;
-                    double c64 = 0.0;
+                    Pt64<T> pc{(T)0, (T)0, 0.0};
                     if (MOVING) {
                         cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
                         et = fma_<T>(tt[g], eb[g] - ea[g], ea[g]);
-                        if (SUB) c64 = (1.0 - t64[g]) * (double)ca[g] + t64[g] * (double)cb[g];
+                        if (SUB) pc = Pt64<T>{ca[g], cb[g], t64[g]};
                     } else {
                         cc = ca[g];
                         et = ea[g];
-                        if (SUB) c64 = (double)ca[g];
+                        if (SUB) pc = Pt64<T>{ca[g], ca[g], 0.0};
                     }
                     const T S = et * rcp<T>(cc);
                     if (done > 0) {
                         if (SUB) {
-                            substep_interval<T>(c, st, done == 1, c_prev, e_prev, S_prev, cc, et, ds_prev, c64_prev,
-                                                c64, ds64_prev, I);
+                            substep_interval<T>(c, st, done == 1, c_prev, e_prev, S_prev, cc, et, ds_prev, p_prev, pc,
+                                                ds64_prev, I);
                         } else {
                             const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
                             row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
@@ -432,7 +448,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     ds_prev = dsv[g];
                     if (SUB) {
                         e_prev = et;
-                        c64_prev = c64;
+                        p_prev = pc;
                         ds64_prev = ds64v[g];
                     }
                     ++done;
@@ -442,8 +458,8 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     }
     if (n > 0) {
         if (SUB) {
-            substep_interval<T>(c, st, n == 1, c_prev, e_prev, S_prev, chi_o, eta_o, ds_prev, c64_prev, (double)chi_o,
-                                ds64_prev, I);
+            substep_interval<T>(c, st, n == 1, c_prev, e_prev, S_prev, chi_o, eta_o, ds_prev, p_prev,
+                                Pt64<T>{chi_o, chi_o, 0.0}, ds64_prev, I);
         } else {
             const T dt = (c_prev + chi_o) * ds_prev;
             row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
