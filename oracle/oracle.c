@@ -556,6 +556,13 @@ typedef struct {
     int64_t* nsub;              /* optical-depth sub-steps per interval */
     int64_t rcap;               /* line refined by optical-depth sub-steps */
     double* rdtau; double* rS; double* rchi;
+    int64_t vcap;               /* line after velocity sampling: point i lies between */
+    int32_t* va; int32_t* vb;   /* assembled points va[i] and vb[i] at weight vw[i] */
+    double* vw; double* vdot;   /* (0 for an assembled point), projected velocity, */
+    double* vds;                /* length of the interval to point i+1 */
+    int64_t* vk; double* vt;    /* shift of point i in the current block */
+    double* vchi; double* veta; double* vS;
+    int64_t* vn;                /* velocity sub-steps per assembled interval */
 } or_ws;
 
 static void ws_grow(or_ws* w, int64_t n) {
@@ -567,14 +574,28 @@ static void ws_grow(or_ws* w, int64_t n) {
     w->dtau = realloc(w->dtau, (2 * c + 1) * sizeof(double)); w->S = realloc(w->S, (2 * c + 1) * sizeof(double));
     w->chi = realloc(w->chi, (2 * c + 1) * sizeof(double)); w->eta = realloc(w->eta, (2 * c + 1) * sizeof(double));
     w->k = realloc(w->k, (2 * c + 1) * sizeof(int64_t)); w->t = realloc(w->t, (2 * c + 1) * sizeof(double));
-    w->nsub = realloc(w->nsub, (2 * c + 1) * sizeof(int64_t));
+    w->vn = realloc(w->vn, (2 * c + 1) * sizeof(int64_t));
     w->cap = c;
 }
 
 static void ws_free(or_ws* w) {
     free(w->idm); free(w->Zm); free(w->idp); free(w->Zp); free(w->q); free(w->s);
-    free(w->dtau); free(w->S); free(w->chi); free(w->eta); free(w->k); free(w->t); free(w->nsub);
+    free(w->dtau); free(w->S); free(w->chi); free(w->eta); free(w->k); free(w->t);
     free(w->rdtau); free(w->rS); free(w->rchi);
+    free(w->va); free(w->vb); free(w->vw); free(w->vdot); free(w->vds);
+    free(w->vk); free(w->vt); free(w->vchi); free(w->veta); free(w->vS); free(w->vn); free(w->nsub);
+}
+
+static void ws_grow_vel(or_ws* w, int64_t n) {
+    if (n <= w->vcap) return;
+    int64_t c = n * 2;
+    w->va = realloc(w->va, c * sizeof(int32_t)); w->vb = realloc(w->vb, c * sizeof(int32_t));
+    w->vw = realloc(w->vw, c * sizeof(double)); w->vdot = realloc(w->vdot, c * sizeof(double));
+    w->vds = realloc(w->vds, c * sizeof(double));
+    w->vk = realloc(w->vk, c * sizeof(int64_t)); w->vt = realloc(w->vt, c * sizeof(double));
+    w->vchi = realloc(w->vchi, c * sizeof(double)); w->veta = realloc(w->veta, c * sizeof(double));
+    w->vS = realloc(w->vS, c * sizeof(double)); w->nsub = realloc(w->nsub, c * sizeof(int64_t));
+    w->vcap = c;
 }
 
 static void ws_grow_refined(or_ws* w, int64_t n) {
@@ -590,7 +611,7 @@ static void ws_grow_refined(or_ws* w, int64_t n) {
  * between line points d and d+1 is split into
  *     n_d = ceil(max(chi_d, chi_{d+1}) ds_d / dtau_max)
  * equal parts (computed as (max * ds) * (1/dtau_max), the reciprocal rounded
- * once; n_d clamped to 1 .. max_sub), and chi and eta are interpolated
+ * once; n_d clamped to 1 .. max_sub; ds_d the interval's length), and chi and eta are interpolated
  * linearly on the sub-intervals: at w = i/n_d, chi = (1-w) chi_d + w chi_{d+1},
  * eta likewise, S = eta/chi.  Every sub-interval gets the trapezoid
  * dtau = (0.5 (chi_j + chi_{j+1})) (ds_d / n_d).  Writes the refined line into
@@ -602,8 +623,8 @@ static int64_t refine_line(or_ws* w, int64_t N, int64_t m, double dtau_max, int6
     for (int64_t d = 0; d + 1 < N; ++d) {
         int64_t n = 1;
         if (dtau_max > 0.0) {
-            const double ds = w->s[d + 1] - w->s[d];
-            const double cm = w->chi[d] > w->chi[d + 1] ? w->chi[d] : w->chi[d + 1];
+            const double ds = w->vds[d];
+            const double cm = w->vchi[d] > w->vchi[d + 1] ? w->vchi[d] : w->vchi[d + 1];
             double c = ceil((cm * ds) * rdt);
             if (c > (double)max_sub) c = (double)max_sub;
             n = c >= 1.0 ? (int64_t)c : 1;
@@ -615,15 +636,15 @@ static int64_t refine_line(or_ws* w, int64_t N, int64_t m, double dtau_max, int6
     int64_t j = 0;
     for (int64_t d = 0; d < N; ++d) {
         if (d == m) *m_out = j;
-        w->rS[j] = w->S[d];
-        w->rchi[j] = w->chi[d];
+        w->rS[j] = w->vS[d];
+        w->rchi[j] = w->vchi[d];
         ++j;
         if (d + 1 == N) break;
         const int64_t n = w->nsub[d];
         for (int64_t i = 1; i < n; ++i) {
             const double wt = (double)i / (double)n;
-            const double c = (1.0 - wt) * w->chi[d] + wt * w->chi[d + 1];
-            const double e = (1.0 - wt) * w->eta[d] + wt * w->eta[d + 1];
+            const double c = (1.0 - wt) * w->vchi[d] + wt * w->vchi[d + 1];
+            const double e = (1.0 - wt) * w->veta[d] + wt * w->veta[d + 1];
             w->rS[j] = e / c;
             w->rchi[j] = c;
             ++j;
@@ -632,13 +653,78 @@ static int64_t refine_line(or_ws* w, int64_t N, int64_t m, double dtau_max, int6
     j = 0;
     for (int64_t d = 0; d + 1 < N; ++d) {
         const int64_t n = w->nsub[d];
-        const double h = (w->s[d + 1] - w->s[d]) / (double)n;
+        const double h = w->vds[d] / (double)n;
         for (int64_t i = 0; i < n; ++i, ++j) w->rdtau[j] = (0.5 * (w->rchi[j] + w->rchi[j + 1])) * h;
     }
     return total;
 }
 
 static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Adaptive velocity sampling (Section 2.1.1).  With p_d = n_r . (v_{q_d} - v_o)
+ * the projected velocity of assembled line point d (in Doppler widths), the
+ * interval d .. d+1 is split into
+ *     m_d = ceil(|p_{d+1} - p_d| / dv_max)
+ * equal parts (the product with the reciprocal of dv_max rounded once; m_d
+ * clamped to 1 .. max_sub).  A point at weight w = j/m_d carries the projected
+ * velocity (1-w) p_d + w p_{d+1}; its optics are (1-w) X_d + w X_{d+1}, where
+ * X_e is point e's table interpolated at that point's own shift (so the line
+ * profile moves smoothly along the interval), and each part is ds_d / m_d long.
+ * Fills w->va/vb/vw/vdot/vds for the sampled line, returns its length and the
+ * new index of the origin in *m_out.  dv_max <= 0 (or a static medium) keeps
+ * the assembled points. */
+static int64_t velocity_line(or_ws* w, int64_t N, int64_t m, const float* vel, int64_t o, const double* dp,
+                             double dv_max, int64_t max_sub, int64_t* m_out) {
+    /* projected velocities of the assembled points, kept in w->t (re-filled per block later) */
+    for (int64_t d = 0; d < N; ++d) {
+        if (vel) {
+            const float* vq = vel + 3 * (int64_t)w->q[d];
+            const float* vo = vel + 3 * o;
+            double dvx = (double)vq[0] - (double)vo[0];
+            double dvy = (double)vq[1] - (double)vo[1];
+            double dvz = (double)vq[2] - (double)vo[2];
+            w->t[d] = (dp[0] * dvx + dp[1] * dvy) + dp[2] * dvz;
+        } else {
+            w->t[d] = 0.0;
+        }
+    }
+    const double rdv = dv_max > 0.0 ? 1.0 / dv_max : 0.0;
+    int64_t total = 1;
+    for (int64_t d = 0; d + 1 < N; ++d) {
+        int64_t n = 1;
+        if (dv_max > 0.0 && vel) {
+            double c = ceil(fabs(w->t[d + 1] - w->t[d]) * rdv);
+            if (c > (double)max_sub) c = (double)max_sub;
+            n = c >= 1.0 ? (int64_t)c : 1;
+        }
+        w->vn[d] = n;
+        total += n;
+    }
+    ws_grow_vel(w, total);
+    int64_t i = 0;
+    for (int64_t d = 0; d < N; ++d) {
+        if (d == m) *m_out = i;
+        w->va[i] = (int32_t)d;
+        w->vb[i] = (int32_t)d;
+        w->vw[i] = 0.0;
+        w->vdot[i] = w->t[d];
+        ++i;
+        if (d + 1 == N) break;
+        const int64_t n = w->vn[d];
+        const double h = (w->s[d + 1] - w->s[d]) / (double)n;
+        w->vds[i - 1] = h;
+        for (int64_t j = 1; j < n; ++j) {
+            const double wt = (double)j / (double)n;
+            w->va[i] = (int32_t)d;
+            w->vb[i] = (int32_t)(d + 1);
+            w->vw[i] = wt;
+            w->vdot[i] = (1.0 - wt) * w->t[d] + wt * w->t[d + 1];
+            w->vds[i] = h;
+            ++i;
+        }
+    }
+    return total;
+}
 
 /* J[o][f] at every listed origin (eq. 3, eq. 4).
  *
@@ -660,7 +746,8 @@ OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, co
                             const double* blk_dx, const double* chi, const double* eta, int64_t ld,
                             const double* I_bc, int64_t R, const double* dirs, const double* w2,
                             int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
-                            double dtau_max, int64_t max_sub, double* J, double* u_out, int nthreads) {
+                            double dv_max, double dtau_max, int64_t max_sub, double* J, double* u_out,
+                            int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -672,6 +759,7 @@ OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, co
         or_ws w;
         memset(&w, 0, sizeof(w));
         ws_grow(&w, 256);
+        ws_grow_vel(&w, 512);
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 16)
 #endif
@@ -703,49 +791,52 @@ OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, co
                     w.q[m + 1 + j] = w.idp[j];
                     w.s[m + 1 + j] = w.Zp[j];
                 }
+                int64_t mv = m;
+                const int64_t Nv = velocity_line(&w, N, m, vel, o, dp, dv_max, max_sub, &mv);
                 int64_t fb = 0;
                 for (int32_t b = 0; b < nblk; ++b) {
                     const int64_t L = blk_len[b];
                     /* per-point Doppler shift in this block's index units */
-                    for (int64_t d = 0; d < N; ++d) {
+                    for (int64_t i = 0; i < Nv; ++i) {
                         if (vel) {
-                            const float* vq = vel + 3 * (int64_t)w.q[d];
-                            const float* vo = vel + 3 * o;
-                            double dvx = (double)vq[0] - (double)vo[0];
-                            double dvy = (double)vq[1] - (double)vo[1];
-                            double dvz = (double)vq[2] - (double)vo[2];
-                            double delta = ((dp[0] * dvx + dp[1] * dvy) + dp[2] * dvz) / blk_dx[b];
+                            double delta = w.vdot[i] / blk_dx[b];
                             double fl = floor(delta);
-                            w.k[d] = (int64_t)fl;
-                            w.t[d] = delta - fl;
+                            w.vk[i] = (int64_t)fl;
+                            w.vt[i] = delta - fl;
                         } else {
-                            w.k[d] = 0;
-                            w.t[d] = 0.0;
+                            w.vk[i] = 0;
+                            w.vt[i] = 0.0;
                         }
                     }
                     for (int64_t j = 0; j < L; ++j) {
                         const int64_t f = fb + j;
-                        for (int64_t d = 0; d < N; ++d) {
-                            const double* cr = chi + (int64_t)w.q[d] * ld + fb;
-                            const double* er = eta + (int64_t)w.q[d] * ld + fb;
-                            int64_t ia = clampi(j - w.k[d], 0, L - 1);
-                            int64_t ib = clampi(j - w.k[d] - 1, 0, L - 1);
-                            double t = w.t[d];
-                            w.chi[d] = (1.0 - t) * cr[ia] + t * cr[ib];
-                            w.eta[d] = (1.0 - t) * er[ia] + t * er[ib];
-                            w.S[d] = w.eta[d] / w.chi[d];
+                        for (int64_t i = 0; i < Nv; ++i) {
+                            const double* ca = chi + (int64_t)w.q[w.va[i]] * ld + fb;
+                            const double* ea = eta + (int64_t)w.q[w.va[i]] * ld + fb;
+                            const double* cb = chi + (int64_t)w.q[w.vb[i]] * ld + fb;
+                            const double* eb = eta + (int64_t)w.q[w.vb[i]] * ld + fb;
+                            int64_t ia = clampi(j - w.vk[i], 0, L - 1);
+                            int64_t ib = clampi(j - w.vk[i] - 1, 0, L - 1);
+                            double t = w.vt[i], wt = w.vw[i];
+                            /* each end point's table at this point's shift, then mixed by weight */
+                            const double xa = (1.0 - t) * ca[ia] + t * ca[ib];
+                            const double xb = (1.0 - t) * cb[ia] + t * cb[ib];
+                            const double ya = (1.0 - t) * ea[ia] + t * ea[ib];
+                            const double yb = (1.0 - t) * eb[ia] + t * eb[ib];
+                            w.vchi[i] = (1.0 - wt) * xa + wt * xb;
+                            w.veta[i] = (1.0 - wt) * ya + wt * yb;
+                            w.vS[i] = w.veta[i] / w.vchi[i];
                         }
                         double u;
                         if (dtau_max > 0.0) {
                             int64_t mr = 0;
-                            const int64_t Nr = refine_line(&w, N, m, dtau_max, max_sub, &mr);
+                            const int64_t Nr = refine_line(&w, Nv, mv, dtau_max, max_sub, &mr);
                             u = or_feautrier_u(Nr, mr, w.rdtau, w.rS, I_bc[f]);
                         } else {
-                            for (int64_t d = 0; d + 1 < N; ++d) {
-                                double ds = w.s[d + 1] - w.s[d];
-                                w.dtau[d] = (0.5 * (w.chi[d] + w.chi[d + 1])) * ds;
-                            }
-                            u = or_feautrier_u(N, m, w.dtau, w.S, I_bc[f]);
+                            ws_grow_refined(&w, Nv);
+                            for (int64_t i = 0; i + 1 < Nv; ++i)
+                                w.rdtau[i] = (0.5 * (w.vchi[i] + w.vchi[i + 1])) * w.vds[i];
+                            u = or_feautrier_u(Nv, mv, w.rdtau, w.vS, I_bc[f]);
                         }
                         if (!(u == u)) err = 1;
                         if (u_out) u_out[(oi * R + r) * F + f] = u;
@@ -768,5 +859,5 @@ OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const 
                         int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
                         double* J, double* u_out, int nthreads) {
     return or_compute_J_sub(P, pos, off, idx, vel, F, nblk, blk_len, blk_dx, chi, eta, ld, I_bc, R, dirs, w2,
-                            per_origin_dirs, origins, n_origins, 0.0, 1, J, u_out, nthreads);
+                            per_origin_dirs, origins, n_origins, 0.0, 0.0, 1, J, u_out, nthreads);
 }

@@ -143,3 +143,126 @@ def test_refined_line_exact(orc, dtau_max):
                 assert abs(u[oi, r, f] - float(ue)) <= 1e-12 * abs(float(ue)), (o, r, f)
                 checked += 1
     assert checked >= 10
+
+
+# ----------------------------------------------------------------------------- velocity sampling (Section 2.1.1)
+
+def _sampled_exact_u(trace_ray, m, o, d, f, I, dv_max, dtau_max=0.0, max_sub=1024):
+    """Exact rational construction with velocity sampling: assembled points get their
+    projected velocity p; an interval whose |p_{d+1} - p_d| exceeds dv_max gets
+    ceil(|dp|/dv_max) equal parts whose points carry the interpolated velocity and the
+    weight-mixed optics of the two end points, each read at the new point's own shift;
+    then the optical-depth split (if any) and the exact solve.  Returns (u, gap) with gap
+    the smallest distance of a split argument to an integer."""
+    ids_p, Z_p = trace_ray(m, o, d)
+    ids_m, Z_m = trace_ray(m, o, -d)
+    q = list(ids_m[::-1]) + [o] + list(ids_p)
+    s = [-Fr(float(z)) for z in Z_m[::-1]] + [Fr(0)] + [Fr(float(z)) for z in Z_p]
+    mi = len(ids_m)
+    starts = np.concatenate([[0], np.cumsum(m.freq.len)])
+    b = int(np.searchsorted(starts, f, side="right") - 1)
+    fb, L, dx = int(starts[b]), int(m.freq.len[b]), Fr(float(m.freq.dx[b]))
+    j = f - fb
+    vo = [Fr(float(v)) for v in m.vel[o]]
+    dd = [Fr(float(c)) for c in d]
+    pv = [sum(a * (Fr(float(v)) - w) for a, v, w in zip(dd, m.vel[p], vo)) for p in q]
+
+    def table(p, tab, shift):
+        k = math.floor(shift)
+        t = shift - k
+        ia = min(max(j - k, 0), L - 1)
+        ib = min(max(j - k - 1, 0), L - 1)
+        return (1 - t) * Fr(float(tab[p, fb + ia])) + t * Fr(float(tab[p, fb + ib]))
+
+    gap = 1.0
+    chi, eta, ds, mref = [], [], [], None
+    for i in range(len(q)):
+        if i == mi:
+            mref = len(chi)
+        sh = pv[i] / dx
+        chi.append(table(q[i], m.chi, sh))
+        eta.append(table(q[i], m.eta, sh))
+        if i + 1 == len(q):
+            break
+        arg = abs(pv[i + 1] - pv[i]) / Fr(dv_max)
+        gap = min(gap, abs(float(arg) - round(float(arg))))
+        n = min(max(math.ceil(arg), 1), max_sub)
+        h = (s[i + 1] - s[i]) / n
+        ds.append(h)
+        for k in range(1, n):
+            w = Fr(k, n)
+            sh = ((1 - w) * pv[i] + w * pv[i + 1]) / dx
+            chi.append((1 - w) * table(q[i], m.chi, sh) + w * table(q[i + 1], m.chi, sh))
+            eta.append((1 - w) * table(q[i], m.eta, sh) + w * table(q[i + 1], m.eta, sh))
+            ds.append(h)
+    rc, re, rds, mr = [], [], [], None
+    for i in range(len(chi)):
+        if i == mref:
+            mr = len(rc)
+        rc.append(chi[i])
+        re.append(eta[i])
+        if i + 1 == len(chi):
+            break
+        n = 1
+        if dtau_max > 0:
+            arg = max(chi[i], chi[i + 1]) * ds[i] / Fr(dtau_max)
+            gap = min(gap, abs(float(arg) - round(float(arg))))
+            n = min(max(math.ceil(arg), 1), max_sub)
+        for k in range(1, n):
+            w = Fr(k, n)
+            rc.append((1 - w) * chi[i] + w * chi[i + 1])
+            re.append((1 - w) * eta[i] + w * eta[i + 1])
+        rds += [ds[i] / n] * n
+    dtau = [(rc[i] + rc[i + 1]) / 2 * rds[i] for i in range(len(rc) - 1)]
+    S = [e / c for e, c in zip(re, rc)]
+    return exact_u_tridiag(dtau, S, mr, Fr(float(I))), gap
+
+
+def test_velocity_sampling_identities(orc):
+    m = synth.tiny_model(51, P=60, F=6, moving=True)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    J0 = orc.compute_J(m, dirs, w2)
+    assert np.array_equal(J0, orc.compute_J(m, dirs, w2, dv_max=1e6))      # nothing to split
+    assert not np.allclose(J0, orc.compute_J(m, dirs, w2, dv_max=0.2), rtol=1e-6)
+    ms = synth.tiny_model(51, P=60, F=6, moving=False)                      # static: no velocities to sample
+    assert np.array_equal(orc.compute_J(ms, dirs, w2), orc.compute_J(ms, dirs, w2, dv_max=0.1))
+    S = 0.4                                                                  # S = I: still exactly S
+    m.eta = m.chi * S
+    m.I_bc = np.full(m.F, S)
+    assert np.allclose(orc.compute_J(m, dirs, w2, dv_max=0.1, dtau_max=0.05), S, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dv_max,dtau_max", [(0.5, 0.0), (0.25, 0.4)])
+def test_velocity_sampled_line_exact(orc, dv_max, dtau_max):
+    m = synth.tiny_model(52, P=40, F=8, moving=True)
+    m.freq = synth.FreqGrid(np.array([5, 3], np.int32), np.array([-3.0, -1.0]), np.array([0.8, 0.55]))
+    rng = np.random.default_rng(12)
+    m.I_bc = rng.uniform(0.0, 0.4, m.F)
+    _, dirs, w2 = orc.dirset_uniform(1)
+    origins = np.array([6, 25], np.int32)
+    J, u = orc.compute_J(m, dirs, w2, origins=origins, want_u=True, dv_max=dv_max, dtau_max=dtau_max)
+    checked = 0
+    for oi, o in enumerate(origins):
+        for r in (0, 3):
+            for f in (1, 4, 6):
+                ue, gap = _sampled_exact_u(orc.trace_ray, m, int(o), dirs[r], f, m.I_bc[f], dv_max, dtau_max)
+                if gap < 1e-9:
+                    continue
+                assert abs(u[oi, r, f] - float(ue)) <= 1e-12 * abs(float(ue)), (o, r, f)
+                checked += 1
+    assert checked >= 9
+
+
+def test_velocity_sampling_converges(orc):
+    """A steep velocity gradient along the line: successive halvings of dv_max change J
+    less and less."""
+    m = synth.tiny_model(53, P=80, F=24, moving=True)
+    m.vel = (m.vel * 4.0).astype(np.float32)
+    m.freq = synth.FreqGrid(np.array([24], np.int32), np.array([-4.0]), np.array([8.0 / 23]))
+    x = m.freq.x()
+    m.chi = 0.5 + 5.0 * np.exp(-x[None, :] ** 2) * np.ones((m.P, 1))
+    m.eta = m.chi * np.linspace(0.5, 1.5, m.P)[:, None]
+    _, dirs, w2 = orc.dirset_uniform(1)
+    Js = [orc.compute_J(m, dirs, w2, origins=np.arange(0, m.P, 8), dv_max=v) for v in (1.0, 0.5, 0.25, 0.125)]
+    diffs = [np.max(np.abs(Js[i + 1] - Js[i]) / np.abs(Js[-1])) for i in range(3)]
+    assert diffs[2] < diffs[0] / 2.5, diffs
