@@ -207,6 +207,9 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=20000, help="closure training steps")
     ap.add_argument("--closure-batch", type=int, default=8192)
     ap.add_argument("--closure-lr", type=float, default=2e-3)
+    ap.add_argument("--dv-max", type=float, default=0.0,
+                    help="adaptive velocity sampling: split line intervals whose projected velocity changes by "
+                         "more than this many Doppler widths (0 = off)")
     ap.add_argument("--dtau-max", type=float, default=0.0,
                     help="adaptive optical-depth increments: split line intervals to at most this optical depth "
                          "(0 = off)")
@@ -287,7 +290,7 @@ def main():
         _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   dtau_fp64_below=args.fp64_below, dtau_max=args.dtau_max,
+                   dtau_fp64_below=args.fp64_below, dtau_max=args.dtau_max, dv_max=args.dv_max,
                    walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
                    **opts)
     total = plan.info()["total"]
@@ -340,7 +343,7 @@ def main():
             "workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep",
             "points": m.P, "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
             "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "walk": args.walk,
-            "dtau_max": args.dtau_max, "autotune": tuned,
+            "dtau_max": args.dtau_max, "dv_max": args.dv_max, "autotune": tuned,
             "fp64_rows_below_dtau": args.fp64_below, "frequency_chunks_per_pair": nfc,
         },
         "roofline": {

@@ -204,7 +204,14 @@ typedef struct {
                                  (chi' Doppler-shifted, evaluated in FP64 as (1-t) chi_a + t chi_b;
                                  the product times the reciprocal of dtau_max rounded once), chi'
                                  and eta' interpolated linearly between the end points; 0 = off */
-    int32_t max_substeps;     /* cap on n per interval (0 = 1024) */
+    int32_t max_substeps;     /* cap on n (and on m below) per interval (0 = 1024) */
+    double dv_max;            /* > 0 (moving media): adaptive velocity sampling (Section 2.1.1), before
+                                 the optical-depth split: with p_d = n_r.(v_d - v_o) the interval d, d+1
+                                 gets m = ceil(|p_{d+1} - p_d| / dv_max) equal parts (Doppler widths;
+                                 the reciprocal rounded once); a point at weight w = j/m from the point
+                                 of smaller line coordinate carries p = (1-w) p_d + w p_{d+1} and the
+                                 optics (1-w) X_d + w X_{d+1}, X_e being point e's table read at the new
+                                 point's own shift; 0 = off */
 } rt_solve_opts;
 enum { RT_WALK_EXACT = 0, RT_WALK_PADDED = 1, RT_WALK_TWO_PASS = 2 };
 

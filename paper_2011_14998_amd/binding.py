@@ -37,7 +37,8 @@ class FreqGridC(C.Structure):
 class SolveOptsC(C.Structure):
     _fields_ = [("precision", _i32), ("schedule", _i32), ("dtau_fp64_below", _dbl),
                 ("waves_per_cu", _i32), ("n_bins", _i32), ("group", _i32), ("trace_lanes", _i32),
-                ("padded_trace_budget", _i64), ("walk", _i32), ("dtau_max", _dbl), ("max_substeps", _i32)]
+                ("padded_trace_budget", _i64), ("walk", _i32), ("dtau_max", _dbl), ("max_substeps", _i32),
+                ("dv_max", _dbl)]
 
 
 # name -> (restype, argtypes)
@@ -297,15 +298,15 @@ def _grid(freq_len: Sequence[int], freq_dx: Sequence[float]):
 
 
 def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget=0, group=0,
-          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0):
+          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0, dv_max=0.0):
     return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group, trace_lanes,
-                      padded_trace_budget, walk, dtau_max, max_substeps)
+                      padded_trace_budget, walk, dtau_max, max_substeps, dv_max)
 
 
 def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
           precision: int = RT_F32, schedule: int = SCHED_DIRECT, dtau_fp64_below: float = 1e-4,
           waves_per_cu: int = 0, n_bins: int = 0, group: int = 0, want_u: bool = False, dtau_max: float = 0.0,
-          max_substeps: int = 0, stream=None):
+          max_substeps: int = 0, dv_max: float = 0.0, stream=None):
     """J [n_o][F] (dtype of the precision) from ray lists; optionally u [n_o][R][F].  dtau_max > 0
     splits line intervals into optical-depth sub-steps (rt_solve_opts.dtau_max)."""
     torch = _torch()
@@ -324,7 +325,7 @@ def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc,
     R = dirset.R
     g, keep = _grid(freq_len, freq_dx)
     o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group=group, dtau_max=dtau_max,
-              max_substeps=max_substeps)
+              max_substeps=max_substeps, dv_max=dv_max)
     u = torch.empty((n_origins, R, F), dtype=dt, device=chi.device) if want_u else None
     wsb = _sz()
     _check(L.rt_solve_workspace(dirset._h, n_origins, F, C.byref(o), C.byref(wsb)))
@@ -377,7 +378,7 @@ class Plan:
                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT,
                  dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0,
                  padded_trace_budget: int = 0, group: int = 0, trace_lanes: int = 0, walk: int = WALK_EXACT,
-                 dtau_max: float = 0.0, max_substeps: int = 0, stream=None):
+                 dtau_max: float = 0.0, max_substeps: int = 0, dv_max: float = 0.0, stream=None):
         torch = _torch()
         dt = torch.float64 if precision == RT_F64 else torch.float32
         self.chi, self.eta, self.J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
@@ -391,7 +392,7 @@ class Plan:
         self.model, self.dirset = model, dirset
         g, self._keep = _grid(freq_len, freq_dx)
         o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes,
-                  walk, dtau_max, max_substeps)
+                  walk, dtau_max, max_substeps, dv_max)
         h = _vp()
         _check(load().rt_plan_create(model._h, dirset._h, _ptr(origins), n_origins, _ptr(self.chi),
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),

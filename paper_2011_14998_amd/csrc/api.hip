@@ -337,6 +337,7 @@ static rt_solve_opts default_opts() {
     o.walk = RT_WALK_EXACT;
     o.dtau_max = 0.0;
     o.max_substeps = 0;
+    o.dv_max = 0.0;
     return o;
 }
 
@@ -375,6 +376,7 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
         if (grid->len[b] <= 0 || !(grid->dx[b] > 0.0)) return fail(RT_ERR_ARG, "solve: block lengths and dx must be > 0");
         a.blk_start[b] = (int32_t)F;
         a.inv_dx[b] = 1.0 / grid->dx[b];
+        a.dx[b] = grid->dx[b];
         F += grid->len[b];
     }
     for (int b = grid->n_blocks; b <= RT_MAX_FREQ_BLOCKS; ++b) a.blk_start[b] = (int32_t)F;
@@ -403,8 +405,10 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.I_bc = I_bc;
     a.J = J;
     a.dtau_fp64_below = o.dtau_fp64_below;
-    if (!(o.dtau_max >= 0.0) || o.max_substeps < 0) return fail(RT_ERR_ARG, "solve: dtau_max and max_substeps must be >= 0");
+    if (!(o.dtau_max >= 0.0) || !(o.dv_max >= 0.0) || o.max_substeps < 0)
+        return fail(RT_ERR_ARG, "solve: dtau_max, dv_max and max_substeps must be >= 0");
     a.dtau_max_rcp = o.dtau_max > 0.0 ? 1.0 / o.dtau_max : 0.0;
+    a.dv_max_rcp = o.dv_max > 0.0 && m->vel ? 1.0 / o.dv_max : 0.0;
     a.max_sub = o.max_substeps > 0 ? o.max_substeps : 1024;
     a.schedule = o.schedule;
     a.n_bins = opts_bins(o);

@@ -142,12 +142,14 @@ struct SolveLaunch {
     int32_t n_blocks;
     int32_t blk_start[RT_MAX_FREQ_BLOCKS + 1];
     double inv_dx[RT_MAX_FREQ_BLOCKS];
+    double dx[RT_MAX_FREQ_BLOCKS];
     const float* vel;
     const double* I_bc;
     void* u;
     void* J;
     double dtau_fp64_below;
     double dtau_max_rcp;   // 1/dtau_max (adaptive optical-depth increments), 0 = off
+    double dv_max_rcp;     // 1/dv_max (adaptive velocity sampling), 0 = off
     int32_t max_sub;       // cap on the sub-steps of one interval
     // scheduling
     int32_t schedule;

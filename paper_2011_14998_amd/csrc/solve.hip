@@ -79,6 +79,7 @@ struct LaneFreq {
     int L;       // length of the block
     int fl;      // index inside the block
     double inv_dx;
+    double dx;
 };
 
 __device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) {
@@ -91,18 +92,20 @@ __device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) {
     for (int bb = 1; bb < RT_MAX_FREQ_BLOCKS; ++bb)
         if (bb < a.n_blocks && lf.f >= a.blk_start[bb]) b = bb;
     int fb = a.blk_start[0], nb = a.blk_start[1];
-    double idx = a.inv_dx[0];
+    double idx = a.inv_dx[0], dxb = a.dx[0];
 #pragma unroll
     for (int bb = 1; bb < RT_MAX_FREQ_BLOCKS; ++bb)
         if (bb == b) {
             fb = a.blk_start[bb];
             nb = a.blk_start[bb + 1];
             idx = a.inv_dx[bb];
+            dxb = a.dx[bb];
         }
     lf.fb = fb;
     lf.L = nb - fb;
     lf.fl = lf.f - fb;
     lf.inv_dx = idx;
+    lf.dx = dxb;
     return lf;
 }
 
@@ -270,27 +273,47 @@ struct ItemCtx {
     float vox, voy, voz;
     float thr;
     double dtau_rcp;   // adaptive optical-depth increments: 1/dtau_max
+    double dv_rcp;     // adaptive velocity sampling: 1/dv_max
+    double dx0;        // width of the first block's frequency step
+    int64_t row_o;     // the origin's table row offset in bytes
     int max_sub;
 };
 
-// Adaptive optical-depth increments (Section 2.1.2, eq. 2) for the interval
-// from the far point (chi cf, eta ef, S Sf) to the near point (cn, en) of one
-// side of the line; hds is half the interval's length.  The split count
-// n = ceil(max(chi'_far, chi'_near) ds / dtau_max), clamped to 1 .. max_sub, is
-// decided in FP64 from chi' evaluated as (1-t) chi_a + t chi_b from the point's
-// two table values and shift fraction (Pt64) and the FP64 length ds64, so every
-// precision takes the same decision.  When the kernel-precision estimate is
-// below 1 - 1e-4 in every lane (it is within a few ulps of the FP64 value), n is
-// 1 everywhere and the FP64 evaluation is skipped.  The n-1 interior points
-// interpolate chi' and eta' linearly from the far point; rows are emitted far
-// to near, each with its inner step, the last being the sub-point next to the
-// near point.  `first` marks the far end of the line (its row is the boundary row).
+// ---------------------------------------------------------------- refined lines
+// Adaptive velocity sampling (Section 2.1.1) and adaptive optical-depth
+// increments (Section 2.1.2, eq. 2) generate extra line points on the fly,
+// between consecutive points of a ray list, in registers.
+//
+// Both split counts are integers decided from floating point, so they are
+// decided in FP64 with the oracle's arithmetic: the projected velocities
+// p = n.(v - v_o), the shift p/dx (a division), chi' of a point as
+// (1-w)((1-t) a0 + t a1) + w((1-t) b0 + t b1) from its table values (a: the
+// end point of smaller line coordinate, b: the other; w = 0 for a point of
+// the list), lengths ds and ds/m, and the products with the reciprocals of the
+// bounds.  The optics that enter the solve are computed in the kernel's
+// precision.
+
+// What the FP64 split decision needs of a line point.
 template <typename T>
 struct Pt64 {
-    T ca, cb;    // table values at rows f - k and f - k - 1
-    double t;    // shift fraction
+    T a0, a1, b0, b1;  // table values: end points a and b at rows f - k and f - k - 1
+    double t, w;       // shift fraction, weight of b
 };
 
+template <typename T>
+__device__ inline double chi64(const Pt64<T>& p) {
+    return (1.0 - p.w) * ((1.0 - p.t) * (double)p.a0 + p.t * (double)p.a1) +
+           p.w * ((1.0 - p.t) * (double)p.b0 + p.t * (double)p.b1);
+}
+
+// Interval from the far point (chi cf, eta ef, S Sf) to the near point (cn, en)
+// of one side: n = ceil(max(chi'_far, chi'_near) ds / dtau_max), clamped to
+// 1 .. max_sub; hds is half the interval's length.  When the kernel-precision
+// estimate is below 1 - 1e-4 in every lane (it is within a few ulps of the FP64
+// value) n is 1 everywhere and the FP64 evaluation is skipped.  The n-1
+// interior points interpolate chi' and eta' linearly; rows are emitted far to
+// near, each with its inner step, the last being the sub-point next to the near
+// point.  `first` marks the far end of the line (its row is the boundary row).
 template <typename T>
 __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
                                         T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I) {
@@ -299,8 +322,7 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
         row_policy<T>(st, first, (cf + cn) * hds, Sf, I, c.thr);
         return;
     }
-    const double c64f = (1.0 - pf.t) * (double)pf.ca + pf.t * (double)pf.cb;
-    const double c64n = (1.0 - pn.t) * (double)pn.ca + pn.t * (double)pn.cb;
+    const double c64f = chi64(pf), c64n = chi64(pn);
     const double cm = c64f > c64n ? c64f : c64n;
     double q = ceil((cm * ds64) * c.dtau_rcp);
     if (q > (double)c.max_sub) q = (double)c.max_sub;
@@ -323,6 +345,174 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
     row_policy<T>(st, fr, (cp + cn) * hh, Sp, I, c.thr);
 }
 
+// The stream of line points of one side, far to near, after velocity sampling.
+template <typename T>
+struct Emitter {
+    T c, e, S;
+    Pt64<T> p;
+    bool first = true;  // no row emitted yet: the next one is the boundary row
+    bool have = false;
+};
+
+// Emit the next line point; the interval from the previous one (half length
+// hds, FP64 length ds64) is split by optical depth when that is on.
+template <typename T>
+__device__ inline void emit_point(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, T cn, T en, T Sn,
+                                  const Pt64<T>& pn, T hds, double ds64, T I) {
+    if (em.have) {
+        if (c.dtau_rcp > 0.0) substep_interval<T>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I);
+        else row_policy<T>(st, em.first, (em.c + cn) * hds, em.S, I, c.thr);
+        em.first = false;
+    }
+    em.c = cn;
+    em.e = en;
+    em.S = Sn;
+    em.p = pn;
+    em.have = true;
+}
+
+// A list point (real) of the current side, as the refinement needs it.
+template <typename T>
+struct RealPt {
+    T c, e, S;
+    Pt64<T> p;
+    double dot;   // projected velocity n.(v - v_o)
+    int64_t row;  // table row offset in bytes
+};
+
+// Interval from real point P (far) to real point C (near), hds / ds64 its half
+// and FP64 lengths: velocity sub-points first (m from |p_C - p_P|), each emitted,
+// then C itself.  fwd: this side is the +n ray, whose nearer point has the
+// smaller line coordinate (so it is the interval's point a).
+template <typename T, bool UDX>
+__device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, const RealPt<T>& P,
+                                     const RealPt<T>& C, T hds, double ds64, bool fwd, const LaneFreq& lf, T I) {
+    int m = 1;
+    if (c.dv_rcp > 0.0) {
+        double q = ceil(fabs(C.dot - P.dot) * c.dv_rcp);
+        if (q > (double)c.max_sub) q = (double)c.max_sub;
+        m = q >= 1.0 ? (int)q : 1;
+        m = __builtin_amdgcn_readfirstlane(m);  // the same in every lane
+    }
+    if (m == 1) {
+        emit_point<T>(c, st, em, C.c, C.e, C.S, C.p, hds, ds64, I);
+        return;
+    }
+    const T hs = hds * rcp<T>((T)m);
+    const double ds64s = ds64 / (double)m;
+    const RealPt<T>& A = fwd ? C : P;  // the end point of smaller line coordinate
+    const RealPt<T>& B = fwd ? P : C;
+    const double dx = UDX ? c.dx0 : lf.dx;
+    const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
+    const int lo_bytes = lf.fb * (int)sizeof(T);
+    const int hi_bytes = (lf.fb + lf.L - 1) * (int)sizeof(T);
+    for (int jj = 1; jj < m; ++jj) {  // far to near
+        const int jo = fwd ? m - jj : jj;
+        const double w = (double)jo / (double)m;
+        const double vdot = (1.0 - w) * A.dot + w * B.dot;
+        const double delta = vdot / dx;
+        const double kf = floor(delta);
+        const int k = (int)kf;
+        const double t64 = delta - kf;
+        const T t = (T)t64;
+        const int ks = k * (int)sizeof(T);
+        const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
+        const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
+        const T a0 = *(const T*)(c.chi + A.row + oa), a1 = *(const T*)(c.chi + A.row + ob);
+        const T b0 = *(const T*)(c.chi + B.row + oa), b1 = *(const T*)(c.chi + B.row + ob);
+        const T g0 = *(const T*)(c.eta + A.row + oa), g1 = *(const T*)(c.eta + A.row + ob);
+        const T h0 = *(const T*)(c.eta + B.row + oa), h1 = *(const T*)(c.eta + B.row + ob);
+        const T wt = (T)w;
+        const T xa = fma_<T>(t, a1 - a0, a0), xb = fma_<T>(t, b1 - b0, b0);
+        const T ya = fma_<T>(t, g1 - g0, g0), yb = fma_<T>(t, h1 - h0, h0);
+        const T cv = fma_<T>(wt, xb - xa, xa);
+        const T ev = fma_<T>(wt, yb - ya, ya);
+        emit_point<T>(c, st, em, cv, ev, ev * rcp<T>(cv), Pt64<T>{a0, a1, b0, b1, t64, w}, hs, ds64s, I);
+    }
+    emit_point<T>(c, st, em, C.c, C.e, C.S, C.p, hs, ds64s, I);
+}
+
+// One side of the line with velocity sampling and/or optical-depth sub-steps
+// (the plain sweep below is the same without them).
+template <typename T, bool MOVING, bool UDX>
+__device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, bool fwd,
+                                 T chi_o, T eta_o, T S_o, T I, SweepState<T>& st) {
+    Emitter<T> em;
+    RealPt<T> prev{};
+    T hds_prev = (T)0;
+    double ds64_prev = 0.0;
+    int done = 0;
+    const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
+    const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
+    const int lo_bytes = lf.fb * (int)sizeof(T);
+    const int hi_bytes = (lf.fb + lf.L - 1) * (int)sizeof(T);
+    for (int hi = n - 1; hi >= 0; hi -= 64) {
+        const int cnt = hi + 1 < 64 ? hi + 1 : 64;
+        const int e = hi - lane;
+        const bool v = lane < cnt;
+        int64_t row_l = 0;
+        double ds64_l = 0.0, dot_l = 0.0;
+        if (v) {
+            const int q = c.ids[base + e];
+            row_l = (int64_t)q * c.ld_bytes;
+            const double z = c.Zr[base + e];
+            const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
+            ds64_l = z - zi;
+            if (MOVING) {
+                const float* vq = c.vel + 3 * (int64_t)q;
+                const double dvx = (double)vq[0] - (double)c.vox;
+                const double dvy = (double)vq[1] - (double)c.voy;
+                const double dvz = (double)vq[2] - (double)c.voz;
+                dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
+            }
+        }
+        for (int j = 0; j < cnt; ++j) {
+            RealPt<T> cur;
+            cur.row = readlane_64(row_l, j);
+            cur.dot = MOVING ? readlane_d(dot_l, j) : 0.0;
+            const double ds64 = readlane_d(ds64_l, j);
+            const char* cr = c.chi + cur.row;
+            const char* er = c.eta + cur.row;
+            if (MOVING) {
+                const double delta = cur.dot / (UDX ? c.dx0 : lf.dx);
+                const double kf = floor(delta);
+                const int k = (int)kf;
+                const double t64 = delta - kf;
+                const T t = (T)t64;
+                const int ks = k * (int)sizeof(T);
+                const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
+                const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
+                const T ca = *(const T*)(cr + oa), cb = *(const T*)(cr + ob);
+                const T ea = *(const T*)(er + oa), eb = *(const T*)(er + ob);
+                cur.c = fma_<T>(t, cb - ca, ca);
+                cur.e = fma_<T>(t, eb - ea, ea);
+                cur.p = Pt64<T>{ca, cb, ca, cb, t64, 0.0};
+            } else {
+                cur.c = *(const T*)(cr + lane_off);
+                cur.e = *(const T*)(er + lane_off);
+                cur.p = Pt64<T>{cur.c, cur.c, cur.c, cur.c, 0.0, 0.0};
+            }
+            cur.S = cur.e * rcp<T>(cur.c);
+            if (done == 0) emit_point<T>(c, st, em, cur.c, cur.e, cur.S, cur.p, (T)0, 0.0, I);
+            else real_interval<T, UDX>(c, st, em, prev, cur, hds_prev, ds64_prev, fwd, lf, I);
+            prev = cur;
+            ds64_prev = ds64;
+            hds_prev = (T)0.5 * (T)ds64;
+            ++done;
+        }
+    }
+    if (n > 0) {
+        RealPt<T> org;
+        org.c = chi_o;
+        org.e = eta_o;
+        org.S = S_o;
+        org.p = Pt64<T>{chi_o, chi_o, chi_o, chi_o, 0.0, 0.0};
+        org.dot = 0.0;
+        org.row = c.row_o;
+        real_interval<T, UDX>(c, st, em, prev, org, hds_prev, ds64_prev, fwd, lf, I);
+    }
+}
+
 // Eliminate one side of the line (entries base .. base+n-1 of a ray list,
 // walked from the far end inwards), up to the origin; on return st holds the
 // row next to the origin and st.a the step between that row and the origin.
@@ -333,13 +523,10 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
 // GROUP line points have their loads issued together before the recurrence
 // consumes them (a tuning parameter: more points in flight per wave against
 // more registers, i.e. fewer waves).
-// SUB: adaptive optical-depth increments between consecutive points.
-template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
-__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T eta_o,
-                             T I, SweepState<T>& st) {
-    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0, e_prev = (T)0;
-    Pt64<T> p_prev{(T)0, (T)0, 0.0};
-    double ds64_prev = 0.0;
+template <typename T, bool MOVING, bool UDX, int GROUP>
+__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
+                             SweepState<T>& st) {
+    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
@@ -354,14 +541,13 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
         int q_l = 0, k_l = 0;
         int64_t row_l = 0;
         T ds_l = (T)0, t_l = (T)0;
-        double dot_l = 0.0, t64_l = 0.0, ds64_l = 0.0;
+        double dot_l = 0.0;
         if (v) {
             q_l = c.ids[base + e];
             row_l = (int64_t)q_l * c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
-            ds64_l = z - zi;
-            ds_l = (T)0.5 * (T)ds64_l;  // half the difference of FP64 projections, rounded once
+            ds_l = (T)0.5 * (T)(z - zi);  // half the difference of FP64 projections, rounded once
             if (MOVING) {
                 const float* vq = c.vel + 3 * (int64_t)q_l;
                 const double dvx = (double)vq[0] - (double)c.vox;
@@ -369,17 +555,15 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                 const double dvz = (double)vq[2] - (double)c.voz;
                 dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
                 if (UDX) {
-                    const double delta = dot_l * c.inv_dx0;
+                    const double delta = dot_l / c.dx0;
                     const double kf = floor(delta);
                     k_l = (int)kf;
-                    t64_l = delta - kf;
-                    t_l = (T)t64_l;
+                    t_l = (T)(delta - kf);
                 }
             }
         }
         for (int j = 0; j < cnt; j += GROUP) {
             T ca[GROUP], cb[GROUP], ea[GROUP], eb[GROUP], tt[GROUP], dsv[GROUP];
-            double t64[GROUP], ds64v[GROUP];
 #pragma unroll
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
@@ -387,22 +571,17 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     const char* cr = c.chi + row;
                     const char* er = c.eta + row;
                     dsv[g] = readlane_t<T>(ds_l, j + g);
-                    if (SUB) ds64v[g] = readlane_d(ds64_l, j + g);
                     if (MOVING) {
                         int k;
                         T t;
                         if (UDX) {
                             k = readlane_i(k_l, j + g);
                             t = readlane_t<T>(t_l, j + g);
-                            if (SUB) t64[g] = readlane_d(t64_l, j + g);
-                        } else {
-                            // the oracle divides by dx_b; the product with its reciprocal can
-                            // differ in the last bit, which only moves t by an ulp
-                            const double delta = readlane_d(dot_l, j + g) * lf.inv_dx;
+                        } else {  // per-lane block widths: the shift as the oracle forms it, a division
+                            const double delta = readlane_d(dot_l, j + g) / lf.dx;
                             const double kf = floor(delta);
                             k = (int)kf;
                             t = (T)(delta - kf);
-                            if (SUB) t64[g] = delta - kf;
                         }
                         // byte offsets of rows fl - k and fl - k - 1, clamped to the block
                         const int ks = k * (int)sizeof(T);
@@ -423,51 +602,33 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
             for (int g = 0; g < GROUP; ++g) {
                 if (j + g < cnt) {
                     T cc, et;
-                    Pt64<T> pc{(T)0, (T)0, 0.0};
                     if (MOVING) {
                         cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
                         et = fma_<T>(tt[g], eb[g] - ea[g], ea[g]);
-                        if (SUB) pc = Pt64<T>{ca[g], cb[g], t64[g]};
                     } else {
                         cc = ca[g];
                         et = ea[g];
-                        if (SUB) pc = Pt64<T>{ca[g], ca[g], 0.0};
                     }
                     const T S = et * rcp<T>(cc);
                     if (done > 0) {
-                        if (SUB) {
-                            substep_interval<T>(c, st, done == 1, c_prev, e_prev, S_prev, cc, et, ds_prev, p_prev, pc,
-                                                ds64_prev, I);
-                        } else {
-                            const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
-                            row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
-                        }
+                        const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
+                        row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
                     }
                     c_prev = cc;
                     S_prev = S;
                     ds_prev = dsv[g];
-                    if (SUB) {
-                        e_prev = et;
-                        p_prev = pc;
-                        ds64_prev = ds64v[g];
-                    }
                     ++done;
                 }
             }
         }
     }
     if (n > 0) {
-        if (SUB) {
-            substep_interval<T>(c, st, n == 1, c_prev, e_prev, S_prev, chi_o, eta_o, ds_prev, p_prev,
-                                Pt64<T>{chi_o, chi_o, 0.0}, ds64_prev, I);
-        } else {
-            const T dt = (c_prev + chi_o) * ds_prev;
-            row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
-        }
+        const T dt = (c_prev + chi_o) * ds_prev;
+        row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane) {
     // w is the same in every lane of the wave
     w = uni64(w);
@@ -497,6 +658,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     c.ny = dv[1];
     c.nz = dv[2];
     c.inv_dx0 = a.inv_dx[0];
+    c.dx0 = a.dx[0];
     c.vox = c.voy = c.voz = 0.f;
     if (MOVING) {
         c.vox = a.vel[3 * o];
@@ -505,14 +667,21 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
     c.thr = (float)a.dtau_fp64_below;
     c.dtau_rcp = a.dtau_max_rcp;
+    c.dv_rcp = a.dv_max_rcp;
     c.max_sub = a.max_sub;
+    c.row_o = o * c.ld_bytes;
     const T I = (T)a.I_bc[lf.f];
     const T chi_o = ((const T*)a.chi)[o * a.ld + lf.f];
     const T eta_o = ((const T*)a.eta)[o * a.ld + lf.f];
     const T S_o = eta_o * rcp<T>(chi_o);
     SweepState<T> m{}, p{};
-    sweep<T, MOVING, UDX, GROUP, SUB>(c, bm, nm, lf, lane, chi_o, eta_o, I, m);
-    sweep<T, MOVING, UDX, GROUP, SUB>(c, bp, np, lf, lane, chi_o, eta_o, I, p);
+    if (REF) {
+        sweep_ref<T, MOVING, UDX>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m);
+        sweep_ref<T, MOVING, UDX>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p);
+    } else {
+        sweep<T, MOVING, UDX, GROUP>(c, bm, nm, lf, lane, chi_o, I, m);
+        sweep<T, MOVING, UDX, GROUP>(c, bp, np, lf, lane, chi_o, I, p);
+    }
     const T u = origin_policy<T>(nm > 0, np > 0, m, p, S_o, I, c.thr);
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
@@ -520,7 +689,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -537,14 +706,14 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
         }
-        solve_item<T, MOVING, UDX, GROUP, SUB>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane);
     }
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
 // takes the next item with one atomic and exits when the queue is empty, so
 // every wave reaches the end.
-template <typename T, bool MOVING, bool UDX, int GROUP, bool SUB>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
@@ -555,7 +724,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX, GROUP, SUB>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane);
     }
 }
 
@@ -670,13 +839,13 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
-template <typename T, int G, bool SUB>
+template <typename T, int G, bool REF>
 static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     const bool moving = a.vel != nullptr;
     // the shift of a point is lane-independent when every block has the same dx
     bool udx = true;
     for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
-#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, SUB>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, REF>), grid, dim3(SOLVE_BLOCK), 0, s, a)
     if (persist) {
         if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
         else if (moving) RT_LAUNCH(k_solve_persist, true, false);
@@ -691,8 +860,8 @@ static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipS
 
 template <typename T>
 static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
-    // optical-depth sub-steps are built with load group 4 only
-    if (a.dtau_max_rcp > 0.0) solve_dispatch_g<T, 4, true>(a, persist, grid, s);
+    // refined lines (velocity sampling, optical-depth sub-steps) take their own sweep
+    if (a.dtau_max_rcp > 0.0 || a.dv_max_rcp > 0.0) solve_dispatch_g<T, 4, true>(a, persist, grid, s);
     else if (a.group == 4) solve_dispatch_g<T, 4, false>(a, persist, grid, s);
     else solve_dispatch_g<T, 8, false>(a, persist, grid, s);
 }

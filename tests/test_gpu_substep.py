@@ -1,7 +1,8 @@
-"""GPU parity of the adaptive optical-depth increments (Section 2.1.2, eq. 2)
-against the oracle: FP64 within 1e-12 and FP32 within 1e-4 relative, split
-counts decided identically on both sides; a bound above every interval leaves
-the sweep bit-identical to the unsplit one; the cap on sub-steps is honoured."""
+"""GPU parity of the refined lines -- adaptive optical-depth increments (Section
+2.1.2, eq. 2) and adaptive velocity sampling (Section 2.1.1) -- against the
+oracle: FP64 within 1e-12 and FP32 within 1e-4 relative, split counts decided
+identically on both sides; bounds that split nothing leave the sweep
+bit-identical to the plain one; the cap on sub-steps is honoured."""
 import numpy as np
 import pytest
 
@@ -124,3 +125,58 @@ def test_substep_plan_graph(rt, orc):
         plan.run(use_graph=True)
         rt.sync_status()
         assert np.array_equal(J.cpu().numpy(), ref)
+
+
+# ----------------------------------------------------------------------------- velocity sampling (Section 2.1.1)
+
+@pytest.mark.parametrize("case,dv_max,dtau_max", [("tiny", 0.3, 0.0), ("tiny", 0.25, 0.2),
+                                                  ("two_blocks", 0.4, 0.0), ("two_blocks", 0.2, 0.15)])
+def test_velocity_sampling_parity(rt, orc, case, dv_max, dtau_max):
+    if case == "tiny":
+        m, nside = synth.tiny_model(61, P=60, F=12, moving=True), 2
+        m.chi, m.eta = m.chi * 2.0, m.eta * 2.0
+    else:  # per-lane shifts: blocks of different widths
+        m, nside = synth.tiny_model(62, P=50, F=20, moving=True), 1
+        m.freq = synth.FreqGrid(np.array([12, 8], np.int32), np.array([-3.0, -2.0]), np.array([0.5, 0.6]))
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    model, ds, dirs, w2, oo, org, rays = _setup(rt, orc, m, nside, None)
+    Je, ue = orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64, want_u=True, dv_max=dv_max,
+                           dtau_max=dtau_max)
+    assert _rel(orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64, dtau_max=dtau_max), Je) > 1e-6
+    J64, u64 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F64, c64, e64, dv_max=dv_max, dtau_max=dtau_max,
+                    want_u=True)
+    rt.sync_status()
+    assert _rel(u64.cpu().numpy(), ue) <= TOL64
+    J32 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F32, c32, e32, dv_max=dv_max, dtau_max=dtau_max)
+    err = _rel(J32.cpu().numpy().astype(np.float64), Je)
+    print(f"{case} dv {dv_max} dtau {dtau_max}: fp32 max rel {err:.2e}")
+    assert err <= TOL32
+
+
+def test_velocity_sampling_wind(rt, orc):
+    """The wind's radial flow reaches 20 Doppler widths: rays crossing it get sampled."""
+    m = synth.wind_model(P=20_000)
+    rng = np.random.default_rng(4)
+    origins = rng.choice(m.P, 120, replace=False)
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    model, ds, dirs, w2, oo, org, rays = _setup(rt, orc, m, 2, origins)
+    Je = orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64, dv_max=1.0 / 3.0, dtau_max=0.5)
+    J64 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F64, c64, e64, dv_max=1.0 / 3.0, dtau_max=0.5)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    J32 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F32, c32, e32, dv_max=1.0 / 3.0, dtau_max=0.5)
+    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
+    rt.sync_status()
+
+
+def test_refined_path_without_splits_is_bit_identical(rt, orc):
+    """Bounds that split nothing: the refined sweep gives the plain sweep's bits."""
+    for seed, blocks in ((63, False), (64, True)):
+        m = synth.tiny_model(seed, P=50, F=12, moving=True)
+        if blocks:
+            m.freq = synth.FreqGrid(np.array([7, 5], np.int32), np.array([-3.0, -1.0]), np.array([0.5, 0.7]))
+        c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+        model, ds, dirs, w2, oo, org, rays = _setup(rt, orc, m, 2, None)
+        for prec, (c, e) in ((rt.RT_F64, (c64, e64)), (rt.RT_F32, (c32, e32))):
+            J0 = _gpu(rt, m, model, ds, rays, org, len(oo), prec, c, e).cpu().numpy()
+            J1 = _gpu(rt, m, model, ds, rays, org, len(oo), prec, c, e, dv_max=1e9, dtau_max=1e9).cpu().numpy()
+            assert np.array_equal(J0, J1)
