@@ -387,6 +387,21 @@ rt_status rt_closure_merge(const float* J_fine, const int32_t* flagged, int64_t 
 rt_status rt_spatial_order(const rt_model* model, const int32_t* origins, int64_t n_origins, int32_t* order,
                            void* stream);
 
+/* ------------------------------------------------------------------ re-meshing indicators
+ * For a tracer f (device f64 [P], > 0) on the model's points (Section 2.2.2):
+ *   Gf_i  = max over neighbours n of |(f_i - f_n)/(f_i + f_n)|      (eq. 6, in [0, 1])
+ *   L_i   = mean over neighbours n of |x_i - x_n|                    (eq. 8)
+ *   ell_i = L_i f_small if Gf_i >= G_thres, else L_i f_large         (eq. 7)
+ * The paper's parameters (Table 1): AMR f_small 0.90, f_large 2.10, G_thres 0.10;
+ * SPH 1.00, 2.15, 0.21.  Gf, L, ell: device f64 [P], each may be NULL.  Async. */
+rt_status rt_mesh_indicators(const rt_model* model, const double* f, double f_small, double f_large,
+                             double G_thres, double* Gf, double* L, double* ell, void* stream);
+
+/* Ring-scheme HEALPix pixel (Section 2.1.3) of each of n host directions
+ * dirs[n][3] (any length) at resolution nside (a power of two up to 2^13), on
+ * the host, with the same fixed arithmetic the adaptive sets use. */
+rt_status rt_healpix_vec2pix(int32_t nside, const double* dirs, int64_t n, int64_t* pix);
+
 /* Synchronise `stream` and return the error latched by kernels since the last
  * call (RT_ERR_CAPACITY; RT_ERR_NONFINITE; RT_ERR_ARG for an origin id outside
  * 0 .. P-1, whose rays are then empty and whose J row is undefined), then

@@ -9,6 +9,7 @@ no GPU is present, the calls raise.
 from .binding import (  # noqa: F401
     RT_F32,
     RT_F64,
+    REDUCTION_PARAMS,
     SCHED_BINNED,
     SCHED_DIRECT,
     SCHED_SPATIAL,
@@ -28,7 +29,9 @@ from .binding import (  # noqa: F401
     closure_normalize,
     closure_targets,
     compute_J,
+    healpix_vec2pix,
     load,
+    mesh_indicators,
     mlp_nll,
     solve,
     spatial_order,

@@ -86,6 +86,8 @@ _SIGS = {
     "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rt_plan_copy_u": (_i32, [_vp, _vp, _vp]),
     "rt_spatial_order": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "rt_mesh_indicators": (_i32, [_vp, _vp, _dbl, _dbl, _dbl, _vp, _vp, _vp, _vp]),
+    "rt_healpix_vec2pix": (_i32, [_i32, _vp, _i64, _vp]),
     "rt_closure_feature_stats": (_i32, [_vp, _i64, _vp, _vp, _vp]),
     "rt_closure_normalize": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "rt_closure_apply": (_i32, [_vp, _vp, _i64, _i64, C.c_float, _vp, _vp, _vp, _vp]),
@@ -634,3 +636,28 @@ def closure_targets(J1, J_fine, T=None, stream=None):
     _check(load().rt_closure_targets(_ptr(J1), _ptr(J_fine), J1.numel(), _ptr(_dev(T, torch.float32)),
                                      _stream(stream)))
     return T
+
+
+# ---------------------------------------------------------------- re-meshing indicators
+
+# The paper's reduction parameters (Table 1): (f_small, f_large, G_thres)
+REDUCTION_PARAMS = {"AMR": (0.90, 2.10, 0.10), "SPH": (1.00, 2.15, 0.21)}
+
+
+def mesh_indicators(model: Model, f, f_small: float, f_large: float, G_thres: float, stream=None):
+    """(Gf, L, ell) device f64 [P] for the tracer f (device f64 [P]); see rt_mesh_indicators."""
+    torch = _torch()
+    f = _dev(f, torch.float64)
+    P = model.P
+    Gf, L, ell = (torch.empty(P, dtype=torch.float64, device=f.device) for _ in range(3))
+    _check(load().rt_mesh_indicators(model._h, _ptr(f), float(f_small), float(f_large), float(G_thres), _ptr(Gf),
+                                     _ptr(L), _ptr(ell), _stream(stream)))
+    return Gf, L, ell
+
+
+def healpix_vec2pix(nside: int, dirs) -> np.ndarray:
+    """Ring-scheme pixels of host directions [n][3] at resolution nside."""
+    d = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.empty(len(d), np.int64)
+    _check(load().rt_healpix_vec2pix(int(nside), d.ctypes.data, len(d), out.ctypes.data))
+    return out

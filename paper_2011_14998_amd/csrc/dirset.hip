@@ -337,3 +337,11 @@ extern "C" rt_status rt_dirset_adaptive(const rt_model* model, int32_t lmin, int
     *out = set;
     return RT_OK;
 }
+
+extern "C" rt_status rt_healpix_vec2pix(int32_t nside, const double* dirs, int64_t n, int64_t* pix) {
+    if (nside < 1 || (nside & (nside - 1)) || nside > (1 << RT_MAX_LEVEL))
+        return rt::fail(RT_ERR_UNSUPPORTED, "rt_healpix_vec2pix: nside must be a power of two up to 2^13");
+    if (n < 0 || (n > 0 && (!dirs || !pix))) return rt::fail(RT_ERR_ARG, "rt_healpix_vec2pix: bad arguments");
+    for (int64_t i = 0; i < n; ++i) pix[i] = rt::fx_vec2pix(nside, dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]);
+    return RT_OK;
+}

@@ -116,3 +116,16 @@ def test_workspace_queries(lib):
     o = lib.SolveOptsC(lib.RT_F64, lib.SCHED_BINNED, 1e-4, 0, 0, 0, 0, 0)
     assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
     assert sz.value >= 1000 * 24 * 64 * 8 + 1000 * 24 * 4
+
+
+def test_healpix_lookup_matches_oracle(orc):
+    """Host-side pixel lookup of the library against the oracle's (no GPU needed)."""
+    import paper_2011_14998_amd as rt
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(3000, 3))
+    for nside in (1, 2, 4, 16, 64):
+        got = rt.healpix_vec2pix(nside, d)
+        want = np.array([orc.hp_vec2pix(nside, v) for v in d])
+        assert np.sum(got != want) <= 1  # only directions within ~1e-15 of a boundary may differ
+    with pytest.raises(rt.RtError):
+        rt.healpix_vec2pix(3, d[:1])
