@@ -181,14 +181,16 @@ def main():
     ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial",
                     help="plan schedule when the autotuner is skipped")
     ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
-    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure", "precision"],
+    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure", "precision",
+                                           "directions"],
                     default="wind",
                     help="wind: the headline 50k-point wind (default); octree: ~500k-leaf AMR-like cloud, 2x48 "
                          "frequencies; octree_reduced: the same field with ~50k leaves; sph_batch: 64 SPH-like "
                          "clouds as one disjoint union (size scaled by --batch-scale); closure: the learned "
                          "closure trained on winds of seeds 500-503 and judged on 510-511 against the plain "
                          "nside-8 solve (--closure-points each); precision: the FP32 sweep's error against the "
-                         "FP64 oracle, model by model")
+                         "FP64 oracle, model by model; directions: adaptive (l 1..4) against regular nside-16 "
+                         "directions on the AMR-like cloud")
     ap.add_argument("--batch-scale", type=float, default=0.25)
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner and use the library defaults")
     ap.add_argument("--nside", type=int, default=0, help="HEALPix nside (0 = the workload's own)")
@@ -248,6 +250,9 @@ def main():
         return
     if args.workload == "precision":
         run_precision(args)
+        return
+    if args.workload == "directions":
+        run_directions(args)
         return
 
     t_gen = time.perf_counter()
@@ -421,6 +426,87 @@ def run_precision(args):
         out.append(rec)
     print(json.dumps({"metric": "relative error of J against the FP64 oracle, per model", "per_model": out,
                       "fp64_rows_below_dtau": args.fp64_below}), flush=True)
+
+
+def run_directions(args, n_origins=1000, n_sample=10_000):
+    """Section 3.2.1's comparison on the AMR-like cloud (~50 000 leaves): the adaptive
+    set l = 1..4 (276 pairs, 552 rays, refined towards the point density seen from each
+    origin) against the regular nside-16 set (1536 pairs, 3072 rays).  Per pair: the
+    adaptive leaf containing a regular pair's direction is compared with that pair's u;
+    per point: J.  Times are plan replays of the whole path.  One JSON line."""
+    import torch
+
+    import paper_2011_14998_amd as rt
+    import synth
+
+    m = synth.octree_model(seed=3, target=50_000)
+    _log(f"AMR-like cloud: {m.P} leaves, F = {m.F}")
+    rng = np.random.default_rng(21)
+    org_h = np.sort(rng.choice(m.P, min(n_origins, m.P), replace=False)).astype(np.int32)
+    sample = rng.choice(m.P, min(n_sample, m.P), replace=False).astype(np.int32)
+    model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
+    c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+    chi, eta = torch.as_tensor(c32, device="cuda"), torch.as_tensor(e32, device="cuda")
+    I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device="cuda")
+    org = torch.as_tensor(org_h, device="cuda")
+    n_o = len(org_h)
+    reg = rt.DirSet.uniform(16)
+    ada = rt.DirSet.adaptive(model, 1, 4, torch.as_tensor(sample, device="cuda"), origins=org)
+    out = {}
+    for name, ds in (("regular", reg), ("adaptive", ada)):
+        J = torch.empty((n_o, m.F), dtype=torch.float32, device="cuda")
+        plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, origins=org, precision=rt.RT_F32,
+                       schedule=rt.SCHED_SPATIAL)
+        plan.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            plan.run()
+        e1.record()
+        e1.synchronize()
+        out[name] = dict(J=J.double().cpu().numpy(), u=plan.copy_u().double().cpu().numpy(),
+                         ms=e0.elapsed_time(e1) / 3, pairs=ds.R)
+        rt.sync_status()
+        _log(f"{name}: {ds.R} pairs, {out[name]['ms']:.2f} ms per run")
+        del plan
+    # regular pair -> adaptive leaf, per origin
+    _, _, rdirs, _ = reg.export()
+    apix, alev, _, _ = ada.export()
+    lut_pix = {}
+    for lv in range(1, 5):
+        ns = 1 << lv
+        p = rt.healpix_vec2pix(ns, rdirs)
+        q = rt.healpix_vec2pix(ns, -rdirs)
+        lut_pix[lv] = (np.minimum(p, q), 12 * ns * ns)
+    u_reg, u_ada = out["regular"]["u"], out["adaptive"]["u"]
+    errs = []
+    for o in range(n_o):
+        leaf = np.full(len(rdirs), -1, np.int64)
+        for lv in range(1, 5):
+            canon, npix = lut_pix[lv]
+            lut = np.full(npix, -1, np.int64)
+            sel = alev[o] == lv
+            lut[apix[o][sel]] = np.nonzero(sel)[0]
+            hit = lut[canon]
+            leaf = np.where((leaf < 0) & (hit >= 0), hit, leaf)
+        assert np.all(leaf >= 0)
+        errs.append(np.abs(u_ada[o][leaf] - u_reg[o]) / np.abs(u_reg[o]))
+    e = np.concatenate([x.ravel() for x in errs])
+    eJ = np.abs(out["adaptive"]["J"] - out["regular"]["J"]) / np.abs(out["regular"]["J"])
+    rec = {
+        "metric": "adaptive (l 1..4, 552 rays) vs regular (nside 16, 3072 rays) directions: ray-pair and J relative "
+                  "errors, speedup of the whole path",
+        "value": out["regular"]["ms"] / out["adaptive"]["ms"], "unit": "x (regular time / adaptive time)",
+        "n_gpus": 1, "higher_is_better": True,
+        "config": {"workload": f"AMR-like cloud, {m.P} leaves, 2x48 frequencies, {n_o} seeded origins, sample of "
+                               f"{len(sample)} points for the refinement", "origins": n_o},
+        "pairs": {"regular": out["regular"]["pairs"], "adaptive": out["adaptive"]["pairs"]},
+        "ms": {"regular": out["regular"]["ms"], "adaptive": out["adaptive"]["ms"]},
+        "pair_error_cdf": {str(t): float(np.mean(e < t)) for t in (1e-3, 1e-2, 0.1, 0.2)},
+        "J_error": {"median": float(np.median(eJ)), "p90": float(np.quantile(eJ, 0.9)), "max": float(eJ.max())},
+    }
+    print(json.dumps(rec), flush=True)
 
 
 def _gen_wind(seed_P):
