@@ -451,7 +451,8 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
         const int e = hi - lane;
         const bool v = lane < cnt;
         int64_t row_l = 0;
-        double ds64_l = 0.0, dot_l = 0.0;
+        double ds64_l = 0.0, dot_l = 0.0, t64_l = 0.0;
+        int k_l = 0;
         if (v) {
             const int q = c.ids[base + e];
             row_l = (int64_t)q * c.ld_bytes;
@@ -464,6 +465,12 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
                 const double dvy = (double)vq[1] - (double)c.voy;
                 const double dvz = (double)vq[2] - (double)c.voz;
                 dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
+                if (UDX) {  // the same shift in every lane: formed once per point while staging
+                    const double delta = dot_l / c.dx0;
+                    const double kf = floor(delta);
+                    k_l = (int)kf;
+                    t64_l = delta - kf;
+                }
             }
         }
         for (int j = 0; j < cnt; ++j) {
@@ -474,10 +481,17 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
             const char* cr = c.chi + cur.row;
             const char* er = c.eta + cur.row;
             if (MOVING) {
-                const double delta = cur.dot / (UDX ? c.dx0 : lf.dx);
-                const double kf = floor(delta);
-                const int k = (int)kf;
-                const double t64 = delta - kf;
+                int k;
+                double t64;
+                if (UDX) {
+                    k = readlane_i(k_l, j);
+                    t64 = readlane_d(t64_l, j);
+                } else {
+                    const double delta = cur.dot / lf.dx;
+                    const double kf = floor(delta);
+                    k = (int)kf;
+                    t64 = delta - kf;
+                }
                 const T t = (T)t64;
                 const int ks = k * (int)sizeof(T);
                 const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
