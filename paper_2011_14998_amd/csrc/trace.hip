@@ -62,19 +62,29 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
 
 // GL lanes (4, 8 or 16) walk one ray.  At every step lane s takes neighbours s,
 // s+GL, ... of the current point's row (contiguous records, so a group reads
-// whole cache lines; a lane's loads are issued four at a time), keeps its best
-// forward candidate together with that candidate's own CSR row (start,
+// whole cache lines; a lane's loads are issued four at a time) and keeps its
+// best forward candidate together with that candidate's own CSR row (start,
 // degree, held in the record, so the next step's loads depend on nothing
-// else), and the group reduces to the lexicographic minimum of (D, id) with
-// DPP lane permutations: (16 lanes: mirror within the row; 8 or 16: mirror
-// within the half-row), then swap neighbours, then swap pairs.  The result
-// equals a sequential scan of the row.
+// else).  The group then finds the lexicographic minimum of (D, id) in two
+// DPP reductions (the minimum D, then the smallest id among the lanes that
+// reach it; stages: mirror within the row for 16 lanes, mirror within the
+// half-row for 8 or 16, then swap neighbours, then swap pairs), and every lane
+// reads the winner's Z and row from the one lane that holds it with a ballot
+// and ds_bpermute.  The result equals a sequential scan of the row.
+//
+// List entries are buffered across the group: lane n mod GL keeps entry n, and
+// every GL steps the group stores GL consecutive ids and Z values at once, so
+// the lists are written in contiguous runs instead of one 4- and one 8-byte
+// store per step and ray.
 enum TraceMode { TRACE_COUNT = 0, TRACE_WRITE = 1, TRACE_PADDED = 2 };
 
 
+// Every source lane of these permutations lies in the reading lane's own group
+// (groups of 4, 8 or 16 lanes move through the loop together), so no lane
+// reads a disabled one and the bound-control value is never used.
 template <int CTRL>
 __device__ inline int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL>
@@ -91,20 +101,46 @@ struct Cand {
 };
 
 template <int CTRL>
-__device__ inline void cand_merge(Cand& b) {
-    Cand o;
-    o.D = dpp_d<CTRL>(b.D);
-    o.Z = dpp_d<CTRL>(b.Z);
-    o.id = dpp_i<CTRL>(b.id);
-    o.start = dpp_i<CTRL>(b.start);
-    o.deg = dpp_i<CTRL>(b.deg);
-    if (o.D < b.D || (o.D == b.D && o.id < b.id)) b = o;
+__device__ inline int dpp_min_i(int v) {
+    const int o = dpp_i<CTRL>(v);
+    return o < v ? o : v;
+}
+
+template <int CTRL>
+__device__ inline double dpp_min_d(double v) {
+    return __builtin_fmin(v, dpp_d<CTRL>(v));
+}
+
+__device__ inline int bperm_i(int src_lane, int v) { return __builtin_amdgcn_ds_bpermute(src_lane << 2, v); }
+
+__device__ inline double bperm_d(int src_lane, double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = bperm_i(src_lane, p.x);
+    p.y = bperm_i(src_lane, p.y);
+    return __builtin_bit_cast(double, p);
 }
 
 constexpr int DPP_ROW_MIRROR = 0x140;   // lane i <-> 15-i within each 16 lanes
 constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
 constexpr int DPP_SWAP1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int DPP_SWAP2 = 0x4E;         // quad_perm [2,3,0,1]
+
+// Minimum over the GL lanes of a group, left in every lane of it.
+template <int GL>
+__device__ inline double group_min_d(double v) {
+    if (GL == 16) v = dpp_min_d<DPP_ROW_MIRROR>(v);
+    if (GL >= 8) v = dpp_min_d<DPP_HALF_MIRROR>(v);
+    v = dpp_min_d<DPP_SWAP1>(v);
+    return dpp_min_d<DPP_SWAP2>(v);
+}
+
+template <int GL>
+__device__ inline int group_min_i(int v) {
+    if (GL == 16) v = dpp_min_i<DPP_ROW_MIRROR>(v);
+    if (GL >= 8) v = dpp_min_i<DPP_HALF_MIRROR>(v);
+    v = dpp_min_i<DPP_SWAP1>(v);
+    return dpp_min_i<DPP_SWAP2>(v);
+}
 
 // Work order.  Without `order`, ray L is slot L (origin-major).  With `order`
 // (a permutation of origin positions, spatially sorted) ray L is direction
@@ -172,6 +208,8 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     int32_t e0 = row0.x, deg = row0.y;
     int32_t n = 0;
     double Zc = 0.0;
+    int32_t keep_id = 0;  // entry n of the list waits in lane n mod GL
+    double keep_Z = 0.0;
     for (int32_t step = 0; step < (int32_t)P; ++step) {
         Cand b;
         b.D = __builtin_inf();
@@ -205,26 +243,44 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                 }
             }
         }
-        if (GL == 16) cand_merge<DPP_ROW_MIRROR>(b);
-        if (GL >= 8) cand_merge<DPP_HALF_MIRROR>(b);
-        cand_merge<DPP_SWAP1>(b);
-        cand_merge<DPP_SWAP2>(b);
-        if (b.id == INT32_MAX) break;
+        // group minimum of (D, id); the smallest id breaks ties in D
+        const double Dmin = group_min_d<GL>(b.D);
+        const int32_t idmin = group_min_i<GL>(b.D == Dmin ? b.id : INT32_MAX);
+        if (idmin == INT32_MAX) break;  // no forward neighbour: the ray leaves the model
+        // the winner's Z and row, read from the lane that holds it
+        const uint64_t won = __ballot(b.D == Dmin && b.id == idmin);
+        const int gbase = (int)(threadIdx.x & 63) & ~(GL - 1);
+        const uint32_t gbits = (uint32_t)(won >> gbase) & (uint32_t)((1ull << GL) - 1);
+        const int src = gbase + __builtin_ctz(gbits);
+        const double Zn = bperm_d(src, b.Z);
+        const int32_t start_n = bperm_i(src, b.start);
+        const int32_t deg_n = bperm_i(src, b.deg);
         if (MODE != TRACE_COUNT) {
-            if (n < room) {
-                if (sub == 0) {
-                    ids[base + n] = b.id;
-                    Zout[base + n] = b.Z;
-                }
-            } else {
+            if (n >= room) {
                 if (sub == 0) atomicOr(err, ERRBIT_CAPACITY);
                 break;
             }
+            const int slot = n & (GL - 1);
+            if (sub == slot) {
+                keep_id = idmin;
+                keep_Z = Zn;
+            }
+            if (slot == GL - 1) {  // GL entries buffered: one contiguous store per list
+                ids[base + (n - (GL - 1)) + sub] = keep_id;
+                Zout[base + (n - (GL - 1)) + sub] = keep_Z;
+            }
         }
         ++n;
-        e0 = b.start;
-        deg = b.deg;
-        Zc = b.Z;
+        e0 = start_n;
+        deg = deg_n;
+        Zc = Zn;
+    }
+    if (MODE != TRACE_COUNT) {  // entries still buffered
+        const int32_t done = n & ~(GL - 1);
+        if (sub < n - done) {
+            ids[base + done + sub] = keep_id;
+            Zout[base + done + sub] = keep_Z;
+        }
     }
     if (MODE != TRACE_WRITE && sub == 0) lens[ray] = n;
     // a ray shorter than its slot leaves entries unwritten: the offsets do not match this walk
