@@ -400,9 +400,12 @@ OR_API int64_t or_dirset_adaptive(const double* pos, int64_t P, const int32_t* o
 
 /* Trace one ray from `origin` along unit direction d (Section 2.1, Fig. 2).
  * From the current point c with projection Zc, every neighbour k with
- *     Z_k = (R.x d.x + R.y d.y) + R.z d.z,  R = x_k - x_origin,
+ *     Z_k = R.d,  R = x_k - x_origin,
  * strictly greater than Zc is a forward candidate; its squared distance to
- * the ray axis is D_k = (q.x^2 + q.y^2) + q.z^2 with q = R - Z_k d.  The ray
+ * the ray axis is D_k = |q|^2 with q = R - Z_k d.  Both are evaluated in FP64
+ * with explicit fused multiply-adds, x first:
+ *     Z_k = fma(R.z, d.z, fma(R.y, d.y, R.x d.x)),  q.i = fma(-Z_k, d.i, R.i),
+ *     D_k = fma(q.z, q.z, fma(q.y, q.y, q.x q.x)).  The ray
  * steps to the candidate of least D_k (equal D: smaller point id), records
  * (k, Z_k), and continues from k with Zc = Z_k.  It ends where no neighbour
  * is forward.  The origin is not recorded.  Returns the number of points;
@@ -418,10 +421,10 @@ OR_API int64_t or_trace_ray(const double* pos, const int64_t* off, const int32_t
         for (int64_t e = off[c]; e < off[c + 1]; ++e) {
             int64_t k = idx[e];
             double Rx = pos[3 * k] - ox, Ry = pos[3 * k + 1] - oy, Rz = pos[3 * k + 2] - oz;
-            double Zk = (Rx * d[0] + Ry * d[1]) + Rz * d[2];
+            double Zk = fma(Rz, d[2], fma(Ry, d[1], Rx * d[0]));
             if (!(Zk > Zc)) continue;
-            double qx = Rx - Zk * d[0], qy = Ry - Zk * d[1], qz = Rz - Zk * d[2];
-            double Dk = (qx * qx + qy * qy) + qz * qz;
+            double qx = fma(-Zk, d[0], Rx), qy = fma(-Zk, d[1], Ry), qz = fma(-Zk, d[2], Rz);
+            double Dk = fma(qz, qz, fma(qy, qy, qx * qx));
             if (best < 0 || Dk < bestD || (Dk == bestD && k < best)) {
                 best = k; bestD = Dk; bestZ = Zk;
             }

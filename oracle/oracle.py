@@ -18,7 +18,8 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc: FP64, no FMA contraction, no fast-math, OpenMP."""
+    """Compile oracle.c with gcc: FP64, no FMA contraction (fused multiply-adds only where
+    written as fma), no fast-math, OpenMP."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",

@@ -4,9 +4,11 @@
 // From the current point a ray takes the forward neighbour (projection on the
 // ray axis strictly beyond the current one) that lies closest to the axis,
 // equal distances going to the smaller point id.  The
-// geometry is IEEE FP64 in a fixed operation order with FMA contraction off
-// (this file is compiled with -ffp-contract=off as well), so every list is
-// bit-identical to any other evaluation of the same rule.
+// geometry is IEEE FP64 in a fixed operation order, the fused multiply-adds
+// written out and nothing else contracted (this file is compiled with
+// -ffp-contract=off as well): Z = fma(R.z, d.z, fma(R.y, d.y, R.x d.x)),
+// q = fma(-Z, d, R) per axis, D = fma(q.z, q.z, fma(q.y, q.y, q.x q.x)).  Every
+// list is bit-identical to any other evaluation of the same rule.
 //
 // Data layout: neighbour records {x, y, z, id, row start, degree} (48 bytes)
 // in CSR order and a per-point {row start, degree} table, both built once per
@@ -230,10 +232,11 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                 const int32_t i = i0 + u * GL + sub;
                 if (i >= deg) continue;
                 const double Rx = rec[u].x - ox, Ry = rec[u].y - oy, Rz = rec[u].z - oz;
-                const double Zk = (Rx * dx + Ry * dy) + Rz * dz;
+                const double Zk = __builtin_fma(Rz, dz, __builtin_fma(Ry, dy, Rx * dx));
                 if (!(Zk > Zc)) continue;
-                const double qx = Rx - Zk * dx, qy = Ry - Zk * dy, qz = Rz - Zk * dz;
-                const double Dk = (qx * qx + qy * qy) + qz * qz;
+                const double qx = __builtin_fma(-Zk, dx, Rx), qy = __builtin_fma(-Zk, dy, Ry),
+                             qz = __builtin_fma(-Zk, dz, Rz);
+                const double Dk = __builtin_fma(qz, qz, __builtin_fma(qy, qy, qx * qx));
                 if (Dk < b.D || (Dk == b.D && rec[u].id < b.id)) {
                     b.D = Dk;
                     b.Z = Zk;

@@ -66,6 +66,33 @@ def test_exact_rational_bruteforce(orc, seed):
     assert checked > 0.9 * m.P * 12
 
 
+def _rnd(x):
+    """Round an exact rational to the nearest FP64 (ties to even)."""
+    return Fraction(x.numerator / x.denominator) if x.denominator != 1 else Fraction(float(x.numerator))
+
+
+def test_recorded_Z_is_the_stated_fma_chain(orc):
+    """The recorded projection of each step is the stated FP64 evaluation:
+    R = x_k - x_o rounded per axis, then Z = fma(R.z, d.z, fma(R.y, d.y, R.x d.x)),
+    each operation rounded once (evaluated here in exact rationals)."""
+    m = synth.tiny_model(14, P=40)
+    _, dirs, _ = orc.dirset_uniform(1)
+    n = 0
+    for o in range(0, m.P, 3):
+        for r in range(len(dirs)):
+            for sgn in (1.0, -1.0):
+                d = [Fraction(float(x)) for x in dirs[r] * sgn]
+                ids, Z = orc.trace_ray(m, o, dirs[r] * sgn)
+                for k, z in zip(ids, Z):
+                    R = [_rnd(Fraction(float(m.pos[k][i])) - Fraction(float(m.pos[o][i]))) for i in range(3)]
+                    e = _rnd(R[0] * d[0])
+                    e = _rnd(R[1] * d[1] + e)
+                    e = _rnd(R[2] * d[2] + e)
+                    assert Fraction(float(z)) == e
+                    n += 1
+    assert n > 100
+
+
 def _forward_set(m, c, o, d, Zc):
     ks = m.nbr_idx[m.nbr_off[c]:m.nbr_off[c + 1]]
     R = m.pos[ks] - m.pos[o]
