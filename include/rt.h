@@ -164,10 +164,11 @@ rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int3
  * J[o][f] = sum_r w2_r u_r[f], summed in ascending r (eq. 3, eq. 4).
  *
  * precision RT_F64: all FP64 (tables must be RT_F64).  RT_F32: tables RT_F32,
- * sweep in FP32, except that for rows where some frequency of the 64-wide
- * chunk has min(dtau_{d-1}, dtau_d) < dtau_fp64_below the elimination
- * coefficients are evaluated in FP64; ds is always formed in FP64 from the
- * FP64 Z. */
+ * sweep in FP32; ds is always formed in FP64 from the FP64 Z.  The rows are
+ * carried per unit inner step (F = dtau G, Z = dtau Y), so the only
+ * elimination coefficient, (dtau_{d-1} + dtau_d)/2, is in FP32 exactly its FP64
+ * value rounded once: every row, however small its steps, has FP64
+ * coefficients, and no row needs a separate FP64 path. */
 typedef struct {
     int32_t n_blocks;
     const int32_t* len; /* host [n_blocks] */
@@ -185,7 +186,9 @@ typedef struct {
                                  each XCD on a contiguous range -- concurrent waves then read mostly the
                                  same rows and the L2s hold them.  A plan's walk always uses that
                                  order. */
-    double dtau_fp64_below;   /* FP32 path: rows with a smaller dtau are eliminated in FP64 (e.g. 1e-4) */
+    double dtau_fp64_below;   /* threshold of the FP64-coefficient rule (e.g. 1e-4); kept in the
+                                 struct, but every row already has FP64 coefficients (above), so the
+                                 value does not change results; must be >= 0 */
     int32_t waves_per_cu;     /* persistent grid size (0 = default) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
     int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 4) */

@@ -404,9 +404,8 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.P = m->P;
     a.I_bc = I_bc;
     a.J = J;
-    a.dtau_fp64_below = o.dtau_fp64_below;
-    if (!(o.dtau_max >= 0.0) || !(o.dv_max >= 0.0) || o.max_substeps < 0)
-        return fail(RT_ERR_ARG, "solve: dtau_max, dv_max and max_substeps must be >= 0");
+    if (!(o.dtau_max >= 0.0) || !(o.dv_max >= 0.0) || o.max_substeps < 0 || !(o.dtau_fp64_below >= 0.0))
+        return fail(RT_ERR_ARG, "solve: dtau_max, dv_max, max_substeps and dtau_fp64_below must be >= 0");
     a.dtau_max_rcp = o.dtau_max > 0.0 ? 1.0 / o.dtau_max : 0.0;
     a.dv_max_rcp = o.dv_max > 0.0 && m->vel ? 1.0 / o.dv_max : 0.0;
     a.max_sub = o.max_substeps > 0 ? o.max_substeps : 1024;

@@ -147,7 +147,6 @@ struct SolveLaunch {
     const double* I_bc;
     void* u;
     void* J;
-    double dtau_fp64_below;
     double dtau_max_rcp;   // 1/dtau_max (adaptive optical-depth increments), 0 = off
     double dv_max_rcp;     // 1/dv_max (adaptive velocity sampling), 0 = off
     int32_t max_sub;       // cap on the sub-steps of one interval

@@ -12,16 +12,24 @@
 // Rescaled elimination.  With the three-point rows
 //     -A_d u_{d-1} + (1 + A_d + C_d) u_d - C_d u_{d+1} = S_d,
 //     A_d = 2/(a(a+b)), C_d = 2/(b(a+b)),  a = outer dtau, b = inner dtau,
-// and u_d = u_{d+1}/(1+F_d) + Z_d, the recurrences become
+// and u_d = u_{d+1}/(1+F_d) + Z_d, the recurrences are
 //     F_d = b(a+b)/2 + (b/a) F_{d-1}/(1+F_{d-1})
 //     Z_d = (b(a+b)/2 S_d + (b/a) Z_{d-1}) / (1 + F_d)
 // and at the far end (boundary row from u' = u - I to second order)
 //     F_0 = b(1 + b/2),  Z_0 = (b^2/2 S_0 + b I)/(1 + F_0).
-// Every term is a sum or quotient of positive numbers, so small optical-depth
-// steps lose nothing to cancellation.  At the origin, with h = ab(a+b)/2,
-//     u = (h S + b Z_- + a Z_+) / (h + b F_-/(1+F_-) + a F_+/(1+F_+)),
+// Carried per unit inner step, F_d = b G_d and Z_d = b Y_d, and since the
+// outer step a of row d is the inner step of row d-1, the ratio b/a cancels:
+//     G_d = (a+b)/2 + G_{d-1} r_{d-1},   r_d = 1/(1 + b G_d),
+//     Y_d = ((a+b)/2 S_d + Y_{d-1}) r_d,
+//     G_0 = 1 + b/2,  Y_0 = (b/2 S_0 + I) r_0.
+// One reciprocal per row, and the only coefficient, (a+b)/2, is the correctly
+// rounded exact value in any precision (an FP32 evaluation equals the FP64
+// one rounded once), however small the steps.  Every term is a sum or product
+// of positive numbers, so small optical-depth steps lose nothing to
+// cancellation.  At the origin (a, b the steps to the two sides' last rows)
+//     u = ((a+b)/2 S + Y_- + Y_+) / ((a+b)/2 + G_- r_- + G_+ r_+),
 // and with one side empty (dtau t on the other)
-//     u = (t^2/2 S + t I + Z) / (t^2/2 + t + F/(1+F)).
+//     u = (t/2 S + I + Y) / (1 + t/2 + G r).
 //
 // Per-point data that is the same for every frequency (point id, ds, the
 // velocity projection) is loaded for 64 points at once, one per lane, and
@@ -119,6 +127,14 @@ __device__ inline double rcp64(double x) {
     return r;
 }
 
+// min(max(x, lo), hi) for lo <= hi in one instruction (the compiler forms
+// v_med3_i32 only for constant bounds).
+__device__ inline int clamp_i32(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 template <typename T>
 __device__ inline T fma_(T a, T b, T c) { return __builtin_fma(a, b, c); }
 template <>
@@ -131,135 +147,44 @@ __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
 __device__ inline double rcp<double>(double x) { return rcp64(x); }
 
-// Running state of one side's elimination.  r1 = 1/(1+F) and ra = 1/a are
-// carried so that every row costs three reciprocals: 1/(1+F_new), 1/dtau and
-// 1/chi' (for S).
+// Running state of one side's elimination (file header).
 template <typename T>
 struct SweepState {
-    T F, Z, r1;   // rescaled pivot, right-hand side, 1/(1+F)
-    T a, ra;      // outer optical-depth step of the pending row and its reciprocal
+    T G, Y, r;  // rescaled pivot and right-hand side, r = 1/(1 + a G)
+    T a;        // inner optical-depth step of the last row: the outer step of the next
 };
 
-// Row d of the elimination, given its outer step a (ra = 1/a), inner step b and S_d.
+// Row d of the elimination, given its inner step b and S_d (the outer step is st.a).
 template <typename T>
 __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
     if (far_end) {
-        st.F = b * ((T)1 + (T)0.5 * b);
-        st.r1 = rcp<T>((T)1 + st.F);
-        st.Z = ((T)0.5 * b * b * S + b * I) * st.r1;
+        const T hb = (T)0.5 * b;
+        st.G = (T)1 + hb;
+        st.r = rcp<T>(fma_<T>(b, st.G, (T)1));
+        st.Y = fma_<T>(hb, S, I) * st.r;
     } else {
-        const T hb = (T)0.5 * b * (st.a + b);
-        const T ba = b * st.ra;
-        st.F = fma_<T>(ba, st.F * st.r1, hb);
-        const T Zn = fma_<T>(hb, S, ba * st.Z);
-        st.r1 = rcp<T>((T)1 + st.F);
-        st.Z = Zn * st.r1;
+        const T h = (T)0.5 * (st.a + b);
+        st.G = fma_<T>(st.G, st.r, h);
+        st.r = rcp<T>(fma_<T>(b, st.G, (T)1));
+        st.Y = fma_<T>(h, S, st.Y) * st.r;
     }
     st.a = b;
-    st.ra = rcp<T>(b);
-}
-
-// The same row with its elimination coefficients -- b(a+b)/2 and b/a, or at the
-// far end b(1+b/2) and b^2/2 -- evaluated in FP64 and rounded once; the
-// recurrence itself stays FP32.  Used for rows with tiny optical-depth steps.
-__device__ inline void row_coef64(SweepState<float>& st, bool far_end, float b, float S, float I) {
-    const double bd = b;
-    if (far_end) {
-        st.F = (float)(bd * (1.0 + 0.5 * bd));
-        const float h = (float)(0.5 * bd * bd);
-        st.r1 = __builtin_amdgcn_rcpf(1.0f + st.F);
-        st.Z = (h * S + b * I) * st.r1;
-    } else {
-        const double ad = st.a;
-        const double ra = __builtin_fma((double)st.ra, __builtin_fma(-ad, (double)st.ra, 1.0), (double)st.ra);
-        const float hb = (float)(0.5 * bd * (ad + bd));
-        const float ba = (float)(bd * ra);
-        st.F = __builtin_fmaf(ba, st.F * st.r1, hb);
-        const float Zn = __builtin_fmaf(hb, S, ba * st.Z);
-        st.r1 = __builtin_amdgcn_rcpf(1.0f + st.F);
-        st.Z = Zn * st.r1;
-    }
-    st.a = b;
-    st.ra = __builtin_amdgcn_rcpf(b);
-}
-
-// Precision policy.  FP64 sweep: plain rows.  FP32 sweep: when any lane of the
-// wave has a step below the threshold (min(a, b), or b at the far end) the
-// wave computes this row's coefficients in FP64 -- one path per wave instead of
-// two divergent ones.
-template <typename T>
-__device__ inline void row_policy(SweepState<T>& st, bool far_end, T b, T S, T I, float thr) {
-    row<T>(st, far_end, b, S, I);
-}
-
-template <>
-__device__ inline void row_policy<float>(SweepState<float>& st, bool far_end, float b, float S, float I,
-                                         float thr) {
-    // far_end is the same in every lane (a scalar branch) except with optical-depth
-    // sub-steps, where lanes split the first interval differently
-    if (far_end) {
-        if (__builtin_amdgcn_ballot_w64(b < thr)) row_coef64(st, true, b, S, I);
-        else row<float>(st, true, b, S, I);
-    } else {
-        const float m = st.a < b ? st.a : b;
-        if (__builtin_amdgcn_ballot_w64(m < thr)) row_coef64(st, false, b, S, I);
-        else row<float>(st, false, b, S, I);
-    }
 }
 
 // u at the origin from the two sides' states (file header).
 template <typename T>
 __device__ inline T origin_u(bool hm, bool hp, const SweepState<T>& m, const SweepState<T>& p, T S, T I) {
-    const T a = m.a, b = p.a;
     if (hm && hp) {
-        const T h = (T)0.5 * a * b * (a + b);
-        return (h * S + b * m.Z + a * p.Z) * rcp<T>(h + b * (m.F * m.r1) + a * (p.F * p.r1));
+        const T h = (T)0.5 * (m.a + p.a);
+        return fma_<T>(h, S, m.Y + p.Y) * rcp<T>(h + fma_<T>(m.G, m.r, p.G * p.r));
     }
-    if (hp) {
-        const T h = (T)0.5 * b * b;
-        return (h * S + b * I + p.Z) * rcp<T>(h + b + p.F * p.r1);
-    }
-    if (hm) {
-        const T h = (T)0.5 * a * a;
-        return (h * S + a * I + m.Z) * rcp<T>(h + a + m.F * m.r1);
+    if (hm || hp) {
+        const SweepState<T>& q = hp ? p : m;
+        const T ht = (T)0.5 * q.a;
+        return (fma_<T>(ht, S, I) + q.Y) * rcp<T>(fma_<T>(q.G, q.r, (T)1 + ht));
     }
     return I;
 }
-
-// Origin row with its coefficients h = ab(a+b)/2 (or t^2/2) in FP64, rounded once.
-__device__ inline float origin_u_coef64(bool hm, bool hp, const SweepState<float>& m, const SweepState<float>& p,
-                                        float S, float I) {
-    const double a = m.a, b = p.a;
-    if (hm && hp) {
-        const float h = (float)(0.5 * a * b * (a + b));
-        return (h * S + p.a * m.Z + m.a * p.Z) *
-               __builtin_amdgcn_rcpf(h + p.a * (m.F * m.r1) + m.a * (p.F * p.r1));
-    }
-    if (hp) {
-        const float h = (float)(0.5 * b * b);
-        return (h * S + p.a * I + p.Z) * __builtin_amdgcn_rcpf(h + p.a + p.F * p.r1);
-    }
-    if (hm) {
-        const float h = (float)(0.5 * a * a);
-        return (h * S + m.a * I + m.Z) * __builtin_amdgcn_rcpf(h + m.a + m.F * m.r1);
-    }
-    return I;
-}
-
-template <typename T>
-__device__ inline T origin_policy(bool hm, bool hp, const SweepState<T>& m, const SweepState<T>& p, T S, T I,
-                                  float thr) {
-    return origin_u<T>(hm, hp, m, p, S, I);
-}
-
-template <>
-__device__ inline float origin_policy<float>(bool hm, bool hp, const SweepState<float>& m,
-                                             const SweepState<float>& p, float S, float I, float thr) {
-    const float mn = (hm && hp) ? fminf(m.a, p.a) : (hp ? p.a : m.a);
-    if ((hm || hp) && __builtin_amdgcn_ballot_w64(mn < thr)) return origin_u_coef64(hm, hp, m, p, S, I);
-    return origin_u<float>(hm, hp, m, p, S, I);
-}
-
 
 // Per-wave constants of one item.
 struct ItemCtx {
@@ -271,7 +196,6 @@ struct ItemCtx {
     const float* vel;
     double nx, ny, nz, inv_dx0;
     float vox, voy, voz;
-    float thr;
     double dtau_rcp;   // adaptive optical-depth increments: 1/dtau_max
     double dv_rcp;     // adaptive velocity sampling: 1/dv_max
     double dx0;        // width of the first block's frequency step
@@ -319,7 +243,7 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
                                         T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I) {
     const T est = (cf > cn ? cf : cn) * (hds + hds) * (T)c.dtau_rcp;
     if (!__builtin_amdgcn_ballot_w64(est > (T)0.9999)) {
-        row_policy<T>(st, first, (cf + cn) * hds, Sf, I, c.thr);
+        row<T>(st, first, (cf + cn) * hds, Sf, I);
         return;
     }
     const double c64f = chi64(pf), c64n = chi64(pn);
@@ -336,13 +260,13 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
             const T w = (T)k * rn;
             const T ck = fma_<T>(w, cn - cf, cf);
             const T ek = fma_<T>(w, en - ef, ef);
-            row_policy<T>(st, fr, (cp + ck) * hh, Sp, I, c.thr);
+            row<T>(st, fr, (cp + ck) * hh, Sp, I);
             cp = ck;
             Sp = ek * rcp<T>(ck);
             fr = false;
         }
     }
-    row_policy<T>(st, fr, (cp + cn) * hh, Sp, I, c.thr);
+    row<T>(st, fr, (cp + cn) * hh, Sp, I);
 }
 
 // The stream of line points of one side, far to near, after velocity sampling.
@@ -361,7 +285,7 @@ __device__ inline void emit_point(const ItemCtx& c, SweepState<T>& st, Emitter<T
                                   const Pt64<T>& pn, T hds, double ds64, T I) {
     if (em.have) {
         if (c.dtau_rcp > 0.0) substep_interval<T>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I);
-        else row_policy<T>(st, em.first, (em.c + cn) * hds, em.S, I, c.thr);
+        else row<T>(st, em.first, (em.c + cn) * hds, em.S, I);
         em.first = false;
     }
     em.c = cn;
@@ -416,8 +340,8 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
         const double t64 = delta - kf;
         const T t = (T)t64;
         const int ks = k * (int)sizeof(T);
-        const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
-        const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
+        const uint32_t oa = (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
+        const uint32_t ob = (uint32_t)clamp_i32(lb_bytes - (int)sizeof(T) - ks, lo_bytes, hi_bytes);
         const T a0 = *(const T*)(c.chi + A.row + oa), a1 = *(const T*)(c.chi + A.row + ob);
         const T b0 = *(const T*)(c.chi + B.row + oa), b1 = *(const T*)(c.chi + B.row + ob);
         const T g0 = *(const T*)(c.eta + A.row + oa), g1 = *(const T*)(c.eta + A.row + ob);
@@ -494,8 +418,8 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
                 }
                 const T t = (T)t64;
                 const int ks = k * (int)sizeof(T);
-                const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
-                const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
+                const uint32_t oa = (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
+                const uint32_t ob = (uint32_t)clamp_i32(lb_bytes - (int)sizeof(T) - ks, lo_bytes, hi_bytes);
                 const T ca = *(const T*)(cr + oa), cb = *(const T*)(cr + ob);
                 const T ea = *(const T*)(er + oa), eb = *(const T*)(er + ob);
                 cur.c = fma_<T>(t, cb - ca, ca);
@@ -599,8 +523,8 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                         }
                         // byte offsets of rows fl - k and fl - k - 1, clamped to the block
                         const int ks = k * (int)sizeof(T);
-                        const uint32_t oa = (uint32_t)min(max(lb_bytes - ks, lo_bytes), hi_bytes);
-                        const uint32_t ob = (uint32_t)min(max(lb_bytes - ks - (int)sizeof(T), lo_bytes), hi_bytes);
+                        const uint32_t oa = (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
+                        const uint32_t ob = (uint32_t)clamp_i32(lb_bytes - (int)sizeof(T) - ks, lo_bytes, hi_bytes);
                         ca[g] = *(const T*)(cr + oa);
                         cb[g] = *(const T*)(cr + ob);
                         ea[g] = *(const T*)(er + oa);
@@ -626,7 +550,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     const T S = et * rcp<T>(cc);
                     if (done > 0) {
                         const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
-                        row_policy<T>(st, done == 1, dt, S_prev, I, c.thr);
+                        row<T>(st, done == 1, dt, S_prev, I);
                     }
                     c_prev = cc;
                     S_prev = S;
@@ -638,7 +562,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     }
     if (n > 0) {
         const T dt = (c_prev + chi_o) * ds_prev;
-        row_policy<T>(st, n == 1, dt, S_prev, I, c.thr);
+        row<T>(st, n == 1, dt, S_prev, I);
     }
 }
 
@@ -679,7 +603,6 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
         c.voy = a.vel[3 * o + 1];
         c.voz = a.vel[3 * o + 2];
     }
-    c.thr = (float)a.dtau_fp64_below;
     c.dtau_rcp = a.dtau_max_rcp;
     c.dv_rcp = a.dv_max_rcp;
     c.max_sub = a.max_sub;
@@ -696,7 +619,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
         sweep<T, MOVING, UDX, GROUP>(c, bm, nm, lf, lane, chi_o, I, m);
         sweep<T, MOVING, UDX, GROUP>(c, bp, np, lf, lane, chi_o, I, p);
     }
-    const T u = origin_policy<T>(nm > 0, np > 0, m, p, S_o, I, c.thr);
+    const T u = origin_u<T>(nm > 0, np > 0, m, p, S_o, I);
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
         if (!(u == u) || u - u != (T)0) atomicOr(a.err, ERRBIT_NONFINITE);
