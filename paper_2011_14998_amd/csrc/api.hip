@@ -416,6 +416,10 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.n_xcd = num_xcds();
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
     a.group = o.group ? o.group : 4;
+    {  // every byte offset into chi and eta (row * ld + column) fits in 32 bits
+        const double tbytes = (double)m->P * (double)ld * (double)(dtype == RT_F64 ? 8 : 4);
+        a.small_tables = tbytes < 4294967296.0 ? 1 : 0;
+    }
     a.err = error_word();
     if (!a.err) return fail(RT_ERR_HIP, "solve: no device error word");
     return RT_OK;

@@ -163,6 +163,7 @@ struct SolveLaunch {
     int64_t P;             // number of points (origin ids are checked against it)
     int n_xcd;             // XCDs for the block renumbering of the direct launch
     int group;             // sweep load-group size (4 or 8)
+    int small_tables;      // chi and eta each below 4 GiB: 32-bit row offsets in the sweep
 };
 int64_t solve_items(const SolveLaunch& a);
 size_t bin_workspace(int64_t n_items, int32_t n_bins);

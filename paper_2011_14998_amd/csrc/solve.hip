@@ -38,6 +38,8 @@
 // table for FP32.
 #include "rt_internal.h"
 
+#include <type_traits>
+
 namespace rt {
 
 namespace {
@@ -451,94 +453,122 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
     }
 }
 
+// Per-point data of the line points being swept, staged in LDS: 64 records of
+// eight 32-bit words per wave.  Words 0-1: table row offset in bytes; with a
+// uniform dx, word 2 the whole-step shift in bytes and word 3 (FP32) or 4-5
+// (FP64) the fraction t, otherwise words 2-3 the projected velocity (FP64);
+// word 4 (FP32) or 6-7 (FP64): ds/2.
+constexpr int STAGE_WORDS = 8;
+
 // Eliminate one side of the line (entries base .. base+n-1 of a ray list,
 // walked from the far end inwards), up to the origin; on return st holds the
 // row next to the origin and st.a the step between that row and the origin.
 //
-// UDX: every frequency block has the same dx, so the Doppler shift of a point
-// (whole steps k and fraction t) is the same in every lane and is computed
-// once per point while the 64-point segment is staged.
+// Staging: for each run of 64 points, lane j computes the record of point
+// hi-j (id, ds from the FP64 Z, and with a uniform dx the Doppler shift as
+// whole steps + fraction, the same in every lane) and writes it to LDS; the
+// elimination then reads one record per point with a broadcast LDS read, so
+// the per-point values reach every lane without VALU lane transfers.  SMALL:
+// the tables are below 4 GiB, so a lane's address is the table base (scalar)
+// plus a 32-bit offset row + its clamped column; otherwise the row offset is
+// moved to scalar registers per point.
 // GROUP line points have their loads issued together before the recurrence
 // consumes them (a tuning parameter: more points in flight per wave against
 // more registers, i.e. fewer waves).
-template <typename T, bool MOVING, bool UDX, int GROUP>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SMALL>
 __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
-                             SweepState<T>& st) {
+                             SweepState<T>& st, uint32_t* stage) {
     T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
     const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
+    const int lbm_bytes = lb_bytes - (int)sizeof(T);
     const int lo_bytes = lf.fb * (int)sizeof(T);
     const int hi_bytes = (lf.fb + lf.L - 1) * (int)sizeof(T);
+    constexpr int T_WORD = sizeof(T) == 4 ? 3 : 4;   // the fraction t
+    constexpr int DS_WORD = sizeof(T) == 4 ? 4 : 6;  // ds/2
     for (int hi = n - 1; hi >= 0; hi -= 64) {
         const int cnt = hi + 1 < 64 ? hi + 1 : 64;
-        // staging: lane j holds entry hi-j
+        // staging: lane j writes the record of entry hi-j
         const int e = hi - lane;
-        const bool v = lane < cnt;
-        int q_l = 0, k_l = 0;
-        int64_t row_l = 0;
-        T ds_l = (T)0, t_l = (T)0;
-        double dot_l = 0.0;
-        if (v) {
-            q_l = c.ids[base + e];
-            row_l = (int64_t)q_l * c.ld_bytes;
+        if (lane < cnt) {
+            uint32_t* w = stage + lane * STAGE_WORDS;
+            const int q = c.ids[base + e];
+            const uint64_t row = (uint64_t)q * (uint64_t)c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
-            ds_l = (T)0.5 * (T)(z - zi);  // half the difference of FP64 projections, rounded once
+            const T ds = (T)0.5 * (T)(z - zi);  // half the difference of FP64 projections, rounded once
+            w[0] = (uint32_t)row;
+            w[1] = (uint32_t)(row >> 32);
             if (MOVING) {
-                const float* vq = c.vel + 3 * (int64_t)q_l;
+                const float* vq = c.vel + 3 * (int64_t)q;
                 const double dvx = (double)vq[0] - (double)c.vox;
                 const double dvy = (double)vq[1] - (double)c.voy;
                 const double dvz = (double)vq[2] - (double)c.voz;
-                dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
+                const double dot = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
                 if (UDX) {
-                    const double delta = dot_l / c.dx0;
+                    const double delta = dot / c.dx0;
                     const double kf = floor(delta);
-                    k_l = (int)kf;
-                    t_l = (T)(delta - kf);
+                    w[2] = (uint32_t)((int)kf * (int)sizeof(T));
+                    *(T*)(w + T_WORD) = (T)(delta - kf);
+                } else {
+                    *(double*)(w + 2) = dot;
                 }
             }
+            *(T*)(w + DS_WORD) = ds;
         }
-        for (int j = 0; j < cnt; j += GROUP) {
+        __builtin_amdgcn_wave_barrier();
+        // a group of GROUP points: loads first, then the recurrence; FULL groups
+        // carry no per-point bounds test, so their loads are issued together
+        auto point_group = [&](auto full, int j) {
+            constexpr bool FULL = decltype(full)::value;
             T ca[GROUP], cb[GROUP], ea[GROUP], eb[GROUP], tt[GROUP], dsv[GROUP];
 #pragma unroll
             for (int g = 0; g < GROUP; ++g) {
-                if (j + g < cnt) {
-                    const int64_t row = readlane_64(row_l, j + g);
-                    const char* cr = c.chi + row;
-                    const char* er = c.eta + row;
-                    dsv[g] = readlane_t<T>(ds_l, j + g);
+                if (FULL || j + g < cnt) {
+                    const uint32_t* w = stage + (j + g) * STAGE_WORDS;
+                    const uint4 r0 = *(const uint4*)w;  // one broadcast read: row, shift, t
+                    dsv[g] = *(const T*)(w + DS_WORD);
+                    const char* cr = c.chi;
+                    const char* er = c.eta;
+                    uint32_t rlo = r0.x;
+                    if (!SMALL) {  // the row in scalar registers, the column as the offset
+                        const uint64_t row = uni64((int64_t)(((uint64_t)r0.y << 32) | r0.x));
+                        cr += row;
+                        er += row;
+                        rlo = 0;
+                    }
                     if (MOVING) {
-                        int k;
+                        int ks;
                         T t;
                         if (UDX) {
-                            k = readlane_i(k_l, j + g);
-                            t = readlane_t<T>(t_l, j + g);
+                            ks = (int)r0.z;
+                            t = *(const T*)(w + T_WORD);
                         } else {  // per-lane block widths: the shift as the oracle forms it, a division
-                            const double delta = readlane_d(dot_l, j + g) / lf.dx;
+                            const double delta = __builtin_bit_cast(double, (((uint64_t)r0.w << 32) | r0.z)) / lf.dx;
                             const double kf = floor(delta);
-                            k = (int)kf;
+                            ks = (int)kf * (int)sizeof(T);
                             t = (T)(delta - kf);
                         }
                         // byte offsets of rows fl - k and fl - k - 1, clamped to the block
-                        const int ks = k * (int)sizeof(T);
-                        const uint32_t oa = (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
-                        const uint32_t ob = (uint32_t)clamp_i32(lb_bytes - (int)sizeof(T) - ks, lo_bytes, hi_bytes);
+                        const uint32_t oa = rlo + (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
+                        const uint32_t ob = rlo + (uint32_t)clamp_i32(lbm_bytes - ks, lo_bytes, hi_bytes);
                         ca[g] = *(const T*)(cr + oa);
                         cb[g] = *(const T*)(cr + ob);
                         ea[g] = *(const T*)(er + oa);
                         eb[g] = *(const T*)(er + ob);
                         tt[g] = t;
                     } else {
-                        ca[g] = *(const T*)(cr + lane_off);
-                        ea[g] = *(const T*)(er + lane_off);
+                        const uint32_t o = rlo + lane_off;
+                        ca[g] = *(const T*)(cr + o);
+                        ea[g] = *(const T*)(er + o);
                     }
                 }
             }
 #pragma unroll
             for (int g = 0; g < GROUP; ++g) {
-                if (j + g < cnt) {
+                if (FULL || j + g < cnt) {
                     T cc, et;
                     if (MOVING) {
                         cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
@@ -558,7 +588,11 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                     ++done;
                 }
             }
-        }
+        };
+        int j = 0;
+        for (; j + GROUP <= cnt; j += GROUP) point_group(std::true_type{}, j);
+        if (j < cnt) point_group(std::false_type{}, j);
+        __builtin_amdgcn_wave_barrier();  // every lane has read this run before the next is staged
     }
     if (n > 0) {
         const T dt = (c_prev + chi_o) * ds_prev;
@@ -567,7 +601,7 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
 }
 
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
-__device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane) {
+__device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane, uint32_t* stage) {
     // w is the same in every lane of the wave
     w = uni64(w);
     const int fc = (int)(w % nfc);
@@ -616,8 +650,13 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
         sweep_ref<T, MOVING, UDX>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m);
         sweep_ref<T, MOVING, UDX>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p);
     } else {
-        sweep<T, MOVING, UDX, GROUP>(c, bm, nm, lf, lane, chi_o, I, m);
-        sweep<T, MOVING, UDX, GROUP>(c, bp, np, lf, lane, chi_o, I, p);
+        if (a.small_tables) {
+            sweep<T, MOVING, UDX, GROUP, true>(c, bm, nm, lf, lane, chi_o, I, m, stage);
+            sweep<T, MOVING, UDX, GROUP, true>(c, bp, np, lf, lane, chi_o, I, p, stage);
+        } else {
+            sweep<T, MOVING, UDX, GROUP, false>(c, bm, nm, lf, lane, chi_o, I, m, stage);
+            sweep<T, MOVING, UDX, GROUP, false>(c, bp, np, lf, lane, chi_o, I, p, stage);
+        }
     }
     const T u = origin_u<T>(nm > 0, np > 0, m, p, S_o, I);
     if (lf.active) {
@@ -628,6 +667,8 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
 
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
+    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * STAGE_WORDS];
+    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * STAGE_WORDS;
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
@@ -643,7 +684,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
         }
-        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane, stage);
     }
 }
 
@@ -652,6 +693,8 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
 // every wave reaches the end.
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
+    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * STAGE_WORDS];
+    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * STAGE_WORDS;
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
@@ -661,7 +704,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane);
+        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane, stage);
     }
 }
 
