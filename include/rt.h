@@ -101,11 +101,15 @@ rt_status rt_dirset_destroy(rt_dirset* set);
 
 /* ------------------------------------------------------------------ model
  * Borrows the caller's device arrays for the handle's lifetime.  Validates the
- * neighbour lists on the device (indices in range, no self entries) and
- * synchronises once on `stream` to read the verdict.  Builds a neighbour-
+ * neighbour lists on the device (indices in range, no self entries; error
+ * RT_ERR_MESH) and the positions (finite, every coordinate of magnitude at most
+ * 1e150 so that the walk's squared distances stay finite; error RT_ERR_ARG)
+ * and synchronises once on `stream` to read the verdict.  Builds a neighbour-
  * record table (48 bytes per neighbour entry: position, id, the neighbour's
- * own row) that the tracer reads instead of chasing nbr_idx into pos and
- * nbr_off.  The positions and lists must not change while the handle lives. */
+ * own row; each row sorted by id) that the tracer reads instead of chasing
+ * nbr_idx into pos and nbr_off.  The order of a point's neighbours in nbr_idx
+ * does not affect any result.  The positions and lists must not change while
+ * the handle lives. */
 rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
                           int64_t E, const float* vel, void* stream, rt_model** out);
 rt_status rt_model_destroy(rt_model* model);
@@ -120,14 +124,16 @@ rt_status rt_validate_host(const double* pos, int64_t P, const int64_t* nbr_off,
 /* ------------------------------------------------------------------ tracing
  * Every ray of every listed origin walks the neighbour graph (Section 2.1,
  * Fig. 2): from the current point it steps to the forward neighbour closest to
- * the ray axis.  With R = x_k - x_origin and d the ray direction,
- *   Z_k = (R.x d.x + R.y d.y) + R.z d.z           (projection, FP64)
+ * the ray axis.  With R = x_k - x_origin (per axis, FP64) and d the ray
+ * direction, in FP64 with the fused multiply-adds written out:
+ *   Z_k = fma(R.z, d.z, fma(R.y, d.y, R.x d.x))      (projection)
  *   forward:  Z_k > Z_current (strict)
- *   D_k = (q.x^2 + q.y^2) + q.z^2, q = R - Z_k d  (squared distance to the axis)
+ *   q = fma(-Z_k, d, R) per axis,
+ *   D_k = fma(q.z, q.z, fma(q.y, q.y, q.x q.x))      (squared distance to the axis)
  * the least D_k wins, equal D_k go to the smaller point id; the ray records
  * (k, Z_k) and continues from k; it ends where no neighbour is forward.  The
- * origin itself is not recorded.  All geometry is IEEE FP64 without FMA
- * contraction, so lists are bit-exact and independent of launch shape.
+ * origin itself is not recorded.  Nothing else is contracted, so lists are
+ * bit-exact and independent of launch shape.
  *
  * origins: device int32 [n_origins], or NULL for 0..n_origins-1. */
 

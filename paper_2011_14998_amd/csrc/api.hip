@@ -222,9 +222,10 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
         if (m->nbr) (void)hipFree(m->nbr);
         if (m->rows) (void)hipFree(m->rows);
         delete m;
-        return fail(RT_ERR_MESH, std::string("rt_model_create: invalid neighbour lists (") +
+        return fail(hbad == 8 ? RT_ERR_ARG : RT_ERR_MESH, std::string("rt_model_create: invalid model (") +
                                      ((hbad & 1) ? "index out of range " : "") + ((hbad & 2) ? "bad offsets " : "") +
-                                     ((hbad & 4) ? "self neighbour" : "") + ")");
+                                     ((hbad & 4) ? "self neighbour " : "") +
+                                     ((hbad & 8) ? "position not finite or beyond 1e150" : "") + ")");
     }
     *out = m;
     return RT_OK;

@@ -50,7 +50,8 @@ __global__ __launch_bounds__(256) void k_build_nbr(const double* __restrict__ po
 }
 
 __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
-                                                    int64_t P, int64_t E, int32_t* __restrict__ bad) {
+                                                    const double* __restrict__ pos, int64_t P, int64_t E,
+                                                    int32_t* __restrict__ bad) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     int64_t a = off[p], b = off[p + 1];
@@ -60,12 +61,37 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
     }
     for (int64_t e = a; e < b; ++e)
         if (idx[e] == p) atomicOr(bad, 4);
+    // |x| <= 1e150 keeps every squared distance of the walk finite
+    for (int i = 0; i < 3; ++i)
+        if (!(fabs(pos[3 * p + i]) <= 1e150)) atomicOr(bad, 8);
+}
+
+// Each row's records in ascending neighbour id (insertion sort, one thread per
+// row; rows with invalid offsets are left alone -- k_check_off reports them).
+// The walk's per-lane scan relies on it: a lane meets its candidates in
+// ascending id, so keeping the first of equal distances keeps the smaller id.
+__global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ off, int64_t P, int64_t E,
+                                                    NbrRec* __restrict__ nbr) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t a = off[p], b = off[p + 1];
+    if (a < 0 || a > b || b > E) return;
+    for (int64_t e = a + 1; e < b; ++e) {
+        const NbrRec r = nbr[e];
+        int64_t f = e - 1;
+        while (f >= a && nbr[f].id > r.id) {
+            nbr[f + 1] = nbr[f];
+            --f;
+        }
+        nbr[f + 1] = r;
+    }
 }
 
 // GL lanes (4, 8 or 16) walk one ray.  At every step lane s takes neighbours s,
-// s+GL, ... of the current point's row (contiguous records, so a group reads
-// whole cache lines; a lane's loads are issued four at a time) and keeps its
-// best forward candidate together with that candidate's own CSR row (start,
+// s+GL, ... of the current point's row (contiguous records sorted by id, so a
+// group reads whole cache lines and a lane meets its candidates in ascending
+// id; a lane's loads are issued four at a time) and keeps its best forward
+// candidate (least D, the first of equal D) together with that candidate's own CSR row (start,
 // degree, held in the record, so the next step's loads depend on nothing
 // else).  The group then finds the lexicographic minimum of (D, id) in two
 // DPP reductions (the minimum D, then the smallest id among the lanes that
@@ -237,7 +263,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                 const double qx = __builtin_fma(-Zk, dx, Rx), qy = __builtin_fma(-Zk, dy, Ry),
                              qz = __builtin_fma(-Zk, dz, Rz);
                 const double Dk = __builtin_fma(qz, qz, __builtin_fma(qy, qy, qx * qx));
-                if (Dk < b.D || (Dk == b.D && rec[u].id < b.id)) {
+                if (Dk < b.D) {  // ascending ids within the lane: the first of equal D has the smaller id
                     b.D = Dk;
                     b.Z = Zk;
                     b.id = rec[u].id;
@@ -407,7 +433,10 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
     if (m->E > 0)
         hipLaunchKernelGGL(k_build_nbr, dim3((unsigned)blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
                            m->E, m->nbr, bad);
-    hipLaunchKernelGGL(k_check_off, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->P, m->E, bad);
+    hipLaunchKernelGGL(k_check_off, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->pos, m->P,
+                       m->E, bad);
+    if (m->E > 0)
+        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->E, m->nbr);
     return hipGetLastError();
 }
 

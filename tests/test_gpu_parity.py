@@ -68,6 +68,34 @@ def test_trace_lattice_ties(rt, orc):
     _assert_rays_equal(g, e)
 
 
+def test_trace_ties_independent_of_row_order(rt, orc):
+    """Each point's neighbours in a seeded random order: on the lattice (exact
+    distance ties everywhere) the lists equal the oracle's on the original order."""
+    m = synth.lattice_model(6)
+    rng = np.random.default_rng(17)
+    idx = m.nbr_idx.copy()
+    for p in range(m.P):
+        a, b = m.nbr_off[p], m.nbr_off[p + 1]
+        idx[a:b] = idx[a:b][rng.permutation(b - a)]
+    assert not np.array_equal(idx, m.nbr_idx)
+    shuffled = synth.Model(m.name, m.pos, m.nbr_off, idx, m.vel, m.chi, m.eta, m.freq, m.I_bc)
+    model = _gpu_model(rt, shuffled)
+    ds = rt.DirSet.uniform(1)
+    off, ids, Z = rt.trace(model, ds)
+    _, dirs, _ = orc.dirset_uniform(1)
+    e_off, e_ids, e_Z = orc.trace_all(m, dirs, np.arange(m.P, dtype=np.int32))
+    _assert_rays_equal((off, ids, Z), (e_off, e_ids, e_Z))
+
+
+def test_model_rejects_huge_positions(rt):
+    m = synth.tiny_model(6, P=20)
+    pos = m.pos.copy()
+    pos[3, 1] = 1e200
+    with pytest.raises(rt.RtError) as ex:
+        rt.Model.from_numpy(pos, m.nbr_off, m.nbr_idx)
+    assert ex.value.code == -1
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_trace_tiny(rt, orc, seed):
     m = synth.tiny_model(seed, P=60)
