@@ -752,8 +752,16 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     hipError_t e = hipMalloc((void**)&p->lens, sizeof(int32_t) * (size_t)std::max<int64_t>(p->n_rays, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&p->ray_off, sizeof(int64_t) * (size_t)(p->n_rays + 1));
     if (e == hipSuccess) e = hipMalloc(&p->scan_ws, scan_workspace(p->n_rays));
+    // the walk's origin order (Morton), used by the count pass here and by every walk of the plan
+    if (e == hipSuccess && n_origins > 0) {
+        std::vector<int32_t> ord;
+        e = morton_order(m, origins, n_origins, s, ord);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->order, sizeof(int32_t) * ord.size());
+        if (e == hipSuccess) e = hipMemcpy(p->order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess)
-        e = launch_trace_count(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, p->lens, s);
+        e = launch_trace_count(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, p->lens, s, p->order,
+                               p->o.trace_lanes);
     if (e == hipSuccess) e = launch_scan(p->lens, p->n_rays, p->ray_off, p->scan_ws, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&p->total, p->ray_off + p->n_rays, sizeof(int64_t), hipMemcpyDeviceToHost, s);
