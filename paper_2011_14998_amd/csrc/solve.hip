@@ -360,9 +360,14 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
 
 // One side of the line with velocity sampling and/or optical-depth sub-steps
 // (the plain sweep below is the same without them).
+// Per-point records of the refined sweep in LDS: words 0-1 row offset (bytes),
+// 2-3 projected velocity (FP64), 4-5 the FP64 interval length to the previous
+// list point, 6 the whole-step shift (uniform dx), 8-9 its FP64 fraction.
+constexpr int REF_STAGE_WORDS = 12;
+
 template <typename T, bool MOVING, bool UDX>
 __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, bool fwd,
-                                 T chi_o, T eta_o, T S_o, T I, SweepState<T>& st) {
+                                 T chi_o, T eta_o, T S_o, T I, SweepState<T>& st, uint32_t* stage) {
     Emitter<T> em;
     RealPt<T> prev{};
     T hds_prev = (T)0;
@@ -375,61 +380,87 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
     for (int hi = n - 1; hi >= 0; hi -= 64) {
         const int cnt = hi + 1 < 64 ? hi + 1 : 64;
         const int e = hi - lane;
-        const bool v = lane < cnt;
-        int64_t row_l = 0;
-        double ds64_l = 0.0, dot_l = 0.0, t64_l = 0.0;
-        int k_l = 0;
-        if (v) {
+        if (lane < cnt) {  // lane j stages the record of entry hi-j
+            uint32_t* w = stage + lane * REF_STAGE_WORDS;
             const int q = c.ids[base + e];
-            row_l = (int64_t)q * c.ld_bytes;
+            const uint64_t row = (uint64_t)q * (uint64_t)c.ld_bytes;
             const double z = c.Zr[base + e];
             const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
-            ds64_l = z - zi;
+            w[0] = (uint32_t)row;
+            w[1] = (uint32_t)(row >> 32);
+            *(double*)(w + 4) = z - zi;
+            double dot = 0.0;
             if (MOVING) {
                 const float* vq = c.vel + 3 * (int64_t)q;
                 const double dvx = (double)vq[0] - (double)c.vox;
                 const double dvy = (double)vq[1] - (double)c.voy;
                 const double dvz = (double)vq[2] - (double)c.voz;
-                dot_l = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
+                dot = (c.nx * dvx + c.ny * dvy) + c.nz * dvz;
                 if (UDX) {  // the same shift in every lane: formed once per point while staging
-                    const double delta = dot_l / c.dx0;
+                    const double delta = dot / c.dx0;
                     const double kf = floor(delta);
-                    k_l = (int)kf;
-                    t64_l = delta - kf;
+                    w[6] = (uint32_t)(int)kf;
+                    *(double*)(w + 8) = delta - kf;
                 }
             }
+            *(double*)(w + 2) = dot;
         }
-        for (int j = 0; j < cnt; ++j) {
-            RealPt<T> cur;
-            cur.row = readlane_64(row_l, j);
-            cur.dot = MOVING ? readlane_d(dot_l, j) : 0.0;
-            const double ds64 = readlane_d(ds64_l, j);
-            const char* cr = c.chi + cur.row;
-            const char* er = c.eta + cur.row;
+        __builtin_amdgcn_wave_barrier();
+        // the table values of point j are loaded while point j-1 is processed
+        struct Fetch {
+            int64_t row;
+            double dot, ds64, t64;
+            T ca, cb, ea, eb;
+        };
+        auto fetch = [&](int j) {
+            const uint32_t* w = stage + j * REF_STAGE_WORDS;
+            Fetch f;
+            f.row = uni64((int64_t)(((uint64_t)w[1] << 32) | w[0]));
+            f.dot = MOVING ? *(const double*)(w + 2) : 0.0;
+            f.ds64 = *(const double*)(w + 4);
+            f.t64 = 0.0;
+            const char* cr = c.chi + f.row;
+            const char* er = c.eta + f.row;
             if (MOVING) {
                 int k;
-                double t64;
                 if (UDX) {
-                    k = readlane_i(k_l, j);
-                    t64 = readlane_d(t64_l, j);
+                    k = (int)w[6];
+                    f.t64 = *(const double*)(w + 8);
                 } else {
-                    const double delta = cur.dot / lf.dx;
+                    const double delta = f.dot / lf.dx;
                     const double kf = floor(delta);
                     k = (int)kf;
-                    t64 = delta - kf;
+                    f.t64 = delta - kf;
                 }
-                const T t = (T)t64;
                 const int ks = k * (int)sizeof(T);
                 const uint32_t oa = (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
                 const uint32_t ob = (uint32_t)clamp_i32(lb_bytes - (int)sizeof(T) - ks, lo_bytes, hi_bytes);
-                const T ca = *(const T*)(cr + oa), cb = *(const T*)(cr + ob);
-                const T ea = *(const T*)(er + oa), eb = *(const T*)(er + ob);
-                cur.c = fma_<T>(t, cb - ca, ca);
-                cur.e = fma_<T>(t, eb - ea, ea);
-                cur.p = Pt64<T>{ca, cb, ca, cb, t64, 0.0};
+                f.ca = *(const T*)(cr + oa);
+                f.cb = *(const T*)(cr + ob);
+                f.ea = *(const T*)(er + oa);
+                f.eb = *(const T*)(er + ob);
             } else {
-                cur.c = *(const T*)(cr + lane_off);
-                cur.e = *(const T*)(er + lane_off);
+                f.ca = f.cb = *(const T*)(cr + lane_off);
+                f.ea = f.eb = *(const T*)(er + lane_off);
+            }
+            return f;
+        };
+        Fetch nxt = fetch(0);
+        for (int j = 0; j < cnt; ++j) {
+            const Fetch f = nxt;
+            if (j + 1 < cnt) nxt = fetch(j + 1);
+            const double ds64 = f.ds64;
+            RealPt<T> cur;
+            cur.row = f.row;
+            cur.dot = f.dot;
+            if (MOVING) {
+                const T t = (T)f.t64;
+                cur.c = fma_<T>(t, f.cb - f.ca, f.ca);
+                cur.e = fma_<T>(t, f.eb - f.ea, f.ea);
+                cur.p = Pt64<T>{f.ca, f.cb, f.ca, f.cb, f.t64, 0.0};
+            } else {
+                cur.c = f.ca;
+                cur.e = f.ea;
                 cur.p = Pt64<T>{cur.c, cur.c, cur.c, cur.c, 0.0, 0.0};
             }
             cur.S = cur.e * rcp<T>(cur.c);
@@ -440,6 +471,7 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
             hds_prev = (T)0.5 * (T)ds64;
             ++done;
         }
+        __builtin_amdgcn_wave_barrier();  // every lane has read this run before the next is staged
     }
     if (n > 0) {
         RealPt<T> org;
@@ -647,8 +679,8 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     const T S_o = eta_o * rcp<T>(chi_o);
     SweepState<T> m{}, p{};
     if (REF) {
-        sweep_ref<T, MOVING, UDX>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m);
-        sweep_ref<T, MOVING, UDX>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p);
+        sweep_ref<T, MOVING, UDX>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m, stage);
+        sweep_ref<T, MOVING, UDX>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p, stage);
     } else {
         if (a.small_tables) {
             sweep<T, MOVING, UDX, GROUP, true>(c, bm, nm, lf, lane, chi_o, I, m, stage);
@@ -667,8 +699,9 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
 
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
-    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * STAGE_WORDS];
-    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * STAGE_WORDS;
+    constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
+    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
+    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * WORDS;
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
@@ -693,8 +726,9 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
 // every wave reaches the end.
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
-    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * STAGE_WORDS];
-    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * STAGE_WORDS;
+    constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
+    __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
+    uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * WORDS;
     const int lane = threadIdx.x & 63;
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
