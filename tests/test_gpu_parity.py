@@ -461,3 +461,34 @@ def test_autotune_and_cache(rt, wind, tmp_path):
         plan.run()
         rt.sync_status()
         assert np.array_equal(J.cpu().numpy(), ref.cpu().numpy())
+
+
+@pytest.mark.parametrize("blocks", ["one", "two_same_dx", "two_dx"])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_plan_moving_blocks_bitwise(rt, blocks, fp64):
+    """Plans of moving models (spatial schedule, graph replays) give the direct
+    solve's bits for one block, two blocks of one width and two blocks of different
+    widths, and still do after the tables change in place between runs."""
+    torch = _torch()
+    m = synth.tiny_model(81, P=150, F=20, moving=True)
+    if blocks == "two_same_dx":
+        m.freq = synth.FreqGrid(np.array([12, 8], np.int32), np.array([-3.0, -2.0]), np.array([0.5, 0.5]))
+    elif blocks == "two_dx":
+        m.freq = synth.FreqGrid(np.array([12, 8], np.int32), np.array([-3.0, -2.0]), np.array([0.5, 0.7]))
+    prec = rt.RT_F64 if fp64 else rt.RT_F32
+    dt = np.float64 if fp64 else np.float32
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(2)
+    chi, eta = _t(m.chi.astype(dt)), _t(m.eta.astype(dt))
+    I_bc = _t(m.I_bc, torch.float64)
+    J = torch.empty((m.P, m.F), dtype=chi.dtype, device="cuda")
+    plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=prec,
+                   schedule=rt.SCHED_SPATIAL)
+    for scale in (1.0, 3.0):
+        chi.mul_(scale)
+        ref = rt.compute_J(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, precision=prec).cpu().numpy()
+        for use_graph in (False, True, True):
+            J.zero_()
+            plan.run(use_graph=use_graph)
+            rt.sync_status()
+            assert np.array_equal(J.cpu().numpy(), ref)
