@@ -105,7 +105,7 @@ rt_status rt_dirset_destroy(rt_dirset* set);
  * RT_ERR_MESH) and the positions (finite, every coordinate of magnitude at most
  * 1e150 so that the walk's squared distances stay finite; error RT_ERR_ARG)
  * and synchronises once on `stream` to read the verdict.  Builds a neighbour-
- * record table (48 bytes per neighbour entry: position, id, the neighbour's
+ * record table (36 bytes per neighbour entry: position, id, the neighbour's
  * own row; each row sorted by id) that the tracer reads instead of chasing
  * nbr_idx into pos and nbr_off.  The order of a point's neighbours in nbr_idx
  * does not affect any result.  The positions and lists must not change while

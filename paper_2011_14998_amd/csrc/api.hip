@@ -203,6 +203,7 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
     RT_HIP(hipGetDevice(&m->device));
     int32_t* bad = nullptr;
     hipError_t e = hipMalloc((void**)&m->nbr, sizeof(NbrRec) * (size_t)std::max<int64_t>(E, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&m->nid, sizeof(int32_t) * (size_t)std::max<int64_t>(E, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&m->rows, sizeof(int2) * (size_t)P);
     if (e == hipSuccess) e = hipMalloc((void**)&bad, sizeof(int32_t));
     if (e == hipSuccess) e = launch_fill_i32(bad, 1, 0, s);
@@ -214,12 +215,14 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
     if (e != hipSuccess) {
         rt_status st = hip_fail(e, "rt_model_create");
         if (m->nbr) (void)hipFree(m->nbr);
+        if (m->nid) (void)hipFree(m->nid);
         if (m->rows) (void)hipFree(m->rows);
         delete m;
         return st;
     }
     if (hbad) {
         if (m->nbr) (void)hipFree(m->nbr);
+        if (m->nid) (void)hipFree(m->nid);
         if (m->rows) (void)hipFree(m->rows);
         delete m;
         return fail(hbad == 8 ? RT_ERR_ARG : RT_ERR_MESH, std::string("rt_model_create: invalid model (") +
@@ -234,6 +237,7 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
 extern "C" rt_status rt_model_destroy(rt_model* m) {
     if (!m) return RT_OK;
     if (m->nbr) (void)hipFree(m->nbr);
+    if (m->nid) (void)hipFree(m->nid);
     if (m->rows) (void)hipFree(m->rows);
     delete m;
     return RT_OK;

@@ -78,15 +78,14 @@ struct rt_dirset {
     const double* d_w2() const { return dev.w2; }
 };
 
-// One neighbour entry as the tracer reads it: the neighbour's position, its
-// id, and its own CSR row (start, degree), so a step needs no further load to
-// continue from the chosen neighbour.
+// One neighbour entry as the tracer reads it (32 bytes, two 16-byte loads): the
+// neighbour's position and its own CSR row (start, degree), so a step needs no
+// further load to continue from the chosen neighbour.  Rows are sorted by
+// neighbour id; the ids themselves sit in a separate array in the same order.
 struct alignas(16) NbrRec {
     double x, y, z;
-    int32_t id;
     int32_t start;
     int32_t deg;
-    int32_t pad;
 };
 
 struct rt_model {
@@ -96,7 +95,8 @@ struct rt_model {
     const int32_t* idx = nullptr;
     int64_t E = 0;
     const float* vel = nullptr;
-    NbrRec* nbr = nullptr;  // owned: neighbour records in CSR order
+    NbrRec* nbr = nullptr;  // owned: neighbour records in CSR order, rows sorted by id
+    int32_t* nid = nullptr; // owned: the neighbour id of each record
     int2* rows = nullptr;   // owned: per point {row start, degree}
     int device = -1;
 };

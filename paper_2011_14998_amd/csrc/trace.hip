@@ -10,13 +10,16 @@
 // q = fma(-Z, d, R) per axis, D = fma(q.z, q.z, fma(q.y, q.y, q.x q.x)).  Every
 // list is bit-identical to any other evaluation of the same rule.
 //
-// Data layout: neighbour records {x, y, z, id, row start, degree} (48 bytes)
-// in CSR order and a per-point {row start, degree} table, both built once per
-// model, so a step reads one record per neighbour instead of an index, a
+// Data layout: neighbour records {x, y, z, row start, degree} (32 bytes, two
+// 16-byte loads) in CSR order with each row sorted by neighbour id, the ids in
+// a parallel array, and a per-point {row start, degree} table, all built once
+// per model, so a step reads one record per neighbour instead of an index, a
 // position and the next row's offsets; a group of 8 lanes reads a point's whole
-// row (~15 records, ~740 contiguous bytes) per step.  The tables of a
-// 50k-point Delaunay mesh (~37 MB) stay in the Infinity cache; the walk is
-// latency bound.
+// row (~15 records, ~500 contiguous bytes) per step.  The walk's loads are
+// limited by the vector memory instructions the L1 path serves per clock, so
+// a record is two loads, and a chosen neighbour's id is read only when its
+// list entry is stored.  The tables of a 50k-point Delaunay mesh (~28 MB)
+// stay in the Infinity cache.
 #include "rt_internal.h"
 
 #pragma clang fp contract(off)
@@ -30,23 +33,23 @@ constexpr int TRACE_BLOCK = 256;
 __global__ __launch_bounds__(256) void k_build_nbr(const double* __restrict__ pos, int64_t P,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ idx, int64_t E,
-                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ bad) {
+                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid,
+                                                    int32_t* __restrict__ bad) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= E) return;
     int32_t k = idx[e];
-    NbrRec r;
     if (k < 0 || k >= P) {
         atomicOr(bad, 1);
         k = 0;
     }
+    NbrRec r;
     r.x = pos[3 * (int64_t)k];
     r.y = pos[3 * (int64_t)k + 1];
     r.z = pos[3 * (int64_t)k + 2];
-    r.id = k;
     r.start = (int32_t)off[k];
     r.deg = (int32_t)(off[k + 1] - off[k]);
-    r.pad = 0;
     nbr[e] = r;
+    nid[e] = k;
 }
 
 __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
@@ -71,19 +74,22 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
 // The walk's per-lane scan relies on it: a lane meets its candidates in
 // ascending id, so keeping the first of equal distances keeps the smaller id.
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ off, int64_t P, int64_t E,
-                                                    NbrRec* __restrict__ nbr) {
+                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int64_t a = off[p], b = off[p + 1];
     if (a < 0 || a > b || b > E) return;
     for (int64_t e = a + 1; e < b; ++e) {
         const NbrRec r = nbr[e];
+        const int32_t k = nid[e];
         int64_t f = e - 1;
-        while (f >= a && nbr[f].id > r.id) {
+        while (f >= a && nid[f] > k) {
             nbr[f + 1] = nbr[f];
+            nid[f + 1] = nid[f];
             --f;
         }
         nbr[f + 1] = r;
+        nid[f + 1] = k;
     }
 }
 
@@ -125,7 +131,7 @@ __device__ inline double dpp_d(double v) {
 
 struct Cand {
     double D, Z;
-    int32_t id, start, deg;
+    int32_t e, start, deg;  // e: record index (in a row sorted by id, the same order as the id)
 };
 
 template <int CTRL>
@@ -178,7 +184,8 @@ __device__ inline int group_min_i(int v) {
 template <int MODE, int GL>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
-                                                        const NbrRec* __restrict__ nbr, int64_t P,
+                                                        const NbrRec* __restrict__ nbr,
+                                                        const int32_t* __restrict__ nid, int64_t P,
                                                         const int32_t* __restrict__ origins, int64_t n_origins,
                                                         int64_t R, const double* __restrict__ dirs, int per_origin,
                                                         int32_t* __restrict__ lens, const int64_t* __restrict__ ray_off,
@@ -236,13 +243,13 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     int32_t e0 = row0.x, deg = row0.y;
     int32_t n = 0;
     double Zc = 0.0;
-    int32_t keep_id = 0;  // entry n of the list waits in lane n mod GL
+    int32_t keep_e = 0;  // entry n of the list (as a record index) waits in lane n mod GL
     double keep_Z = 0.0;
     for (int32_t step = 0; step < (int32_t)P; ++step) {
         Cand b;
         b.D = __builtin_inf();
         b.Z = 0.0;
-        b.id = INT32_MAX;
+        b.e = INT32_MAX;
         b.start = 0;
         b.deg = 0;
         // GL lanes x U candidates per pass (32 entries); a lane's U loads are issued together
@@ -266,18 +273,19 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                 if (Dk < b.D) {  // ascending ids within the lane: the first of equal D has the smaller id
                     b.D = Dk;
                     b.Z = Zk;
-                    b.id = rec[u].id;
+                    b.e = (int32_t)(e0 + i);
                     b.start = rec[u].start;
                     b.deg = rec[u].deg;
                 }
             }
         }
-        // group minimum of (D, id); the smallest id breaks ties in D
+        // group minimum of (D, record index); within the sorted row the smaller
+        // index is the smaller id, so this is the minimum of (D, id)
         const double Dmin = group_min_d<GL>(b.D);
-        const int32_t idmin = group_min_i<GL>(b.D == Dmin ? b.id : INT32_MAX);
-        if (idmin == INT32_MAX) break;  // no forward neighbour: the ray leaves the model
+        const int32_t emin = group_min_i<GL>(b.D == Dmin ? b.e : INT32_MAX);
+        if (emin == INT32_MAX) break;  // no forward neighbour: the ray leaves the model
         // the winner's Z and row, read from the lane that holds it
-        const uint64_t won = __ballot(b.D == Dmin && b.id == idmin);
+        const uint64_t won = __ballot(b.D == Dmin && b.e == emin);
         const int gbase = (int)(threadIdx.x & 63) & ~(GL - 1);
         const uint32_t gbits = (uint32_t)(won >> gbase) & (uint32_t)((1ull << GL) - 1);
         const int src = gbase + __builtin_ctz(gbits);
@@ -291,11 +299,11 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
             }
             const int slot = n & (GL - 1);
             if (sub == slot) {
-                keep_id = idmin;
+                keep_e = emin;
                 keep_Z = Zn;
             }
             if (slot == GL - 1) {  // GL entries buffered: one contiguous store per list
-                ids[base + (n - (GL - 1)) + sub] = keep_id;
+                ids[base + (n - (GL - 1)) + sub] = nid[keep_e];
                 Zout[base + (n - (GL - 1)) + sub] = keep_Z;
             }
         }
@@ -307,7 +315,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     if (MODE != TRACE_COUNT) {  // entries still buffered
         const int32_t done = n & ~(GL - 1);
         if (sub < n - done) {
-            ids[base + done + sub] = keep_id;
+            ids[base + done + sub] = nid[keep_e];
             Zout[base + done + sub] = keep_Z;
         }
     }
@@ -432,11 +440,12 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
     hipLaunchKernelGGL(k_build_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
     if (m->E > 0)
         hipLaunchKernelGGL(k_build_nbr, dim3((unsigned)blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
-                           m->E, m->nbr, bad);
+                           m->E, m->nbr, m->nid, bad);
     hipLaunchKernelGGL(k_check_off, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->pos, m->P,
                        m->E, bad);
     if (m->E > 0)
-        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->E, m->nbr);
+        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->E, m->nbr,
+                           m->nid);
     return hipGetLastError();
 }
 
@@ -450,15 +459,15 @@ static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_
     int32_t* ew = MODE == TRACE_COUNT ? nullptr : error_word();
     if (gl == 16)
         hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(capped_blocks(blocks_for(n * 16, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
-                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     else if (gl == 8)
         hipLaunchKernelGGL((k_trace<MODE, 8>), dim3(capped_blocks(blocks_for(n * 8, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
-                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     else
         hipLaunchKernelGGL((k_trace<MODE, 4>), dim3(capped_blocks(blocks_for(n * 4, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
-                           m->rows, m->nbr, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
+                           m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
                            capacity, ew, order, num_xcds());
     return hipGetLastError();
 }
