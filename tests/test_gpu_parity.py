@@ -463,14 +463,14 @@ def test_autotune_and_cache(rt, wind, tmp_path):
         assert np.array_equal(J.cpu().numpy(), ref.cpu().numpy())
 
 
-@pytest.mark.parametrize("blocks", ["one", "two_same_dx", "two_dx"])
+@pytest.mark.parametrize("blocks", ["one", "two_same_dx", "two_dx", "static"])
 @pytest.mark.parametrize("fp64", [False, True])
 def test_plan_moving_blocks_bitwise(rt, blocks, fp64):
-    """Plans of moving models (spatial schedule, graph replays) give the direct
-    solve's bits for one block, two blocks of one width and two blocks of different
-    widths, and still do after the tables change in place between runs."""
+    """Plans (spatial schedule, graph replays) give the direct solve's bits for
+    one block, two blocks of one width, two blocks of different widths and a
+    static model, and still do after the tables change in place between runs."""
     torch = _torch()
-    m = synth.tiny_model(81, P=150, F=20, moving=True)
+    m = synth.tiny_model(81, P=150, F=20, moving=blocks != "static")
     if blocks == "two_same_dx":
         m.freq = synth.FreqGrid(np.array([12, 8], np.int32), np.array([-3.0, -2.0]), np.array([0.5, 0.5]))
     elif blocks == "two_dx":
