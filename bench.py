@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--closure-test", type=int, default=2, help="closure test models (seeds 510..)")
     ap.add_argument("--closure-steps", type=int, default=20000, help="closure training steps")
     ap.add_argument("--closure-batch", type=int, default=8192)
+    ap.add_argument("--closure-coarse-nside", type=int, default=1,
+                    help="nside of the coarse solve the closure corrects (1: 6 pairs, 2: 24, 4: 96)")
     ap.add_argument("--closure-lr", type=float, default=2e-3)
     ap.add_argument("--dv-max", type=float, default=0.0,
                     help="adaptive velocity sampling: split line intervals whose projected velocity changes by "
@@ -540,13 +542,14 @@ def run_closure(args):
             models[m.meta["seed"]] = m
             _log(f"generated wind seed {m.meta['seed']}: {m.P} points, {m.E} entries ({sec:.0f} s)")
     gen_s = time.perf_counter() - t0
-    ds1, ds2, ds8 = rt.DirSet.uniform(1), rt.DirSet.uniform(2), rt.DirSet.uniform(8)
+    nc = args.closure_coarse_nside
+    ds1, ds2, ds8 = rt.DirSet.uniform(nc), rt.DirSet.uniform(2), rt.DirSet.uniform(8)
     labs = []
     t0 = time.perf_counter()
     for sd in seeds_train:
         dm = cl.DeviceModel.from_synth(models.pop(sd))
         labs.append(cl.label(dm, ds1, ds8, verbose=True))
-        _log(f"labelled seed {sd}: nside-1 {labs[-1].coarse.ms:.0f} ms, nside-8 {labs[-1].fine.ms:.0f} ms")
+        _log(f"labelled seed {sd}: nside-{nc} {labs[-1].coarse.ms:.0f} ms, nside-8 {labs[-1].fine.ms:.0f} ms")
     label_s = time.perf_counter() - t0
     X, T, norm = cl.dataset(labs)
     del labs
@@ -591,7 +594,7 @@ def run_closure(args):
         "dtype": "bf16 mfma / f32 accumulate (network), f32 sweep, f64 geometry",
         "data": "synthetic (seeded analytic winds)",
         "config": {"workload": f"learned closure, winds of {P} points, train seeds {seeds_train}, test seeds "
-                               f"{seeds_test}; coarse nside 1, fine nside 8, F=64",
+                               f"{seeds_test}; coarse nside {nc}, fine nside 8, F=64",
                    "points": P, "train_models": len(seeds_train), "test_models": len(seeds_test),
                    "steps": args.closure_steps, "batch": args.closure_batch, "lr": args.closure_lr},
         "headline": head, "fallback_sweep": summary, "per_model": results,
