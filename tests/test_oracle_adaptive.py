@@ -155,3 +155,21 @@ def test_empty_sample_refines_lowest_indices(orc):
     lv1 = sorted(pix[0][lev[0] == 1].tolist())
     canon1 = [p for p in range(48) if orc.hp_antipode(2, p) > p]
     assert lv1 == canon1[12:]  # counts all zero: the 12 smallest indices are refined
+
+
+def test_ray_counts_printed_in_the_paper(orc):
+    """The stored fixture holds the ray counts the paper prints (Section 3.2.1):
+    the oracle's regular and adaptive sets have exactly those."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ray_counts.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
+    for kind, lmin, lmax, rays in rows:
+        lmin, lmax, rays = int(lmin), int(lmax), int(rays)
+        if kind == "regular":
+            _, dirs, w2 = orc.dirset_uniform(2 ** lmax)
+            assert 2 * len(dirs) == rays
+            # eq. 4: each ray weighs 1/(12 4^l); a pair carries both rays' weight
+            assert np.all(w2 == 2.0 / rays)
+        else:
+            assert 2 * orc.dirset_adaptive_R(lmin, lmax) == rays

@@ -37,3 +37,25 @@ def test_bounds_and_symmetry():
     i = 11
     nb = m.nbr_idx[m.nbr_off[i]:m.nbr_off[i + 1]]
     assert np.isclose(L[i], sum(np.linalg.norm(m.pos[i] - m.pos[n]) for n in nb) / len(nb))
+
+
+def _golden_table1():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_reduction_parameters.txt")
+    rows = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, *vals = line.split()
+            rows[name] = tuple(float(v) for v in vals)
+    return rows
+
+
+def test_table1_constants_are_the_papers():
+    """The oracle's and the library's reduction parameters equal the values the
+    paper prints in Table 1 (stored fixture)."""
+    import paper_2011_14998_amd.binding as b
+    t = _golden_table1()
+    assert set(t) == {"AMR", "SPH"}
+    for k, v in t.items():
+        assert tuple(om.TABLE1[k]) == v
+        assert tuple(b.REDUCTION_PARAMS[k]) == v
