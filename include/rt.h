@@ -270,7 +270,17 @@ rt_status rt_plan_copy_rays(const rt_plan* plan, int64_t* ray_off, int32_t* ray_
  * (eq. 3 before the weighted sum; dtype of the precision), into a caller device
  * buffer.  Async. */
 rt_status rt_plan_copy_u(const rt_plan* plan, void* u, void* stream);
+/* Destroy a plan.  Waits for the device to be idle (as freeing device memory
+ * does), then keeps the plan's large buffers (ray lists, padded slots, u; each
+ * 64 MiB or more) in a per-device cache of at most 96 GiB, from which later
+ * plans of similar size take their buffers instead of allocating: building
+ * plan after plan over origin chunks then maps no new memory.  An allocation
+ * that fails releases the cache of its device and retries once. */
 rt_status rt_plan_destroy(rt_plan* plan);
+/* Free every cached buffer (all devices). */
+rt_status rt_release_cached_memory(void);
+/* Bytes currently held by the cache (all devices). */
+rt_status rt_cached_memory(size_t* bytes);
 
 /* Re-capture a plan's graph with other scheduling options (schedule, group,
  * trace_lanes, waves_per_cu, n_bins; precision and threshold stay), reusing its

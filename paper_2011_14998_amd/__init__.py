@@ -22,12 +22,14 @@ from .binding import (  # noqa: F401
     Plan,
     RtError,
     autotune,
+    cached_memory,
     closure_apply,
     closure_feature_stats,
     closure_features,
     closure_merge,
     closure_normalize,
     closure_targets,
+    release_cached_memory,
     compute_J,
     healpix_vec2pix,
     load,

@@ -66,6 +66,8 @@ _SIGS = {
     "rt_plan_copy_rays": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rt_plan_profile": (_i32, [_vp, _i32, _vp, _vp]),
     "rt_plan_destroy": (_i32, [_vp]),
+    "rt_release_cached_memory": (_i32, []),
+    "rt_cached_memory": (_i32, [C.POINTER(C.c_size_t)]),
     "rt_autotune": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC), _vp, _vp,
                            C.POINTER(SolveOptsC), _i32, C.c_char_p, _i32, _vp, C.POINTER(SolveOptsC),
                            C.POINTER(_dbl)]),
@@ -260,6 +262,18 @@ def spatial_order(model: Model, origins=None, n_origins=None, stream=None) -> np
     out = np.empty(max(n_origins, 1), np.int32)
     _check(load().rt_spatial_order(model._h, _ptr(origins), n_origins, out.ctypes.data, _stream(stream)))
     return out[:n_origins]
+
+
+def release_cached_memory():
+    """Free the device buffers that destroyed plans left in the library's cache."""
+    _check(load().rt_release_cached_memory())
+
+
+def cached_memory() -> int:
+    """Bytes of device memory held by the library's cache of plan buffers."""
+    b = _sz()
+    _check(load().rt_cached_memory(C.byref(b)))
+    return int(b.value)
 
 
 def sync_status(stream=None):

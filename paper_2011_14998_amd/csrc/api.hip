@@ -24,7 +24,87 @@ int g_xcds[MAX_DEVICES] = {0};
 std::mutex g_mu;
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Cache of large device buffers freed by plans (lists, u), per device, so that
+// building plan after plan over origin chunks does not map and unmap tens of
+// GB each time.  A request takes the smallest cached block of its device that
+// is at least as large and at most twice as large (plus 64 MiB); blocks beyond
+// POOL_MAX_BYTES held in total are freed instead of cached.
+struct PoolBlock {
+    void* p;
+    size_t bytes;
+    int dev;
+};
+std::mutex g_pool_mu;
+std::vector<PoolBlock> g_pool;
+size_t g_pool_bytes = 0;
+constexpr size_t POOL_MIN_BYTES = (size_t)64 << 20;   // smaller buffers go straight to hipMalloc
+constexpr size_t POOL_MAX_BYTES = (size_t)96 << 30;
+
+void pool_release_device(int dev) {  // with g_pool_mu held
+    for (size_t i = 0; i < g_pool.size();) {
+        if (g_pool[i].dev == dev) {
+            (void)hipFree(g_pool[i].p);
+            g_pool_bytes -= g_pool[i].bytes;
+            g_pool[i] = g_pool.back();
+            g_pool.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
 }  // namespace
+
+// Buffer of at least `bytes` (exactly the requested size is what the caller may use).
+hipError_t pool_alloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (bytes >= POOL_MIN_BYTES) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        size_t best = g_pool.size();
+        for (size_t i = 0; i < g_pool.size(); ++i) {
+            const PoolBlock& b = g_pool[i];
+            if (b.dev == dev && b.bytes >= bytes && b.bytes <= 2 * bytes + POOL_MIN_BYTES &&
+                (best == g_pool.size() || b.bytes < g_pool[best].bytes))
+                best = i;
+        }
+        if (best < g_pool.size()) {
+            *ptr = g_pool[best].p;
+            g_pool_bytes -= g_pool[best].bytes;
+            g_pool[best] = g_pool.back();
+            g_pool.pop_back();
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(ptr, bytes);
+    if (e == hipErrorOutOfMemory) {  // give the cached blocks back and try once more
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            pool_release_device(dev);
+        }
+        e = hipMalloc(ptr, bytes);
+    }
+    return e;
+}
+
+// Return a buffer from pool_alloc on device `dev`.  The caller guarantees no work still uses it.
+void pool_free(void* ptr, size_t bytes, int dev) {
+    if (!ptr) return;
+    if (bytes < POOL_MIN_BYTES) {
+        (void)hipFree(ptr);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_bytes + bytes > POOL_MAX_BYTES) {
+        (void)hipFree(ptr);
+        return;
+    }
+    g_pool.push_back(PoolBlock{ptr, bytes, dev});
+    g_pool_bytes += bytes;
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -534,6 +614,8 @@ struct rt_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool exact = false;  // RT_WALK_EXACT: walk straight into the creation-time slots
+    // bytes of the cached large buffers (ids, Z, padded slots, u)
+    size_t ids_bytes = 0, Z_bytes = 0, pids_bytes = 0, pZ_bytes = 0, u_bytes = 0;
 };
 
 // Stages: 0 count, 1 scan, 2 write, 3 bin (+ queue reset), 4 sweep, 5 reduce.
@@ -588,11 +670,19 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
 }
 
 static void plan_free(rt_plan* p) {
+    // the cached buffers may be handed to the next plan at once: no work of this one may still run
+    // (hipFree, which the small buffers go through, waits for the device the same way)
+    (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    for (void* q : {(void*)p->lens, (void*)p->ray_off, (void*)p->ids, (void*)p->Z, p->scan_ws, p->solve_ws,
-                    (void*)p->pids, (void*)p->pZ, (void*)p->order, p->u_buf, p->bin_buf})
+    for (void* q : {(void*)p->lens, (void*)p->ray_off, p->scan_ws, p->solve_ws, (void*)p->order, p->bin_buf})
         if (q) (void)hipFree(q);
+    const int dev = p->m->device;
+    pool_free(p->ids, p->ids_bytes, dev);
+    pool_free(p->Z, p->Z_bytes, dev);
+    pool_free(p->pids, p->pids_bytes, dev);
+    pool_free(p->pZ, p->pZ_bytes, dev);
+    pool_free(p->u_buf, p->u_bytes, dev);
     delete p;
 }
 
@@ -770,8 +860,10 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (e == hipSuccess)
         e = hipMemcpyAsync(&p->total, p->ray_off + p->n_rays, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->ids, sizeof(int32_t) * (size_t)std::max<int64_t>(p->total, 1));
-    if (e == hipSuccess) e = hipMalloc((void**)&p->Z, sizeof(double) * (size_t)std::max<int64_t>(p->total, 1));
+    p->ids_bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(p->total, 1);
+    p->Z_bytes = sizeof(double) * (size_t)std::max<int64_t>(p->total, 1);
+    if (e == hipSuccess) e = pool_alloc((void**)&p->ids, p->ids_bytes);
+    if (e == hipSuccess) e = pool_alloc((void**)&p->Z, p->Z_bytes);
     p->exact = p->o.walk == RT_WALK_EXACT;
     // Longest ray: the padded single-pass walk is used when its slots fit the budget.
     int32_t longest = 0;
@@ -787,8 +879,10 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     if (e == hipSuccess && p->n_rays > 0 && p->o.walk == RT_WALK_PADDED && !(opts && opts->padded_trace_budget < 0) &&
         pad_bytes <= budget) {
         p->cap = std::max(longest, 1);
-        e = hipMalloc((void**)&p->pids, sizeof(int32_t) * (size_t)p->n_rays * p->cap);
-        if (e == hipSuccess) e = hipMalloc((void**)&p->pZ, sizeof(double) * (size_t)p->n_rays * p->cap);
+        p->pids_bytes = sizeof(int32_t) * (size_t)p->n_rays * p->cap;
+        p->pZ_bytes = sizeof(double) * (size_t)p->n_rays * p->cap;
+        e = pool_alloc((void**)&p->pids, p->pids_bytes);
+        if (e == hipSuccess) e = pool_alloc((void**)&p->pZ, p->pZ_bytes);
     }
     if (e != hipSuccess) {
         st = hip_fail(e, "rt_plan_create");
@@ -804,7 +898,8 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     }
     p->base = p->a;
     const size_t es = p->o.precision == RT_F64 ? 8 : 4;
-    e = hipMalloc(&p->u_buf, es * (size_t)std::max<int64_t>(n_origins * set->R * p->a.F, 1));
+    p->u_bytes = es * (size_t)std::max<int64_t>(n_origins * set->R * p->a.F, 1);
+    e = pool_alloc(&p->u_buf, p->u_bytes);
     if (e != hipSuccess) {
         st = hip_fail(e, "rt_plan_create: u buffer");
         plan_free(p);
@@ -885,6 +980,21 @@ extern "C" rt_status rt_plan_copy_u(const rt_plan* p, void* u, void* stream) {
 
 extern "C" rt_status rt_plan_destroy(rt_plan* p) {
     if (p) plan_free(p);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_release_cached_memory(void) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (const PoolBlock& b : g_pool) (void)hipFree(b.p);
+    g_pool.clear();
+    g_pool_bytes = 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_cached_memory(size_t* bytes) {
+    if (!bytes) return fail(RT_ERR_ARG, "rt_cached_memory: NULL output");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    *bytes = g_pool_bytes;
     return RT_OK;
 }
 

@@ -492,3 +492,44 @@ def test_plan_moving_blocks_bitwise(rt, blocks, fp64):
             plan.run(use_graph=use_graph)
             rt.sync_status()
             assert np.array_equal(J.cpu().numpy(), ref)
+
+
+def test_plan_buffer_cache(rt, wind):
+    """Destroyed plans leave their large buffers in the library's cache; the next
+    plans take them (no new allocation) and give the same bits as fresh ones, and
+    releasing the cache empties it."""
+    import gc
+    torch = _torch()
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(2)
+    c32, e32, _, _ = synth.to_fp32_tables(wind.chi, wind.eta)
+    chi, eta = _t(c32), _t(e32)
+    I_bc = _t(wind.I_bc, torch.float64)
+    rt.release_cached_memory()
+    assert rt.cached_memory() == 0
+    n = 20_000
+    org = _t(np.arange(n, dtype=np.int32))
+
+    def run(origins, k):
+        J = torch.empty((k, wind.F), dtype=torch.float32, device="cuda")
+        plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=origins,
+                       precision=rt.RT_F32, schedule=rt.SCHED_SPATIAL)
+        plan.run()
+        rt.sync_status()
+        out = J.cpu().numpy()
+        del plan
+        gc.collect()
+        return out
+
+    ref = run(org, n)
+    held = rt.cached_memory()
+    assert held >= 3 * (64 << 20)  # ids, Z and u of the plan
+    again = run(org, n)
+    assert np.array_equal(again, ref)
+    assert rt.cached_memory() == held  # the second plan took the same buffers and returned them
+    half = run(org[: n // 2], n // 2)  # smaller plans fit the cached blocks too
+    direct = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org[: n // 2],
+                          precision=rt.RT_F32).cpu().numpy()
+    assert np.array_equal(half, direct)
+    rt.release_cached_memory()
+    assert rt.cached_memory() == 0
