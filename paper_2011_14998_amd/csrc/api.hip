@@ -690,9 +690,19 @@ static void plan_free(rt_plan* p) {
 // 21 bits per axis over the bounding box of the origins.
 static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
                                std::vector<int32_t>& order) {
-    std::vector<double> pos((size_t)m->P * 3);
+    std::lock_guard<std::mutex> lk(m->host_mu);
+    std::vector<double>& pos = m->host_pos;
     std::vector<int32_t> org;
-    hipError_t e = hipMemcpyAsync(pos.data(), m->pos, sizeof(double) * pos.size(), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipSuccess;
+    if (pos.empty()) {
+        pos.resize((size_t)m->P * 3);
+        e = hipMemcpyAsync(pos.data(), m->pos, sizeof(double) * pos.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            pos.clear();
+            return e;
+        }
+    }
     if (e == hipSuccess && origins) {
         org.resize((size_t)n_o);
         e = hipMemcpyAsync(org.data(), origins, sizeof(int32_t) * org.size(), hipMemcpyDeviceToHost, s);

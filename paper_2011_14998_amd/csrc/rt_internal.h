@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,10 @@ struct rt_model {
     int32_t* nid = nullptr; // owned: the neighbour id of each record
     int2* rows = nullptr;   // owned: per point {row start, degree}
     int device = -1;
+    // host copy of the positions, made on first need (spatial orders of plans); the
+    // positions may not change while the handle lives
+    mutable std::vector<double> host_pos;
+    mutable std::mutex host_mu;
 };
 
 namespace rt {
