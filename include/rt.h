@@ -272,10 +272,13 @@ rt_status rt_plan_copy_rays(const rt_plan* plan, int64_t* ray_off, int32_t* ray_
 rt_status rt_plan_copy_u(const rt_plan* plan, void* u, void* stream);
 /* Destroy a plan.  Waits for the device to be idle (as freeing device memory
  * does), then keeps the plan's large buffers (ray lists, padded slots, u; each
- * 64 MiB or more) in a per-device cache of at most 96 GiB, from which later
+ * 64 MiB or more) in a per-device cache of at most 32 GiB, from which later
  * plans of similar size take their buffers instead of allocating: building
- * plan after plan over origin chunks then maps no new memory.  An allocation
- * that fails releases the cache of its device and retries once. */
+ * plan after plan over origin chunks then maps no new memory.  A request that
+ * no cached block fits frees the smaller blocks of its device; an allocation
+ * that fails releases the cache of its device and retries once.  Memory held
+ * by the cache is not available to other allocators (e.g. PyTorch's): call
+ * rt_release_cached_memory when the plans are done. */
 rt_status rt_plan_destroy(rt_plan* plan);
 /* Free every cached buffer (all devices). */
 rt_status rt_release_cached_memory(void);

@@ -131,6 +131,7 @@ def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: flo
         ms += e0.elapsed_time(e1)
         del Jw, Uw
     rt.sync_status()
+    rt.release_cached_memory()  # the chunks' plans shared their buffers; free them for other allocators
     return SolveResult(J, ms, build_s, entries, U)
 
 

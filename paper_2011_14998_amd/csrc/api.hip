@@ -28,8 +28,9 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Cache of large device buffers freed by plans (lists, u), per device, so that
 // building plan after plan over origin chunks does not map and unmap tens of
 // GB each time.  A request takes the smallest cached block of its device that
-// is at least as large and at most twice as large (plus 64 MiB); blocks beyond
-// POOL_MAX_BYTES held in total are freed instead of cached.
+// is at least as large and at most twice as large (plus 64 MiB); without a fit
+// the smaller blocks of its device are freed; blocks beyond POOL_MAX_BYTES held
+// in total are freed instead of cached.
 struct PoolBlock {
     void* p;
     size_t bytes;
@@ -39,7 +40,7 @@ std::mutex g_pool_mu;
 std::vector<PoolBlock> g_pool;
 size_t g_pool_bytes = 0;
 constexpr size_t POOL_MIN_BYTES = (size_t)64 << 20;   // smaller buffers go straight to hipMalloc
-constexpr size_t POOL_MAX_BYTES = (size_t)96 << 30;
+constexpr size_t POOL_MAX_BYTES = (size_t)32 << 30;
 
 void pool_release_device(int dev) {  // with g_pool_mu held
     for (size_t i = 0; i < g_pool.size();) {
@@ -76,6 +77,17 @@ hipError_t pool_alloc(void** ptr, size_t bytes) {
             g_pool[best] = g_pool.back();
             g_pool.pop_back();
             return hipSuccess;
+        }
+        // no fit: the blocks too small for this request go back to the device
+        for (size_t i = 0; i < g_pool.size();) {
+            if (g_pool[i].dev == dev && g_pool[i].bytes < bytes) {
+                (void)hipFree(g_pool[i].p);
+                g_pool_bytes -= g_pool[i].bytes;
+                g_pool[i] = g_pool.back();
+                g_pool.pop_back();
+            } else {
+                ++i;
+            }
         }
     }
     e = hipMalloc(ptr, bytes);
