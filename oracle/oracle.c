@@ -547,6 +547,88 @@ OR_API double or_feautrier_u(int64_t N, int64_t m, const double* dtau, const dou
     return (S[m] + A * Zf + C * W) / (1.0 + A * F / (1.0 + F) + C * G / (1.0 + G));
 }
 
+/* u at row m of the fourth-order Hermitian discretisation of the same equation
+ * (the scheme of Auer 1976 that the paper names for its solver, Section 2.1;
+ * the paper gives no formulas, so the rows are derived here).
+ *
+ * Interior rows: with f = u - S = u" (eq. 1) and the outer and inner steps
+ * a = dtau_{d-1}, b = dtau_d, the compact relation
+ *   (u_{d+1} - u_d)/b - (u_d - u_{d-1})/a = w_- f_{d-1} + w_0 f_d + w_+ f_{d+1}
+ * is exact for every polynomial u of degree <= 4 when
+ *   w_- = (a^3 + 2a^2 b - b^3) / (12 a (a+b)),  w_+ = (b^3 + 2a b^2 - a^3) / (12 b (a+b)),
+ *   w_- + w_0 + w_+ = (a+b)/2
+ * (h/12, 10h/12, h/12 on a uniform grid).  Divided by (a+b)/2, with
+ * alpha, beta, gamma = w_-, w_0, w_+ over (a+b)/2 and A, C the second-order
+ * coefficients above:
+ *   -(A - alpha) u_{d-1} + (1 + A - alpha + C - gamma) u_d - (C - gamma) u_{d+1}
+ *      = alpha S_{d-1} + beta S_d + gamma S_{d+1}.
+ * Boundary rows (third order): the second-order condition with the next
+ * Taylor term, u''' = u' - S', the slope of S taken one-sided:
+ *   (u_1 - u_0)/dt = (u_0 - I)(1 + dt^2/6) + (dt/2)(u_0 - S_0) - (dt/6)(S_1 - S_0),
+ * i.e. (1 + E + 2/dt^2) u_0 - (2/dt^2) u_1 = S_0 + E I + (S_1 - S_0)/3 with
+ * E = (2/dt)(1 + dt^2/6); the mirror image at d = N-1.
+ * The system is eliminated from both ends towards m in the same rescaled form
+ * as the second-order rows (u_d = u_{d+1}/(1+F_d) + Z_d forward, the mirror image
+ * backward), which loses nothing to cancellation for small steps as long as
+ * the off-diagonals -(A - alpha), -(C - gamma) are non-positive: true while every
+ * step is below about 3.46 (2 sqrt 3 on a uniform grid); a row beyond that limit
+ * makes the result NaN (the caller keeps steps small, e.g. with dtau_max).
+ * The weights assume S smooth in tau: between very unequal steps the weight of
+ * the far neighbour grows like -(long step)/(6 short step) and amplifies jumps
+ * of S.  N == 1 returns I. */
+OR_API double or_feautrier_u_hermite(int64_t N, int64_t m, const double* dtau, const double* S, double I) {
+    if (N == 1) return I;
+    /* row d: -Am u_{d-1} + (1 + Am + Cp) u_d - Cp u_{d+1} = Rd; the end rows have
+     * (Am, Cp) = (0, K) at d = 0 and (K, 0) at d = N-1 and an extra E on the diagonal */
+#define OR_HERM_ROW(d, Am, Cp, Ex, Rd)                                                         \
+    do {                                                                                       \
+        if ((d) == 0 || (d) == N - 1) {                                                        \
+            const double dt_ = (d) == 0 ? dtau[0] : dtau[N - 2];                               \
+            const int64_t nb_ = (d) == 0 ? 1 : N - 2;                                          \
+            const double K_ = 2.0 / (dt_ * dt_);                                               \
+            Ex = (2.0 / dt_) * (1.0 + dt_ * dt_ / 6.0);                                        \
+            Am = (d) == 0 ? 0.0 : K_;                                                          \
+            Cp = (d) == 0 ? K_ : 0.0;                                                          \
+            Rd = S[d] + Ex * I + (S[nb_] - S[d]) / 3.0;                                        \
+        } else {                                                                               \
+            const double a_ = dtau[(d) - 1], b_ = dtau[d], h_ = 0.5 * (a_ + b_);               \
+            const double wm_ = (a_ * a_ * a_ + 2.0 * a_ * a_ * b_ - b_ * b_ * b_) / (12.0 * a_ * (a_ + b_)); \
+            const double wp_ = (b_ * b_ * b_ + 2.0 * a_ * b_ * b_ - a_ * a_ * a_) / (12.0 * b_ * (a_ + b_)); \
+            const double al_ = wm_ / h_, ga_ = wp_ / h_, be_ = 1.0 - al_ - ga_;                \
+            Am = 2.0 / (a_ * (a_ + b_)) - al_;                                                 \
+            Cp = 2.0 / (b_ * (a_ + b_)) - ga_;                                                 \
+            Ex = 0.0;                                                                          \
+            Rd = al_ * S[(d) - 1] + be_ * S[d] + ga_ * S[(d) + 1];                             \
+            if (!(Am >= 0.0) || !(Cp > 0.0)) bad = 1;                                          \
+        }                                                                                      \
+    } while (0)
+    int bad = 0;
+    /* forward over rows 0 .. m-1: u_d = u_{d+1}/(1+F) + Z */
+    double F = 0.0, Z = 0.0;
+    for (int64_t d = 0; d < m; ++d) {
+        double Am, Cp, Ex, Rd;
+        OR_HERM_ROW(d, Am, Cp, Ex, Rd);
+        const double Fn = (1.0 + Ex + Am * F / (1.0 + F)) / Cp;
+        Z = (Rd + Am * Z) / (Cp * (1.0 + Fn));
+        F = Fn;
+    }
+    /* backward over rows N-1 .. m+1: u_d = u_{d-1}/(1+G) + W */
+    double G = 0.0, W = 0.0;
+    for (int64_t d = N - 1; d > m; --d) {
+        double Am, Cp, Ex, Rd;
+        OR_HERM_ROW(d, Am, Cp, Ex, Rd);
+        const double Gn = (1.0 + Ex + Cp * G / (1.0 + G)) / Am;
+        W = (Rd + Cp * W) / (Am * (1.0 + Gn));
+        G = Gn;
+    }
+    double Am, Cp, Ex, Rd;
+    OR_HERM_ROW(m, Am, Cp, Ex, Rd);
+#undef OR_HERM_ROW
+    if (bad) return NAN;  /* a step beyond the rows' limit: no value (the caller reports it) */
+    /* row m with u_{m-1} = u_m/(1+F) + Z and u_{m+1} = u_m/(1+G) + W */
+    return (Rd + Am * Z + Cp * W) / (1.0 + Ex + Am * F / (1.0 + F) + Cp * G / (1.0 + G));
+}
+
 /* ------------------------------------------------------- full J at origins */
 
 typedef struct {
@@ -749,8 +831,8 @@ OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, co
                             const double* blk_dx, const double* chi, const double* eta, int64_t ld,
                             const double* I_bc, int64_t R, const double* dirs, const double* w2,
                             int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
-                            double dv_max, double dtau_max, int64_t max_sub, double* J, double* u_out,
-                            int nthreads) {
+                            double dv_max, double dtau_max, int64_t max_sub, int32_t scheme, double* J,
+                            double* u_out, int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -834,12 +916,14 @@ OR_API int or_compute_J_sub(int64_t P, const double* pos, const int64_t* off, co
                         if (dtau_max > 0.0) {
                             int64_t mr = 0;
                             const int64_t Nr = refine_line(&w, Nv, mv, dtau_max, max_sub, &mr);
-                            u = or_feautrier_u(Nr, mr, w.rdtau, w.rS, I_bc[f]);
+                            u = scheme == 1 ? or_feautrier_u_hermite(Nr, mr, w.rdtau, w.rS, I_bc[f])
+                                            : or_feautrier_u(Nr, mr, w.rdtau, w.rS, I_bc[f]);
                         } else {
                             ws_grow_refined(&w, Nv);
                             for (int64_t i = 0; i + 1 < Nv; ++i)
                                 w.rdtau[i] = (0.5 * (w.vchi[i] + w.vchi[i + 1])) * w.vds[i];
-                            u = or_feautrier_u(Nv, mv, w.rdtau, w.vS, I_bc[f]);
+                            u = scheme == 1 ? or_feautrier_u_hermite(Nv, mv, w.rdtau, w.vS, I_bc[f])
+                                            : or_feautrier_u(Nv, mv, w.rdtau, w.vS, I_bc[f]);
                         }
                         if (!(u == u)) err = 1;
                         if (u_out) u_out[(oi * R + r) * F + f] = u;
@@ -862,5 +946,5 @@ OR_API int or_compute_J(int64_t P, const double* pos, const int64_t* off, const 
                         int32_t per_origin_dirs, const int32_t* origins, int64_t n_origins,
                         double* J, double* u_out, int nthreads) {
     return or_compute_J_sub(P, pos, off, idx, vel, F, nblk, blk_len, blk_dx, chi, eta, ld, I_bc, R, dirs, w2,
-                            per_origin_dirs, origins, n_origins, 0.0, 0.0, 1, J, u_out, nthreads);
+                            per_origin_dirs, origins, n_origins, 0.0, 0.0, 1, 0, J, u_out, nthreads);
 }

@@ -58,6 +58,8 @@ def lib():
         L.or_trace_all.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp, i64, vp, vp, vp, C.c_int]
         L.or_feautrier_u.restype = C.c_double
         L.or_feautrier_u.argtypes = [i64, i64, vp, vp, C.c_double]
+        L.or_feautrier_u_hermite.restype = C.c_double
+        L.or_feautrier_u_hermite.argtypes = [i64, i64, vp, vp, C.c_double]
         L.or_fx_sqrt.restype = C.c_double
         L.or_fx_sqrt.argtypes = [C.c_double]
         L.or_fx_atan2.restype = C.c_double
@@ -73,7 +75,7 @@ def lib():
                                    vp, i32, vp, i64, vp, vp, C.c_int]
         L.or_compute_J_sub.restype = C.c_int
         L.or_compute_J_sub.argtypes = [i64, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, i64, vp, i64, vp,
-                                       vp, i32, vp, i64, C.c_double, C.c_double, i64, vp, vp, C.c_int]
+                                       vp, i32, vp, i64, C.c_double, C.c_double, i64, i32, vp, vp, C.c_int]
         _ = dp
         _lib = L
     return _lib
@@ -206,12 +208,20 @@ def feautrier_u(dtau, S, m: int, I: float) -> float:
     return lib().or_feautrier_u(len(S), m, _p(dtau), _p(S), float(I))
 
 
+def feautrier_u_hermite(dtau, S, m: int, I: float) -> float:
+    dtau = _c(dtau, np.float64)
+    S = _c(S, np.float64)
+    return lib().or_feautrier_u_hermite(len(S), m, _p(dtau), _p(S), float(I))
+
+
 def compute_J(model, dirs, w2, origins=None, chi=None, eta=None, I_bc=None, nthreads: int = 0,
-              want_u: bool = False, dtau_max: float = 0.0, max_sub: int = 1024, dv_max: float = 0.0):
+              want_u: bool = False, dtau_max: float = 0.0, max_sub: int = 1024, dv_max: float = 0.0,
+              scheme: int = 0):
     """J[n_origins][F] (and optionally u[n_origins][R][F]) in FP64.  dv_max > 0 samples line
     intervals whose projected velocity changes by more than dv_max Doppler widths (Section 2.1.1);
     dtau_max > 0 then splits every interval into optical-depth sub-steps (Section 2.1.2, eq. 2);
-    at most max_sub parts per interval for each."""
+    at most max_sub parts per interval for each.  scheme 0: second-order Feautrier rows; 1: the
+    fourth-order Hermitian rows with third-order boundary conditions (Section 2.1)."""
     L = lib()
     dirs = _c(dirs, np.float64)
     w2 = _c(w2, np.float64)
@@ -235,8 +245,8 @@ def compute_J(model, dirs, w2, origins=None, chi=None, eta=None, I_bc=None, nthr
     u = np.zeros((n_o, R, F)) if want_u else None
     rc = L.or_compute_J_sub(model.P, _p(pos), _p(off), _p(idx), _p(vel), F, len(blk_len), _p(blk_len),
                             _p(blk_dx), _p(chi), _p(eta), chi.shape[1], _p(I_bc), R, _p(dirs), _p(w2), per,
-                            _p(origins), n_o, float(dv_max), float(dtau_max), int(max_sub), _p(J), _p(u),
-                            nthreads)
+                            _p(origins), n_o, float(dv_max), float(dtau_max), int(max_sub), int(scheme), _p(J),
+                            _p(u), nthreads)
     if rc != 0:
         raise FloatingPointError("oracle produced a non-finite u (rc=%d)" % rc)
     return (J, u) if want_u else J
