@@ -575,7 +575,10 @@ OR_API double or_feautrier_u(int64_t N, int64_t m, const double* dtau, const dou
  * makes the result NaN (the caller keeps steps small, e.g. with dtau_max).
  * The weights assume S smooth in tau: between very unequal steps the weight of
  * the far neighbour grows like -(long step)/(6 short step) and amplifies jumps
- * of S.  N == 1 returns I. */
+ * of S.  Since alpha + beta + gamma = 1 the right-hand side is evaluated as
+ * S_d + alpha (S_{d-1} - S_d) + gamma (S_{d+1} - S_d), the same value without
+ * the large, nearly cancelling products beta S_d and gamma S_{d+1} that unequal
+ * steps would bring into its rounding.  N == 1 returns I. */
 OR_API double or_feautrier_u_hermite(int64_t N, int64_t m, const double* dtau, const double* S, double I) {
     if (N == 1) return I;
     /* row d: -Am u_{d-1} + (1 + Am + Cp) u_d - Cp u_{d+1} = Rd; the end rows have
@@ -594,11 +597,11 @@ OR_API double or_feautrier_u_hermite(int64_t N, int64_t m, const double* dtau, c
             const double a_ = dtau[(d) - 1], b_ = dtau[d], h_ = 0.5 * (a_ + b_);               \
             const double wm_ = (a_ * a_ * a_ + 2.0 * a_ * a_ * b_ - b_ * b_ * b_) / (12.0 * a_ * (a_ + b_)); \
             const double wp_ = (b_ * b_ * b_ + 2.0 * a_ * b_ * b_ - a_ * a_ * a_) / (12.0 * b_ * (a_ + b_)); \
-            const double al_ = wm_ / h_, ga_ = wp_ / h_, be_ = 1.0 - al_ - ga_;                \
+            const double al_ = wm_ / h_, ga_ = wp_ / h_;                                       \
             Am = 2.0 / (a_ * (a_ + b_)) - al_;                                                 \
             Cp = 2.0 / (b_ * (a_ + b_)) - ga_;                                                 \
             Ex = 0.0;                                                                          \
-            Rd = al_ * S[(d) - 1] + be_ * S[d] + ga_ * S[(d) + 1];                             \
+            Rd = S[d] + al_ * (S[(d) - 1] - S[d]) + ga_ * (S[(d) + 1] - S[d]);                 \
             if (!(Am >= 0.0) || !(Cp > 0.0)) bad = 1;                                          \
         }                                                                                      \
     } while (0)
