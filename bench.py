@@ -218,7 +218,11 @@ def main():
                     help="adaptive optical-depth increments: split line intervals to at most this optical depth "
                          "(0 = off)")
     ap.add_argument("--fp64-below", type=float, default=1e-4,
-                    help="FP32 sweep: rows with an optical-depth step below this are eliminated in FP64")
+                    help="rt_solve_opts.dtau_fp64_below (kept in the options; no effect: every row already has "
+                         "FP64 coefficients)")
+    ap.add_argument("--scheme", choices=["feautrier2", "hermite"], default="feautrier2",
+                    help="rows of the line solve: second-order Feautrier, or the fourth-order Hermitian rows "
+                         "(steps must stay below about 3.46: use --dtau-max)")
     args = ap.parse_args()
     if args.summarize_counters:
         print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
@@ -286,18 +290,19 @@ def main():
     J = torch.empty((m.P, Fw), dtype=torch.float32, device=dev)
     sched = {"direct": rt.SCHED_DIRECT, "binned": rt.SCHED_BINNED, "spatial": rt.SCHED_SPATIAL}[args.schedule]
     opts = dict(schedule=sched, group=args.group, trace_lanes=args.trace_lanes)
+    scheme = {"feautrier2": rt.SCHEME_FEAUTRIER2, "hermite": rt.SCHEME_HERMITE}[args.scheme]
     tuned = None
     if not args.no_autotune:
         _log("autotuning (schedule, sweep load group, walk lanes, persistent grid) ...")
         t0 = time.perf_counter()
         opts, tuned_ms = rt.autotune(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P,
                                      precision=rt.RT_F32, dtau_fp64_below=args.fp64_below, n_runs=2,
-                                     verbose=True)
+                                     verbose=True, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme)
         tuned = dict(opts, ms_per_step=tuned_ms, seconds=time.perf_counter() - t0)
         _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   dtau_fp64_below=args.fp64_below, dtau_max=args.dtau_max, dv_max=args.dv_max,
+                   dtau_fp64_below=args.fp64_below, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme,
                    walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
                    **opts)
     total = plan.info()["total"]
@@ -350,8 +355,8 @@ def main():
             "workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep",
             "points": m.P, "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
             "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "walk": args.walk,
-            "dtau_max": args.dtau_max, "dv_max": args.dv_max, "autotune": tuned,
-            "fp64_rows_below_dtau": args.fp64_below, "frequency_chunks_per_pair": nfc,
+            "dtau_max": args.dtau_max, "dv_max": args.dv_max, "scheme": args.scheme, "autotune": tuned,
+            "frequency_chunks_per_pair": nfc,
         },
         "roofline": {
             "kernel": "feautrier sweep",
@@ -520,6 +525,12 @@ def _gen_wind(seed_P):
     return m, time.perf_counter() - t0
 
 
+def _mem_line(torch, rt) -> str:
+    free, total = torch.cuda.mem_get_info()
+    return (f"device memory in use {(total - free) / 2**30:.1f} GiB (torch reserved "
+            f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB, plan cache {rt.cached_memory() / 2**30:.1f} GiB)")
+
+
 def run_closure(args):
     """Learned closure vs the plain nside-8 solve: label, train, judge; one JSON line."""
     import math
@@ -549,7 +560,8 @@ def run_closure(args):
     for sd in seeds_train:
         dm = cl.DeviceModel.from_synth(models.pop(sd))
         labs.append(cl.label(dm, ds1, ds8, verbose=True))
-        _log(f"labelled seed {sd}: nside-{nc} {labs[-1].coarse.ms:.0f} ms, nside-8 {labs[-1].fine.ms:.0f} ms")
+        _log(f"labelled seed {sd}: nside-{nc} {labs[-1].coarse.ms:.0f} ms, nside-8 {labs[-1].fine.ms:.0f} ms; "
+             + _mem_line(torch, rt))
     label_s = time.perf_counter() - t0
     X, T, norm = cl.dataset(labs)
     del labs

@@ -48,7 +48,8 @@ enum {
     RT_ERR_HIP = -5,         /* a HIP runtime call failed */
     RT_ERR_UNSUPPORTED = -6, /* nside not a power of two, level > 13, too many blocks */
     RT_ERR_NONFINITE = -7,   /* the solve produced a non-finite u */
-    RT_ERR_STATE = -8        /* handle used in the wrong state */
+    RT_ERR_STATE = -8,       /* handle used in the wrong state */
+    RT_ERR_STEP = -9         /* RT_SCHEME_HERMITE: an optical-depth step beyond the rows' limit */
 };
 
 enum { RT_F32 = 1, RT_F64 = 2 };
@@ -221,7 +222,21 @@ typedef struct {
                                  of smaller line coordinate carries p = (1-w) p_d + w p_{d+1} and the
                                  optics (1-w) X_d + w X_{d+1}, X_e being point e's table read at the new
                                  point's own shift; 0 = off */
+    int32_t scheme;           /* rows of the line solve (Section 2.1): RT_SCHEME_FEAUTRIER2 (0), the
+                                 second-order equation with second-order end rows (eq. 1);
+                                 RT_SCHEME_HERMITE (1), the fourth-order Hermitian rows with
+                                 third-order end rows.  Hermitian row d, outer step a, inner step b:
+                                 -A' u_{d-1} + (1 + A' + C') u_d - C' u_{d+1}
+                                   = al S_{d-1} + (1 - al - ga) S_d + ga S_{d+1},
+                                 al = w(a,b), ga = w(b,a), w(x,y) = (x^3 + 2x^2 y - y^3)/(6x(x+y)^2),
+                                 A' = 2/(a(a+b)) - al, C' = 2/(b(a+b)) - ga; end row with step t:
+                                 (1 + E + 2/t^2) u_0 - (2/t^2) u_1 = S_0 + E I + (S_1 - S_0)/3,
+                                 E = (2/t)(1 + t^2/6).  The elimination needs A' >= 0 and C' > 0,
+                                 i.e. steps below about 3.46 (e.g. through dtau_max); a line that
+                                 breaks this gets u = NaN and latches RT_ERR_STEP.  FP32 tables
+                                 need steps above about 1e-18 (2/step^2 stays finite). */
 } rt_solve_opts;
+enum { RT_SCHEME_FEAUTRIER2 = 0, RT_SCHEME_HERMITE = 1 };
 enum { RT_WALK_EXACT = 0, RT_WALK_PADDED = 1, RT_WALK_TWO_PASS = 2 };
 
 /* Scratch needed by rt_solve (u per (origin, pair, frequency), bins). */
@@ -300,7 +315,7 @@ rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream)
  * defaults) and the sum of the stage times to *best_ms.  With cache_path, a line
  * "<signature> <schedule> <group> <lanes> <waves_per_cu> <bins> <ms>" is
  * appended, and a later call with the same signature (device, P, E, R, origins,
- * F, precision, moving, adaptive) returns the cached choice without timing.
+ * F, precision, moving, adaptive, scheme, refinement switches) returns the cached choice without timing.
  * verbose != 0 prints one line per candidate to stderr.  Synchronises, allocates. */
 rt_status rt_autotune(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
                       const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,

@@ -13,6 +13,8 @@ from .binding import (  # noqa: F401
     SCHED_BINNED,
     SCHED_DIRECT,
     SCHED_SPATIAL,
+    SCHEME_FEAUTRIER2,
+    SCHEME_HERMITE,
     WALK_EXACT,
     WALK_PADDED,
     WALK_TWO_PASS,

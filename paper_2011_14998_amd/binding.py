@@ -15,6 +15,8 @@ RT_F64 = 2
 SCHED_DIRECT = 0
 SCHED_BINNED = 1
 SCHED_SPATIAL = 2
+SCHEME_FEAUTRIER2 = 0
+SCHEME_HERMITE = 1
 WALK_EXACT = 0
 WALK_PADDED = 1
 WALK_TWO_PASS = 2
@@ -38,7 +40,7 @@ class SolveOptsC(C.Structure):
     _fields_ = [("precision", _i32), ("schedule", _i32), ("dtau_fp64_below", _dbl),
                 ("waves_per_cu", _i32), ("n_bins", _i32), ("group", _i32), ("trace_lanes", _i32),
                 ("padded_trace_budget", _i64), ("walk", _i32), ("dtau_max", _dbl), ("max_substeps", _i32),
-                ("dv_max", _dbl)]
+                ("dv_max", _dbl), ("scheme", _i32)]
 
 
 # name -> (restype, argtypes)
@@ -314,17 +316,18 @@ def _grid(freq_len: Sequence[int], freq_dx: Sequence[float]):
 
 
 def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget=0, group=0,
-          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0, dv_max=0.0):
+          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0, dv_max=0.0, scheme=0):
     return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group, trace_lanes,
-                      padded_trace_budget, walk, dtau_max, max_substeps, dv_max)
+                      padded_trace_budget, walk, dtau_max, max_substeps, dv_max, scheme)
 
 
 def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
           precision: int = RT_F32, schedule: int = SCHED_DIRECT, dtau_fp64_below: float = 1e-4,
           waves_per_cu: int = 0, n_bins: int = 0, group: int = 0, want_u: bool = False, dtau_max: float = 0.0,
-          max_substeps: int = 0, dv_max: float = 0.0, stream=None):
+          max_substeps: int = 0, dv_max: float = 0.0, scheme: int = SCHEME_FEAUTRIER2, stream=None):
     """J [n_o][F] (dtype of the precision) from ray lists; optionally u [n_o][R][F].  dtau_max > 0
-    splits line intervals into optical-depth sub-steps (rt_solve_opts.dtau_max)."""
+    splits line intervals into optical-depth sub-steps (rt_solve_opts.dtau_max); scheme picks the
+    second-order or the fourth-order Hermitian rows (rt_solve_opts.scheme)."""
     torch = _torch()
     L = load()
     dt = torch.float64 if precision == RT_F64 else torch.float32
@@ -341,7 +344,7 @@ def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc,
     R = dirset.R
     g, keep = _grid(freq_len, freq_dx)
     o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group=group, dtau_max=dtau_max,
-              max_substeps=max_substeps, dv_max=dv_max)
+              max_substeps=max_substeps, dv_max=dv_max, scheme=scheme)
     u = torch.empty((n_origins, R, F), dtype=dt, device=chi.device) if want_u else None
     wsb = _sz()
     _check(L.rt_solve_workspace(dirset._h, n_origins, F, C.byref(o), C.byref(wsb)))
@@ -362,7 +365,8 @@ def compute_J(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, o
 
 def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None, n_origins=None,
              precision: int = RT_F32, dtau_fp64_below: float = 1e-4, n_runs: int = 2, cache_path: str = None,
-             verbose: bool = False, stream=None):
+             verbose: bool = False, dtau_max: float = 0.0, dv_max: float = 0.0, scheme: int = SCHEME_FEAUTRIER2,
+             stream=None):
     """Fastest plan options for this workload (see rt_autotune); returns (options dict, ms per step)."""
     torch = _torch()
     dt = torch.float64 if precision == RT_F64 else torch.float32
@@ -374,7 +378,7 @@ def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J,
     elif n_origins is None:
         n_origins = model.P
     g, keep = _grid(freq_len, freq_dx)
-    base = _opts(precision, SCHED_SPATIAL, dtau_fp64_below, 0, 0)
+    base = _opts(precision, SCHED_SPATIAL, dtau_fp64_below, 0, 0, dtau_max=dtau_max, dv_max=dv_max, scheme=scheme)
     best = SolveOptsC()
     ms = _dbl()
     _check(load().rt_autotune(model._h, dirset._h, _ptr(origins), n_origins, _ptr(chi), _ptr(eta), precision,
@@ -394,7 +398,8 @@ class Plan:
                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT,
                  dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0,
                  padded_trace_budget: int = 0, group: int = 0, trace_lanes: int = 0, walk: int = WALK_EXACT,
-                 dtau_max: float = 0.0, max_substeps: int = 0, dv_max: float = 0.0, stream=None):
+                 dtau_max: float = 0.0, max_substeps: int = 0, dv_max: float = 0.0,
+                 scheme: int = SCHEME_FEAUTRIER2, stream=None):
         torch = _torch()
         dt = torch.float64 if precision == RT_F64 else torch.float32
         self.chi, self.eta, self.J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
@@ -408,7 +413,7 @@ class Plan:
         self.model, self.dirset = model, dirset
         g, self._keep = _grid(freq_len, freq_dx)
         o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes,
-                  walk, dtau_max, max_substeps, dv_max)
+                  walk, dtau_max, max_substeps, dv_max, scheme)
         h = _vp()
         _check(load().rt_plan_create(model._h, dirset._h, _ptr(origins), n_origins, _ptr(self.chi),
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),

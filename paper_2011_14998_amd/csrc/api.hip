@@ -435,6 +435,7 @@ static rt_solve_opts default_opts() {
     o.dtau_max = 0.0;
     o.max_substeps = 0;
     o.dv_max = 0.0;
+    o.scheme = RT_SCHEME_FEAUTRIER2;
     return o;
 }
 
@@ -513,6 +514,9 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.n_xcd = num_xcds();
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
     a.group = o.group ? o.group : 4;
+    if (o.scheme != RT_SCHEME_FEAUTRIER2 && o.scheme != RT_SCHEME_HERMITE)
+        return fail(RT_ERR_ARG, "solve: scheme must be RT_SCHEME_FEAUTRIER2 or RT_SCHEME_HERMITE");
+    a.scheme = o.scheme;
     {  // every byte offset into chi and eta (row * ld + column) fits in 32 bits
         const double tbytes = (double)m->P * (double)ld * (double)(dtype == RT_F64 ? 8 : 4);
         a.small_tables = tbytes < 4294967296.0 ? 1 : 0;
@@ -589,6 +593,8 @@ extern "C" rt_status rt_sync_status(void* stream) {
     RT_HIP(hipMemcpy(&h, w, sizeof(int32_t), hipMemcpyDeviceToHost));
     RT_HIP(hipMemset(w, 0, sizeof(int32_t)));
     if (h & ERRBIT_CAPACITY) return fail(RT_ERR_CAPACITY, "a ray list exceeded its capacity");
+    if (h & ERRBIT_STEP)
+        return fail(RT_ERR_STEP, "a fourth-order row met an optical-depth step beyond its limit (about 3.46)");
     if (h & ERRBIT_NONFINITE) return fail(RT_ERR_NONFINITE, "the solve produced a non-finite u");
     if (h & ERRBIT_ORIGIN) return fail(RT_ERR_ARG, "an origin id was outside 0 .. P-1");
     return RT_OK;
@@ -1023,7 +1029,7 @@ extern "C" rt_status rt_cached_memory(size_t* bytes) {
 // ------------------------------------------------------------------ autotuner
 
 static std::string tune_signature(const rt_model* m, const rt_dirset* set, int64_t n_origins, int64_t F,
-                                  int32_t precision) {
+                                  const rt_solve_opts& o) {
     int dev = 0;
     hipDeviceProp_t prop;
     std::string arch = "unknown";
@@ -1031,9 +1037,11 @@ static std::string tune_signature(const rt_model* m, const rt_dirset* set, int64
     for (char& c : arch)
         if (c == ' ' || c == ':') c = '_';
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s_P%lld_E%lld_R%lld_n%lld_F%lld_p%d_v%d_a%d", arch.c_str(), (long long)m->P,
-                  (long long)m->E, (long long)set->R, (long long)n_origins, (long long)F, (int)precision,
-                  m->vel ? 1 : 0, set->n_origins > 0 ? 1 : 0);
+    // the sweep's kernel variant: rows of the scheme, refined lines (optical depth, velocity)
+    const int refine = (o.dtau_max > 0.0 ? 1 : 0) | (o.dv_max > 0.0 && m->vel ? 2 : 0);
+    std::snprintf(buf, sizeof(buf), "%s_P%lld_E%lld_R%lld_n%lld_F%lld_p%d_v%d_a%d_s%d_r%d", arch.c_str(),
+                  (long long)m->P, (long long)m->E, (long long)set->R, (long long)n_origins, (long long)F,
+                  (int)o.precision, m->vel ? 1 : 0, set->n_origins > 0 ? 1 : 0, (int)o.scheme, refine);
     return buf;
 }
 
@@ -1046,7 +1054,7 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     rt_solve_opts b0 = base ? *base : default_opts();
     int64_t F = 0;
     for (int i = 0; i < grid->n_blocks && grid->len; ++i) F += grid->len[i];
-    const std::string sig = tune_signature(m, set, n_origins, F, b0.precision);
+    const std::string sig = tune_signature(m, set, n_origins, F, b0);
     if (cache_path && *cache_path) {
         FILE* f = std::fopen(cache_path, "r");
         if (f) {

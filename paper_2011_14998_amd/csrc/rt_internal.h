@@ -23,7 +23,7 @@ rt_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // Device-side error word (per device), written by kernels with atomicOr.
-enum : int32_t { ERRBIT_CAPACITY = 1, ERRBIT_NONFINITE = 2, ERRBIT_ORIGIN = 4 };
+enum : int32_t { ERRBIT_CAPACITY = 1, ERRBIT_NONFINITE = 2, ERRBIT_ORIGIN = 4, ERRBIT_STEP = 8 };
 int32_t* error_word();  // device address for the current device, nullptr on failure
 int num_cus();
 int num_xcds();
@@ -169,6 +169,7 @@ struct SolveLaunch {
     int n_xcd;             // XCDs for the block renumbering of the direct launch
     int group;             // sweep load-group size (4 or 8)
     int small_tables;      // chi and eta each below 4 GiB: 32-bit row offsets in the sweep
+    int scheme;            // RT_SCHEME_FEAUTRIER2 or RT_SCHEME_HERMITE
 };
 int64_t solve_items(const SolveLaunch& a);
 size_t bin_workspace(int64_t n_items, int32_t n_bins);

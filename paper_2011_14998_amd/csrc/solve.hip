@@ -6,6 +6,8 @@
 // and only u at the origin is needed, so each side is eliminated from its far
 // end inwards (second-order Feautrier equation, eq. 1, with second-order
 // boundary conditions at both ends) and the two sides meet at the origin.
+// The fourth-order (Hermitian) rows are an option with the same structure
+// (below, at row_h).
 // Nothing but the running (F, Z) pair and the previous point's optics is kept
 // per lane: a line of any length streams through registers.
 //
@@ -154,6 +156,11 @@ template <typename T>
 struct SweepState {
     T G, Y, r;  // rescaled pivot and right-hand side, r = 1/(1 + a G)
     T a;        // inner optical-depth step of the last row: the outer step of the next
+    // fourth-order rows: u_d = u_{d+1}/(1+F) + Z; S (FP64) of the last row's
+    // point and of its next point; whether a row met a step beyond the limit
+    T F, Z;
+    double Sp, Sc;
+    bool bad;
 };
 
 // Row d of the elimination, given its inner step b and S_d (the outer step is st.a).
@@ -171,6 +178,106 @@ __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
         st.Y = fma_<T>(h, S, st.Y) * st.r;
     }
     st.a = b;
+}
+
+// Fourth-order (Hermitian) rows with third-order end rows: the scheme Section
+// 2.1 names for the solver (Auer 1976); derived from exactness for quartic u.
+// A row d with outer step a, inner step b (toward the origin) reads
+//   -A' u_far + (1 + A' + C') u_d - C' u_near = al S_far + (1 - al - ga) S_d + ga S_near,
+//   al = w(a, b), ga = w(b, a),  w(x, y) = (x^3 + 2x^2 y - y^3) / (6 x (x+y)^2),
+//   A' = 2/(a(a+b)) - al,  C' = 2/(b(a+b)) - ga,
+// and the far end (step t to its neighbour) with E = (2/t)(1 + t^2/6):
+//   (1 + E + 2/t^2) u_0 - (2/t^2) u_1 = S_0 + E I + (S_1 - S_0)/3.
+// The right-hand side is formed as S_d + al (S_far - S_d) + ga (S_near - S_d)
+// (al + be + ga = 1) with S = eta/chi and this sum in FP64, rounded once to the
+// kernel's precision: for unequal steps one weight grows like the step ratio
+// (which reaches 1e3 and more on unstructured lines), so an S rounded to FP32,
+// or the literal form be S_d + ga S_near, would carry that factor into u.  The elimination itself runs in the kernel's precision:
+// u_d = u_{d+1}/(1+F_d) + Z_d with
+//   F_d = (1 + A' F_{d-1}/(1+F_{d-1})) / C',  Z_d = (R_d + A' Z_{d-1}) / (C'(1+F_d)),
+// free of cancellation while A' >= 0 and C' > 0 (steps below about 3.46); a
+// row beyond that marks the side bad (reported as an error).
+// w(x, y) in the scale-free form: with p = x/(x+y), q = y/(x+y),
+// w = (p^2 (p + 2q) - q^3) / (6p), so no cube of a step can underflow.
+template <typename T>
+__device__ inline T herm_w(T x, T y) {
+    const T rs = rcp<T>(x + y);
+    const T p = x * rs, q = y * rs;
+    return fma_<T>(p * p, p + (q + q), -(q * q * q)) * rcp<T>((T)6 * p);
+}
+
+// S = eta/chi in FP64, a correctly rounded division (the widened FP32 values
+// give the same S as FP64 tables of those values would).
+template <typename T>
+__device__ inline double src64(T e, T c) { return (double)e / (double)c; }
+
+// Row d: its inner step b, its own optics (c, e) and the next point's (cn, en).
+// The state carries S of the previous row's point (Sp) and of this one (Sc,
+// the previous row's next point), so each row forms one new FP64 S.
+template <typename T>
+__device__ inline void row_h(SweepState<T>& st, bool far_end, T b, T c, T e, T cn, T en, T I) {
+    const double Sn = src64<T>(en, cn);
+    if (far_end) {
+        const double S = src64<T>(e, c);
+        const T rb = rcp<T>(b);
+        const T E = (T)2 * rb * fma_<T>(b * b, (T)(1.0 / 6.0), (T)1);
+        const T hk = (T)0.5 * b * b;  // 1/K
+        st.F = ((T)1 + E) * hk;
+        const T R0 = (T)(S + __builtin_fma((double)E, (double)I, (Sn - S) * (1.0 / 3.0)));
+        st.Z = R0 * hk * rcp<T>((T)1 + st.F);
+        st.Sc = S;
+    } else {
+        const double S = st.Sc;
+        const T a = st.a, sab = a + b;
+        const T al = herm_w<T>(a, b), ga = herm_w<T>(b, a);
+        const T Am = (T)2 * rcp<T>(a * sab) - al;
+        const T Cp = (T)2 * rcp<T>(b * sab) - ga;
+        st.bad = st.bad || !(Am >= (T)0) || !(Cp > (T)0);
+        const T R = (T)__builtin_fma((double)al, st.Sp - S, __builtin_fma((double)ga, Sn - S, S));
+        const T rc = rcp<T>(Cp);
+        const T Fn = fma_<T>(Am, st.F * rcp<T>((T)1 + st.F), (T)1) * rc;
+        st.Z = fma_<T>(Am, st.Z, R) * rc * rcp<T>((T)1 + Fn);
+        st.F = Fn;
+    }
+    st.a = b;
+    st.Sp = st.Sc;
+    st.Sc = Sn;
+}
+
+// u at the origin with the fourth-order rows: each non-empty side's last row
+// had the origin as its next point, so its state holds S_o (Sc) and S of its
+// last point (Sp).
+template <typename T>
+__device__ inline T origin_h(bool hm, bool hp, SweepState<T>& m, SweepState<T>& p, T I) {
+    if (hm && hp) {
+        const double S = m.Sc;
+        const T a = m.a, b = p.a, sab = a + b;
+        const T al = herm_w<T>(a, b), ga = herm_w<T>(b, a);
+        const T Am = (T)2 * rcp<T>(a * sab) - al;
+        const T Cp = (T)2 * rcp<T>(b * sab) - ga;
+        m.bad = m.bad || !(Am >= (T)0) || !(Cp > (T)0);
+        const T R = (T)__builtin_fma((double)al, m.Sp - S, __builtin_fma((double)ga, p.Sp - S, S));
+        const T den = (T)1 + fma_<T>(Am, m.F * rcp<T>((T)1 + m.F), Cp * p.F * rcp<T>((T)1 + p.F));
+        return fma_<T>(Am, m.Z, fma_<T>(Cp, p.Z, R)) * rcp<T>(den);
+    }
+    if (hm || hp) {
+        const SweepState<T>& q = hp ? p : m;
+        const double S = q.Sc;
+        const T t = q.a, rt_ = rcp<T>(t);
+        const T E = (T)2 * rt_ * fma_<T>(t * t, (T)(1.0 / 6.0), (T)1);
+        const T K = (T)2 * rt_ * rt_;
+        const T R0 = (T)(S + __builtin_fma((double)E, (double)I, (q.Sp - S) * (1.0 / 3.0)));
+        return fma_<T>(K, q.Z, R0) * rcp<T>((T)1 + E + K * q.F * rcp<T>((T)1 + q.F));
+    }
+    return I;
+}
+
+// A row of the chosen scheme.  SCH 0, second order: the point's S.  SCH 1,
+// fourth order: the point's optics and the next point's (cn, en).
+template <typename T, int SCH>
+__device__ inline void row_s(SweepState<T>& st, bool far_end, T b, T S, T c, T e, T cn, T en, T I) {
+    if (SCH == 1) row_h<T>(st, far_end, b, c, e, cn, en, I);
+    else row<T>(st, far_end, b, S, I);
 }
 
 // u at the origin from the two sides' states (file header).
@@ -240,12 +347,12 @@ __device__ inline double chi64(const Pt64<T>& p) {
 // interior points interpolate chi' and eta' linearly; rows are emitted far to
 // near, each with its inner step, the last being the sub-point next to the near
 // point.  `first` marks the far end of the line (its row is the boundary row).
-template <typename T>
+template <typename T, int SCH>
 __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
                                         T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I) {
     const T est = (cf > cn ? cf : cn) * (hds + hds) * (T)c.dtau_rcp;
     if (!__builtin_amdgcn_ballot_w64(est > (T)0.9999)) {
-        row<T>(st, first, (cf + cn) * hds, Sf, I);
+        row_s<T, SCH>(st, first, (cf + cn) * hds, Sf, cf, ef, cn, en, I);
         return;
     }
     const double c64f = chi64(pf), c64n = chi64(pn);
@@ -255,20 +362,21 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
     const int n = q >= 1.0 ? (int)q : 1;  // also 1 for a NaN
     const T rn = rcp<T>((T)n);
     const T hh = hds * rn;  // half a sub-interval
-    T cp = cf, Sp = Sf;
+    T cp = cf, ep = ef, Sp = Sf;
     bool fr = first;
     for (int k = 1; __builtin_amdgcn_ballot_w64(k < n); ++k) {
         if (k < n) {
             const T w = (T)k * rn;
             const T ck = fma_<T>(w, cn - cf, cf);
             const T ek = fma_<T>(w, en - ef, ef);
-            row<T>(st, fr, (cp + ck) * hh, Sp, I);
+            row_s<T, SCH>(st, fr, (cp + ck) * hh, Sp, cp, ep, ck, ek, I);
             cp = ck;
-            Sp = ek * rcp<T>(ck);
+            ep = ek;
+            if (SCH == 0) Sp = ek * rcp<T>(ck);
             fr = false;
         }
     }
-    row<T>(st, fr, (cp + cn) * hh, Sp, I);
+    row_s<T, SCH>(st, fr, (cp + cn) * hh, Sp, cp, ep, cn, en, I);
 }
 
 // The stream of line points of one side, far to near, after velocity sampling.
@@ -282,12 +390,13 @@ struct Emitter {
 
 // Emit the next line point; the interval from the previous one (half length
 // hds, FP64 length ds64) is split by optical depth when that is on.
-template <typename T>
+template <typename T, int SCH>
 __device__ inline void emit_point(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, T cn, T en, T Sn,
                                   const Pt64<T>& pn, T hds, double ds64, T I) {
     if (em.have) {
-        if (c.dtau_rcp > 0.0) substep_interval<T>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I);
-        else row<T>(st, em.first, (em.c + cn) * hds, em.S, I);
+        if (c.dtau_rcp > 0.0)
+            substep_interval<T, SCH>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I);
+        else row_s<T, SCH>(st, em.first, (em.c + cn) * hds, em.S, em.c, em.e, cn, en, I);
         em.first = false;
     }
     em.c = cn;
@@ -310,7 +419,7 @@ struct RealPt {
 // and FP64 lengths: velocity sub-points first (m from |p_C - p_P|), each emitted,
 // then C itself.  fwd: this side is the +n ray, whose nearer point has the
 // smaller line coordinate (so it is the interval's point a).
-template <typename T, bool UDX>
+template <typename T, bool UDX, int SCH>
 __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, const RealPt<T>& P,
                                      const RealPt<T>& C, T hds, double ds64, bool fwd, const LaneFreq& lf, T I) {
     int m = 1;
@@ -321,7 +430,7 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
         m = __builtin_amdgcn_readfirstlane(m);  // the same in every lane
     }
     if (m == 1) {
-        emit_point<T>(c, st, em, C.c, C.e, C.S, C.p, hds, ds64, I);
+        emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hds, ds64, I);
         return;
     }
     const T hs = hds * rcp<T>((T)m);
@@ -353,9 +462,9 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
         const T ya = fma_<T>(t, g1 - g0, g0), yb = fma_<T>(t, h1 - h0, h0);
         const T cv = fma_<T>(wt, xb - xa, xa);
         const T ev = fma_<T>(wt, yb - ya, ya);
-        emit_point<T>(c, st, em, cv, ev, ev * rcp<T>(cv), Pt64<T>{a0, a1, b0, b1, t64, w}, hs, ds64s, I);
+        emit_point<T, SCH>(c, st, em, cv, ev, ev * rcp<T>(cv), Pt64<T>{a0, a1, b0, b1, t64, w}, hs, ds64s, I);
     }
-    emit_point<T>(c, st, em, C.c, C.e, C.S, C.p, hs, ds64s, I);
+    emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hs, ds64s, I);
 }
 
 // One side of the line with velocity sampling and/or optical-depth sub-steps
@@ -365,7 +474,7 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
 // list point, 6 the whole-step shift (uniform dx), 8-9 its FP64 fraction.
 constexpr int REF_STAGE_WORDS = 12;
 
-template <typename T, bool MOVING, bool UDX>
+template <typename T, bool MOVING, bool UDX, int SCH>
 __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, bool fwd,
                                  T chi_o, T eta_o, T S_o, T I, SweepState<T>& st, uint32_t* stage) {
     Emitter<T> em;
@@ -464,8 +573,8 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
                 cur.p = Pt64<T>{cur.c, cur.c, cur.c, cur.c, 0.0, 0.0};
             }
             cur.S = cur.e * rcp<T>(cur.c);
-            if (done == 0) emit_point<T>(c, st, em, cur.c, cur.e, cur.S, cur.p, (T)0, 0.0, I);
-            else real_interval<T, UDX>(c, st, em, prev, cur, hds_prev, ds64_prev, fwd, lf, I);
+            if (done == 0) emit_point<T, SCH>(c, st, em, cur.c, cur.e, cur.S, cur.p, (T)0, 0.0, I);
+            else real_interval<T, UDX, SCH>(c, st, em, prev, cur, hds_prev, ds64_prev, fwd, lf, I);
             prev = cur;
             ds64_prev = ds64;
             hds_prev = (T)0.5 * (T)ds64;
@@ -481,7 +590,7 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
         org.p = Pt64<T>{chi_o, chi_o, chi_o, chi_o, 0.0, 0.0};
         org.dot = 0.0;
         org.row = c.row_o;
-        real_interval<T, UDX>(c, st, em, prev, org, hds_prev, ds64_prev, fwd, lf, I);
+        real_interval<T, UDX, SCH>(c, st, em, prev, org, hds_prev, ds64_prev, fwd, lf, I);
     }
 }
 
@@ -507,10 +616,10 @@ constexpr int STAGE_WORDS = 8;
 // GROUP line points have their loads issued together before the recurrence
 // consumes them (a tuning parameter: more points in flight per wave against
 // more registers, i.e. fewer waves).
-template <typename T, bool MOVING, bool UDX, int GROUP, bool SMALL>
-__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T I,
-                             SweepState<T>& st, uint32_t* stage) {
-    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
+template <typename T, bool MOVING, bool UDX, int GROUP, bool SMALL, int SCH>
+__device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFreq& lf, int lane, T chi_o, T eta_o,
+                             T I, SweepState<T>& st, uint32_t* stage) {
+    T c_prev = (T)0, e_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
     int done = 0;
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
@@ -609,13 +718,13 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                         cc = ca[g];
                         et = ea[g];
                     }
-                    const T S = et * rcp<T>(cc);
                     if (done > 0) {
                         const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
-                        row<T>(st, done == 1, dt, S_prev, I);
+                        row_s<T, SCH>(st, done == 1, dt, S_prev, c_prev, e_prev, cc, et, I);
                     }
                     c_prev = cc;
-                    S_prev = S;
+                    e_prev = et;
+                    if (SCH == 0) S_prev = et * rcp<T>(cc);
                     ds_prev = dsv[g];
                     ++done;
                 }
@@ -628,11 +737,11 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     }
     if (n > 0) {
         const T dt = (c_prev + chi_o) * ds_prev;
-        row<T>(st, n == 1, dt, S_prev, I);
+        row_s<T, SCH>(st, n == 1, dt, S_prev, c_prev, e_prev, chi_o, eta_o, I);
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane, uint32_t* stage) {
     // w is the same in every lane of the wave
     w = uni64(w);
@@ -679,25 +788,34 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     const T S_o = eta_o * rcp<T>(chi_o);
     SweepState<T> m{}, p{};
     if (REF) {
-        sweep_ref<T, MOVING, UDX>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m, stage);
-        sweep_ref<T, MOVING, UDX>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p, stage);
+        sweep_ref<T, MOVING, UDX, SCH>(c, bm, nm, lf, lane, false, chi_o, eta_o, S_o, I, m, stage);
+        sweep_ref<T, MOVING, UDX, SCH>(c, bp, np, lf, lane, true, chi_o, eta_o, S_o, I, p, stage);
     } else {
         if (a.small_tables) {
-            sweep<T, MOVING, UDX, GROUP, true>(c, bm, nm, lf, lane, chi_o, I, m, stage);
-            sweep<T, MOVING, UDX, GROUP, true>(c, bp, np, lf, lane, chi_o, I, p, stage);
+            sweep<T, MOVING, UDX, GROUP, true, SCH>(c, bm, nm, lf, lane, chi_o, eta_o, I, m, stage);
+            sweep<T, MOVING, UDX, GROUP, true, SCH>(c, bp, np, lf, lane, chi_o, eta_o, I, p, stage);
         } else {
-            sweep<T, MOVING, UDX, GROUP, false>(c, bm, nm, lf, lane, chi_o, I, m, stage);
-            sweep<T, MOVING, UDX, GROUP, false>(c, bp, np, lf, lane, chi_o, I, p, stage);
+            sweep<T, MOVING, UDX, GROUP, false, SCH>(c, bm, nm, lf, lane, chi_o, eta_o, I, m, stage);
+            sweep<T, MOVING, UDX, GROUP, false, SCH>(c, bp, np, lf, lane, chi_o, eta_o, I, p, stage);
         }
     }
-    const T u = origin_u<T>(nm > 0, np > 0, m, p, S_o, I);
+    T u;
+    if (SCH == 1) {
+        u = origin_h<T>(nm > 0, np > 0, m, p, I);
+        if (m.bad || p.bad) {  // a row beyond the step limit: no trustworthy u
+            u = (T)NAN;
+            if (lf.active) atomicOr(a.err, ERRBIT_STEP);
+        }
+    } else {
+        u = origin_u<T>(nm > 0, np > 0, m, p, S_o, I);
+    }
     if (lf.active) {
         ((T*)a.u)[(oi * a.R + r) * a.F + lf.f] = u;
         if (!(u == u) || u - u != (T)0) atomicOr(a.err, ERRBIT_NONFINITE);
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
     __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
@@ -717,14 +835,14 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
         }
-        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane, stage);
+        solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
     }
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
 // takes the next item with one atomic and exits when the queue is empty, so
 // every wave reaches the end.
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
     __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
@@ -738,7 +856,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= n_items) break;
         const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX, GROUP, REF>(a, w, nfc, lane, stage);
+        solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
     }
 }
 
@@ -853,13 +971,13 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
-template <typename T, int G, bool REF>
+template <typename T, int G, bool REF, int SCH>
 static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     const bool moving = a.vel != nullptr;
     // the shift of a point is lane-independent when every block has the same dx
     bool udx = true;
     for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
-#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, REF>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, REF, SCH>), grid, dim3(SOLVE_BLOCK), 0, s, a)
     if (persist) {
         if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
         else if (moving) RT_LAUNCH(k_solve_persist, true, false);
@@ -875,9 +993,17 @@ static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipS
 template <typename T>
 static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     // refined lines (velocity sampling, optical-depth sub-steps) take their own sweep
-    if (a.dtau_max_rcp > 0.0 || a.dv_max_rcp > 0.0) solve_dispatch_g<T, 4, true>(a, persist, grid, s);
-    else if (a.group == 4) solve_dispatch_g<T, 4, false>(a, persist, grid, s);
-    else solve_dispatch_g<T, 8, false>(a, persist, grid, s);
+    const bool ref = a.dtau_max_rcp > 0.0 || a.dv_max_rcp > 0.0;
+    if (a.scheme == RT_SCHEME_HERMITE) {  // fourth-order rows: one load group size
+        if (ref) solve_dispatch_g<T, 4, true, 1>(a, persist, grid, s);
+        else solve_dispatch_g<T, 4, false, 1>(a, persist, grid, s);
+    } else if (ref) {
+        solve_dispatch_g<T, 4, true, 0>(a, persist, grid, s);
+    } else if (a.group == 4) {
+        solve_dispatch_g<T, 4, false, 0>(a, persist, grid, s);
+    } else {
+        solve_dispatch_g<T, 8, false, 0>(a, persist, grid, s);
+    }
 }
 
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s) {

@@ -509,6 +509,9 @@ def test_plan_buffer_cache(rt, wind):
     assert rt.cached_memory() == 0
     n = 20_000
     org = _t(np.arange(n, dtype=np.int32))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
 
     def run(origins, k):
         J = torch.empty((k, wind.F), dtype=torch.float32, device="cuda")
@@ -533,3 +536,10 @@ def test_plan_buffer_cache(rt, wind):
     assert np.array_equal(half, direct)
     rt.release_cached_memory()
     assert rt.cached_memory() == 0
+    # every plan buffer went back to the device
+    del direct
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free1 = torch.cuda.mem_get_info()[0]
+    print(f"device memory free before {free0 / 2**30:.3f} GiB, after {free1 / 2**30:.3f} GiB", flush=True)
+    assert free1 >= free0 - (64 << 20)
