@@ -528,7 +528,8 @@ def _gen_wind(seed_P):
 def _mem_line(torch, rt) -> str:
     free, total = torch.cuda.mem_get_info()
     return (f"device memory in use {(total - free) / 2**30:.1f} GiB (torch reserved "
-            f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB, plan cache {rt.cached_memory() / 2**30:.1f} GiB)")
+            f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB, plan cache {rt.cached_memory() / 2**30:.1f} GiB, "
+            f"live plans {rt.plan_memory() / 2**30:.1f} GiB)")
 
 
 def run_closure(args):

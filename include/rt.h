@@ -299,6 +299,9 @@ rt_status rt_plan_destroy(rt_plan* plan);
 rt_status rt_release_cached_memory(void);
 /* Bytes currently held by the cache (all devices). */
 rt_status rt_cached_memory(size_t* bytes);
+/* Bytes of the large plan buffers (ray lists, padded slots, u) owned by plans
+ * not yet destroyed (all devices; the requested sizes). */
+rt_status rt_plan_memory(size_t* bytes);
 
 /* Re-capture a plan's graph with other scheduling options (schedule, group,
  * trace_lanes, waves_per_cu, n_bins; precision and threshold stay), reusing its

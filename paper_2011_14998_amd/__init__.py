@@ -25,6 +25,7 @@ from .binding import (  # noqa: F401
     RtError,
     autotune,
     cached_memory,
+    plan_memory,
     closure_apply,
     closure_feature_stats,
     closure_features,

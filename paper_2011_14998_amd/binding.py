@@ -70,6 +70,7 @@ _SIGS = {
     "rt_plan_destroy": (_i32, [_vp]),
     "rt_release_cached_memory": (_i32, []),
     "rt_cached_memory": (_i32, [C.POINTER(C.c_size_t)]),
+    "rt_plan_memory": (_i32, [C.POINTER(C.c_size_t)]),
     "rt_autotune": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC), _vp, _vp,
                            C.POINTER(SolveOptsC), _i32, C.c_char_p, _i32, _vp, C.POINTER(SolveOptsC),
                            C.POINTER(_dbl)]),
@@ -275,6 +276,13 @@ def cached_memory() -> int:
     """Bytes of device memory held by the library's cache of plan buffers."""
     b = _sz()
     _check(load().rt_cached_memory(C.byref(b)))
+    return int(b.value)
+
+
+def plan_memory() -> int:
+    """Bytes of the large plan buffers owned by plans not yet destroyed."""
+    b = _sz()
+    _check(load().rt_plan_memory(C.byref(b)))
     return int(b.value)
 
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -39,6 +40,7 @@ struct PoolBlock {
 std::mutex g_pool_mu;
 std::vector<PoolBlock> g_pool;
 size_t g_pool_bytes = 0;
+std::atomic<int64_t> g_plan_bytes{0};  // bytes of pool_alloc buffers currently owned by plans
 constexpr size_t POOL_MIN_BYTES = (size_t)64 << 20;   // smaller buffers go straight to hipMalloc
 constexpr size_t POOL_MAX_BYTES = (size_t)32 << 30;
 
@@ -56,8 +58,16 @@ void pool_release_device(int dev) {  // with g_pool_mu held
 }
 }  // namespace
 
+static hipError_t pool_alloc_(void** ptr, size_t bytes);
+
 // Buffer of at least `bytes` (exactly the requested size is what the caller may use).
 hipError_t pool_alloc(void** ptr, size_t bytes) {
+    const hipError_t e = pool_alloc_(ptr, bytes);
+    if (e == hipSuccess) g_plan_bytes += (int64_t)bytes;
+    return e;
+}
+
+static hipError_t pool_alloc_(void** ptr, size_t bytes) {
     *ptr = nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -105,6 +115,7 @@ hipError_t pool_alloc(void** ptr, size_t bytes) {
 // Return a buffer from pool_alloc on device `dev`.  The caller guarantees no work still uses it.
 void pool_free(void* ptr, size_t bytes, int dev) {
     if (!ptr) return;
+    g_plan_bytes -= (int64_t)bytes;
     if (bytes < POOL_MIN_BYTES) {
         (void)hipFree(ptr);
         return;
@@ -1016,6 +1027,13 @@ extern "C" rt_status rt_release_cached_memory(void) {
     for (const PoolBlock& b : g_pool) (void)hipFree(b.p);
     g_pool.clear();
     g_pool_bytes = 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_memory(size_t* bytes) {
+    if (!bytes) return fail(RT_ERR_ARG, "rt_plan_memory: NULL output");
+    const int64_t v = g_plan_bytes.load();
+    *bytes = v > 0 ? (size_t)v : 0;
     return RT_OK;
 }
 

@@ -536,6 +536,7 @@ def test_plan_buffer_cache(rt, wind):
     assert np.array_equal(half, direct)
     rt.release_cached_memory()
     assert rt.cached_memory() == 0
+    assert rt.plan_memory() == 0  # no plan is alive
     # every plan buffer went back to the device
     del direct
     torch.cuda.synchronize()
