@@ -156,7 +156,7 @@ template <typename T>
 struct SweepState {
     T G, Y, r;  // rescaled pivot and right-hand side, r = 1/(1 + a G)
     T a;        // inner optical-depth step of the last row: the outer step of the next
-    // fourth-order rows: u_d = u_{d+1}/(1+F) + Z; S (FP64) of the last row's
+    // fourth-order rows: u_d = (1 - F) u_{d+1} + Z; S (FP64) of the last row's
     // point and of its next point; whether a row met a step beyond the limit
     T F, Z;
     double Sp, Sc;
@@ -192,18 +192,30 @@ __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
 // (al + be + ga = 1) with S = eta/chi and this sum in FP64, rounded once to the
 // kernel's precision: for unequal steps one weight grows like the step ratio
 // (which reaches 1e3 and more on unstructured lines), so an S rounded to FP32,
-// or the literal form be S_d + ga S_near, would carry that factor into u.  The elimination itself runs in the kernel's precision:
-// u_d = u_{d+1}/(1+F_d) + Z_d with
-//   F_d = (1 + A' F_{d-1}/(1+F_{d-1})) / C',  Z_d = (R_d + A' Z_{d-1}) / (C'(1+F_d)),
-// free of cancellation while A' >= 0 and C' > 0 (steps below about 3.46); a
-// row beyond that marks the side bad (reported as an error).
-// w(x, y) in the scale-free form: with p = x/(x+y), q = y/(x+y),
-// w = (p^2 (p + 2q) - q^3) / (6p), so no cube of a step can underflow.
+// or the literal form be S_d + ga S_near, would carry that factor into u.
+// With u_d = (1 - H_d) u_{d+1} + Z_d (H = F/(1+F) of the usual u_d =
+// u_{d+1}/(1+F_d) + Z_d) the elimination takes one reciprocal per row:
+//   D = 1 + C' + A' H_{d-1},  H_d = (1 + A' H_{d-1}) / D,  Z_d = (R_d + A' Z_{d-1}) / D,
+// sums of non-negative terms while A' >= 0 and C' > 0 (steps below about
+// 3.46); a row beyond that marks the side bad (reported as an error).
+// The weights in the scale-free form: with s = a + b, p = a/s, q = b/s,
+//   al = P/(6p), ga = Q/(6q),  P = p^2 (p + 2q) - q^3,  Q = q^2 (q + 2p) - p^3,
+//   A' = (12/s^2 - P)/(6p),  C' = (12/s^2 - Q)/(6q),
+// so no cube of a step can underflow and three reciprocals give all four.
 template <typename T>
-__device__ inline T herm_w(T x, T y) {
-    const T rs = rcp<T>(x + y);
-    const T p = x * rs, q = y * rs;
-    return fma_<T>(p * p, p + (q + q), -(q * q * q)) * rcp<T>((T)6 * p);
+struct HermCoef {
+    T al, ga, Am, Cp;
+};
+
+template <typename T>
+__device__ inline HermCoef<T> herm_coef(T a, T b) {
+    const T rs = rcp<T>(a + b);
+    const T p = a * rs, q = b * rs;
+    const T t12 = (T)12 * rs * rs;
+    const T P = fma_<T>(p * p, p + (q + q), -(q * q * q));
+    const T Q = fma_<T>(q * q, q + (p + p), -(p * p * p));
+    const T r6p = rcp<T>((T)6 * p), r6q = rcp<T>((T)6 * q);
+    return HermCoef<T>{P * r6p, Q * r6q, (t12 - P) * r6p, (t12 - Q) * r6q};
 }
 
 // S = eta/chi in FP64, a correctly rounded division (the widened FP32 values
@@ -218,26 +230,25 @@ template <typename T>
 __device__ inline void row_h(SweepState<T>& st, bool far_end, T b, T c, T e, T cn, T en, T I) {
     const double Sn = src64<T>(en, cn);
     if (far_end) {
+        // (1 + E + K) u_0 - K u_1 = R_0, K = 2/b^2, scaled by b^2/2
         const double S = src64<T>(e, c);
         const T rb = rcp<T>(b);
         const T E = (T)2 * rb * fma_<T>(b * b, (T)(1.0 / 6.0), (T)1);
         const T hk = (T)0.5 * b * b;  // 1/K
-        st.F = ((T)1 + E) * hk;
+        const T F0 = ((T)1 + E) * hk;
         const T R0 = (T)(S + __builtin_fma((double)E, (double)I, (Sn - S) * (1.0 / 3.0)));
-        st.Z = R0 * hk * rcp<T>((T)1 + st.F);
+        const T rD = rcp<T>((T)1 + F0);
+        st.F = F0 * rD;
+        st.Z = R0 * hk * rD;
         st.Sc = S;
     } else {
         const double S = st.Sc;
-        const T a = st.a, sab = a + b;
-        const T al = herm_w<T>(a, b), ga = herm_w<T>(b, a);
-        const T Am = (T)2 * rcp<T>(a * sab) - al;
-        const T Cp = (T)2 * rcp<T>(b * sab) - ga;
-        st.bad = st.bad || !(Am >= (T)0) || !(Cp > (T)0);
-        const T R = (T)__builtin_fma((double)al, st.Sp - S, __builtin_fma((double)ga, Sn - S, S));
-        const T rc = rcp<T>(Cp);
-        const T Fn = fma_<T>(Am, st.F * rcp<T>((T)1 + st.F), (T)1) * rc;
-        st.Z = fma_<T>(Am, st.Z, R) * rc * rcp<T>((T)1 + Fn);
-        st.F = Fn;
+        const HermCoef<T> k = herm_coef<T>(st.a, b);
+        st.bad = st.bad || !(k.Am >= (T)0) || !(k.Cp > (T)0);
+        const T R = (T)__builtin_fma((double)k.al, st.Sp - S, __builtin_fma((double)k.ga, Sn - S, S));
+        const T rD = rcp<T>((T)1 + fma_<T>(k.Am, st.F, k.Cp));
+        st.Z = fma_<T>(k.Am, st.Z, R) * rD;
+        st.F = fma_<T>(k.Am, st.F, (T)1) * rD;
     }
     st.a = b;
     st.Sp = st.Sc;
@@ -251,14 +262,11 @@ template <typename T>
 __device__ inline T origin_h(bool hm, bool hp, SweepState<T>& m, SweepState<T>& p, T I) {
     if (hm && hp) {
         const double S = m.Sc;
-        const T a = m.a, b = p.a, sab = a + b;
-        const T al = herm_w<T>(a, b), ga = herm_w<T>(b, a);
-        const T Am = (T)2 * rcp<T>(a * sab) - al;
-        const T Cp = (T)2 * rcp<T>(b * sab) - ga;
-        m.bad = m.bad || !(Am >= (T)0) || !(Cp > (T)0);
-        const T R = (T)__builtin_fma((double)al, m.Sp - S, __builtin_fma((double)ga, p.Sp - S, S));
-        const T den = (T)1 + fma_<T>(Am, m.F * rcp<T>((T)1 + m.F), Cp * p.F * rcp<T>((T)1 + p.F));
-        return fma_<T>(Am, m.Z, fma_<T>(Cp, p.Z, R)) * rcp<T>(den);
+        const HermCoef<T> k = herm_coef<T>(m.a, p.a);
+        m.bad = m.bad || !(k.Am >= (T)0) || !(k.Cp > (T)0);
+        const T R = (T)__builtin_fma((double)k.al, m.Sp - S, __builtin_fma((double)k.ga, p.Sp - S, S));
+        const T den = (T)1 + fma_<T>(k.Am, m.F, k.Cp * p.F);
+        return fma_<T>(k.Am, m.Z, fma_<T>(k.Cp, p.Z, R)) * rcp<T>(den);
     }
     if (hm || hp) {
         const SweepState<T>& q = hp ? p : m;
@@ -267,7 +275,7 @@ __device__ inline T origin_h(bool hm, bool hp, SweepState<T>& m, SweepState<T>& 
         const T E = (T)2 * rt_ * fma_<T>(t * t, (T)(1.0 / 6.0), (T)1);
         const T K = (T)2 * rt_ * rt_;
         const T R0 = (T)(S + __builtin_fma((double)E, (double)I, (q.Sp - S) * (1.0 / 3.0)));
-        return fma_<T>(K, q.Z, R0) * rcp<T>((T)1 + E + K * q.F * rcp<T>((T)1 + q.F));
+        return fma_<T>(K, q.Z, R0) * rcp<T>((T)1 + E + K * q.F);
     }
     return I;
 }
