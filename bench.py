@@ -115,8 +115,14 @@ def summarize_counters(d, out_json, out_md):
                      f"SQ_BUSY_CYCLES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE --output-format csv -d <dir>/sq -o run -- {B}\n")
             fo.write("    python3 bench.py --summarize-counters <dir> profiles/sweep_wind50k_nside4_counters.json "
                      "profiles/wind50k_nside4_kernel_stats.md\n\n")
-            fo.write("`--no-autotune` runs the plan options the autotuner picks for this workload (spatial schedule, "
-                     "load group 4, 8 lanes per ray), without its candidate runs in the trace.\n\n")
+            fo.write("    rocprofv3 --pmc TA_TA_BUSY_sum TD_TD_BUSY_sum GRBM_GUI_ACTIVE --output-format csv -d <dir>/ta "
+                     f"-o run -- {B}\n")
+            fo.write("    rocprofv3 --pmc TCP_TCP_TA_DATA_STALL_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum "
+                     "TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum --output-format csv -d <dir>/tcp "
+                     f"-o run -- {B}\n\n")
+            fo.write("`--no-autotune` runs the library defaults (spatial schedule, load group 8, 8 lanes per ray), "
+                     "which the autotuner keeps unless a candidate is 2% faster, without its candidate runs in the "
+                     "trace.\n\n")
             fo.write("## rocprofv3 --stats (kernel trace)\n\n")
             fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
             for r in rows:
@@ -141,6 +147,27 @@ def summarize_counters(d, out_json, out_md):
                 for fam in ("sweep", "walk", "compact"):
                     vals = [_counter_means(sq[0], n).get(fam, float("nan")) for n in names]
                     fo.write(f"| {fam} | " + " | ".join(f"{x:.3g}" for x in vals) + " |\n")
+            ta = glob.glob(os.path.join(d, "ta", "*counter_collection.csv"))
+            tcp = glob.glob(os.path.join(d, "tcp", "*counter_collection.csv"))
+            if ta:
+                # busy fraction: the counter summed over the 256 TA/TD units over 256 x the launch's active
+                # cycles per XCD (GRBM_GUI_ACTIVE summed over the 8 XCDs / 8)
+                fo.write("\n## L1 data path per launch (TA/TD busy fractions, TCP accesses)\n\n")
+                fo.write("| kernel | active cycles per XCD | TA busy | TD busy | L1 accesses | L1 -> L2 reads | "
+                         "VALU instructions | VALU issue (4-cycle estimate) |\n|---|---|---|---|---|---|---|---|\n")
+                for fam in ("walk", "sweep"):
+                    act = _counter_means(ta[0], "GRBM_GUI_ACTIVE").get(fam, float("nan")) / 8
+                    tab = _counter_means(ta[0], "TA_TA_BUSY_sum").get(fam, float("nan")) / 256 / act
+                    tdb = _counter_means(ta[0], "TD_TD_BUSY_sum").get(fam, float("nan")) / 256 / act
+                    acc = _counter_means(tcp[0], "TCP_TOTAL_CACHE_ACCESSES_sum").get(fam, float("nan")) if tcp \
+                        else float("nan")
+                    l2r = _counter_means(tcp[0], "TCP_TCC_READ_REQ_sum").get(fam, float("nan")) if tcp \
+                        else float("nan")
+                    valu = _counter_means(sq[0], "SQ_INSTS_VALU").get(fam, float("nan")) if sq else float("nan")
+                    fo.write(f"| {fam} | {act:.3g} | {tab:.2f} | {tdb:.2f} | {acc:.3g} | {l2r:.3g} | {valu:.3g} | "
+                             f"{valu * 4 / (1024 * act):.2f} |\n")
+                fo.write("\nVALU issue: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x active cycles), an upper estimate "
+                         "for FP32 work, which can issue faster.\n")
     return res
 
 

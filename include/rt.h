@@ -198,7 +198,7 @@ typedef struct {
                                  value does not change results; must be >= 0 */
     int32_t waves_per_cu;     /* persistent grid size (0 = default) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
-    int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 4) */
+    int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 8) */
     int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */
     int64_t padded_trace_budget; /* plans, RT_WALK_PADDED: bytes allowed for single-pass tracing into
                                     padded per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB;
@@ -315,7 +315,9 @@ rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream)
  * 8 at 32 waves per CU; binned 4 at 16; direct 4), and the HIP-event stage times
  * (one warm-up, n_runs timed, rt_plan_profile) credit the walk and the sweep
  * separately.  The fastest of each goes to *best (other fields from *base, or
- * defaults) and the sum of the stage times to *best_ms.  With cache_path, a line
+ * defaults) unless it beats the library default (spatial, group 8, 8 lanes) by
+ * less than 2%, in which case the default stays; the sum of the chosen stage
+ * times goes to *best_ms.  With cache_path, a line
  * "<signature> <schedule> <group> <lanes> <waves_per_cu> <bins> <ms>" is
  * appended, and a later call with the same signature (device, P, E, R, origins,
  * F, precision, moving, adaptive, scheme, refinement switches) returns the cached choice without timing.

@@ -524,7 +524,7 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.grid_waves = num_cus() * wpc;
     a.n_xcd = num_xcds();
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
-    a.group = o.group ? o.group : 4;
+    a.group = o.group ? o.group : 8;
     if (o.scheme != RT_SCHEME_FEAUTRIER2 && o.scheme != RT_SCHEME_HERMITE)
         return fail(RT_ERR_ARG, "solve: scheme must be RT_SCHEME_FEAUTRIER2 or RT_SCHEME_HERMITE");
     a.scheme = o.scheme;
@@ -802,7 +802,7 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     SolveLaunch a = p->base;
     a.u = p->u_buf;
     a.schedule = o.schedule == RT_SCHED_BINNED ? RT_SCHED_BINNED : RT_SCHED_DIRECT;
-    a.group = o.group ? o.group : 4;
+    a.group = o.group ? o.group : 8;
     a.n_bins = opts_bins(o);
     a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? o.waves_per_cu : 32);
     a.items = nullptr;
@@ -1101,16 +1101,16 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     // (HIP events between stages) are credited separately.
     const int lanes[3] = {8, 16, 4};
     struct SweepCand { int sc, gr, wpc; };
-    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 4, 0}, {RT_SCHED_SPATIAL, 8, 0}, {RT_SCHED_BINNED, 4, 32},
+    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 8, 0}, {RT_SCHED_SPATIAL, 4, 0}, {RT_SCHED_BINNED, 4, 32},
                              {RT_SCHED_BINNED, 8, 32}, {RT_SCHED_BINNED, 4, 16}, {RT_SCHED_DIRECT, 4, 0}};
     rt_plan* p = nullptr;
     rt_solve_opts o = b0;
     o.schedule = RT_SCHED_SPATIAL;
-    o.group = 4;
+    o.group = 8;
     o.trace_lanes = 8;
     rt_status st = rt_plan_create(m, set, origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J, &o, stream, &p);
     if (st) return st;
-    double walk_best = 1e300, sweep_best = 1e300, other = 0.0;
+    double walk_best = 1e300, sweep_best = 1e300, other = 0.0, walk_default = 0.0, sweep_default = 0.0;
     int lane_best = 8;
     SweepCand sw_best = sw[0];
     for (int i = 0; i < 6 && !st; ++i) {
@@ -1126,6 +1126,10 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
         if (!st) st = rt_plan_profile(p, n_runs, ms, stream);
         if (st) break;
         const double walk = ms[0] + ms[2], sweep = ms[3] + ms[4];
+        if (i == 0) {  // the library defaults: spatial schedule, group 8, 8 lanes
+            walk_default = walk;
+            sweep_default = sweep;
+        }
         if (i < 3 && walk < walk_best) {
             walk_best = walk;
             lane_best = lanes[i];
@@ -1141,6 +1145,15 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     }
     rt_plan_destroy(p);
     if (st) return st;
+    // keep a default unless a candidate beats it by 2% (run-to-run noise is about 1%)
+    if (!(walk_best < 0.98 * walk_default)) {
+        lane_best = 8;
+        walk_best = walk_default;
+    }
+    if (!(sweep_best < 0.98 * sweep_default)) {
+        sw_best = sw[0];
+        sweep_best = sweep_default;
+    }
     *best = b0;
     best->schedule = sw_best.sc;
     best->group = sw_best.gr;
