@@ -60,6 +60,9 @@ enum { RT_F32 = 1, RT_F64 = 2 };
 /* Message of the last failing call on this thread ("" if none). */
 const char* rt_last_error(void);
 rt_status rt_version(int32_t* major, int32_t* minor);
+/* sizeof(rt_solve_opts) and sizeof(rt_freq_grid) as the library was built, for
+ * bindings that mirror the structs. */
+rt_status rt_struct_sizes(size_t* solve_opts, size_t* freq_grid);
 
 /* ------------------------------------------------------------------ direction sets
  * HEALPix ring-scheme pixels at level l (nside = 2^l) have equal area, 12*4^l of

@@ -47,6 +47,7 @@ class SolveOptsC(C.Structure):
 _SIGS = {
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (_i32, [C.POINTER(_i32), C.POINTER(_i32)]),
+    "rt_struct_sizes": (_i32, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "rt_dirset_uniform": (_i32, [_i32, C.POINTER(_vp)]),
     "rt_dirset_adaptive": (_i32, [_vp, _i32, _i32, _vp, _i64, _vp, _i64, _vp, C.POINTER(_vp)]),
     "rt_dirset_info": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),

@@ -187,7 +187,14 @@ extern "C" const char* rt_last_error(void) { return g_last_error.c_str(); }
 extern "C" rt_status rt_version(int32_t* major, int32_t* minor) {
     if (!major || !minor) return fail(RT_ERR_ARG, "rt_version: NULL output");
     *major = 0;
-    *minor = 1;
+    *minor = 2;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_struct_sizes(size_t* solve_opts, size_t* freq_grid) {
+    if (!solve_opts || !freq_grid) return fail(RT_ERR_ARG, "rt_struct_sizes: NULL output");
+    *solve_opts = sizeof(rt_solve_opts);
+    *freq_grid = sizeof(rt_freq_grid);
     return RT_OK;
 }
 

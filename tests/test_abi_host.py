@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version(lib):
-    assert lib.version() == (0, 1)
+    assert lib.version() == (0, 2)
 
 
 @pytest.mark.parametrize("nside", [1, 2, 4, 8, 16])
@@ -101,6 +101,31 @@ def test_null_arguments_rejected(lib):
     assert L.rt_trace_count_workspace(None, 10, None) == -1
     assert L.rt_plan_run(None, 1, None) == -1
     assert L.rt_dirset_destroy(None) == 0
+    assert L.rt_cached_memory(None) == -1
+    assert L.rt_plan_memory(None) == -1
+
+
+def test_memory_queries_without_device(lib):
+    """With no plan created, the plan-buffer cache and the live-plan count are zero;
+    releasing an empty cache is a no-op."""
+    assert lib.cached_memory() == 0
+    assert lib.plan_memory() == 0
+    lib.release_cached_memory()
+    assert lib.cached_memory() == 0
+
+
+def test_solve_options_struct_layout(lib):
+    """The binding's SolveOptsC matches rt_solve_opts field by field (natural C layout):
+    the scheme field, last, sits after dv_max."""
+    import ctypes as C
+    S = lib.SolveOptsC
+    names = [f[0] for f in S._fields_]
+    assert names[-1] == "scheme" and names[-2] == "dv_max"
+    assert S.scheme.offset == S.dv_max.offset + 8
+    assert C.sizeof(S) == S.scheme.offset + 8  # int32 + tail padding to the struct's 8-byte alignment
+    a, b = C.c_size_t(), C.c_size_t()
+    assert lib.load().rt_struct_sizes(C.byref(a), C.byref(b)) == 0
+    assert (a.value, b.value) == (C.sizeof(S), C.sizeof(lib.FreqGridC))
 
 
 def test_workspace_queries(lib):
