@@ -544,3 +544,43 @@ def test_plan_buffer_cache(rt, wind):
     free1 = torch.cuda.mem_get_info()[0]
     print(f"device memory free before {free0 / 2**30:.3f} GiB, after {free1 / 2**30:.3f} GiB", flush=True)
     assert free1 >= free0 - (64 << 20)
+
+
+def test_full_size_plan_sampled_parity(rt, orc, wind):
+    """The headline configuration as the benchmark times it: one plan over all 50 000
+    wind origins at nside 4, FP32 sweep, library defaults (spatial schedule, load
+    group 8, 8 lanes per ray, exact-slot walk), replayed as a graph.  Sampled origins
+    (the oracle walks and solves them one by one): their ray lists bit-exact, their
+    J within 1e-4 of the FP64 oracle on the same FP32 tables."""
+    torch = _torch()
+    nside = 4
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(nside)
+    _, dirs, w2 = orc.dirset_uniform(nside)
+    c32, e32, c64, e64 = synth.to_fp32_tables(wind.chi, wind.eta)
+    J = torch.empty((wind.P, wind.F), dtype=torch.float32, device="cuda")
+    plan = rt.Plan(model, ds, _t(c32), _t(e32), wind.freq.len, wind.freq.dx, _t(wind.I_bc, torch.float64), J,
+                   n_origins=wind.P, precision=rt.RT_F32, schedule=rt.SCHED_SPATIAL)
+    for _ in range(2):
+        plan.run(use_graph=True)
+    rt.sync_status()
+    rng = np.random.default_rng(77)
+    sample = np.sort(rng.choice(wind.P, 300, replace=False)).astype(np.int32)
+    sample[0], sample[-1] = 0, wind.P - 1  # the first and last slots of the lists too
+    # the sampled origins' ray lists: each origin's 2R rays are one contiguous run
+    off, ids, Z = plan.rays()
+    two_r = 2 * ds.R
+    off_h = off.cpu().numpy()
+    idx = torch.as_tensor(np.concatenate([np.arange(off_h[o * two_r], off_h[(o + 1) * two_r]) for o in sample]),
+                          device="cuda")
+    g_ids, g_Z = ids[idx].cpu().numpy(), Z[idx].cpu().numpy()
+    g_off = np.concatenate([[0], np.cumsum(np.concatenate([np.diff(off_h[o * two_r:(o + 1) * two_r + 1])
+                                                           for o in sample]))])
+    e_off, e_ids, e_Z = orc.trace_all(wind, dirs, sample)
+    assert np.array_equal(g_off, e_off)
+    assert np.array_equal(g_ids, e_ids)
+    assert np.array_equal(g_Z.view(np.uint64), e_Z.view(np.uint64))
+    Je = orc.compute_J(wind, dirs, w2, origins=sample, chi=c64, eta=e64)
+    err = _rel(J[_t(sample).long()].cpu().numpy().astype(np.float64), Je)
+    print(f"full-size plan: {plan.info()['total']} entries, sampled J max rel {err:.2e}", flush=True)
+    assert err <= TOL32
