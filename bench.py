@@ -231,6 +231,8 @@ def main():
                     help="plan walk: once into the creation-time slots (default), once into padded slots plus "
                          "compaction, or count + write")
     ap.add_argument("--closure-points", type=int, default=2_000_000, help="points per closure model")
+    ap.add_argument("--closure-family", choices=["wind", "octree"], default="wind",
+                    help="closure models: analytic winds, or AMR-octree-like clouds (about --closure-points leaves)")
     ap.add_argument("--closure-train", type=int, default=4, help="closure training models (seeds 500..)")
     ap.add_argument("--closure-test", type=int, default=2, help="closure test models (seeds 510..)")
     ap.add_argument("--closure-steps", type=int, default=20000, help="closure training steps")
@@ -543,12 +545,13 @@ def run_directions(args, n_origins=1000, n_sample=10_000):
     print(json.dumps(rec), flush=True)
 
 
-def _gen_wind(seed_P):
+def _gen_model(spec):
+    """One closure model: an analytic wind of P points, or an AMR-octree-like cloud of about P leaves."""
     import synth
-    seed, P = seed_P
-    _log(f"generating wind seed {seed} ({P} points) ...")
+    family, seed, P = spec
+    _log(f"generating {family} seed {seed} ({P} points) ...")
     t0 = time.perf_counter()
-    m = synth.wind_model(seed=seed, P=P)
+    m = synth.wind_model(seed=seed, P=P) if family == "wind" else synth.octree_model(seed=seed, target=P)
     return m, time.perf_counter() - t0
 
 
@@ -570,16 +573,17 @@ def run_closure(args):
     from paper_2011_14998_amd import closure as cl
 
     P = args.closure_points
+    fam = args.closure_family
     seeds_train = [500 + i for i in range(args.closure_train)]
     seeds_test = [510 + i for i in range(args.closure_test)]
     models = {}
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=min(8, len(seeds_train) + len(seeds_test))) as ex:
-        futs = [ex.submit(_gen_wind, (s, P)) for s in seeds_train + seeds_test]
+        futs = [ex.submit(_gen_model, (fam, s, P)) for s in seeds_train + seeds_test]
         for f in as_completed(futs):
             m, sec = f.result()
             models[m.meta["seed"]] = m
-            _log(f"generated wind seed {m.meta['seed']}: {m.P} points, {m.E} entries ({sec:.0f} s)")
+            _log(f"generated {fam} seed {m.meta['seed']}: {m.P} points, {m.E} entries ({sec:.0f} s)")
     gen_s = time.perf_counter() - t0
     nc = args.closure_coarse_nside
     ds1, ds2, ds8 = rt.DirSet.uniform(nc), rt.DirSet.uniform(2), rt.DirSet.uniform(8)
@@ -632,9 +636,10 @@ def run_closure(args):
         "ms_per_step": head["closure_ms"] / len(results),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 mfma / f32 accumulate (network), f32 sweep, f64 geometry",
-        "data": "synthetic (seeded analytic winds)",
-        "config": {"workload": f"learned closure, winds of {P} points, train seeds {seeds_train}, test seeds "
-                               f"{seeds_test}; coarse nside {nc}, fine nside 8, F=64",
+        "data": "synthetic (seeded analytic winds)" if fam == "wind" else "synthetic (seeded AMR-octree-like clouds)",
+        "config": {"workload": f"learned closure, {fam} models of {P} points, train seeds {seeds_train}, test "
+                               f"seeds {seeds_test}; coarse nside {nc}, fine nside 8, F={results[0]['F']}",
+                   "family": fam,
                    "points": P, "train_models": len(seeds_train), "test_models": len(seeds_test),
                    "steps": args.closure_steps, "batch": args.closure_batch, "lr": args.closure_lr},
         "headline": head, "fallback_sweep": summary, "per_model": results,
