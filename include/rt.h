@@ -191,7 +191,8 @@ typedef struct {
     int32_t precision;        /* RT_F32 or RT_F64 */
     int32_t schedule;         /* RT_SCHED_DIRECT: one wave per (origin, pair, 64-frequency chunk) in
                                  slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
-                                 queue, longest lines first; RT_SCHED_SPATIAL (plans only): sweep items
+                                 queue, longest lines first, 16 items per queue atomic (plans: the
+                                 origins' Morton order inside each bin); RT_SCHED_SPATIAL (plans only): sweep items
                                  direction by direction, origins in Morton order of their positions,
                                  each XCD on a contiguous range -- concurrent waves then read mostly the
                                  same rows and the L2s hold them.  A plan's walk always uses that
@@ -199,7 +200,7 @@ typedef struct {
     double dtau_fp64_below;   /* threshold of the FP64-coefficient rule (e.g. 1e-4); kept in the
                                  struct, but every row already has FP64 coefficients (above), so the
                                  value does not change results; must be >= 0 */
-    int32_t waves_per_cu;     /* persistent grid size (0 = default) */
+    int32_t waves_per_cu;     /* persistent grid size in waves per CU (0 = 32; at most 256) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
     int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 8) */
     int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */

@@ -527,7 +527,7 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.max_sub = o.max_substeps > 0 ? o.max_substeps : 1024;
     a.schedule = o.schedule;
     a.n_bins = opts_bins(o);
-    int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;
+    int wpc = o.waves_per_cu > 0 ? std::min(o.waves_per_cu, MAX_WAVES_PER_CU) : 32;
     a.grid_waves = num_cus() * wpc;
     a.n_xcd = num_xcds();
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
@@ -595,7 +595,8 @@ extern "C" rt_status rt_solve(const rt_model* m, const rt_dirset* set_, const in
     rt_status st = fill_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid, I_bc, J,
                                o, a);
     if (st) return st;
-    if (n_origins * a.R * ((a.F + 63) / 64) > INT32_MAX) return fail(RT_ERR_UNSUPPORTED, "rt_solve: too many work items");
+    if (n_origins * a.R * ((a.F + 63) / 64) > MAX_SOLVE_ITEMS)
+        return fail(RT_ERR_UNSUPPORTED, "rt_solve: too many work items");
     void* bin_ws = nullptr;
     st = carve_solve_ws(a, o, u_out, ws, ws_bytes, &bin_ws);
     if (st) return st;
@@ -811,7 +812,7 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     a.schedule = o.schedule == RT_SCHED_BINNED ? RT_SCHED_BINNED : RT_SCHED_DIRECT;
     a.group = o.group ? o.group : 8;
     a.n_bins = opts_bins(o);
-    a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? o.waves_per_cu : 32);
+    a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? std::min(o.waves_per_cu, MAX_WAVES_PER_CU) : 32);
     a.items = nullptr;
     a.order = nullptr;
     a.queue = nullptr;
@@ -829,7 +830,9 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
             return hip_fail(e, "plan: spatial order");
         }
     }
-    if (o.schedule == RT_SCHED_SPATIAL) a.order = p->order;
+    // the spatial schedule walks the sweep's items in the origins' Morton order; the
+    // binned schedule uses the same order inside each length bin
+    if (o.schedule == RT_SCHED_SPATIAL || o.schedule == RT_SCHED_BINNED) a.order = p->order;
     if (o.schedule == RT_SCHED_BINNED) {
         const size_t need = align_up(bin_workspace(solve_items(a), 128)) + 256;
         if (!p->bin_buf) {
@@ -937,7 +940,7 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     }
     st = fill_launch(m, set, origins, n_origins, p->ray_off, p->ids, p->Z, chi, eta, dtype, ld, grid, I_bc, J, p->o,
                      p->a);
-    if (!st && solve_items(p->a) > INT32_MAX) st = fail(RT_ERR_UNSUPPORTED, "rt_plan_create: too many work items");
+    if (!st && solve_items(p->a) > MAX_SOLVE_ITEMS) st = fail(RT_ERR_UNSUPPORTED, "rt_plan_create: too many work items");
     if (st) {
         plan_free(p);
         return st;

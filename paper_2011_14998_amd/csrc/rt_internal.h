@@ -172,6 +172,11 @@ struct SolveLaunch {
     int scheme;            // RT_SCHEME_FEAUTRIER2 or RT_SCHEME_HERMITE
 };
 int64_t solve_items(const SolveLaunch& a);
+// Items a persistent wave takes per queue atomic, the cap on its grid (waves per
+// CU), and so the largest item count whose int32 queue counter cannot overflow.
+constexpr int PERSIST_CHUNK = 16;
+constexpr int MAX_WAVES_PER_CU = 256;
+constexpr int64_t MAX_SOLVE_ITEMS = (int64_t)INT32_MAX - ((int64_t)1 << 26);
 size_t bin_workspace(int64_t n_items, int32_t n_bins);
 hipError_t launch_bin(const SolveLaunch& a, void* ws, int32_t** items_out, hipStream_t s);
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s);

@@ -848,8 +848,9 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
 }
 
 // Persistent variant: a fixed grid of waves drains the item queue; each wave
-// takes the next item with one atomic and exits when the queue is empty, so
-// every wave reaches the end.
+// takes the next PERSIST_CHUNK items with one atomic (one counter shared by
+// every wave: an atomic per item serialised the queue) and exits when the
+// queue is empty, so every wave reaches the end.
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
@@ -859,12 +860,15 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
     for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(a.queue, 1);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if ((int64_t)it >= n_items) break;
-        const int64_t w = a.items ? (int64_t)a.items[it] : (int64_t)it;
-        solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
+        int it0 = 0;
+        if (lane == 0) it0 = atomicAdd(a.queue, PERSIST_CHUNK);
+        it0 = __builtin_amdgcn_readfirstlane(it0);
+        if ((int64_t)it0 >= n_items) break;
+        const int64_t end = (int64_t)it0 + PERSIST_CHUNK < n_items ? (int64_t)it0 + PERSIST_CHUNK : n_items;
+        for (int64_t it = it0; it < end; ++it) {
+            const int64_t w = a.items ? (int64_t)a.items[it] : it;
+            solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
+        }
     }
 }
 
@@ -887,7 +891,16 @@ __global__ __launch_bounds__(256) void k_reduce(const SolveLaunch a) {
 // Bin b holds pairs whose line length N = n_- + n_+ + 1 has floor(4 log2 N) = b
 // (quarter-octave bins, the last bin open-ended).  Items are laid out bin by
 // bin, longest lines first, so the persistent grid starts the long lines early
-// and finishes on short ones.
+// and finishes on short ones.  With a spatial order of the origins (plans), the
+// pairs are visited direction by direction over that order, so inside each bin
+// consecutive items are neighbouring origins along one direction and share
+// table rows in L2, as in the spatial schedule.
+__device__ inline int64_t bin_pair(const SolveLaunch& a, int64_t t) {
+    if (!a.order) return t;
+    const int64_t rc = t / a.n_origins;
+    return (int64_t)a.order[t - rc * a.n_origins] * a.R + rc;
+}
+
 __device__ inline int bin_of(int64_t N, int n_bins) {
     int b = 0;
     double x = (double)N;
@@ -904,9 +917,9 @@ __global__ __launch_bounds__(256) void k_bin_count(const SolveLaunch a) {
     __shared__ int h[MAX_BINS];
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < a.n_origins * a.R) {
-        const int64_t s = 2 * p;  // slot of the +ray: origin*2R + 2r = 2*(origin*R + r)
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < a.n_origins * a.R) {
+        const int64_t s = 2 * bin_pair(a, t);  // slot of the +ray: origin*2R + 2r = 2*(origin*R + r)
         const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
         atomicAdd(&h[bin_of(N, a.n_bins)], 1);
     }
@@ -930,8 +943,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const SolveLaunch a, int32_
     __shared__ int base[MAX_BINS];
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool live = p < a.n_origins * a.R;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool live = t < a.n_origins * a.R;
+    const int64_t p = live ? bin_pair(a, t) : 0;
     int b = 0, local = 0;
     if (live) {
         const int64_t s = 2 * p;
