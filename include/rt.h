@@ -276,8 +276,9 @@ rt_status rt_plan_run(rt_plan* plan, int32_t use_graph, void* stream);
 /* Run the plan eagerly n_runs times on `stream` with HIP events between its
  * stages and return the mean time per stage in ms: stage_ms[6] = {walk (exact
  * write, padded or count), scan, list output (write walk or compaction), bin,
- * sweep, reduce} (scan and list output are ~0 for RT_WALK_EXACT, bin for
- * RT_SCHED_DIRECT).  Synchronises. */
+ * sweep, reduce} (scan and list output are ~0 for RT_WALK_EXACT; bin, the
+ * queue reset of RT_SCHED_BINNED whose item order a plan builds once when it is
+ * configured, is ~0).  Synchronises. */
 rt_status rt_plan_profile(rt_plan* plan, int32_t n_runs, double* stage_ms, void* stream);
 /* Total ray-list entries, and the plan's device ray lists (borrowed views). */
 rt_status rt_plan_info(const rt_plan* plan, int64_t* total_entries, const int64_t** ray_off,

@@ -637,6 +637,7 @@ struct rt_plan {
     void* scan_ws = nullptr;
     void* solve_ws = nullptr;
     void* bin_ws = nullptr;
+    int32_t* bin_items = nullptr;  // the length-binned item order (inside bin_buf), built by plan_configure
     // single-pass tracing into padded slots (cap per ray), then compaction
     int64_t cap = 0;
     int32_t* pids = nullptr;
@@ -692,11 +693,9 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
     }
     mark(3);
     SolveLaunch a = p->a;
-    if (e == hipSuccess && a.schedule == RT_SCHED_BINNED) {
-        int32_t* items = nullptr;
-        e = launch_bin(a, p->bin_ws, &items, s);
-        a.items = items;
-        if (e == hipSuccess) e = launch_fill_i32(a.queue, 1, 0, s);
+    if (e == hipSuccess && a.schedule == RT_SCHED_BINNED) {  // the binned order was built when configured
+        a.items = p->bin_items;
+        e = launch_fill_i32(a.queue, 1, 0, s);
     }
     mark(4);
     if (e == hipSuccess) e = launch_solve(a, p->o.precision, s);
@@ -817,6 +816,7 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     a.order = nullptr;
     a.queue = nullptr;
     p->bin_ws = nullptr;
+    p->bin_items = nullptr;
     // The walk always runs direction-major over Morton-ordered origins (best L2
     // reuse whatever the sweep's schedule); the spatial schedule applies the same
     // order to the sweep's items.
@@ -844,6 +844,14 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
         }
         a.queue = (int32_t*)p->bin_buf;
         p->bin_ws = (char*)p->bin_buf + 256;
+        // Ray lengths are fixed for the plan's life (the count pass at creation gave ray_off, and every walk
+        // of the plan reproduces them), so the length-binned item order is built once here, not per replay.
+        e = launch_bin(a, p->bin_ws, &p->bin_items, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) {
+            p->o = prev;
+            return hip_fail(e, "plan: binned order");
+        }
     }
     p->a = a;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
