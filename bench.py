@@ -121,7 +121,7 @@ def summarize_counters(d, out_json, out_md):
                      "TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum --output-format csv -d <dir>/tcp "
                      f"-o run -- {B}\n\n")
             fo.write("`--no-autotune` runs the library defaults (spatial schedule, load group 8, 8 lanes per ray), "
-                     "which the autotuner keeps unless a candidate is 2% faster, without its candidate runs in the "
+                     "which the autotuner keeps unless a candidate is 5% faster, without its candidate runs in the "
                      "trace.\n\n")
             fo.write("## rocprofv3 --stats (kernel trace)\n\n")
             fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")

@@ -321,7 +321,7 @@ rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream)
  * (one warm-up, n_runs timed, rt_plan_profile) credit the walk and the sweep
  * separately.  The fastest of each goes to *best (other fields from *base, or
  * defaults) unless it beats the library default (spatial, group 8, 8 lanes) by
- * less than 2%, in which case the default stays; the sum of the chosen stage
+ * less than 5%, in which case the default stays; the sum of the chosen stage
  * times goes to *best_ms.  With cache_path, a line
  * "<signature> <schedule> <group> <lanes> <waves_per_cu> <bins> <ms>" is
  * appended, and a later call with the same signature (device, P, E, R, origins,

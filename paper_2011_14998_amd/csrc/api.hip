@@ -1163,12 +1163,12 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     }
     rt_plan_destroy(p);
     if (st) return st;
-    // keep a default unless a candidate beats it by 2% (run-to-run noise is about 1%)
-    if (!(walk_best < 0.98 * walk_default)) {
+    // keep a default unless a candidate beats it by 5%: choices closer than that swap from box to box
+    if (!(walk_best < 0.95 * walk_default)) {
         lane_best = 8;
         walk_best = walk_default;
     }
-    if (!(sweep_best < 0.98 * sweep_default)) {
+    if (!(sweep_best < 0.95 * sweep_default)) {
         sw_best = sw[0];
         sweep_best = sweep_default;
     }
