@@ -316,8 +316,9 @@ rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream)
 
 /* Autotuner.  On the caller's data, one plan is built and re-captured for six
  * candidate runs; each run varies the walk's lanes per ray (8, 16, 4) and the
- * sweep's schedule / load group / persistent grid (spatial 4 and 8; binned 4 and
- * 8 at 32 waves per CU; binned 4 at 16; direct 4), and the HIP-event stage times
+ * sweep's schedule / load group / persistent grid / length bins (spatial 8 and 4;
+ * binned 8 at 32 waves per CU with 64 and with 32 bins; binned 4 at 16 waves per
+ * CU with 128 bins; direct 4), and the HIP-event stage times
  * (one warm-up, n_runs timed, rt_plan_profile) credit the walk and the sweep
  * separately.  The fastest of each goes to *best (other fields from *base, or
  * defaults) unless it beats the library default (spatial, group 8, 8 lanes) by

@@ -1118,9 +1118,10 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     // different stages, so each candidate run varies both and the stage times
     // (HIP events between stages) are credited separately.
     const int lanes[3] = {8, 16, 4};
-    struct SweepCand { int sc, gr, wpc; };
-    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 8, 0}, {RT_SCHED_SPATIAL, 4, 0}, {RT_SCHED_BINNED, 4, 32},
-                             {RT_SCHED_BINNED, 8, 32}, {RT_SCHED_BINNED, 4, 16}, {RT_SCHED_DIRECT, 4, 0}};
+    struct SweepCand { int sc, gr, wpc, bins; };
+    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 8, 0, 0},   {RT_SCHED_SPATIAL, 4, 0, 0},
+                             {RT_SCHED_BINNED, 8, 32, 64},  {RT_SCHED_BINNED, 8, 32, 32},
+                             {RT_SCHED_BINNED, 4, 16, 128}, {RT_SCHED_DIRECT, 4, 0, 0}};
     rt_plan* p = nullptr;
     rt_solve_opts o = b0;
     o.schedule = RT_SCHED_SPATIAL;
@@ -1135,7 +1136,7 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
         o.schedule = sw[i].sc;
         o.group = sw[i].gr;
         o.waves_per_cu = sw[i].wpc;
-        o.n_bins = sw[i].sc == RT_SCHED_BINNED ? 64 : 0;
+        o.n_bins = sw[i].bins;
         o.trace_lanes = lanes[i % 3];
         st = plan_configure(p, o);
         if (st) break;
@@ -1158,8 +1159,9 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
         }
         other = ms[1] + ms[5];
         if (verbose)
-            std::fprintf(stderr, "autotune: lanes %d schedule %d group %d waves/CU %d -> walk %.3f ms, sweep %.3f ms\n",
-                         o.trace_lanes, o.schedule, o.group, o.waves_per_cu, walk, sweep);
+            std::fprintf(stderr,
+                         "autotune: lanes %d schedule %d group %d waves/CU %d bins %d -> walk %.3f ms, sweep %.3f ms\n",
+                         o.trace_lanes, o.schedule, o.group, o.waves_per_cu, o.n_bins, walk, sweep);
     }
     rt_plan_destroy(p);
     if (st) return st;
@@ -1176,7 +1178,7 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     best->schedule = sw_best.sc;
     best->group = sw_best.gr;
     best->waves_per_cu = sw_best.wpc;
-    best->n_bins = sw_best.sc == RT_SCHED_BINNED ? 64 : 0;
+    best->n_bins = sw_best.bins;
     best->trace_lanes = lane_best;
     const double bms = walk_best + sweep_best + other;
     if (best_ms) *best_ms = bms;
