@@ -128,6 +128,18 @@ def summarize_counters(d, out_json, out_md):
             for r in rows:
                 fo.write(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                          f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |\n")
+            dflt = glob.glob(os.path.join(d, "stats_default", "*kernel_stats.csv"))
+            if dflt:
+                fo.write("\n## rocprofv3 --stats of the default command\n\n")
+                fo.write("    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats_default -o bench -- "
+                         "python3 bench.py\n\n")
+                fo.write("The whole default run: autotuner candidates (one warm-up and two timed runs each), warm-up, "
+                         "the timed graph replays and the per-stage profile runs; the kernel instance the bench "
+                         "times is the one its JSON line names.\n\n")
+                fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
+                for r in list(csv.DictReader(open(dflt[0]))):
+                    fo.write(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                             f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |\n")
             fo.write("\n## HBM traffic per launch (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale)\n\n")
             c = res["calibration"]
             fo.write(f"Calibration: a plain 1 GiB device copy reads as FETCH_SIZE {c['FETCH_SIZE_KiB']:.0f} KiB and "
