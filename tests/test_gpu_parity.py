@@ -584,3 +584,27 @@ def test_full_size_plan_sampled_parity(rt, orc, wind):
     err = _rel(J[_t(sample).long()].cpu().numpy().astype(np.float64), Je)
     print(f"full-size plan: {plan.info()['total']} entries, sampled J max rel {err:.2e}", flush=True)
     assert err <= TOL32
+
+
+@pytest.mark.parametrize("n_org", [1, 3, 7, 33])
+def test_persistent_queue_small_and_ragged(rt, orc, n_org):
+    """The persistent launch takes 16 items per queue atomic: item counts below one
+    chunk, and counts that leave a partial last chunk (nside 1: 6 pairs per origin,
+    two 64-frequency chunks at F = 70), give the direct launch's bits, eagerly and
+    from a binned plan replayed twice; FP64 also against the oracle."""
+    torch = _torch()
+    m = synth.tiny_model(90 + n_org, P=40, F=70, moving=True)
+    origins = np.arange(n_org, dtype=np.int32) * 3 % m.P
+    model, ds, g, _, dirs, w2, org, oo = _trace_both(rt, orc, m, 1, origins)
+    Jd = _solve_gpu(rt, m, model, ds, g, org, len(oo), rt.RT_F64, schedule=rt.SCHED_DIRECT).cpu().numpy()
+    assert _rel(Jd, orc.compute_J(m, dirs, w2, origins=oo)) <= TOL64
+    Jb = _solve_gpu(rt, m, model, ds, g, org, len(oo), rt.RT_F64, schedule=rt.SCHED_BINNED).cpu().numpy()
+    assert np.array_equal(Jd, Jb)
+    J = torch.empty((len(oo), m.F), dtype=torch.float64, device="cuda")
+    plan = rt.Plan(model, ds, _t(m.chi), _t(m.eta), m.freq.len, m.freq.dx, _t(m.I_bc, torch.float64), J,
+                   origins=org, precision=rt.RT_F64, schedule=rt.SCHED_BINNED, waves_per_cu=1)
+    for _ in range(2):
+        J.zero_()
+        plan.run(use_graph=True)
+        rt.sync_status()
+        assert np.array_equal(J.cpu().numpy(), Jd)
