@@ -218,10 +218,11 @@ __device__ inline HermCoef<T> herm_coef(T a, T b) {
     return HermCoef<T>{P * r6p, Q * r6q, (t12 - P) * r6p, (t12 - Q) * r6q};
 }
 
-// S = eta/chi in FP64, a correctly rounded division (the widened FP32 values
-// give the same S as FP64 tables of those values would).
+// S = eta/chi in FP64 through the refined reciprocal (within an ulp or two of
+// the correctly rounded quotient: the rows' own rounding sensitivity, which the
+// parity bar of these rows allows, is larger).
 template <typename T>
-__device__ inline double src64(T e, T c) { return (double)e / (double)c; }
+__device__ inline double src64(T e, T c) { return (double)e * rcp64((double)c); }
 
 // Row d: its inner step b, its own optics (c, e) and the next point's (cn, en).
 // The state carries S of the previous row's point (Sp) and of this one (Sc,
