@@ -183,6 +183,26 @@ def summarize_counters(d, out_json, out_md):
     return res
 
 
+def copy_ceiling_gbs(dev, n_bytes: int = 2 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (read + write bytes per second) of a 2 GiB
+    buffer on this machine: the practical HBM ceiling beside the 8 TB/s specification."""
+    import torch
+    x = torch.empty(n_bytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    rate = 2.0 * n_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return rate
+
+
 def load_traffic(kernel_hash, launch_bytes_alg):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source."""
@@ -409,6 +429,8 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg,
             "sweep_ms": stages["sweep"],
+            "traffic_gbs": traffic / (stages["sweep"] * 1e-3) / 1e9 if traffic else None,
+            "copy_ceiling_gbs": copy_ceiling_gbs(dev),
         },
         "stages_ms": stages,
         "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms_step * 1e-3),
