@@ -31,6 +31,26 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile a modified copy of oracle.c (given as text) with the oracle's flags into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                           "-fno-builtin-sin", "-fno-builtin-cos", "-shared", "-fPIC", "-o", out_path, src, "-lm"])
+    return out_path
+
+
+def load_variant(path: str):
+    """A separately built oracle library, with the signature of or_compute_J_sub declared."""
+    L = C.CDLL(path)
+    i64, i32, vp = C.c_int64, C.c_int32, C.c_void_p
+    L.or_compute_J_sub.restype = C.c_int
+    L.or_compute_J_sub.argtypes = [i64, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, i64, vp, i64, vp,
+                                   vp, i32, vp, i64, C.c_double, C.c_double, i64, i32, vp, vp, C.c_int]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -216,13 +236,15 @@ def feautrier_u_hermite(dtau, S, m: int, I: float) -> float:
 
 def compute_J(model, dirs, w2, origins=None, chi=None, eta=None, I_bc=None, nthreads: int = 0,
               want_u: bool = False, dtau_max: float = 0.0, max_sub: int = 1024, dv_max: float = 0.0,
-              scheme: int = 0):
+              scheme: int = 0, lib_path: str = None):
     """J[n_origins][F] (and optionally u[n_origins][R][F]) in FP64.  dv_max > 0 samples line
     intervals whose projected velocity changes by more than dv_max Doppler widths (Section 2.1.1);
     dtau_max > 0 then splits every interval into optical-depth sub-steps (Section 2.1.2, eq. 2);
     at most max_sub parts per interval for each.  scheme 0: second-order Feautrier rows; 1: the
-    fourth-order Hermitian rows with third-order boundary conditions (Section 2.1)."""
-    L = lib()
+    fourth-order Hermitian rows with third-order boundary conditions (Section 2.1).
+    lib_path: another build of oracle.c to run instead (the tests check that their pins catch
+    mistakes planted in a copy of the source)."""
+    L = lib() if lib_path is None else load_variant(lib_path)
     dirs = _c(dirs, np.float64)
     w2 = _c(w2, np.float64)
     per = 1 if dirs.ndim == 3 else 0

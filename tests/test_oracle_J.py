@@ -185,7 +185,9 @@ def _exact_line_u(trace_ray, m, o, d, f, I):
 
 def test_general_doppler_shift_exact(orc):
     """Moving medium with non-integer shifts in two blocks of different widths: the
-    oracle's per-pair u against an independent exact-rational construction."""
+    oracle's per-pair u against the reading restated in exact rationals (general tables).
+    This is a consistency check of the whole line path; the interpolation itself is pinned
+    by a closed form that does not restate it (test_oracle_doppler.py)."""
     m = synth.tiny_model(31, P=45, F=10, moving=True)
     m.freq = synth.FreqGrid(np.array([6, 4], np.int32), np.array([-3.0, -1.0]), np.array([0.7, 0.45]))
     rng = np.random.default_rng(8)
