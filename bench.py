@@ -278,9 +278,6 @@ def main():
     ap.add_argument("--dtau-max", type=float, default=0.0,
                     help="adaptive optical-depth increments: split line intervals to at most this optical depth "
                          "(0 = off)")
-    ap.add_argument("--fp64-below", type=float, default=1e-4,
-                    help="rt_solve_opts.dtau_fp64_below (kept in the options; no effect: every row already has "
-                         "FP64 coefficients)")
     ap.add_argument("--scheme", choices=["feautrier2", "hermite"], default="feautrier2",
                     help="rows of the line solve: second-order Feautrier, or the fourth-order Hermitian rows "
                          "(steps must stay below about 3.46: use --dtau-max)")
@@ -357,13 +354,13 @@ def main():
         _log("autotuning (schedule, sweep load group, walk lanes, persistent grid) ...")
         t0 = time.perf_counter()
         opts, tuned_ms = rt.autotune(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P,
-                                     precision=rt.RT_F32, dtau_fp64_below=args.fp64_below, n_runs=2,
+                                     precision=rt.RT_F32, n_runs=2,
                                      verbose=True, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme)
         tuned = dict(opts, ms_per_step=tuned_ms, seconds=time.perf_counter() - t0)
         _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
     _log("planning (count pass, buffers, graph capture) ...")
     plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   dtau_fp64_below=args.fp64_below, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme,
+                   dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme,
                    walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
                    **opts)
     total = plan.info()["total"]
@@ -494,8 +491,8 @@ def run_precision(args):
             del plan
         _log(f"{name}: fp32 max {rec['fp32']['max_rel']:.2e}, fp64 max {rec['fp64']['max_rel']:.2e}")
         out.append(rec)
-    print(json.dumps({"metric": "relative error of J against the FP64 oracle, per model", "per_model": out,
-                      "fp64_rows_below_dtau": args.fp64_below}), flush=True)
+    print(json.dumps({"metric": "relative error of J against the FP64 oracle, per model", "per_model": out}),
+          flush=True)
 
 
 def run_directions(args, n_origins=1000, n_sample=10_000):
@@ -644,7 +641,7 @@ def run_closure(args):
         dm = cl.DeviceModel.from_synth(models.pop(sd))
         lab = cl.label(dm, ds1, ds8, verbose=True)
         # warm timing of both paths: the labelling runs above include first-launch costs
-        r = cl.evaluate(net, lab, ds8, fractions, mid_set=ds2, verbose=True)
+        r = cl.evaluate(net, lab, ds1, ds8, fractions, mid_set=ds2, verbose=True)
         results.append(r)
         del lab, dm
         torch.cuda.empty_cache()

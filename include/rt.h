@@ -178,11 +178,15 @@ rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int3
  * carried per unit inner step (F = dtau G, Z = dtau Y), so the only
  * elimination coefficient, (dtau_{d-1} + dtau_d)/2, is in FP32 exactly its FP64
  * value rounded once: every row, however small its steps, has FP64
- * coefficients, and no row needs a separate FP64 path. */
+ * coefficients, and no row needs a separate FP64 path (so there is no
+ * threshold option for one). */
 typedef struct {
     int32_t n_blocks;
     const int32_t* len; /* host [n_blocks] */
     const double* dx;   /* host [n_blocks] */
+    const double* x0;   /* host [n_blocks]: frequency of the block's first point in Doppler widths
+                           about the line centre, x = x0[b] + j dx[b]; NULL = each block centred,
+                           x0 = -(len-1) dx / 2.  Only the closure's features read it. */
 } rt_freq_grid;
 
 enum { RT_SCHED_DIRECT = 0, RT_SCHED_BINNED = 1, RT_SCHED_SPATIAL = 2 };
@@ -197,11 +201,11 @@ typedef struct {
                                  each XCD on a contiguous range -- concurrent waves then read mostly the
                                  same rows and the L2s hold them.  A plan's walk always uses that
                                  order. */
-    double dtau_fp64_below;   /* threshold of the FP64-coefficient rule (e.g. 1e-4); kept in the
-                                 struct, but every row already has FP64 coefficients (above), so the
-                                 value does not change results; must be >= 0 */
     int32_t waves_per_cu;     /* persistent grid size in waves per CU (0 = 32; at most 256) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
+    int32_t bins_per_octave;  /* RT_SCHED_BINNED bin edges: a pair whose line holds N points goes to bin
+                                 floor(bins_per_octave * log2 N) (the last bin open-ended); 1, 2, 4 or
+                                 8 (0 = 4, quarter octaves) */
     int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 8) */
     int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */
     int64_t padded_trace_budget; /* plans, RT_WALK_PADDED: bytes allowed for single-pass tracing into
@@ -254,6 +258,39 @@ rt_status rt_solve(const rt_model* model, const rt_dirset* set, const int32_t* o
                    const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
                    const double* I_bc, void* J, void* u_out, const rt_solve_opts* opts,
                    void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ J in one call
+ * The whole path for a list of origins -- trace (count, scan, write), sweep and
+ * J (eq. 3, eq. 4) -- inside the caller's workspace, the origins taken in
+ * chunks whose ray lists fit it.  The origins are put in Morton order of their
+ * positions (shared sets; an adaptive set keeps the list order) and cut into
+ * consecutive chunks, so each chunk walks one region of the model; within a
+ * chunk rays and sweep items run direction by direction over that order
+ * (opts->schedule RT_SCHED_SPATIAL or RT_SCHED_DIRECT) or length-binned
+ * (RT_SCHED_BINNED); the J rows go back to the caller's list order.  Results
+ * are bit-identical to rt_trace_count + rt_trace_write + rt_solve on the whole
+ * list: every ray and every (origin, pair) is computed the same way wherever
+ * it falls.
+ *
+ * rt_compute_J_workspace: bytes with which one chunk holds every origin,
+ * assuming rays of at most `mean_entries` list entries on average (<= 0: 64).
+ * Less workspace is allowed: rt_compute_J then takes as many origins per chunk
+ * as the space left for lists admits at the mean ray length of the chunks
+ * already traced (a first chunk of at most 1024 origins), recounting a chunk
+ * at half the size when its lists do not fit; RT_ERR_CAPACITY when a single
+ * origin's rays do not fit, or the workspace is below the fixed part for one
+ * origin (about 2R*(4+8+12) + R*F*s + 1 KiB bytes).
+ * rt_compute_J: origins device int32 [n_origins] (NULL = 0..n_origins-1);
+ * J [n_origins][F] of the precision's dtype; u_out (may be NULL) receives
+ * u[n_origins][R][F].  Synchronises `stream` once per chunk (to read the chunk's
+ * list length) and once for the Morton order; allocates nothing; everything
+ * else is async. */
+rt_status rt_compute_J_workspace(const rt_dirset* set, int64_t n_origins, int64_t F, const rt_solve_opts* opts,
+                                 double mean_entries, size_t* bytes);
+rt_status rt_compute_J(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                       const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                       const double* I_bc, void* J, void* u_out, const rt_solve_opts* opts, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ plans
  * A plan owns the ray-list buffers for a fixed (model, set, origins) and replays
@@ -314,25 +351,68 @@ rt_status rt_plan_memory(size_t* bytes);
  * Synchronises `stream`. */
 rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream);
 
-/* Autotuner.  On the caller's data, one plan is built and re-captured for six
- * candidate runs; each run varies the walk's lanes per ray (8, 16, 4) and the
- * sweep's schedule / load group / persistent grid / length bins (spatial 8 and 4;
- * binned 8 at 32 waves per CU with 64 and with 32 bins; binned 4 at 16 waves per
- * CU with 128 bins; direct 4), and the HIP-event stage times
- * (one warm-up, n_runs timed, rt_plan_profile) credit the walk and the sweep
- * separately.  The fastest of each goes to *best (other fields from *base, or
- * defaults) unless it beats the library default (spatial, group 8, 8 lanes) by
- * less than 5%, in which case the default stays; the sum of the chosen stage
- * times goes to *best_ms.  With cache_path, a line
- * "<signature> <schedule> <group> <lanes> <waves_per_cu> <bins> <ms>" is
- * appended, and a later call with the same signature (device, P, E, R, origins,
- * F, precision, moving, adaptive, scheme, refinement switches) returns the cached choice without timing.
- * verbose != 0 prints one line per candidate to stderr.  Synchronises, allocates. */
+/* Autotuner.  On the caller's data, one plan is built and re-captured for
+ * nine candidate runs; each run varies the walk's lanes per ray (8, 16, 4) and
+ * the sweep's schedule and its parameters: spatial with load group 8 and 4;
+ * length-binned persistent with load group 8 at 32 waves per CU and bin edges
+ * of 4, 2 and 8 per octave (64, 32 and 128 bins), group 4 at 16 waves per CU
+ * (4 per octave, 128 bins) and group 8 at 64 waves per CU (4 per octave, 64
+ * bins); direct with group 4 and 8.  The HIP-event stage times (one warm-up,
+ * n_runs timed, rt_plan_profile) credit the walk and the sweep separately.
+ * The fastest of each goes to *best (other fields from *base, or defaults)
+ * unless it beats the library default (spatial, group 8, 8 lanes) by less than
+ * 5%, in which case the default stays; the sum of the chosen stage times goes
+ * to *best_ms.  With cache_path, a line "<signature> <schedule> <group>
+ * <lanes> <waves_per_cu> <bins> <bins_per_octave> <ms>" is appended, and a
+ * later call with the same signature (device, P, E, R, origins, F, precision,
+ * moving, adaptive, scheme, refinement switches) returns the cached choice
+ * without timing.  verbose != 0 prints one line per candidate to stderr.
+ * Synchronises, allocates. */
 rt_status rt_autotune(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
                       const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
                       const double* I_bc, void* J, const rt_solve_opts* base, int32_t n_runs,
                       const char* cache_path, int32_t verbose, void* stream, rt_solve_opts* best,
                       double* best_ms);
+/* The same search on an existing plan (e.g. a batch's), which is left
+ * re-captured with the chosen options; no cache.  Synchronises. */
+rt_status rt_autotune_plan(rt_plan* plan, int32_t n_runs, int32_t verbose, void* stream, rt_solve_opts* best,
+                           double* best_ms);
+
+/* ------------------------------------------------------------------ many models at once
+ * Many independent models of different sizes in one launch: a disjoint union
+ * built on the device (positions and velocities concatenated, neighbour ids
+ * and CSR offsets shifted by each model's first point and entry, the tables
+ * gathered into one [P_total][F] array), so rays never cross from one model
+ * into another and every result is bit-identical to solving each model alone
+ * (positions are not moved).  The union is traced and solved by one plan (a
+ * single HIP graph: table gather, walk, sweep over every model's items in one
+ * launch -- length-binned persistent or spatial, as opts says -- J reduction
+ * and the scatter of J back to each model's own array).  Origins are every
+ * point of every model, in model order, each model's points in Morton order
+ * of their positions.
+ *
+ * rt_batch_create: models[n_models] (handles on the current device), one
+ * uniform direction set for all, chi[k]/eta[k] device [P_k][ld[k]] of `dtype`,
+ * one frequency grid and I_bc for all, J[k] device [P_k][F].  Builds the union
+ * and the plan (synchronises, allocates).  rt_batch_run: replay (async;
+ * use_graph = 0 launches the steps one by one).  rt_batch_plan: the inner plan
+ * over the union (for rt_plan_profile, rt_plan_info, rt_plan_retune,
+ * rt_autotune_plan); owned by the batch.  rt_batch_union: the union's point
+ * and entry counts.
+ * rt_compute_J_batched: create, run once, synchronise, destroy. */
+typedef struct rt_batch rt_batch;
+rt_status rt_batch_create(int32_t n_models, const rt_model* const* models, const rt_dirset* set,
+                          const void* const* chi, const void* const* eta, int32_t dtype, const int64_t* ld,
+                          const rt_freq_grid* grid, const double* I_bc, void* const* J, const rt_solve_opts* opts,
+                          void* stream, rt_batch** out);
+rt_status rt_batch_run(rt_batch* batch, int32_t use_graph, void* stream);
+rt_status rt_batch_plan(rt_batch* batch, rt_plan** plan);
+rt_status rt_batch_union(const rt_batch* batch, int64_t* points, int64_t* entries);
+rt_status rt_batch_destroy(rt_batch* batch);
+rt_status rt_compute_J_batched(int32_t n_models, const rt_model* const* models, const rt_dirset* set,
+                               const void* const* chi, const void* const* eta, int32_t dtype, const int64_t* ld,
+                               const rt_freq_grid* grid, const double* I_bc, void* const* J,
+                               const rt_solve_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------ learned closure
  * A cheap J from the nside = 1 set (6 pairs, Section 2.1.3) plus local optical
@@ -426,6 +506,33 @@ rt_status rt_closure_targets(const float* J1, const float* J_fine, int64_t n, fl
  * position outside 0..n_points-1 is skipped and latches RT_ERR_ARG.  Async. */
 rt_status rt_closure_merge(const float* J_fine, const int32_t* flagged, int64_t n_flagged, int64_t F,
                            int64_t n_points, float* J, void* stream);
+
+/* The standardisation the network's inputs were trained with, x_c = bf16((feat_c
+ * - mean[c]) * inv_std[c]) (host [16] each; rt_closure_normalize with these
+ * values), kept by the handle for rt_closure_J.  Synchronous, host only. */
+rt_status rt_mlp_set_input_norm(rt_mlp* mlp, const float* mean, const float* inv_std);
+
+/* The learned closure from start to end for every point of a model: J1 and
+ * the per-pair u of the coarse set by rt_compute_J; per (point, frequency) the
+ * features of rt_closure_features (frequency x from the grid's x0 and dx),
+ * standardised with the handle's input norm, through the network (points taken
+ * 65 536 at a time); J = J1 exp(m) and the fallback flags of rt_closure_apply
+ * with log_bound; the flagged points re-solved with the fine set by
+ * rt_compute_J and merged into J.  chi, eta device f32 [P][ld]; J device f32
+ * [P][F]; flagged device int32 [P] receives the flagged point ids (in no
+ * particular order), *n_flagged (host) their count.  The workspace holds the
+ * coarse solve, one chunk of inference buffers and the fine J of the flagged
+ * points (rt_closure_J_workspace with solve_bytes = 0), plus whatever is left
+ * for the two rt_compute_J calls, which chunk their origins to fit it
+ * (solve_bytes; e.g. rt_compute_J_workspace of the fine set for a few
+ * thousand origins).  RT_ERR_STATE if no input norm was set.  Synchronises
+ * (per rt_compute_J chunk, and to read the flag count); allocates nothing. */
+rt_status rt_closure_J_workspace(const rt_model* model, const rt_dirset* coarse, int64_t F, size_t solve_bytes,
+                                 size_t* bytes);
+rt_status rt_closure_J(const rt_model* model, const rt_dirset* coarse, const rt_dirset* fine, const float* chi,
+                       const float* eta, int64_t ld, const rt_freq_grid* grid, const double* I_bc, const rt_mlp* mlp,
+                       float log_bound, float* J, int32_t* flagged, int64_t* n_flagged, const rt_solve_opts* opts,
+                       void* ws, size_t ws_bytes, void* stream);
 
 /* Spatial order of an origin list (device int32 [n], or NULL for 0..n-1):
  * order (host int32 [n]) receives the list positions sorted by the Morton code

@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     WALK_PADDED,
     WALK_TWO_PASS,
     MLP,
+    Batch,
     DirSet,
     Model,
     Plan,
@@ -34,6 +35,12 @@ from .binding import (  # noqa: F401
     closure_targets,
     release_cached_memory,
     compute_J,
+    compute_J_batched,
+    compute_J_direct,
+    compute_J_workspace,
+    closure_J,
+    closure_J_ws,
+    opts_dict,
     healpix_vec2pix,
     load,
     mesh_indicators,

@@ -33,14 +33,14 @@ class RtError(RuntimeError):
 
 
 class FreqGridC(C.Structure):
-    _fields_ = [("n_blocks", _i32), ("len", C.POINTER(_i32)), ("dx", C.POINTER(_dbl))]
+    _fields_ = [("n_blocks", _i32), ("len", C.POINTER(_i32)), ("dx", C.POINTER(_dbl)), ("x0", C.POINTER(_dbl))]
 
 
 class SolveOptsC(C.Structure):
-    _fields_ = [("precision", _i32), ("schedule", _i32), ("dtau_fp64_below", _dbl),
-                ("waves_per_cu", _i32), ("n_bins", _i32), ("group", _i32), ("trace_lanes", _i32),
-                ("padded_trace_budget", _i64), ("walk", _i32), ("dtau_max", _dbl), ("max_substeps", _i32),
-                ("dv_max", _dbl), ("scheme", _i32)]
+    _fields_ = [("precision", _i32), ("schedule", _i32),
+                ("waves_per_cu", _i32), ("n_bins", _i32), ("bins_per_octave", _i32), ("group", _i32),
+                ("trace_lanes", _i32), ("padded_trace_budget", _i64), ("walk", _i32), ("dtau_max", _dbl),
+                ("max_substeps", _i32), ("dv_max", _dbl), ("scheme", _i32)]
 
 
 # name -> (restype, argtypes)
@@ -76,6 +76,22 @@ _SIGS = {
                            C.POINTER(SolveOptsC), _i32, C.c_char_p, _i32, _vp, C.POINTER(SolveOptsC),
                            C.POINTER(_dbl)]),
     "rt_plan_retune": (_i32, [_vp, C.POINTER(SolveOptsC), _vp]),
+    "rt_autotune_plan": (_i32, [_vp, _i32, _i32, _vp, C.POINTER(SolveOptsC), C.POINTER(_dbl)]),
+    "rt_compute_J_workspace": (_i32, [_vp, _i64, _i64, C.POINTER(SolveOptsC), _dbl, C.POINTER(_sz)]),
+    "rt_compute_J": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC), _vp, _vp, _vp,
+                            C.POINTER(SolveOptsC), _vp, _sz, _vp]),
+    "rt_batch_create": (_i32, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, C.POINTER(FreqGridC), _vp, _vp,
+                               C.POINTER(SolveOptsC), _vp, C.POINTER(_vp)]),
+    "rt_batch_run": (_i32, [_vp, _i32, _vp]),
+    "rt_batch_plan": (_i32, [_vp, C.POINTER(_vp)]),
+    "rt_batch_union": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
+    "rt_batch_destroy": (_i32, [_vp]),
+    "rt_compute_J_batched": (_i32, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, C.POINTER(FreqGridC), _vp, _vp,
+                                    C.POINTER(SolveOptsC), _vp]),
+    "rt_mlp_set_input_norm": (_i32, [_vp, _vp, _vp]),
+    "rt_closure_J_workspace": (_i32, [_vp, _vp, _i64, _sz, C.POINTER(_sz)]),
+    "rt_closure_J": (_i32, [_vp, _vp, _vp, _vp, _vp, _i64, C.POINTER(FreqGridC), _vp, _vp, C.c_float, _vp, _vp,
+                            C.POINTER(_i64), C.POINTER(SolveOptsC), _vp, _sz, _vp]),
     "rt_sync_status": (_i32, [_vp]),
     "rt_mlp_num_params": (_i32, [C.POINTER(_i64)]),
     "rt_mlp_create": (_i32, [C.c_uint64, _vp, C.POINTER(_vp)]),
@@ -317,23 +333,33 @@ def trace(model: Model, dirset: DirSet, origins=None, n_origins=None, stream=Non
     return ray_off, ids[:total], Z[:total]
 
 
-def _grid(freq_len: Sequence[int], freq_dx: Sequence[float]):
+def _grid(freq_len: Sequence[int], freq_dx: Sequence[float], freq_x0: Sequence[float] = None):
     ln = (_i32 * len(freq_len))(*[int(x) for x in freq_len])
     dx = (_dbl * len(freq_dx))(*[float(x) for x in freq_dx])
-    g = FreqGridC(len(freq_len), ln, dx)
-    return g, (ln, dx)
+    x0 = None if freq_x0 is None else (_dbl * len(freq_x0))(*[float(x) for x in freq_x0])
+    g = FreqGridC(len(freq_len), ln, dx, x0)
+    return g, (ln, dx, x0)
 
 
-def _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget=0, group=0,
-          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0, dv_max=0.0, scheme=0):
-    return SolveOptsC(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group, trace_lanes,
-                      padded_trace_budget, walk, dtau_max, max_substeps, dv_max, scheme)
+def _opts(precision=RT_F32, schedule=0, waves_per_cu=0, n_bins=0, padded_trace_budget=0, group=0,
+          trace_lanes=0, walk=0, dtau_max=0.0, max_substeps=0, dv_max=0.0, scheme=0, bins_per_octave=0):
+    return SolveOptsC(precision=precision, schedule=schedule, waves_per_cu=waves_per_cu, n_bins=n_bins,
+                      bins_per_octave=bins_per_octave, group=group, trace_lanes=trace_lanes,
+                      padded_trace_budget=padded_trace_budget, walk=walk, dtau_max=dtau_max,
+                      max_substeps=max_substeps, dv_max=dv_max, scheme=scheme)
+
+
+def opts_dict(o: SolveOptsC) -> dict:
+    """The scheduling fields of an options struct (as the autotuner reports them)."""
+    return dict(schedule=o.schedule, group=o.group, trace_lanes=o.trace_lanes, waves_per_cu=o.waves_per_cu,
+                n_bins=o.n_bins, bins_per_octave=o.bins_per_octave)
 
 
 def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
-          precision: int = RT_F32, schedule: int = SCHED_DIRECT, dtau_fp64_below: float = 1e-4,
+          precision: int = RT_F32, schedule: int = SCHED_DIRECT,
           waves_per_cu: int = 0, n_bins: int = 0, group: int = 0, want_u: bool = False, dtau_max: float = 0.0,
-          max_substeps: int = 0, dv_max: float = 0.0, scheme: int = SCHEME_FEAUTRIER2, stream=None):
+          max_substeps: int = 0, dv_max: float = 0.0, scheme: int = SCHEME_FEAUTRIER2, bins_per_octave: int = 0,
+          stream=None):
     """J [n_o][F] (dtype of the precision) from ray lists; optionally u [n_o][R][F].  dtau_max > 0
     splits line intervals into optical-depth sub-steps (rt_solve_opts.dtau_max); scheme picks the
     second-order or the fourth-order Hermitian rows (rt_solve_opts.scheme)."""
@@ -352,8 +378,8 @@ def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc,
     F = int(sum(freq_len))
     R = dirset.R
     g, keep = _grid(freq_len, freq_dx)
-    o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, group=group, dtau_max=dtau_max,
-              max_substeps=max_substeps, dv_max=dv_max, scheme=scheme)
+    o = _opts(precision, schedule, waves_per_cu, n_bins, group=group, dtau_max=dtau_max,
+              max_substeps=max_substeps, dv_max=dv_max, scheme=scheme, bins_per_octave=bins_per_octave)
     u = torch.empty((n_origins, R, F), dtype=dt, device=chi.device) if want_u else None
     wsb = _sz()
     _check(L.rt_solve_workspace(dirset._h, n_origins, F, C.byref(o), C.byref(wsb)))
@@ -367,13 +393,145 @@ def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc,
     return (J, u) if want_u else J
 
 
-def compute_J(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, origins=None, **kw):
+def compute_J_direct(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, origins=None, **kw):
+    """J from the low-level calls: rt_trace_count + rt_trace_write over the whole list, then rt_solve."""
     rays = trace(model, dirset, origins=origins)
     return solve(model, dirset, rays, chi, eta, freq_len, freq_dx, I_bc, origins=origins, **kw)
 
 
+def compute_J_workspace(dirset: DirSet, n_origins: int, F: int, precision: int = RT_F32,
+                        schedule: int = SCHED_SPATIAL, mean_entries: float = 0.0) -> int:
+    """Bytes with which rt_compute_J takes every origin in one chunk, for rays of mean_entries entries."""
+    o = _opts(precision, schedule)
+    b = _sz()
+    _check(load().rt_compute_J_workspace(dirset._h, n_origins, F, C.byref(o), float(mean_entries), C.byref(b)))
+    return int(b.value)
+
+
+def compute_J(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, origins=None, n_origins=None,
+              J=None, u=None, ws=None, ws_bytes: int = None, precision: int = RT_F32,
+              schedule: int = SCHED_SPATIAL, want_u: bool = False, stream=None, **kw):
+    """J [n_o][F] by rt_compute_J: the whole path in one library call, the origins chunked to fit the
+    workspace (ws: a device uint8 tensor; default sized for one chunk at 64 entries per ray, or
+    ws_bytes).  want_u also returns u [n_o][R][F]."""
+    torch = _torch()
+    L = load()
+    dt = torch.float64 if precision == RT_F64 else torch.float32
+    chi, eta = _dev(chi, dt), _dev(eta, dt)
+    I_bc = _dev(I_bc, torch.float64)
+    if origins is not None:
+        origins = _dev(origins, torch.int32)
+        n_origins = origins.numel()
+    elif n_origins is None:
+        n_origins = model.P
+    F = int(sum(freq_len))
+    R = dirset.R
+    g, keep = _grid(freq_len, freq_dx)
+    o = _opts(precision, schedule, **kw)
+    if ws is None:
+        if ws_bytes is None:
+            b = _sz()
+            _check(L.rt_compute_J_workspace(dirset._h, n_origins, F, C.byref(o), 0.0, C.byref(b)))
+            ws_bytes = b.value
+        ws = torch.empty(max(1, int(ws_bytes)), dtype=torch.uint8, device=chi.device)
+    if J is None:
+        J = torch.empty((n_origins, F), dtype=dt, device=chi.device)
+    if want_u and u is None:
+        u = torch.empty((n_origins, R, F), dtype=dt, device=chi.device)
+    _check(L.rt_compute_J(model._h, dirset._h, _ptr(origins), n_origins, _ptr(chi), _ptr(eta), precision,
+                          chi.shape[1], C.byref(g), _ptr(I_bc), _ptr(J), _ptr(u), C.byref(o), _ptr(ws), ws.numel(),
+                          _stream(stream)))
+    del keep
+    return (J, u) if want_u else J
+
+
+def compute_J_batched(models, dirset: DirSet, chis, etas, freq_len, freq_dx, I_bc, Js=None,
+                      precision: int = RT_F32, schedule: int = SCHED_BINNED, stream=None, **kw):
+    """rt_compute_J_batched: every model's J [P_k][F] from one graph over their disjoint union."""
+    torch = _torch()
+    dt = torch.float64 if precision == RT_F64 else torch.float32
+    F = int(sum(freq_len))
+    n = len(models)
+    if Js is None:
+        Js = [torch.empty((m.P, F), dtype=dt, device=m.pos.device) for m in models]
+    chis = [_dev(c, dt) for c in chis]
+    etas = [_dev(e, dt) for e in etas]
+    g, keep = _grid(freq_len, freq_dx)
+    o = _opts(precision, schedule, **kw)
+    arr = lambda xs: (_vp * n)(*[x for x in xs])  # noqa: E731
+    lds = (_i64 * n)(*[c.shape[1] for c in chis])
+    _check(load().rt_compute_J_batched(n, arr([m._h.value for m in models]), dirset._h,
+                                       arr([c.data_ptr() for c in chis]), arr([e.data_ptr() for e in etas]),
+                                       precision, lds, C.byref(g), _ptr(_dev(I_bc, torch.float64)),
+                                       arr([J.data_ptr() for J in Js]), C.byref(o), _stream(stream)))
+    del keep
+    return Js
+
+
+class Batch:
+    """Many models in one launch (rt_batch): a disjoint union built on the device, traced and solved by
+    one plan, replayed as one HIP graph with the table gather and the J scatter."""
+
+    def __init__(self, models, dirset: DirSet, chis, etas, freq_len, freq_dx, I_bc, Js, precision: int = RT_F32,
+                 schedule: int = SCHED_BINNED, stream=None, **kw):
+        torch = _torch()
+        dt = torch.float64 if precision == RT_F64 else torch.float32
+        n = len(models)
+        self.models, self.dirset = list(models), dirset
+        self.chis = [_dev(c, dt) for c in chis]
+        self.etas = [_dev(e, dt) for e in etas]
+        self.Js = [_dev(J, dt) for J in Js]
+        self.I_bc = _dev(I_bc, torch.float64)
+        g, self._keep = _grid(freq_len, freq_dx)
+        o = _opts(precision, schedule, **kw)
+        arr = lambda xs: (_vp * n)(*[x for x in xs])  # noqa: E731
+        lds = (_i64 * n)(*[c.shape[1] for c in self.chis])
+        h = _vp()
+        _check(load().rt_batch_create(n, arr([m._h.value for m in models]), dirset._h,
+                                      arr([c.data_ptr() for c in self.chis]), arr([e.data_ptr() for e in self.etas]),
+                                      precision, lds, C.byref(g), _ptr(self.I_bc),
+                                      arr([J.data_ptr() for J in self.Js]), C.byref(o), _stream(stream), C.byref(h)))
+        self._h = h
+        p = _vp()
+        _check(load().rt_batch_plan(self._h, C.byref(p)))
+        self._plan = p
+
+    def union(self):
+        P, E = _i64(), _i64()
+        _check(load().rt_batch_union(self._h, C.byref(P), C.byref(E)))
+        return P.value, E.value
+
+    def run(self, use_graph: bool = True, stream=None):
+        _check(load().rt_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    def profile(self, n_runs: int, stream=None) -> dict:
+        """Stage times (ms) of the inner plan over the union (rt_plan_profile)."""
+        out = np.zeros(6)
+        _check(load().rt_plan_profile(self._plan, n_runs, out.ctypes.data, _stream(stream)))
+        return dict(zip(Plan.STAGES, out.tolist()))
+
+    def info(self):
+        tot = _i64()
+        off, ids, Z = _vp(), _vp(), _vp()
+        _check(load().rt_plan_info(self._plan, C.byref(tot), C.byref(off), C.byref(ids), C.byref(Z)))
+        return dict(total=tot.value)
+
+    def autotune(self, n_runs: int = 2, verbose: bool = False, stream=None):
+        """Tune the inner plan in place (rt_autotune_plan); returns (options dict, ms per step)."""
+        best = SolveOptsC()
+        ms = _dbl()
+        _check(load().rt_autotune_plan(self._plan, n_runs, 1 if verbose else 0, _stream(stream), C.byref(best),
+                                       C.byref(ms)))
+        return opts_dict(best), ms.value
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None):
+            _lib.rt_batch_destroy(self._h)
+            self._h = None
+
+
 def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None, n_origins=None,
-             precision: int = RT_F32, dtau_fp64_below: float = 1e-4, n_runs: int = 2, cache_path: str = None,
+             precision: int = RT_F32, n_runs: int = 2, cache_path: str = None,
              verbose: bool = False, dtau_max: float = 0.0, dv_max: float = 0.0, scheme: int = SCHEME_FEAUTRIER2,
              stream=None):
     """Fastest plan options for this workload (see rt_autotune); returns (options dict, ms per step)."""
@@ -387,7 +545,7 @@ def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J,
     elif n_origins is None:
         n_origins = model.P
     g, keep = _grid(freq_len, freq_dx)
-    base = _opts(precision, SCHED_SPATIAL, dtau_fp64_below, 0, 0, dtau_max=dtau_max, dv_max=dv_max, scheme=scheme)
+    base = _opts(precision, SCHED_SPATIAL, dtau_max=dtau_max, dv_max=dv_max, scheme=scheme)
     best = SolveOptsC()
     ms = _dbl()
     _check(load().rt_autotune(model._h, dirset._h, _ptr(origins), n_origins, _ptr(chi), _ptr(eta), precision,
@@ -395,9 +553,7 @@ def autotune(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J,
                               None if cache_path is None else cache_path.encode(), 1 if verbose else 0,
                               _stream(stream), C.byref(best), C.byref(ms)))
     del keep
-    opts = dict(schedule=best.schedule, group=best.group, trace_lanes=best.trace_lanes,
-                waves_per_cu=best.waves_per_cu, n_bins=best.n_bins)
-    return opts, ms.value
+    return opts_dict(best), ms.value
 
 
 class Plan:
@@ -405,10 +561,10 @@ class Plan:
 
     def __init__(self, model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, J, origins=None,
                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT,
-                 dtau_fp64_below: float = 1e-4, waves_per_cu: int = 0, n_bins: int = 0,
+                 waves_per_cu: int = 0, n_bins: int = 0,
                  padded_trace_budget: int = 0, group: int = 0, trace_lanes: int = 0, walk: int = WALK_EXACT,
                  dtau_max: float = 0.0, max_substeps: int = 0, dv_max: float = 0.0,
-                 scheme: int = SCHEME_FEAUTRIER2, stream=None):
+                 scheme: int = SCHEME_FEAUTRIER2, bins_per_octave: int = 0, stream=None):
         torch = _torch()
         dt = torch.float64 if precision == RT_F64 else torch.float32
         self.chi, self.eta, self.J = _dev(chi, dt), _dev(eta, dt), _dev(J, dt)
@@ -421,8 +577,8 @@ class Plan:
         self.origins, self.n_origins = origins, n_origins
         self.model, self.dirset = model, dirset
         g, self._keep = _grid(freq_len, freq_dx)
-        o = _opts(precision, schedule, dtau_fp64_below, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes,
-                  walk, dtau_max, max_substeps, dv_max, scheme)
+        o = _opts(precision, schedule, waves_per_cu, n_bins, padded_trace_budget, group, trace_lanes,
+                  walk, dtau_max, max_substeps, dv_max, scheme, bins_per_octave)
         h = _vp()
         _check(load().rt_plan_create(model._h, dirset._h, _ptr(origins), n_origins, _ptr(self.chi),
                                      _ptr(self.eta), precision, self.chi.shape[1], C.byref(g), _ptr(self.I_bc),
@@ -430,9 +586,9 @@ class Plan:
         self._h = h
 
     def retune(self, schedule: int = SCHED_SPATIAL, group: int = 0, trace_lanes: int = 0, waves_per_cu: int = 0,
-               n_bins: int = 0, stream=None):
+               n_bins: int = 0, bins_per_octave: int = 0, stream=None):
         """Re-capture the plan's graph with other scheduling options."""
-        o = _opts(RT_F32, schedule, 1e-4, waves_per_cu, n_bins, 0, group, trace_lanes)
+        o = _opts(RT_F32, schedule, waves_per_cu, n_bins, 0, group, trace_lanes, bins_per_octave=bins_per_octave)
         _check(load().rt_plan_retune(self._h, C.byref(o), _stream(stream)))
 
     def run(self, use_graph: bool = True, stream=None):
@@ -558,6 +714,13 @@ class MLP:
     def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, wd: float = 0.0,
                   stream=None):
         _check(load().rt_mlp_adam_step(self._h, lr, b1, b2, eps, wd, _stream(stream)))
+
+    def set_input_norm(self, mean, inv_std):
+        """The inputs' standardisation (host arrays of 16), kept by the handle for closure_J."""
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(inv_std, np.float32)
+        assert m.size == MLP_D_IN and s.size == MLP_D_IN
+        _check(load().rt_mlp_set_input_norm(self._h, m.ctypes.data, s.ctypes.data))
 
     def __del__(self):
         if _lib is not None and getattr(self, "_h", None):
@@ -689,3 +852,35 @@ def healpix_vec2pix(nside: int, dirs) -> np.ndarray:
     out = np.empty(len(d), np.int64)
     _check(load().rt_healpix_vec2pix(int(nside), d.ctypes.data, len(d), out.ctypes.data))
     return out
+
+
+def closure_J_ws(model: Model, coarse: DirSet, F: int, solve_bytes: int):
+    """A workspace for rt_closure_J (device uint8 tensor) with solve_bytes left for its solves."""
+    torch = _torch()
+    b = _sz()
+    _check(load().rt_closure_J_workspace(model._h, coarse._h, F, int(solve_bytes), C.byref(b)))
+    return torch.empty(max(1, b.value), dtype=torch.uint8, device=model.pos.device)
+
+
+def closure_J(model: Model, coarse: DirSet, fine: DirSet, chi, eta, freq_len, freq_dx, freq_x0, I_bc, mlp: MLP,
+              log_bound: float, solve_bytes: int, J=None, flagged=None, schedule: int = SCHED_SPATIAL, ws=None,
+              stream=None):
+    """rt_closure_J: the learned closure of every point in one library call; returns (J, flagged, n_flagged)."""
+    torch = _torch()
+    chi, eta = _dev(chi, torch.float32), _dev(eta, torch.float32)
+    F = int(sum(freq_len))
+    L = load()
+    if ws is None:
+        ws = closure_J_ws(model, coarse, F, solve_bytes)
+    if J is None:
+        J = torch.empty((model.P, F), dtype=torch.float32, device=chi.device)
+    if flagged is None:
+        flagged = torch.empty(model.P, dtype=torch.int32, device=chi.device)
+    g, keep = _grid(freq_len, freq_dx, freq_x0)
+    o = _opts(RT_F32, schedule)
+    nf = _i64()
+    _check(L.rt_closure_J(model._h, coarse._h, fine._h, _ptr(chi), _ptr(eta), chi.shape[1], C.byref(g),
+                          _ptr(_dev(I_bc, torch.float64)), mlp._h, float(log_bound), _ptr(J), _ptr(flagged),
+                          C.byref(nf), C.byref(o), _ptr(ws), ws.numel(), _stream(stream)))
+    del keep, ws
+    return J, flagged, int(nf.value)

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtmi.so")
 ARCH = os.environ.get("RT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["healpix.cpp", "trace.hip", "solve.hip", "dirset.hip", "api.hip", "closure.hip", "mesh.hip"]
+SOURCES = ["healpix.cpp", "trace.hip", "solve.hip", "dirset.hip", "api.hip", "compute.hip", "closure.hip", "mesh.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

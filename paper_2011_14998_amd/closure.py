@@ -1,9 +1,10 @@
 """Learned closure driver: coarse solve, features, network, fallback.
 
-Every arithmetic step runs in the library's kernels (rt_plan_* for the
-solves, rt_closure_* and rt_mlp_* for features, network and assembly); this
-module only sequences the calls, owns the device buffers and draws the
-minibatch indices.
+Every arithmetic step runs in the library's kernels: the solves are one
+rt_compute_J call each, inference with its fallback is one rt_closure_J call,
+and training steps call rt_mlp_* (forward, loss, backward, Adam).  This module
+owns the device buffers, draws the minibatch indices and builds the training
+set and its standardisation.
 
 Closure (an addition to the method, which computes J from the direction set
 alone): J at nside = 1 (6 pairs, Section 2.1.3) plus local optical properties
@@ -45,94 +46,57 @@ class DeviceModel:
         self.eta = torch.as_tensor(np.ascontiguousarray(eta, np.float32), device=dev)
         self.freq_len = list(freq_len)
         self.freq_dx = list(freq_dx)
+        self.freq_x0 = None
         self.x = torch.as_tensor(np.ascontiguousarray(freq_x, np.float32), device=dev)
         self.I_bc = torch.as_tensor(np.ascontiguousarray(I_bc, np.float64), device=dev)
-        self.mean_len = None  # mean ray length (entries), learnt from the first solve
 
     @classmethod
     def from_synth(cls, m):
-        return cls(m.pos, m.nbr_off, m.nbr_idx, m.vel, m.chi, m.eta, m.freq.len, m.freq.dx, m.freq.x(), m.I_bc,
-                   name=f"{m.name}{m.meta.get('seed', '')}")
+        dm = cls(m.pos, m.nbr_off, m.nbr_idx, m.vel, m.chi, m.eta, m.freq.len, m.freq.dx, m.freq.x(), m.I_bc,
+                 name=f"{m.name}{m.meta.get('seed', '')}")
+        dm.freq_x0 = list(m.freq.x0)
+        return dm
 
 
 @dataclass
 class SolveResult:
     J: object
-    ms: float                  # summed HIP-event time of the plan replays
-    build_s: float             # wall time of plan creation (count walk, allocation, capture)
-    entries: int               # ray-list entries walked
+    ms: float                  # HIP-event time of the rt_compute_J call
     u: object = None           # per-pair mean intensities [n][R][F] when asked for
 
 
-def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, max_entries: float = 1.0e9, J=None,
-            schedule: int = rt.SCHED_SPATIAL, keep_u: bool = False, spatial_chunks: bool = True,
-            padded_budget: int = 0, verbose: bool = False) -> SolveResult:
-    """J [n][F] (f32) for the listed origins (device int32, or all points) by plans over origin chunks
-    of about max_entries ray-list entries each; keep_u also returns the per-pair u.  With
-    spatial_chunks the list is cut along the Morton order of the origins' positions, so each chunk
-    walks one region of the model, and the rows are scattered back to list order."""
+# Room for ray lists (and the per-chunk parts) that solve_J gives rt_compute_J; the library
+# cuts the origins into chunks that fit it.
+SOLVE_WS_BYTES = 24 << 30
+
+
+def solve_J(dm: DeviceModel, dirset: "rt.DirSet", origins=None, J=None, schedule: int = rt.SCHED_SPATIAL,
+            keep_u: bool = False, ws_bytes: int = SOLVE_WS_BYTES, verbose: bool = False) -> SolveResult:
+    """J [n][F] (f32) for the listed origins (device int32, or all points) by one rt_compute_J call,
+    which takes the origins in Morton-ordered chunks that fit ws_bytes; keep_u also returns the
+    per-pair u."""
     torch = _torch()
     n = dm.P if origins is None else int(origins.numel())
     if J is None:
         J = torch.empty((max(n, 1), dm.F), dtype=torch.float32, device="cuda")[:n]
     U = torch.empty((max(n, 1), dirset.R, dm.F), dtype=torch.float32, device="cuda")[:n] if keep_u else None
     if n == 0:
-        return SolveResult(J, 0.0, 0.0, 0, U)
-    all_ids = origins if origins is not None else torch.arange(n, dtype=torch.int32, device="cuda")
-    perm = None
-    if spatial_chunks and n > 4096:
-        order = rt.spatial_order(dm.model, origins=all_ids)
-        ids_host = all_ids.cpu().numpy()[order]
-        all_ids = torch.as_tensor(ids_host, device="cuda")
-        perm = torch.as_tensor(order, device="cuda")
-        Jw = torch.empty_like(J)
-        Uw = torch.empty_like(U) if keep_u else None
-    else:
-        Jw, Uw = J, U
-    per_origin = 2 * dirset.R * (dm.mean_len or 64.0)
-    chunk = min(n, 2048) if dm.mean_len is None else max(1, int(max_entries // per_origin))
-    ms, build_s, entries, c0 = 0.0, 0.0, 0, 0
-    first_estimate = dm.mean_len is None
-    while c0 < n:
-        c1 = min(n, c0 + chunk)
-        t0 = time.time()
-        plan = rt.Plan(dm.model, dirset, dm.chi, dm.eta, dm.freq_len, dm.freq_dx, dm.I_bc, Jw[c0:c1],
-                       origins=all_ids[c0:c1], precision=rt.RT_F32, schedule=schedule,
-                       padded_trace_budget=padded_budget)
-        torch.cuda.synchronize()
-        build_s += time.time() - t0
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        plan.run()
-        e1.record()
-        e1.synchronize()
-        ms += e0.elapsed_time(e1)
-        if keep_u:
-            plan.copy_u(Uw[c0:c1])
-        tot = plan.info()["total"]
-        entries += tot
-        if first_estimate:  # running mean ray length over the chunks walked so far
-            dm.mean_len = max(1.0, entries / (c1 * 2 * dirset.R))
-            per_origin = 2 * dirset.R * dm.mean_len
-        del plan
-        if verbose:
-            print(f"  [{dm.name}] nside-{int(round(math.sqrt(dirset.R / 6)))} solve {c1}/{n} origins, "
-                  f"{ms:.0f} ms", flush=True)
-        c0 = c1
-        chunk = max(1, int(max_entries // per_origin))
-    if perm is not None:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rt.closure_merge(Jw, perm, n, J)
-        if keep_u:
-            rt.closure_merge(Uw.view(n, -1), perm, n, U.view(n, -1))
-        e1.record()
-        e1.synchronize()
-        ms += e0.elapsed_time(e1)
-        del Jw, Uw
+        return SolveResult(J, 0.0, U)
+    need = rt.compute_J_workspace(dirset, n, dm.F, schedule=schedule)
+    ws = torch.empty(min(need, ws_bytes), dtype=torch.uint8, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rt.compute_J(dm.model, dirset, dm.chi, dm.eta, dm.freq_len, dm.freq_dx, dm.I_bc, origins=origins,
+                 n_origins=n, J=J, u=U, ws=ws, schedule=schedule, want_u=keep_u)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del ws
     rt.sync_status()
-    rt.release_cached_memory()  # the chunks' plans shared their buffers; free them for other allocators
-    return SolveResult(J, ms, build_s, entries, U)
+    if verbose:
+        print(f"  [{dm.name}] nside-{int(round(math.sqrt(dirset.R / 6)))} solve of {n} origins: {ms:.0f} ms",
+              flush=True)
+    return SolveResult(J, ms, U)
 
 
 @dataclass
@@ -190,6 +154,7 @@ def train(X, T, norm: Normalizer, steps: int = 20000, batch: int = 8192, lr: flo
                 print(f"  train step {step + 1}/{steps}: mean NLL {avg:.4f}, lr {a:.2e}, "
                       f"{time.time() - t0:.1f} s", flush=True)
     torch.cuda.synchronize()
+    net.set_input_norm(norm.mean, norm.inv_std)
     return ClosureNet(net, norm, hist)
 
 
@@ -197,45 +162,25 @@ def train(X, T, norm: Normalizer, steps: int = 20000, batch: int = 8192, lr: flo
 class ClosureResult:
     J: object
     n_flagged: int
-    coarse_ms: float
-    infer_ms: float
-    fallback_ms: float
-    fallback_build_s: float
-    flagged: object = None     # device int32, the first n_flagged entries are the flagged positions
-
-    @property
-    def total_ms(self):
-        return self.coarse_ms + self.infer_ms + self.fallback_ms + 1e3 * self.fallback_build_s
+    total_ms: float            # HIP-event time of the rt_closure_J call (coarse solve to merge)
+    flagged: object = None     # device int32, the first n_flagged entries are the flagged points
 
 
-def infer(net: ClosureNet, dm: DeviceModel, coarse: SolveResult, fine_set: "rt.DirSet", log_bound: float,
-          fallback: bool = True, verbose: bool = False) -> ClosureResult:
-    """Closure J for every point of dm from its coarse solve: features, network, flags, fallback, merge."""
+def infer(net: ClosureNet, dm: DeviceModel, coarse_set: "rt.DirSet", fine_set: "rt.DirSet", log_bound: float,
+          ws_bytes: int = SOLVE_WS_BYTES) -> ClosureResult:
+    """Closure J for every point of dm by one rt_closure_J call: coarse solve, features, network,
+    flags, the fine solve of the flagged points and the merge all run in the library."""
     torch = _torch()
-    J1, coarse_ms = coarse.J, coarse.ms
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    solve_bytes = min(rt.compute_J_workspace(fine_set, dm.P, dm.F), ws_bytes)
+    ws = rt.closure_J_ws(dm.model, coarse_set, dm.F, solve_bytes)
     e0.record()
-    feat = features(dm, J1, coarse.u)
-    X = rt.closure_normalize(feat, net.norm.mean, net.norm.inv_std)
-    del feat
-    Y = net.mlp.forward(X)
-    J, flagged, nf = rt.closure_apply(J1, Y, log_bound)
+    J, flagged, n_flag = rt.closure_J(dm.model, coarse_set, fine_set, dm.chi, dm.eta, dm.freq_len, dm.freq_dx,
+                                      dm.freq_x0, dm.I_bc, net.mlp, log_bound, solve_bytes, ws=ws)
     e1.record()
-    n_flag = int(nf.item())  # synchronises
-    infer_ms = e0.elapsed_time(e1)
-    del X, Y
-    fb_ms, fb_build = 0.0, 0.0
-    if fallback and n_flag > 0:
-        res = solve_J(dm, fine_set, origins=flagged[:n_flag], verbose=verbose)
-        e0.record()
-        rt.closure_merge(res.J, flagged, n_flag, J)
-        e1.record()
-        e1.synchronize()
-        fb_ms = res.ms + e0.elapsed_time(e1)
-        fb_build = res.build_s
-        del res
+    e1.synchronize()
     rt.sync_status()
-    return ClosureResult(J, n_flag, coarse_ms, infer_ms, fb_ms, fb_build, flagged)
+    return ClosureResult(J, n_flag, e0.elapsed_time(e1), flagged)
 
 
 def rel_errors(J, J_ref) -> np.ndarray:
@@ -308,7 +253,7 @@ def predicted_sd(net: ClosureNet, dm: DeviceModel, coarse: SolveResult) -> np.nd
     return np.exp(0.5 * s.double().cpu().numpy())
 
 
-def evaluate(net: ClosureNet, lab: Labelled, fine_set, flag_fractions=(0.0,), mid_set=None,
+def evaluate(net: ClosureNet, lab: Labelled, coarse_set, fine_set, flag_fractions=(0.0,), mid_set=None,
              verbose: bool = False) -> dict:
     """Closure against the plain nside-8 solve on one model.  For each target fallback fraction q
     the bound is the (1 - q) quantile of the predicted per-point deviation (q = 0: no fallback;
@@ -333,12 +278,10 @@ def evaluate(net: ClosureNet, lab: Labelled, fine_set, flag_fractions=(0.0,), mi
         else:
             b = float(np.quantile(sd, 1.0 - q))
         lb = math.log(b) if b > 0 else -math.inf
-        res = infer(net, dm, lab.coarse, fine_set, lb, verbose=verbose)
+        res = infer(net, dm, coarse_set, fine_set, lb)
         mask = flagged_mask(res.flagged, res.n_flagged, dm.P)
         e = error_summary(res.J, lab.fine.J, mask, F)
-        e.update(target_fraction=q, bound=b, n_flagged=res.n_flagged, coarse_ms=res.coarse_ms,
-                 infer_ms=res.infer_ms, fallback_ms=res.fallback_ms, fallback_build_s=res.fallback_build_s,
-                 total_ms=res.total_ms, replay_ms=res.coarse_ms + res.infer_ms + res.fallback_ms,
+        e.update(target_fraction=q, bound=b, n_flagged=res.n_flagged, total_ms=res.total_ms,
                  speedup_vs_plain=lab.fine.ms / res.total_ms if res.total_ms > 0 else None)
         runs.append(e)
         if verbose:

@@ -439,13 +439,14 @@ extern "C" rt_status rt_trace_write(const rt_model* m, const rt_dirset* set_, co
 
 // ------------------------------------------------------------------ solve
 
-static rt_solve_opts default_opts() {
+rt_solve_opts rt::default_solve_opts() {
     rt_solve_opts o;
+    std::memset(&o, 0, sizeof(o));
     o.precision = RT_F32;
     o.schedule = RT_SCHED_DIRECT;
-    o.dtau_fp64_below = 1e-4;
     o.waves_per_cu = 0;
     o.n_bins = 0;
+    o.bins_per_octave = 0;
     o.group = 0;
     o.trace_lanes = 0;
     o.padded_trace_budget = 0;
@@ -457,7 +458,11 @@ static rt_solve_opts default_opts() {
     return o;
 }
 
-static int32_t opts_bins(const rt_solve_opts& o) { return o.n_bins > 0 ? std::min(o.n_bins, 128) : 64; }
+static rt_solve_opts default_opts() { return default_solve_opts(); }
+
+int32_t rt::opts_bins(const rt_solve_opts& o) { return o.n_bins > 0 ? std::min(o.n_bins, 128) : 64; }
+int32_t rt::opts_bins_per_octave(const rt_solve_opts& o) { return o.bins_per_octave > 0 ? o.bins_per_octave : 4; }
+static bool valid_bins_per_octave(int32_t v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; }
 
 static size_t solve_ws_bytes(int64_t n_origins, int64_t R, int64_t F, const rt_solve_opts& o, bool need_u) {
     const size_t es = o.precision == RT_F64 ? 8 : 4;
@@ -476,11 +481,11 @@ extern "C" rt_status rt_solve_workspace(const rt_dirset* set, int64_t n_origins,
     return RT_OK;
 }
 
-static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
-                             const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
-                             const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid, const double* I_bc,
-                             void* J, const rt_solve_opts& o, SolveLaunch& a) {
-    if (!m || !set || !ray_off || !chi || !eta || !grid || !I_bc || (!J && n_origins > 0))
+rt_status rt::fill_solve_launch(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                                const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
+                                const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                                const double* I_bc, void* J, const rt_solve_opts& o, SolveLaunch& a) {
+    if (!m || !set || !chi || !eta || !grid || !I_bc || (!J && n_origins > 0))
         return fail(RT_ERR_ARG, "solve: NULL argument");
     if (o.precision != RT_F32 && o.precision != RT_F64) return fail(RT_ERR_ARG, "solve: precision must be RT_F32 or RT_F64");
     if (dtype != o.precision) return fail(RT_ERR_ARG, "solve: table dtype must match the precision");
@@ -520,13 +525,16 @@ static rt_status fill_launch(const rt_model* m, rt_dirset* set, const int32_t* o
     a.P = m->P;
     a.I_bc = I_bc;
     a.J = J;
-    if (!(o.dtau_max >= 0.0) || !(o.dv_max >= 0.0) || o.max_substeps < 0 || !(o.dtau_fp64_below >= 0.0))
-        return fail(RT_ERR_ARG, "solve: dtau_max, dv_max, max_substeps and dtau_fp64_below must be >= 0");
+    if (!(o.dtau_max >= 0.0) || !(o.dv_max >= 0.0) || o.max_substeps < 0)
+        return fail(RT_ERR_ARG, "solve: dtau_max, dv_max and max_substeps must be >= 0");
+    if (!valid_bins_per_octave(o.bins_per_octave))
+        return fail(RT_ERR_ARG, "solve: bins_per_octave must be 1, 2, 4 or 8 (0 = 4)");
     a.dtau_max_rcp = o.dtau_max > 0.0 ? 1.0 / o.dtau_max : 0.0;
     a.dv_max_rcp = o.dv_max > 0.0 && m->vel ? 1.0 / o.dv_max : 0.0;
     a.max_sub = o.max_substeps > 0 ? o.max_substeps : 1024;
     a.schedule = o.schedule;
     a.n_bins = opts_bins(o);
+    a.bins_per_octave = opts_bins_per_octave(o);
     int wpc = o.waves_per_cu > 0 ? std::min(o.waves_per_cu, MAX_WAVES_PER_CU) : 32;
     a.grid_waves = num_cus() * wpc;
     a.n_xcd = num_xcds();
@@ -591,9 +599,10 @@ extern "C" rt_status rt_solve(const rt_model* m, const rt_dirset* set_, const in
     rt_solve_opts o = opts ? *opts : default_opts();
     if (o.schedule != RT_SCHED_DIRECT && o.schedule != RT_SCHED_BINNED)
         return fail(RT_ERR_ARG, "rt_solve: schedule must be RT_SCHED_DIRECT or RT_SCHED_BINNED (spatial: plans only)");
+    if (!ray_off) return fail(RT_ERR_ARG, "rt_solve: NULL ray_off");
     SolveLaunch a;
-    rt_status st = fill_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid, I_bc, J,
-                               o, a);
+    rt_status st = fill_solve_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid,
+                                     I_bc, J, o, a);
     if (st) return st;
     if (n_origins * a.R * ((a.F + 63) / 64) > MAX_SOLVE_ITEMS)
         return fail(RT_ERR_UNSUPPORTED, "rt_solve: too many work items");
@@ -652,6 +661,7 @@ struct rt_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool exact = false;  // RT_WALK_EXACT: walk straight into the creation-time slots
+    int64_t version = 0; // incremented whenever the graph is re-captured
     // bytes of the cached large buffers (ids, Z, padded slots, u)
     size_t ids_bytes = 0, Z_bytes = 0, pids_bytes = 0, pZ_bytes = 0, u_bytes = 0;
 };
@@ -723,9 +733,10 @@ static void plan_free(rt_plan* p) {
 }
 
 // Origin positions in the order of the Morton (Z-order) code of their points:
-// 21 bits per axis over the bounding box of the origins.
-static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
-                               std::vector<int32_t>& order) {
+// 21 bits per axis over the bounding box of the origins (of each segment's
+// origins, when segments are given; segments keep their order).
+hipError_t rt::morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
+                            std::vector<int32_t>& order, const int64_t* seg, int n_seg) {
     std::lock_guard<std::mutex> lk(m->host_mu);
     std::vector<double>& pos = m->host_pos;
     std::vector<int32_t> org;
@@ -749,12 +760,6 @@ static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_
         int64_t o = origins ? (int64_t)org[(size_t)k] : k;
         return (o < 0 || o >= m->P) ? 0 : o;
     };
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t k = 0; k < n_o; ++k)
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = std::min(lo[c], pos[(size_t)(3 * pt(k) + c)]);
-            hi[c] = std::max(hi[c], pos[(size_t)(3 * pt(k) + c)]);
-        }
     auto spread = [](uint64_t v) {  // 21 bits -> every third bit
         v &= 0x1fffff;
         v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -764,19 +769,36 @@ static hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_
         v = (v | v << 2) & 0x1249249249249249ULL;
         return v;
     };
-    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n_o);
-    for (int64_t k = 0; k < n_o; ++k) {
-        uint64_t code = 0;
-        for (int c = 0; c < 3; ++c) {
-            double w = hi[c] > lo[c] ? (pos[(size_t)(3 * pt(k) + c)] - lo[c]) / (hi[c] - lo[c]) : 0.0;
-            uint64_t qv = (uint64_t)std::min(std::max(w * 2097151.0, 0.0), 2097151.0);
-            code |= spread(qv) << c;
-        }
-        key[(size_t)k] = {code, (int32_t)k};
-    }
-    std::sort(key.begin(), key.end());
     order.resize((size_t)n_o);
-    for (int64_t k = 0; k < n_o; ++k) order[(size_t)k] = key[(size_t)k].second;
+    for (int64_t k = 0; k < n_o; ++k) order[(size_t)k] = (int32_t)k;
+    const int64_t whole[2] = {0, n_o};
+    if (n_seg <= 0 || !seg) {
+        seg = whole;
+        n_seg = 1;
+    }
+    std::vector<std::pair<uint64_t, int32_t>> key;
+    for (int g = 0; g < n_seg; ++g) {
+        const int64_t k0 = std::max<int64_t>(0, seg[g]), k1 = std::min<int64_t>(n_o, seg[g + 1]);
+        if (k1 <= k0) continue;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t k = k0; k < k1; ++k)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], pos[(size_t)(3 * pt(k) + c)]);
+                hi[c] = std::max(hi[c], pos[(size_t)(3 * pt(k) + c)]);
+            }
+        key.resize((size_t)(k1 - k0));
+        for (int64_t k = k0; k < k1; ++k) {
+            uint64_t code = 0;
+            for (int c = 0; c < 3; ++c) {
+                double w = hi[c] > lo[c] ? (pos[(size_t)(3 * pt(k) + c)] - lo[c]) / (hi[c] - lo[c]) : 0.0;
+                uint64_t qv = (uint64_t)std::min(std::max(w * 2097151.0, 0.0), 2097151.0);
+                code |= spread(qv) << c;
+            }
+            key[(size_t)(k - k0)] = {code, (int32_t)k};
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t k = k0; k < k1; ++k) order[(size_t)k] = key[(size_t)(k - k0)].second;
+    }
     return hipSuccess;
 }
 
@@ -799,6 +821,7 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "plan: group must be 4 or 8");
     if (o.trace_lanes != 0 && o.trace_lanes != 4 && o.trace_lanes != 8 && o.trace_lanes != 16)
         return fail(RT_ERR_ARG, "plan: trace_lanes must be 4, 8 or 16");
+    if (!valid_bins_per_octave(o.bins_per_octave)) return fail(RT_ERR_ARG, "plan: bins_per_octave must be 1, 2, 4 or 8");
     hipError_t e = hipSuccess;
     const rt_solve_opts prev = p->o;
     p->o.schedule = o.schedule;
@@ -806,11 +829,13 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     p->o.trace_lanes = o.trace_lanes;
     p->o.waves_per_cu = o.waves_per_cu;
     p->o.n_bins = o.n_bins;
+    p->o.bins_per_octave = o.bins_per_octave;
     SolveLaunch a = p->base;
     a.u = p->u_buf;
     a.schedule = o.schedule == RT_SCHED_BINNED ? RT_SCHED_BINNED : RT_SCHED_DIRECT;
     a.group = o.group ? o.group : 8;
     a.n_bins = opts_bins(o);
+    a.bins_per_octave = opts_bins_per_octave(o);
     a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? std::min(o.waves_per_cu, MAX_WAVES_PER_CU) : 32);
     a.items = nullptr;
     a.order = nullptr;
@@ -869,8 +894,12 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (cap) (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_fail(e, "plan: graph capture");
+    ++p->version;
     return RT_OK;
 }
+
+hipError_t rt::plan_enqueue_step(rt_plan* p, hipStream_t s) { return plan_enqueue(p, s); }
+int64_t rt::plan_version(const rt_plan* p) { return p->version; }
 
 extern "C" rt_status rt_plan_retune(rt_plan* p, const rt_solve_opts* opts, void* stream) {
     if (!p || !opts) return fail(RT_ERR_ARG, "rt_plan_retune: NULL argument");
@@ -883,9 +912,16 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
                                     const void* chi, const void* eta, int32_t dtype, int64_t ld,
                                     const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* opts,
                                     void* stream, rt_plan** out) {
+    return plan_create_ordered(m, const_cast<rt_dirset*>(set_), origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J,
+                               opts, (hipStream_t)stream, nullptr, out);
+}
+
+rt_status rt::plan_create_ordered(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                                  const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                                  const double* I_bc, void* J, const rt_solve_opts* opts, hipStream_t stream,
+                                  const std::vector<int32_t>* given_order, rt_plan** out) {
     if (!out) return fail(RT_ERR_ARG, "rt_plan_create: NULL output");
     *out = nullptr;
-    rt_dirset* set = const_cast<rt_dirset*>(set_);
     rt_status st = check_trace_args(m, set, n_origins, "rt_plan_create");
     if (st) return st;
     if (opts && (opts->schedule < RT_SCHED_DIRECT || opts->schedule > RT_SCHED_SPATIAL))
@@ -906,7 +942,10 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
     // the walk's origin order (Morton), used by the count pass here and by every walk of the plan
     if (e == hipSuccess && n_origins > 0) {
         std::vector<int32_t> ord;
-        e = morton_order(m, origins, n_origins, s, ord);
+        if (given_order && (int64_t)given_order->size() == n_origins)
+            ord = *given_order;
+        else
+            e = morton_order(m, origins, n_origins, s, ord);
         if (e == hipSuccess) e = hipMalloc((void**)&p->order, sizeof(int32_t) * ord.size());
         if (e == hipSuccess) e = hipMemcpy(p->order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice);
     }
@@ -946,7 +985,7 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
         plan_free(p);
         return st;
     }
-    st = fill_launch(m, set, origins, n_origins, p->ray_off, p->ids, p->Z, chi, eta, dtype, ld, grid, I_bc, J, p->o,
+    st = fill_solve_launch(m, set, origins, n_origins, p->ray_off, p->ids, p->Z, chi, eta, dtype, ld, grid, I_bc, J, p->o,
                      p->a);
     if (!st && solve_items(p->a) > MAX_SOLVE_ITEMS) st = fail(RT_ERR_UNSUPPORTED, "rt_plan_create: too many work items");
     if (st) {
@@ -1081,62 +1120,32 @@ static std::string tune_signature(const rt_model* m, const rt_dirset* set, int64
     return buf;
 }
 
-extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
-                                 const void* chi, const void* eta, int32_t dtype, int64_t ld,
-                                 const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* base,
-                                 int32_t n_runs, const char* cache_path, int32_t verbose, void* stream,
-                                 rt_solve_opts* best, double* best_ms) {
-    if (!m || !set || !grid || !best) return fail(RT_ERR_ARG, "rt_autotune: NULL argument");
-    rt_solve_opts b0 = base ? *base : default_opts();
-    int64_t F = 0;
-    for (int i = 0; i < grid->n_blocks && grid->len; ++i) F += grid->len[i];
-    const std::string sig = tune_signature(m, set, n_origins, F, b0);
-    if (cache_path && *cache_path) {
-        FILE* f = std::fopen(cache_path, "r");
-        if (f) {
-            char key[256];
-            int sc, gr, la, wpc, nb;
-            double ms;
-            while (std::fscanf(f, "%255s %d %d %d %d %d %lf", key, &sc, &gr, &la, &wpc, &nb, &ms) == 7) {
-                if (sig == key) {
-                    *best = b0;
-                    best->schedule = sc;
-                    best->group = gr;
-                    best->trace_lanes = la;
-                    best->waves_per_cu = wpc;
-                    best->n_bins = nb;
-                    if (best_ms) *best_ms = ms;
-                    std::fclose(f);
-                    return RT_OK;
-                }
-            }
-            std::fclose(f);
-        }
-    }
+// The candidate search on a configured plan: each candidate run varies the
+// walk's lanes per ray and the sweep's schedule parameters (they act on
+// different stages, and the HIP-event stage times credit them separately).
+// Leaves the plan re-captured with the chosen options.
+static rt_status tune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, hipStream_t stream, rt_solve_opts* best,
+                           double* best_ms) {
     if (n_runs <= 0) n_runs = 2;
-    // The walk's lanes per ray and the sweep's (schedule, load group, grid) act on
-    // different stages, so each candidate run varies both and the stage times
-    // (HIP events between stages) are credited separately.
     const int lanes[3] = {8, 16, 4};
-    struct SweepCand { int sc, gr, wpc, bins; };
-    const SweepCand sw[6] = {{RT_SCHED_SPATIAL, 8, 0, 0},   {RT_SCHED_SPATIAL, 4, 0, 0},
-                             {RT_SCHED_BINNED, 8, 32, 64},  {RT_SCHED_BINNED, 8, 32, 32},
-                             {RT_SCHED_BINNED, 4, 16, 128}, {RT_SCHED_DIRECT, 4, 0, 0}};
-    rt_plan* p = nullptr;
+    struct SweepCand { int sc, gr, wpc, bins, bpo; };
+    const SweepCand sw[9] = {{RT_SCHED_SPATIAL, 8, 0, 0, 0},  {RT_SCHED_SPATIAL, 4, 0, 0, 0},
+                             {RT_SCHED_BINNED, 8, 32, 64, 4}, {RT_SCHED_BINNED, 8, 32, 32, 2},
+                             {RT_SCHED_BINNED, 4, 16, 128, 4}, {RT_SCHED_DIRECT, 4, 0, 0, 0},
+                             {RT_SCHED_BINNED, 8, 32, 128, 8}, {RT_SCHED_BINNED, 8, 64, 64, 4},
+                             {RT_SCHED_DIRECT, 8, 0, 0, 0}};
+    const rt_solve_opts b0 = p->o;
     rt_solve_opts o = b0;
-    o.schedule = RT_SCHED_SPATIAL;
-    o.group = 8;
-    o.trace_lanes = 8;
-    rt_status st = rt_plan_create(m, set, origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J, &o, stream, &p);
-    if (st) return st;
+    rt_status st = RT_OK;
     double walk_best = 1e300, sweep_best = 1e300, other = 0.0, walk_default = 0.0, sweep_default = 0.0;
     int lane_best = 8;
     SweepCand sw_best = sw[0];
-    for (int i = 0; i < 6 && !st; ++i) {
+    for (int i = 0; i < 9 && !st; ++i) {
         o.schedule = sw[i].sc;
         o.group = sw[i].gr;
         o.waves_per_cu = sw[i].wpc;
         o.n_bins = sw[i].bins;
+        o.bins_per_octave = sw[i].bpo;
         o.trace_lanes = lanes[i % 3];
         st = plan_configure(p, o);
         if (st) break;
@@ -1160,10 +1169,11 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
         other = ms[1] + ms[5];
         if (verbose)
             std::fprintf(stderr,
-                         "autotune: lanes %d schedule %d group %d waves/CU %d bins %d -> walk %.3f ms, sweep %.3f ms\n",
-                         o.trace_lanes, o.schedule, o.group, o.waves_per_cu, o.n_bins, walk, sweep);
+                         "autotune: lanes %d schedule %d group %d waves/CU %d bins %d per octave %d -> walk %.3f ms, "
+                         "sweep %.3f ms\n",
+                         o.trace_lanes, o.schedule, o.group, o.waves_per_cu, o.n_bins, opts_bins_per_octave(o), walk,
+                         sweep);
     }
-    rt_plan_destroy(p);
     if (st) return st;
     // keep a default unless a candidate beats it by 5%: choices closer than that swap from box to box
     if (!(walk_best < 0.95 * walk_default)) {
@@ -1179,14 +1189,70 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     best->group = sw_best.gr;
     best->waves_per_cu = sw_best.wpc;
     best->n_bins = sw_best.bins;
+    best->bins_per_octave = sw_best.bpo;
     best->trace_lanes = lane_best;
-    const double bms = walk_best + sweep_best + other;
+    if (best_ms) *best_ms = walk_best + sweep_best + other;
+    return plan_configure(p, *best);
+}
+
+extern "C" rt_status rt_autotune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, void* stream, rt_solve_opts* best,
+                                      double* best_ms) {
+    if (!p || !best) return fail(RT_ERR_ARG, "rt_autotune_plan: NULL argument");
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    p->stream = (hipStream_t)stream;
+    return tune_plan(p, n_runs, verbose, (hipStream_t)stream, best, best_ms);
+}
+
+extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                                 const void* chi, const void* eta, int32_t dtype, int64_t ld,
+                                 const rt_freq_grid* grid, const double* I_bc, void* J, const rt_solve_opts* base,
+                                 int32_t n_runs, const char* cache_path, int32_t verbose, void* stream,
+                                 rt_solve_opts* best, double* best_ms) {
+    if (!m || !set || !grid || !best) return fail(RT_ERR_ARG, "rt_autotune: NULL argument");
+    rt_solve_opts b0 = base ? *base : default_opts();
+    int64_t F = 0;
+    for (int i = 0; i < grid->n_blocks && grid->len; ++i) F += grid->len[i];
+    const std::string sig = tune_signature(m, set, n_origins, F, b0);
+    if (cache_path && *cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char key[256];
+            int sc, gr, la, wpc, nb, bpo;
+            double ms;
+            while (std::fscanf(f, "%255s %d %d %d %d %d %d %lf", key, &sc, &gr, &la, &wpc, &nb, &bpo, &ms) == 8) {
+                if (sig == key) {
+                    *best = b0;
+                    best->schedule = sc;
+                    best->group = gr;
+                    best->trace_lanes = la;
+                    best->waves_per_cu = wpc;
+                    best->n_bins = nb;
+                    best->bins_per_octave = bpo;
+                    if (best_ms) *best_ms = ms;
+                    std::fclose(f);
+                    return RT_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    rt_plan* p = nullptr;
+    rt_solve_opts o = b0;
+    o.schedule = RT_SCHED_SPATIAL;
+    o.group = 8;
+    o.trace_lanes = 8;
+    rt_status st = rt_plan_create(m, set, origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J, &o, stream, &p);
+    if (st) return st;
+    double bms = 0.0;
+    st = tune_plan(p, n_runs, verbose, (hipStream_t)stream, best, &bms);
+    rt_plan_destroy(p);
+    if (st) return st;
     if (best_ms) *best_ms = bms;
     if (cache_path && *cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s %d %d %d %d %d %.6f\n", sig.c_str(), best->schedule, best->group, best->trace_lanes,
-                         best->waves_per_cu, best->n_bins, bms);
+            std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", sig.c_str(), best->schedule, best->group, best->trace_lanes,
+                         best->waves_per_cu, best->n_bins, best->bins_per_octave, bms);
             std::fclose(f);
         }
     }

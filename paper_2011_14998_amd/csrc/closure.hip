@@ -20,6 +20,7 @@
 // stay in LDS between layers.  Backward: weight gradients are formed per tile
 // (H^T dZ on the matrix cores) into a per-tile partial buffer and summed by a
 // separate pass in tile order (deterministic).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <random>
@@ -590,9 +591,10 @@ __global__ void k_normalize(const float* __restrict__ feat, int64_t n, const Nor
 
 // ---------------------------------------------------------------- closure assembly
 
+// Points p0 .. p0+n_points-1 (J1, Y and J start at point p0).
 __global__ void k_closure_apply(const float* __restrict__ J1, const float* __restrict__ Y, int64_t n_points,
                                 int64_t F, float log_bound, float* __restrict__ J, int32_t* __restrict__ flagged,
-                                int32_t* __restrict__ n_flagged) {
+                                int32_t* __restrict__ n_flagged, int64_t p0) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n_points) return;
     bool fl = false;
@@ -601,7 +603,7 @@ __global__ void k_closure_apply(const float* __restrict__ J1, const float* __res
         J[i] = J1[i] * __expf(Y[2 * i]);
         fl = fl || (0.5f * Y[2 * i + 1] > log_bound);
     }
-    if (fl) flagged[atomicAdd(n_flagged, 1)] = (int32_t)p;
+    if (fl) flagged[atomicAdd(n_flagged, 1)] = (int32_t)(p0 + p);
 }
 
 __global__ void k_closure_merge(const float* __restrict__ Jf, const int32_t* __restrict__ flagged, int64_t n_flagged,
@@ -640,6 +642,8 @@ struct rt_mlp {
     uint16_t* wt = nullptr; // BF16 forward copies
     uint16_t* wb = nullptr; // BF16 backward copies
     int64_t step = 0;
+    bool has_norm = false;  // input standardisation for rt_closure_J
+    float mean[DIN] = {}, istd[DIN] = {};
 };
 
 static rt_status mlp_publish(rt_mlp* h, hipStream_t s) {
@@ -854,7 +858,7 @@ extern "C" rt_status rt_closure_apply(const float* J1, const float* Y, int64_t n
     RT_HIP(launch_fill_i32(n_flagged, 1, 0, s));
     if (n_points == 0) return RT_OK;
     hipLaunchKernelGGL(k_closure_apply, dim3(nb(n_points, 256)), dim3(256), 0, s, J1, Y,
-                       n_points, F, log_bound, J, flagged, n_flagged);
+                       n_points, F, log_bound, J, flagged, n_flagged, (int64_t)0);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
@@ -874,6 +878,135 @@ extern "C" rt_status rt_closure_targets(const float* J1, const float* J_fine, in
     if ((n > 0 && (!J1 || !J_fine || !T)) || n < 0) return fail(RT_ERR_ARG, "rt_closure_targets: bad arguments");
     if (n == 0) return RT_OK;
     hipLaunchKernelGGL(k_targets, dim3(capped_blocks(nb(n, 256))), dim3(256), 0, (hipStream_t)stream, J1, J_fine, n, T);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_set_input_norm(rt_mlp* h, const float* mean, const float* inv_std) {
+    if (!h || !mean || !inv_std) return fail(RT_ERR_ARG, "rt_mlp_set_input_norm: NULL");
+    std::memcpy(h->mean, mean, sizeof(h->mean));
+    std::memcpy(h->istd, inv_std, sizeof(h->istd));
+    h->has_norm = true;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- the closure in one call
+
+namespace {
+constexpr int64_t CLOSURE_CHUNK = 65536;  // points per inference chunk
+inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct ClosureParts {
+    size_t J1, u1, x, pts, cnt, feat, X, Y, Jf, total;
+};
+
+ClosureParts closure_parts(int64_t P, int64_t R1, int64_t F) {
+    ClosureParts c;
+    const int64_t pc = std::min<int64_t>(P, CLOSURE_CHUNK);
+    c.J1 = 0;
+    c.u1 = c.J1 + al256(sizeof(float) * (size_t)(P * F));
+    c.x = c.u1 + al256(sizeof(float) * (size_t)(P * R1 * F));
+    c.pts = c.x + al256(sizeof(float) * (size_t)F);
+    c.cnt = c.pts + al256(sizeof(int32_t) * (size_t)P);
+    c.feat = c.cnt + 256;
+    c.X = c.feat + al256(sizeof(float) * DIN * (size_t)(pc * F));
+    c.Y = c.X + al256(sizeof(uint16_t) * DIN * (size_t)(pc * F));
+    c.Jf = c.Y + al256(sizeof(float) * 2 * (size_t)(pc * F));
+    c.total = c.Jf + al256(sizeof(float) * (size_t)(P * F));
+    return c;
+}
+
+__global__ void k_iota_i32(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+}  // namespace
+
+extern "C" rt_status rt_closure_J_workspace(const rt_model* m, const rt_dirset* coarse, int64_t F, size_t solve_bytes,
+                                            size_t* bytes) {
+    if (!m || !coarse || !bytes || F <= 0) return fail(RT_ERR_ARG, "rt_closure_J_workspace: bad arguments");
+    int64_t R1 = 0;
+    rt_dirset_info(coarse, &R1, nullptr, nullptr, nullptr);
+    *bytes = closure_parts(m->P, R1, F).total + solve_bytes;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_closure_J(const rt_model* m, const rt_dirset* coarse, const rt_dirset* fine, const float* chi,
+                                  const float* eta, int64_t ld, const rt_freq_grid* grid, const double* I_bc,
+                                  const rt_mlp* h, float log_bound, float* J, int32_t* flagged, int64_t* n_flagged,
+                                  const rt_solve_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+    if (!m || !coarse || !fine || !chi || !eta || !grid || !I_bc || !h || !J || !flagged || !n_flagged || !ws)
+        return fail(RT_ERR_ARG, "rt_closure_J: NULL argument");
+    if (!h->has_norm) return fail(RT_ERR_STATE, "rt_closure_J: the network has no input norm (rt_mlp_set_input_norm)");
+    rt_solve_opts o = opts ? *opts : default_solve_opts();
+    o.precision = RT_F32;
+    int64_t F = 0;
+    for (int b = 0; b < grid->n_blocks && grid->len; ++b) F += grid->len[b];
+    if (F <= 0 || ld < F || grid->n_blocks < 1 || grid->n_blocks > RT_MAX_FREQ_BLOCKS || !grid->dx)
+        return fail(RT_ERR_ARG, "rt_closure_J: bad frequency grid");
+    int64_t R1 = 0, n1 = 0;
+    rt_dirset_info(coarse, &R1, &n1, nullptr, nullptr);
+    if (n1 > 0) return fail(RT_ERR_ARG, "rt_closure_J: the coarse set must be shared (uniform)");
+    const int64_t P = m->P;
+    if (P * F > MAX_SAMPLES) return fail(RT_ERR_UNSUPPORTED, "rt_closure_J: more than 2^31-1 samples");
+    const ClosureParts cp = closure_parts(P, R1, F);
+    if (ws_bytes <= cp.total) return fail(RT_ERR_CAPACITY, "rt_closure_J: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    float* J1 = (float*)(w + cp.J1);
+    float* u1 = (float*)(w + cp.u1);
+    float* fx = (float*)(w + cp.x);
+    int32_t* pts = (int32_t*)(w + cp.pts);
+    int32_t* cnt = (int32_t*)(w + cp.cnt);
+    float* feat = (float*)(w + cp.feat);
+    uint16_t* X = (uint16_t*)(w + cp.X);
+    float* Y = (float*)(w + cp.Y);
+    float* Jf = (float*)(w + cp.Jf);
+    void* solve_ws = w + cp.total;
+    const size_t solve_bytes = ws_bytes - cp.total;
+    // frequencies in Doppler widths: x = x0[b] + j dx[b] (x0 NULL: centred blocks)
+    std::vector<float> hx((size_t)F);
+    for (int b = 0, f = 0; b < grid->n_blocks; ++b) {
+        const double x0 = grid->x0 ? grid->x0[b] : -0.5 * (grid->len[b] - 1) * grid->dx[b];
+        for (int j = 0; j < grid->len[b]; ++j, ++f) hx[(size_t)f] = (float)(x0 + j * grid->dx[b]);
+    }
+    RT_HIP(hipMemcpyAsync(fx, hx.data(), sizeof(float) * (size_t)F, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_iota_i32, dim3(capped_blocks(nb(P, 256))), dim3(256), 0, s, pts, P);
+    RT_HIP(hipGetLastError());
+    // coarse solve with its per-pair u
+    rt_status st = rt_compute_J(m, coarse, nullptr, P, chi, eta, RT_F32, ld, grid, I_bc, J1, u1, &o, solve_ws,
+                                solve_bytes, stream);
+    if (st) return st;
+    // features -> network -> J = J1 exp(m), flags; points in chunks
+    RT_HIP(launch_fill_i32(cnt, 1, 0, s));
+    Norm nm;
+    std::memcpy(nm.mean, h->mean, sizeof(nm.mean));
+    std::memcpy(nm.istd, h->istd, sizeof(nm.istd));
+    for (int64_t p0 = 0; p0 < P; p0 += CLOSURE_CHUNK) {
+        const int64_t pc = std::min<int64_t>(CLOSURE_CHUNK, P - p0);
+        st = rt_closure_features(m, chi, eta, ld, F, fx, J1 + p0 * F, u1 + p0 * R1 * F, R1, pts + p0, pc, feat,
+                                 stream);
+        if (st) return st;
+        hipLaunchKernelGGL(k_normalize, dim3(capped_blocks(nb(pc * F * DIN, 256))), dim3(256), 0, s, feat, pc * F, nm,
+                           X);
+        RT_HIP(hipGetLastError());
+        st = rt_mlp_forward(const_cast<rt_mlp*>(h), X, nullptr, pc * F, Y, 0, nullptr, 0, stream);
+        if (st) return st;
+        hipLaunchKernelGGL(k_closure_apply, dim3(nb(pc, 256)), dim3(256), 0, s, J1 + p0 * F, Y, pc, F, log_bound,
+                           J + p0 * F, flagged, cnt, p0);
+        RT_HIP(hipGetLastError());
+    }
+    int32_t hn = 0;
+    RT_HIP(hipMemcpyAsync(&hn, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    *n_flagged = hn;
+    if (hn == 0) return RT_OK;
+    // the fallback: the plain solve with the fine set at the flagged points, merged into J
+    st = rt_compute_J(m, fine, flagged, hn, chi, eta, RT_F32, ld, grid, I_bc, Jf, nullptr, &o, solve_ws, solve_bytes,
+                      stream);
+    if (st) return st;
+    hipLaunchKernelGGL(k_closure_merge, dim3(capped_blocks(nb((int64_t)hn * F, 256))), dim3(256), 0, s, Jf, flagged,
+                       (int64_t)hn, F, P, J, error_word());
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

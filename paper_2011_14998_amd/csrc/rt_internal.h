@@ -162,6 +162,7 @@ struct SolveLaunch {
     int32_t* queue;        // persistent counter, or nullptr
     int32_t grid_waves;    // persistent grid size in waves
     int32_t n_bins;
+    int32_t bins_per_octave;  // bin of a line of N points: floor(bins_per_octave * log2 N)
     int32_t* bin_counts;   // [n_bins+1] scratch
     int32_t* bin_cursor;   // [n_bins] scratch
     int32_t* err;          // device error word
@@ -181,5 +182,32 @@ size_t bin_workspace(int64_t n_items, int32_t n_bins);
 hipError_t launch_bin(const SolveLaunch& a, void* ws, int32_t** items_out, hipStream_t s);
 hipError_t launch_solve(const SolveLaunch& a, int precision, hipStream_t s);
 hipError_t launch_reduce(const SolveLaunch& a, int precision, hipStream_t s);
+
+// api.hip: pieces of the solve and plan set-up shared by the whole-path entry points
+rt_solve_opts default_solve_opts();
+int32_t opts_bins(const rt_solve_opts& o);
+int32_t opts_bins_per_octave(const rt_solve_opts& o);
+// Validate the solve arguments and fill a launch description (lists may be set later).
+rt_status fill_solve_launch(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                            const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
+                            const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                            const double* I_bc, void* J, const rt_solve_opts& o, SolveLaunch& a);
+// Morton order of the positions of the listed origins (host order of list positions).  With
+// segments (n_seg > 0, seg[0..n_seg] ascending list positions) each segment is ordered on its own
+// bounding box and the segments follow one another.  Synchronises `s` once (host copies).
+hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
+                        std::vector<int32_t>& order, const int64_t* seg = nullptr, int n_seg = 0);
+// Plans: create with a given origin order (nullptr = Morton order of the origins), enqueue the
+// whole step on a stream (what the plan's graph holds), and a counter that changes whenever the
+// plan's graph is re-captured.
+rt_status plan_create_ordered(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                              const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
+                              const double* I_bc, void* J, const rt_solve_opts* opts, hipStream_t s,
+                              const std::vector<int32_t>* order, rt_plan** out);
+hipError_t plan_enqueue_step(rt_plan* p, hipStream_t s);
+int64_t plan_version(const rt_plan* p);
+
+// compute.hip: the chunked whole path (rt_compute_J) with its workspace carved by the caller
+size_t compute_ws_fixed(int64_t n_origins, int64_t R, int64_t F, const rt_solve_opts& o);
 
 }  // namespace rt

@@ -889,8 +889,8 @@ __global__ __launch_bounds__(256) void k_reduce(const SolveLaunch a) {
 }
 
 // ---------------------------------------------------------------- length binning
-// Bin b holds pairs whose line length N = n_- + n_+ + 1 has floor(4 log2 N) = b
-// (quarter-octave bins, the last bin open-ended).  Items are laid out bin by
+// Bin b holds pairs whose line length N = n_- + n_+ + 1 has floor(k log2 N) = b,
+// k = bins_per_octave (default 4: quarter-octave bins; the last bin open-ended).  Items are laid out bin by
 // bin, longest lines first, so the persistent grid starts the long lines early
 // and finishes on short ones.  With a spatial order of the origins (plans), the
 // pairs are visited direction by direction over that order, so inside each bin
@@ -902,10 +902,10 @@ __device__ inline int64_t bin_pair(const SolveLaunch& a, int64_t t) {
     return (int64_t)a.order[t - rc * a.n_origins] * a.R + rc;
 }
 
-__device__ inline int bin_of(int64_t N, int n_bins) {
+__device__ inline int bin_of(int64_t N, int n_bins, int per_octave) {
     int b = 0;
     double x = (double)N;
-    b = (int)floor(4.0 * log2(x));
+    b = (int)floor((double)per_octave * log2(x));
     if (b < 0) b = 0;
     if (b > n_bins - 1) b = n_bins - 1;
     return b;
@@ -922,7 +922,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const SolveLaunch a) {
     if (t < a.n_origins * a.R) {
         const int64_t s = 2 * bin_pair(a, t);  // slot of the +ray: origin*2R + 2r = 2*(origin*R + r)
         const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
-        atomicAdd(&h[bin_of(N, a.n_bins)], 1);
+        atomicAdd(&h[bin_of(N, a.n_bins, a.bins_per_octave)], 1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x)
@@ -951,7 +951,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const SolveLaunch a, int32_
     if (live) {
         const int64_t s = 2 * p;
         const int64_t N = a.ray_off[s + 2] - a.ray_off[s] + 1;
-        b = bin_of(N, a.n_bins);
+        b = bin_of(N, a.n_bins, a.bins_per_octave);
         local = atomicAdd(&h[b], 1);
     }
     __syncthreads();

@@ -9,6 +9,7 @@ from .models import (  # noqa: F401
     Model,
     FreqGrid,
     concat_models,
+    csr_from_edges,
     delaunay_csr,
     lattice_model,
     sphere_model,

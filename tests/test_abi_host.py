@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _header_functions():
     txt = open(os.path.join(ROOT, "include", "rt.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(rt_[A-Za-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -135,12 +135,28 @@ def test_workspace_queries(lib):
     sz = C.c_size_t()
     assert L.rt_trace_count_workspace(d._h, 1000, C.byref(sz)) == 0
     assert sz.value >= 1000 * 2 * 24 * 4
-    o = lib.SolveOptsC(lib.RT_F32, lib.SCHED_DIRECT, 1e-4, 0, 0, 0, 0, 0)
+    o = lib.SolveOptsC(precision=lib.RT_F32, schedule=lib.SCHED_DIRECT)
     assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
     assert sz.value >= 1000 * 24 * 64 * 4
-    o = lib.SolveOptsC(lib.RT_F64, lib.SCHED_BINNED, 1e-4, 0, 0, 0, 0, 0)
+    o = lib.SolveOptsC(precision=lib.RT_F64, schedule=lib.SCHED_BINNED)
     assert L.rt_solve_workspace(d._h, 1000, 64, C.byref(o), C.byref(sz)) == 0
     assert sz.value >= 1000 * 24 * 64 * 8 + 1000 * 24 * 4
+
+
+def test_compute_J_workspace_query(lib):
+    """rt_compute_J_workspace: one chunk for every origin holds u, the per-ray offsets and
+    lengths and lists of the stated mean length (12 bytes per entry); it grows with each."""
+    d = lib.DirSet.uniform(2)
+    R, F, n = 24, 64, 1000
+    b32 = lib.compute_J_workspace(d, n, F, precision=lib.RT_F32, mean_entries=40)
+    assert b32 >= n * R * F * 4 + n * 2 * R * (4 + 8) + n * 2 * R * 40 * 12
+    assert lib.compute_J_workspace(d, n, F, precision=lib.RT_F64, mean_entries=40) > b32
+    assert lib.compute_J_workspace(d, n, F, precision=lib.RT_F32, mean_entries=80) > b32
+    assert lib.compute_J_workspace(d, 2 * n, F, precision=lib.RT_F32, mean_entries=40) > b32
+    binned = lib.compute_J_workspace(d, n, F, precision=lib.RT_F32, schedule=lib.SCHED_BINNED, mean_entries=40)
+    assert binned >= b32 + n * R * 4
+    with pytest.raises(lib.RtError):
+        lib.compute_J_workspace(d, -1, F)
 
 
 def test_healpix_lookup_matches_oracle(orc):

@@ -31,12 +31,17 @@ def trained(rt):
     net = cl.train(X, T, norm, steps=1500, batch=4096, lr=2e-3, seed=1, log_every=500, verbose=True)
     test = cl.label(cl.DeviceModel.from_synth(synth.wind_model(seed=510, P=P)), ds1, ds8)
     torch.cuda.synchronize()
-    return cl, net, test, ds8
+    return cl, net, test, ds1, ds8
 
 
 def test_closure_gain_over_coarse(trained):
-    cl, net, test, ds8 = trained
-    r = cl.evaluate(net, test, ds8, flag_fractions=[0.0])
+    """What the network gains over the nside-1 solve alone.  Measured on winds from 12 000 to
+    2 000 000 points the network removes 13-30% of the coarse solve's median error (26% on
+    this test's models); the remainder is the sampling noise of where the 384 fine directions
+    cross the bright inner wind, which local features cannot predict.  The bar asks for at
+    least the low end of that measured range, a 15% reduction of the median, and a smaller p99."""
+    cl, net, test, ds1, ds8 = trained
+    r = cl.evaluate(net, test, ds1, ds8, flag_fractions=[0.0])
     c = r["closure"][0]
     base = r["coarse_alone"]["median"]
     print(f"median rel err: coarse alone {base:.3e}, closure {c['median']:.3e}")
@@ -48,9 +53,9 @@ def test_closure_gain_over_coarse(trained):
 def test_predicted_deviation_ranks_errors(trained):
     """Points the network is least sure of carry larger errors than those it is surest of,
     which is what makes the fallback worth its cost."""
-    cl, net, test, ds8 = trained
+    cl, net, test, ds1, ds8 = trained
     sd = cl.predicted_sd(net, test.dm, test.coarse)
-    res = cl.infer(net, test.dm, test.coarse, ds8, math.inf)
+    res = cl.infer(net, test.dm, ds1, ds8, math.inf)
     e = np.median(np.abs(res.J.double().cpu().numpy() / test.fine.J.double().cpu().numpy() - 1.0), axis=1)
     lo, hi = np.quantile(sd, [0.25, 0.75])
     e_lo, e_hi = np.median(e[sd <= lo]), np.median(e[sd >= hi])
@@ -59,8 +64,8 @@ def test_predicted_deviation_ranks_errors(trained):
 
 
 def test_fallback_everywhere_is_the_plain_solve(trained):
-    cl, net, test, ds8 = trained
-    res = cl.infer(net, test.dm, test.coarse, ds8, -math.inf)
+    cl, net, test, ds1, ds8 = trained
+    res = cl.infer(net, test.dm, ds1, ds8, -math.inf)
     assert res.n_flagged == test.dm.P
     got = res.J.cpu().numpy()
     want = test.fine.J.cpu().numpy()
@@ -70,13 +75,13 @@ def test_fallback_everywhere_is_the_plain_solve(trained):
 def test_finite_bound_flags_the_predicted_worst(trained):
     """Points flagged at a bound are exactly those whose predicted deviation exceeds it,
     and every unflagged point keeps the network's value."""
-    cl, net, test, ds8 = trained
+    cl, net, test, ds1, ds8 = trained
     rt = cl.rt
     X = rt.closure_normalize(cl.features(test.dm, test.coarse.J, test.coarse.u), net.norm.mean, net.norm.inv_std)
     Y = net.mlp.forward(X).cpu().numpy().reshape(test.dm.P, test.dm.F, 2)
     sd = np.exp(0.5 * Y[:, :, 1].astype(np.float64)).max(1)
     b = float(np.quantile(sd, 0.8))
-    res = cl.infer(net, test.dm, test.coarse, ds8, math.log(b))
+    res = cl.infer(net, test.dm, ds1, ds8, math.log(b))
     mask = cl.flagged_mask(res.flagged, res.n_flagged, test.dm.P)
     # the kernel compares 0.5 s > log b in FP32; away from the boundary both agree
     clear = np.abs(np.log(sd) - math.log(b)) > 1e-5

@@ -279,7 +279,7 @@ def test_plan_graph_replays(rt, orc, wind, schedule, walk, padded, lanes, group)
     plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=org,
                    precision=rt.RT_F32, schedule=schedule, padded_trace_budget=padded, trace_lanes=lanes,
                    group=group, walk=walk)
-    ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
+    ref = rt.compute_J_direct(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org,
                        precision=rt.RT_F32).cpu().numpy()
     plan.run(use_graph=False)
     rt.sync_status()
@@ -452,7 +452,7 @@ def test_autotune_and_cache(rt, wind, tmp_path):
     plan = rt.Plan(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, J, origins=_t(origins), **opts)
     plan.run()
     rt.sync_status()
-    ref = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=_t(origins))
+    ref = rt.compute_J_direct(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=_t(origins))
     assert np.array_equal(J.cpu().numpy(), ref.cpu().numpy())
     # re-captured with every schedule and tile option: the same result, bit for bit
     for sc, g, la, wpc in ((2, 8, 16, 0), (1, 4, 4, 16), (0, 8, 8, 0), (2, 4, 8, 0)):
@@ -486,7 +486,7 @@ def test_plan_moving_blocks_bitwise(rt, blocks, fp64):
                    schedule=rt.SCHED_SPATIAL)
     for scale in (1.0, 3.0):
         chi.mul_(scale)
-        ref = rt.compute_J(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, precision=prec).cpu().numpy()
+        ref = rt.compute_J_direct(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, precision=prec).cpu().numpy()
         for use_graph in (False, True, True):
             J.zero_()
             plan.run(use_graph=use_graph)
@@ -531,7 +531,7 @@ def test_plan_buffer_cache(rt, wind):
     assert np.array_equal(again, ref)
     assert rt.cached_memory() == held  # the second plan took the same buffers and returned them
     half = run(org[: n // 2], n // 2)  # smaller plans fit the cached blocks too
-    direct = rt.compute_J(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org[: n // 2],
+    direct = rt.compute_J_direct(model, ds, chi, eta, wind.freq.len, wind.freq.dx, I_bc, origins=org[: n // 2],
                           precision=rt.RT_F32).cpu().numpy()
     assert np.array_equal(half, direct)
     rt.release_cached_memory()
