@@ -128,6 +128,9 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RtError(-5, f"{LIB_PATH} is not built; run paper_2011_14998_amd/build.py")
+        # torch first: its HIP runtime is the one the process uses (device memory and streams come
+        # from torch), and the library must bind to that runtime rather than load one of its own
+        _torch()
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

@@ -154,6 +154,7 @@ def _batch_models():
     ms = synth.sph_batch_models(n_models=4, lo=800, hi=3000, seed0=920)
     st = synth.tiny_model(33, P=500, F=64, moving=False)  # a static model among moving ones
     st.freq = ms[0].freq
+    st.I_bc = ms[0].I_bc.copy()  # one grid and one boundary intensity for the whole batch
     return ms + [st]
 
 
