@@ -292,6 +292,26 @@ rt_status rt_compute_J(const rt_model* model, const rt_dirset* set, const int32_
                        const double* I_bc, void* J, void* u_out, const rt_solve_opts* opts, void* ws,
                        size_t ws_bytes, void* stream);
 
+/* rt_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments and results as rt_solve without the workspace.  Its scratch (u,
+ * unless u_out is given, and the length bins of RT_SCHED_BINNED) is a static
+ * 64 MiB device array that each GPU the library runs on holds until the
+ * process ends; a call needing more (rt_solve_workspace for the same
+ * arguments, with u_out NULL counting u) returns RT_ERR_CAPACITY before
+ * launching anything.  The call allocates nothing and never synchronises,
+ * except that the first call on a device looks up the scratch's and the error
+ * word's addresses (make one call before capturing); the direction set's tables
+ * must already be on the device (a shared set uploads them on its first use by
+ * any other call, e.g. rt_trace_count; otherwise RT_ERR_STATE).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (different streams, or host threads) race and must be serialised by the
+ * caller.  Async. */
+rt_status rt_solve_noalloc(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                           const int64_t* ray_off, const int32_t* ray_ids, const double* ray_Z, const void* chi,
+                           const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid, const double* I_bc,
+                           void* J, void* u_out, const rt_solve_opts* opts, void* stream);
+
 /* ------------------------------------------------------------------ plans
  * A plan owns the ray-list buffers for a fixed (model, set, origins) and replays
  * the whole hot path -- trace, (scan, list output), bin, sweep, reduce -- as one

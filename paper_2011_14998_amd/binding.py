@@ -62,6 +62,8 @@ _SIGS = {
     "rt_solve_workspace": (_i32, [_vp, _i64, _i64, C.POINTER(SolveOptsC), C.POINTER(_sz)]),
     "rt_solve": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC),
                         _vp, _vp, _vp, C.POINTER(SolveOptsC), _vp, _sz, _vp]),
+    "rt_solve_noalloc": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC),
+                                _vp, _vp, _vp, C.POINTER(SolveOptsC), _vp]),
     "rt_plan_create": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC), _vp, _vp,
                               C.POINTER(SolveOptsC), _vp, C.POINTER(_vp)]),
     "rt_plan_run": (_i32, [_vp, _i32, _vp]),
@@ -394,6 +396,28 @@ def solve(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc,
     sync_status(stream)
     del keep
     return (J, u) if want_u else J
+
+
+def solve_noalloc(model: Model, dirset: DirSet, rays, chi, eta, freq_len, freq_dx, I_bc, J, origins=None,
+                  n_origins=None, precision: int = RT_F32, schedule: int = SCHED_DIRECT, u=None, stream=None, **kw):
+    """rt_solve_noalloc into the caller's J (and u, if given): the solve with the library's static
+    scratch instead of a workspace.  Nothing is allocated here either: J (and u) are the caller's."""
+    torch = _torch()
+    dt = torch.float64 if precision == RT_F64 else torch.float32
+    if origins is not None:
+        origins = _dev(origins, torch.int32)
+        n_origins = origins.numel()
+    elif n_origins is None:
+        n_origins = model.P
+    ray_off, ids, Z = rays
+    g, keep = _grid(freq_len, freq_dx)
+    o = _opts(precision, schedule, **kw)
+    _check(load().rt_solve_noalloc(model._h, dirset._h, _ptr(origins), n_origins, _ptr(ray_off), _ptr(ids), _ptr(Z),
+                                   _ptr(_dev(chi, dt)), _ptr(_dev(eta, dt)), precision, chi.shape[1], C.byref(g),
+                                   _ptr(_dev(I_bc, torch.float64)), _ptr(_dev(J, dt)), _ptr(u), C.byref(o),
+                                   _stream(stream)))
+    del keep
+    return J
 
 
 def compute_J_direct(model: Model, dirset: DirSet, chi, eta, freq_len, freq_dx, I_bc, origins=None, **kw):

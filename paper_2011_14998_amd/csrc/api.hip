@@ -613,6 +613,72 @@ extern "C" rt_status rt_solve(const rt_model* m, const rt_dirset* set_, const in
     return RT_OK;
 }
 
+// ------------------------------------------------------------------ solve without allocation
+
+namespace {
+// Scratch of rt_solve_noalloc: the per-pair u and the length bins.  Each device
+// holds its own copy from the time the library's code is loaded on it until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+void* g_scratch_ptr[MAX_DEVICES] = {nullptr};
+}  // namespace
+
+// Device address of the current device's scratch, looked up once per device.
+static rt_status noalloc_scratch(void** out) {
+    int dev = 0;
+    RT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(RT_ERR_UNSUPPORTED, "rt_solve_noalloc: device index too large");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        RT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RT_ERR_HIP, "rt_solve_noalloc: no address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RT_OK;
+}
+
+extern "C" rt_status rt_solve_noalloc(const rt_model* m, const rt_dirset* set_, const int32_t* origins,
+                                      int64_t n_origins, const int64_t* ray_off, const int32_t* ray_ids,
+                                      const double* ray_Z, const void* chi, const void* eta, int32_t dtype, int64_t ld,
+                                      const rt_freq_grid* grid, const double* I_bc, void* J, void* u_out,
+                                      const rt_solve_opts* opts, void* stream) {
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_solve_opts o = opts ? *opts : default_opts();
+    if (o.schedule != RT_SCHED_DIRECT && o.schedule != RT_SCHED_BINNED)
+        return fail(RT_ERR_ARG, "rt_solve_noalloc: schedule must be RT_SCHED_DIRECT or RT_SCHED_BINNED");
+    if (!ray_off) return fail(RT_ERR_ARG, "rt_solve_noalloc: NULL ray_off");
+    if (set) {  // a shared set uploads its tables on first use on a device: that must have happened already
+        int dev = -1;
+        RT_HIP(hipGetDevice(&dev));
+        if (!set->dev.dirs || set->dev.device != dev)
+            return fail(RT_ERR_STATE, "rt_solve_noalloc: the direction set's tables are not on this device yet "
+                                      "(use the set once with an allocating call, e.g. rt_trace_count)");
+    }
+    SolveLaunch a;
+    rt_status st = fill_solve_launch(m, set, origins, n_origins, ray_off, ray_ids, ray_Z, chi, eta, dtype, ld, grid,
+                                     I_bc, J, o, a);
+    if (st) return st;
+    if (n_origins * a.R * ((a.F + 63) / 64) > MAX_SOLVE_ITEMS)
+        return fail(RT_ERR_UNSUPPORTED, "rt_solve_noalloc: too many work items");
+    const size_t need = solve_ws_bytes(n_origins, a.R, a.F, o, u_out == nullptr);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(RT_ERR_CAPACITY, "rt_solve_noalloc: " + std::to_string(need) +
+                                         " bytes of scratch needed, above the static 64 MiB; pass u_out or "
+                                         "solve fewer origins per call");
+    void* ws = nullptr;
+    st = noalloc_scratch(&ws);
+    if (st) return st;
+    void* bin_ws = nullptr;
+    st = carve_solve_ws(a, o, u_out, ws, NOALLOC_SCRATCH_BYTES, &bin_ws);
+    if (st) return st;
+    RT_HIP(enqueue_solve(a, o.precision, bin_ws, (hipStream_t)stream));
+    return RT_OK;
+}
+
 extern "C" rt_status rt_sync_status(void* stream) {
     RT_HIP(hipStreamSynchronize((hipStream_t)stream));
     int32_t* w = error_word();
