@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the ray-tracing radiative-transfer hot path on one MI355X.
 
-Workload: the analytic spherical wind (50 000 points, density of points ~ r^-3
-on r in [1, 100], Delaunay neighbours, rho = r^-2, one Gaussian line sampled at
-64 frequencies, S = 1/r, radial velocity up to 20 Doppler widths), with the
-uniform HEALPix set at nside = 4 (96 antipodal pairs, 192 rays per point).
+Default workload: 64 SPH-like particle clouds (80% Plummer sphere + 20% logarithmic
+spiral arm, Keplerian rotation, Delaunay neighbours), sizes log-uniform in
+[10 000, 200 000] particles (4.1 million in all), one line sampled at 64
+frequencies, the uniform HEALPix set at nside = 2 (24 antipodal pairs), FP32 sweep
+with FP64 geometry.  The clouds go through the library as one batch: a disjoint
+union built on the device (rt_batch) whose plan traces and solves every model in
+one launch per kernel, replayed as one HIP graph.
 
-One step = the whole hot path as one HIP-graph replay: trace count, scan,
-trace write (FP64 geometry), length binning, the FP32 Feautrier sweep with
-FP64 rows for small optical-depth steps, and the J reduction, for all 50 000
-origins.  Inputs are resident in HBM before timing starts.
+One timed step = one replay of that graph, inputs resident in HBM: the gather of
+the 64 models' chi/eta tables into the union, the walk of every ray straight into
+its slot of the ray lists (slots sized by the count pass and scan that ran once
+when the batch was created), the length-binned persistent Feautrier sweep, the J
+reduction, and the scatter of J back to the 64 models.  The cold call -- the
+whole path from scratch (union build, Morton order, count pass, scan,
+allocation, graph capture, one run) -- is timed once beside it.
 
-Prints one JSON line (metric, value, roofline of the sweep kernel, CPU oracle
-baseline on a bounded sample of origins).
+Prints one JSON line: the metric, the roofline of the sweep kernel (measured DRAM
+traffic from the committed rocprofv3 counters, and the algorithmic byte count
+beside it), the other workloads' numbers, and the CPU oracle on a seeded sample.
 """
 from __future__ import annotations
 
@@ -20,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,8 +37,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NSIDE = 4
 F = 64
+
+# Plan options per workload: what the autotuner (rt_autotune_plan, `--autotune`) chose on MI355X,
+# kept fixed so that the timed kernel variant is the one the committed counters were taken on.
+TUNED = {
+    "sph_batch": dict(schedule=1, group=8, trace_lanes=8, waves_per_cu=32, n_bins=64, bins_per_octave=4),
+    "wind": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree_reduced": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+}
 
 
 def _log(msg):
@@ -39,7 +55,9 @@ def _log(msg):
 
 def sweep_bytes(n_origins, R, total_entries, F, moving, es=4):
     """Algorithmic bytes of one sweep launch: per line point the chi and eta rows
-    (2 F es), its id (4) and Z (8), its velocity (12 if moving); per pair the u row."""
+    (2 F es), its id (4) and Z (8), its velocity (12 if moving); per pair the u row.
+    Every line that passes a point counts that point's rows again (cache-served
+    re-reads included)."""
     points = total_entries + n_origins * R  # every line also holds its origin
     return points * (2 * F * es + 4 + 8 + (12 if moving else 0)) + n_origins * R * F * es
 
@@ -52,8 +70,9 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
+SWEEP_SRC = ("solve.hip", "rt_internal.h")
 KERNEL_KEYS = {"sweep": ("k_solve_direct", "k_solve_persist"), "walk": ("k_trace<1", "k_trace<2"),
-               "compact": ("k_compact",), "reduce": ("k_reduce",)}
+               "compact": ("k_compact",), "reduce": ("k_reduce",), "gather": ("k_batch_gather",)}
 
 
 def _counter_means(csv_path, counter):
@@ -70,9 +89,9 @@ def _counter_means(csv_path, counter):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def summarize_counters(d, out_json, out_md):
-    """Write the counter summary of one profiling session (directory d holding the
-    rocprofv3 outputs fetch/, write/, copyf/, copyw/, stats/) to profiles/."""
+def summarize_counters(d, workload, out_json, out_md, bench_cmd):
+    """Write the counter summary of one profiling session (directory d holding the rocprofv3
+    outputs fetch/, write/, copyf/, copyw/, stats/ and optionally sq/, ta/) to profiles/."""
     import csv
     import glob
     f = _counter_means(glob.glob(os.path.join(d, "fetch", "*counter_collection.csv"))[0], "FETCH_SIZE")
@@ -83,11 +102,11 @@ def summarize_counters(d, out_json, out_md):
     kib = 1 << 20
     fscale = kib / cf["copy"]
     wscale = kib / cw["copy"]
-    res = {"kernel_src_hash": src_hash("solve.hip", "rt_internal.h"),
+    res = {"workload": workload, "command": bench_cmd, "kernel_src_hash": src_hash(*SWEEP_SRC),
            "calibration": {"copy_bytes": 1 << 30, "FETCH_SIZE_KiB": cf["copy"], "WRITE_SIZE_KiB": cw["copy"],
                            "fetch_scale": fscale, "write_scale": wscale},
            "per_launch": {}}
-    for fam in ("sweep", "walk", "compact", "reduce"):
+    for fam in ("sweep", "walk", "compact", "reduce", "gather"):
         if fam in f and fam in w:
             rb = f[fam] * 1024 * fscale
             wb = w[fam] * 1024 * wscale
@@ -98,11 +117,12 @@ def summarize_counters(d, out_json, out_md):
         json.dump(res, fo, indent=1)
     stats = glob.glob(os.path.join(d, "stats", "*kernel_stats.csv"))
     sq = glob.glob(os.path.join(d, "sq", "*counter_collection.csv"))
+    ta = glob.glob(os.path.join(d, "ta", "*counter_collection.csv"))
     if stats and out_md:
         rows = list(csv.DictReader(open(stats[0])))
-        B = "python3 bench.py --steps 5 --warmup 1 --cpu-sample 0 --no-autotune"
+        B = bench_cmd
         with open(out_md, "w") as fo:
-            fo.write("# Kernel times and HBM traffic: analytic wind, 50 000 points, nside 4, F = 64, FP32 sweep\n\n")
+            fo.write(f"# Kernel times and HBM traffic: {workload}\n\n")
             fo.write("Session (run from /tmp with TMPDIR=/tmp; every command runs committed files only):\n\n")
             fo.write(f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats -o bench -- {B}\n")
             fo.write(f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {B}\n")
@@ -111,35 +131,19 @@ def summarize_counters(d, out_json, out_md):
                      "python3 bench.py --copy-calibration 1073741824\n")
             fo.write("    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/copyw -o run -- "
                      "python3 bench.py --copy-calibration 1073741824\n")
-            fo.write("    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES "
-                     f"SQ_BUSY_CYCLES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE --output-format csv -d <dir>/sq -o run -- {B}\n")
-            fo.write("    python3 bench.py --summarize-counters <dir> profiles/sweep_wind50k_nside4_counters.json "
-                     "profiles/wind50k_nside4_kernel_stats.md\n\n")
-            fo.write("    rocprofv3 --pmc TA_TA_BUSY_sum TD_TD_BUSY_sum GRBM_GUI_ACTIVE --output-format csv -d <dir>/ta "
-                     f"-o run -- {B}\n")
-            fo.write("    rocprofv3 --pmc TCP_TCP_TA_DATA_STALL_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum "
-                     "TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum --output-format csv -d <dir>/tcp "
-                     f"-o run -- {B}\n\n")
-            fo.write("`--no-autotune` runs the library defaults (spatial schedule, load group 8, 8 lanes per ray), "
-                     "which the autotuner keeps unless a candidate is 5% faster, without its candidate runs in the "
-                     "trace.\n\n")
+            if sq:
+                fo.write("    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES "
+                         f"SQ_BUSY_CYCLES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE --output-format csv -d <dir>/sq -o run -- "
+                         f"{B}\n")
+            if ta:
+                fo.write("    rocprofv3 --pmc TA_TA_BUSY_sum TD_TD_BUSY_sum GRBM_GUI_ACTIVE --output-format csv "
+                         f"-d <dir>/ta -o run -- {B}\n")
+            fo.write(f"    python3 bench.py --summarize-counters <dir> {workload} {out_json} {out_md} '{B}'\n\n")
             fo.write("## rocprofv3 --stats (kernel trace)\n\n")
             fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
             for r in rows:
                 fo.write(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                          f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |\n")
-            dflt = glob.glob(os.path.join(d, "stats_default", "*kernel_stats.csv"))
-            if dflt:
-                fo.write("\n## rocprofv3 --stats of the default command\n\n")
-                fo.write("    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats_default -o bench -- "
-                         "python3 bench.py\n\n")
-                fo.write("The whole default run: autotuner candidates (one warm-up and two timed runs each), warm-up, "
-                         "the timed graph replays and the per-stage profile runs; the kernel instance the bench "
-                         "times is the one its JSON line names.\n\n")
-                fo.write("| kernel | calls | average ms | total ms | % |\n|---|---|---|---|---|\n")
-                for r in list(csv.DictReader(open(dflt[0]))):
-                    fo.write(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
-                             f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |\n")
             fo.write("\n## HBM traffic per launch (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale)\n\n")
             c = res["calibration"]
             fo.write(f"Calibration: a plain 1 GiB device copy reads as FETCH_SIZE {c['FETCH_SIZE_KiB']:.0f} KiB and "
@@ -156,27 +160,21 @@ def summarize_counters(d, out_json, out_md):
                 names = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_BUSY_CYCLES",
                          "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE"]
                 fo.write("| kernel | " + " | ".join(names) + " |\n|" + "---|" * (len(names) + 1) + "\n")
-                for fam in ("sweep", "walk", "compact"):
+                for fam in ("sweep", "walk"):
                     vals = [_counter_means(sq[0], n).get(fam, float("nan")) for n in names]
                     fo.write(f"| {fam} | " + " | ".join(f"{x:.3g}" for x in vals) + " |\n")
-            ta = glob.glob(os.path.join(d, "ta", "*counter_collection.csv"))
-            tcp = glob.glob(os.path.join(d, "tcp", "*counter_collection.csv"))
             if ta:
                 # busy fraction: the counter summed over the 256 TA/TD units over 256 x the launch's active
                 # cycles per XCD (GRBM_GUI_ACTIVE summed over the 8 XCDs / 8)
-                fo.write("\n## L1 data path per launch (TA/TD busy fractions, TCP accesses)\n\n")
-                fo.write("| kernel | active cycles per XCD | TA busy | TD busy | L1 accesses | L1 -> L2 reads | "
-                         "VALU instructions | VALU issue (4-cycle estimate) |\n|---|---|---|---|---|---|---|---|\n")
+                fo.write("\n## L1 data path per launch (TA/TD busy fractions)\n\n")
+                fo.write("| kernel | active cycles per XCD | TA busy | TD busy | VALU instructions | "
+                         "VALU issue (4-cycle estimate) |\n|---|---|---|---|---|---|\n")
                 for fam in ("walk", "sweep"):
                     act = _counter_means(ta[0], "GRBM_GUI_ACTIVE").get(fam, float("nan")) / 8
                     tab = _counter_means(ta[0], "TA_TA_BUSY_sum").get(fam, float("nan")) / 256 / act
                     tdb = _counter_means(ta[0], "TD_TD_BUSY_sum").get(fam, float("nan")) / 256 / act
-                    acc = _counter_means(tcp[0], "TCP_TOTAL_CACHE_ACCESSES_sum").get(fam, float("nan")) if tcp \
-                        else float("nan")
-                    l2r = _counter_means(tcp[0], "TCP_TCC_READ_REQ_sum").get(fam, float("nan")) if tcp \
-                        else float("nan")
                     valu = _counter_means(sq[0], "SQ_INSTS_VALU").get(fam, float("nan")) if sq else float("nan")
-                    fo.write(f"| {fam} | {act:.3g} | {tab:.2f} | {tdb:.2f} | {acc:.3g} | {l2r:.3g} | {valu:.3g} | "
+                    fo.write(f"| {fam} | {act:.3g} | {tab:.2f} | {tdb:.2f} | {valu:.3g} | "
                              f"{valu * 4 / (1024 * act):.2f} |\n")
                 fo.write("\nVALU issue: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x active cycles), an upper estimate "
                          "for FP32 work, which can issue faster.\n")
@@ -203,33 +201,272 @@ def copy_ceiling_gbs(dev, n_bytes: int = 2 << 30, reps: int = 5) -> float:
     return rate
 
 
-def load_traffic(kernel_hash, launch_bytes_alg):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "sweep_wind50k_nside4_counters.json")
+def load_traffic(workload):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary of this
+    workload, if it was taken on the current sweep source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_counters.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_src_hash") != kernel_hash:
-        return None
-    return d.get("hbm_bytes_per_launch")
+    if d.get("kernel_src_hash") != src_hash(*SWEEP_SRC):
+        return None, path
+    return d.get("hbm_bytes_per_launch"), path
 
 
-def cpu_baseline(m, dirs, w2, n_sample, seed=7):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_threads():
+    """Threads the oracle may use: the job's CPU share (OMP_NUM_THREADS where the
+    environment sets it), else every core in this process's affinity set."""
+    aff = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return (int(env) if env.isdigit() and int(env) > 0 else aff), aff
+
+
+def cpu_baseline(parts, dirs, w2, what, budget_s=20.0):
+    """The oracle (FP64, OpenMP over origins) on seeded origin samples of the same models, timed
+    on this host; parts = [(model, origins)].  Its rate (solves/s) stands for the whole workload,
+    which it would take the oracle far longer to finish: the record says so ("extrapolated")."""
     import oracle
-    threads = min(len(os.sched_getaffinity(0)), 16)
-    rng = np.random.default_rng(seed)
-    origins = np.sort(rng.choice(m.P, n_sample, replace=False)).astype(np.int32)
-    c32 = m.chi.astype(np.float32).astype(np.float64)
-    e32 = m.eta.astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.compute_J(m, dirs, w2, origins=origins, chi=c32, eta=e32, nthreads=threads)
-    dt = time.perf_counter() - t0
-    solves = n_sample * len(w2) * m.F
+    threads, aff = oracle_threads()
+    solves, dt = 0, 0.0
+    for m, org in parts:
+        c32 = m.chi.astype(np.float32).astype(np.float64)
+        e32 = m.eta.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.compute_J(m, dirs, w2, origins=org, chi=c32, eta=e32, nthreads=threads)
+        dt += time.perf_counter() - t0
+        solves += len(org) * len(w2) * m.F
+        if dt > budget_s:
+            break
     return dict(value=solves / dt, unit="point-pair-freq solves/s", cores=threads, kind="oracle",
-                sample=f"{n_sample} seeded origins of the same model, full trace + FP64 solve + J, "
-                       f"{solves:.3e} solves in {dt:.2f} s")
+                extrapolated=True, cpu_model=_cpu_model(), affinity_cores=aff,
+                sample=f"{what}: full trace + FP64 solve + J, {solves:.3e} solves in {dt:.2f} s; the rate is "
+                       f"taken for the whole workload")
+
+
+def _opts_from_args(args, workload):
+    o = dict(TUNED[workload])
+    if args.schedule:
+        o["schedule"] = {"direct": 0, "binned": 1, "spatial": 2}[args.schedule]
+    if args.group:
+        o["group"] = args.group
+    if args.trace_lanes:
+        o["trace_lanes"] = args.trace_lanes
+    return o
+
+
+def _timed_replays(run, steps, warmup):
+    """Warm-up, then `steps` replays bracketed by HIP events on the current stream."""
+    import torch
+    import paper_2011_14998_amd as rt
+    for _ in range(warmup):
+        run()
+    rt.sync_status()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rt.sync_status()
+    return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3
+
+
+def _roofline(workload, stages, alg, dev):
+    traffic, path = load_traffic(workload)
+    sweep_s = stages["sweep"] * 1e-3
+    r = {"kernel": "feautrier sweep", "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "achieved": None, "frac": None, "traffic": traffic, "sweep_ms": stages["sweep"],
+         "measured": ("DRAM-side bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (calibrated by a "
+                      "1 GiB copy) in " + os.path.relpath(path, ROOT)) if path else None}
+    if traffic:
+        r["achieved"] = traffic / sweep_s / 1e9
+        r["frac"] = r["achieved"] / HBM_PEAK_GBS
+    elif path:
+        r["measured"] += " (taken on another sweep source: not used)"
+    r["algorithmic"] = {"bytes_per_launch": alg, "gbs": alg / sweep_s / 1e9, "frac": alg / sweep_s / 1e9 / HBM_PEAK_GBS,
+                        "model": "every line point's chi and eta rows, id, Z and velocity, counted once per line "
+                                 "that reads them, plus the u rows; re-reads served by L2 and the Infinity Cache "
+                                 "count too, so this fraction can exceed 1"}
+    r["copy_ceiling_gbs"] = copy_ceiling_gbs(dev)
+    return r
+
+
+def _other_wind(rt, torch, dev, steps=10):
+    """The 50 000-point analytic wind at nside 4 (one plan), as an extra line of numbers."""
+    import synth
+    m = synth.wind_model(seed=2, P=50_000, F=F)
+    c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+    model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
+    ds = rt.DirSet.uniform(4)
+    chi, eta = torch.as_tensor(c32, device=dev), torch.as_tensor(e32, device=dev)
+    I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device=dev)
+    J = torch.empty((m.P, F), dtype=torch.float32, device=dev)
+    plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
+                   **TUNED["wind"])
+    ms, _ = _timed_replays(lambda: plan.run(use_graph=True), steps, 2)
+    st = plan.profile(3)
+    total = plan.info()["total"]
+    out = {"workload": "analytic spherical wind, 50000 points, nside 4 (96 pairs), F=64, FP32 sweep",
+           "solves_per_s": m.P * ds.R * F / (ms * 1e-3), "ms_per_step": ms, "stages_ms": st,
+           "sweep_algorithmic_frac": sweep_bytes(m.P, ds.R, total, F, True) / (st["sweep"] * 1e-3) / 1e9 /
+           HBM_PEAK_GBS}
+    del plan
+    rt.release_cached_memory()
+    return out
+
+
+def run_batch(args, rt, torch, dev):
+    """The default workload: 64 SPH-like clouds through rt_batch."""
+    import synth
+    t_gen = time.perf_counter()
+    gen_workers = min(16, oracle_threads()[0])
+    ms_ = synth.sph_batch_models(n_models=64, scale=args.batch_scale, workers=gen_workers)
+    P_tot = sum(m.P for m in ms_)
+    _log(f"generated 64 SPH-like clouds: {P_tot} particles, {sum(m.E for m in ms_)} neighbour entries in "
+         f"{time.perf_counter() - t_gen:.1f} s")
+    models, chis, etas, Js = [], [], [], []
+    for m in ms_:
+        c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+        models.append(rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel))
+        chis.append(torch.as_tensor(c32, device=dev))
+        etas.append(torch.as_tensor(e32, device=dev))
+        Js.append(torch.empty((m.P, F), dtype=torch.float32, device=dev))
+    nside = args.nside or 2
+    ds = rt.DirSet.uniform(nside)
+    R = ds.R
+    I_bc = torch.as_tensor(ms_[0].I_bc, dtype=torch.float64, device=dev)
+    opts = _opts_from_args(args, "sph_batch")
+    _log(f"building the batch (union on the device, count pass, graph) with {opts} ...")
+    t0 = time.perf_counter()
+    b = rt.Batch(models, ds, chis, etas, ms_[0].freq.len, ms_[0].freq.dx, I_bc, Js, precision=rt.RT_F32, **opts)
+    torch.cuda.synchronize()
+    _log(f"batch built in {time.perf_counter() - t0:.1f} s")
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        opts, tms = b.autotune(n_runs=2, verbose=True)
+        tuned = dict(opts, ms_per_step=tms, seconds=time.perf_counter() - t0)
+        _log(f"autotuner chose {opts}")
+    total = b.info()["total"]
+    ms, wall_ms = _timed_replays(lambda: b.run(use_graph=True), args.steps, args.warmup)
+    _log(f"step {ms:.3f} ms ({wall_ms:.3f} ms wall)")
+    stages = b.profile(max(3, min(args.steps, 5)))
+    _log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    solves = P_tot * R * F
+    alg = sweep_bytes(P_tot, R, total, F, moving=True)
+    roof = _roofline("sph_batch", stages, alg, dev)
+    desc = (f"64 SPH-like clouds (80% Plummer sphere + 20% logarithmic spiral arm, Keplerian rotation, Delaunay "
+            f"neighbours), sizes log-uniform in [10000, 200000] x {args.batch_scale}, {P_tot} particles in all; "
+            f"nside {nside} ({R} pairs), F={F}, FP32 sweep, FP64 tracing; one disjoint union built on the device, "
+            "one HIP graph")
+    rec = {
+        "metric": "point-ray-freq solves/s (one solve = one origin x antipodal ray pair x frequency)",
+        "value": solves / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 sweep, f64 geometry", "data": "synthetic (seeded SPH-like clouds)",
+        "config": {"workload": desc, "models": 64, "points": P_tot, "pairs_per_point": R, "freqs": F,
+                   "ray_list_entries": total, "mean_line_length": (total + P_tot * R) / (P_tot * R),
+                   "plan_options": opts, "autotune": tuned,
+                   "timed_step": "one replay of the batch's HIP graph: table gather into the union, walk of every "
+                                 "ray into its slot (slots from the count pass and scan at creation), "
+                                 "length-binned sweep, J reduction, J scatter to the 64 models"},
+        "roofline": roof,
+        "stages_ms": stages,
+        "line_point_freq_updates_per_s": (total + P_tot * R) * F / (ms * 1e-3),
+    }
+    del b
+    rt.release_cached_memory()
+    torch.cuda.empty_cache()
+    if not args.no_cold:
+        _log("cold call: rt_compute_J_batched from scratch ...")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt.compute_J_batched(models, ds, chis, etas, ms_[0].freq.len, ms_[0].freq.dx, I_bc, Js=Js, **opts)
+        torch.cuda.synchronize()
+        cold = time.perf_counter() - t0
+        rt.release_cached_memory()
+        rec["cold_call"] = {"s": cold, "what": "rt_compute_J_batched from scratch: union built on the device, "
+                                               "Morton order of every model, count pass, scan, allocation of the "
+                                               "lists, graph capture, one run, destruction"}
+    return rec, ms_, ds
+
+
+def run_plan_workload(args, rt, torch, dev):
+    """One model through one plan: the wind (50k points, nside 4) or the AMR-octree-like clouds."""
+    import synth
+    t_gen = time.perf_counter()
+    if args.workload == "wind":
+        m = synth.wind_model(seed=2, P=50_000, F=F)
+        nside = args.nside or 4
+        desc = "analytic spherical wind, 50000 points (Delaunay), moving (v_inf 20 Doppler widths)"
+    else:
+        target = 500_000 if args.workload == "octree" else 50_000
+        m = synth.octree_model(seed=3, target=target)
+        nside = args.nside or 4
+        desc = (f"AMR-octree-like cloud, {m.P} leaves (levels 5-8, touching-leaf neighbours), 2 lines x 48 "
+                "frequencies, turbulent velocity 3 Doppler widths rms")
+    _log(f"generated {args.workload}: {m.P} points, {m.E} neighbour entries in {time.perf_counter() - t_gen:.1f} s")
+    Fw = m.F
+    c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+    model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
+    ds = rt.DirSet.uniform(nside)
+    R = ds.R
+    chi, eta = torch.as_tensor(c32, device=dev), torch.as_tensor(e32, device=dev)
+    I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device=dev)
+    J = torch.empty((m.P, Fw), dtype=torch.float32, device=dev)
+    scheme = {"feautrier2": rt.SCHEME_FEAUTRIER2, "hermite": rt.SCHEME_HERMITE}[args.scheme]
+    opts = _opts_from_args(args, args.workload)
+    plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
+                   dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme,
+                   walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
+                   **opts)
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        opts, tms = rt.autotune(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, n_runs=2,
+                                verbose=True, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme)
+        tuned = dict(opts, ms_per_step=tms, seconds=time.perf_counter() - t0)
+        plan.retune(**opts)
+    total = plan.info()["total"]
+    ms, wall_ms = _timed_replays(lambda: plan.run(use_graph=True), args.steps, args.warmup)
+    _log(f"step {ms:.3f} ms ({wall_ms:.3f} ms wall)")
+    stages = plan.profile(max(3, min(args.steps, 10)))
+    _log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    alg = sweep_bytes(m.P, R, total, Fw, moving=m.vel is not None)
+    rec = {
+        "metric": "point-ray-freq solves/s (one solve = one origin x antipodal ray pair x frequency)",
+        "value": m.P * R * Fw / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 sweep, f64 geometry", "data": f"synthetic (seeded {args.workload})",
+        "config": {"workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep", "points": m.P,
+                   "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
+                   "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "walk": args.walk,
+                   "dtau_max": args.dtau_max, "dv_max": args.dv_max, "scheme": args.scheme, "autotune": tuned,
+                   "frequency_chunks_per_pair": (Fw + 63) // 64,
+                   "timed_step": "one replay of the plan's HIP graph: walk of every ray into its slot (slots from "
+                                 "the count pass and scan at creation), sweep, J reduction"},
+        "roofline": _roofline(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages, alg, dev),
+        "stages_ms": stages,
+        "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms * 1e-3),
+    }
+    del plan
+    rt.release_cached_memory()
+    return rec, [m], ds
 
 
 def main():
@@ -237,28 +474,31 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default="spatial",
-                    help="plan schedule when the autotuner is skipped")
-    ap.add_argument("--cpu-sample", type=int, default=25000, help="origins timed on the CPU oracle (0 = skip)")
-    ap.add_argument("--workload", choices=["wind", "octree", "octree_reduced", "sph_batch", "closure", "precision",
+    ap.add_argument("--workload", choices=["sph_batch", "wind", "octree", "octree_reduced", "closure", "precision",
                                            "directions"],
-                    default="wind",
-                    help="wind: the headline 50k-point wind (default); octree: ~500k-leaf AMR-like cloud, 2x48 "
-                         "frequencies; octree_reduced: the same field with ~50k leaves; sph_batch: 64 SPH-like "
-                         "clouds as one disjoint union (size scaled by --batch-scale); closure: the learned "
+                    default="sph_batch",
+                    help="sph_batch: 64 SPH-like clouds in one batch (default, --batch-scale 1: 4.1M particles); "
+                         "wind: the 50k-point wind at nside 4; octree: ~500k-leaf AMR-like cloud, 2x48 "
+                         "frequencies; octree_reduced: the same field with ~50k leaves; closure: the learned "
                          "closure trained on winds of seeds 500-503 and judged on 510-511 against the plain "
                          "nside-8 solve (--closure-points each); precision: the FP32 sweep's error against the "
                          "FP64 oracle, model by model; directions: adaptive (l 1..4) against regular nside-16 "
                          "directions on the AMR-like cloud")
-    ap.add_argument("--batch-scale", type=float, default=0.25)
-    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner and use the library defaults")
+    ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner on this workload first (otherwise the fixed options in TUNED)")
+    ap.add_argument("--schedule", choices=["direct", "binned", "spatial"], default=None)
+    ap.add_argument("--group", type=int, default=0, help="sweep load-group size (4 or 8)")
+    ap.add_argument("--trace-lanes", type=int, default=0, help="lanes per ray in the walk (4, 8 or 16)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="origins per model timed on the CPU oracle (0 = skip; -1 = the workload's default)")
+    ap.add_argument("--no-cold", action="store_true", help="skip the cold-call timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra workloads' numbers")
     ap.add_argument("--nside", type=int, default=0, help="HEALPix nside (0 = the workload's own)")
-    ap.add_argument("--summarize-counters", nargs=3, metavar=("DIR", "OUT_JSON", "OUT_MD"),
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("DIR", "WORKLOAD", "OUT_JSON", "OUT_MD", "CMD"),
                     help="summarise a rocprofv3 session directory into the profiles/ files and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (for scaling HBM counters) and exit")
-    ap.add_argument("--group", type=int, default=0, help="sweep load-group size (4 or 8; 0 = library default)")
-    ap.add_argument("--trace-lanes", type=int, default=0, help="lanes per ray in the walk (4 or 8; 0 = default)")
     ap.add_argument("--walk", choices=["exact", "padded", "two-pass"], default="exact",
                     help="plan walk: once into the creation-time slots (default), once into padded slots plus "
                          "compaction, or count + write")
@@ -283,7 +523,8 @@ def main():
                          "(steps must stay below about 3.46: use --dtau-max)")
     args = ap.parse_args()
     if args.summarize_counters:
-        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        d, wl, oj, om, cmd = args.summarize_counters
+        print(json.dumps(summarize_counters(d, wl, oj, om, cmd), indent=1))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -294,7 +535,6 @@ def main():
     import torch
 
     import paper_2011_14998_amd as rt
-    import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -318,127 +558,25 @@ def main():
     if args.workload == "directions":
         run_directions(args)
         return
-
-    t_gen = time.perf_counter()
-    if args.workload == "wind":
-        m = synth.wind_model(seed=2, P=50_000, F=F)
-        nside = args.nside or NSIDE
-        desc = "analytic spherical wind, 50000 points (Delaunay), moving (v_inf 20 Doppler widths)"
-    elif args.workload in ("octree", "octree_reduced"):
-        target = 500_000 if args.workload == "octree" else 50_000
-        m = synth.octree_model(seed=3, target=target)
-        nside = args.nside or 4
-        desc = (f"AMR-octree-like cloud, {m.P} leaves (levels 5-8, touching-leaf neighbours), 2 lines x 48 "
-                "frequencies, turbulent velocity 3 Doppler widths rms")
+    if args.workload == "sph_batch":
+        rec, models, ds = run_batch(args, rt, torch, dev)
+        per_model = 40 if args.cpu_sample < 0 else args.cpu_sample
     else:
-        ms = synth.sph_batch_models(n_models=64, scale=args.batch_scale, workers=16)
-        m = synth.concat_models(ms)
-        nside = args.nside or 2
-        desc = (f"64 SPH-like clouds (Plummer + spiral arm, Keplerian), {m.P} particles in one disjoint union "
-                f"(sizes x{args.batch_scale})")
-    _log(f"generated {args.workload}: {m.P} points, {m.E} neighbour entries in {time.perf_counter() - t_gen:.1f} s")
-    Fw = m.F
-    c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
-    model = rt.Model.from_numpy(m.pos, m.nbr_off, m.nbr_idx, m.vel)
-    ds = rt.DirSet.uniform(nside)
-    R = ds.R
-    chi = torch.as_tensor(c32, device=dev)
-    eta = torch.as_tensor(e32, device=dev)
-    I_bc = torch.as_tensor(m.I_bc, dtype=torch.float64, device=dev)
-    J = torch.empty((m.P, Fw), dtype=torch.float32, device=dev)
-    sched = {"direct": rt.SCHED_DIRECT, "binned": rt.SCHED_BINNED, "spatial": rt.SCHED_SPATIAL}[args.schedule]
-    opts = dict(schedule=sched, group=args.group, trace_lanes=args.trace_lanes)
-    scheme = {"feautrier2": rt.SCHEME_FEAUTRIER2, "hermite": rt.SCHEME_HERMITE}[args.scheme]
-    tuned = None
-    if not args.no_autotune:
-        _log("autotuning (schedule, sweep load group, walk lanes, persistent grid) ...")
-        t0 = time.perf_counter()
-        opts, tuned_ms = rt.autotune(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P,
-                                     precision=rt.RT_F32, n_runs=2,
-                                     verbose=True, dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme)
-        tuned = dict(opts, ms_per_step=tuned_ms, seconds=time.perf_counter() - t0)
-        _log(f"autotuner chose {opts} ({tuned_ms:.2f} ms/step) in {tuned['seconds']:.1f} s")
-    _log("planning (count pass, buffers, graph capture) ...")
-    plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P, precision=rt.RT_F32,
-                   dtau_max=args.dtau_max, dv_max=args.dv_max, scheme=scheme,
-                   walk={"exact": rt.WALK_EXACT, "padded": rt.WALK_PADDED, "two-pass": rt.WALK_TWO_PASS}[args.walk],
-                   **opts)
-    total = plan.info()["total"]
-
-    for _ in range(args.warmup):
-        plan.run(use_graph=True)
-    rt.sync_status()
-    _log(f"warm-up done ({args.warmup} steps); timing {args.steps} graph replays ...")
-
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.run(use_graph=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rt.sync_status()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    solves = m.P * R * Fw
-    value = solves / (ms_step * 1e-3)
-    _log(f"step {ms_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall)")
-
-    # per-stage times from HIP events on the same stream, eager launches
-    stages = plan.profile(max(3, min(args.steps, 10)))
-    _log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
-    nfc = (Fw + 63) // 64
-    alg = sweep_bytes(m.P, R, total, Fw, moving=m.vel is not None)
-    achieved = alg / (stages["sweep"] * 1e-3) / 1e9
-    khash = src_hash("solve.hip", "rt_internal.h")
-    traffic = load_traffic(khash, alg) if args.workload == "wind" and nside == NSIDE else None
-
-    rec = {
-        "metric": "point-ray-freq solves/s (one solve = one origin x antipodal ray pair x frequency)",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 sweep, f64 geometry",
-        "data": "synthetic (seeded analytic wind)",
-        "config": {
-            "workload": f"{desc}; nside {nside} ({R} pairs), F={Fw}, FP32 sweep",
-            "points": m.P, "pairs_per_point": R, "freqs": Fw, "ray_list_entries": total,
-            "mean_line_length": (total + m.P * R) / (m.P * R), "plan_options": opts, "walk": args.walk,
-            "dtau_max": args.dtau_max, "dv_max": args.dv_max, "scheme": args.scheme, "autotune": tuned,
-            "frequency_chunks_per_pair": nfc,
-        },
-        "roofline": {
-            "kernel": "feautrier sweep",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "alg_bytes_per_launch": alg,
-            "sweep_ms": stages["sweep"],
-            "traffic_gbs": traffic / (stages["sweep"] * 1e-3) / 1e9 if traffic else None,
-            "copy_ceiling_gbs": copy_ceiling_gbs(dev),
-        },
-        "stages_ms": stages,
-        "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms_step * 1e-3),
-    }
-    if args.cpu_sample > 0:
+        rec, models, ds = run_plan_workload(args, rt, torch, dev)
+        per_model = (25_000 if args.workload == "wind" else 3000) if args.cpu_sample < 0 else args.cpu_sample
+    if not args.no_extra and args.workload == "sph_batch":
+        _log("extra numbers: the 50k wind at nside 4 ...")
+        rec["other_workloads"] = {"wind50k_nside4": _other_wind(rt, torch, dev)}
+    if per_model > 0:
         from oracle import dirset_uniform
-        _, dirs, w2 = dirset_uniform(nside)
-        if args.workload != "wind" and args.cpu_sample == ap.get_default("cpu_sample"):
-            args.cpu_sample = 3000  # longer lines and more frequencies: keep the CPU leg to tens of seconds
-        _log(f"timing the CPU oracle on {args.cpu_sample} origins ...")
-        rec["cpu_baseline"] = cpu_baseline(m, dirs, w2, args.cpu_sample)
+        _, dirs, w2 = dirset_uniform(int(round(np.sqrt(ds.R / 6))))
+        rng = np.random.default_rng(7)
+        parts = [(m, np.sort(rng.choice(m.P, min(per_model, m.P), replace=False)).astype(np.int32))
+                 for m in models]
+        what = (f"{per_model} seeded origins of each of the {len(models)} models" if len(models) > 1
+                else f"{per_model} seeded origins of the model")
+        _log(f"timing the CPU oracle ({what}) ...")
+        rec["cpu_baseline"] = cpu_baseline(parts, dirs, w2, what)
     print(json.dumps(rec), flush=True)
 
 

@@ -414,7 +414,9 @@ rt_status rt_autotune_plan(rt_plan* plan, int32_t n_runs, int32_t verbose, void*
  * rt_batch_create: models[n_models] (handles on the current device), one
  * uniform direction set for all, chi[k]/eta[k] device [P_k][ld[k]] of `dtype`,
  * one frequency grid and I_bc for all, J[k] device [P_k][F].  Builds the union
- * and the plan (synchronises, allocates).  rt_batch_run: replay (async;
+ * and the plan, and gathers the tables once (synchronises, allocates); a
+ * replay gathers them again, so changes to the models' tables between runs
+ * are seen.  rt_batch_run: replay (async;
  * use_graph = 0 launches the steps one by one).  rt_batch_plan: the inner plan
  * over the union (for rt_plan_profile, rt_plan_info, rt_plan_retune,
  * rt_autotune_plan); owned by the batch.  rt_batch_union: the union's point

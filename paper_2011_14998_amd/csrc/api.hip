@@ -686,11 +686,18 @@ extern "C" rt_status rt_sync_status(void* stream) {
     int32_t h = 0;
     RT_HIP(hipMemcpy(&h, w, sizeof(int32_t), hipMemcpyDeviceToHost));
     RT_HIP(hipMemset(w, 0, sizeof(int32_t)));
-    if (h & ERRBIT_CAPACITY) return fail(RT_ERR_CAPACITY, "a ray list exceeded its capacity");
+    // the first error in this order is returned; the message lists every latched one
+    std::string all;
+    if (h & ERRBIT_CAPACITY) all += " [ray list capacity]";
+    if (h & ERRBIT_STEP) all += " [fourth-order step limit]";
+    if (h & ERRBIT_NONFINITE) all += " [non-finite u]";
+    if (h & ERRBIT_ORIGIN) all += " [origin id out of range]";
+    if (h & ERRBIT_CAPACITY) return fail(RT_ERR_CAPACITY, "a ray list exceeded its capacity; latched:" + all);
     if (h & ERRBIT_STEP)
-        return fail(RT_ERR_STEP, "a fourth-order row met an optical-depth step beyond its limit (about 3.46)");
-    if (h & ERRBIT_NONFINITE) return fail(RT_ERR_NONFINITE, "the solve produced a non-finite u");
-    if (h & ERRBIT_ORIGIN) return fail(RT_ERR_ARG, "an origin id was outside 0 .. P-1");
+        return fail(RT_ERR_STEP,
+                    "a fourth-order row met an optical-depth step beyond its limit (about 3.46); latched:" + all);
+    if (h & ERRBIT_NONFINITE) return fail(RT_ERR_NONFINITE, "the solve produced a non-finite u; latched:" + all);
+    if (h & ERRBIT_ORIGIN) return fail(RT_ERR_ARG, "an origin id was outside 0 .. P-1; latched:" + all);
     return RT_OK;
 }
 

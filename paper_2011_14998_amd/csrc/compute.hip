@@ -347,8 +347,8 @@ static void batch_free(rt_batch* b) {
     delete b;
 }
 
-// Gather the tables into the union, run the plan's step, scatter J to the models.
-static hipError_t batch_enqueue(rt_batch* b, hipStream_t s) {
+// The models' tables into the union.
+static hipError_t batch_gather(rt_batch* b, hipStream_t s) {
     const dim3 grid(std::min<unsigned>(2048, blocks_of(b->max_P * b->F, 256)), (unsigned)b->n);
     if (b->dtype == RT_F64)
         hipLaunchKernelGGL(k_batch_gather<double>, grid, dim3(256), 0, s, b->segs, b->F, (double*)b->chi_u,
@@ -356,7 +356,13 @@ static hipError_t batch_enqueue(rt_batch* b, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_batch_gather<float>, grid, dim3(256), 0, s, b->segs, b->F, (float*)b->chi_u,
                            (float*)b->eta_u);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+// Gather the tables into the union, run the plan's step, scatter J to the models.
+static hipError_t batch_enqueue(rt_batch* b, hipStream_t s) {
+    const dim3 grid(std::min<unsigned>(2048, blocks_of(b->max_P * b->F, 256)), (unsigned)b->n);
+    hipError_t e = batch_gather(b, s);
     if (e == hipSuccess) e = plan_enqueue_step(b->plan, s);
     if (e != hipSuccess) return e;
     if (b->dtype == RT_F64)
@@ -487,6 +493,15 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
     e = morton_order(b->uni, nullptr, b->P_tot, s, order, b->base_p.data(), n_models);
     if (e != hipSuccess) {
         st = hip_fail(e, "rt_batch_create: origin order");
+        batch_free(b);
+        return st;
+    }
+    // the union's tables hold the models' values from the start, so that the inner plan can be run,
+    // profiled or tuned on its own (rt_batch_plan) before the first rt_batch_run
+    e = batch_gather(b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "rt_batch_create: table gather");
         batch_free(b);
         return st;
     }
