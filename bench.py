@@ -42,11 +42,15 @@ F = 64
 # Plan options per workload: what the autotuner (rt_autotune_plan, `--autotune`) chose on MI355X,
 # kept fixed so that the timed kernel variant is the one the committed counters were taken on.
 TUNED = {
-    "sph_batch": dict(schedule=1, group=8, trace_lanes=8, waves_per_cu=32, n_bins=64, bins_per_octave=4),
+    "sph_batch": dict(schedule=2, group=8, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "wind": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "octree": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "octree_reduced": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
 }
+
+
+SCHEDULE_NAMES = {0: "direct launch in slot order", 1: "length-binned persistent launch",
+                  2: "direct launch direction by direction over Morton-ordered origins, XCD-contiguous"}
 
 
 def _log(msg):
@@ -383,8 +387,8 @@ def run_batch(args, rt, torch, dev):
                    "ray_list_entries": total, "mean_line_length": (total + P_tot * R) / (P_tot * R),
                    "plan_options": opts, "autotune": tuned,
                    "timed_step": "one replay of the batch's HIP graph: table gather into the union, walk of every "
-                                 "ray into its slot (slots from the count pass and scan at creation), "
-                                 "length-binned sweep, J reduction, J scatter to the 64 models"},
+                                 "ray into its slot (slots from the count pass and scan at creation), sweep ("
+                                 + SCHEDULE_NAMES[opts["schedule"]] + "), J reduction, J scatter to the 64 models"},
         "roofline": roof,
         "stages_ms": stages,
         "line_point_freq_updates_per_s": (total + P_tot * R) * F / (ms * 1e-3),
@@ -459,7 +463,8 @@ def run_plan_workload(args, rt, torch, dev):
                    "dtau_max": args.dtau_max, "dv_max": args.dv_max, "scheme": args.scheme, "autotune": tuned,
                    "frequency_chunks_per_pair": (Fw + 63) // 64,
                    "timed_step": "one replay of the plan's HIP graph: walk of every ray into its slot (slots from "
-                                 "the count pass and scan at creation), sweep, J reduction"},
+                                 "the count pass and scan at creation), sweep (" + SCHEDULE_NAMES[opts["schedule"]]
+                                 + "), J reduction"},
         "roofline": _roofline(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages, alg, dev),
         "stages_ms": stages,
         "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms * 1e-3),
@@ -560,7 +565,7 @@ def main():
         return
     if args.workload == "sph_batch":
         rec, models, ds = run_batch(args, rt, torch, dev)
-        per_model = 40 if args.cpu_sample < 0 else args.cpu_sample
+        per_model = 150 if args.cpu_sample < 0 else args.cpu_sample
     else:
         rec, models, ds = run_plan_workload(args, rt, torch, dev)
         per_model = (25_000 if args.workload == "wind" else 3000) if args.cpu_sample < 0 else args.cpu_sample
