@@ -168,6 +168,21 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+class _DevArray:
+    """Library-owned device memory described for torch.as_tensor (zero copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2}
+
+
+def _view(ptr: int, n: int, typestr: str):
+    """A torch tensor aliasing n elements of library-owned device memory at ptr (no copy); valid
+    while the owning handle lives."""
+    torch = _torch()
+    return torch.as_tensor(_DevArray(ptr, max(n, 0), typestr), device="cuda")
+
+
 def _dev(t, dtype):
     torch = _torch()
     assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
@@ -541,7 +556,15 @@ class Batch:
         tot = _i64()
         off, ids, Z = _vp(), _vp(), _vp()
         _check(load().rt_plan_info(self._plan, C.byref(tot), C.byref(off), C.byref(ids), C.byref(Z)))
-        return dict(total=tot.value)
+        return dict(total=tot.value, ray_off=off.value, ray_ids=ids.value, ray_Z=Z.value)
+
+    def rays_view(self):
+        """The union's ray lists (ray_off, ids, Z; origins = every union point in order, ids union
+        point ids) aliasing the inner plan's buffers (no copy; valid while the batch lives)."""
+        inf = self.info()
+        n = self.union()[0] * 2 * self.dirset.R + 1
+        return (_view(inf["ray_off"], n, "<i8"), _view(inf["ray_ids"], inf["total"], "<i4"),
+                _view(inf["ray_Z"], inf["total"], "<f8"))
 
     def autotune(self, n_runs: int = 2, verbose: bool = False, stream=None):
         """Tune the inner plan in place (rt_autotune_plan); returns (options dict, ms per step)."""
@@ -642,6 +665,14 @@ class Plan:
         off, ids, Z = _vp(), _vp(), _vp()
         _check(load().rt_plan_info(self._h, C.byref(tot), C.byref(off), C.byref(ids), C.byref(Z)))
         return dict(total=tot.value, ray_off=off.value, ray_ids=ids.value, ray_Z=Z.value)
+
+    def rays_view(self):
+        """The plan's own ray lists (ray_off, ids, Z) as device tensors aliasing its buffers (no
+        copy; valid while the plan lives)."""
+        inf = self.info()
+        n = self.n_origins * 2 * self.dirset.R + 1
+        return (_view(inf["ray_off"], n, "<i8"), _view(inf["ray_ids"], inf["total"], "<i4"),
+                _view(inf["ray_Z"], inf["total"], "<f8"))
 
     def rays(self, stream=None):
         """Copies of the plan's ray lists (ray_off, ids, Z) as device tensors."""
