@@ -214,6 +214,163 @@ __global__ __launch_bounds__(256, MTW == 4 ? 2 : 1) void k_mlp_fwd(
     }
 }
 
+// ---------------------------------------------------------------- forward, weights held in registers
+//
+// For inference over many samples: a persistent workgroup of 8 waves per CU
+// loads the hidden layers' weights once and keeps them in registers, then
+// streams tiles of 64 samples through all layers with the activations in LDS.
+// Wave w owns the hidden columns [32w, 32w+32) of every layer: its strips of
+// W2 and W3 (32 columns x 256 rows each) are A operands of
+// v_mfma_f32_16x16x32_bf16, lane (r, g) holding row n0 + r, columns
+// 32 ks + 8g .. +7 of Wt.  The activations are the B operands, lane (r, g)
+// reading 16 contiguous bytes of sample m0 + r; the four accumulators of a
+// lane are four consecutive columns of one sample (one 8-byte LDS store).
+// The first layer (K = 16, padded to 32 with zeros) and the head read their
+// weights from LDS.  Rounding points and results are those of k_mlp_fwd (the
+// products are summed 32 at a time instead of 16, so a BF16 rounding of z may
+// fall the other way).
+typedef short v8i16 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int PT = 64;          // samples per tile
+constexpr int PWAVES = 8;       // waves per workgroup
+constexpr int LDP = HW + 8;     // LDS row stride (bf16) of activation tiles
+constexpr int LDXP = 32 + 8;    // LDS row stride of the input tile (K padded to 32)
+constexpr int LDW1 = 32 + 8;    // LDS row stride of W1t (K padded to 32)
+constexpr int64_t WS_MIN_SAMPLES = 65536;  // below this the per-tile kernel (k_mlp_fwd) fills the chip better
+
+__device__ inline v4f32 mfma32(v8i16 a, v8i16 b, v4f32 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+__device__ inline v8i16 ld8(const uint16_t* p) { return *(const v8i16*)p; }  // 16-byte aligned
+
+// bias, BF16 z, SiLU, BF16 h for the lane's 2 x 4 accumulator tiles; h into LDS, z (KEEP) to HBM
+template <bool KEEP>
+__device__ __attribute__((always_inline)) inline void ws_epilogue(const v4f32 (&acc)[2][4], const float* sbias,
+                                                                  uint16_t* out, uint16_t* __restrict__ zout,
+                                                                  int64_t row0, int nvalid, int wv, int g, int r) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int n0 = 32 * wv + 16 * nt + 4 * g;
+        const float4 bb = *(const float4*)(sbias + n0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int m = 16 * mt + r;
+            const uint32_t z01 = f2bf2(acc[nt][mt][0] + bb.x, acc[nt][mt][1] + bb.y);
+            const uint32_t z23 = f2bf2(acc[nt][mt][2] + bb.z, acc[nt][mt][3] + bb.w);
+            const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
+            const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
+            *(uint2*)(out + m * LDP + n0) = make_uint2(h01, h23);
+            if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
+        }
+    }
+}
+
+template <bool KEEP>
+__device__ __attribute__((always_inline)) inline void ws_hidden(const uint16_t* in, const v8i16 (&wr)[2][8],
+                                                                const float* sbias, uint16_t* out,
+                                                                uint16_t* __restrict__ zout, int64_t row0,
+                                                                int nvalid, int wv, int g, int r) {
+    v4f32 acc[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        v8i16 b[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) b[mt] = ld8(in + (16 * mt + r) * LDP + 32 * ks + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma32(wr[nt][ks], b[mt], acc[nt][mt]);
+    }
+    ws_epilogue<KEEP>(acc, sbias, out, zout, row0, nvalid, wv, g, r);
+}
+
+template <bool KEEP>
+__global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restrict__ wt, const float* __restrict__ w,
+                                                       const uint16_t* __restrict__ X,
+                                                       const int32_t* __restrict__ rows, int64_t n,
+                                                       float* __restrict__ Y, uint16_t* __restrict__ Z) {
+    __shared__ __attribute__((aligned(16))) uint16_t sx[PT * LDXP];
+    __shared__ __attribute__((aligned(16))) uint16_t ha[PT * LDP];
+    __shared__ __attribute__((aligned(16))) uint16_t hb[PT * LDP];
+    __shared__ __attribute__((aligned(16))) uint16_t sw1[HW * LDW1];
+    __shared__ __attribute__((aligned(16))) uint16_t sw4[2 * HW];
+    __shared__ __attribute__((aligned(16))) float sbias[3 * HW];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    for (int i = t; i < HW * 32; i += 512) {
+        const int nn = i >> 5, k = i & 31;
+        sw1[nn * LDW1 + k] = k < DIN ? wt[WT1 + nn * DIN + k] : (uint16_t)0;
+    }
+    for (int i = t; i < 2 * HW; i += 512) sw4[i] = wt[WT4 + i];
+    for (int i = t; i < HW; i += 512) {
+        sbias[i] = w[OFF_B1 + i];
+        sbias[HW + i] = w[OFF_B2 + i];
+        sbias[2 * HW + i] = w[OFF_B3 + i];
+    }
+    for (int i = t; i < PT * LDXP; i += 512) sx[i] = 0;  // columns 16..31 stay zero
+    v8i16 w2r[2][8], w3r[2][8];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int64_t o = (int64_t)(32 * wv + 16 * nt + r) * HW + 32 * ks + 8 * g;
+            w2r[nt][ks] = ld8(wt + WT2 + o);
+            w3r[nt][ks] = ld8(wt + WT3 + o);
+        }
+    const float b40 = w[OFF_B4], b41 = w[OFF_B4 + 1];
+    const int64_t tiles = (n + PT - 1) / PT;
+    uint16_t* Z1 = KEEP ? Z : nullptr;
+    uint16_t* Z2 = KEEP ? Z + n * HW : nullptr;
+    uint16_t* Z3 = KEEP ? Z + 2 * n * HW : nullptr;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t row0 = tile * PT;
+        const int nvalid = (int)(n - row0 < PT ? n - row0 : PT);
+        if (t < PT * 4) {  // 64 samples x 16 inputs, 4 per thread
+            const int m = t >> 2, q = t & 3;
+            v4i16 v = (v4i16){0, 0, 0, 0};
+            if (m < nvalid) {
+                const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
+                v = ld4(X + src * DIN + 4 * q);
+            }
+            *(v4i16*)(sx + m * LDXP + 4 * q) = v;
+        }
+        __syncthreads();  // also: the previous tile's head has read ha
+        {  // layer 1: one k-step of 32 (inputs 16..31 and their weights are zero)
+            v4f32 acc[2][4];
+            v8i16 a[2], b[4];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) a[nt] = ld8(sw1 + (32 * wv + 16 * nt + r) * LDW1 + 8 * g);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) b[mt] = ld8(sx + (16 * mt + r) * LDXP + 8 * g);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma32(a[nt], b[mt], (v4f32){0.f, 0.f, 0.f, 0.f});
+            ws_epilogue<KEEP>(acc, sbias, ha, Z1, row0, nvalid, wv, g, r);
+        }
+        __syncthreads();
+        ws_hidden<KEEP>(ha, w2r, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        __syncthreads();
+        ws_hidden<KEEP>(hb, w3r, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        __syncthreads();
+        if (wv < 4) {  // head: wave wv takes samples 16 wv .. 16 wv + 15; A = W4t rows 0, 1 (others zero)
+            v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const v8i16 a = r < 2 ? ld8(sw4 + r * HW + 32 * ks + 8 * g) : (v8i16){0, 0, 0, 0, 0, 0, 0, 0};
+                acc = mfma32(a, ld8(ha + (16 * wv + r) * LDP + 32 * ks + 8 * g), acc);
+            }
+            const int m = 16 * wv + r;
+            if (g == 0 && m < nvalid) *(float2*)(Y + (row0 + m) * DOUT) = make_float2(acc[0] + b40, acc[1] + b41);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- backward
 
 // part[wofs + j*Ncols + n] = sum over the 64 samples of H[m][j] dZ[m][n]:
@@ -756,6 +913,18 @@ extern "C" rt_status rt_mlp_forward(rt_mlp* h, const uint16_t* X, const int32_t*
     if (n == 0) return RT_OK;
     if (keep && (!ws || ws_bytes < ws_bytes_for(n))) return fail(RT_ERR_CAPACITY, "rt_mlp_forward: workspace too small");
     hipStream_t s = (hipStream_t)stream;
+    if (n >= WS_MIN_SAMPLES) {  // many samples: persistent workgroups with the weights in registers
+        const int64_t tiles = (n + PT - 1) / PT;
+        const unsigned grid = (unsigned)std::min<int64_t>(tiles, num_cus());
+        if (keep)
+            hipLaunchKernelGGL(k_mlp_fwd_ws<true>, dim3(grid), dim3(64 * PWAVES), 0, s, h->wt, h->w, X, rows, n, Y,
+                               (uint16_t*)ws);
+        else
+            hipLaunchKernelGGL(k_mlp_fwd_ws<false>, dim3(grid), dim3(64 * PWAVES), 0, s, h->wt, h->w, X, rows, n, Y,
+                               nullptr);
+        RT_HIP(hipGetLastError());
+        return RT_OK;
+    }
     // small batches (training) in 64-sample tiles to fill the chip, large ones in 128
     if (n < (int64_t)num_cus() * 256) {
         if (keep)

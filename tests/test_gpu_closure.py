@@ -88,6 +88,39 @@ def test_mlp_forward(rt, n, use_rows):
     assert np.array_equal(Yk.astype(np.float64), Y)
 
 
+@pytest.mark.parametrize("use_rows", [False, True])
+def test_mlp_forward_many_samples(rt, use_rows):
+    """Above 65 536 samples the forward runs persistent workgroups that keep the hidden
+    weights in registers (16x16x32 matrix-core products): the same bars against the oracle,
+    a ragged last tile, keep=True bit-identical to keep=False, and every stored
+    pre-activation the oracle's (same rounding points) up to a few BF16 rounding flips."""
+    torch = _torch()
+    flat = _params(11)
+    net = rt.MLP(seed=0)
+    net.set_params(flat)
+    n = 70_001
+    X = _inputs(12, 80_000 if use_rows else n)
+    Xb = _bf16_bits(X)
+    rows = np.random.default_rng(13).integers(0, len(X), n).astype(np.int32) if use_rows else None
+    Y = net.forward(_t(Xb), rows=None if rows is None else _t(rows)).cpu().numpy().astype(np.float64)
+    Xo = oc.bf16_round(X)[rows if use_rows else slice(None)]
+    onet = _oracle_net(flat, oc.bf16_round)
+    y_m, _ = onet.forward(Xo)
+    y_e, _ = _oracle_net(flat, None).forward(Xo)
+    print(f"forward n={n}: rel vs mirrored {_relF(Y, y_m):.2e}, vs unrounded {_relF(Y, y_e):.2e}")
+    assert _relF(Y, y_m) <= 5e-4
+    assert _relF(Y, y_e) <= 2e-2
+    ws = net.workspace(n)
+    Yk = net.forward(_t(Xb), rows=None if rows is None else _t(rows), keep=True).cpu().numpy()
+    assert np.array_equal(Yk.astype(np.float64), Y)
+    # the stored z of the first hidden layer: BF16 values of the oracle's pre-activations
+    z1 = ws[: n * 256 * 2].view(torch.int16).cpu().numpy().reshape(n, 256)
+    z1 = (z1.astype(np.int32).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    W1 = oc.bf16_round(flat[:16 * 256].astype(np.float64).reshape(16, 256))
+    z_ref = oc.bf16_round(Xo @ W1 + flat[16 * 256:16 * 256 + 256].astype(np.float64))
+    assert np.mean(z1 != z_ref) < 1e-3
+
+
 def test_mlp_params_roundtrip(rt):
     flat = _params(4)
     net = rt.MLP(seed=0)
