@@ -4,17 +4,15 @@ sweep and on refined lines; a step beyond the rows' limit latches RT_ERR_STEP
 (and the oracle refuses the same line); a uniform source equal to the incident
 intensity is reproduced.
 
-Tolerances.  FP32: 1e-4, FP64: 1e-12 relative, or more where the rows
-themselves are that ill-conditioned: between very unequal steps a Hermitian
-weight grows like the step ratio (1e3 and more on unstructured lines), so the
-FP64 answer moves by up to ~1e-12 when the tables move by two ulps, three
-orders of magnitude more than the second-order rows' answer does.  The test
-measures that on the oracle (its own u under a seeded 2-ulp perturbation of
-chi and eta) and allows 4 times it: two correct FP64 evaluations that round
-their sub-point optics and steps differently differ by that much.  FP32 the
-same with a perturbation of FP32 size (the kernel's steps, weights and
-Doppler-interpolated optics are FP32): on lines with step ratios near 1e3 the
-FP32 answer of these rows is only defined to ~1e-3."""
+Tolerances.  J, the quantity the method returns: 1e-12 (FP64) and 1e-4 (FP32)
+relative, the bars of the second-order path.  The per-pair u (FP64) may also
+differ by up to 4 times the oracle's own rounding sensitivity where that is
+larger: between very unequal steps a Hermitian weight grows like the step
+ratio (1e3 and more on unstructured lines), so a single pair's answer moves by
+up to ~1e-12 when the tables move by two ulps, three orders of magnitude more
+than the second-order rows' answer does.  The test measures that on the oracle
+(its own u under a seeded 2-ulp perturbation of chi and eta) and prints it,
+with the same measurement at FP32 size for the record."""
 import numpy as np
 import pytest
 
@@ -129,14 +127,16 @@ def test_hermite_parity_fp64_fp32(rt, orc, name):
     rt.sync_status()
     e_u, e_J = _rel(u64.cpu().numpy(), ue), _rel(J64.cpu().numpy(), Je)
     print(f"{name}: fp64 max rel u {e_u:.2e}, J {e_J:.2e}", flush=True)
+    # per-pair u to the oracle's own rounding sensitivity (the rows are that ill-conditioned on some
+    # lines); J, the weighted sum over pairs, to the fixed bars of the second-order path
     assert e_u <= tol64
-    assert e_J <= tol64
-    tol32 = _tol32(orc, m, dirs, w2, oo, c64, e64, kw, ue)
+    assert e_J <= TOL64
+    _tol32(orc, m, dirs, w2, oo, c64, e64, kw, ue)  # printed for the record
     J32 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F32, c32, e32, scheme=rt.SCHEME_HERMITE, **kw)
     rt.sync_status()
     err = _rel(J32.cpu().numpy().astype(np.float64), Je)
     print(f"{name}: fp32 max rel {err:.2e}", flush=True)
-    assert err <= tol32
+    assert err <= TOL32
 
 
 def test_hermite_wind_sample(rt, orc):
@@ -149,14 +149,14 @@ def test_hermite_wind_sample(rt, orc):
     model, ds, dirs, w2, oo, org, rays = _setup(rt, orc, m, 2, origins)
     kw = dict(dv_max=1.0 / 3.0, dtau_max=0.5)
     Je, ue = orc.compute_J(m, dirs, w2, origins=oo, chi=c64, eta=e64, want_u=True, scheme=HERM, **kw)
-    tol64 = _tol64(orc, m, dirs, w2, oo, c64, e64, kw, ue)
+    _tol64(orc, m, dirs, w2, oo, c64, e64, kw, ue)  # printed for the record
     J64 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F64, c64, e64, scheme=rt.SCHEME_HERMITE, **kw)
     print(f"wind: fp64 max rel J {_rel(J64.cpu().numpy(), Je):.2e}", flush=True)
-    assert _rel(J64.cpu().numpy(), Je) <= tol64
-    tol32 = _tol32(orc, m, dirs, w2, oo, c64, e64, kw, ue)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    _tol32(orc, m, dirs, w2, oo, c64, e64, kw, ue)
     J32 = _gpu(rt, m, model, ds, rays, org, len(oo), rt.RT_F32, c32, e32, scheme=rt.SCHEME_HERMITE, **kw)
     print(f"wind: fp32 max rel J {_rel(J32.cpu().numpy().astype(np.float64), Je):.2e}", flush=True)
-    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= tol32
+    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
     rt.sync_status()
 
 

@@ -205,7 +205,8 @@ def test_J_wind_fp64_and_fp32(rt, orc, wind, nside):
 
 
 def test_fp32_error_on_optically_thin_and_thick_lines(rt, orc):
-    # dtau spanning 1e-7 .. 1e3: the FP64 coefficient rows keep the FP32 sweep within 1e-4
+    # dtau spanning 1e-7 .. 1e3: with the rows carried per unit inner step every coefficient is its
+    # FP64 value rounded once, which keeps the FP32 sweep within 1e-4 without an FP64 branch
     m = synth.tiny_model(9, P=60, F=16, moving=True)
     rng = np.random.default_rng(1)
     scale = 10.0 ** rng.uniform(-6, 3, (m.P, 1))
