@@ -789,6 +789,7 @@ def run_closure(args):
         del lab, dm
         torch.cuda.empty_cache()
     # headline: per target fallback fraction, error and time over the test models
+    curves = [r.get("fallback_for_target") for r in results]
     summary = []
     for i, q in enumerate(fractions):
         runs = [r["closure"][i] for r in results]
@@ -817,6 +818,7 @@ def run_closure(args):
                    "points": P, "train_models": len(seeds_train), "test_models": len(seeds_test),
                    "steps": args.closure_steps, "batch": args.closure_batch, "lr": args.closure_lr},
         "headline": head, "fallback_sweep": summary, "per_model": results,
+        "fallback_needed_for_1e-3": curves,
         "training": {"loss_history": net.history, "train_s": train_s, "label_s": label_s, "generate_s": gen_s},
     }
     print(json.dumps(rec), flush=True)

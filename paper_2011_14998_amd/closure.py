@@ -270,6 +270,7 @@ def evaluate(net: ClosureNet, lab: Labelled, coarse_set, fine_set, flag_fraction
     sd = predicted_sd(net, dm, lab.coarse)
     out["predicted_sd_quantiles"] = {str(q): float(np.quantile(sd, q)) for q in (0.1, 0.25, 0.5, 0.75, 0.9)}
     runs = []
+    e_net = None  # per (point, frequency) errors of the network alone (no fallback)
     for q in flag_fractions:
         if q <= 0:
             b = math.inf
@@ -283,6 +284,8 @@ def evaluate(net: ClosureNet, lab: Labelled, coarse_set, fine_set, flag_fraction
         e = error_summary(res.J, lab.fine.J, mask, F)
         e.update(target_fraction=q, bound=b, n_flagged=res.n_flagged, total_ms=res.total_ms,
                  speedup_vs_plain=lab.fine.ms / res.total_ms if res.total_ms > 0 else None)
+        if res.n_flagged == 0 and e_net is None:
+            e_net = rel_errors(res.J, lab.fine.J).reshape(dm.P, F)
         runs.append(e)
         if verbose:
             print(f"  [{dm.name}] fallback {e['flagged_fraction']:.3f} (bound {b:.3g}): median "
@@ -290,4 +293,36 @@ def evaluate(net: ClosureNet, lab: Labelled, coarse_set, fine_set, flag_fraction
                   f"vs plain {lab.fine.ms:.0f} ms", flush=True)
         del res
     out["closure"] = runs
+    if e_net is not None:
+        out["fallback_for_target"] = fallback_curve(e_net, sd, runs, lab.fine.ms)
     return out
+
+
+def fallback_curve(e_net, sd, runs, plain_ms, target: float = 1e-3) -> dict:
+    """The smallest fallback fraction at which the median relative error over every (point,
+    frequency) reaches `target`.  A fallen-back point carries the plain fine solve's J exactly
+    (error 0, bit for bit), the others the network's, and points fall back in decreasing order
+    of predicted deviation, so the median at fraction q follows from the network-only errors
+    and the predictions without running the fallback at every q.  The time at that fraction is
+    interpolated linearly between the measured closure runs."""
+    P, F = e_net.shape
+    order = np.argsort(-sd, kind="stable")
+    qs = np.linspace(0.0, 1.0, 201)
+    med, med_unflagged = [], []
+    for q in qs:
+        k = int(round(q * P))
+        e = e_net.copy()
+        e[order[:k]] = 0.0
+        med.append(float(np.median(e)))
+        rest = e_net[order[k:]]
+        med_unflagged.append(float(np.median(rest)) if rest.size else 0.0)
+    med = np.array(med)
+    hit = np.nonzero(med <= target)[0]
+    q_star = float(qs[hit[0]]) if hit.size else None
+    pts = sorted((r["flagged_fraction"], r["total_ms"]) for r in runs)
+    t_star = float(np.interp(q_star, [p for p, _ in pts], [t for _, t in pts])) if q_star is not None else None
+    return dict(target=target, fraction=q_star,
+                median_unflagged_at_fraction=med_unflagged[int(hit[0])] if hit.size else None,
+                closure_ms_interpolated=t_star, plain_ms=plain_ms,
+                speedup_vs_plain=plain_ms / t_star if t_star else None,
+                curve={f"{q:.2f}": m for q, m in zip(qs[::10], med[::10])})
