@@ -157,6 +157,17 @@ rt_status rt_trace_write(const rt_model* model, const rt_dirset* set, const int3
                          int64_t n_origins, const int64_t* ray_off, int32_t* ray_ids, double* ray_Z,
                          int64_t capacity, void* stream);
 
+/* Count, scan and write in one call: ray_off (device int64 [n_rays + 1]) gets
+ * the offsets, ray_ids / ray_Z (device, `capacity` entries each) the lists, and
+ * total_dev (device int64 [1]) the total number of entries -- written even when
+ * it exceeds `capacity`, in which case the rays past it are truncated and
+ * RT_ERR_CAPACITY is latched for rt_sync_status() (call again with a larger
+ * capacity: the lists are deterministic).  ws: rt_trace_count_workspace()
+ * bytes.  Async; allocates nothing. */
+rt_status rt_trace(const rt_model* model, const rt_dirset* set, const int32_t* origins, int64_t n_origins,
+                   int64_t* ray_off, int32_t* ray_ids, double* ray_Z, int64_t capacity, int64_t* total_dev,
+                   void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ solve
  * Frequency grid: n_blocks blocks, block b holding len[b] consecutive
  * frequencies uniformly spaced by dx[b] Doppler widths (host arrays).

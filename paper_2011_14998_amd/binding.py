@@ -59,6 +59,7 @@ _SIGS = {
     "rt_trace_count_workspace": (_i32, [_vp, _i64, C.POINTER(_sz)]),
     "rt_trace_count": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "rt_trace_write": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp]),
+    "rt_trace": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "rt_solve_workspace": (_i32, [_vp, _i64, _i64, C.POINTER(SolveOptsC), C.POINTER(_sz)]),
     "rt_solve": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _i64, C.POINTER(FreqGridC),
                         _vp, _vp, _vp, C.POINTER(SolveOptsC), _vp, _sz, _vp]),
@@ -351,6 +352,29 @@ def trace(model: Model, dirset: DirSet, origins=None, n_origins=None, stream=Non
                             total, s))
     sync_status(stream)
     return ray_off, ids[:total], Z[:total]
+
+
+def trace_once(model: Model, dirset: DirSet, capacity: int, origins=None, n_origins=None, stream=None):
+    """rt_trace: count, scan and write in one call into lists of `capacity` entries; returns
+    (ray_off, ids, Z, total) with total read back (the lists are complete when total <= capacity)."""
+    torch = _torch()
+    L = load()
+    if origins is not None:
+        origins = _dev(origins, torch.int32)
+        n_origins = origins.numel()
+    elif n_origins is None:
+        n_origins = model.P
+    dev = model.pos.device
+    wsb = _sz()
+    _check(L.rt_trace_count_workspace(dirset._h, n_origins, C.byref(wsb)))
+    ws = torch.empty(max(1, wsb.value), dtype=torch.uint8, device=dev)
+    ray_off = torch.empty(n_origins * 2 * dirset.R + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    Z = torch.empty(max(capacity, 1), dtype=torch.float64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(L.rt_trace(model._h, dirset._h, _ptr(origins), n_origins, _ptr(ray_off), _ptr(ids), _ptr(Z), capacity,
+                      _ptr(total), _ptr(ws), wsb.value, _stream(stream)))
+    return ray_off, ids, Z, int(total.item())
 
 
 def _grid(freq_len: Sequence[int], freq_dx: Sequence[float], freq_x0: Sequence[float] = None):

@@ -437,6 +437,30 @@ extern "C" rt_status rt_trace_write(const rt_model* m, const rt_dirset* set_, co
     return RT_OK;
 }
 
+extern "C" rt_status rt_trace(const rt_model* m, const rt_dirset* set_, const int32_t* origins, int64_t n_origins,
+                              int64_t* ray_off, int32_t* ray_ids, double* ray_Z, int64_t capacity, int64_t* total_dev,
+                              void* ws, size_t ws_bytes, void* stream) {
+    rt_dirset* set = const_cast<rt_dirset*>(set_);
+    rt_status st = check_trace_args(m, set, n_origins, "rt_trace");
+    if (st) return st;
+    if (!ray_off || !total_dev || capacity < 0 || (capacity > 0 && (!ray_ids || !ray_Z)))
+        return fail(RT_ERR_ARG, "rt_trace: NULL output or negative capacity");
+    size_t need = 0;
+    rt_trace_count_workspace(set, n_origins, &need);
+    if (!ws || ws_bytes < need) return fail(RT_ERR_CAPACITY, "rt_trace: workspace too small");
+    if (!error_word()) return fail(RT_ERR_HIP, "rt_trace: no device error word");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = n_origins * 2 * set->R;
+    int32_t* lens = (int32_t*)ws;
+    void* scan_ws = (char*)ws + align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    RT_HIP(launch_trace_count(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, lens, s));
+    RT_HIP(launch_scan(lens, n, ray_off, scan_ws, s));
+    RT_HIP(hipMemcpyAsync(total_dev, ray_off + n, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    RT_HIP(launch_trace_write(m, origins, n_origins, set->R, set->d_dirs(), set->n_origins > 0, ray_off, ray_ids,
+                              ray_Z, capacity, s));
+    return RT_OK;
+}
+
 // ------------------------------------------------------------------ solve
 
 rt_solve_opts rt::default_solve_opts() {

@@ -139,6 +139,27 @@ def test_compute_J_adaptive_set(rt, orc):
     assert _rel(J.cpu().numpy(), Je) <= TOL64
 
 
+def test_trace_in_one_call(rt, wind):
+    """rt_trace (count, scan, write in one call) gives the two-call lists bit for bit; with too
+    little capacity it still reports the total, truncates, and latches RT_ERR_CAPACITY."""
+    torch = _torch()
+    model = _gpu_model(rt, wind)
+    ds = rt.DirSet.uniform(2)
+    org = _t(np.arange(0, wind.P, 7).astype(np.int32))
+    off, ids, Z = rt.trace(model, ds, origins=org)
+    total = int(off[-1].item())
+    off1, ids1, Z1, t1 = rt.trace_once(model, ds, total, origins=org)
+    rt.sync_status()
+    assert t1 == total
+    assert torch.equal(off1, off) and torch.equal(ids1[:total], ids) and torch.equal(Z1[:total], Z)
+    _, ids2, _, t2 = rt.trace_once(model, ds, total // 2, origins=org)
+    assert t2 == total
+    with pytest.raises(rt.RtError) as e:
+        rt.sync_status()
+    assert e.value.code == -4
+    rt.sync_status()  # cleared
+
+
 def test_compute_J_workspace_too_small(rt, wind):
     torch = _torch()
     model = _gpu_model(rt, wind)
