@@ -480,7 +480,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["sph_batch", "wind", "octree", "octree_reduced", "closure", "precision",
-                                           "directions"],
+                                           "directions", "mlp"],
                     default="sph_batch",
                     help="sph_batch: 64 SPH-like clouds in one batch (default, --batch-scale 1: 4.1M particles); "
                          "wind: the 50k-point wind at nside 4; octree: ~500k-leaf AMR-like cloud, 2x48 "
@@ -563,6 +563,9 @@ def main():
     if args.workload == "directions":
         run_directions(args)
         return
+    if args.workload == "mlp":
+        run_mlp(args)
+        return
     if args.workload == "sph_batch":
         rec, models, ds = run_batch(args, rt, torch, dev)
         per_model = 150 if args.cpu_sample < 0 else args.cpu_sample
@@ -582,6 +585,74 @@ def main():
                 else f"{per_model} seeded origins of the model")
         _log(f"timing the CPU oracle ({what}) ...")
         rec["cpu_baseline"] = cpu_baseline(parts, dirs, w2, what)
+    print(json.dumps(rec), flush=True)
+
+
+# multiply-adds per sample of the closure network (16 -> 256 -> 256 -> 256 -> 2), as FLOPs
+MLP_FWD_FLOP = 2 * (16 * 256 + 2 * 256 * 256 + 256 * 2)
+# backward: the two hidden products of the signal pass (dZ W^T for W3, W2) and the weight
+# gradients of W1..W3 (H^T dZ); the head and elementwise work are not counted
+MLP_BWD_FLOP = 2 * (2 * 256 * 256) + 2 * (16 * 256 + 2 * 256 * 256)
+
+
+def run_mlp(args):
+    """The closure network alone: inference over 6.4M samples (100 000 points x 64 frequencies),
+    the backward at the training batch, and whole training steps replayed from one captured
+    graph (rt_mlp_train); HIP-event times, FLOPs of the matrix products, one JSON line."""
+    import torch
+
+    import paper_2011_14998_amd as rt
+
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    N, n_inf, batch = 1_000_000, 6_400_000, args.closure_batch
+    X = torch.randn((N, 16), generator=g, device=dev).to(torch.bfloat16).view(torch.int16)
+    T = torch.randn(N, generator=g, device=dev)
+    rows_inf = torch.randint(0, N, (n_inf,), generator=g, device=dev, dtype=torch.int32)
+    net = rt.MLP(seed=1)
+    Y = torch.empty((n_inf, 2), dtype=torch.float32, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(args.steps, 5)
+    t_inf = timed(lambda: net.forward(X, rows=rows_inf, Y=Y), reps)
+    rows = torch.randint(0, N, (batch,), generator=g, device=dev, dtype=torch.int32)
+    Yb = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    net.forward(X, rows=rows, Y=Yb, keep=True)
+    dY = rt.mlp_nll(Yb, T, rows=rows)
+    t_fwd_keep = timed(lambda: net.forward(X, rows=rows, Y=Yb, keep=True), reps)
+    net.forward(X, rows=rows, Y=Yb, keep=True)
+    t_bwd = timed(lambda: net.backward(X, dY, rows=rows), reps)
+    steps = 1000
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    kw = dict(batch=batch, total_steps=steps * 10, lr=1e-3, lr_final=1e-5, loss_sum=loss)
+    t_step = timed(lambda: net.train(X, T, steps, **kw), 2) / steps
+    rec = {
+        "metric": "closure network: inference and training rates on the matrix cores",
+        "value": MLP_FWD_FLOP * n_inf / (t_inf * 1e-3) / 1e12,
+        "unit": "TFLOP/s (inference, BF16 MFMA, FP32 accumulate)",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t_inf, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic (random inputs and weights)",
+        "config": {"workload": f"MLP 16-256-256-256-2, inference over {n_inf} samples, training batch {batch}"},
+        "inference": {"samples": n_inf, "ms": t_inf, "tflops": MLP_FWD_FLOP * n_inf / (t_inf * 1e-3) / 1e12,
+                      "frac_of_2.5PF": MLP_FWD_FLOP * n_inf / (t_inf * 1e-3) / 2.5e15},
+        "forward_keep": {"samples": batch, "ms": t_fwd_keep,
+                         "tflops": MLP_FWD_FLOP * batch / (t_fwd_keep * 1e-3) / 1e12},
+        "backward": {"samples": batch, "ms": t_bwd, "tflops": MLP_BWD_FLOP * batch / (t_bwd * 1e-3) / 1e12,
+                     "frac_of_2.5PF": MLP_BWD_FLOP * batch / (t_bwd * 1e-3) / 2.5e15},
+        "train_step_graph": {"samples": batch, "ms": t_step, "steps_timed": 2 * steps,
+                             "tflops": (MLP_FWD_FLOP + MLP_BWD_FLOP) * batch / (t_step * 1e-3) / 1e12},
+    }
     print(json.dumps(rec), flush=True)
 
 

@@ -482,7 +482,10 @@ rt_status rt_mlp_set_params(rt_mlp* mlp, const float* host, void* stream);
 rt_status rt_mlp_get_grads(const rt_mlp* mlp, float* host, void* stream);
 rt_status rt_mlp_zero_grad(rt_mlp* mlp, void* stream); /* async */
 /* Workspace bytes for n samples: 0 for inference, else the stored
- * pre-activations (3*n*256 BF16) plus per-64-sample-tile gradient partials. */
+ * pre-activations (3*n*256 BF16) plus the backward's transposed signals and
+ * activations (5*256 + 16 rows of n rounded up to 32, BF16) and its FP32
+ * partial sums (at most 64 chunks of the W1..W3 gradients, one row of the
+ * small gradients per signal-pass workgroup). */
 rt_status rt_mlp_workspace(int64_t n, int32_t training, size_t* bytes);
 /* Y[i][2] (device f32) = network(X[rows[i]]) for i < n; X device BF16 [*][16]
  * (bit patterns as uint16), rows device int32 or NULL (identity).  keep != 0
@@ -491,7 +494,8 @@ rt_status rt_mlp_forward(rt_mlp* mlp, const uint16_t* X, const int32_t* rows, in
                          void* ws, size_t ws_bytes, void* stream);
 /* Adds to the gradients d(sum_i dY[i] . Y[i])/d(params) for the samples of the
  * last keep-forward with the same X, rows, n and ws (dY device f32 [n][2]).
- * The per-tile partials are summed in tile order (deterministic).  Async. */
+ * Partial sums are added in a fixed order: the result is deterministic for a
+ * given n on a given device.  Async. */
 rt_status rt_mlp_backward(rt_mlp* mlp, const uint16_t* X, const int32_t* rows, int64_t n, const float* dY,
                           void* ws, size_t ws_bytes, void* stream);
 /* Mean Gaussian negative log-likelihood over n samples, per sample
@@ -504,6 +508,36 @@ rt_status rt_mlp_nll(const float* Y, const float* T, const int32_t* rows, int64_
  * decoupled weight decay wd: w -= lr (m_hat / (sqrt(v_hat) + eps) + wd w)),
  * then the BF16 copies are refreshed.  Gradients are left as they are.  Async. */
 rt_status rt_mlp_adam_step(rt_mlp* mlp, float lr, float b1, float b2, float eps, float wd, void* stream);
+/* Training schedule of rt_mlp_train.  Step k (the network's k-th Adam step,
+ * counted from 0 over its lifetime) draws its batch rows i < batch as
+ * splitmix64(seed + (k * batch + i + 1) * 0x9E3779B97F4A7C15) mod N (the
+ * SplitMix64 finaliser of Steele, Lea and Flood, 2014), and uses the learning
+ * rate lr_final + (lr - lr_final) (1 + cos(pi min(k, total_steps) / total_steps)) / 2. */
+typedef struct rt_train_opts {
+    int64_t batch;       /* samples per step, 1 .. 2^31 - 1 */
+    int64_t total_steps; /* length of the cosine schedule, >= 1 */
+    float lr, lr_final;
+    float b1, b2, eps, wd; /* Adam, as rt_mlp_adam_step */
+    uint64_t seed;
+} rt_train_opts;
+/* Workspace bytes of rt_mlp_train for the given batch. */
+rt_status rt_mlp_train_workspace(int64_t batch, size_t* bytes);
+/* n_steps training steps on the samples X (device BF16 [N][16]) with targets T
+ * (device f32 [N]): each step draws its rows, runs the keep-forward, the NLL
+ * (rt_mlp_nll; *loss_sum, device f32 or NULL, accumulates the per-sample
+ * losses, the caller zeroes it), clears the gradients, runs the backward and
+ * the Adam step of rt_mlp_adam_step.  One step is captured in a HIP graph and
+ * replayed n_steps times on `stream`; the step counter and the learning rate
+ * are read on the device, so every replay is the step of its own number.  The
+ * same steps taken one call at a time with the same rows and learning rates
+ * give the same parameters up to the rounding of the learning rate, which is
+ * formed here in FP64 from the FP32 lr and lr_final.  The handle keeps the
+ * captured graph and reuses it while X, T, N, opts, loss_sum, ws and ws_bytes
+ * stay the same (so ws must stay allocated until the handle's next call or
+ * its destruction).  Async; RT_ERR_CAPACITY if ws_bytes is below
+ * rt_mlp_train_workspace. */
+rt_status rt_mlp_train(rt_mlp* mlp, const uint16_t* X, const float* T, int64_t N, const rt_train_opts* opts,
+                       int64_t n_steps, float* loss_sum, void* ws, size_t ws_bytes, void* stream);
 /* Features feat[(k*F + f)][16] (device f32) for points p = points[k] (device
  * int32, or NULL for p = k) at frequency f < F: 0 log J1[k][f], 1 log chi,
  * 2 log S (S = eta/chi), 3 and 4 neighbour means of log chi and log S, 5 the

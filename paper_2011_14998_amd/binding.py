@@ -43,6 +43,11 @@ class SolveOptsC(C.Structure):
                 ("max_substeps", _i32), ("dv_max", _dbl), ("scheme", _i32)]
 
 
+class TrainOptsC(C.Structure):
+    _fields_ = [("batch", _i64), ("total_steps", _i64), ("lr", C.c_float), ("lr_final", C.c_float),
+                ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float), ("wd", C.c_float), ("seed", C.c_uint64)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "rt_last_error": (C.c_char_p, []),
@@ -108,6 +113,8 @@ _SIGS = {
     "rt_mlp_backward": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "rt_mlp_nll": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "rt_mlp_adam_step": (_i32, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "rt_mlp_train_workspace": (_i32, [_i64, C.POINTER(_sz)]),
+    "rt_mlp_train": (_i32, [_vp, _vp, _vp, _i64, C.POINTER(TrainOptsC), _i64, _vp, _vp, _sz, _vp]),
     "rt_closure_features": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rt_plan_copy_u": (_i32, [_vp, _vp, _vp]),
     "rt_spatial_order": (_i32, [_vp, _vp, _i64, _vp, _vp]),
@@ -796,6 +803,24 @@ class MLP:
     def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, wd: float = 0.0,
                   stream=None):
         _check(load().rt_mlp_adam_step(self._h, lr, b1, b2, eps, wd, _stream(stream)))
+
+    def train(self, X, T, n_steps: int, batch: int, total_steps: int, lr: float, lr_final: float = 0.0,
+              b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, wd: float = 0.0, seed: int = 0,
+              loss_sum=None, stream=None):
+        """n_steps graph-replayed training steps (rt_mlp_train) on the samples X [N][16] (BF16 bits)
+        with targets T [N]; rows and the cosine learning rate follow the network's step counter."""
+        torch = _torch()
+        X = _dev(X, torch.int16)
+        T = _dev(T, torch.float32)
+        b = _sz()
+        _check(load().rt_mlp_train_workspace(batch, C.byref(b)))
+        if getattr(self, "_tws", None) is None or self._tws.numel() < b.value:
+            self._tws = torch.empty(b.value, dtype=torch.uint8, device=X.device)
+        o = TrainOptsC(batch=batch, total_steps=total_steps, lr=lr, lr_final=lr_final, b1=b1, b2=b2, eps=eps,
+                       wd=wd, seed=seed)
+        _check(load().rt_mlp_train(self._h, _ptr(X), _ptr(T), X.shape[0], C.byref(o), n_steps,
+                                   _ptr(None if loss_sum is None else _dev(loss_sum, torch.float32)),
+                                   _ptr(self._tws), self._tws.numel(), _stream(stream)))
 
     def set_input_norm(self, mean, inv_std):
         """The inputs' standardisation (host arrays of 16), kept by the handle for closure_J."""

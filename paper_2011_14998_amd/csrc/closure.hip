@@ -15,11 +15,12 @@
 // accumulate in FP32 (MFMA); biases and the head are FP32; the backward signal
 // dz = dh * silu'(z) is rounded to BF16 before it enters the matrix cores.
 //
-// Tiles: one workgroup (4 waves) takes 64 samples.  Forward: each wave owns 64
-// of the 256 output columns, 4x4 tiles of v_mfma_f32_16x16x16_bf16, activations
-// stay in LDS between layers.  Backward: weight gradients are formed per tile
-// (H^T dZ on the matrix cores) into a per-tile partial buffer and summed by a
-// separate pass in tile order (deterministic).
+// Tiles: forward, one workgroup (4 waves) takes 64 or 128 samples, each wave
+// owning 64 of the 256 output columns (v_mfma_f32_16x16x16_bf16), activations
+// kept in LDS between layers; for many samples a persistent kernel holds the
+// hidden weights in registers (v_mfma_f32_16x16x32_bf16).  Backward: a signal
+// pass per 32-sample tile and a split-K weight pass over sample chunks, both on
+// v_mfma_f32_16x16x32_bf16, then an ordered sum of the partials (deterministic).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -38,7 +39,6 @@ typedef float v4f32 __attribute__((ext_vector_type(4)));
 constexpr int DIN = 16;
 constexpr int HW = 256;   // hidden width
 constexpr int DOUT = 2;
-constexpr int MT = 64;    // samples per workgroup
 constexpr int LDH = HW + 8;  // LDS row stride (bf16 elements) of activation tiles
 constexpr int LDX = DIN + 4;
 
@@ -372,203 +372,307 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restric
 }
 
 // ---------------------------------------------------------------- backward
+//
+// Three passes.  The signal pass takes tiles of 32 samples through the layers
+// in reverse: dZ3 from the head, then dZ2 = bf16((dZ3 W3^T) silu'(z2)) and dZ1
+// likewise, the products on v_mfma_f32_16x16x32_bf16 with dZ in LDS (A
+// operand, rows = samples) and the BF16 weights in their [K][N] copy read
+// from L2 (B operand; wave w owns the 64 columns [64w, 64w+64)).  It writes
+// dZ1..dZ3, the activations h1, h2 and the (row-selected) inputs transposed,
+// as [feature][sample] arrays over the padded sample range (zero beyond n),
+// and accumulates the small gradients (W4, b4, the biases), which are owned
+// column by column, in registers over its tiles.  The weight pass forms
+// dW = H^T dZ for W1..W3 over chunks of samples: both operands are rows of
+// the transposed arrays, so a lane's 8 consecutive samples are one 16-byte
+// load straight into registers; a workgroup owns a 64 x 64 block of W2 or W3
+// (16 x 64 of W1) and one chunk, its four waves interleave the chunk's
+// 32-sample steps and are summed in LDS in wave order.  The last pass adds
+// the chunk and workgroup partials, in order, to the gradients, so the
+// result is deterministic.
+constexpr int BT = 32;  // samples per signal-pass tile
+// per-workgroup small partials: W4 [256][2], b4, b3, b2, b1
+constexpr int SP_W4 = 0, SP_B4 = SP_W4 + HW * DOUT, SP_B3 = SP_B4 + DOUT, SP_B2 = SP_B3 + HW, SP_B1 = SP_B2 + HW;
+constexpr int SMALLP = (SP_B1 + HW + 7) / 8 * 8;
+// per-chunk weight partials: W1 [16][256], W2, W3 [256][256]
+constexpr int64_t BP_W1 = 0, BP_W2 = BP_W1 + DIN * HW, BP_W3 = BP_W2 + HW * HW, NBIG = BP_W3 + HW * HW;
+constexpr int MAX_WCHUNKS = 64;
 
-// part[wofs + j*Ncols + n] = sum over the 64 samples of H[m][j] dZ[m][n]:
-// wave w takes rows j in [64w, 64w+64), in column strips of 64.
-__device__ __attribute__((always_inline)) inline void grad_HtdZ(const uint16_t* H, int ldh, const uint16_t* dZ, float* __restrict__ part,
-                                 int64_t wofs, int Ncols) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, r = lane & 15;
-    const int jbase = 64 * w;
-    for (int nh = 0; nh < HW; nh += 64) {
-        v4f32 acc[4][4];
+// rows [0, 32) of Z (zero beyond nvalid) into s[m][LDH]
+__device__ inline void bwd_load_z(const uint16_t* __restrict__ Z, uint16_t* s, int64_t row0, int nvalid) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
-        for (int m0 = 0; m0 < MT; m0 += 16) {
-            v4i16 a[4], b[4];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const uint16_t* p = H + (m0 + 4 * g) * ldh + jbase + 16 * mt + r;
-                a[mt] = pack4(p[0], p[ldh], p[2 * ldh], p[3 * ldh]);
-            }
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const uint16_t* p = dZ + (m0 + 4 * g) * LDH + nh + 16 * nt + r;
-                b[nt] = pack4(p[0], p[LDH], p[2 * LDH], p[3 * LDH]);
-            }
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int j = jbase + 16 * mt + 4 * g + i;
-                    part[wofs + (int64_t)j * Ncols + nh + 16 * nt + r] = acc[mt][nt][i];
-                }
+    for (int i = 0; i < BT * HW / 8 / 256; ++i) {
+        const int idx = threadIdx.x + 256 * i, m = idx >> 5, c = idx & 31;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (m < nvalid) v = *(const uint4*)(Z + (row0 + m) * HW + 8 * c);
+        *(uint4*)(s + m * LDH + 8 * c) = v;
     }
 }
 
-// dH[64][256] = dZ[64][256] * W^T (W as [K][N] row-major = B operand [n][k]);
-// then dZ_prev = bf16(dH * silu'(z_prev)) into out, rows >= nvalid zero.
-__device__ __attribute__((always_inline)) inline void bwd_dH(const uint16_t* dZ, const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ zprev,
-                              uint16_t* out, int64_t row0, int nvalid) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, r = lane & 15;
-    v4f32 acc[4][4];
+// HT[j][row0 + m] = bf16(silu(z[m][j])) for column j = threadIdx.x (zero beyond nvalid)
+__device__ inline void bwd_store_ht(const uint16_t* sz, uint16_t* __restrict__ HT, int64_t npad, int64_t row0,
+                                    int nvalid) {
+    const int j = threadIdx.x;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int q = 0; q < BT / 8; ++q) {
+        uint32_t p[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = 8 * q + 2 * i;
+            const float h0 = m < nvalid ? silu(bf2f(sz[m * LDH + j])) : 0.f;
+            const float h1 = m + 1 < nvalid ? silu(bf2f(sz[(m + 1) * LDH + j])) : 0.f;
+            p[i] = f2bf2(h0, h1);
+        }
+        *(uint4*)(HT + (int64_t)j * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
+    }
+}
+
+// dZ_prev[m][j] = bf16((sum_n dZ[m][n] W[j][n]) silu'(z[m][j])) for the tile: dZ in sd
+// (replaced by dZ_prev), z in sz, W as the [K][N] copy; dZ_prev also to dZT[j][sample].
+__device__ __attribute__((always_inline)) inline void bwd_signal_layer(uint16_t* sd, const uint16_t* sz,
+                                                                       const uint16_t* __restrict__ Wb,
+                                                                       uint16_t* __restrict__ dZT, int64_t npad,
+                                                                       int64_t row0, int nvalid) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    v4f32 acc[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < HW; k0 += 16) {
-        v4i16 a[4], b[4];
+#pragma unroll 2
+    for (int k0 = 0; k0 < HW; k0 += 32) {
+        v8i16 a[2], b[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = ld4(dZ + (mt * 16 + r) * LDH + k0 + 4 * g);
+        for (int nt = 0; nt < 4; ++nt) b[nt] = ld8(Wb + (int64_t)(64 * wv + 16 * nt + r) * HW + k0 + 8 * g);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = ld4(Wb + (int64_t)(64 * w + 16 * nt + r) * HW + k0 + 4 * g);
+        for (int mt = 0; mt < 2; ++mt) a[mt] = ld8(sd + (16 * mt + r) * LDH + k0 + 8 * g);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma32(a[mt], b[nt], acc[mt][nt]);
     }
-    __syncthreads();  // every wave has read dZ before it is overwritten
+    __syncthreads();  // every wave has read dZ before it is replaced
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const int col = 64 * w + 16 * nt + r;
+            const int j = 64 * wv + 16 * nt + r, m0 = 16 * mt + 4 * g;
+            uint16_t d[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int row = mt * 16 + 4 * g + i;
-                float v = 0.f;
-                if (row < nvalid) v = acc[mt][nt][i] * dsilu(bf2f(zprev[(row0 + row) * HW + col]));
-                out[row * LDH + col] = f2bf(v);
+                const int m = m0 + i;
+                d[i] = m < nvalid ? f2bf(acc[mt][nt][i] * dsilu(bf2f(sz[m * LDH + j]))) : (uint16_t)0;
+                sd[m * LDH + j] = d[i];
             }
+            *(uint2*)(dZT + (int64_t)j * npad + row0 + m0) =
+                make_uint2((uint32_t)d[0] | ((uint32_t)d[1] << 16), (uint32_t)d[2] | ((uint32_t)d[3] << 16));
         }
 }
 
-// h[m][j] = bf16(silu(z[m][j])) for the 64 rows of the tile (zero beyond nvalid).
-__device__ inline void load_h(const uint16_t* __restrict__ z, uint16_t* h, int64_t row0, int nvalid) {
-    const int j = threadIdx.x;
-    for (int m = 0; m < MT; ++m)
-        h[m * LDH + j] = m < nvalid ? f2bf(silu(bf2f(z[(row0 + m) * HW + j]))) : (uint16_t)0;
-}
-
-// column sums of dZ (bias gradient) into the partial row
-__device__ inline void bias_grad(const uint16_t* dZ, float* __restrict__ part, int64_t ofs) {
-    const int j = threadIdx.x;
-    float s = 0.f;
-    for (int m = 0; m < MT; ++m) s += bf2f(dZ[m * LDH + j]);
-    part[ofs + j] = s;
-}
-
-__global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t* __restrict__ wt, const uint16_t* __restrict__ wb,
-                                                  const float* __restrict__ w, const uint16_t* __restrict__ X,
-                                                  const int32_t* __restrict__ rows, int64_t n,
-                                                  const uint16_t* __restrict__ Z, const float* __restrict__ dY,
-                                                  float* __restrict__ partial) {
-    __shared__ __attribute__((aligned(16))) uint16_t sx[MT * LDH];  // inputs (16 columns used), then reused
-    __shared__ __attribute__((aligned(16))) uint16_t sd[MT * LDH];  // dZ of the current layer
-    __shared__ __attribute__((aligned(16))) uint16_t sh[MT * LDH];  // activations feeding the current layer
-    __shared__ float sdy[MT * DOUT];
-    const int64_t tile = blockIdx.x;
-    const int64_t row0 = tile * MT;
-    const int nvalid = (int)(n - row0 < MT ? n - row0 : MT);
-    float* part = partial + tile * NPARAM;
+// Signal pass over tiles blockIdx.x, +gridDim.x, ...; T holds dZT3, dZT2, dZT1, HT2, HT1
+// ([256][npad] each), XT the inputs [16][npad]; sp[blockIdx.x][SMALLP] the small partials.
+__global__ __launch_bounds__(256, 2) void k_bwd_signal(const uint16_t* __restrict__ wb, const float* __restrict__ w,
+                                                     const uint16_t* __restrict__ X, const int32_t* __restrict__ rows,
+                                                     int64_t n, int64_t npad, const uint16_t* __restrict__ Z,
+                                                     const float* __restrict__ dY, uint16_t* __restrict__ T,
+                                                     uint16_t* __restrict__ XT, float* __restrict__ sp) {
+    __shared__ __attribute__((aligned(16))) uint16_t sd[BT * LDH];  // dZ of the current layer, [m][j]
+    __shared__ __attribute__((aligned(16))) uint16_t sz[BT * LDH];  // z of the layer below, [m][j]
+    __shared__ float sdy[BT * DOUT];
+    const int t = threadIdx.x, j = t;
+    const int64_t tiles = npad / BT, plane = HW * npad;
     const uint16_t* Z1 = Z;
     const uint16_t* Z2 = Z + n * HW;
     const uint16_t* Z3 = Z + 2 * n * HW;
-    const int t = threadIdx.x;
-    if (t < MT * DOUT) {
-        const int m = t / DOUT;
-        sdy[t] = m < nvalid ? dY[(row0 + m) * DOUT + (t % DOUT)] : 0.f;
-    }
-    {
-        const int m = t >> 2, q = t & 3;
-        v4i16 v = (v4i16){0, 0, 0, 0};
-        if (m < nvalid) {
-            const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
-            v = ld4(X + src * DIN + 4 * q);
+    uint16_t* dZT3 = T;
+    uint16_t* dZT2 = T + plane;
+    uint16_t* dZT1 = T + 2 * plane;
+    uint16_t* HT2 = T + 3 * plane;
+    uint16_t* HT1 = T + 4 * plane;
+    const float w40 = bf2f(f2bf(w[OFF_W4 + j * DOUT])), w41 = bf2f(f2bf(w[OFF_W4 + j * DOUT + 1]));
+    float gw0 = 0.f, gw1 = 0.f, gb3 = 0.f, gb2 = 0.f, gb1 = 0.f, gb4 = 0.f;  // column j's partials
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t row0 = tile * BT;
+        const int nvalid = (int)(n - row0 < BT ? n - row0 : BT);
+        if (t < BT * DOUT) {
+            const int m = t / DOUT;
+            sdy[t] = m < nvalid ? dY[(row0 + m) * DOUT + (t % DOUT)] : 0.f;
         }
-        *(v4i16*)(sx + m * LDH + 4 * q) = v;
-    }
-    __syncthreads();
-    // head: dW4[j][c] = sum_m h3[m][j] dY[m][c];  dZ3 = bf16((dY W4^T) * silu'(z3))
-    {
-        const int j = t;
-        const float w40 = bf2f(f2bf(w[OFF_W4 + j * DOUT])), w41 = bf2f(f2bf(w[OFF_W4 + j * DOUT + 1]));
-        float g0 = 0.f, g1 = 0.f, db = 0.f;
-        for (int m = 0; m < MT; ++m) {
-            float z = m < nvalid ? bf2f(Z3[(row0 + m) * HW + j]) : 0.f;
-            const float h = m < nvalid ? bf2f(f2bf(silu(z))) : 0.f;
-            g0 += h * sdy[m * DOUT];
-            g1 += h * sdy[m * DOUT + 1];
-            const float dz = (sdy[m * DOUT] * w40 + sdy[m * DOUT + 1] * w41) * dsilu(z);
-            const uint16_t dzb = m < nvalid ? f2bf(dz) : (uint16_t)0;
-            sd[m * LDH + j] = dzb;
-            db += bf2f(dzb);
-        }
-        part[OFF_W4 + j * DOUT] = g0;
-        part[OFF_W4 + j * DOUT + 1] = g1;
-        part[OFF_B3 + j] = db;
-        if (j < DOUT) {
-            float s = 0.f;
-            for (int m = 0; m < MT; ++m) s += sdy[m * DOUT + j];
-            part[OFF_B4 + j] = s;
-        }
-    }
-    load_h(Z2, sh, row0, nvalid);
-    __syncthreads();
-    // layer 3: dW3 = H2^T dZ3; dZ2 = bf16((dZ3 W3^T) * silu'(z2))
-    grad_HtdZ(sh, LDH, sd, part, OFF_W3, HW);
-    __syncthreads();
-    bwd_dH(sd, wb + WB3, Z2, sd, row0, nvalid);
-    __syncthreads();
-    bias_grad(sd, part, OFF_B2);
-    load_h(Z1, sh, row0, nvalid);
-    __syncthreads();
-    // layer 2: dW2 = H1^T dZ2; dZ1 = bf16((dZ2 W2^T) * silu'(z1))
-    grad_HtdZ(sh, LDH, sd, part, OFF_W2, HW);
-    __syncthreads();
-    bwd_dH(sd, wb + WB2, Z1, sd, row0, nvalid);
-    __syncthreads();
-    bias_grad(sd, part, OFF_B1);
-    __syncthreads();
-    // layer 1: dW1 = X^T dZ1 (16 x 256): wave w takes columns [64w, 64w+64)
-    {
-        const int lane = t & 63, wv = t >> 6;
-        const int g = lane >> 4, r = lane & 15;
-        v4f32 acc[4];
+        if (t < DIN * (BT / 8)) {  // inputs, transposed: thread (k, q) writes x[8q .. 8q+7][k]
+            const int k = t & (DIN - 1), q = t / DIN;
+            uint32_t p[4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
-        for (int m0 = 0; m0 < MT; m0 += 16) {
-            const uint16_t* pa = sx + (m0 + 4 * g) * LDH + r;
-            const v4i16 a = pack4(pa[0], pa[LDH], pa[2 * LDH], pa[3 * LDH]);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const uint16_t* pb = sd + (m0 + 4 * g) * LDH + 64 * wv + 16 * nt + r;
-                acc[nt] = mfma(a, pack4(pb[0], pb[LDH], pb[2 * LDH], pb[3 * LDH]), acc[nt]);
+            for (int i = 0; i < 4; ++i) {
+                uint32_t lo = 0, hi = 0;
+                const int m = 8 * q + 2 * i;
+                if (m < nvalid) lo = X[(rows ? (int64_t)rows[row0 + m] : row0 + m) * DIN + k];
+                if (m + 1 < nvalid) hi = X[(rows ? (int64_t)rows[row0 + m + 1] : row0 + m + 1) * DIN + k];
+                p[i] = lo | (hi << 16);
             }
+            *(uint4*)(XT + (int64_t)k * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
         }
+        bwd_load_z(Z3, sz, row0, nvalid);
+        __syncthreads();
+        // head, column j: dW4[j][c] += sum_m h3[m][j] dY[m][c]; dZ3 = bf16((dY W4^T) silu'(z3))
+        {
+#pragma unroll 1
+            for (int q = 0; q < BT / 8; ++q) {
+                uint32_t p[4];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int m = 8 * q + i;
+                    const float z = bf2f(sz[m * LDH + j]);
+                    const bool ok = m < nvalid;
+                    const float h = ok ? bf2f(f2bf(silu(z))) : 0.f;
+                    const float d0 = sdy[m * DOUT], d1 = sdy[m * DOUT + 1];
+                    gw0 += h * d0;
+                    gw1 += h * d1;
+                    const uint16_t dz = ok ? f2bf((d0 * w40 + d1 * w41) * dsilu(z)) : (uint16_t)0;
+                    sd[m * LDH + j] = dz;
+                    gb3 += bf2f(dz);
+                    if (i & 1) p[i >> 1] |= (uint32_t)dz << 16;
+                    else p[i >> 1] = dz;
+                }
+                *(uint4*)(dZT3 + (int64_t)j * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
+            }
+            if (j < DOUT)
+                for (int m = 0; m < BT; ++m) gb4 += sdy[m * DOUT + j];
+        }
+        __syncthreads();  // sz (z3) and sdy are read
+        bwd_load_z(Z2, sz, row0, nvalid);
+        __syncthreads();
+        bwd_store_ht(sz, HT2, npad, row0, nvalid);
+        bwd_signal_layer(sd, sz, wb + WB3, dZT2, npad, row0, nvalid);
+        __syncthreads();
+        for (int m = 0; m < BT; ++m) gb2 += bf2f(sd[m * LDH + j]);
+        bwd_load_z(Z1, sz, row0, nvalid);
+        __syncthreads();
+        bwd_store_ht(sz, HT1, npad, row0, nvalid);
+        bwd_signal_layer(sd, sz, wb + WB2, dZT1, npad, row0, nvalid);
+        __syncthreads();
+        for (int m = 0; m < BT; ++m) gb1 += bf2f(sd[m * LDH + j]);
+        __syncthreads();  // before the next tile overwrites sd, sz, sdy
+    }
+    float* part = sp + blockIdx.x * (int64_t)SMALLP;
+    part[SP_W4 + j * DOUT] = gw0;
+    part[SP_W4 + j * DOUT + 1] = gw1;
+    part[SP_B3 + j] = gb3;
+    part[SP_B2 + j] = gb2;
+    part[SP_B1 + j] = gb1;
+    if (j < DOUT) part[SP_B4 + j] = gb4;
+}
+
+// One 16*MTA x 64 block of dW = A^T B over the 32-sample steps [s0, s1) of the
+// transposed arrays (A rows a0.., B rows b0.., leading dimension npad): wave w
+// takes steps s0 + w, s0 + w + 4, ...; the four waves are summed through LDS
+// in wave order and the block goes to out[row][col] (row stride ldo).
+template <int MTA>
+__device__ __attribute__((always_inline)) inline void wgrad_block(const uint16_t* __restrict__ A,
+                                                                  const uint16_t* __restrict__ B, int64_t npad,
+                                                                  int64_t s0, int64_t s1, float* red,
+                                                                  float* __restrict__ out, int ldo) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    v4f32 acc[MTA][4];
+#pragma unroll
+    for (int mt = 0; mt < MTA; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    const uint16_t* pa = A + (int64_t)r * npad + 8 * g;
+    const uint16_t* pb = B + (int64_t)r * npad + 8 * g;
+    int64_t s = s0 + wv;
+    v8i16 a[MTA], b[4];
+    if (s < s1) {  // the next step's operands are loaded while this step's products run
+#pragma unroll
+        for (int mt = 0; mt < MTA; ++mt) a[mt] = ld8(pa + 16 * mt * npad + 32 * s);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) b[nt] = ld8(pb + 16 * nt * npad + 32 * s);
+    }
+    for (; s < s1; s += 4) {
+        const bool more = s + 4 < s1;
+        v8i16 an[MTA], bn[4];
+        if (more) {
+#pragma unroll
+            for (int mt = 0; mt < MTA; ++mt) an[mt] = ld8(pa + 16 * mt * npad + 32 * (s + 4));
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bn[nt] = ld8(pb + 16 * nt * npad + 32 * (s + 4));
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTA; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma32(a[mt], b[nt], acc[mt][nt]);
+        if (more) {
+#pragma unroll
+            for (int mt = 0; mt < MTA; ++mt) a[mt] = an[mt];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b[nt] = bn[nt];
+        }
+    }
+    constexpr int PER_WAVE = MTA * 4 * 4 * 64;
+#pragma unroll
+    for (int mt = 0; mt < MTA; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) part[OFF_W1 + (int64_t)(4 * g + i) * HW + 64 * wv + 16 * nt + r] = acc[nt][i];
+            for (int i = 0; i < 4; ++i) red[wv * PER_WAVE + ((mt * 4 + nt) * 4 + i) * 64 + lane] = acc[mt][nt][i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < PER_WAVE; e += 256) {
+        const float v = ((red[e] + red[PER_WAVE + e]) + red[2 * PER_WAVE + e]) + red[3 * PER_WAVE + e];
+        const int ln = e & 63, q = e >> 6, i = q & 3, nt = (q >> 2) & 3, mt = q >> 4;
+        out[(16 * mt + 4 * (ln >> 4) + i) * ldo + 16 * nt + (ln & 15)] = v;
     }
 }
 
-// grad[p] += sum over tiles, in tile order, of partial[tile][p]
-__global__ void k_grad_reduce(const float* __restrict__ partial, int64_t n_tiles, float* __restrict__ grad) {
+// Weight pass: workgroup b takes chunk b % n_chunks of job b / n_chunks; jobs 0..15 are the
+// 64 x 64 blocks of W3 (H2^T dZ3), 16..31 those of W2 (H1^T dZ2), 32..35 the
+// 16 x 64 blocks of W1 (X^T dZ1).  bp[chunk][NBIG] receives the chunk's partials.
+__global__ __launch_bounds__(256) void k_bwd_wgrad(const uint16_t* __restrict__ T, const uint16_t* __restrict__ XT,
+                                                    int64_t npad, int n_chunks, float* __restrict__ bp) {
+    __shared__ __attribute__((aligned(16))) float red[4 * 4 * 4 * 4 * 64];
+    const int64_t plane = HW * npad;
+    const int chunk = (int)(blockIdx.x % n_chunks), job = (int)(blockIdx.x / n_chunks);
+    const int64_t steps = npad / 32, per = (steps + n_chunks - 1) / n_chunks;
+    const int64_t s0 = chunk * per, s1 = s0 + per < steps ? s0 + per : steps;
+    float* base = bp + chunk * NBIG;
+    if (job < 32) {
+        const int mat = job < 16 ? 3 : 2, blk = job & 15, jb = blk >> 2, nb4 = blk & 3;
+        const uint16_t* A = (mat == 3 ? T + 3 * plane : T + 4 * plane) + (int64_t)(64 * jb) * npad;  // HT2 / HT1
+        const uint16_t* B = (mat == 3 ? T : T + plane) + (int64_t)(64 * nb4) * npad;                // dZT3 / dZT2
+        float* out = base + (mat == 3 ? BP_W3 : BP_W2) + (64 * jb) * HW + 64 * nb4;
+        wgrad_block<4>(A, B, npad, s0, s1, red, out, HW);
+    } else {
+        const int nb4 = job - 32;
+        wgrad_block<1>(XT, T + 2 * plane + (int64_t)(64 * nb4) * npad, npad, s0, s1, red, base + BP_W1 + 64 * nb4,
+                       HW);
+    }
+}
+
+// grad[p] += the partials of p in order: weight-pass chunks for W1..W3, signal-pass workgroups otherwise
+__global__ void k_grad_sum(const float* __restrict__ bp, int n_chunks, const float* __restrict__ sp, int n_groups,
+                           float* __restrict__ grad) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= NPARAM) return;
+    int64_t src = -1, stride = 0, cnt = 0;
+    const float* base = nullptr;
+    if (p >= OFF_W1 && p < OFF_B1) src = BP_W1 + (p - OFF_W1);
+    else if (p >= OFF_W2 && p < OFF_B2) src = BP_W2 + (p - OFF_W2);
+    else if (p >= OFF_W3 && p < OFF_B3) src = BP_W3 + (p - OFF_W3);
+    if (src >= 0) {
+        base = bp;
+        stride = NBIG;
+        cnt = n_chunks;
+    } else {
+        if (p >= OFF_B1 && p < OFF_W2) src = SP_B1 + (p - OFF_B1);
+        else if (p >= OFF_B2 && p < OFF_W3) src = SP_B2 + (p - OFF_B2);
+        else if (p >= OFF_B3 && p < OFF_W4) src = SP_B3 + (p - OFF_B3);
+        else if (p >= OFF_W4 && p < OFF_B4) src = SP_W4 + (p - OFF_W4);
+        else src = SP_B4 + (p - OFF_B4);
+        base = sp;
+        stride = SMALLP;
+        cnt = n_groups;
+    }
     float s = 0.f;
-    for (int64_t t = 0; t < n_tiles; ++t) s += partial[t * NPARAM + p];
+    for (int64_t c = 0; c < cnt; ++c) s += base[c * stride + src];
     grad[p] += s;
 }
 
@@ -595,16 +699,66 @@ __global__ void k_nll(const float* __restrict__ Y, const float* __restrict__ T, 
     if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0]);
 }
 
-__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= NPARAM) return;
+__device__ inline void adam_one(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                                float* __restrict__ v, int64_t i, float lr, float b1, float b2, float eps, float wd,
+                                float c1, float c2) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    adam_one(w, g, m, v, i, lr, b1, b2, eps, wd, c1, c2);
+}
+
+// bias correction 1 - b^t, formed in FP64 and rounded once (host and device agree)
+__host__ __device__ inline float bias_corr(float b, int64_t t) { return (float)(1.0 - pow((double)b, (double)t)); }
+
+// ---------------------------------------------------------------- training steps on the device
+//
+// The step number k lives in device memory, so one captured step serves every
+// replay: rows drawn from (seed, k), the cosine learning rate of k, the bias
+// corrections of k + 1, then k += 1.
+__global__ void k_set_step(int64_t* __restrict__ st, int64_t v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st = v;
+}
+
+__global__ void k_step_inc(int64_t* __restrict__ st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st += 1;
+}
+
+__global__ void k_train_rows(const int64_t* __restrict__ st, uint64_t seed, int64_t N, int64_t batch,
+                             int32_t* __restrict__ rows) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= batch) return;
+    const uint64_t k = (uint64_t)*st;
+    uint64_t z = seed + (k * (uint64_t)batch + (uint64_t)i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    rows[i] = (int32_t)(z % (uint64_t)N);
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ void k_adam_sched(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                             float* __restrict__ v, const int64_t* __restrict__ st, rt_train_opts o) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const int64_t k = *st;
+    const double frac = (double)(k < o.total_steps ? k : o.total_steps) / (double)o.total_steps;
+    const float lr = (float)((double)o.lr_final +
+                             0.5 * ((double)o.lr - (double)o.lr_final) * (1.0 + cos(3.141592653589793 * frac)));
+    adam_one(w, g, m, v, i, lr, o.b1, o.b2, o.eps, o.wd, bias_corr(o.b1, k + 1), bias_corr(o.b2, k + 1));
 }
 
 // ---------------------------------------------------------------- features
@@ -801,6 +955,13 @@ struct rt_mlp {
     int64_t step = 0;
     bool has_norm = false;  // input standardisation for rt_closure_J
     float mean[DIN] = {}, istd[DIN] = {};
+    // the captured training step of the last rt_mlp_train call and what it was captured for
+    hipGraph_t train_graph = nullptr;
+    hipGraphExec_t train_exec = nullptr;
+    const void* train_key[5] = {};
+    int64_t train_N = 0;
+    size_t train_ws_bytes = 0;
+    rt_train_opts train_opts = {};
 };
 
 static rt_status mlp_publish(rt_mlp* h, hipStream_t s) {
@@ -858,6 +1019,8 @@ extern "C" rt_status rt_mlp_create(uint64_t seed, void* stream, rt_mlp** out) {
 
 extern "C" rt_status rt_mlp_destroy(rt_mlp* h) {
     if (!h) return RT_OK;
+    if (h->train_exec) (void)hipGraphExecDestroy(h->train_exec);
+    if (h->train_graph) (void)hipGraphDestroy(h->train_graph);
     for (void* q : {(void*)h->w, (void*)h->g, (void*)h->m, (void*)h->v, (void*)h->wt, (void*)h->wb})
         if (q) (void)hipFree(q);
     delete h;
@@ -892,13 +1055,31 @@ extern "C" rt_status rt_mlp_zero_grad(rt_mlp* h, void* stream) {
     return RT_OK;
 }
 
-// Training workspace: the BF16 pre-activations Z[3][n][256], then (256-byte
-// aligned) the per-tile weight-gradient partials [tiles][NPARAM] in FP32.
-static size_t z_bytes(int64_t n) { return (((size_t)(3 * n * HW) * sizeof(uint16_t)) + 255) & ~(size_t)255; }
-static size_t ws_bytes_for(int64_t n) {
-    const int64_t tiles = (n + MT - 1) / MT;
-    return z_bytes(n) + (size_t)(tiles * NPARAM) * sizeof(float);
+// Training workspace (each part 256-byte aligned): the BF16 pre-activations
+// Z[3][n][256] that the forward keeps; the backward's transposed arrays
+// dZ3, dZ2, dZ1, h2, h1 [256][npad] and x [16][npad] (BF16, npad = n rounded
+// up to 32); the signal pass's small partials [groups][SMALLP] and the weight
+// pass's partials [chunks][NBIG] (FP32).
+namespace {
+struct BwdParts {
+    int64_t npad, groups, chunks;
+    size_t t, xt, sp, bp, total;
+};
+inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+BwdParts bwd_parts(int64_t n) {
+    BwdParts b;
+    b.npad = (n + BT - 1) / BT * BT;
+    b.groups = std::max<int64_t>(1, std::min<int64_t>(b.npad / BT, 4 * (int64_t)num_cus()));
+    b.chunks = std::max<int64_t>(1, std::min<int64_t>(b.npad / 32 / 32, MAX_WCHUNKS));
+    b.t = al256((size_t)(3 * n * HW) * sizeof(uint16_t));
+    b.xt = b.t + al256((size_t)(5 * HW * b.npad) * sizeof(uint16_t));
+    b.sp = b.xt + al256((size_t)(DIN * b.npad) * sizeof(uint16_t));
+    b.bp = b.sp + al256((size_t)(b.groups * SMALLP) * sizeof(float));
+    b.total = b.bp + (size_t)(b.chunks * NBIG) * sizeof(float);
+    return b;
 }
+}  // namespace
+static size_t ws_bytes_for(int64_t n) { return bwd_parts(n).total; }
 
 extern "C" rt_status rt_mlp_workspace(int64_t n, int32_t training, size_t* bytes) {
     if (!bytes || n < 0) return fail(RT_ERR_ARG, "rt_mlp_workspace: bad arguments");
@@ -951,13 +1132,19 @@ extern "C" rt_status rt_mlp_backward(rt_mlp* h, const uint16_t* X, const int32_t
         return fail(RT_ERR_ARG, "rt_mlp_backward: bad arguments");
     if (n == 0) return RT_OK;
     if (!ws || ws_bytes < ws_bytes_for(n)) return fail(RT_ERR_CAPACITY, "rt_mlp_backward: workspace too small");
-    const int64_t tiles = (n + MT - 1) / MT;
-    const uint16_t* Z = (const uint16_t*)ws;
-    float* partial = (float*)((char*)ws + z_bytes(n));
+    const BwdParts b = bwd_parts(n);
+    char* base = (char*)ws;
+    uint16_t* T = (uint16_t*)(base + b.t);
+    uint16_t* XT = (uint16_t*)(base + b.xt);
+    float* sp = (float*)(base + b.sp);
+    float* bp = (float*)(base + b.bp);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)tiles), dim3(256), 0, s, h->wt, h->wb, h->w, X, rows, n, Z, dY,
-                       partial);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(nb(NPARAM, 256)), dim3(256), 0, s, partial, tiles, h->g);
+    hipLaunchKernelGGL(k_bwd_signal, dim3((unsigned)b.groups), dim3(256), 0, s, h->wb, h->w, X, rows, n, b.npad,
+                       (const uint16_t*)ws, dY, T, XT, sp);
+    hipLaunchKernelGGL(k_bwd_wgrad, dim3((unsigned)(36 * b.chunks)), dim3(256), 0, s, T, XT, b.npad, (int)b.chunks,
+                       bp);
+    hipLaunchKernelGGL(k_grad_sum, dim3(nb(NPARAM, 256)), dim3(256), 0, s, bp, (int)b.chunks, sp, (int)b.groups,
+                       h->g);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
@@ -974,12 +1161,111 @@ extern "C" rt_status rt_mlp_nll(const float* Y, const float* T, const int32_t* r
 extern "C" rt_status rt_mlp_adam_step(rt_mlp* h, float lr, float b1, float b2, float eps, float wd, void* stream) {
     if (!h) return fail(RT_ERR_ARG, "rt_mlp_adam_step: NULL");
     h->step += 1;
-    const float c1 = 1.f - std::pow(b1, (float)h->step), c2 = 1.f - std::pow(b2, (float)h->step);
+    const float c1 = bias_corr(b1, h->step), c2 = bias_corr(b2, h->step);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_adam, dim3(nb(NPARAM, 256)), dim3(256), 0, s, h->w, h->g, h->m, h->v, lr, b1, b2, eps, wd,
                        c1, c2);
     RT_HIP(hipGetLastError());
     return mlp_publish(h, s);
+}
+
+// Training workspace: batch rows (int32), Y and dY (f32 [batch][2]), the step
+// counter, then the forward/backward workspace of the batch.
+namespace {
+struct TrainParts {
+    size_t rows, Y, dY, st, mlp, total;
+};
+TrainParts train_parts(int64_t batch) {
+    TrainParts t;
+    t.rows = 0;
+    t.Y = t.rows + al256(sizeof(int32_t) * (size_t)batch);
+    t.dY = t.Y + al256(sizeof(float) * DOUT * (size_t)batch);
+    t.st = t.dY + al256(sizeof(float) * DOUT * (size_t)batch);
+    t.mlp = t.st + 256;
+    t.total = t.mlp + ws_bytes_for(batch);
+    return t;
+}
+
+bool same_opts(const rt_train_opts& a, const rt_train_opts& b) {
+    return a.batch == b.batch && a.total_steps == b.total_steps && a.lr == b.lr && a.lr_final == b.lr_final &&
+           a.b1 == b.b1 && a.b2 == b.b2 && a.eps == b.eps && a.wd == b.wd && a.seed == b.seed;
+}
+
+// one training step on stream s (captured by rt_mlp_train)
+rt_status train_enqueue(rt_mlp* h, const uint16_t* X, const float* T, int64_t N, const rt_train_opts& o,
+                        float* loss_sum, char* ws, hipStream_t s) {
+    const TrainParts tp = train_parts(o.batch);
+    int32_t* rows = (int32_t*)(ws + tp.rows);
+    float* Y = (float*)(ws + tp.Y);
+    float* dY = (float*)(ws + tp.dY);
+    int64_t* st = (int64_t*)(ws + tp.st);
+    void* mws = ws + tp.mlp;
+    const size_t mbytes = ws_bytes_for(o.batch);
+    hipLaunchKernelGGL(k_train_rows, dim3(nb(o.batch, 256)), dim3(256), 0, s, st, o.seed, N, o.batch, rows);
+    RT_HIP(hipGetLastError());
+    rt_status e = rt_mlp_forward(h, X, rows, o.batch, Y, 1, mws, mbytes, s);
+    if (!e) e = rt_mlp_nll(Y, T, rows, o.batch, dY, loss_sum, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_zero_f32, dim3(nb(NPARAM, 256)), dim3(256), 0, s, h->g, NPARAM);
+    e = rt_mlp_backward(h, X, rows, o.batch, dY, mws, mbytes, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_adam_sched, dim3(nb(NPARAM, 256)), dim3(256), 0, s, h->w, h->g, h->m, h->v, st, o);
+    RT_HIP(hipGetLastError());
+    e = mlp_publish(h, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, st);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+}  // namespace
+
+extern "C" rt_status rt_mlp_train_workspace(int64_t batch, size_t* bytes) {
+    if (!bytes || batch < 1 || batch > MAX_SAMPLES) return fail(RT_ERR_ARG, "rt_mlp_train_workspace: bad arguments");
+    *bytes = train_parts(batch).total;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_train(rt_mlp* h, const uint16_t* X, const float* T, int64_t N, const rt_train_opts* opts,
+                                  int64_t n_steps, float* loss_sum, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !X || !T || !opts || !ws || N < 1 || N > MAX_SAMPLES || n_steps < 0)
+        return fail(RT_ERR_ARG, "rt_mlp_train: bad arguments");
+    const rt_train_opts o = *opts;
+    if (o.batch < 1 || o.batch > MAX_SAMPLES || o.total_steps < 1)
+        return fail(RT_ERR_ARG, "rt_mlp_train: bad batch or schedule");
+    if (ws_bytes < train_parts(o.batch).total) return fail(RT_ERR_CAPACITY, "rt_mlp_train: workspace too small");
+    if (n_steps == 0) return RT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const void* key[5] = {X, T, loss_sum, ws, nullptr};
+    bool reuse = h->train_exec && h->train_N == N && h->train_ws_bytes == ws_bytes && same_opts(h->train_opts, o);
+    for (int i = 0; i < 5 && reuse; ++i) reuse = h->train_key[i] == key[i];
+    if (!reuse) {
+        if (h->train_exec) (void)hipGraphExecDestroy(h->train_exec);
+        if (h->train_graph) (void)hipGraphDestroy(h->train_graph);
+        h->train_exec = nullptr;
+        h->train_graph = nullptr;
+        hipStream_t cap = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        rt_status st = RT_OK;
+        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = train_enqueue(h, X, T, N, o, loss_sum, (char*)ws, cap);
+            e = hipStreamEndCapture(cap, &h->train_graph);
+        }
+        if (e == hipSuccess && !st) e = hipGraphInstantiate(&h->train_exec, h->train_graph, nullptr, nullptr, 0);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (st) return st;
+        if (e != hipSuccess) return hip_fail(e, "rt_mlp_train: graph capture");
+        for (int i = 0; i < 5; ++i) h->train_key[i] = key[i];
+        h->train_N = N;
+        h->train_ws_bytes = ws_bytes;
+        h->train_opts = o;
+    }
+    int64_t* st = (int64_t*)((char*)ws + train_parts(o.batch).st);
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, st, h->step);
+    RT_HIP(hipGetLastError());
+    for (int64_t i = 0; i < n_steps; ++i) RT_HIP(hipGraphLaunch(h->train_exec, s));
+    h->step += n_steps;
+    return RT_OK;
 }
 
 extern "C" rt_status rt_closure_features(const rt_model* m, const float* chi, const float* eta, int64_t ld, int64_t F,
@@ -1063,7 +1349,6 @@ extern "C" rt_status rt_mlp_set_input_norm(rt_mlp* h, const float* mean, const f
 
 namespace {
 constexpr int64_t CLOSURE_CHUNK = 65536;  // points per inference chunk
-inline size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct ClosureParts {
     size_t J1, u1, x, pts, cnt, feat, X, Y, Jf, total;

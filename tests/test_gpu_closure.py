@@ -175,6 +175,110 @@ def test_mlp_loss_and_gradients(rt, n, use_rows):
     assert np.allclose(g2, 2 * g, rtol=1e-6, atol=1e-12)
 
 
+def _grad_errors(g, flat, Xo, dYh):
+    out = {}
+    for rnd, key in ((oc.bf16_round, "mirrored"), (None, "unrounded")):
+        o = _oracle_net(flat, rnd)
+        _, cache = o.forward(Xo)
+        go = o.flat(o.backward(cache, dYh))
+        ofs = 0
+        for name, shp in oc.MLP.SHAPES:
+            k = int(np.prod(shp))
+            out[(name, key)] = _relF(g[ofs:ofs + k].astype(np.float64), go[ofs:ofs + k])
+            ofs += k
+    return out
+
+
+def test_mlp_gradients_training_batch(rt):
+    """The training batch (8192 samples drawn with replacement): the signal pass runs 256
+    workgroups and the weight pass 8 sample chunks per block; same bars as the small batches."""
+    torch = _torch()
+    flat = _params(21)
+    net = rt.MLP(seed=0)
+    net.set_params(flat)
+    N, n = 20_000, 8192
+    X = _inputs(22, N)
+    Xb = _t(_bf16_bits(X))
+    rng = np.random.default_rng(23)
+    T = rng.normal(0, 0.5, N).astype(np.float32)
+    rows = rng.integers(0, N, n).astype(np.int32)
+    Y = net.forward(Xb, rows=_t(rows), keep=True)
+    dY = rt.mlp_nll(Y, _t(T), rows=_t(rows))
+    net.zero_grad()
+    net.backward(Xb, dY, rows=_t(rows))
+    g = net.get_grads()
+    errs = _grad_errors(g, flat, oc.bf16_round(X[rows]), dY.cpu().numpy().astype(np.float64))
+    for (name, key), e in errs.items():
+        print(f"grad {name} ({key}): rel {e:.2e}")
+        assert e <= (1e-3 if key == "mirrored" else 1e-2), (name, key, e)
+    # deterministic: the same call gives the same bits
+    net.zero_grad()
+    net.backward(Xb, dY, rows=_t(rows))
+    assert np.array_equal(net.get_grads(), g)
+    torch.cuda.synchronize()
+
+
+def _splitmix_rows(seed, step, batch, N):
+    """Rows of training step `step` by the SplitMix64 finaliser (Steele, Lea and Flood 2014)."""
+    M = np.uint64(0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        i = np.arange(batch, dtype=np.uint64)
+        z = np.uint64(seed) + (np.uint64(step) * np.uint64(batch) + i + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = (z ^ (z >> np.uint64(31))) & M
+    return (z % np.uint64(N)).astype(np.int32)
+
+
+def test_mlp_train_graph_matches_steps(rt):
+    """rt_mlp_train (one captured step, replayed) against the same steps called one at a time
+    with the rows drawn by the published SplitMix64 and the cosine learning rate computed on
+    the host; split calls continue the step counter.  The first step is bit-identical (same
+    rows, gradients and learning rate); later learning rates are formed on the device from
+    the FP32 lr and lr_final and may differ from the host's by an ulp, so after seven steps
+    the parameters agree to 1e-6 (one Adam step moves them by about lr = 2e-3)."""
+    import math
+    torch = _torch()
+    N, batch, total = 3000, 700, 10
+    X = _inputs(31, N)
+    Xb = _t(_bf16_bits(X))
+    T = _t(np.random.default_rng(32).normal(0, 0.5, N).astype(np.float32))
+    kw = dict(batch=batch, total_steps=total, lr=2e-3, lr_final=1e-4, wd=1e-3, seed=77)
+    one_a, one_b = rt.MLP(seed=5), rt.MLP(seed=5)
+    one_a.train(Xb, T, 1, **kw)
+    rows0 = _t(_splitmix_rows(77, 0, batch, N))
+    Y0 = one_b.forward(Xb, rows=rows0, keep=True)
+    one_b.zero_grad()
+    one_b.backward(Xb, rt.mlp_nll(Y0, T, rows=rows0), rows=rows0)
+    one_b.adam_step(lr=2e-3, wd=1e-3)
+    assert np.array_equal(one_a.get_params(), one_b.get_params())
+    assert np.array_equal(one_a.get_grads(), one_b.get_grads())
+    a = rt.MLP(seed=5)
+    la = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a.train(Xb, T, 3, loss_sum=la, **kw)
+    a.train(Xb, T, 4, loss_sum=la, **kw)
+    b = rt.MLP(seed=5)
+    lb = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for k in range(7):
+        rows = _t(_splitmix_rows(77, k, batch, N))
+        lr = 1e-4 + 0.5 * (2e-3 - 1e-4) * (1.0 + math.cos(math.pi * min(k, total) / total))
+        Y = b.forward(Xb, rows=rows, keep=True)
+        dY = rt.mlp_nll(Y, T, rows=rows, loss_sum=lb)
+        b.zero_grad()
+        b.backward(Xb, dY, rows=rows)
+        b.adam_step(lr=lr, wd=1e-3)
+    pa, pb = a.get_params(), b.get_params()
+    d = float(np.max(np.abs(pa - pb)))
+    print(f"graph vs steps: max |dw| {d:.3e}, loss {la.item():.6f} vs {lb.item():.6f}")
+    assert d <= 1e-6
+    # the loss sums are accumulated by atomics (order not fixed)
+    assert abs(la.item() - lb.item()) <= 1e-5 * abs(lb.item())
+    # one call of 7 steps is the same as 3 + 4
+    c = rt.MLP(seed=5)
+    c.train(Xb, T, 7, **kw)
+    assert np.array_equal(c.get_params(), pa)
+
+
 def test_adam_steps(rt):
     flat = _params(8)
     net = rt.MLP(seed=0)
