@@ -3,9 +3,12 @@
 // rt_compute_J: trace (count, scan, write), sweep and J for a list of origins
 // inside the caller's workspace.  The origins are put in Morton order of their
 // positions and cut into consecutive chunks whose ray lists fit the space left
-// after the fixed per-origin parts; rays and sweep items of a chunk run
-// direction by direction over that order, and the J rows are scattered back to
-// the caller's list order.
+// after the fixed per-origin parts: a window of origins is counted, and the
+// chunk is the longest prefix of the window whose lists fit (read from the
+// scanned offsets at origin boundaries); the counts of the rest of the window
+// carry over to the next chunk, so every origin is counted once.  Rays and
+// sweep items of a chunk run direction by direction over that order, and the
+// J rows are scattered back to the caller's list order.
 //
 // rt_batch: a disjoint union of many models built on the device (neighbour ids
 // and CSR offsets shifted by each model's first point and entry; positions are
@@ -66,6 +69,17 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
+// out[k] = off[k * stride] for k <= n (list offsets at origin boundaries)
+__global__ void k_gather_bounds(const int64_t* __restrict__ off, int64_t stride, int64_t n, int64_t* __restrict__ out) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k <= n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = off[k * stride];
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int64_t n, int32_t* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // One model of a batch: its tables, its J and where its points start in the union.
 struct BatchSeg {
     const void* chi;
@@ -100,10 +114,13 @@ __global__ __launch_bounds__(256) void k_batch_scatter(const BatchSeg* __restric
         J[i] = J_u[g.base * F + i];
 }
 
-// Bytes of the per-chunk parts of the workspace for a chunk of c origins
-// (everything but the ray lists), and where each part starts.
+// Bytes of the per-chunk parts of the workspace for windows and chunks of up
+// to c origins (everything but the ray lists), and where each part starts:
+// two buffers of ray lengths (the window's, and the carried-over rest), the
+// offsets and their scan space, the origin-boundary offsets, per-pair u, the
+// chunk's J rows and the bins.
 struct ChunkParts {
-    size_t identity, lens, off, scan, u, Jc, bins, total;
+    size_t identity, lens, lens2, off, bnd, scan, u, Jc, bins, total;
 };
 
 ChunkParts chunk_parts(int64_t c, int64_t R, int64_t F, size_t es, bool permute, bool binned) {
@@ -111,8 +128,10 @@ ChunkParts chunk_parts(int64_t c, int64_t R, int64_t F, size_t es, bool permute,
     const int64_t rays = c * 2 * R;
     p.identity = 0;
     p.lens = p.identity + al(sizeof(int32_t) * (size_t)std::max<int64_t>(c, 1));
-    p.off = p.lens + al(sizeof(int32_t) * (size_t)std::max<int64_t>(rays, 1));
-    p.scan = p.off + al(sizeof(int64_t) * (size_t)(rays + 1));
+    p.lens2 = p.lens + al(sizeof(int32_t) * (size_t)std::max<int64_t>(rays, 1));
+    p.off = p.lens2 + al(sizeof(int32_t) * (size_t)std::max<int64_t>(rays, 1));
+    p.bnd = p.off + al(sizeof(int64_t) * (size_t)(rays + 1));
+    p.scan = p.bnd + al(sizeof(int64_t) * (size_t)(c + 1));
     p.u = p.scan + al(scan_workspace(rays));
     p.Jc = p.u + al(es * (size_t)std::max<int64_t>(c * R * F, 1));
     p.bins = p.Jc + (permute ? al(es * (size_t)std::max<int64_t>(c * F, 1)) : 0);
@@ -206,60 +225,61 @@ extern "C" rt_status rt_compute_J(const rt_model* m, const rt_dirset* set_, cons
     }
     char* cw = wp + G;
     const size_t W = ws_bytes - G;
-    // chunk size for a mean ray length L: the per-chunk parts plus lists with a 10% margin
-    auto fits = [&](int64_t c, double L) {
-        const ChunkParts cp = chunk_parts(c, R, F, es, permute, binned);
-        const double lists = 1.1 * (double)c * 2.0 * (double)R * L * 12.0 + 1024.0;
+    // window size: the per-chunk parts for w origins plus the lists of 0.8 w origins at a
+    // mean of 64 entries per ray fit the space (a window longer than its chunk keeps the
+    // rest of its counts for the next one)
+    auto fits = [&](int64_t w) {
+        const ChunkParts cp = chunk_parts(w, R, F, es, permute, binned);
+        const double lists = 0.8 * (double)w * 2.0 * (double)R * 64.0 * 12.0 + 1024.0;
         return (double)cp.total + lists <= (double)W;
     };
-    auto chunk_for = [&](int64_t remaining, double L) -> int64_t {
-        int64_t lo = 0, hi = std::min<int64_t>(remaining, MAX_SOLVE_ITEMS / (R * nfc));
-        while (lo < hi) {  // largest c that fits
-            const int64_t mid = lo + (hi - lo + 1) / 2;
-            if (fits(mid, L)) lo = mid;
-            else hi = mid - 1;
-        }
-        return std::max<int64_t>(lo, 1);
-    };
-    int64_t done_entries = 0, done_rays = 0;
-    int64_t c0 = 0;
-    int64_t c = std::min<int64_t>(chunk_for(n, 64.0), 1024);
-    int64_t* host_total = nullptr;
-    int64_t total_v = 0;
-    host_total = &total_v;
+    int64_t lo = 0, hi = std::min<int64_t>(n, MAX_SOLVE_ITEMS / (R * nfc));
+    while (lo < hi) {  // largest window that fits
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (fits(mid)) lo = mid;
+        else hi = mid - 1;
+    }
+    int64_t wmax = std::max<int64_t>(lo, 1);
+    ChunkParts cp = chunk_parts(wmax, R, F, es, permute, binned);
+    while (cp.total + 1024 > W && wmax > 1) cp = chunk_parts(wmax /= 2, R, F, es, permute, binned);
+    if (cp.total + 1024 > W) return fail(RT_ERR_CAPACITY, "rt_compute_J: workspace below the fixed part for one origin");
+    const int64_t cap = (int64_t)((W - cp.total - 512) / 12);
+    int32_t* identity = (int32_t*)(cw + cp.identity);
+    int32_t* lens = (int32_t*)(cw + cp.lens);
+    int32_t* lens_rest = (int32_t*)(cw + cp.lens2);
+    int64_t* off = (int64_t*)(cw + cp.off);
+    int64_t* bnd = (int64_t*)(cw + cp.bnd);
+    void* scan_ws = cw + cp.scan;
+    char* u_c = cw + cp.u;
+    char* J_c = cw + cp.Jc;
+    char* lists = cw + cp.total;
+    int32_t* ids = (int32_t*)lists;
+    double* Z = (double*)(lists + al(sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1)));
+    hipLaunchKernelGGL(k_iota, dim3(blocks_of(wmax, 256)), dim3(256), 0, s, identity, wmax);
+    RT_HIP(hipGetLastError());
+    std::vector<int64_t> hb;
+    int64_t c0 = 0, have = 0;  // origins [c0, c0 + have) are counted, their lengths in lens
     while (c0 < n) {
-        c = std::min(c, n - c0);
-        const ChunkParts cp = chunk_parts(c, R, F, es, permute, binned);
-        if (cp.total + 1024 > W) {
-            if (c == 1) return fail(RT_ERR_CAPACITY, "rt_compute_J: workspace below the fixed part for one origin");
-            c = std::max<int64_t>(1, c / 2);
-            continue;
+        const int64_t want = std::min(n - c0, wmax);
+        if (have < want) {  // count the window's new origins
+            const int64_t a0 = c0 + have, extra = want - have;
+            RT_HIP(launch_trace_count(m, ids_all + a0, extra, R, set->d_dirs() + (per ? 3 * R * a0 : 0), per,
+                                      lens + have * 2 * R, s, identity, o.trace_lanes));
+            have = want;
         }
-        const int64_t cap = (int64_t)((W - cp.total - 512) / 12);
-        int32_t* identity = (int32_t*)(cw + cp.identity);
-        int32_t* lens = (int32_t*)(cw + cp.lens);
-        int64_t* off = (int64_t*)(cw + cp.off);
-        void* scan_ws = cw + cp.scan;
-        char* u_c = cw + cp.u;
-        char* J_c = cw + cp.Jc;
-        char* lists = cw + cp.total;
-        int32_t* ids = (int32_t*)lists;
-        double* Z = (double*)(lists + al(sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1)));
-        const int32_t* org_c = ids_all ? ids_all + c0 : nullptr;
+        RT_HIP(launch_scan(lens, have * 2 * R, off, scan_ws, s));
+        hipLaunchKernelGGL(k_gather_bounds, dim3(blocks_of(have + 1, 256)), dim3(256), 0, s, off, 2 * R, have, bnd);
+        RT_HIP(hipGetLastError());
+        hb.resize((size_t)(have + 1));
+        RT_HIP(hipMemcpyAsync(hb.data(), bnd, sizeof(int64_t) * (size_t)(have + 1), hipMemcpyDeviceToHost, s));
+        RT_HIP(hipStreamSynchronize(s));
+        // the chunk: the longest prefix of the window whose lists fit
+        const int64_t c = (int64_t)(std::upper_bound(hb.begin(), hb.end(), cap) - hb.begin()) - 1;
+        if (c < 1) return fail(RT_ERR_CAPACITY, "rt_compute_J: one origin's rays do not fit the workspace");
+        const int64_t total = hb[(size_t)c];
+        const int32_t* org_c = ids_all + c0;
         const double* dirs_c = set->d_dirs() + (per ? 3 * R * c0 : 0);
         const double* w2_c = set->d_w2() + (per ? R * c0 : 0);
-        hipLaunchKernelGGL(k_iota, dim3(blocks_of(c, 256)), dim3(256), 0, s, identity, c);
-        RT_HIP(hipGetLastError());
-        RT_HIP(launch_trace_count(m, org_c, c, R, dirs_c, per, lens, s, identity, o.trace_lanes));
-        RT_HIP(launch_scan(lens, c * 2 * R, off, scan_ws, s));
-        RT_HIP(hipMemcpyAsync(host_total, off + c * 2 * R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        RT_HIP(hipStreamSynchronize(s));
-        const int64_t total = *host_total;
-        if (total > cap) {  // the lists do not fit: recount half the origins
-            if (c == 1) return fail(RT_ERR_CAPACITY, "rt_compute_J: one origin's rays do not fit the workspace");
-            c = std::max<int64_t>(1, c / 2);
-            continue;
-        }
         RT_HIP(launch_trace_write(m, org_c, c, R, dirs_c, per, off, ids, Z, total, s, identity, o.trace_lanes));
         SolveLaunch a = base;
         a.origins = org_c;
@@ -300,11 +320,16 @@ extern "C" rt_status rt_compute_J(const rt_model* m, const rt_dirset* set_, cons
             }
             RT_HIP(hipGetLastError());
         }
-        done_entries += total;
-        done_rays += c * 2 * R;
+        // the window's uncut origins keep their counts
+        const int64_t rest = have - c;
+        if (rest > 0) {
+            hipLaunchKernelGGL(k_copy_i32, dim3(blocks_of(rest * 2 * R, 256)), dim3(256), 0, s, lens + c * 2 * R,
+                               rest * 2 * R, lens_rest);
+            RT_HIP(hipGetLastError());
+            std::swap(lens, lens_rest);
+        }
+        have = rest;
         c0 += c;
-        const double L = std::max(1.0, (double)done_entries / (double)done_rays);
-        c = chunk_for(n - c0, L);
     }
     return RT_OK;
 }

@@ -92,10 +92,11 @@ def test_compute_J_chunked_equals_direct(rt, wind, schedule):
     assert np.array_equal(Jall[sub].cpu().numpy(), ref.cpu().numpy())
 
 
-def test_compute_J_long_rays_recount(rt, orc):
-    """Rays averaging well over the 64 entries the first chunk is sized for, in a workspace
-    far below one chunk: chunks whose lists do not fit are recounted at half the size.  FP64
-    against the oracle, FP32 against the direct solve bit for bit."""
+def test_compute_J_long_rays_window_cut(rt, orc):
+    """Rays averaging well over the 64 entries the window is sized for, in a workspace far below
+    one chunk: each chunk is the longest prefix of the counted window whose lists fit, and the
+    rest of the window keeps its counts for the next chunks.  FP64 against the oracle, FP32
+    against the direct solve bit for bit."""
     torch = _torch()
     m = _bar_model()
     model = _gpu_model(rt, m)
