@@ -106,10 +106,16 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ o
 // reads the winner's Z and row from the one lane that holds it with a ballot
 // and ds_bpermute.  The result equals a sequential scan of the row.
 //
-// List entries are buffered across the group: lane n mod GL keeps entry n, and
-// every GL steps the group stores GL consecutive ids and Z values at once, so
-// the lists are written in contiguous runs instead of one 4- and one 8-byte
-// store per step and ray.
+// List entries are buffered across the group and written in blocks of RUNL =
+// max(GL, 8) entries aligned to absolute list positions (ids 32 or 64 bytes, Z
+// 64 or 128 bytes at addresses that are multiples of those sizes), so the lists
+// reach memory as whole aligned segments.  Lane s holds entries s*EPL ..
+// s*EPL + EPL - 1 of a block (EPL = RUNL / GL, one or two), in a ring of two
+// blocks.  Every RUNL steps -- the same step for every group of the wave, so
+// the stores are issued once per wave -- each group stores the last block it
+// has completed (exactly one completes per RUNL steps); the first block of a
+// list is masked below its start, and when the ray ends the group stores what
+// is left (at most the two ring blocks).
 enum TraceMode { TRACE_COUNT = 0, TRACE_WRITE = 1, TRACE_PADDED = 2 };
 
 
@@ -182,7 +188,7 @@ __device__ inline int group_min_i(int v) {
 // origins in the same direction and share most of the rows they read.  Blocks
 // are renumbered so that each XCD (own L2) gets a contiguous range of rays.
 template <int MODE, int GL>
-__global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict__ pos,
+__global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
                                                         const NbrRec* __restrict__ nbr,
                                                         const int32_t* __restrict__ nid, int64_t P,
@@ -243,8 +249,33 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
     int32_t e0 = row0.x, deg = row0.y;
     int32_t n = 0;
     double Zc = 0.0;
-    int32_t keep_e = 0;  // entry n of the list (as a record index) waits in lane n mod GL
-    double keep_Z = 0.0;
+    constexpr int RUNL = GL >= 8 ? GL : 8;  // entries per stored block
+    constexpr int EPL = RUNL / GL;          // entries per lane per block
+    int32_t ke[2 * EPL];                    // the ring: [block][entry] as record indices
+    double kz[2 * EPL];
+#pragma unroll
+    for (int i = 0; i < 2 * EPL; ++i) {
+        ke[i] = 0;
+        kz[i] = 0.0;
+    }
+    // end of the last stored block (blocks before the one holding `base` count as stored)
+    int64_t p_last = (base & ~(int64_t)(RUNL - 1)) - 1;
+    // the group's EPL entries of the block starting at S (ring half rb), positions below
+    // `lo` and from `hi` on left out
+    auto store_block = [&](int64_t S, int rb, int64_t lo, int64_t hi) {
+        const int64_t q = S + sub * EPL;
+        if (EPL == 2 && q >= lo && q + 1 < hi) {
+            *(int2*)(ids + q) = make_int2(nid[ke[2 * rb]], nid[ke[2 * rb + 1]]);
+            *(double2*)(Zout + q) = make_double2(kz[2 * rb], kz[2 * rb + 1]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPL; ++e)
+                if (q + e >= lo && q + e < hi) {
+                    ids[q + e] = nid[ke[rb * EPL + e]];
+                    Zout[q + e] = kz[rb * EPL + e];
+                }
+        }
+    };
     for (int32_t step = 0; step < (int32_t)P; ++step) {
         Cand b;
         b.D = __builtin_inf();
@@ -297,14 +328,22 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
                 if (sub == 0) atomicOr(err, ERRBIT_CAPACITY);
                 break;
             }
-            const int slot = n & (GL - 1);
-            if (sub == slot) {
-                keep_e = emin;
-                keep_Z = Zn;
+            const int64_t at = base + n;  // absolute list position of this entry
+            const int o = (int)(at & (RUNL - 1));
+            if (sub == o / EPL) {
+                const int k = (int)((at / RUNL) & 1) * EPL + o % EPL;
+#pragma unroll
+                for (int i = 0; i < 2 * EPL; ++i)
+                    if (i == k) {
+                        ke[i] = emin;
+                        kz[i] = Zn;
+                    }
             }
-            if (slot == GL - 1) {  // GL entries buffered: one contiguous store per list
-                ids[base + (n - (GL - 1)) + sub] = nid[keep_e];
-                Zout[base + (n - (GL - 1)) + sub] = keep_Z;
+            if ((n & (RUNL - 1)) == RUNL - 1) {  // the step of the wave's stores
+                const int64_t Pend = at - ((at + 1) & (RUNL - 1));  // end of the last completed block
+                const int64_t S = Pend - (RUNL - 1);
+                store_block(S, (int)((S / RUNL) & 1), base, at + 1);
+                p_last = Pend;
             }
         }
         ++n;
@@ -312,11 +351,11 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(const double* __restrict_
         deg = deg_n;
         Zc = Zn;
     }
-    if (MODE != TRACE_COUNT) {  // entries still buffered
-        const int32_t done = n & ~(GL - 1);
-        if (sub < n - done) {
-            ids[base + done + sub] = nid[keep_e];
-            Zout[base + done + sub] = keep_Z;
+    if (MODE != TRACE_COUNT) {  // what is left: at most the two ring blocks after p_last
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            const int64_t S = p_last + 1 + (int64_t)b2 * RUNL;
+            if (S < base + n) store_block(S, (int)((S / RUNL) & 1), base, base + n);
         }
     }
     if (MODE != TRACE_WRITE && sub == 0) lens[ray] = n;
