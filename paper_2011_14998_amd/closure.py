@@ -126,33 +126,27 @@ class ClosureNet:
 def train(X, T, norm: Normalizer, steps: int = 20000, batch: int = 8192, lr: float = 1e-3,
           lr_final: float = 1e-5, wd: float = 0.0, seed: int = 0, log_every: int = 2000,
           verbose: bool = True) -> ClosureNet:
-    """Adam on the mean Gaussian NLL over minibatches drawn with replacement (seeded) from
-    the samples X (BF16 bits, [N][16]) with targets T ([N]); cosine learning-rate decay."""
+    """Adam on the mean Gaussian NLL over minibatches drawn with replacement from the samples X
+    (BF16 bits, [N][16]) with targets T ([N]), cosine learning-rate decay: rt_mlp_train, one
+    captured step replayed log_every times per call (rows drawn on the device from the seed)."""
     torch = _torch()
-    N = X.shape[0]
     net = rt.MLP(seed=seed)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    dY = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
-    Y = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
     hist = []
     t0 = time.time()
-    for step in range(steps):
-        rows = torch.randint(0, N, (batch,), generator=gen, device="cuda", dtype=torch.int32)
-        a = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(1, steps)))
-        net.forward(X, rows=rows, Y=Y, keep=True)
-        rt.mlp_nll(Y, T, rows=rows, dY=dY, loss_sum=loss)
-        net.zero_grad()
-        net.backward(X, dY, rows=rows)
-        net.adam_step(lr=a, wd=wd)
-        if (step + 1) % log_every == 0 or step + 1 == steps:
-            avg = loss.item() / (log_every * batch)
-            loss.zero_()
-            hist.append(avg)
-            if verbose:
-                print(f"  train step {step + 1}/{steps}: mean NLL {avg:.4f}, lr {a:.2e}, "
-                      f"{time.time() - t0:.1f} s", flush=True)
+    done = 0
+    while done < steps:
+        k = min(log_every, steps - done)
+        net.train(X, T, k, batch=batch, total_steps=steps, lr=lr, lr_final=lr_final, wd=wd, seed=seed,
+                  loss_sum=loss)
+        done += k
+        avg = loss.item() / (k * batch)
+        loss.zero_()
+        hist.append(avg)
+        if verbose:
+            a = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * (done - 1) / max(1, steps)))
+            print(f"  train step {done}/{steps}: mean NLL {avg:.4f}, lr {a:.2e}, {time.time() - t0:.1f} s",
+                  flush=True)
     torch.cuda.synchronize()
     net.set_input_norm(norm.mean, norm.inv_std)
     return ClosureNet(net, norm, hist)

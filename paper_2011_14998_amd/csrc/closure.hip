@@ -244,49 +244,92 @@ __device__ inline v4f32 mfma32(v8i16 a, v8i16 b, v4f32 c) {
 }
 __device__ inline v8i16 ld8(const uint16_t* p) { return *(const v8i16*)p; }  // 16-byte aligned
 
-// bias, BF16 z, SiLU, BF16 h for the lane's 2 x 4 accumulator tiles; h into LDS, z (KEEP) to HBM
+// Each tile is taken in two halves of 32 samples, A and B, one half behind
+// the other: while a wave's matrix products of one half run, its epilogue
+// (bias, BF16 z, SiLU, BF16 h) of the other half's previous layer is issued
+// between them, so the matrix cores and the vector ALUs work at the same time
+// instead of in turns between the layer barriers.  Phases of a tile (each
+// ends at a barrier; M = products, E = epilogue, layer 1..3):
+//   M(B,1)+E(A,1), M(A,2)+E(B,1), M(B,2)+E(A,2), M(A,3)+E(B,2), M(B,3)+E(A,3),
+//   E(B,3) with the next tile's input load, then the head of this tile with
+//   M(A,1) of the next.  Layer l's activations go to ha (l odd) or hb (l even),
+//   rows 0-31 for A and 32-63 for B, so no phase writes rows another reads.
+
+// bias, BF16 z, SiLU, BF16 h of accumulator block (nt, mt) of half hf; h into LDS, z (KEEP) to HBM
 template <bool KEEP>
-__device__ __attribute__((always_inline)) inline void ws_epilogue(const v4f32 (&acc)[2][4], const float* sbias,
-                                                                  uint16_t* out, uint16_t* __restrict__ zout,
-                                                                  int64_t row0, int nvalid, int wv, int g, int r) {
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const int n0 = 32 * wv + 16 * nt + 4 * g;
-        const float4 bb = *(const float4*)(sbias + n0);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int m = 16 * mt + r;
-            const uint32_t z01 = f2bf2(acc[nt][mt][0] + bb.x, acc[nt][mt][1] + bb.y);
-            const uint32_t z23 = f2bf2(acc[nt][mt][2] + bb.z, acc[nt][mt][3] + bb.w);
-            const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
-            const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
-            *(uint2*)(out + m * LDP + n0) = make_uint2(h01, h23);
-            if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
-        }
-    }
+__device__ __attribute__((always_inline)) inline void ws_epi_block(const v4f32& acc, const float* sbias,
+                                                                   uint16_t* out, uint16_t* __restrict__ zout,
+                                                                   int64_t row0, int nvalid, int hf, int nt, int mt,
+                                                                   int wv, int g, int r) {
+    const int n0 = 32 * wv + 16 * nt + 4 * g;
+    const int m = 16 * (2 * hf + mt) + r;
+    const float4 bb = *(const float4*)(sbias + n0);
+    const uint32_t z01 = f2bf2(acc[0] + bb.x, acc[1] + bb.y);
+    const uint32_t z23 = f2bf2(acc[2] + bb.z, acc[3] + bb.w);
+    const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
+    const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
+    *(uint2*)(out + m * LDP + n0) = make_uint2(h01, h23);
+    if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
 }
 
-template <bool KEEP>
-__device__ __attribute__((always_inline)) inline void ws_hidden(const uint16_t* in, const v8i16 (&wr)[2][8],
-                                                                const float* sbias, uint16_t* out,
-                                                                uint16_t* __restrict__ zout, int64_t row0,
-                                                                int nvalid, int wv, int g, int r) {
-    v4f32 acc[2][4];
+// One phase of a hidden layer: the products of half hm (activations `in`, weights in
+// registers) into accm, with the epilogue of half he from acce (if EPI) spread between them.
+template <bool KEEP, bool EPI>
+__device__ __attribute__((always_inline)) inline void ws_phase(const uint16_t* in, const v8i16 (&wr)[2][8], int hm,
+                                                               v4f32 (&accm)[2][2], const v4f32 (&acce)[2][2],
+                                                               int he, const float* sbias, uint16_t* out,
+                                                               uint16_t* __restrict__ zout, int64_t row0, int nvalid,
+                                                               int wv, int g, int r) {
+    v4f32 acc[2][2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
-        v8i16 b[4];
+        v8i16 b[2];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) b[mt] = ld8(in + (16 * mt + r) * LDP + 32 * ks + 8 * g);
+        for (int mt = 0; mt < 2; ++mt) b[mt] = ld8(in + (16 * (2 * hm + mt) + r) * LDP + 32 * ks + 8 * g);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma32(wr[nt][ks], b[mt], acc[nt][mt]);
+            for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = mfma32(wr[nt][ks], b[mt], acc[nt][mt]);
+        if (EPI && (ks & 1)) {
+            const int q = ks >> 1, nt = q >> 1, mt = q & 1;
+            ws_epi_block<KEEP>(acce[nt][mt], sbias, out, zout, row0, nvalid, he, nt, mt, wv, g, r);
+        }
     }
-    ws_epilogue<KEEP>(acc, sbias, out, zout, row0, nvalid, wv, g, r);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) accm[nt][mt] = acc[nt][mt];
+}
+
+// epilogue of a whole half
+template <bool KEEP>
+__device__ __attribute__((always_inline)) inline void ws_epi_half(const v4f32 (&acc)[2][2], int hf,
+                                                                  const float* sbias, uint16_t* out,
+                                                                  uint16_t* __restrict__ zout, int64_t row0,
+                                                                  int nvalid, int wv, int g, int r) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            ws_epi_block<KEEP>(acc[nt][mt], sbias, out, zout, row0, nvalid, hf, nt, mt, wv, g, r);
+}
+
+// layer 1 products of half hf: one k-step of 32 (inputs 16..31 and their weights are zero)
+__device__ __attribute__((always_inline)) inline void ws_l1(const uint16_t* sx, const uint16_t* sw1, int hf,
+                                                            v4f32 (&acc)[2][2], int wv, int g, int r) {
+    v8i16 a[2], b[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) a[nt] = ld8(sw1 + (32 * wv + 16 * nt + r) * LDW1 + 8 * g);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) b[mt] = ld8(sx + (16 * (2 * hf + mt) + r) * LDXP + 8 * g);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = mfma32(a[nt], b[mt], (v4f32){0.f, 0.f, 0.f, 0.f});
 }
 
 template <bool KEEP>
@@ -327,36 +370,42 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restric
     uint16_t* Z1 = KEEP ? Z : nullptr;
     uint16_t* Z2 = KEEP ? Z + n * HW : nullptr;
     uint16_t* Z3 = KEEP ? Z + 2 * n * HW : nullptr;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const int64_t row0 = tile * PT;
-        const int nvalid = (int)(n - row0 < PT ? n - row0 : PT);
-        if (t < PT * 4) {  // 64 samples x 16 inputs, 4 per thread
+    // 64 samples x 16 inputs of tile tl into sx, 4 per thread (zero beyond n)
+    auto load_x = [&](int64_t tl) {
+        if (t < PT * 4) {
+            const int64_t r0 = tl * PT;
             const int m = t >> 2, q = t & 3;
             v4i16 v = (v4i16){0, 0, 0, 0};
-            if (m < nvalid) {
-                const int64_t src = rows ? (int64_t)rows[row0 + m] : row0 + m;
+            if (r0 + m < n) {
+                const int64_t src = rows ? (int64_t)rows[r0 + m] : r0 + m;
                 v = ld4(X + src * DIN + 4 * q);
             }
             *(v4i16*)(sx + m * LDXP + 4 * q) = v;
         }
-        __syncthreads();  // also: the previous tile's head has read ha
-        {  // layer 1: one k-step of 32 (inputs 16..31 and their weights are zero)
-            v4f32 acc[2][4];
-            v8i16 a[2], b[4];
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) a[nt] = ld8(sw1 + (32 * wv + 16 * nt + r) * LDW1 + 8 * g);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) b[mt] = ld8(sx + (16 * mt + r) * LDXP + 8 * g);
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma32(a[nt], b[mt], (v4f32){0.f, 0.f, 0.f, 0.f});
-            ws_epilogue<KEEP>(acc, sbias, ha, Z1, row0, nvalid, wv, g, r);
-        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile >= tiles) return;  // the grid never exceeds the tile count; every wave leaves together
+    load_x(tile);
+    __syncthreads();
+    v4f32 aA[2][2], aB[2][2];
+    ws_l1(sx, sw1, 0, aA, wv, g, r);
+    for (;;) {
+        const int64_t row0 = tile * PT;
+        const int nvalid = (int)(n - row0 < PT ? n - row0 : PT);
+        ws_l1(sx, sw1, 1, aB, wv, g, r);
+        ws_epi_half<KEEP>(aA, 0, sbias, ha, Z1, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_hidden<KEEP>(ha, w2r, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(ha, w2r, 0, aA, aB, 1, sbias, ha, Z1, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_hidden<KEEP>(hb, w3r, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(ha, w2r, 1, aB, aA, 0, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        __syncthreads();
+        ws_phase<KEEP, true>(hb, w3r, 0, aA, aB, 1, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        __syncthreads();
+        ws_phase<KEEP, true>(hb, w3r, 1, aB, aA, 0, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        __syncthreads();
+        ws_epi_half<KEEP>(aB, 1, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        const int64_t next = tile + gridDim.x;
+        if (next < tiles) load_x(next);  // sx was last read by this tile's M(B,1)
         __syncthreads();
         if (wv < 4) {  // head: wave wv takes samples 16 wv .. 16 wv + 15; A = W4t rows 0, 1 (others zero)
             v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
@@ -368,6 +417,10 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restric
             const int m = 16 * wv + r;
             if (g == 0 && m < nvalid) *(float2*)(Y + (row0 + m) * DOUT) = make_float2(acc[0] + b40, acc[1] + b41);
         }
+        if (next >= tiles) break;
+        ws_l1(sx, sw1, 0, aA, wv, g, r);
+        __syncthreads();  // the head has read ha before the next tile writes it
+        tile = next;
     }
 }
 
@@ -393,70 +446,95 @@ constexpr int BT = 32;  // samples per signal-pass tile
 // per-workgroup small partials: W4 [256][2], b4, b3, b2, b1
 constexpr int SP_W4 = 0, SP_B4 = SP_W4 + HW * DOUT, SP_B3 = SP_B4 + DOUT, SP_B2 = SP_B3 + HW, SP_B1 = SP_B2 + HW;
 constexpr int SMALLP = (SP_B1 + HW + 7) / 8 * 8;
-// per-chunk weight partials: W1 [16][256], W2, W3 [256][256]
-constexpr int64_t BP_W1 = 0, BP_W2 = BP_W1 + DIN * HW, BP_W3 = BP_W2 + HW * HW, NBIG = BP_W3 + HW * HW;
+// per-chunk partials: W1 [16][256], W2, W3 [256][256], then the chunk's share of the small partials
+constexpr int64_t BP_W1 = 0, BP_W2 = BP_W1 + DIN * HW, BP_W3 = BP_W2 + HW * HW, BP_SMALL = BP_W3 + HW * HW,
+                  NBIG = BP_SMALL + SMALLP;
+constexpr int SMALL_JOBS = (SMALLP + 255) / 256;  // weight-pass jobs summing the small partials
+constexpr int WG_JOBS = 36 + SMALL_JOBS;         // weight-pass jobs per chunk
 constexpr int MAX_WCHUNKS = 64;
 
-// rows [0, 32) of Z (zero beyond nvalid) into s[m][LDH]
-__device__ inline void bwd_load_z(const uint16_t* __restrict__ Z, uint16_t* s, int64_t row0, int nvalid) {
+constexpr int SIG_THREADS = 512;  // signal-pass workgroup: 8 waves; thread (j, hs) owns column j, half hs
+constexpr int SIG_HALF = BT / 2;   // samples of a half
+
+// Rows [0, 32) of a Z tile (zero beyond nvalid): the thread's share loaded into registers
+// (all three layers' tiles are fetched together at the start of a tile) and later put in LDS.
+constexpr int ZPT = BT * HW / 8 / SIG_THREADS;  // 16-byte pieces per thread
+__device__ inline void bwd_fetch_z(const uint16_t* __restrict__ Z, uint4 (&v)[ZPT], int64_t row0, int nvalid) {
 #pragma unroll
-    for (int i = 0; i < BT * HW / 8 / 256; ++i) {
-        const int idx = threadIdx.x + 256 * i, m = idx >> 5, c = idx & 31;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (m < nvalid) v = *(const uint4*)(Z + (row0 + m) * HW + 8 * c);
-        *(uint4*)(s + m * LDH + 8 * c) = v;
+    for (int i = 0; i < ZPT; ++i) {
+        const int idx = threadIdx.x + SIG_THREADS * i, m = idx >> 5, c = idx & 31;
+        v[i] = m < nvalid ? *(const uint4*)(Z + (row0 + m) * HW + 8 * c) : make_uint4(0, 0, 0, 0);
+    }
+}
+__device__ inline void bwd_put_z(const uint4 (&v)[ZPT], uint16_t* s) {
+#pragma unroll
+    for (int i = 0; i < ZPT; ++i) {
+        const int idx = threadIdx.x + SIG_THREADS * i, m = idx >> 5, c = idx & 31;
+        *(uint4*)(s + m * LDH + 8 * c) = v[i];
     }
 }
 
-// HT[j][row0 + m] = bf16(silu(z[m][j])) for column j = threadIdx.x (zero beyond nvalid)
+// HT[j][row0 + m] = bf16(silu(z[m][j])) for the thread's column j and half hs (zero beyond nvalid)
 __device__ inline void bwd_store_ht(const uint16_t* sz, uint16_t* __restrict__ HT, int64_t npad, int64_t row0,
-                                    int nvalid) {
-    const int j = threadIdx.x;
+                                    int nvalid, int j, int hs) {
 #pragma unroll
-    for (int q = 0; q < BT / 8; ++q) {
+    for (int q = 0; q < SIG_HALF / 8; ++q) {
         uint32_t p[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int m = 8 * q + 2 * i;
+            const int m = SIG_HALF * hs + 8 * q + 2 * i;
             const float h0 = m < nvalid ? silu(bf2f(sz[m * LDH + j])) : 0.f;
             const float h1 = m + 1 < nvalid ? silu(bf2f(sz[(m + 1) * LDH + j])) : 0.f;
             p[i] = f2bf2(h0, h1);
         }
-        *(uint4*)(HT + (int64_t)j * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
+        *(uint4*)(HT + (int64_t)j * npad + row0 + SIG_HALF * hs + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
     }
 }
 
+// The wave's B operands of a weight matrix for all 8 k-steps (W as the [K][N] copy, rows
+// j in [32w, 32w+32)), loaded ahead of the product that uses them.
+__device__ __attribute__((always_inline)) inline void bwd_load_w(const uint16_t* __restrict__ Wb,
+                                                                 v8i16 (&wf)[8][2]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) wf[ks][nt] = ld8(Wb + (int64_t)(32 * wv + 16 * nt + r) * HW + 32 * ks + 8 * g);
+}
+
 // dZ_prev[m][j] = bf16((sum_n dZ[m][n] W[j][n]) silu'(z[m][j])) for the tile: dZ in sd
-// (replaced by dZ_prev), z in sz, W as the [K][N] copy; dZ_prev also to dZT[j][sample].
+// (replaced by dZ_prev), z in sz, W's fragments in wf; dZ_prev also to dZT[j][sample].
+// Once the products are issued, wf is refilled from Wnext for the next product.
 __device__ __attribute__((always_inline)) inline void bwd_signal_layer(uint16_t* sd, const uint16_t* sz,
-                                                                       const uint16_t* __restrict__ Wb,
+                                                                       v8i16 (&wf)[8][2],
+                                                                       const uint16_t* __restrict__ Wnext,
                                                                        uint16_t* __restrict__ dZT, int64_t npad,
                                                                        int64_t row0, int nvalid) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
-    v4f32 acc[2][4];
+    v4f32 acc[2][2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int k0 = 0; k0 < HW; k0 += 32) {
-        v8i16 a[2], b[4];
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = ld8(Wb + (int64_t)(64 * wv + 16 * nt + r) * HW + k0 + 8 * g);
+    for (int ks = 0; ks < 8; ++ks) {
+        v8i16 a[2];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) a[mt] = ld8(sd + (16 * mt + r) * LDH + k0 + 8 * g);
+        for (int mt = 0; mt < 2; ++mt) a[mt] = ld8(sd + (16 * mt + r) * LDH + 32 * ks + 8 * g);
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma32(a[mt], b[nt], acc[mt][nt]);
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma32(a[mt], wf[ks][nt], acc[mt][nt]);
     }
+    bwd_load_w(Wnext, wf);
     __syncthreads();  // every wave has read dZ before it is replaced
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int j = 64 * wv + 16 * nt + r, m0 = 16 * mt + 4 * g;
+        for (int nt = 0; nt < 2; ++nt) {
+            const int j = 32 * wv + 16 * nt + r, m0 = 16 * mt + 4 * g;
             uint16_t d[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -471,15 +549,18 @@ __device__ __attribute__((always_inline)) inline void bwd_signal_layer(uint16_t*
 
 // Signal pass over tiles blockIdx.x, +gridDim.x, ...; T holds dZT3, dZT2, dZT1, HT2, HT1
 // ([256][npad] each), XT the inputs [16][npad]; sp[blockIdx.x][SMALLP] the small partials.
-__global__ __launch_bounds__(256, 2) void k_bwd_signal(const uint16_t* __restrict__ wb, const float* __restrict__ w,
-                                                     const uint16_t* __restrict__ X, const int32_t* __restrict__ rows,
-                                                     int64_t n, int64_t npad, const uint16_t* __restrict__ Z,
-                                                     const float* __restrict__ dY, uint16_t* __restrict__ T,
-                                                     uint16_t* __restrict__ XT, float* __restrict__ sp) {
+__global__ __launch_bounds__(SIG_THREADS, 1) void k_bwd_signal(const uint16_t* __restrict__ wb,
+                                                               const float* __restrict__ w,
+                                                               const uint16_t* __restrict__ X,
+                                                               const int32_t* __restrict__ rows, int64_t n,
+                                                               int64_t npad, const uint16_t* __restrict__ Z,
+                                                               const float* __restrict__ dY, uint16_t* __restrict__ T,
+                                                               uint16_t* __restrict__ XT, float* __restrict__ sp) {
     __shared__ __attribute__((aligned(16))) uint16_t sd[BT * LDH];  // dZ of the current layer, [m][j]
     __shared__ __attribute__((aligned(16))) uint16_t sz[BT * LDH];  // z of the layer below, [m][j]
     __shared__ float sdy[BT * DOUT];
-    const int t = threadIdx.x, j = t;
+    __shared__ float sred[6 * HW];  // the second half's column partials, added in a fixed order
+    const int t = threadIdx.x, j = t & (HW - 1), hs = t / HW;
     const int64_t tiles = npad / BT, plane = HW * npad;
     const uint16_t* Z1 = Z;
     const uint16_t* Z2 = Z + n * HW;
@@ -490,7 +571,9 @@ __global__ __launch_bounds__(256, 2) void k_bwd_signal(const uint16_t* __restric
     uint16_t* HT2 = T + 3 * plane;
     uint16_t* HT1 = T + 4 * plane;
     const float w40 = bf2f(f2bf(w[OFF_W4 + j * DOUT])), w41 = bf2f(f2bf(w[OFF_W4 + j * DOUT + 1]));
-    float gw0 = 0.f, gw1 = 0.f, gb3 = 0.f, gb2 = 0.f, gb1 = 0.f, gb4 = 0.f;  // column j's partials
+    float gw0 = 0.f, gw1 = 0.f, gb3 = 0.f, gb2 = 0.f, gb1 = 0.f, gb4 = 0.f;  // partials of column j, half hs
+    v8i16 wf[8][2];
+    bwd_load_w(wb + WB3, wf);
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t row0 = tile * BT;
         const int nvalid = (int)(n - row0 < BT ? n - row0 : BT);
@@ -511,16 +594,21 @@ __global__ __launch_bounds__(256, 2) void k_bwd_signal(const uint16_t* __restric
             }
             *(uint4*)(XT + (int64_t)k * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
         }
-        bwd_load_z(Z3, sz, row0, nvalid);
+        uint4 z3[ZPT], z2[ZPT], z1[ZPT];
+        bwd_fetch_z(Z3, z3, row0, nvalid);
+        bwd_fetch_z(Z2, z2, row0, nvalid);
+        bwd_fetch_z(Z1, z1, row0, nvalid);
+        bwd_put_z(z3, sz);
         __syncthreads();
-        // head, column j: dW4[j][c] += sum_m h3[m][j] dY[m][c]; dZ3 = bf16((dY W4^T) silu'(z3))
+        // head, column j, samples of half hs: dW4[j][c] += sum_m h3[m][j] dY[m][c];
+        // dZ3 = bf16((dY W4^T) silu'(z3))
         {
 #pragma unroll 1
-            for (int q = 0; q < BT / 8; ++q) {
+            for (int q = 0; q < SIG_HALF / 8; ++q) {
                 uint32_t p[4];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const int m = 8 * q + i;
+                    const int m = SIG_HALF * hs + 8 * q + i;
                     const float z = bf2f(sz[m * LDH + j]);
                     const bool ok = m < nvalid;
                     const float h = ok ? bf2f(f2bf(silu(z))) : 0.f;
@@ -533,33 +621,44 @@ __global__ __launch_bounds__(256, 2) void k_bwd_signal(const uint16_t* __restric
                     if (i & 1) p[i >> 1] |= (uint32_t)dz << 16;
                     else p[i >> 1] = dz;
                 }
-                *(uint4*)(dZT3 + (int64_t)j * npad + row0 + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
+                *(uint4*)(dZT3 + (int64_t)j * npad + row0 + SIG_HALF * hs + 8 * q) = make_uint4(p[0], p[1], p[2], p[3]);
             }
             if (j < DOUT)
-                for (int m = 0; m < BT; ++m) gb4 += sdy[m * DOUT + j];
+                for (int m = SIG_HALF * hs; m < SIG_HALF * (hs + 1); ++m) gb4 += sdy[m * DOUT + j];
         }
         __syncthreads();  // sz (z3) and sdy are read
-        bwd_load_z(Z2, sz, row0, nvalid);
+        bwd_put_z(z2, sz);
         __syncthreads();
-        bwd_store_ht(sz, HT2, npad, row0, nvalid);
-        bwd_signal_layer(sd, sz, wb + WB3, dZT2, npad, row0, nvalid);
+        bwd_store_ht(sz, HT2, npad, row0, nvalid, j, hs);
+        bwd_signal_layer(sd, sz, wf, wb + WB2, dZT2, npad, row0, nvalid);
         __syncthreads();
-        for (int m = 0; m < BT; ++m) gb2 += bf2f(sd[m * LDH + j]);
-        bwd_load_z(Z1, sz, row0, nvalid);
+        for (int m = SIG_HALF * hs; m < SIG_HALF * (hs + 1); ++m) gb2 += bf2f(sd[m * LDH + j]);
+        bwd_put_z(z1, sz);
         __syncthreads();
-        bwd_store_ht(sz, HT1, npad, row0, nvalid);
-        bwd_signal_layer(sd, sz, wb + WB2, dZT1, npad, row0, nvalid);
+        bwd_store_ht(sz, HT1, npad, row0, nvalid, j, hs);
+        bwd_signal_layer(sd, sz, wf, wb + WB3, dZT1, npad, row0, nvalid);  // W3 again for the next tile
         __syncthreads();
-        for (int m = 0; m < BT; ++m) gb1 += bf2f(sd[m * LDH + j]);
+        for (int m = SIG_HALF * hs; m < SIG_HALF * (hs + 1); ++m) gb1 += bf2f(sd[m * LDH + j]);
         __syncthreads();  // before the next tile overwrites sd, sz, sdy
     }
-    float* part = sp + blockIdx.x * (int64_t)SMALLP;
-    part[SP_W4 + j * DOUT] = gw0;
-    part[SP_W4 + j * DOUT + 1] = gw1;
-    part[SP_B3 + j] = gb3;
-    part[SP_B2 + j] = gb2;
-    part[SP_B1 + j] = gb1;
-    if (j < DOUT) part[SP_B4 + j] = gb4;
+    if (hs == 1) {
+        sred[0 * HW + j] = gw0;
+        sred[1 * HW + j] = gw1;
+        sred[2 * HW + j] = gb3;
+        sred[3 * HW + j] = gb2;
+        sred[4 * HW + j] = gb1;
+        sred[5 * HW + j] = gb4;
+    }
+    __syncthreads();
+    if (hs == 0) {
+        float* part = sp + blockIdx.x * (int64_t)SMALLP;
+        part[SP_W4 + j * DOUT] = gw0 + sred[0 * HW + j];
+        part[SP_W4 + j * DOUT + 1] = gw1 + sred[1 * HW + j];
+        part[SP_B3 + j] = gb3 + sred[2 * HW + j];
+        part[SP_B2 + j] = gb2 + sred[3 * HW + j];
+        part[SP_B1 + j] = gb1 + sred[4 * HW + j];
+        if (j < DOUT) part[SP_B4 + j] = gb4 + sred[5 * HW + j];
+    }
 }
 
 // One 16*MTA x 64 block of dW = A^T B over the 32-sample steps [s0, s1) of the
@@ -625,15 +724,29 @@ __device__ __attribute__((always_inline)) inline void wgrad_block(const uint16_t
 
 // Weight pass: workgroup b takes chunk b % n_chunks of job b / n_chunks; jobs 0..15 are the
 // 64 x 64 blocks of W3 (H2^T dZ3), 16..31 those of W2 (H1^T dZ2), 32..35 the
-// 16 x 64 blocks of W1 (X^T dZ1).  bp[chunk][NBIG] receives the chunk's partials.
+// 16 x 64 blocks of W1 (X^T dZ1), and jobs 36.. add the chunk's share of the signal pass's
+// small partials (its groups, in order; 256 of them per job).  bp[chunk][NBIG] receives the
+// chunk's partials.
 __global__ __launch_bounds__(256) void k_bwd_wgrad(const uint16_t* __restrict__ T, const uint16_t* __restrict__ XT,
-                                                    int64_t npad, int n_chunks, float* __restrict__ bp) {
+                                                    int64_t npad, int n_chunks, const float* __restrict__ sp,
+                                                    int n_groups, float* __restrict__ bp) {
     __shared__ __attribute__((aligned(16))) float red[4 * 4 * 4 * 4 * 64];
     const int64_t plane = HW * npad;
     const int chunk = (int)(blockIdx.x % n_chunks), job = (int)(blockIdx.x / n_chunks);
     const int64_t steps = npad / 32, per = (steps + n_chunks - 1) / n_chunks;
     const int64_t s0 = chunk * per, s1 = s0 + per < steps ? s0 + per : steps;
     float* base = bp + chunk * NBIG;
+    if (job >= 36) {
+        const int g0 = (int)((int64_t)chunk * n_groups / n_chunks), g1 = (int)((int64_t)(chunk + 1) * n_groups / n_chunks);
+        const int i = (job - 36) * 256 + threadIdx.x;
+        if (i < SMALLP) {
+            float acc = 0.f;
+#pragma unroll 8
+            for (int gi = g0; gi < g1; ++gi) acc += sp[(int64_t)gi * SMALLP + i];
+            base[BP_SMALL + i] = acc;
+        }
+        return;
+    }
     if (job < 32) {
         const int mat = job < 16 ? 3 : 2, blk = job & 15, jb = blk >> 2, nb4 = blk & 3;
         const uint16_t* A = (mat == 3 ? T + 3 * plane : T + 4 * plane) + (int64_t)(64 * jb) * npad;  // HT2 / HT1
@@ -647,32 +760,21 @@ __global__ __launch_bounds__(256) void k_bwd_wgrad(const uint16_t* __restrict__ 
     }
 }
 
-// grad[p] += the partials of p in order: weight-pass chunks for W1..W3, signal-pass workgroups otherwise
-__global__ void k_grad_sum(const float* __restrict__ bp, int n_chunks, const float* __restrict__ sp, int n_groups,
-                           float* __restrict__ grad) {
+// grad[p] += the chunk partials of p, in chunk order
+__global__ void k_grad_sum(const float* __restrict__ bp, int n_chunks, float* __restrict__ grad) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= NPARAM) return;
-    int64_t src = -1, stride = 0, cnt = 0;
-    const float* base = nullptr;
-    if (p >= OFF_W1 && p < OFF_B1) src = BP_W1 + (p - OFF_W1);
-    else if (p >= OFF_W2 && p < OFF_B2) src = BP_W2 + (p - OFF_W2);
-    else if (p >= OFF_W3 && p < OFF_B3) src = BP_W3 + (p - OFF_W3);
-    if (src >= 0) {
-        base = bp;
-        stride = NBIG;
-        cnt = n_chunks;
-    } else {
-        if (p >= OFF_B1 && p < OFF_W2) src = SP_B1 + (p - OFF_B1);
-        else if (p >= OFF_B2 && p < OFF_W3) src = SP_B2 + (p - OFF_B2);
-        else if (p >= OFF_B3 && p < OFF_W4) src = SP_B3 + (p - OFF_B3);
-        else if (p >= OFF_W4 && p < OFF_B4) src = SP_W4 + (p - OFF_W4);
-        else src = SP_B4 + (p - OFF_B4);
-        base = sp;
-        stride = SMALLP;
-        cnt = n_groups;
-    }
+    int64_t src;
+    if (p < OFF_B1) src = BP_W1 + (p - OFF_W1);
+    else if (p < OFF_W2) src = BP_SMALL + SP_B1 + (p - OFF_B1);
+    else if (p < OFF_B2) src = BP_W2 + (p - OFF_W2);
+    else if (p < OFF_W3) src = BP_SMALL + SP_B2 + (p - OFF_B2);
+    else if (p < OFF_B3) src = BP_W3 + (p - OFF_W3);
+    else if (p < OFF_W4) src = BP_SMALL + SP_B3 + (p - OFF_B3);
+    else if (p < OFF_B4) src = BP_SMALL + SP_W4 + (p - OFF_W4);
+    else src = BP_SMALL + SP_B4 + (p - OFF_B4);
     float s = 0.f;
-    for (int64_t c = 0; c < cnt; ++c) s += base[c * stride + src];
+    for (int c = 0; c < n_chunks; ++c) s += bp[(int64_t)c * NBIG + src];
     grad[p] += s;
 }
 
@@ -1139,12 +1241,11 @@ extern "C" rt_status rt_mlp_backward(rt_mlp* h, const uint16_t* X, const int32_t
     float* sp = (float*)(base + b.sp);
     float* bp = (float*)(base + b.bp);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_bwd_signal, dim3((unsigned)b.groups), dim3(256), 0, s, h->wb, h->w, X, rows, n, b.npad,
+    hipLaunchKernelGGL(k_bwd_signal, dim3((unsigned)b.groups), dim3(SIG_THREADS), 0, s, h->wb, h->w, X, rows, n, b.npad,
                        (const uint16_t*)ws, dY, T, XT, sp);
-    hipLaunchKernelGGL(k_bwd_wgrad, dim3((unsigned)(36 * b.chunks)), dim3(256), 0, s, T, XT, b.npad, (int)b.chunks,
-                       bp);
-    hipLaunchKernelGGL(k_grad_sum, dim3(nb(NPARAM, 256)), dim3(256), 0, s, bp, (int)b.chunks, sp, (int)b.groups,
-                       h->g);
+    hipLaunchKernelGGL(k_bwd_wgrad, dim3((unsigned)(WG_JOBS * b.chunks)), dim3(256), 0, s, T, XT, b.npad,
+                       (int)b.chunks, sp, (int)b.groups, bp);
+    hipLaunchKernelGGL(k_grad_sum, dim3(nb(NPARAM, 256)), dim3(256), 0, s, bp, (int)b.chunks, h->g);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
