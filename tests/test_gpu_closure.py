@@ -218,6 +218,27 @@ def test_mlp_gradients_training_batch(rt):
     torch.cuda.synchronize()
 
 
+def test_mlp_gradients_many_samples(rt):
+    """70 001 samples: more tiles than signal-pass workgroups (each takes several), 64 sample
+    chunks in the weight pass and a ragged last tile; same bars against the oracle."""
+    flat = _params(24)
+    net = rt.MLP(seed=0)
+    net.set_params(flat)
+    n = 70_001
+    X = _inputs(25, n)
+    Xb = _t(_bf16_bits(X))
+    T = np.random.default_rng(26).normal(0, 0.5, n).astype(np.float32)
+    Y = net.forward(Xb, keep=True)
+    dY = rt.mlp_nll(Y, _t(T))
+    net.zero_grad()
+    net.backward(Xb, dY)
+    g = net.get_grads()
+    errs = _grad_errors(g, flat, oc.bf16_round(X), dY.cpu().numpy().astype(np.float64))
+    for (name, key), e in errs.items():
+        print(f"grad {name} ({key}): rel {e:.2e}")
+        assert e <= (1e-3 if key == "mirrored" else 1e-2), (name, key, e)
+
+
 def _splitmix_rows(seed, step, batch, N):
     """Rows of training step `step` by the SplitMix64 finaliser (Steele, Lea and Flood 2014)."""
     M = np.uint64(0xFFFFFFFFFFFFFFFF)
