@@ -180,6 +180,27 @@ __device__ inline void row(SweepState<T>& st, bool far_end, T b, T S, T I) {
     st.a = b;
 }
 
+// Row d of the second-order elimination for a point of opacity c whose source the
+// next row needs: the row's reciprocal r = 1/D (D = 1 + b G) and 1/c come from one
+// reciprocal of their product, q = 1/(D c), r = q c, 1/c = q D (three multiplies
+// instead of a second quarter-rate reciprocal; D >= 1 and c > 0, so the product
+// neither cancels nor, for opacities below ~1e30, overflows).  Returns 1/c.  The sweep
+// starts a side from the state G = 1, r = 1, a = 0, Y = I, on which this generic row
+// with the far end's step is the far-end row of `row` (G = 1 + b/2, Y = (b/2 S + I) r),
+// and runs it for the first point too, with b = 0: that row leaves G = 1, a = 0 and
+// r, Y within an ulp of 1 and I, and yields the first point's 1/c.
+template <typename T>
+__device__ inline T row_rc(SweepState<T>& st, T b, T S, T c) {
+    const T h = (T)0.5 * (st.a + b);
+    st.G = fma_<T>(st.G, st.r, h);
+    const T D = fma_<T>(b, st.G, (T)1);
+    const T q = rcp<T>(D * c);
+    st.r = q * c;
+    st.Y = fma_<T>(h, S, st.Y) * st.r;
+    st.a = b;
+    return q * D;
+}
+
 // Fourth-order (Hermitian) rows with third-order end rows: the scheme Section
 // 2.1 names for the solver (Auer 1976); derived from exactness for quartic u.
 // A row d with outer step a, inner step b (toward the origin) reads
@@ -356,14 +377,26 @@ __device__ inline double chi64(const Pt64<T>& p) {
 // interior points interpolate chi' and eta' linearly; rows are emitted far to
 // near, each with its inner step, the last being the sub-point next to the near
 // point.  `first` marks the far end of the line (its row is the boundary row).
+// With the second-order rows (SCH 0) every row whose near point is a line point forms that
+// point's 1/chi with the row's reciprocal (row_rc) and the interval returns it; the row into
+// the origin (to_origin) is the plain row, a far-end row when it is the line's first.
 template <typename T, int SCH>
-__device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
-                                        T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I) {
-    const T est = (cf > cn ? cf : cn) * (hds + hds) * (T)c.dtau_rcp;
-    if (!__builtin_amdgcn_ballot_w64(est > (T)0.9999)) {
-        row_s<T, SCH>(st, first, (cf + cn) * hds, Sf, cf, ef, cn, en, I);
-        return;
+__device__ inline T near_row(SweepState<T>& st, bool first, T b, T Sf, T cf, T ef, T cn, T en, T I, bool to_origin) {
+    if (SCH == 0) {
+        if (!to_origin) return row_rc<T>(st, b, Sf, cn);
+        row<T>(st, first, b, Sf, I);
+        return (T)0;
     }
+    row_s<T, SCH>(st, first, b, Sf, cf, ef, cn, en, I);
+    return (T)0;
+}
+
+template <typename T, int SCH>
+__device__ inline T substep_interval(const ItemCtx& c, SweepState<T>& st, bool first, T cf, T ef, T Sf, T cn, T en,
+                                     T hds, const Pt64<T>& pf, const Pt64<T>& pn, double ds64, T I, bool to_origin) {
+    const T est = (cf > cn ? cf : cn) * (hds + hds) * (T)c.dtau_rcp;
+    if (!__builtin_amdgcn_ballot_w64(est > (T)0.9999))
+        return near_row<T, SCH>(st, first, (cf + cn) * hds, Sf, cf, ef, cn, en, I, to_origin);
     const double c64f = chi64(pf), c64n = chi64(pn);
     const double cm = c64f > c64n ? c64f : c64n;
     double q = ceil((cm * ds64) * c.dtau_rcp);
@@ -378,14 +411,14 @@ __device__ inline void substep_interval(const ItemCtx& c, SweepState<T>& st, boo
             const T w = (T)k * rn;
             const T ck = fma_<T>(w, cn - cf, cf);
             const T ek = fma_<T>(w, en - ef, ef);
-            row_s<T, SCH>(st, fr, (cp + ck) * hh, Sp, cp, ep, ck, ek, I);
+            const T ic = near_row<T, SCH>(st, fr, (cp + ck) * hh, Sp, cp, ep, ck, ek, I, false);
             cp = ck;
             ep = ek;
-            if (SCH == 0) Sp = ek * rcp<T>(ck);
+            if (SCH == 0) Sp = ek * ic;
             fr = false;
         }
     }
-    row_s<T, SCH>(st, fr, (cp + cn) * hh, Sp, cp, ep, cn, en, I);
+    return near_row<T, SCH>(st, fr, (cp + cn) * hh, Sp, cp, ep, cn, en, I, to_origin);
 }
 
 // The stream of line points of one side, far to near, after velocity sampling.
@@ -399,14 +432,21 @@ struct Emitter {
 
 // Emit the next line point; the interval from the previous one (half length
 // hds, FP64 length ds64) is split by optical depth when that is on.
+// (SCH 0: Sn is ignored and formed from the row's reciprocal, the first point's from the
+// harmless row of row_rc; the state starts as row_rc describes.)
 template <typename T, int SCH>
 __device__ inline void emit_point(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, T cn, T en, T Sn,
-                                  const Pt64<T>& pn, T hds, double ds64, T I) {
+                                  const Pt64<T>& pn, T hds, double ds64, T I, bool to_origin) {
     if (em.have) {
+        T ic;
         if (c.dtau_rcp > 0.0)
-            substep_interval<T, SCH>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I);
-        else row_s<T, SCH>(st, em.first, (em.c + cn) * hds, em.S, em.c, em.e, cn, en, I);
+            ic = substep_interval<T, SCH>(c, st, em.first, em.c, em.e, em.S, cn, en, hds, em.p, pn, ds64, I,
+                                          to_origin);
+        else ic = near_row<T, SCH>(st, em.first, (em.c + cn) * hds, em.S, em.c, em.e, cn, en, I, to_origin);
+        if (SCH == 0) Sn = en * ic;
         em.first = false;
+    } else if (SCH == 0) {
+        Sn = en * row_rc<T>(st, (T)0, (T)0, cn);
     }
     em.c = cn;
     em.e = en;
@@ -430,7 +470,8 @@ struct RealPt {
 // smaller line coordinate (so it is the interval's point a).
 template <typename T, bool UDX, int SCH>
 __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitter<T>& em, const RealPt<T>& P,
-                                     const RealPt<T>& C, T hds, double ds64, bool fwd, const LaneFreq& lf, T I) {
+                                     const RealPt<T>& C, T hds, double ds64, bool fwd, const LaneFreq& lf, T I,
+                                     bool to_origin) {
     int m = 1;
     if (c.dv_rcp > 0.0) {
         double q = ceil(fabs(C.dot - P.dot) * c.dv_rcp);
@@ -439,7 +480,7 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
         m = __builtin_amdgcn_readfirstlane(m);  // the same in every lane
     }
     if (m == 1) {
-        emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hds, ds64, I);
+        emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hds, ds64, I, to_origin);
         return;
     }
     const T hs = hds * rcp<T>((T)m);
@@ -471,9 +512,10 @@ __device__ inline void real_interval(const ItemCtx& c, SweepState<T>& st, Emitte
         const T ya = fma_<T>(t, g1 - g0, g0), yb = fma_<T>(t, h1 - h0, h0);
         const T cv = fma_<T>(wt, xb - xa, xa);
         const T ev = fma_<T>(wt, yb - ya, ya);
-        emit_point<T, SCH>(c, st, em, cv, ev, ev * rcp<T>(cv), Pt64<T>{a0, a1, b0, b1, t64, w}, hs, ds64s, I);
+        emit_point<T, SCH>(c, st, em, cv, ev, SCH == 0 ? (T)0 : ev * rcp<T>(cv), Pt64<T>{a0, a1, b0, b1, t64, w},
+                           hs, ds64s, I, false);
     }
-    emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hs, ds64s, I);
+    emit_point<T, SCH>(c, st, em, C.c, C.e, C.S, C.p, hs, ds64s, I, to_origin);
 }
 
 // One side of the line with velocity sampling and/or optical-depth sub-steps
@@ -491,6 +533,12 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
     T hds_prev = (T)0;
     double ds64_prev = 0.0;
     int done = 0;
+    if (SCH == 0) {  // the state before the far end (row_rc)
+        st.G = (T)1;
+        st.r = (T)1;
+        st.a = (T)0;
+        st.Y = I;
+    }
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
     const int lo_bytes = lf.fb * (int)sizeof(T);
@@ -581,9 +629,9 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
                 cur.e = f.ea;
                 cur.p = Pt64<T>{cur.c, cur.c, cur.c, cur.c, 0.0, 0.0};
             }
-            cur.S = cur.e * rcp<T>(cur.c);
-            if (done == 0) emit_point<T, SCH>(c, st, em, cur.c, cur.e, cur.S, cur.p, (T)0, 0.0, I);
-            else real_interval<T, UDX, SCH>(c, st, em, prev, cur, hds_prev, ds64_prev, fwd, lf, I);
+            cur.S = SCH == 0 ? (T)0 : cur.e * rcp<T>(cur.c);  // SCH 0: formed with the row (emit_point)
+            if (done == 0) emit_point<T, SCH>(c, st, em, cur.c, cur.e, cur.S, cur.p, (T)0, 0.0, I, false);
+            else real_interval<T, UDX, SCH>(c, st, em, prev, cur, hds_prev, ds64_prev, fwd, lf, I, false);
             prev = cur;
             ds64_prev = ds64;
             hds_prev = (T)0.5 * (T)ds64;
@@ -599,7 +647,7 @@ __device__ inline void sweep_ref(const ItemCtx& c, int64_t base, int n, const La
         org.p = Pt64<T>{chi_o, chi_o, chi_o, chi_o, 0.0, 0.0};
         org.dot = 0.0;
         org.row = c.row_o;
-        real_interval<T, UDX, SCH>(c, st, em, prev, org, hds_prev, ds64_prev, fwd, lf, I);
+        real_interval<T, UDX, SCH>(c, st, em, prev, org, hds_prev, ds64_prev, fwd, lf, I, true);
     }
 }
 
@@ -630,6 +678,12 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                              T I, SweepState<T>& st, uint32_t* stage) {
     T c_prev = (T)0, e_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
     int done = 0;
+    if (SCH == 0) {  // the state before the far end (row_rc)
+        st.G = (T)1;
+        st.r = (T)1;
+        st.a = (T)0;
+        st.Y = I;
+    }
     const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
     // the lane's own frequency and its block's first and last, in bytes
     const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
@@ -727,13 +781,17 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
                         cc = ca[g];
                         et = ea[g];
                     }
-                    if (done > 0) {
+                    if (SCH == 0) {
+                        // the row and this point's 1/chi from one reciprocal; at the first point
+                        // c_prev and ds_prev are 0, so dt = 0 (see row_rc)
                         const T dt = (c_prev + cc) * ds_prev;  // ds_prev holds ds/2
+                        S_prev = et * row_rc<T>(st, dt, S_prev, cc);
+                    } else if (done > 0) {
+                        const T dt = (c_prev + cc) * ds_prev;
                         row_s<T, SCH>(st, done == 1, dt, S_prev, c_prev, e_prev, cc, et, I);
                     }
                     c_prev = cc;
                     e_prev = et;
-                    if (SCH == 0) S_prev = et * rcp<T>(cc);
                     ds_prev = dsv[g];
                     ++done;
                 }
