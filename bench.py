@@ -570,7 +570,7 @@ def main():
         return
     if args.workload == "sph_batch":
         rec, models, ds = run_batch(args, rt, torch, dev)
-        per_model = 150 if args.cpu_sample < 0 else args.cpu_sample
+        per_model = 600 if args.cpu_sample < 0 else args.cpu_sample
     else:
         rec, models, ds = run_plan_workload(args, rt, torch, dev)
         per_model = (25_000 if args.workload == "wind" else 3000) if args.cpu_sample < 0 else args.cpu_sample
