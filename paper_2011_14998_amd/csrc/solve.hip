@@ -94,9 +94,8 @@ struct LaneFreq {
     double dx;
 };
 
-__device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) {
+__device__ inline LaneFreq lane_freq_at(const SolveLaunch& a, int f) {
     LaneFreq lf;
-    int f = fc * 64 + lane;
     lf.active = f < a.F;
     lf.f = lf.active ? f : a.F - 1;
     int b = 0;
@@ -120,6 +119,8 @@ __device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) {
     lf.dx = dxb;
     return lf;
 }
+
+__device__ inline LaneFreq lane_freq(const SolveLaunch& a, int fc, int lane) { return lane_freq_at(a, fc * 64 + lane); }
 
 // Reciprocals.  FP32: the hardware reciprocal (1 ulp).  FP64: the hardware
 // estimate refined by two Newton steps r <- r + r(1 - x r), within about 1 ulp
@@ -808,7 +809,179 @@ __device__ inline void sweep(const ItemCtx& c, int64_t base, int n, const LaneFr
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
+// ---------------------------------------------------------------- packed half waves
+//
+// Between 65 and 96 frequencies a pair needs a full wave for its first 64 and half a wave
+// for the rest.  The second-chunk items of pairs r and r+1 (r even) share one wave: lanes
+// 0-31 take pair r's frequencies 64..F-1, lanes 32-63 those of pair r+1, each half walking
+// its own line, and the item of pair r+1 is left empty.  The halves stage their points 32
+// at a time, each into its own half of the wave's LDS records, and run the elimination
+// together for the longer of the two runs (lanes past the end of their own line are
+// masked).  Second-order rows on unrefined lines, tables below 4 GiB (32-bit row offsets);
+// the arithmetic of every lane is that of `sweep`, so u is the same bit for bit.
+template <typename T, bool MOVING, bool UDX, int GROUP>
+__device__ inline void sweep_half(const ItemCtx& c, double nx, double ny, double nz, int64_t base, int n,
+                                  const LaneFreq& lf, int lane, T chi_o, T I, SweepState<T>& st,
+                                  uint32_t* stage) {
+    const int hl = lane & 31;
+    uint32_t* my = stage + (lane >> 5) * 32 * STAGE_WORDS;
+    T c_prev = (T)0, S_prev = (T)0, ds_prev = (T)0;
+    st.G = (T)1;  // the state before the far end (row_rc)
+    st.r = (T)1;
+    st.a = (T)0;
+    st.Y = I;
+    const uint32_t lane_off = (uint32_t)lf.f * (uint32_t)sizeof(T);
+    const int lb_bytes = (lf.fb + lf.fl) * (int)sizeof(T);
+    const int lbm_bytes = lb_bytes - (int)sizeof(T);
+    const int lo_bytes = lf.fb * (int)sizeof(T);
+    const int hi_bytes = (lf.fb + lf.L - 1) * (int)sizeof(T);
+    constexpr int T_WORD = sizeof(T) == 4 ? 3 : 4;
+    constexpr int DS_WORD = sizeof(T) == 4 ? 4 : 6;
+    const int n0 = __builtin_amdgcn_readlane(n, 0), n1 = __builtin_amdgcn_readlane(n, 32);
+    const int n_max = n0 > n1 ? n0 : n1;
+    for (int run0 = 0; run0 < n_max; run0 += 32) {
+        const int hi = n - 1 - run0;                        // this half's newest entry of the run
+        const int cnt = hi + 1 < 32 ? (hi + 1 > 0 ? hi + 1 : 0) : 32;  // this half's points in the run
+        const int cnt_max = n_max - run0 < 32 ? n_max - run0 : 32;
+        if (hl < cnt) {  // lane hl of a half stages entry hi - hl of its own line
+            const int e = hi - hl;
+            uint32_t* w = my + hl * STAGE_WORDS;
+            const int q = c.ids[base + e];
+            const uint64_t row = (uint64_t)q * (uint64_t)c.ld_bytes;
+            const double z = c.Zr[base + e];
+            const double zi = e > 0 ? c.Zr[base + e - 1] : 0.0;
+            const T ds = (T)0.5 * (T)(z - zi);
+            w[0] = (uint32_t)row;
+            w[1] = (uint32_t)(row >> 32);
+            if (MOVING) {
+                const float* vq = c.vel + 3 * (int64_t)q;
+                const double dvx = (double)vq[0] - (double)c.vox;
+                const double dvy = (double)vq[1] - (double)c.voy;
+                const double dvz = (double)vq[2] - (double)c.voz;
+                const double dot = (nx * dvx + ny * dvy) + nz * dvz;
+                if (UDX) {
+                    const double delta = dot / c.dx0;
+                    const double kf = floor(delta);
+                    w[2] = (uint32_t)((int)kf * (int)sizeof(T));
+                    *(T*)(w + T_WORD) = (T)(delta - kf);
+                } else {
+                    *(double*)(w + 2) = dot;
+                }
+            }
+            *(T*)(w + DS_WORD) = ds;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int c0 = __builtin_amdgcn_readlane(cnt, 0), c1 = __builtin_amdgcn_readlane(cnt, 32);
+        const int cnt_min = c0 < c1 ? c0 : c1;  // points both halves have in this run
+        // a group of GROUP points per lane: loads first, then the recurrence; groups inside both
+        // halves' runs (FULL) carry no per-point test, the rest mask the lanes past their run
+        auto half_group = [&](auto full, int j0) {
+            constexpr bool FULL = decltype(full)::value;
+            T ca[GROUP], cb[GROUP], ea[GROUP], eb[GROUP], tt[GROUP], dsv[GROUP];
+#pragma unroll
+            for (int g = 0; g < GROUP; ++g) {
+                if (FULL || j0 + g < cnt) {
+                    const uint32_t* w = my + (j0 + g) * STAGE_WORDS;
+                    const uint4 r0 = *(const uint4*)w;
+                    dsv[g] = *(const T*)(w + DS_WORD);
+                    const uint32_t rlo = r0.x;
+                    if (MOVING) {
+                        int ks;
+                        T t;
+                        if (UDX) {
+                            ks = (int)r0.z;
+                            t = *(const T*)(w + T_WORD);
+                        } else {
+                            const double delta = __builtin_bit_cast(double, (((uint64_t)r0.w << 32) | r0.z)) / lf.dx;
+                            const double kf = floor(delta);
+                            ks = (int)kf * (int)sizeof(T);
+                            t = (T)(delta - kf);
+                        }
+                        const uint32_t oa = rlo + (uint32_t)clamp_i32(lb_bytes - ks, lo_bytes, hi_bytes);
+                        const uint32_t ob = rlo + (uint32_t)clamp_i32(lbm_bytes - ks, lo_bytes, hi_bytes);
+                        ca[g] = *(const T*)(c.chi + oa);
+                        cb[g] = *(const T*)(c.chi + ob);
+                        ea[g] = *(const T*)(c.eta + oa);
+                        eb[g] = *(const T*)(c.eta + ob);
+                        tt[g] = t;
+                    } else {
+                        ca[g] = *(const T*)(c.chi + rlo + lane_off);
+                        ea[g] = *(const T*)(c.eta + rlo + lane_off);
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < GROUP; ++g) {
+                if (FULL || j0 + g < cnt) {
+                    T cc, et;
+                    if (MOVING) {
+                        cc = fma_<T>(tt[g], cb[g] - ca[g], ca[g]);
+                        et = fma_<T>(tt[g], eb[g] - ea[g], ea[g]);
+                    } else {
+                        cc = ca[g];
+                        et = ea[g];
+                    }
+                    const T dt = (c_prev + cc) * ds_prev;
+                    S_prev = et * row_rc<T>(st, dt, S_prev, cc);
+                    c_prev = cc;
+                    ds_prev = dsv[g];
+                }
+            }
+        };
+        int j0 = 0;
+        for (; j0 + GROUP <= cnt_min; j0 += GROUP) half_group(std::true_type{}, j0);
+        for (; j0 < cnt_max; j0 += GROUP) half_group(std::false_type{}, j0);
+        __builtin_amdgcn_wave_barrier();  // every lane has read this run before the next is staged
+    }
+    if (n > 0) row<T>(st, n == 1, (c_prev + chi_o) * ds_prev, S_prev, I);
+}
+
+// The packed item of pairs r, r+1 (r even), frequencies 64.. of each (see sweep_half).
+template <typename T, bool MOVING, bool UDX, int GROUP>
+__device__ inline void solve_item_half(const SolveLaunch& a, int64_t oi, int64_t r, int64_t o, int lane,
+                                       uint32_t* stage) {
+    const int64_t rh = r + (lane >> 5);
+    const LaneFreq lf = lane_freq_at(a, 64 + (lane & 31));
+    const int64_t slot_p = oi * 2 * a.R + 2 * rh;
+    const int64_t bp = a.ray_off[slot_p], bm = a.ray_off[slot_p + 1], be = a.ray_off[slot_p + 2];
+    const int np = (int)(bm - bp), nm = (int)(be - bm);
+    ItemCtx c;
+    c.chi = (const char*)a.chi;
+    c.eta = (const char*)a.eta;
+    c.ld_bytes = a.ld * (int64_t)sizeof(T);
+    c.ids = a.ray_ids;
+    c.Zr = a.ray_Z;
+    c.vel = a.vel;
+    const double* dv = a.dirs + 3 * ((a.per_origin ? oi * a.R : 0) + rh);
+    const double nx = dv[0], ny = dv[1], nz = dv[2];
+    c.nx = c.ny = c.nz = 0.0;
+    c.inv_dx0 = a.inv_dx[0];
+    c.dx0 = a.dx[0];
+    c.vox = c.voy = c.voz = 0.f;
+    if (MOVING) {
+        c.vox = a.vel[3 * o];
+        c.voy = a.vel[3 * o + 1];
+        c.voz = a.vel[3 * o + 2];
+    }
+    c.dtau_rcp = 0.0;
+    c.dv_rcp = 0.0;
+    c.max_sub = a.max_sub;
+    c.row_o = o * c.ld_bytes;
+    const T I = (T)a.I_bc[lf.f];
+    const T chi_o = ((const T*)a.chi)[o * a.ld + lf.f];
+    const T eta_o = ((const T*)a.eta)[o * a.ld + lf.f];
+    const T S_o = eta_o * rcp<T>(chi_o);
+    SweepState<T> m{}, p{};
+    sweep_half<T, MOVING, UDX, GROUP>(c, nx, ny, nz, bm, nm, lf, lane, chi_o, I, m, stage);
+    sweep_half<T, MOVING, UDX, GROUP>(c, nx, ny, nz, bp, np, lf, lane, chi_o, I, p, stage);
+    const T u = origin_u<T>(nm > 0, np > 0, m, p, S_o, I);
+    if (lf.active) {
+        ((T*)a.u)[(oi * a.R + rh) * a.F + lf.f] = u;
+        if (!(u == u) || u - u != (T)0) atomicOr(a.err, ERRBIT_NONFINITE);
+    }
+}
+
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
 __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int lane, uint32_t* stage) {
     // w is the same in every lane of the wave
     w = uni64(w);
@@ -816,12 +989,16 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     const int64_t pr = w / nfc;
     const int64_t r = pr % a.R;
     const int64_t oi = pr / a.R;
-    const LaneFreq lf = lane_freq(a, fc, lane);
     const int64_t o = a.origins ? (int64_t)uni(a.origins[oi]) : oi;
     if (o < 0 || o >= a.P) {
         if (lane == 0) atomicOr(a.err, ERRBIT_ORIGIN);
         return;
     }
+    if (PACK && fc == 1) {  // launched only for 65..96 frequencies, an even pair count and small tables
+        if ((r & 1) == 0) solve_item_half<T, MOVING, UDX, GROUP>(a, oi, r, o, lane, stage);
+        return;  // odd pairs: done by the even pair's wave
+    }
+    const LaneFreq lf = lane_freq(a, fc, lane);
     const int64_t slot_p = oi * 2 * a.R + 2 * r;
     const int64_t bp = uni64(a.ray_off[slot_p]), bm = uni64(a.ray_off[slot_p + 1]);
     const int64_t be = uni64(a.ray_off[slot_p + 2]);
@@ -882,7 +1059,7 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
 }
 
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
     __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
@@ -902,7 +1079,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
         }
-        solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
+        solve_item<T, MOVING, UDX, GROUP, REF, SCH, PACK>(a, w, nfc, lane, stage);
     }
 }
 
@@ -910,7 +1087,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch 
 // takes the next PERSIST_CHUNK items with one atomic (one counter shared by
 // every wave: an atomic per item serialised the queue) and exits when the
 // queue is empty, so every wave reaches the end.
-template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH>
+template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
 __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
     __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
@@ -926,7 +1103,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_persist(const SolveLaunch
         const int64_t end = (int64_t)it0 + PERSIST_CHUNK < n_items ? (int64_t)it0 + PERSIST_CHUNK : n_items;
         for (int64_t it = it0; it < end; ++it) {
             const int64_t w = a.items ? (int64_t)a.items[it] : it;
-            solve_item<T, MOVING, UDX, GROUP, REF, SCH>(a, w, nfc, lane, stage);
+            solve_item<T, MOVING, UDX, GROUP, REF, SCH, PACK>(a, w, nfc, lane, stage);
         }
     }
 }
@@ -1052,13 +1229,13 @@ hipError_t launch_bin(const SolveLaunch& a0, void* ws, int32_t** items_out, hipS
     return hipGetLastError();
 }
 
-template <typename T, int G, bool REF, int SCH>
+template <typename T, int G, bool REF, int SCH, bool PACK>
 static void solve_dispatch_g(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     const bool moving = a.vel != nullptr;
     // the shift of a point is lane-independent when every block has the same dx
     bool udx = true;
     for (int b = 1; b < a.n_blocks; ++b) udx = udx && (a.inv_dx[b] == a.inv_dx[0]);
-#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, REF, SCH>), grid, dim3(SOLVE_BLOCK), 0, s, a)
+#define RT_LAUNCH(K, MV, U) hipLaunchKernelGGL((K<T, MV, U, G, REF, SCH, PACK>), grid, dim3(SOLVE_BLOCK), 0, s, a)
     if (persist) {
         if (moving && udx) RT_LAUNCH(k_solve_persist, true, true);
         else if (moving) RT_LAUNCH(k_solve_persist, true, false);
@@ -1075,15 +1252,19 @@ template <typename T>
 static void solve_dispatch(const SolveLaunch& a, bool persist, dim3 grid, hipStream_t s) {
     // refined lines (velocity sampling, optical-depth sub-steps) take their own sweep
     const bool ref = a.dtau_max_rcp > 0.0 || a.dv_max_rcp > 0.0;
+    // 65..96 frequencies: the second chunks of two pairs share a wave (solve_item_half)
+    const bool pack = a.F > 64 && a.F <= 96 && (a.R & 1) == 0 && a.small_tables;
     if (a.scheme == RT_SCHEME_HERMITE) {  // fourth-order rows: one load group size
-        if (ref) solve_dispatch_g<T, 4, true, 1>(a, persist, grid, s);
-        else solve_dispatch_g<T, 4, false, 1>(a, persist, grid, s);
+        if (ref) solve_dispatch_g<T, 4, true, 1, false>(a, persist, grid, s);
+        else solve_dispatch_g<T, 4, false, 1, false>(a, persist, grid, s);
     } else if (ref) {
-        solve_dispatch_g<T, 4, true, 0>(a, persist, grid, s);
+        solve_dispatch_g<T, 4, true, 0, false>(a, persist, grid, s);
     } else if (a.group == 4) {
-        solve_dispatch_g<T, 4, false, 0>(a, persist, grid, s);
+        if (pack) solve_dispatch_g<T, 4, false, 0, true>(a, persist, grid, s);
+        else solve_dispatch_g<T, 4, false, 0, false>(a, persist, grid, s);
     } else {
-        solve_dispatch_g<T, 8, false, 0>(a, persist, grid, s);
+        if (pack) solve_dispatch_g<T, 8, false, 0, true>(a, persist, grid, s);
+        else solve_dispatch_g<T, 8, false, 0, false>(a, persist, grid, s);
     }
 }
 

@@ -405,6 +405,34 @@ def test_octree_cloud_parity(rt, orc):
     assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
 
 
+def test_packed_half_waves_match_unpacked(rt):
+    """65..96 frequencies: the second 64-frequency chunks of two pairs share one wave, 32 lanes
+    each.  The octree cloud (F = 96, blocks 48 + 48) against the same cloud cut to its
+    frequencies 32..95 (blocks 16 + 48, F = 64, nothing packed): u of the second block, and so
+    J there, is the same bit for bit, in FP32 and FP64, eagerly and with the persistent launch."""
+    torch = _torch()
+    m = synth.octree_model(seed=31, lmin=3, lmax=5, target=3000)
+    assert m.F == 96 and list(m.freq.len) == [48, 48]
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(2)
+    rng = np.random.default_rng(12)
+    org = _t(np.sort(rng.choice(m.P, 300, replace=False)).astype(np.int32))
+    rays = rt.trace(model, ds, origins=org)
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    dx = list(m.freq.dx)
+    for prec, chi, eta in ((rt.RT_F32, c32, e32), (rt.RT_F64, c64, e64)):
+        for schedule in (rt.SCHED_DIRECT, rt.SCHED_BINNED):
+            JA, uA = rt.solve(model, ds, rays, _t(chi), _t(eta), [48, 48], dx, _t(m.I_bc, torch.float64),
+                              origins=org, precision=prec, want_u=True, schedule=schedule)
+            JB, uB = rt.solve(model, ds, rays, _t(chi[:, 32:]), _t(eta[:, 32:]), [16, 48], dx,
+                              _t(m.I_bc[32:], torch.float64), origins=org, precision=prec, want_u=True,
+                              schedule=schedule)
+            rt.sync_status()
+            a, b = uA.cpu().numpy(), uB.cpu().numpy()
+            assert np.array_equal(a[:, :, 48:], b[:, :, 16:])
+            assert np.array_equal(JA.cpu().numpy()[:, 48:], JB.cpu().numpy()[:, 16:])
+
+
 def test_batched_union(rt, orc):
     torch = _torch()
     ms = synth.sph_batch_models(n_models=5, lo=800, hi=3000, seed0=900)
