@@ -129,7 +129,7 @@ def test_mlp_params_roundtrip(rt):
     assert np.array_equal(net.get_params(), flat)
 
 
-@pytest.mark.parametrize("n,use_rows", [(200, False), (130, True)])
+@pytest.mark.parametrize("n,use_rows", [(200, False), (130, True), (1, False), (33, True)])
 def test_mlp_loss_and_gradients(rt, n, use_rows):
     torch = _torch()
     flat = _params(5)

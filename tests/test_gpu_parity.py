@@ -433,6 +433,31 @@ def test_packed_half_waves_match_unpacked(rt):
             assert np.array_equal(JA.cpu().numpy()[:, 48:], JB.cpu().numpy()[:, 16:])
 
 
+@pytest.mark.parametrize("lmin,lmax", [(1, 3), (0, 3)])
+def test_adaptive_sets_with_96_frequencies(rt, orc, lmin, lmax):
+    """Per-origin direction sets on the 96-frequency octree cloud: with an even pair count (132)
+    the packed half waves take each pair's own direction from the origin's set, with an odd one
+    (69) nothing is packed; FP64 and FP32 against the oracle."""
+    torch = _torch()
+    m = synth.octree_model(seed=31, lmin=3, lmax=5, target=3000)
+    rng = np.random.default_rng(lmin + 13)
+    sample = rng.choice(m.P, 2000, replace=False).astype(np.int32)
+    origins = rng.choice(m.P, 80, replace=False).astype(np.int32)
+    model = _gpu_model(rt, m)
+    org = _t(origins)
+    ds = rt.DirSet.adaptive(model, lmin, lmax, _t(sample), origins=org)
+    assert ds.info()["R"] == orc.dirset_adaptive_R(lmin, lmax)
+    _, _, dirs, w2 = ds.export()
+    rays = rt.trace(model, ds, origins=org)
+    c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
+    Je = orc.compute_J(m, dirs, w2, origins=origins, chi=c64, eta=e64)
+    J64 = _solve_gpu(rt, m, model, ds, rays, org, len(origins), rt.RT_F64, chi=c64, eta=e64)
+    assert _rel(J64.cpu().numpy(), Je) <= TOL64
+    J32 = _solve_gpu(rt, m, model, ds, rays, org, len(origins), rt.RT_F32, chi=c32, eta=e32)
+    assert _rel(J32.cpu().numpy().astype(np.float64), Je) <= TOL32
+    del torch
+
+
 def test_batched_union(rt, orc):
     torch = _torch()
     ms = synth.sph_batch_models(n_models=5, lo=800, hi=3000, seed0=900)
