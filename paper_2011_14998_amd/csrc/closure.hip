@@ -76,6 +76,9 @@ __device__ inline uint32_t f2bf2(float a, float b) {
 __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 __device__ inline float bf_lo(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
 __device__ inline float bf_hi(uint32_t v) { return __builtin_bit_cast(float, v & 0xFFFF0000u); }
+// x rounded to BF16 and read back as FP32: one conversion that puts bf16(x) in the high half
+// and bf16(0) = 0 in the low half
+__device__ inline float bfr(float x) { return __builtin_bit_cast(float, f2bf2(0.f, x)); }
 // logistic function with the hardware reciprocal; silu(z) = z sigma(z)
 __device__ inline float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ inline float silu(float z) { return z * sigm(z); }
@@ -122,11 +125,11 @@ __global__ void k_publish(const float* __restrict__ w, uint16_t* __restrict__ wt
 
 // ---------------------------------------------------------------- forward
 
-// out[m][n] = bf16(silu(z)), z = bf16(sum_k in[m][k] W[k][n] + b[n]) for the
+// out[m][n] = bf16(silu(z)), z = bf16(b[n] + sum_k in[m][k] W[k][n]) for the
 // 16*MTW samples m of the tile, W given as Wt[256][K].  The product is formed
 // transposed (Z^T = Wt in^T: weights as the A operand, samples as B) so that a
 // lane's four accumulators are four consecutive n of one sample and go out as
-// one 8-byte store.  Wave w owns n in [64w, 64w+64).
+// one 8-byte store; they start from the bias.  Wave w owns n in [64w, 64w+64).
 template <int MTW, int K, int ldin, bool KEEP>
 __device__ __attribute__((always_inline)) inline void fwd_layer(const uint16_t* in, const uint16_t* __restrict__ Wt,
                                                                 const float* __restrict__ bias, uint16_t* out,
@@ -136,9 +139,11 @@ __device__ __attribute__((always_inline)) inline void fwd_layer(const uint16_t* 
     const int g = lane >> 4, r = lane & 15;
     v4f32 acc[4][MTW];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+        const float4 bb = *(const float4*)(bias + 64 * w + 16 * nt + 4 * g);
 #pragma unroll
-        for (int mt = 0; mt < MTW; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < MTW; ++mt) acc[nt][mt] = (v4f32){bb.x, bb.y, bb.z, bb.w};
+    }
     for (int k0 = 0; k0 < K; k0 += 16) {
         v4i16 a[4], b[MTW];
 #pragma unroll
@@ -153,16 +158,15 @@ __device__ __attribute__((always_inline)) inline void fwd_layer(const uint16_t* 
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int n0 = 64 * w + 16 * nt + 4 * g;
-        const float4 bb = *(const float4*)(bias + n0);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
             const int m = mt * 16 + r;
-            const uint32_t z01 = f2bf2(acc[nt][mt][0] + bb.x, acc[nt][mt][1] + bb.y);
-            const uint32_t z23 = f2bf2(acc[nt][mt][2] + bb.z, acc[nt][mt][3] + bb.w);
-            const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
-            const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
+            const v4f32& a = acc[nt][mt];
+            const uint32_t h01 = f2bf2(silu(bfr(a[0])), silu(bfr(a[1])));
+            const uint32_t h23 = f2bf2(silu(bfr(a[2])), silu(bfr(a[3])));
             *(uint2*)(out + m * LDH + n0) = make_uint2(h01, h23);
-            if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
+            if (KEEP && m < nvalid)
+                *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(f2bf2(a[0], a[1]), f2bf2(a[2], a[3]));
         }
     }
 }
@@ -246,7 +250,7 @@ __device__ inline v8i16 ld8(const uint16_t* p) { return *(const v8i16*)p; }  // 
 
 // Each tile is taken in two halves of 32 samples, A and B, one half behind
 // the other: while a wave's matrix products of one half run, its epilogue
-// (bias, BF16 z, SiLU, BF16 h) of the other half's previous layer is issued
+// (BF16 z, SiLU, BF16 h) of the other half's previous layer is issued
 // between them, so the matrix cores and the vector ALUs work at the same time
 // instead of in turns between the layer barriers.  Phases of a tile (each
 // ends at a barrier; M = products, E = epilogue, layer 1..3):
@@ -255,36 +259,45 @@ __device__ inline v8i16 ld8(const uint16_t* p) { return *(const v8i16*)p; }  // 
 //   M(A,1) of the next.  Layer l's activations go to ha (l odd) or hb (l even),
 //   rows 0-31 for A and 32-63 for B, so no phase writes rows another reads.
 
-// bias, BF16 z, SiLU, BF16 h of accumulator block (nt, mt) of half hf; h into LDS, z (KEEP) to HBM
+// BF16 z, SiLU, BF16 h of accumulator block (nt, mt) of half hf (the products started from the
+// bias); h into LDS, z (KEEP) to HBM.  Each z is rounded by one conversion, and packed again only
+// when it is stored.
 template <bool KEEP>
-__device__ __attribute__((always_inline)) inline void ws_epi_block(const v4f32& acc, const float* sbias,
-                                                                   uint16_t* out, uint16_t* __restrict__ zout,
-                                                                   int64_t row0, int nvalid, int hf, int nt, int mt,
-                                                                   int wv, int g, int r) {
+__device__ __attribute__((always_inline)) inline void ws_epi_block(const v4f32& acc, uint16_t* out,
+                                                                   uint16_t* __restrict__ zout, int64_t row0,
+                                                                   int nvalid, int hf, int nt, int mt, int wv, int g,
+                                                                   int r) {
     const int n0 = 32 * wv + 16 * nt + 4 * g;
     const int m = 16 * (2 * hf + mt) + r;
-    const float4 bb = *(const float4*)(sbias + n0);
-    const uint32_t z01 = f2bf2(acc[0] + bb.x, acc[1] + bb.y);
-    const uint32_t z23 = f2bf2(acc[2] + bb.z, acc[3] + bb.w);
-    const uint32_t h01 = f2bf2(silu(bf_lo(z01)), silu(bf_hi(z01)));
-    const uint32_t h23 = f2bf2(silu(bf_lo(z23)), silu(bf_hi(z23)));
+    const uint32_t h01 = f2bf2(silu(bfr(acc[0])), silu(bfr(acc[1])));
+    const uint32_t h23 = f2bf2(silu(bfr(acc[2])), silu(bfr(acc[3])));
     *(uint2*)(out + m * LDP + n0) = make_uint2(h01, h23);
-    if (KEEP && m < nvalid) *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(z01, z23);
+    if (KEEP && m < nvalid)
+        *(uint2*)(zout + (row0 + m) * HW + n0) = make_uint2(f2bf2(acc[0], acc[1]), f2bf2(acc[2], acc[3]));
+}
+
+// accumulators of columns n0 .. n0 + 3 (both sample blocks) set to the bias
+__device__ __attribute__((always_inline)) inline void ws_bias(v4f32 (&acc)[2][2], const float* bias, int wv,
+                                                              int g) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const float4 bb = *(const float4*)(bias + 32 * wv + 16 * nt + 4 * g);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = (v4f32){bb.x, bb.y, bb.z, bb.w};
+    }
 }
 
 // One phase of a hidden layer: the products of half hm (activations `in`, weights in
-// registers) into accm, with the epilogue of half he from acce (if EPI) spread between them.
+// registers, bias `mbias`) into accm, with the epilogue of half he from acce (if EPI)
+// spread between them.
 template <bool KEEP, bool EPI>
-__device__ __attribute__((always_inline)) inline void ws_phase(const uint16_t* in, const v8i16 (&wr)[2][8], int hm,
-                                                               v4f32 (&accm)[2][2], const v4f32 (&acce)[2][2],
-                                                               int he, const float* sbias, uint16_t* out,
+__device__ __attribute__((always_inline)) inline void ws_phase(const uint16_t* in, const v8i16 (&wr)[2][8],
+                                                               const float* mbias, int hm, v4f32 (&accm)[2][2],
+                                                               const v4f32 (&acce)[2][2], int he, uint16_t* out,
                                                                uint16_t* __restrict__ zout, int64_t row0, int nvalid,
                                                                int wv, int g, int r) {
     v4f32 acc[2][2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    ws_bias(acc, mbias, wv, g);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
         v8i16 b[2];
@@ -296,7 +309,7 @@ __device__ __attribute__((always_inline)) inline void ws_phase(const uint16_t* i
             for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = mfma32(wr[nt][ks], b[mt], acc[nt][mt]);
         if (EPI && (ks & 1)) {
             const int q = ks >> 1, nt = q >> 1, mt = q & 1;
-            ws_epi_block<KEEP>(acce[nt][mt], sbias, out, zout, row0, nvalid, he, nt, mt, wv, g, r);
+            ws_epi_block<KEEP>(acce[nt][mt], out, zout, row0, nvalid, he, nt, mt, wv, g, r);
         }
     }
 #pragma unroll
@@ -307,20 +320,20 @@ __device__ __attribute__((always_inline)) inline void ws_phase(const uint16_t* i
 
 // epilogue of a whole half
 template <bool KEEP>
-__device__ __attribute__((always_inline)) inline void ws_epi_half(const v4f32 (&acc)[2][2], int hf,
-                                                                  const float* sbias, uint16_t* out,
+__device__ __attribute__((always_inline)) inline void ws_epi_half(const v4f32 (&acc)[2][2], int hf, uint16_t* out,
                                                                   uint16_t* __restrict__ zout, int64_t row0,
                                                                   int nvalid, int wv, int g, int r) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-            ws_epi_block<KEEP>(acc[nt][mt], sbias, out, zout, row0, nvalid, hf, nt, mt, wv, g, r);
+        for (int mt = 0; mt < 2; ++mt) ws_epi_block<KEEP>(acc[nt][mt], out, zout, row0, nvalid, hf, nt, mt, wv, g, r);
 }
 
 // layer 1 products of half hf: one k-step of 32 (inputs 16..31 and their weights are zero)
-__device__ __attribute__((always_inline)) inline void ws_l1(const uint16_t* sx, const uint16_t* sw1, int hf,
-                                                            v4f32 (&acc)[2][2], int wv, int g, int r) {
+__device__ __attribute__((always_inline)) inline void ws_l1(const uint16_t* sx, const uint16_t* sw1,
+                                                            const float* bias, int hf, v4f32 (&acc)[2][2], int wv,
+                                                            int g, int r) {
+    ws_bias(acc, bias, wv, g);
     v8i16 a[2], b[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) a[nt] = ld8(sw1 + (32 * wv + 16 * nt + r) * LDW1 + 8 * g);
@@ -329,7 +342,7 @@ __device__ __attribute__((always_inline)) inline void ws_l1(const uint16_t* sx, 
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = mfma32(a[nt], b[mt], (v4f32){0.f, 0.f, 0.f, 0.f});
+        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = mfma32(a[nt], b[mt], acc[nt][mt]);
 }
 
 template <bool KEEP>
@@ -388,22 +401,22 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restric
     load_x(tile);
     __syncthreads();
     v4f32 aA[2][2], aB[2][2];
-    ws_l1(sx, sw1, 0, aA, wv, g, r);
+    ws_l1(sx, sw1, sbias, 0, aA, wv, g, r);
     for (;;) {
         const int64_t row0 = tile * PT;
         const int nvalid = (int)(n - row0 < PT ? n - row0 : PT);
-        ws_l1(sx, sw1, 1, aB, wv, g, r);
-        ws_epi_half<KEEP>(aA, 0, sbias, ha, Z1, row0, nvalid, wv, g, r);
+        ws_l1(sx, sw1, sbias, 1, aB, wv, g, r);
+        ws_epi_half<KEEP>(aA, 0, ha, Z1, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_phase<KEEP, true>(ha, w2r, 0, aA, aB, 1, sbias, ha, Z1, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(ha, w2r, sbias + HW, 0, aA, aB, 1, ha, Z1, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_phase<KEEP, true>(ha, w2r, 1, aB, aA, 0, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(ha, w2r, sbias + HW, 1, aB, aA, 0, hb, Z2, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_phase<KEEP, true>(hb, w3r, 0, aA, aB, 1, sbias + HW, hb, Z2, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(hb, w3r, sbias + 2 * HW, 0, aA, aB, 1, hb, Z2, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_phase<KEEP, true>(hb, w3r, 1, aB, aA, 0, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        ws_phase<KEEP, true>(hb, w3r, sbias + 2 * HW, 1, aB, aA, 0, ha, Z3, row0, nvalid, wv, g, r);
         __syncthreads();
-        ws_epi_half<KEEP>(aB, 1, sbias + 2 * HW, ha, Z3, row0, nvalid, wv, g, r);
+        ws_epi_half<KEEP>(aB, 1, ha, Z3, row0, nvalid, wv, g, r);
         const int64_t next = tile + gridDim.x;
         if (next < tiles) load_x(next);  // sx was last read by this tile's M(B,1)
         __syncthreads();
@@ -418,7 +431,7 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fwd_ws(const uint16_t* __restric
             if (g == 0 && m < nvalid) *(float2*)(Y + (row0 + m) * DOUT) = make_float2(acc[0] + b40, acc[1] + b41);
         }
         if (next >= tiles) break;
-        ws_l1(sx, sw1, 0, aA, wv, g, r);
+        ws_l1(sx, sw1, sbias, 0, aA, wv, g, r);
         __syncthreads();  // the head has read ha before the next tile writes it
         tile = next;
     }
