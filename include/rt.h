@@ -411,16 +411,20 @@ rt_status rt_autotune_plan(rt_plan* plan, int32_t n_runs, int32_t verbose, void*
 
 /* ------------------------------------------------------------------ many models at once
  * Many independent models of different sizes in one launch: a disjoint union
- * built on the device (positions and velocities concatenated, neighbour ids
- * and CSR offsets shifted by each model's first point and entry, the tables
- * gathered into one [P_total][F] array), so rays never cross from one model
- * into another and every result is bit-identical to solving each model alone
- * (positions are not moved).  The union is traced and solved by one plan (a
- * single HIP graph: table gather, walk, sweep over every model's items in one
- * launch -- length-binned persistent or spatial, as opts says -- J reduction
- * and the scatter of J back to each model's own array).  Origins are every
- * point of every model, in model order, each model's points in Morton order
- * of their positions.
+ * built on the device, so rays never cross from one model into another.  Model
+ * k's points take the union ids base_k .. base_k + P_k - 1 (base_k = P_0 + ... +
+ * P_{k-1}) in the Morton order of that model's positions, so that points near
+ * in space are near in the neighbour records and in the union's [P_total][F]
+ * tables, which are gathered from the models' tables row by row.  Positions are
+ * not moved and every row of neighbour records keeps the order of the model's
+ * own ids (the walk's tie order), so every ray is the model's own (its point ids
+ * renamed) and every result is bit-identical to solving each model alone.  The
+ * union is traced and solved by one plan (a single HIP graph: table gather,
+ * walk, sweep over every model's items in one launch -- length-binned
+ * persistent or spatial, as opts says -- J reduction and the scatter of J back
+ * to each model's own array).  Origins are every point of the union in union
+ * order; the inner plan's ray lists (rt_plan_rays, rt_plan_info) carry union
+ * ids and are slotted by union origin.
  *
  * rt_batch_create: models[n_models] (handles on the current device), one
  * uniform direction set for all, chi[k]/eta[k] device [P_k][ld[k]] of `dtype`,
@@ -431,7 +435,9 @@ rt_status rt_autotune_plan(rt_plan* plan, int32_t n_runs, int32_t verbose, void*
  * use_graph = 0 launches the steps one by one).  rt_batch_plan: the inner plan
  * over the union (for rt_plan_profile, rt_plan_info, rt_plan_retune,
  * rt_autotune_plan); owned by the batch.  rt_batch_union: the union's point
- * and entry counts.
+ * and entry counts.  rt_batch_union_index: index (device int32 [P_total],
+ * caller-owned) receives the union id of each model point, index[base_k + i]
+ * for point i of model k (async on `stream`).
  * rt_compute_J_batched: create, run once, synchronise, destroy. */
 typedef struct rt_batch rt_batch;
 rt_status rt_batch_create(int32_t n_models, const rt_model* const* models, const rt_dirset* set,
@@ -441,6 +447,7 @@ rt_status rt_batch_create(int32_t n_models, const rt_model* const* models, const
 rt_status rt_batch_run(rt_batch* batch, int32_t use_graph, void* stream);
 rt_status rt_batch_plan(rt_batch* batch, rt_plan** plan);
 rt_status rt_batch_union(const rt_batch* batch, int64_t* points, int64_t* entries);
+rt_status rt_batch_union_index(const rt_batch* batch, int32_t* index, void* stream);
 rt_status rt_batch_destroy(rt_batch* batch);
 rt_status rt_compute_J_batched(int32_t n_models, const rt_model* const* models, const rt_dirset* set,
                                const void* const* chi, const void* const* eta, int32_t dtype, const int64_t* ld,

@@ -93,6 +93,7 @@ _SIGS = {
     "rt_batch_run": (_i32, [_vp, _i32, _vp]),
     "rt_batch_plan": (_i32, [_vp, C.POINTER(_vp)]),
     "rt_batch_union": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
+    "rt_batch_union_index": (_i32, [_vp, _vp, _vp]),
     "rt_batch_destroy": (_i32, [_vp]),
     "rt_compute_J_batched": (_i32, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, C.POINTER(FreqGridC), _vp, _vp,
                                     C.POINTER(SolveOptsC), _vp]),
@@ -573,6 +574,15 @@ class Batch:
         P, E = _i64(), _i64()
         _check(load().rt_batch_union(self._h, C.byref(P), C.byref(E)))
         return P.value, E.value
+
+    def union_index(self, stream=None):
+        """Device int32 [P_total]: the union id of point i of model k at [base_k + i]
+        (base_k = the points of the models before k); the inner plan's lists carry union ids."""
+        torch = _torch()
+        P, _ = self.union()
+        idx = torch.empty(P, dtype=torch.int32, device="cuda")
+        _check(load().rt_batch_union_index(self._h, idx.data_ptr(), _stream(stream)))
+        return idx
 
     def run(self, use_graph: bool = True, stream=None):
         _check(load().rt_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))

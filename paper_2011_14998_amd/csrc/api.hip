@@ -296,13 +296,17 @@ extern "C" rt_status rt_dirset_destroy(rt_dirset* set) {
 
 extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
                                      int64_t E, const float* vel, void* stream, rt_model** out) {
+    return model_create(pos, P, nbr_off, nbr_idx, E, vel, nullptr, (hipStream_t)stream, out);
+}
+
+rt_status rt::model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx, int64_t E,
+                           const float* vel, const int32_t* key, hipStream_t s, rt_model** out) {
     if (!out) return fail(RT_ERR_ARG, "rt_model_create: NULL output");
     *out = nullptr;
     if (!pos || !nbr_off || (E > 0 && !nbr_idx) || P <= 0 || E < 0)
         return fail(RT_ERR_ARG, "rt_model_create: NULL array or non-positive size");
     if (P > INT32_MAX || E > INT32_MAX)
         return fail(RT_ERR_UNSUPPORTED, "rt_model_create: more than 2^31-1 points or neighbour entries");
-    hipStream_t s = (hipStream_t)stream;
     auto* m = new rt_model();
     m->pos = pos;
     m->P = P;
@@ -317,7 +321,7 @@ extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t
     if (e == hipSuccess) e = hipMalloc((void**)&m->rows, sizeof(int2) * (size_t)P);
     if (e == hipSuccess) e = hipMalloc((void**)&bad, sizeof(int32_t));
     if (e == hipSuccess) e = launch_fill_i32(bad, 1, 0, s);
-    if (e == hipSuccess) e = launch_build_nbr(m, bad, s);
+    if (e == hipSuccess) e = launch_build_nbr(m, key, bad, s);
     int32_t hbad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -853,9 +857,15 @@ hipError_t rt::morton_order(const rt_model* m, const int32_t* origins, int64_t n
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    morton_order_host(pos.data(), m->P, origins ? org.data() : nullptr, n_o, order, seg, n_seg);
+    return hipSuccess;
+}
+
+void rt::morton_order_host(const double* pos, int64_t P, const int32_t* org, int64_t n_o, std::vector<int32_t>& order,
+                           const int64_t* seg, int n_seg) {
     auto pt = [&](int64_t k) -> int64_t {
-        int64_t o = origins ? (int64_t)org[(size_t)k] : k;
-        return (o < 0 || o >= m->P) ? 0 : o;
+        int64_t o = org ? (int64_t)org[(size_t)k] : k;
+        return (o < 0 || o >= P) ? 0 : o;
     };
     auto spread = [](uint64_t v) {  // 21 bits -> every third bit
         v &= 0x1fffff;
@@ -896,7 +906,6 @@ hipError_t rt::morton_order(const rt_model* m, const int32_t* origins, int64_t n
         std::sort(key.begin(), key.end());
         for (int64_t k = k0; k < k1; ++k) order[(size_t)k] = key[(size_t)(k - k0)].second;
     }
-    return hipSuccess;
 }
 
 extern "C" rt_status rt_spatial_order(const rt_model* m, const int32_t* origins, int64_t n_origins, int32_t* order,

@@ -10,11 +10,14 @@
 // sweep items of a chunk run direction by direction over that order, and the
 // J rows are scattered back to the caller's list order.
 //
-// rt_batch: a disjoint union of many models built on the device (neighbour ids
-// and CSR offsets shifted by each model's first point and entry; positions are
-// not moved, so every ray and every result is the one the model alone gives),
-// traced and solved by one plan; table gather, the plan's step and the scatter
-// of J to each model are one HIP graph.
+// rt_batch: a disjoint union of many models built on the device, traced and
+// solved by one plan; table gather, the plan's step and the scatter of J to
+// each model are one HIP graph.  Model k's points take the union ids base_k ..
+// base_k + P_k - 1 in the Morton order of that model's positions, so points that
+// are near in space are near in the neighbour records and the tables the walk
+// and the sweep read (direction-major over that same order).  Positions are not
+// moved and each union row keeps the order of the model's own neighbour ids, so
+// every ray and every result is the one the model alone gives.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -80,6 +83,29 @@ __global__ void k_copy_i32(const int32_t* __restrict__ src, int64_t n, int32_t* 
         dst[i] = src[i];
 }
 
+// Union point u is point perm[u] of the models' concatenation (model after model, ids
+// shifted by base_k): its position, velocity and degree.
+__global__ void k_union_points(const int32_t* __restrict__ perm, int64_t P, const double* __restrict__ pos_c,
+                               const float* __restrict__ vel_c, const int64_t* __restrict__ off_c,
+                               double* __restrict__ pos, float* __restrict__ vel, int32_t* __restrict__ deg) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < P; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = perm[u];
+        for (int i = 0; i < 3; ++i) pos[3 * u + i] = pos_c[3 * c + i];
+        if (vel) for (int i = 0; i < 3; ++i) vel[3 * u + i] = vel_c[3 * c + i];
+        deg[u] = (int32_t)(off_c[c + 1] - off_c[c]);
+    }
+}
+
+// Union row u: the neighbours of concatenated point perm[u], renamed to union ids.
+__global__ void k_union_rows(const int32_t* __restrict__ perm, const int32_t* __restrict__ uid, int64_t P,
+                             const int64_t* __restrict__ off_c, const int32_t* __restrict__ idx_c,
+                             const int64_t* __restrict__ off, int32_t* __restrict__ idx) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < P; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = perm[u], a = off_c[c], n = off_c[c + 1] - a, d = off[u];
+        for (int64_t j = 0; j < n; ++j) idx[d + j] = uid[idx_c[a + j]];
+    }
+}
+
 // One model of a batch: its tables, its J and where its points start in the union.
 struct BatchSeg {
     const void* chi;
@@ -90,28 +116,33 @@ struct BatchSeg {
     int64_t base;
 };
 
-// Union tables [P_total][F] from the models' [P_k][ld_k] tables; model k = blockIdx.y.
+// Union tables [P_total][F] from the models' [P_k][ld_k] tables; model k = blockIdx.y, union
+// row base_k + r holds the model's row lrow[base_k + r].
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_gather(const BatchSeg* __restrict__ segs, int64_t F,
+__global__ __launch_bounds__(256) void k_batch_gather(const BatchSeg* __restrict__ segs,
+                                                      const int32_t* __restrict__ lrow, int64_t F,
                                                       T* __restrict__ chi_u, T* __restrict__ eta_u) {
     const BatchSeg g = segs[blockIdx.y];
     const T* __restrict__ c = (const T*)g.chi;
     const T* __restrict__ e = (const T*)g.eta;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.P * F; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = i / F, f = i - r * F;
-        chi_u[(g.base + r) * F + f] = c[r * g.ld + f];
-        eta_u[(g.base + r) * F + f] = e[r * g.ld + f];
+        const int64_t r = i / F, f = i - r * F, src = lrow[g.base + r];
+        chi_u[(g.base + r) * F + f] = c[src * g.ld + f];
+        eta_u[(g.base + r) * F + f] = e[src * g.ld + f];
     }
 }
 
 // Each model's J [P_k][F] from the union's J rows.
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_scatter(const BatchSeg* __restrict__ segs, int64_t F,
+__global__ __launch_bounds__(256) void k_batch_scatter(const BatchSeg* __restrict__ segs,
+                                                       const int32_t* __restrict__ lrow, int64_t F,
                                                        const T* __restrict__ J_u) {
     const BatchSeg g = segs[blockIdx.y];
     T* __restrict__ J = (T*)g.J;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.P * F; i += (int64_t)gridDim.x * blockDim.x)
-        J[i] = J_u[g.base * F + i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.P * F; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / F, f = i - r * F;
+        J[lrow[g.base + r] * F + f] = J_u[(g.base + r) * F + f];
+    }
 }
 
 // Bytes of the per-chunk parts of the workspace for windows and chunks of up
@@ -352,6 +383,8 @@ struct rt_batch {
     void* eta_u = nullptr;
     void* J_u = nullptr;
     BatchSeg* segs = nullptr;  // device [n]
+    int32_t* lrow = nullptr;   // device [P_tot]: the model row of each union point
+    int32_t* uid = nullptr;    // device [P_tot]: the union id of point base_k + i of model k
     int64_t max_P = 0;
     rt_model* uni = nullptr;
     rt_plan* plan = nullptr;
@@ -367,7 +400,7 @@ static void batch_free(rt_batch* b) {
     if (b->plan) rt_plan_destroy(b->plan);
     if (b->uni) rt_model_destroy(b->uni);
     for (void* q : {(void*)b->pos, (void*)b->off, (void*)b->idx, (void*)b->vel, b->chi_u, b->eta_u, b->J_u,
-                    (void*)b->segs})
+                    (void*)b->segs, (void*)b->lrow, (void*)b->uid})
         if (q) (void)hipFree(q);
     delete b;
 }
@@ -376,10 +409,10 @@ static void batch_free(rt_batch* b) {
 static hipError_t batch_gather(rt_batch* b, hipStream_t s) {
     const dim3 grid(std::min<unsigned>(2048, blocks_of(b->max_P * b->F, 256)), (unsigned)b->n);
     if (b->dtype == RT_F64)
-        hipLaunchKernelGGL(k_batch_gather<double>, grid, dim3(256), 0, s, b->segs, b->F, (double*)b->chi_u,
+        hipLaunchKernelGGL(k_batch_gather<double>, grid, dim3(256), 0, s, b->segs, b->lrow, b->F, (double*)b->chi_u,
                            (double*)b->eta_u);
     else
-        hipLaunchKernelGGL(k_batch_gather<float>, grid, dim3(256), 0, s, b->segs, b->F, (float*)b->chi_u,
+        hipLaunchKernelGGL(k_batch_gather<float>, grid, dim3(256), 0, s, b->segs, b->lrow, b->F, (float*)b->chi_u,
                            (float*)b->eta_u);
     return hipGetLastError();
 }
@@ -391,9 +424,11 @@ static hipError_t batch_enqueue(rt_batch* b, hipStream_t s) {
     if (e == hipSuccess) e = plan_enqueue_step(b->plan, s);
     if (e != hipSuccess) return e;
     if (b->dtype == RT_F64)
-        hipLaunchKernelGGL(k_batch_scatter<double>, grid, dim3(256), 0, s, b->segs, b->F, (const double*)b->J_u);
+        hipLaunchKernelGGL(k_batch_scatter<double>, grid, dim3(256), 0, s, b->segs, b->lrow, b->F,
+                           (const double*)b->J_u);
     else
-        hipLaunchKernelGGL(k_batch_scatter<float>, grid, dim3(256), 0, s, b->segs, b->F, (const float*)b->J_u);
+        hipLaunchKernelGGL(k_batch_scatter<float>, grid, dim3(256), 0, s, b->segs, b->lrow, b->F,
+                           (const float*)b->J_u);
     return hipGetLastError();
 }
 
@@ -508,19 +543,76 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
         batch_free(b);
         return st;
     }
-    rt_status st = rt_model_create(b->pos, b->P_tot, b->off, b->idx, b->E_tot, b->vel, stream, &b->uni);
+    // The concatenation is renumbered: union point u = concatenated point perm[u], each model's
+    // points in the Morton order of its own positions.
+    const int64_t Pt = b->P_tot;
+    std::vector<int32_t> perm, uid_h((size_t)Pt), lrow_h((size_t)Pt);
+    {
+        std::vector<double> hpos((size_t)(3 * Pt));
+        e = hipMemcpyAsync(hpos.data(), b->pos, sizeof(double) * hpos.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) morton_order_host(hpos.data(), Pt, nullptr, Pt, perm, b->base_p.data(), n_models);
+    }
+    if (e == hipSuccess)
+        for (int k = 0; k < n_models; ++k)
+            for (int64_t u = b->base_p[(size_t)k]; u < b->base_p[(size_t)k + 1]; ++u) {
+                const int32_t c = perm[(size_t)u];
+                uid_h[(size_t)c] = (int32_t)u;
+                lrow_h[(size_t)u] = (int32_t)(c - b->base_p[(size_t)k]);
+            }
+    double* pos_u = nullptr;
+    int64_t* off_u = nullptr;
+    int32_t *idx_u = nullptr, *perm_d = nullptr, *deg = nullptr;
+    float* vel_u = nullptr;
+    void* scan_ws = nullptr;
+    if (e == hipSuccess) e = hipMalloc((void**)&pos_u, sizeof(double) * 3 * (size_t)Pt);
+    if (e == hipSuccess) e = hipMalloc((void**)&off_u, sizeof(int64_t) * (size_t)(Pt + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&idx_u, sizeof(int32_t) * (size_t)std::max<int64_t>(b->E_tot, 1));
+    if (e == hipSuccess && moving) e = hipMalloc((void**)&vel_u, sizeof(float) * 3 * (size_t)Pt);
+    if (e == hipSuccess) e = hipMalloc((void**)&perm_d, sizeof(int32_t) * (size_t)Pt);
+    if (e == hipSuccess) e = hipMalloc((void**)&deg, sizeof(int32_t) * (size_t)Pt);
+    if (e == hipSuccess) e = hipMalloc(&scan_ws, std::max<size_t>(scan_workspace(Pt), 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->uid, sizeof(int32_t) * (size_t)Pt);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->lrow, sizeof(int32_t) * (size_t)Pt);
+    if (e == hipSuccess) e = hipMemcpyAsync(perm_d, perm.data(), sizeof(int32_t) * (size_t)Pt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->uid, uid_h.data(), sizeof(int32_t) * (size_t)Pt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->lrow, lrow_h.data(), sizeof(int32_t) * (size_t)Pt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_union_points, dim3(blocks_of(Pt, 256)), dim3(256), 0, s, perm_d, Pt, b->pos, b->vel, b->off,
+                           pos_u, vel_u, deg);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_scan(deg, Pt, off_u, scan_ws, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_union_rows, dim3(blocks_of(Pt, 256)), dim3(256), 0, s, perm_d, b->uid, Pt, b->off, b->idx,
+                           off_u, idx_u);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // the renumbered arrays replace the concatenation
+    std::swap(b->pos, pos_u);
+    std::swap(b->off, off_u);
+    std::swap(b->idx, idx_u);
+    if (moving) std::swap(b->vel, vel_u);
+    for (void* q : {(void*)pos_u, (void*)off_u, (void*)idx_u, (void*)vel_u, (void*)deg, scan_ws})
+        if (q) (void)hipFree(q);
+    if (e != hipSuccess) {
+        if (perm_d) (void)hipFree(perm_d);
+        rt_status st = hip_fail(e, "rt_batch_create: union order");
+        batch_free(b);
+        return st;
+    }
+    // rows in the order of the concatenation's ids (the models' own order), as each model alone has them
+    rt_status st = model_create(b->pos, Pt, b->off, b->idx, b->E_tot, b->vel, perm_d, s, &b->uni);
+    (void)hipFree(perm_d);
     if (st) {
         batch_free(b);
         return st;
     }
-    // origins: every point, model after model, each model's points in Morton order of its own positions
-    std::vector<int32_t> order;
-    e = morton_order(b->uni, nullptr, b->P_tot, s, order, b->base_p.data(), n_models);
-    if (e != hipSuccess) {
-        st = hip_fail(e, "rt_batch_create: origin order");
-        batch_free(b);
-        return st;
-    }
+    // origins: every point in union order (each model's points in Morton order already)
+    std::vector<int32_t> order((size_t)Pt);
+    for (int64_t u = 0; u < Pt; ++u) order[(size_t)u] = (int32_t)u;
     // the union's tables hold the models' values from the start, so that the inner plan can be run,
     // profiled or tuned on its own (rt_batch_plan) before the first rt_batch_run
     e = batch_gather(b, s);
@@ -567,6 +659,13 @@ extern "C" rt_status rt_batch_union(const rt_batch* b, int64_t* points, int64_t*
     if (!b) return fail(RT_ERR_ARG, "rt_batch_union: NULL batch");
     if (points) *points = b->P_tot;
     if (entries) *entries = b->E_tot;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_batch_union_index(const rt_batch* b, int32_t* index, void* stream) {
+    if (!b || !index) return fail(RT_ERR_ARG, "rt_batch_union_index: NULL argument");
+    RT_HIP(hipMemcpyAsync(index, b->uid, sizeof(int32_t) * (size_t)b->P_tot, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
     return RT_OK;
 }
 

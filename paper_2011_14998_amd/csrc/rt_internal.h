@@ -110,7 +110,8 @@ namespace rt {
 
 // ---------------------------------------------------------------- kernels (launchers)
 // trace.hip
-hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s);
+// Records, ids and rows of the model; each row in ascending key[id] (key NULL: ascending id).
+hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, int32_t* bad, hipStream_t s);
 // `order` (optional): spatially sorted permutation of origin positions; the
 // rays are then walked direction-major in that origin order.
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
@@ -197,6 +198,13 @@ rt_status fill_solve_launch(const rt_model* m, rt_dirset* set, const int32_t* or
 // bounding box and the segments follow one another.  Synchronises `s` once (host copies).
 hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
                         std::vector<int32_t>& order, const int64_t* seg = nullptr, int n_seg = 0);
+// The same order from host arrays: positions [P][3], origin ids (NULL: 0..n_o-1).
+void morton_order_host(const double* pos, int64_t P, const int32_t* origins, int64_t n_o, std::vector<int32_t>& order,
+                       const int64_t* seg, int n_seg);
+// rt_model_create with the rows of the neighbour records in ascending key[id] (device [P],
+// NULL: ascending id); the walk breaks ties of equal distance by that order.
+rt_status model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx, int64_t E,
+                       const float* vel, const int32_t* key, hipStream_t s, rt_model** out);
 // Plans: create with a given origin order (nullptr = Morton order of the origins), enqueue the
 // whole step on a stream (what the plan's graph holds), and a counter that changes whenever the
 // plan's graph is re-captured.

@@ -69,12 +69,14 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
         if (!(fabs(pos[3 * p + i]) <= 1e150)) atomicOr(bad, 8);
 }
 
-// Each row's records in ascending neighbour id (insertion sort, one thread per
-// row; rows with invalid offsets are left alone -- k_check_off reports them).
-// The walk's per-lane scan relies on it: a lane meets its candidates in
-// ascending id, so keeping the first of equal distances keeps the smaller id.
+// Each row's records in ascending neighbour id, or in ascending key[id] when a key is
+// given (insertion sort, one thread per row; rows with invalid offsets are left alone --
+// k_check_off reports them).  The walk's per-lane scan relies on it: a lane meets its
+// candidates in ascending id (key), so keeping the first of equal distances keeps the
+// smaller one.
 __global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ off, int64_t P, int64_t E,
-                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid) {
+                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid,
+                                                    const int32_t* __restrict__ key) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int64_t a = off[p], b = off[p + 1];
@@ -82,8 +84,9 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ o
     for (int64_t e = a + 1; e < b; ++e) {
         const NbrRec r = nbr[e];
         const int32_t k = nid[e];
+        const int32_t kk = key ? key[k] : k;
         int64_t f = e - 1;
-        while (f >= a && nid[f] > k) {
+        while (f >= a && (key ? key[nid[f]] : nid[f]) > kk) {
             nbr[f + 1] = nbr[f];
             nid[f + 1] = nid[f];
             --f;
@@ -475,7 +478,7 @@ inline int64_t blocks_for(int64_t n, int b) { return (n + b - 1) / b; }
 
 }  // namespace
 
-hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
+hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, int32_t* bad, hipStream_t s) {
     hipLaunchKernelGGL(k_build_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
     if (m->E > 0)
         hipLaunchKernelGGL(k_build_nbr, dim3((unsigned)blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
@@ -484,7 +487,7 @@ hipError_t launch_build_nbr(const rt_model* m, int32_t* bad, hipStream_t s) {
                        m->E, bad);
     if (m->E > 0)
         hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->E, m->nbr,
-                           m->nid);
+                           m->nid, key);
     return hipGetLastError();
 }
 

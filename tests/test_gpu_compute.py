@@ -180,10 +180,70 @@ def _batch_models():
     return ms + [st]
 
 
+def _rays_np(views, n_rays):
+    off, ids, Z = views
+    off = off[:n_rays + 1].cpu().numpy()
+    return off, ids[:int(off[-1])].cpu().numpy(), Z[:int(off[-1])].cpu().numpy()
+
+
+def test_batch_union_order(rt):
+    """The union renumbers each model's points into the Morton order of its positions: the
+    union index is a permutation inside each model's id range, consecutive union ids are
+    close in space, and every ray list of the union is the model's own list with its ids
+    renamed, bit for bit (lengths, ids, Z) -- also on a lattice, whose rays meet exact
+    distance ties that the walk breaks by the model's own id order."""
+    torch = _torch()
+    ms = _batch_models()[:2]
+    lat = synth.lattice_model(6, F=ms[0].F)
+    lat.freq, lat.I_bc = ms[0].freq, ms[0].I_bc.copy()
+    ms.append(lat)
+    models = [_gpu_model(rt, m) for m in ms]
+    ds = rt.DirSet.uniform(2)
+    two_r = 2 * ds.R
+    chis, etas = [], []
+    for m in ms:
+        c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+        chis.append(_t(c32))
+        etas.append(_t(e32))
+    I_bc = _t(ms[0].I_bc, torch.float64)
+    Js = [torch.empty((m.P, m.F), dtype=torch.float32, device="cuda") for m in ms]
+    b = rt.Batch(models, ds, chis, etas, ms[0].freq.len, ms[0].freq.dx, I_bc, Js, schedule=rt.SCHED_SPATIAL)
+    b.run()
+    rt.sync_status()
+    uidx = b.union_index().cpu().numpy().astype(np.int64)
+    base = np.concatenate([[0], np.cumsum([m.P for m in ms])])
+    P_tot = int(base[-1])
+    off_u, ids_u, Z_u = _rays_np(b.rays_view(), P_tot * two_r)
+    for k, (m, mo) in enumerate(zip(ms, models)):
+        seg = uidx[base[k]:base[k + 1]]
+        assert np.array_equal(np.sort(seg), np.arange(base[k], base[k + 1]))
+        if m.name == "sph":  # consecutive union ids are neighbours in space, not in generation order
+            inv = np.empty(m.P, np.int64)
+            inv[seg - base[k]] = np.arange(m.P)
+            step_u = np.linalg.norm(np.diff(m.pos[inv], axis=0), axis=1).mean()
+            step_m = np.linalg.norm(np.diff(m.pos, axis=0), axis=1).mean()
+            assert step_u < 0.5 * step_m
+        J = torch.empty((m.P, m.F), dtype=torch.float32, device="cuda")
+        plan = rt.Plan(mo, ds, chis[k], etas[k], m.freq.len, m.freq.dx, I_bc, J, n_origins=m.P,
+                       precision=rt.RT_F32, schedule=rt.SCHED_SPATIAL)
+        plan.run()
+        rt.sync_status()
+        off_a, ids_a, Z_a = _rays_np(plan.rays_view(), m.P * two_r)
+        len_a = np.diff(off_a)
+        ray_u = (seg[np.arange(m.P)][:, None] * two_r + np.arange(two_r)[None, :]).ravel()
+        assert np.array_equal(np.diff(off_u)[ray_u], len_a)
+        src = np.repeat(off_u[ray_u], len_a) + (np.arange(len(ids_a)) - np.repeat(off_a[:-1], len_a))
+        assert np.array_equal(ids_u[src], uidx[base[k] + ids_a])
+        assert np.array_equal(Z_u[src].view(np.uint64), Z_a.view(np.uint64))
+        assert np.array_equal(Js[k].cpu().numpy(), J.cpu().numpy())
+        del plan
+
+
 @pytest.mark.parametrize("schedule", ["binned", "spatial"])
 def test_batch_equals_each_model_alone(rt, schedule):
     """The union's J of every model equals that model solved alone, bit for bit (positions
-    are not moved, neighbour ids are shifted on the device), across graph replays, after the
+    are not moved, each model's points are renumbered into Morton order on the device and
+    its neighbour rows keep the model's own id order), across graph replays, after the
     tables change in place, with one table of row stride > F, and after re-tuning."""
     torch = _torch()
     sc = rt.SCHED_BINNED if schedule == "binned" else rt.SCHED_SPATIAL

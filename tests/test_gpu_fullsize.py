@@ -1,8 +1,9 @@
 """GPU parity at full size: the launch shapes the benchmark times and the paths only large
 inputs reach, checked against the oracle on seeded samples of origins.
 
-- 64 SPH-like clouds, 4.1 million particles, as one device-built union (rt_batch), nside 2,
-  F = 64: the walk (8 lanes per ray, 197 million rays) and the sweep (spatial direct launch,
+- 64 SPH-like clouds, 4.1 million particles, as one device-built union (rt_batch, each
+  model's points renumbered into Morton order; lists compared through the union index), nside
+  2, F = 64: the walk (8 lanes per ray, 197 million rays) and the sweep (spatial direct launch,
   98 million items) both need more workgroups than one dispatch takes, so both run their
   grid-stride rounds.
 - The AMR-octree-like cloud at about 500 000 leaves, nside 4, F = 96 in two lines of 48
@@ -83,6 +84,7 @@ def test_sph_batch_full_size(rt, orc):
     print(f"union of {P_tot} particles, {b.info()['total']} list entries", flush=True)
     _, dirs, w2 = orc.dirset_uniform(2)
     views = b.rays_view()
+    uidx = b.union_index().cpu().numpy().astype(np.int64)  # union id of model point base_k + i
     rng = np.random.default_rng(40)
     base = np.concatenate([[0], np.cumsum([m.P for m in ms])])
     checked = 0
@@ -91,9 +93,9 @@ def test_sph_batch_full_size(rt, orc):
         local = np.sort(rng.choice(m.P, 25, replace=False)).astype(np.int32)
         if k == 0:
             local[0] = 0
-        g = _sampled_rays(views, lambda o: (base[k] + o) * two_r, local, two_r)
+        g = _sampled_rays(views, lambda o: uidx[base[k] + o] * two_r, local, two_r)
         e = orc.trace_all(m, dirs, local)
-        _assert_rays(g, e, id_shift=int(base[k]))
+        _assert_rays(g, (e[0], uidx[base[k] + e[1].astype(np.int64)], e[2]))
         c32, e32, c64, e64 = synth.to_fp32_tables(m.chi, m.eta)
         Je = orc.compute_J(m, dirs, w2, origins=local, chi=c64, eta=e64)
         assert _rel(Js[k][_t(local).long()].cpu().numpy().astype(np.float64), Je) <= TOL32
