@@ -296,11 +296,11 @@ extern "C" rt_status rt_dirset_destroy(rt_dirset* set) {
 
 extern "C" rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
                                      int64_t E, const float* vel, void* stream, rt_model** out) {
-    return model_create(pos, P, nbr_off, nbr_idx, E, vel, nullptr, (hipStream_t)stream, out);
+    return model_create(pos, P, nbr_off, nbr_idx, E, vel, nullptr, true, (hipStream_t)stream, out);
 }
 
 rt_status rt::model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx, int64_t E,
-                           const float* vel, const int32_t* key, hipStream_t s, rt_model** out) {
+                           const float* vel, const int32_t* key, bool morton_rows, hipStream_t s, rt_model** out) {
     if (!out) return fail(RT_ERR_ARG, "rt_model_create: NULL output");
     *out = nullptr;
     if (!pos || !nbr_off || (E > 0 && !nbr_idx) || P <= 0 || E < 0)
@@ -321,11 +321,34 @@ rt_status rt::model_create(const double* pos, int64_t P, const int64_t* nbr_off,
     if (e == hipSuccess) e = hipMalloc((void**)&m->rows, sizeof(int2) * (size_t)P);
     if (e == hipSuccess) e = hipMalloc((void**)&bad, sizeof(int32_t));
     if (e == hipSuccess) e = launch_fill_i32(bad, 1, 0, s);
-    if (e == hipSuccess) e = launch_build_nbr(m, key, bad, s);
+    if (e == hipSuccess) e = launch_check_model(m, bad, s);
     int32_t hbad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (bad) (void)hipFree(bad);
+    if (e == hipSuccess && !hbad) {  // a valid CSR: build the records
+        // rows in the Morton order of the points, so that the rows a walk reads next are near
+        // in memory (the positions' host copy is kept for the plans' origin orders)
+        std::vector<int32_t> lay;
+        int32_t* lay_d = nullptr;
+        void* ws = nullptr;
+        if (morton_rows) {
+            std::lock_guard<std::mutex> lk(m->host_mu);
+            m->host_pos.resize((size_t)P * 3);
+            e = hipMemcpyAsync(m->host_pos.data(), pos, sizeof(double) * m->host_pos.size(), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) morton_order_host(m->host_pos.data(), P, nullptr, P, lay, nullptr, 0);
+            else m->host_pos.clear();
+            if (e == hipSuccess) e = hipMalloc((void**)&lay_d, sizeof(int32_t) * (size_t)P);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lay_d, lay.data(), sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess) e = hipMalloc(&ws, build_nbr_workspace(P));
+        if (e == hipSuccess) e = launch_build_nbr(m, key, lay_d, ws, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (lay_d) (void)hipFree(lay_d);
+        if (ws) (void)hipFree(ws);
+    }
     if (e != hipSuccess) {
         rt_status st = hip_fail(e, "rt_model_create");
         if (m->nbr) (void)hipFree(m->nbr);

@@ -604,7 +604,7 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
         return st;
     }
     // rows in the order of the concatenation's ids (the models' own order), as each model alone has them
-    rt_status st = model_create(b->pos, Pt, b->off, b->idx, b->E_tot, b->vel, perm_d, s, &b->uni);
+    rt_status st = model_create(b->pos, Pt, b->off, b->idx, b->E_tot, b->vel, perm_d, false, s, &b->uni);
     (void)hipFree(perm_d);
     if (st) {
         batch_free(b);

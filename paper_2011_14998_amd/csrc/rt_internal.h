@@ -96,7 +96,7 @@ struct rt_model {
     const int32_t* idx = nullptr;
     int64_t E = 0;
     const float* vel = nullptr;
-    NbrRec* nbr = nullptr;  // owned: neighbour records in CSR order, rows sorted by id
+    NbrRec* nbr = nullptr;  // owned: neighbour records, rows in Morton order of the points, each sorted by id
     int32_t* nid = nullptr; // owned: the neighbour id of each record
     int2* rows = nullptr;   // owned: per point {row start, degree}
     int device = -1;
@@ -110,8 +110,14 @@ namespace rt {
 
 // ---------------------------------------------------------------- kernels (launchers)
 // trace.hip
-// Records, ids and rows of the model; each row in ascending key[id] (key NULL: ascending id).
-hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, int32_t* bad, hipStream_t s);
+// Checks of a model's CSR and positions (bits of *bad: 1 index out of range, 2 bad offsets,
+// 4 self neighbour, 8 position not finite or beyond 1e150).
+hipError_t launch_check_model(const rt_model* m, int32_t* bad, hipStream_t s);
+// Records, ids and rows of a checked model: the rows laid out in the point order `lay`
+// (device [P], NULL: point order), each row in ascending key[id] (key NULL: ascending id);
+// ws: build_nbr_workspace(P) bytes.
+size_t build_nbr_workspace(int64_t P);
+hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, const int32_t* lay, void* ws, hipStream_t s);
 // `order` (optional): spatially sorted permutation of origin positions; the
 // rays are then walked direction-major in that origin order.
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
@@ -203,8 +209,10 @@ void morton_order_host(const double* pos, int64_t P, const int32_t* origins, int
                        const int64_t* seg, int n_seg);
 // rt_model_create with the rows of the neighbour records in ascending key[id] (device [P],
 // NULL: ascending id); the walk breaks ties of equal distance by that order.
+// morton_rows: lay the rows of the records out in the Morton order of the points (else in
+// point order, for points that are already so ordered).
 rt_status model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx, int64_t E,
-                       const float* vel, const int32_t* key, hipStream_t s, rt_model** out);
+                       const float* vel, const int32_t* key, bool morton_rows, hipStream_t s, rt_model** out);
 // Plans: create with a given origin order (nullptr = Morton order of the origins), enqueue the
 // whole step on a stream (what the plan's graph holds), and a counter that changes whenever the
 // plan's graph is re-captured.

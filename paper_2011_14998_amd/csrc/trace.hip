@@ -30,26 +30,46 @@ namespace {
 
 constexpr int TRACE_BLOCK = 256;
 
+// The records' rows are laid out in the order `lay` (a permutation of the points; NULL:
+// point order): the row of point lay[q] is the q-th row in memory.  Degrees in that order:
+__global__ __launch_bounds__(256) void k_layout_deg(const int64_t* __restrict__ off, const int32_t* __restrict__ lay,
+                                                     int64_t P, int32_t* __restrict__ deg) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const int64_t p = lay ? (int64_t)lay[q] : q;
+    deg[q] = (int32_t)(off[p + 1] - off[p]);
+}
+
+// rows[lay[q]] = {start of the q-th row (scanned degrees), degree}
+__global__ __launch_bounds__(256) void k_layout_rows(const int64_t* __restrict__ start, const int32_t* __restrict__ deg,
+                                                      const int32_t* __restrict__ lay, int64_t P,
+                                                      int2* __restrict__ rows) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    rows[lay ? (int64_t)lay[q] : q] = make_int2((int)start[q], deg[q]);
+}
+
+// Point p's records at rows[p].x: each neighbour k's position and its own row (one thread
+// per point; the model has been checked, so every index is in range).
 __global__ __launch_bounds__(256) void k_build_nbr(const double* __restrict__ pos, int64_t P,
                                                     const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ idx, int64_t E,
-                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid,
-                                                    int32_t* __restrict__ bad) {
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int32_t k = idx[e];
-    if (k < 0 || k >= P) {
-        atomicOr(bad, 1);
-        k = 0;
+                                                    const int32_t* __restrict__ idx, const int2* __restrict__ rows,
+                                                    NbrRec* __restrict__ nbr, int32_t* __restrict__ nid) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t a = off[p], d = rows[p].x;
+    const int n = rows[p].y;
+    for (int j = 0; j < n; ++j) {
+        const int32_t k = idx[a + j];
+        NbrRec r;
+        r.x = pos[3 * (int64_t)k];
+        r.y = pos[3 * (int64_t)k + 1];
+        r.z = pos[3 * (int64_t)k + 2];
+        r.start = rows[k].x;
+        r.deg = rows[k].y;
+        nbr[d + j] = r;
+        nid[d + j] = k;
     }
-    NbrRec r;
-    r.x = pos[3 * (int64_t)k];
-    r.y = pos[3 * (int64_t)k + 1];
-    r.z = pos[3 * (int64_t)k + 2];
-    r.start = (int32_t)off[k];
-    r.deg = (int32_t)(off[k + 1] - off[k]);
-    nbr[e] = r;
-    nid[e] = k;
 }
 
 __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
@@ -62,25 +82,25 @@ __global__ __launch_bounds__(256) void k_check_off(const int64_t* __restrict__ o
         atomicOr(bad, 2);
         return;
     }
-    for (int64_t e = a; e < b; ++e)
+    for (int64_t e = a; e < b; ++e) {
+        if (idx[e] < 0 || idx[e] >= P) atomicOr(bad, 1);
         if (idx[e] == p) atomicOr(bad, 4);
+    }
     // |x| <= 1e150 keeps every squared distance of the walk finite
     for (int i = 0; i < 3; ++i)
         if (!(fabs(pos[3 * p + i]) <= 1e150)) atomicOr(bad, 8);
 }
 
 // Each row's records in ascending neighbour id, or in ascending key[id] when a key is
-// given (insertion sort, one thread per row; rows with invalid offsets are left alone --
-// k_check_off reports them).  The walk's per-lane scan relies on it: a lane meets its
-// candidates in ascending id (key), so keeping the first of equal distances keeps the
-// smaller one.
-__global__ __launch_bounds__(256) void k_sort_rows(const int64_t* __restrict__ off, int64_t P, int64_t E,
+// given (insertion sort, one thread per row).  The walk's per-lane scan relies on it: a
+// lane meets its candidates in ascending id (key), so keeping the first of equal
+// distances keeps the smaller one.
+__global__ __launch_bounds__(256) void k_sort_rows(const int2* __restrict__ rows, int64_t P,
                                                     NbrRec* __restrict__ nbr, int32_t* __restrict__ nid,
                                                     const int32_t* __restrict__ key) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int64_t a = off[p], b = off[p + 1];
-    if (a < 0 || a > b || b > E) return;
+    const int64_t a = rows[p].x, b = a + rows[p].y;
     for (int64_t e = a + 1; e < b; ++e) {
         const NbrRec r = nbr[e];
         const int32_t k = nid[e];
@@ -385,12 +405,6 @@ __global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ pid
     }
 }
 
-__global__ __launch_bounds__(256) void k_build_rows(const int64_t* __restrict__ off, int64_t P,
-                                                     int2* __restrict__ rows) {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    rows[p] = make_int2((int)off[p], (int)(off[p + 1] - off[p]));
-}
 
 // ---------------------------------------------------------------- scan
 // Exclusive scan of int32 lengths into int64 offsets, off[n] = total.
@@ -478,16 +492,31 @@ inline int64_t blocks_for(int64_t n, int b) { return (n + b - 1) / b; }
 
 }  // namespace
 
-hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, int32_t* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_build_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->rows);
-    if (m->E > 0)
-        hipLaunchKernelGGL(k_build_nbr, dim3((unsigned)blocks_for(m->E, 256)), dim3(256), 0, s, m->pos, m->P, m->off, m->idx,
-                           m->E, m->nbr, m->nid, bad);
+hipError_t launch_check_model(const rt_model* m, int32_t* bad, hipStream_t s) {
     hipLaunchKernelGGL(k_check_off, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->idx, m->pos, m->P,
                        m->E, bad);
-    if (m->E > 0)
-        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)blocks_for(m->P, 256)), dim3(256), 0, s, m->off, m->P, m->E, m->nbr,
-                           m->nid, key);
+    return hipGetLastError();
+}
+
+static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t build_nbr_workspace(int64_t P) {
+    return al256(sizeof(int32_t) * (size_t)P) + al256(sizeof(int64_t) * (size_t)(P + 1)) + al256(scan_workspace(P));
+}
+
+hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, const int32_t* lay, void* ws, hipStream_t s) {
+    int32_t* deg = (int32_t*)ws;
+    int64_t* start = (int64_t*)((char*)ws + al256(sizeof(int32_t) * (size_t)m->P));
+    void* scan_ws = (char*)start + al256(sizeof(int64_t) * (size_t)(m->P + 1));
+    const unsigned g = (unsigned)blocks_for(m->P, 256);
+    hipLaunchKernelGGL(k_layout_deg, dim3(g), dim3(256), 0, s, m->off, lay, m->P, deg);
+    hipError_t e = launch_scan(deg, m->P, start, scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layout_rows, dim3(g), dim3(256), 0, s, start, deg, lay, m->P, m->rows);
+    if (m->E > 0) {
+        hipLaunchKernelGGL(k_build_nbr, dim3(g), dim3(256), 0, s, m->pos, m->P, m->off, m->idx, m->rows, m->nbr, m->nid);
+        hipLaunchKernelGGL(k_sort_rows, dim3(g), dim3(256), 0, s, m->rows, m->P, m->nbr, m->nid, key);
+    }
     return hipGetLastError();
 }
 
