@@ -42,8 +42,8 @@ F = 64
 # Plan options per workload: what the autotuner (rt_autotune_plan, `--autotune`) chose on MI355X,
 # kept fixed so that the timed kernel variant is the one the committed counters were taken on.
 TUNED = {
-    "sph_batch": dict(schedule=2, group=8, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "wind": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "sph_batch": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "wind": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "octree": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "octree_reduced": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
 }

@@ -1059,8 +1059,19 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
     }
 }
 
+// Waves per SIMD the direct sweep is compiled for: the FP32 second-order sweep with
+// load groups of 4 and one frequency spacing fits 64 VGPRs (one spilled register), so
+// 8 waves share a SIMD and hide more of the table loads' latency (on the 64-cloud batch
+// 396 ms against 407 at the 7 waves its registers would otherwise allow); the others
+// keep the compiler's choice (held to 64 registers they spill heavily).
+template <typename T, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
+constexpr int solve_direct_waves() {
+    return (sizeof(T) == 4 && UDX && GROUP == 4 && !REF && SCH == 0 && !PACK) ? 8 : 1;
+}
+
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
-__global__ __launch_bounds__(SOLVE_BLOCK) void k_solve_direct(const SolveLaunch a) {
+__global__ __launch_bounds__(SOLVE_BLOCK, (solve_direct_waves<T, UDX, GROUP, REF, SCH, PACK>())) void k_solve_direct(
+    const SolveLaunch a) {
     constexpr int WORDS = REF ? REF_STAGE_WORDS : STAGE_WORDS;
     __shared__ uint32_t stage_all[WAVES_PER_BLOCK * 64 * WORDS];
     uint32_t* stage = stage_all + (threadIdx.x >> 6) * 64 * WORDS;
