@@ -44,8 +44,8 @@ F = 64
 TUNED = {
     "sph_batch": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
     "wind": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "octree": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "octree_reduced": dict(schedule=2, group=8, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree_reduced": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
 }
 
 

@@ -1062,11 +1062,13 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
 // Waves per SIMD the direct sweep is compiled for: the FP32 second-order sweep with
 // load groups of 4 and one frequency spacing fits 64 VGPRs (one spilled register), so
 // 8 waves share a SIMD and hide more of the table loads' latency (on the 64-cloud batch
-// 396 ms against 407 at the 7 waves its registers would otherwise allow); the others
-// keep the compiler's choice (held to 64 registers they spill heavily).
+// 396 ms against 407 at the 7 waves its registers would otherwise allow); its packed
+// half-wave variant fits 80 (6 waves, two spilled; the 507k-leaf octree 747 ms against
+// 762 with groups of 8 at 4 waves).  The others keep the compiler's choice (held to 64
+// registers they spill heavily).
 template <typename T, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
 constexpr int solve_direct_waves() {
-    return (sizeof(T) == 4 && UDX && GROUP == 4 && !REF && SCH == 0 && !PACK) ? 8 : 1;
+    return (sizeof(T) == 4 && UDX && GROUP == 4 && !REF && SCH == 0) ? (PACK ? 6 : 8) : 1;
 }
 
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
