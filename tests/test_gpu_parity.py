@@ -153,6 +153,25 @@ def test_model_rejects_bad_indices(rt):
     assert ex.value.code == -2
 
 
+@pytest.mark.parametrize("case", ["non_monotone", "short_end", "self_neighbour", "negative_index"])
+def test_model_rejects_bad_csr(rt, case):
+    """A malformed CSR is refused by the check that runs before the records are laid out
+    (the layout scans the degrees, so it only ever sees offsets that run from 0 to E)."""
+    m = synth.tiny_model(5, P=20)
+    off, idx = m.nbr_off.copy(), m.nbr_idx.copy()
+    if case == "non_monotone":
+        off[5], off[6] = off[6], off[5]
+    elif case == "short_end":
+        idx = idx[:-1].copy()  # offsets end beyond the neighbour array
+    elif case == "self_neighbour":
+        idx[off[3]] = 3
+    else:
+        idx[2] = -1
+    with pytest.raises(rt.RtError) as ex:
+        rt.Model.from_numpy(m.pos, off, idx)
+    assert ex.value.code == -2
+
+
 # ----------------------------------------------------------------------------- solve, FP64
 
 def _solve_gpu(rt, m, model, ds, rays, org, n_o, precision, chi=None, eta=None, **kw):
