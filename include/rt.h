@@ -108,12 +108,15 @@ rt_status rt_dirset_destroy(rt_dirset* set);
  * neighbour lists on the device (indices in range, no self entries; error
  * RT_ERR_MESH) and the positions (finite, every coordinate of magnitude at most
  * 1e150 so that the walk's squared distances stay finite; error RT_ERR_ARG)
- * and synchronises once on `stream` to read the verdict.  Builds a neighbour-
- * record table (36 bytes per neighbour entry: position, id, the neighbour's
- * own row; each row sorted by id) that the tracer reads instead of chasing
- * nbr_idx into pos and nbr_off.  The order of a point's neighbours in nbr_idx
- * does not affect any result.  The positions and lists must not change while
- * the handle lives. */
+ * and synchronises on `stream` to read the verdict before anything is built.
+ * Then builds a neighbour-record table (36 bytes per neighbour entry: position,
+ * id, the neighbour's own row; each row sorted by id) that the tracer reads
+ * instead of chasing nbr_idx into pos and nbr_off, with the rows laid out in
+ * the Morton order of the points (computed on the host from a copy of the
+ * positions, which the handle keeps for the spatial orders of plans; 24 bytes
+ * of host memory per point).  The order of a point's neighbours in nbr_idx and
+ * the order of the points do not affect any result.  The positions and lists
+ * must not change while the handle lives. */
 rt_status rt_model_create(const double* pos, int64_t P, const int64_t* nbr_off, const int32_t* nbr_idx,
                           int64_t E, const float* vel, void* stream, rt_model** out);
 rt_status rt_model_destroy(rt_model* model);
