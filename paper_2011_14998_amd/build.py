@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtmi.so")
 ARCH = os.environ.get("RT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["healpix.cpp", "trace.hip", "solve.hip", "dirset.hip", "api.hip", "compute.hip", "closure.hip", "mesh.hip"]
+SOURCES = ["healpix.cpp", "trace.hip", "solve.hip", "dirset.hip", "api.hip", "compute.hip", "closure.hip", "mesh.hip",
+           "order.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -777,6 +777,10 @@ struct rt_plan {
     double* pZ = nullptr;
     // spatial schedule: origin order (Morton), built on first use
     int32_t* order = nullptr;
+    // the sweep's per-pair orders ([R][n_origins]; uniform sets), built on first use of the spatial
+    // schedule over the segments below (one by default: the model's bounding sphere)
+    int32_t* pair_order = nullptr;
+    std::vector<OrderSeg> segs;
     // the solve launch as filled from the caller's arguments, before any schedule is applied
     SolveLaunch base;
     void* u_buf = nullptr;
@@ -845,7 +849,8 @@ static void plan_free(rt_plan* p) {
     (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    for (void* q : {(void*)p->lens, (void*)p->ray_off, p->scan_ws, p->solve_ws, (void*)p->order, p->bin_buf})
+    for (void* q : {(void*)p->lens, (void*)p->ray_off, p->scan_ws, p->solve_ws, (void*)p->order, p->bin_buf,
+                    (void*)p->pair_order})
         if (q) (void)hipFree(q);
     const int dev = p->m->device;
     pool_free(p->ids, p->ids_bytes, dev);
@@ -945,6 +950,66 @@ extern "C" rt_status rt_spatial_order(const rt_model* m, const int32_t* origins,
 // the schedule needs on first use (spatial origin order, bin workspace) and
 // re-capture the whole step as one graph on a private stream (the caller's
 // stream may be the legacy default stream, which cannot be captured).
+
+// The sweep's per-pair orders of a plan over a uniform set (order.hip), built once; skipped
+// (Morton order for every pair) for per-origin sets and when they would take more than
+// 2 GiB.  Without given segments the model's points' bounding sphere is the one segment.
+static hipError_t plan_pair_orders(rt_plan* p) {
+    if (p->pair_order || p->n_origins <= 0 || p->set->n_origins > 0) return hipSuccess;
+    const int64_t R = p->set->R, n = p->n_origins;
+    if ((double)R * (double)n * 4.0 > 2147483648.0) return hipSuccess;
+    std::vector<OrderSeg> segs = p->segs;
+    if (segs.empty()) {
+        std::lock_guard<std::mutex> lk(p->m->host_mu);
+        std::vector<double>& hp = p->m->host_pos;
+        if (hp.empty()) {
+            hp.resize((size_t)p->m->P * 3);
+            hipError_t e = hipMemcpy(hp.data(), p->m->pos, sizeof(double) * hp.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                hp.clear();
+                return e;
+            }
+        }
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t q = 0; q < p->m->P; ++q)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], hp[(size_t)(3 * q + c)]);
+                hi[c] = std::max(hi[c], hp[(size_t)(3 * q + c)]);
+            }
+        OrderSeg g;
+        g.end = n;
+        double r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            g.c[c] = 0.5 * (lo[c] + hi[c]);
+            r2 += 0.25 * (hi[c] - lo[c]) * (hi[c] - lo[c]);
+        }
+        g.rho = std::sqrt(r2);
+        segs.push_back(g);
+    }
+    std::vector<double> dirs((size_t)(3 * R));
+    hipError_t e = hipMemcpy(dirs.data(), p->set->d_dirs(), sizeof(double) * dirs.size(), hipMemcpyDeviceToHost);
+    OrderSeg* dsegs = nullptr;
+    void* ws = nullptr;
+    int32_t* out = nullptr;
+    if (e == hipSuccess) e = hipMalloc((void**)&dsegs, sizeof(OrderSeg) * segs.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(dsegs, segs.data(), sizeof(OrderSeg) * segs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&ws, pair_order_workspace(n));
+    if (e == hipSuccess) e = hipMalloc((void**)&out, sizeof(int32_t) * (size_t)(R * n));
+    if (e == hipSuccess)
+        e = build_pair_orders(p->m->pos, p->m->P, p->origins, n, dirs.data(), R, dsegs, (int)segs.size(), out, ws,
+                              p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (dsegs) (void)hipFree(dsegs);
+    if (ws) (void)hipFree(ws);
+    if (e != hipSuccess) {
+        if (out) (void)hipFree(out);
+        return e;
+    }
+    p->pair_order = out;
+    return hipSuccess;
+}
+
 static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     if (o.schedule < RT_SCHED_DIRECT || o.schedule > RT_SCHED_SPATIAL) return fail(RT_ERR_ARG, "plan: bad schedule");
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "plan: group must be 4 or 8");
@@ -984,9 +1049,18 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
             return hip_fail(e, "plan: spatial order");
         }
     }
-    // the spatial schedule walks the sweep's items in the origins' Morton order; the
-    // binned schedule uses the same order inside each length bin
+    // the spatial schedule walks the sweep's items direction by direction, each pair's
+    // items in that pair's line order (Morton order of the origins when there is none);
+    // the binned schedule uses the Morton order inside each length bin
     if (o.schedule == RT_SCHED_SPATIAL || o.schedule == RT_SCHED_BINNED) a.order = p->order;
+    if (o.schedule == RT_SCHED_SPATIAL) {
+        e = plan_pair_orders(p);
+        if (e != hipSuccess) {
+            p->o = prev;
+            return hip_fail(e, "plan: pair orders");
+        }
+        a.pair_order = p->pair_order;
+    }
     if (o.schedule == RT_SCHED_BINNED) {
         const size_t need = align_up(bin_workspace(solve_items(a), 128)) + 256;
         if (!p->bin_buf) {
@@ -1048,7 +1122,8 @@ extern "C" rt_status rt_plan_create(const rt_model* m, const rt_dirset* set_, co
 rt_status rt::plan_create_ordered(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
                                   const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
                                   const double* I_bc, void* J, const rt_solve_opts* opts, hipStream_t stream,
-                                  const std::vector<int32_t>* given_order, rt_plan** out) {
+                                  const std::vector<int32_t>* given_order, rt_plan** out,
+                                  const std::vector<OrderSeg>* segs) {
     if (!out) return fail(RT_ERR_ARG, "rt_plan_create: NULL output");
     *out = nullptr;
     rt_status st = check_trace_args(m, set, n_origins, "rt_plan_create");
@@ -1065,6 +1140,7 @@ rt_status rt::plan_create_ordered(const rt_model* m, rt_dirset* set, const int32
     p->n_origins = n_origins;
     p->n_rays = n_origins * 2 * set->R;
     p->o = opts ? *opts : default_opts();
+    if (segs) p->segs = *segs;
     hipError_t e = hipMalloc((void**)&p->lens, sizeof(int32_t) * (size_t)std::max<int64_t>(p->n_rays, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&p->ray_off, sizeof(int64_t) * (size_t)(p->n_rays + 1));
     if (e == hipSuccess) e = hipMalloc(&p->scan_ws, scan_workspace(p->n_rays));

@@ -547,12 +547,10 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
     // points in the Morton order of its own positions.
     const int64_t Pt = b->P_tot;
     std::vector<int32_t> perm, uid_h((size_t)Pt), lrow_h((size_t)Pt);
-    {
-        std::vector<double> hpos((size_t)(3 * Pt));
-        e = hipMemcpyAsync(hpos.data(), b->pos, sizeof(double) * hpos.size(), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess) morton_order_host(hpos.data(), Pt, nullptr, Pt, perm, b->base_p.data(), n_models);
-    }
+    std::vector<double> hpos_seg((size_t)(3 * Pt));  // concatenation order: model k at base_k ..
+    e = hipMemcpyAsync(hpos_seg.data(), b->pos, sizeof(double) * hpos_seg.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) morton_order_host(hpos_seg.data(), Pt, nullptr, Pt, perm, b->base_p.data(), n_models);
     if (e == hipSuccess)
         for (int k = 0; k < n_models; ++k)
             for (int64_t u = b->base_p[(size_t)k]; u < b->base_p[(size_t)k + 1]; ++u) {
@@ -610,9 +608,27 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
         batch_free(b);
         return st;
     }
-    // origins: every point in union order (each model's points in Morton order already)
+    // origins: every point in union order (each model's points in Morton order already); the
+    // sweep's per-pair orders keep the models apart, each in its own bounding sphere
     std::vector<int32_t> order((size_t)Pt);
     for (int64_t u = 0; u < Pt; ++u) order[(size_t)u] = (int32_t)u;
+    std::vector<OrderSeg> segs((size_t)n_models);
+    for (int k = 0; k < n_models; ++k) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t q = b->base_p[(size_t)k]; q < b->base_p[(size_t)k + 1]; ++q)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], hpos_seg[(size_t)(3 * q + c)]);
+                hi[c] = std::max(hi[c], hpos_seg[(size_t)(3 * q + c)]);
+            }
+        OrderSeg& g = segs[(size_t)k];
+        g.end = b->base_p[(size_t)k + 1];
+        double r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            g.c[c] = 0.5 * (lo[c] + hi[c]);
+            r2 += 0.25 * (hi[c] - lo[c]) * (hi[c] - lo[c]);
+        }
+        g.rho = std::sqrt(r2);
+    }
     // the union's tables hold the models' values from the start, so that the inner plan can be run,
     // profiled or tuned on its own (rt_batch_plan) before the first rt_batch_run
     e = batch_gather(b, s);
@@ -623,7 +639,7 @@ extern "C" rt_status rt_batch_create(int32_t n_models, const rt_model* const* mo
         return st;
     }
     st = plan_create_ordered(b->uni, set, nullptr, b->P_tot, b->chi_u, b->eta_u, dtype, F, grid, I_bc, b->J_u, opts,
-                             s, &order, &b->plan);
+                             s, &order, &b->plan, &segs);
     if (!st) st = batch_capture(b);
     if (st) {
         batch_free(b);

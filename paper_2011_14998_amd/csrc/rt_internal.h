@@ -166,6 +166,7 @@ struct SolveLaunch {
     int32_t schedule;
     const int32_t* items;  // binned order, or nullptr
     const int32_t* order;  // spatial order of origin positions (direct launch, direction-major), or nullptr
+    const int32_t* pair_order;  // with order: the sweep's own order per pair ([R][n_origins]), or nullptr
     int32_t* queue;        // persistent counter, or nullptr
     int32_t grid_waves;    // persistent grid size in waves
     int32_t n_bins;
@@ -204,6 +205,20 @@ rt_status fill_solve_launch(const rt_model* m, rt_dirset* set, const int32_t* or
 // bounding box and the segments follow one another.  Synchronises `s` once (host copies).
 hipError_t morton_order(const rt_model* m, const int32_t* origins, int64_t n_o, hipStream_t s,
                         std::vector<int32_t>& order, const int64_t* seg = nullptr, int n_seg = 0);
+// Per-pair sweep orders (order.hip): for each pair r, the origin positions sorted by
+// (segment, 2D Morton code across d_r, position along d_r).  A segment covers the origin
+// positions below `end` not in an earlier one, inside the sphere (c, rho).
+struct OrderSeg {
+    int64_t end;
+    double c[3];
+    double rho;
+};
+size_t pair_order_workspace(int64_t n_o);
+// pos, origins, segs (n_seg <= 65535) and out ([R][n_o]) on the device; dirs_host [R][3] on
+// the host; ws: pair_order_workspace(n_o) bytes.  Asynchronous on s.
+hipError_t build_pair_orders(const double* pos, int64_t P, const int32_t* origins, int64_t n_o, const double* dirs_host,
+                             int64_t R, const OrderSeg* segs, int n_seg, int32_t* out, void* ws, hipStream_t s);
+
 // The same order from host arrays: positions [P][3], origin ids (NULL: 0..n_o-1).
 void morton_order_host(const double* pos, int64_t P, const int32_t* origins, int64_t n_o, std::vector<int32_t>& order,
                        const int64_t* seg, int n_seg);
@@ -219,7 +234,8 @@ rt_status model_create(const double* pos, int64_t P, const int64_t* nbr_off, con
 rt_status plan_create_ordered(const rt_model* m, rt_dirset* set, const int32_t* origins, int64_t n_origins,
                               const void* chi, const void* eta, int32_t dtype, int64_t ld, const rt_freq_grid* grid,
                               const double* I_bc, void* J, const rt_solve_opts* opts, hipStream_t s,
-                              const std::vector<int32_t>* order, rt_plan** out);
+                              const std::vector<int32_t>* order, rt_plan** out,
+                              const std::vector<OrderSeg>* segs = nullptr);
 hipError_t plan_enqueue_step(rt_plan* p, hipStream_t s);
 int64_t plan_version(const rt_plan* p);
 

@@ -1085,9 +1085,10 @@ __global__ __launch_bounds__(SOLVE_BLOCK, (solve_direct_waves<T, UDX, GROUP, REF
         const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
         if (it >= n_items) continue;
         int64_t w;
-        if (a.order) {  // direction-major over spatially ordered origins
+        if (a.order) {  // direction-major over spatially ordered origins (each pair's own order when given)
             const int64_t rc = it / a.n_origins;
-            const int64_t oi = a.order[it - rc * a.n_origins];
+            const int64_t q = it - rc * a.n_origins;
+            const int64_t oi = a.pair_order ? a.pair_order[(rc / nfc) * a.n_origins + q] : a.order[q];
             w = oi * a.R * nfc + rc;  // rc = r * nfc + chunk
         } else {
             w = a.items ? (int64_t)a.items[it] : it;
