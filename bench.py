@@ -12,13 +12,14 @@ one launch per kernel, replayed as one HIP graph.
 One timed step = one replay of that graph, inputs resident in HBM: the gather of
 the 64 models' chi/eta tables into the union, the walk of every ray straight into
 its slot of the ray lists (slots sized by the count pass and scan that ran once
-when the batch was created), the length-binned persistent Feautrier sweep, the J
+when the batch was created), the Feautrier sweep (direction by direction, each pair's
+items in its own line order), the J
 reduction, and the scatter of J back to the 64 models.  The cold call -- the
 whole path from scratch (union build, Morton order, count pass, scan,
 allocation, graph capture, one run) -- is timed once beside it.
 
-Prints one JSON line: the metric, the roofline of the sweep kernel (measured DRAM
-traffic from the committed rocprofv3 counters, and the algorithmic byte count
+Prints one JSON line: the metric, the rooflines of the sweep and the walk (measured
+DRAM traffic from the committed rocprofv3 counters, and the algorithmic byte count
 beside it), the other workloads' numbers, and the CPU oracle on a seeded sample.
 """
 from __future__ import annotations
@@ -66,6 +67,13 @@ def sweep_bytes(n_origins, R, total_entries, F, moving, es=4):
     return points * (2 * F * es + 4 + 8 + (12 if moving else 0)) + n_origins * R * F * es
 
 
+def walk_bytes(n_rays, total_entries, mean_degree):
+    """Algorithmic bytes of one walk launch: every step reads the current point's row of
+    32-byte neighbour records (mean degree of the model), and each list entry reads one id
+    and writes 12 bytes; a ray takes one step per entry plus the step that ends it."""
+    return (total_entries + n_rays) * mean_degree * 32 + total_entries * 16
+
+
 def src_hash(*names):
     h = hashlib.sha256()
     for n in names:
@@ -75,6 +83,7 @@ def src_hash(*names):
 
 
 SWEEP_SRC = ("solve.hip", "rt_internal.h")
+WALK_SRC = ("trace.hip", "rt_internal.h")
 KERNEL_KEYS = {"sweep": ("k_solve_direct", "k_solve_persist"), "walk": ("k_trace<1", "k_trace<2"),
                "compact": ("k_compact",), "reduce": ("k_reduce",), "gather": ("k_batch_gather",)}
 
@@ -107,6 +116,7 @@ def summarize_counters(d, workload, out_json, out_md, bench_cmd):
     fscale = kib / cf["copy"]
     wscale = kib / cw["copy"]
     res = {"workload": workload, "command": bench_cmd, "kernel_src_hash": src_hash(*SWEEP_SRC),
+           "walk_src_hash": src_hash(*WALK_SRC),
            "calibration": {"copy_bytes": 1 << 30, "FETCH_SIZE_KiB": cf["copy"], "WRITE_SIZE_KiB": cw["copy"],
                            "fetch_scale": fscale, "write_scale": wscale},
            "per_launch": {}}
@@ -205,14 +215,18 @@ def copy_ceiling_gbs(dev, n_bytes: int = 2 << 30, reps: int = 5) -> float:
     return rate
 
 
-def load_traffic(workload):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary of this
-    workload, if it was taken on the current sweep source (else None)."""
+def load_traffic(workload, kernel="sweep"):
+    """HBM bytes per launch of the sweep (or the walk) from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the kernel's current source (else None)."""
     path = os.path.join(ROOT, "profiles", f"sweep_{workload}_counters.json")
     if not os.path.exists(path):
         return None, None
     with open(path) as f:
         d = json.load(f)
+    if kernel == "walk":
+        if d.get("walk_src_hash") != src_hash(*WALK_SRC):
+            return None, path
+        return d.get("per_launch", {}).get("walk", {}).get("hbm_bytes"), path
     if d.get("kernel_src_hash") != src_hash(*SWEEP_SRC):
         return None, path
     return d.get("hbm_bytes_per_launch"), path
@@ -310,6 +324,25 @@ def _roofline(workload, stages, alg, dev):
     return r
 
 
+def _roofline_walk(workload, stages, alg):
+    traffic, path = load_traffic(workload, "walk")
+    walk_s = stages["walk"] * 1e-3
+    r = {"kernel": "walk", "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "achieved": None, "frac": None,
+         "traffic": traffic, "walk_ms": stages["walk"],
+         "measured": ("DRAM-side bytes per launch from the same rocprofv3 session in " + os.path.relpath(path, ROOT))
+         if path else None}
+    if traffic:
+        r["achieved"] = traffic / walk_s / 1e9
+        r["frac"] = r["achieved"] / HBM_PEAK_GBS
+    elif path:
+        r["measured"] += " (taken on another walk source: not used)"
+    r["algorithmic"] = {"bytes_per_launch": alg, "gbs": alg / walk_s / 1e9, "frac": alg / walk_s / 1e9 / HBM_PEAK_GBS,
+                        "model": "per step the current point's row of 32-byte neighbour records at the model's mean "
+                                 "degree, per list entry a 4-byte id read and 12 bytes written; re-reads served by "
+                                 "the caches count too"}
+    return r
+
+
 def _other_wind(rt, torch, dev, steps=10):
     """The 50 000-point analytic wind at nside 4 (one plan), as an extra line of numbers."""
     import synth
@@ -390,6 +423,8 @@ def run_batch(args, rt, torch, dev):
                                  "ray into its slot (slots from the count pass and scan at creation), sweep ("
                                  + SCHEDULE_NAMES[opts["schedule"]] + "), J reduction, J scatter to the 64 models"},
         "roofline": roof,
+        "roofline_walk": _roofline_walk("sph_batch", stages,
+                                        walk_bytes(P_tot * 2 * R, total, sum(m.E for m in ms_) / P_tot)),
         "stages_ms": stages,
         "line_point_freq_updates_per_s": (total + P_tot * R) * F / (ms * 1e-3),
     }
@@ -466,6 +501,8 @@ def run_plan_workload(args, rt, torch, dev):
                                  "the count pass and scan at creation), sweep (" + SCHEDULE_NAMES[opts["schedule"]]
                                  + "), J reduction"},
         "roofline": _roofline(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages, alg, dev),
+        "roofline_walk": _roofline_walk(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages,
+                                        walk_bytes(m.P * 2 * R, total, m.E / m.P)),
         "stages_ms": stages,
         "line_point_freq_updates_per_s": (total + m.P * R) * Fw / (ms * 1e-3),
     }
