@@ -952,12 +952,13 @@ extern "C" rt_status rt_spatial_order(const rt_model* m, const int32_t* origins,
 // stream may be the legacy default stream, which cannot be captured).
 
 // The sweep's per-pair orders of a plan over a uniform set (order.hip), built once; skipped
-// (Morton order for every pair) for per-origin sets and when they would take more than
-// 2 GiB.  Without given segments the model's points' bounding sphere is the one segment.
+// (Morton order for every pair) for per-origin sets, when they would take more than 2 GiB,
+// for more than 65 535 segments, and when the device memory for them is not there.
+// Without given segments the model's points' bounding sphere is the one segment.
 static hipError_t plan_pair_orders(rt_plan* p) {
     if (p->pair_order || p->n_origins <= 0 || p->set->n_origins > 0) return hipSuccess;
     const int64_t R = p->set->R, n = p->n_origins;
-    if ((double)R * (double)n * 4.0 > 2147483648.0) return hipSuccess;
+    if ((double)R * (double)n * 4.0 > 2147483648.0 || p->segs.size() > 65535) return hipSuccess;
     std::vector<OrderSeg> segs = p->segs;
     if (segs.empty()) {
         std::lock_guard<std::mutex> lk(p->m->host_mu);
@@ -1004,6 +1005,10 @@ static hipError_t plan_pair_orders(rt_plan* p) {
     if (ws) (void)hipFree(ws);
     if (e != hipSuccess) {
         if (out) (void)hipFree(out);
+        if (e == hipErrorOutOfMemory) {  // an optimisation only: the sweep keeps the Morton order
+            (void)hipGetLastError();
+            return hipSuccess;
+        }
         return e;
     }
     p->pair_order = out;
