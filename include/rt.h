@@ -211,10 +211,14 @@ typedef struct {
                                  slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
                                  queue, longest lines first, 16 items per queue atomic (plans: the
                                  origins' Morton order inside each bin); RT_SCHED_SPATIAL (plans only): sweep items
-                                 direction by direction, origins in Morton order of their positions,
-                                 each XCD on a contiguous range -- concurrent waves then read mostly the
-                                 same rows and the L2s hold them.  A plan's walk always uses that
-                                 order. */
+                                 direction by direction, each XCD on a contiguous range, with a uniform
+                                 set each pair's items in that pair's line order (origins sorted by the
+                                 2D Morton code of their position across the pair's direction, then
+                                 along it; built on the device when the plan is configured, R x
+                                 n_origins int32 of device memory, skipped above 2 GiB) and otherwise in
+                                 the Morton order of the origins' positions -- concurrent waves then
+                                 read mostly the same rows and the L2s hold them.  A plan's walk always
+                                 uses the Morton order. */
     int32_t waves_per_cu;     /* persistent grid size in waves per CU (0 = 32; at most 256) */
     int32_t n_bins;           /* length bins for RT_SCHED_BINNED (0 = default 64, at most 128) */
     int32_t bins_per_octave;  /* RT_SCHED_BINNED bin edges: a pair whose line holds N points goes to bin
