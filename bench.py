@@ -321,6 +321,8 @@ def _roofline(workload, stages, alg, dev):
                                  "that reads them, plus the u rows; re-reads served by L2 and the Infinity Cache "
                                  "count too, so this fraction can exceed 1"}
     r["copy_ceiling_gbs"] = copy_ceiling_gbs(dev)
+    r["note"] = ("frac is the DRAM fraction, not the sweep's limit: the caches serve most of its table reads (the "
+                 "algorithmic fraction exceeds 1) and it is held by VALU issue and the latency of L2-served loads")
     return r
 
 
