@@ -44,9 +44,9 @@ F = 64
 # kept fixed so that the timed kernel variant is the one the committed counters were taken on.
 TUNED = {
     "sph_batch": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "wind": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "octree": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
-    "octree_reduced": dict(schedule=2, group=4, trace_lanes=8, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "wind": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
+    "octree_reduced": dict(schedule=2, group=4, trace_lanes=4, waves_per_cu=0, n_bins=0, bins_per_octave=0),
 }
 
 
@@ -713,7 +713,7 @@ def run_mlp(args):
 
 
 def run_precision(args):
-    """FP32 sweep (FP64 geometry, FP64 rows below the threshold) and FP64 sweep against the FP64
+    """FP32 sweep (FP64 geometry) and FP64 sweep against the FP64
     oracle fed the same FP32 table values, on seeded origin samples of each model; one JSON line."""
     import torch
 

@@ -224,8 +224,8 @@ typedef struct {
     int32_t bins_per_octave;  /* RT_SCHED_BINNED bin edges: a pair whose line holds N points goes to bin
                                  floor(bins_per_octave * log2 N) (the last bin open-ended); 1, 2, 4 or
                                  8 (0 = 4, quarter octaves) */
-    int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 8) */
-    int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 8) */
+    int32_t group;            /* sweep: line points whose loads are issued together, 4 or 8 (0 = 4) */
+    int32_t trace_lanes;      /* plans: lanes walking one ray, 4, 8 or 16 (0 = 4) */
     int64_t padded_trace_budget; /* plans, RT_WALK_PADDED: bytes allowed for single-pass tracing into
                                     padded per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB;
                                     beyond it, or < 0, the walk takes two passes (count, then write) */
@@ -390,15 +390,15 @@ rt_status rt_plan_memory(size_t* bytes);
 rt_status rt_plan_retune(rt_plan* plan, const rt_solve_opts* opts, void* stream);
 
 /* Autotuner.  On the caller's data, one plan is built and re-captured for
- * nine candidate runs; each run varies the walk's lanes per ray (8, 16, 4) and
- * the sweep's schedule and its parameters: spatial with load group 8 and 4;
+ * nine candidate runs; each run varies the walk's lanes per ray (4, 8, 16) and
+ * the sweep's schedule and its parameters: spatial with load group 4 and 8;
  * length-binned persistent with load group 8 at 32 waves per CU and bin edges
  * of 4, 2 and 8 per octave (64, 32 and 128 bins), group 4 at 16 waves per CU
  * (4 per octave, 128 bins) and group 8 at 64 waves per CU (4 per octave, 64
  * bins); direct with group 4 and 8.  The HIP-event stage times (one warm-up,
  * n_runs timed, rt_plan_profile) credit the walk and the sweep separately.
  * The fastest of each goes to *best (other fields from *base, or defaults)
- * unless it beats the library default (spatial, group 8, 8 lanes) by less than
+ * unless it beats the library default (spatial, group 4, 4 lanes) by less than
  * 5%, in which case the default stays; the sum of the chosen stage times goes
  * to *best_ms.  With cache_path, a line "<signature> <schedule> <group>
  * <lanes> <waves_per_cu> <bins> <bins_per_octave> <ms>" is appended, and a

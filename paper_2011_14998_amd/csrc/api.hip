@@ -590,7 +590,7 @@ rt_status rt::fill_solve_launch(const rt_model* m, rt_dirset* set, const int32_t
     a.grid_waves = num_cus() * wpc;
     a.n_xcd = num_xcds();
     if (o.group != 0 && o.group != 4 && o.group != 8) return fail(RT_ERR_ARG, "solve: group must be 4 or 8");
-    a.group = o.group ? o.group : 8;
+    a.group = o.group ? o.group : 4;
     if (o.scheme != RT_SCHEME_FEAUTRIER2 && o.scheme != RT_SCHEME_HERMITE)
         return fail(RT_ERR_ARG, "solve: scheme must be RT_SCHEME_FEAUTRIER2 or RT_SCHEME_HERMITE");
     a.scheme = o.scheme;
@@ -1032,7 +1032,7 @@ static rt_status plan_configure(rt_plan* p, const rt_solve_opts& o) {
     SolveLaunch a = p->base;
     a.u = p->u_buf;
     a.schedule = o.schedule == RT_SCHED_BINNED ? RT_SCHED_BINNED : RT_SCHED_DIRECT;
-    a.group = o.group ? o.group : 8;
+    a.group = o.group ? o.group : 4;
     a.n_bins = opts_bins(o);
     a.bins_per_octave = opts_bins_per_octave(o);
     a.grid_waves = num_cus() * (o.waves_per_cu > 0 ? std::min(o.waves_per_cu, MAX_WAVES_PER_CU) : 32);
@@ -1337,9 +1337,9 @@ static std::string tune_signature(const rt_model* m, const rt_dirset* set, int64
 static rt_status tune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, hipStream_t stream, rt_solve_opts* best,
                            double* best_ms) {
     if (n_runs <= 0) n_runs = 2;
-    const int lanes[3] = {8, 16, 4};
+    const int lanes[3] = {4, 8, 16};
     struct SweepCand { int sc, gr, wpc, bins, bpo; };
-    const SweepCand sw[9] = {{RT_SCHED_SPATIAL, 8, 0, 0, 0},  {RT_SCHED_SPATIAL, 4, 0, 0, 0},
+    const SweepCand sw[9] = {{RT_SCHED_SPATIAL, 4, 0, 0, 0},  {RT_SCHED_SPATIAL, 8, 0, 0, 0},
                              {RT_SCHED_BINNED, 8, 32, 64, 4}, {RT_SCHED_BINNED, 8, 32, 32, 2},
                              {RT_SCHED_BINNED, 4, 16, 128, 4}, {RT_SCHED_DIRECT, 4, 0, 0, 0},
                              {RT_SCHED_BINNED, 8, 32, 128, 8}, {RT_SCHED_BINNED, 8, 64, 64, 4},
@@ -1348,7 +1348,7 @@ static rt_status tune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, hipStrea
     rt_solve_opts o = b0;
     rt_status st = RT_OK;
     double walk_best = 1e300, sweep_best = 1e300, other = 0.0, walk_default = 0.0, sweep_default = 0.0;
-    int lane_best = 8;
+    int lane_best = 4;
     SweepCand sw_best = sw[0];
     for (int i = 0; i < 9 && !st; ++i) {
         o.schedule = sw[i].sc;
@@ -1364,7 +1364,7 @@ static rt_status tune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, hipStrea
         if (!st) st = rt_plan_profile(p, n_runs, ms, stream);
         if (st) break;
         const double walk = ms[0] + ms[2], sweep = ms[3] + ms[4];
-        if (i == 0) {  // the library defaults: spatial schedule, group 8, 8 lanes
+        if (i == 0) {  // the library defaults: spatial schedule, group 4, 4 lanes
             walk_default = walk;
             sweep_default = sweep;
         }
@@ -1387,7 +1387,7 @@ static rt_status tune_plan(rt_plan* p, int32_t n_runs, int32_t verbose, hipStrea
     if (st) return st;
     // keep a default unless a candidate beats it by 5%: choices closer than that swap from box to box
     if (!(walk_best < 0.95 * walk_default)) {
-        lane_best = 8;
+        lane_best = 4;
         walk_best = walk_default;
     }
     if (!(sweep_best < 0.95 * sweep_default)) {
@@ -1449,8 +1449,8 @@ extern "C" rt_status rt_autotune(const rt_model* m, const rt_dirset* set, const 
     rt_plan* p = nullptr;
     rt_solve_opts o = b0;
     o.schedule = RT_SCHED_SPATIAL;
-    o.group = 8;
-    o.trace_lanes = 8;
+    o.group = 4;
+    o.trace_lanes = 4;
     rt_status st = rt_plan_create(m, set, origins, n_origins, chi, eta, dtype, ld, grid, I_bc, J, &o, stream, &p);
     if (st) return st;
     double bms = 0.0;

@@ -14,8 +14,8 @@
 // 16-byte loads) in CSR order with each row sorted by neighbour id, the ids in
 // a parallel array, and a per-point {row start, degree} table, all built once
 // per model, so a step reads one record per neighbour instead of an index, a
-// position and the next row's offsets; a group of 8 lanes reads a point's whole
-// row (~15 records, ~500 contiguous bytes) per step.  The walk's loads are
+// position and the next row's offsets; the lanes walking a ray (4 by default)
+// read a point's whole row (~15 records, ~500 contiguous bytes) per step.  The walk's loads are
 // limited by the vector memory instructions the L1 path serves per clock, so
 // a record is two loads, and a chosen neighbour's id is read only when its
 // list entry is stored.  The tables of a 50k-point Delaunay mesh (~28 MB)
@@ -526,7 +526,7 @@ static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_
                                int32_t* ids, double* Z, int64_t capacity, const int32_t* order, int gl, hipStream_t s) {
     const int64_t n = n_origins * 2 * R;
     if (n == 0) return hipSuccess;
-    if (gl != 4 && gl != 16) gl = 8;
+    if (gl != 8 && gl != 16) gl = 4;  // 0 and other values: the default, 4 lanes
     int32_t* ew = MODE == TRACE_COUNT ? nullptr : error_word();
     if (gl == 16)
         hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(capped_blocks(blocks_for(n * 16, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,

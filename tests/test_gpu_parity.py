@@ -622,7 +622,7 @@ def test_plan_buffer_cache(rt, wind):
 def test_full_size_plan_sampled_parity(rt, orc, wind):
     """The headline configuration as the benchmark times it: one plan over all 50 000
     wind origins at nside 4, FP32 sweep, library defaults (spatial schedule, load
-    group 8, 8 lanes per ray, exact-slot walk), replayed as a graph.  Sampled origins
+    group 4, 4 lanes per ray, exact-slot walk), replayed as a graph.  Sampled origins
     (the oracle walks and solves them one by one): their ray lists bit-exact, their
     J within 1e-4 of the FP64 oracle on the same FP32 tables."""
     torch = _torch()
