@@ -230,8 +230,11 @@ typedef struct {
                                     padded per-ray slots (longest ray x 12 bytes per ray); 0 = 32 GiB;
                                     beyond it, or < 0, the walk takes two passes (count, then write) */
     int32_t walk;             /* plans: RT_WALK_EXACT (0): every run walks each ray once straight into
-                                 its slot of the lists sized by the count pass at creation; a ray whose
-                                 length then differs from its slot latches RT_ERR_CAPACITY.
+                                 its slot of the lists sized by the count pass at creation (each
+                                 direction's rays taken in windows of 64 nearby origins sorted by the
+                                 lengths that pass found, so the rays of a wave end together; 4 bytes
+                                 per ray of device memory); a ray whose length then differs from its
+                                 slot latches RT_ERR_CAPACITY.
                                  RT_WALK_PADDED: once into padded slots, then scan and compaction.
                                  RT_WALK_TWO_PASS: count, scan, write on every run. */
     double dtau_max;          /* > 0: adaptive optical-depth increments (Section 2.1.2, eq. 2): the

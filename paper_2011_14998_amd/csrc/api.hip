@@ -777,6 +777,9 @@ struct rt_plan {
     double* pZ = nullptr;
     // spatial schedule: origin order (Morton), built on first use
     int32_t* order = nullptr;
+    // exact-slot walks: per direction, windows of that order sorted by ray length (from the
+    // creation-time count pass); null when it could not be allocated
+    int32_t* walk_order = nullptr;
     // the sweep's per-pair orders ([R][n_origins]; uniform sets), built on first use of the spatial
     // schedule over the segments below (one by default: the model's bounding sphere)
     int32_t* pair_order = nullptr;
@@ -806,7 +809,7 @@ static hipError_t plan_enqueue(rt_plan* p, hipStream_t s, hipEvent_t* ev = nullp
     if (p->exact) {  // one walk straight into the creation-time slots
         if (e == hipSuccess)
             e = launch_trace_write(p->m, p->origins, p->n_origins, p->set->R, p->set->d_dirs(), per, p->ray_off,
-                                   p->ids, p->Z, p->total, s, p->order, p->o.trace_lanes);
+                                   p->ids, p->Z, p->total, s, p->order, p->o.trace_lanes, p->walk_order);
         mark(1);
         mark(2);
     } else {
@@ -850,7 +853,7 @@ static void plan_free(rt_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     for (void* q : {(void*)p->lens, (void*)p->ray_off, p->scan_ws, p->solve_ws, (void*)p->order, p->bin_buf,
-                    (void*)p->pair_order})
+                    (void*)p->pair_order, (void*)p->walk_order})
         if (q) (void)hipFree(q);
     const int dev = p->m->device;
     pool_free(p->ids, p->ids_bytes, dev);
@@ -1171,6 +1174,16 @@ rt_status rt::plan_create_ordered(const rt_model* m, rt_dirset* set, const int32
     if (e == hipSuccess) e = pool_alloc((void**)&p->ids, p->ids_bytes);
     if (e == hipSuccess) e = pool_alloc((void**)&p->Z, p->Z_bytes);
     p->exact = p->o.walk == RT_WALK_EXACT;
+    // the exact walk's ray order: each direction's windows of the origin order sorted by ray length
+    // (a schedule only: without it the walk takes the origin order itself)
+    if (e == hipSuccess && p->exact && p->order && p->n_rays > 0) {
+        if (hipMalloc((void**)&p->walk_order, sizeof(int32_t) * (size_t)p->n_rays) == hipSuccess) {
+            e = launch_length_order(p->lens, p->order, n_origins, set->R, p->walk_order, s);
+        } else {
+            (void)hipGetLastError();
+            p->walk_order = nullptr;
+        }
+    }
     // Longest ray: the padded single-pass walk is used when its slots fit the budget.
     int32_t longest = 0;
     if (e == hipSuccess && p->n_rays > 0 && p->o.walk == RT_WALK_PADDED) {

@@ -119,17 +119,26 @@ hipError_t launch_check_model(const rt_model* m, int32_t* bad, hipStream_t s);
 size_t build_nbr_workspace(int64_t P);
 hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, const int32_t* lay, void* ws, hipStream_t s);
 // `order` (optional): spatially sorted permutation of origin positions; the
-// rays are then walked direction-major in that origin order.
+// rays are then walked direction-major in that origin order.  gl: lanes per
+// ray, 4, 8 or 16 (anything else: 4).  `ray_order` (optional, n_rays origin
+// positions from launch_length_order): the write walk takes the rays of each
+// direction in that order instead.
 hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
-                              const int32_t* order = nullptr, int gl = 8);
+                              const int32_t* order = nullptr, int gl = 0);
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
                               double* Z, int64_t capacity, hipStream_t s, const int32_t* order = nullptr,
-                              int gl = 8);
+                              int gl = 0, const int32_t* ray_order = nullptr);
 hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
-                               int64_t cap, hipStream_t s, const int32_t* order = nullptr, int gl = 8);
+                               int64_t cap, hipStream_t s, const int32_t* order = nullptr, int gl = 0);
+// Per direction, windows of 64 consecutive positions of `order` (n_origins
+// origin positions) re-sorted by the length of their ray (lens in slot order
+// o * 2R + slot, from a count pass), ties in the given order: out[d * n_origins
+// + k], n_origins * 2R entries, for launch_trace_write's ray_order.
+hipError_t launch_length_order(const int32_t* lens, const int32_t* order, int64_t n_origins, int64_t R,
+                               int32_t* out, hipStream_t s);
 hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
                           int32_t* ids, double* Z, hipStream_t s);
 size_t scan_workspace(int64_t n);

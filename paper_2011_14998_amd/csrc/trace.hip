@@ -208,8 +208,11 @@ __device__ inline int group_min_i(int v) {
 // Work order.  Without `order`, ray L is slot L (origin-major).  With `order`
 // (a permutation of origin positions, spatially sorted) ray L is direction
 // L / n_origins of origin order[L % n_origins]: concurrent waves walk nearby
-// origins in the same direction and share most of the rows they read.  Blocks
-// are renumbered so that each XCD (own L2) gets a contiguous range of rays.
+// origins in the same direction and share most of the rows they read.  With
+// `ray_order` (n_rays origin positions, from k_length_order) ray L is direction
+// L / n_origins of origin ray_order[L]: the same windows of nearby origins,
+// their rays taken in order of length.  Blocks are renumbered so that each XCD
+// (own L2) gets a contiguous range of rays.
 template <int MODE, int GL>
 __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
@@ -220,7 +223,8 @@ __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const do
                                                         int32_t* __restrict__ lens, const int64_t* __restrict__ ray_off,
                                                         int32_t* __restrict__ ids, double* __restrict__ Zout,
                                                         int64_t capacity, int32_t* __restrict__ err,
-                                                        const int32_t* __restrict__ order, int n_xcd) {
+                                                        const int32_t* __restrict__ order,
+                                                        const int32_t* __restrict__ ray_order, int n_xcd) {
     static_assert(GL == 4 || GL == 8 || GL == 16, "4, 8 or 16 lanes per ray");
     constexpr int U = 32 / GL;  // candidates per lane per pass: a whole row of up to 32 in one round of loads
     const int sub = threadIdx.x & (GL - 1);
@@ -231,7 +235,10 @@ __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const do
     const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
     if (L >= n_rays) continue;  // whole groups leave together
     int64_t oi, rr;
-    if (order) {
+    if (ray_order) {
+        rr = L / n_origins;
+        oi = ray_order[L];
+    } else if (order) {
         const int64_t dslot = L / n_origins;
         oi = order[L - dslot * n_origins];
         rr = dslot;
@@ -523,7 +530,8 @@ hipError_t launch_build_nbr(const rt_model* m, const int32_t* key, const int32_t
 template <int MODE>
 static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, const int64_t* ray_off,
-                               int32_t* ids, double* Z, int64_t capacity, const int32_t* order, int gl, hipStream_t s) {
+                               int32_t* ids, double* Z, int64_t capacity, const int32_t* order,
+                               const int32_t* ray_order, int gl, hipStream_t s) {
     const int64_t n = n_origins * 2 * R;
     if (n == 0) return hipSuccess;
     if (gl != 8 && gl != 16) gl = 4;  // 0 and other values: the default, 4 lanes
@@ -531,15 +539,15 @@ static hipError_t trace_launch(const rt_model* m, const int32_t* origins, int64_
     if (gl == 16)
         hipLaunchKernelGGL((k_trace<MODE, 16>), dim3(capped_blocks(blocks_for(n * 16, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
-                           capacity, ew, order, num_xcds());
+                           capacity, ew, order, ray_order, num_xcds());
     else if (gl == 8)
         hipLaunchKernelGGL((k_trace<MODE, 8>), dim3(capped_blocks(blocks_for(n * 8, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
-                           capacity, ew, order, num_xcds());
+                           capacity, ew, order, ray_order, num_xcds());
     else
         hipLaunchKernelGGL((k_trace<MODE, 4>), dim3(capped_blocks(blocks_for(n * 4, TRACE_BLOCK))), dim3(TRACE_BLOCK), 0, s, m->pos,
                            m->rows, m->nbr, m->nid, m->P, origins, n_origins, R, dirs, per_origin, lens, ray_off, ids, Z,
-                           capacity, ew, order, num_xcds());
+                           capacity, ew, order, ray_order, num_xcds());
     return hipGetLastError();
 }
 
@@ -547,21 +555,80 @@ hipError_t launch_trace_count(const rt_model* m, const int32_t* origins, int64_t
                               const double* dirs, int per_origin, int32_t* lens, hipStream_t s,
                               const int32_t* order, int gl) {
     return trace_launch<TRACE_COUNT>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, nullptr, nullptr, 0,
-                                     order, gl, s);
+                                     order, nullptr, gl, s);
 }
 
 hipError_t launch_trace_write(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                               const double* dirs, int per_origin, const int64_t* ray_off, int32_t* ids,
-                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order, int gl) {
+                              double* Z, int64_t capacity, hipStream_t s, const int32_t* order, int gl,
+                              const int32_t* ray_order) {
     return trace_launch<TRACE_WRITE>(m, origins, n_origins, R, dirs, per_origin, nullptr, ray_off, ids, Z, capacity,
-                                     order, gl, s);
+                                     order, ray_order, gl, s);
 }
 
 hipError_t launch_trace_padded(const rt_model* m, const int32_t* origins, int64_t n_origins, int64_t R,
                                const double* dirs, int per_origin, int32_t* lens, int32_t* pids, double* pZ,
                                int64_t cap, hipStream_t s, const int32_t* order, int gl) {
     return trace_launch<TRACE_PADDED>(m, origins, n_origins, R, dirs, per_origin, lens, nullptr, pids, pZ, cap, order,
-                                      gl, s);
+                                      nullptr, gl, s);
+}
+
+// For every direction slot d, the windows of LEN_WINDOW consecutive positions
+// of `order` re-sorted by the length of their ray d (ties keep the given order;
+// a bitonic sort of 32-bit keys (length << 8 | position in window) in LDS).
+// out[d * n_o + k] is an origin position.  Rays walked by one wave then end at
+// nearly the same step instead of the wave running until its longest ray ends,
+// while each window stays a compact group of nearby origins.
+constexpr int LEN_WINDOW = 64;
+
+__global__ __launch_bounds__(LEN_WINDOW) void k_length_order(const int32_t* __restrict__ lens,
+                                                             const int32_t* __restrict__ order, int64_t n_o,
+                                                             int64_t two_r, int32_t* __restrict__ out) {
+    __shared__ uint32_t sk[LEN_WINDOW];
+    __shared__ int32_t so[LEN_WINDOW];
+    const int t = threadIdx.x;
+    const int64_t n_win = (n_o + LEN_WINDOW - 1) / LEN_WINDOW;
+    for (int64_t w = blockIdx.x; w < n_win * two_r; w += gridDim.x) {
+        const int64_t d = w / n_win;
+        const int64_t k = (w - d * n_win) * LEN_WINDOW + t;
+        uint32_t key = 0xFFFFFFFFu;  // past the end: sorts last
+        int32_t oi = 0;
+        if (k < n_o) {
+            oi = order[k];
+            const int32_t len = lens[(int64_t)oi * two_r + d];
+            const uint32_t lc = len <= 0 ? 0u : (len >= 0xFFFFFE ? 0xFFFFFEu : (uint32_t)len);
+            key = (lc << 8) | (uint32_t)t;
+        }
+        sk[t] = key;
+        so[t] = oi;
+        __syncthreads();
+        for (int size = 2; size <= LEN_WINDOW; size <<= 1)
+            for (int j = size >> 1; j > 0; j >>= 1) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const uint32_t a = sk[t], b = sk[u];
+                    if ((a > b) == ((t & size) == 0)) {
+                        sk[t] = b;
+                        sk[u] = a;
+                        const int32_t x = so[t];
+                        so[t] = so[u];
+                        so[u] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        if (k < n_o) out[d * n_o + k] = so[t];
+        __syncthreads();  // the next window reuses the tables
+    }
+}
+
+hipError_t launch_length_order(const int32_t* lens, const int32_t* order, int64_t n_origins, int64_t R,
+                               int32_t* out, hipStream_t s) {
+    const int64_t n_win = (n_origins + LEN_WINDOW - 1) / LEN_WINDOW;
+    if (n_win == 0 || R == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_length_order, dim3(capped_blocks(n_win * 2 * R)), dim3(LEN_WINDOW), 0, s, lens, order,
+                       n_origins, 2 * R, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_compact(const int32_t* pids, const double* pZ, int64_t cap, const int64_t* ray_off, int64_t n_rays,
