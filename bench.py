@@ -422,7 +422,8 @@ def run_batch(args, rt, torch, dev):
                    "ray_list_entries": total, "mean_line_length": (total + P_tot * R) / (P_tot * R),
                    "plan_options": opts, "autotune": tuned,
                    "timed_step": "one replay of the batch's HIP graph: table gather into the union, walk of every "
-                                 "ray into its slot (slots from the count pass and scan at creation), sweep ("
+                                 "ray into its slot (slots from the count pass and scan at creation, rays in "
+                                 "windows of 64 origins ordered by length), sweep ("
                                  + SCHEDULE_NAMES[opts["schedule"]] + "), J reduction, J scatter to the 64 models"},
         "roofline": roof,
         "roofline_walk": _roofline_walk("sph_batch", stages,
@@ -442,8 +443,8 @@ def run_batch(args, rt, torch, dev):
         cold = time.perf_counter() - t0
         rt.release_cached_memory()
         rec["cold_call"] = {"s": cold, "what": "rt_compute_J_batched from scratch: union built on the device, "
-                                               "Morton order of every model, count pass, scan, allocation of the "
-                                               "lists, graph capture, one run, destruction"}
+                                               "Morton order of every model, count pass, scan, length order, "
+                                               "allocation of the lists, graph capture, one run, destruction"}
     return rec, ms_, ds
 
 
@@ -500,7 +501,8 @@ def run_plan_workload(args, rt, torch, dev):
                    "dtau_max": args.dtau_max, "dv_max": args.dv_max, "scheme": args.scheme, "autotune": tuned,
                    "frequency_chunks_per_pair": (Fw + 63) // 64,
                    "timed_step": "one replay of the plan's HIP graph: walk of every ray into its slot (slots from "
-                                 "the count pass and scan at creation), sweep (" + SCHEDULE_NAMES[opts["schedule"]]
+                                 "the count pass and scan at creation, rays in windows of 64 origins ordered by "
+                                 "length), sweep (" + SCHEDULE_NAMES[opts["schedule"]]
                                  + "), J reduction"},
         "roofline": _roofline(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages, alg, dev),
         "roofline_walk": _roofline_walk(args.workload if nside == 4 else args.workload + f"_nside{nside}", stages,
