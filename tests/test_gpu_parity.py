@@ -320,6 +320,45 @@ def test_plan_graph_replays(rt, orc, wind, schedule, walk, padded, lanes, group)
     rt.sync_status()
 
 
+@pytest.fixture(scope="module")
+def sph_cloud():
+    return synth.sph_cloud_model(seed=402, P=12_000)
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_exact_walk_length_order_lists(rt, orc, sph_cloud, lanes):
+    """The exact-slot walk takes each direction's rays in windows of 64 origins ordered by the
+    lengths of the creation-time count: on an SPH-like cloud (rays from none to ~70 entries
+    long, mean ~23), with 777 seeded origins (twelve full windows and a
+    partial one), the plan's lists equal the oracle's walk bit for bit at every lane count,
+    and J equals the same plan walked in two passes (which takes the origins in Morton order)."""
+    torch = _torch()
+    m = sph_cloud
+    rng = np.random.default_rng(31)
+    origins = np.sort(rng.choice(m.P, 777, replace=False)).astype(np.int32)
+    model = _gpu_model(rt, m)
+    ds = rt.DirSet.uniform(2)
+    c32, e32, _, _ = synth.to_fp32_tables(m.chi, m.eta)
+    chi, eta = _t(c32), _t(e32)
+    I_bc = _t(m.I_bc, torch.float64)
+    org = _t(origins)
+    Js = {}
+    for walk in (rt.WALK_EXACT, rt.WALK_TWO_PASS):
+        Js[walk] = torch.empty((len(origins), m.F), dtype=torch.float32, device="cuda")
+        plan = rt.Plan(model, ds, chi, eta, m.freq.len, m.freq.dx, I_bc, Js[walk], origins=org,
+                       precision=rt.RT_F32, schedule=rt.SCHED_SPATIAL, trace_lanes=lanes, walk=walk)
+        plan.run(use_graph=True)
+        rt.sync_status()
+        if walk == rt.WALK_EXACT:
+            _, dirs, _ = orc.dirset_uniform(2)
+            e = orc.trace_all(m, dirs, origins)
+            lens = np.diff(e[0])
+            assert lens.min() == 0 and lens.max() > 2.5 * lens.mean()  # the lengths the order sorts differ widely
+            _assert_rays_equal(plan.rays(), e)
+        del plan
+    assert np.array_equal(Js[rt.WALK_EXACT].cpu().numpy(), Js[rt.WALK_TWO_PASS].cpu().numpy())
+
+
 def test_trace_write_flags_mismatched_offsets(rt, wind):
     """Writing at offsets that do not match the walk (here: every slot one entry too long)
     latches a capacity error instead of leaving the mismatch unnoticed."""
