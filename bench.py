@@ -19,7 +19,7 @@ whole path from scratch (union build, Morton order, count pass, scan,
 allocation, graph capture, one run) -- is timed once beside it.
 
 Prints one JSON line: the metric, the rooflines of the sweep and the walk (measured
-DRAM traffic from the committed rocprofv3 counters, and the algorithmic byte count
+L2-miss traffic (Infinity Cache or HBM) from the committed rocprofv3 counters, and the algorithmic byte count
 beside it), the other workloads' numbers, and the CPU oracle on a seeded sample.
 """
 from __future__ import annotations
@@ -51,7 +51,7 @@ TUNED = {
 
 
 SCHEDULE_NAMES = {0: "direct launch in slot order", 1: "length-binned persistent launch",
-                  2: "direct launch direction by direction over Morton-ordered origins, XCD-contiguous"}
+                  2: "direct launch direction by direction over Morton-ordered origins, runs of 16 workgroups per XCD"}
 
 
 def _log(msg):
@@ -309,7 +309,8 @@ def _roofline(workload, stages, alg, dev):
     sweep_s = stages["sweep"] * 1e-3
     r = {"kernel": "feautrier sweep", "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "achieved": None, "frac": None, "traffic": traffic, "sweep_ms": stages["sweep"],
-         "measured": ("DRAM-side bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (calibrated by a "
+         "measured": ("L2-to-fabric bytes per launch (the Infinity Cache or HBM serves them; an upper bound on HBM "
+                      "bytes) from rocprofv3 FETCH_SIZE + WRITE_SIZE (calibrated by a "
                       "1 GiB copy) in " + os.path.relpath(path, ROOT)) if path else None}
     if traffic:
         r["achieved"] = traffic / sweep_s / 1e9
@@ -321,8 +322,8 @@ def _roofline(workload, stages, alg, dev):
                                  "that reads them, plus the u rows; re-reads served by L2 and the Infinity Cache "
                                  "count too, so this fraction can exceed 1"}
     r["copy_ceiling_gbs"] = copy_ceiling_gbs(dev)
-    r["note"] = ("frac is the DRAM fraction, not the sweep's limit: the caches serve most of its table reads (the "
-                 "algorithmic fraction exceeds 1) and it is held by VALU issue and the latency of L2-served loads")
+    r["note"] = ("frac is the L2-miss fraction of 8 TB/s, not the sweep's limit: the caches serve most of its table "
+                 "reads (the algorithmic fraction exceeds 1) and it is held by VALU issue and the latency of L2-served loads")
     return r
 
 
@@ -331,7 +332,7 @@ def _roofline_walk(workload, stages, alg):
     walk_s = stages["walk"] * 1e-3
     r = {"kernel": "walk", "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "achieved": None, "frac": None,
          "traffic": traffic, "walk_ms": stages["walk"],
-         "measured": ("DRAM-side bytes per launch from the same rocprofv3 session in " + os.path.relpath(path, ROOT))
+         "measured": ("L2-to-fabric bytes per launch from the same rocprofv3 session in " + os.path.relpath(path, ROOT))
          if path else None}
     if traffic:
         r["achieved"] = traffic / walk_s / 1e9

@@ -37,14 +37,22 @@ inline unsigned capped_blocks(int64_t n_blocks) {
 }
 
 // Workgroups are dispatched to the XCDs round-robin (workgroup b runs on XCD
-// b mod n).  This renumbering gives XCD x the contiguous range of logical
-// blocks [start_x, start_x + count_x), a bijection of [0, nb), so work that is
-// adjacent in the logical order shares an L2.
-__device__ inline int64_t xcd_block(int64_t b, int64_t nb, int n) {
+// b mod n).  This renumbering gives each XCD runs of XCD_RUN consecutive
+// logical blocks, the runs of the n XCDs side by side: logical blocks
+// [k n R, (k+1) n R) are run k of every XCD (XCD x takes [k n R + x R, k n R +
+// (x+1) R), R = XCD_RUN).  Work adjacent in the logical order then shares an
+// L2 within a run, while all XCDs work on one stretch of the logical order at a
+// time, so what they read together also stays small in the Infinity Cache that
+// they share (one contiguous range per XCD made the walk of the 64-cloud batch
+// 14% slower).  A bijection of [0, G) for any grid size G: the blocks past the
+// last whole group of n runs keep their own number.
+constexpr int64_t XCD_RUN = 16;
+__device__ inline int64_t xcd_block(int64_t b, int64_t G, int n) {
     if (n <= 1) return b;
-    const int64_t q = nb / n, rem = nb % n;
+    const int64_t span = (int64_t)n * XCD_RUN, full = G / span * span;
+    if (b >= full) return b;
     const int64_t x = b % n, i = b / n;
-    return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+    return (i / XCD_RUN) * span + x * XCD_RUN + (i % XCD_RUN);
 }
 
 // ---------------------------------------------------------------- HEALPix (host)

@@ -212,7 +212,8 @@ __device__ inline int group_min_i(int v) {
 // `ray_order` (n_rays origin positions, from k_length_order) ray L is direction
 // L / n_origins of origin ray_order[L]: the same windows of nearby origins,
 // their rays taken in order of length.  Blocks are renumbered so that each XCD
-// (own L2) gets a contiguous range of rays.
+// (own L2) takes runs of 16 consecutive blocks, the XCDs' runs side by side
+// (xcd_block).
 template <int MODE, int GL>
 __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
