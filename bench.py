@@ -51,7 +51,7 @@ TUNED = {
 
 
 SCHEDULE_NAMES = {0: "direct launch in slot order", 1: "length-binned persistent launch",
-                  2: "direct launch direction by direction over Morton-ordered origins, runs of 16 workgroups per XCD"}
+                  2: "direct launch direction by direction over Morton-ordered origins, XCD runs of 16 (walk) and 256 (sweep) workgroups"}
 
 
 def _log(msg):

@@ -211,7 +211,7 @@ typedef struct {
                                  slot order; RT_SCHED_BINNED: persistent waves draining a length-binned
                                  queue, longest lines first, 16 items per queue atomic (plans: the
                                  origins' Morton order inside each bin); RT_SCHED_SPATIAL (plans only): sweep items
-                                 direction by direction, each XCD taking runs of 16 consecutive
+                                 direction by direction, each XCD taking runs of 256 consecutive
                                  workgroups (the XCDs' runs side by side), with a uniform
                                  set each pair's items in that pair's line order (origins sorted by the
                                  2D Morton code of their position across the pair's direction, then

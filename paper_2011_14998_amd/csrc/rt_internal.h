@@ -37,22 +37,25 @@ inline unsigned capped_blocks(int64_t n_blocks) {
 }
 
 // Workgroups are dispatched to the XCDs round-robin (workgroup b runs on XCD
-// b mod n).  This renumbering gives each XCD runs of XCD_RUN consecutive
-// logical blocks, the runs of the n XCDs side by side: logical blocks
-// [k n R, (k+1) n R) are run k of every XCD (XCD x takes [k n R + x R, k n R +
-// (x+1) R), R = XCD_RUN).  Work adjacent in the logical order then shares an
-// L2 within a run, while all XCDs work on one stretch of the logical order at a
-// time, so what they read together also stays small in the Infinity Cache that
-// they share (one contiguous range per XCD made the walk of the 64-cloud batch
-// 14% slower).  A bijection of [0, G) for any grid size G: the blocks past the
-// last whole group of n runs keep their own number.
-constexpr int64_t XCD_RUN = 16;
-__device__ inline int64_t xcd_block(int64_t b, int64_t G, int n) {
+// b mod n).  This renumbering gives each XCD runs of R consecutive logical
+// blocks, the runs of the n XCDs side by side: logical blocks [k n R, (k+1) n R)
+// are run k of every XCD (XCD x takes [k n R + x R, k n R + (x+1) R)).  Work
+// adjacent in the logical order then shares an L2 within a run, while all XCDs
+// work on one stretch of the logical order at a time, so what they read
+// together also stays small in the Infinity Cache that they share (one
+// contiguous range per XCD made the walk of the 64-cloud batch 14% slower).  A
+// bijection of [0, G) for any grid size G: the blocks past the last whole
+// group of n runs keep their own number.  Run lengths: the walk 16 workgroups
+// (16 windows of 64 origins), the sweep 256 (1024 items); measured on the batch
+// and the octree.
+constexpr int64_t XCD_RUN_WALK = 16;
+constexpr int64_t XCD_RUN_SWEEP = 256;
+__device__ inline int64_t xcd_block(int64_t b, int64_t G, int n, int64_t R) {
     if (n <= 1) return b;
-    const int64_t span = (int64_t)n * XCD_RUN, full = G / span * span;
+    const int64_t span = (int64_t)n * R, full = G / span * span;
     if (b >= full) return b;
     const int64_t x = b % n, i = b / n;
-    return (i / XCD_RUN) * span + x * XCD_RUN + (i % XCD_RUN);
+    return (i / R) * span + x * R + (i % R);
 }
 
 // ---------------------------------------------------------------- HEALPix (host)

@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(SOLVE_BLOCK, (solve_direct_waves<T, UDX, GROUP, REF
     const int nfc = (a.F + 63) / 64;
     const int64_t n_items = a.n_origins * a.R * nfc;
     const int64_t nb = (n_items + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.n_xcd); blk < nb; blk += gridDim.x) {
+    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.n_xcd, XCD_RUN_SWEEP); blk < nb; blk += gridDim.x) {
         const int64_t it = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
         if (it >= n_items) continue;
         int64_t w;

@@ -213,7 +213,7 @@ __device__ inline int group_min_i(int v) {
 // L / n_origins of origin ray_order[L]: the same windows of nearby origins,
 // their rays taken in order of length.  Blocks are renumbered so that each XCD
 // (own L2) takes runs of 16 consecutive blocks, the XCDs' runs side by side
-// (xcd_block).
+// (xcd_block, XCD_RUN_WALK).
 template <int MODE, int GL>
 __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const double* __restrict__ pos,
                                                         const int2* __restrict__ rows,
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(TRACE_BLOCK, GL == 4 ? 4 : 1) void k_trace(const do
     const int64_t two_r = 2 * R;
     const int64_t n_rays = n_origins * two_r;
     const int64_t nb = (n_rays * GL + blockDim.x - 1) / blockDim.x;  // logical blocks
-    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd); blk < nb; blk += gridDim.x) {
+    for (int64_t blk = xcd_block(blockIdx.x, gridDim.x, n_xcd, XCD_RUN_WALK); blk < nb; blk += gridDim.x) {
     const int64_t L = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
     if (L >= n_rays) continue;  // whole groups leave together
     int64_t oi, rr;
