@@ -1064,11 +1064,16 @@ __device__ inline void solve_item(const SolveLaunch& a, int64_t w, int nfc, int 
 // 8 waves share a SIMD and hide more of the table loads' latency (on the 64-cloud batch
 // 396 ms against 407 at the 7 waves its registers would otherwise allow); its packed
 // half-wave variant fits 80 (6 waves, two spilled; the 507k-leaf octree 747 ms against
-// 762 with groups of 8 at 4 waves).  The others keep the compiler's choice (held to 64
-// registers they spill heavily).
+// 762 with groups of 8 at 4 waves).  The refined sweeps take the bounds below; the
+// others keep the compiler's choice (held to 64 registers they spill heavily).
 template <typename T, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
 constexpr int solve_direct_waves() {
-    return (sizeof(T) == 4 && UDX && GROUP == 4 && !REF && SCH == 0) ? (PACK ? 6 : 8) : 1;
+    if (!UDX || GROUP != 4) return 1;
+    // refined lines (measured on the 50k wind at dtau_max = 1, spills 0): FP32 second-order rows at 5 waves
+    // (39.7 -> 38.6 ms; 6 waves 47.1), fourth-order at 4 (70.8 -> 59.6 ms), FP64 at 3 (78.9 -> 59.1 and
+    // 113.5 -> 94.2 ms); the plain FP64 sweep keeps the compiler's choice (43.3 ms against 44.4 at 5 waves)
+    if (REF) return sizeof(T) == 4 ? (SCH == 0 ? 5 : 4) : 3;
+    return (sizeof(T) == 4 && SCH == 0) ? (PACK ? 6 : 8) : 1;
 }
 
 template <typename T, bool MOVING, bool UDX, int GROUP, bool REF, int SCH, bool PACK>
