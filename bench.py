@@ -527,7 +527,7 @@ def main():
                     help="sph_batch: 64 SPH-like clouds in one batch (default, --batch-scale 1: 4.1M particles); "
                          "wind: the 50k-point wind at nside 4; octree: ~500k-leaf AMR-like cloud, 2x48 "
                          "frequencies; octree_reduced: the same field with ~50k leaves; closure: the learned "
-                         "closure trained on winds of seeds 500-503 and judged on 510-511 against the plain "
+                         "closure trained on winds of seeds 500-503 and tested on 510-511 against the plain "
                          "nside-8 solve (--closure-points each); precision: the FP32 sweep's error against the "
                          "FP64 oracle, model by model; directions: adaptive (l 1..4) against regular nside-16 "
                          "directions on the AMR-like cloud")
@@ -867,7 +867,7 @@ def _mem_line(torch, rt) -> str:
 
 
 def run_closure(args):
-    """Learned closure vs the plain nside-8 solve: label, train, judge; one JSON line."""
+    """Learned closure vs the plain nside-8 solve: label, train, test; one JSON line."""
     import math
     from concurrent.futures import ProcessPoolExecutor, as_completed
 

@@ -202,13 +202,13 @@ def error_summary(J, J_ref, flagged_mask: Optional[np.ndarray], F: int) -> dict:
     return out
 
 
-# ---------------------------------------------------------------- experiment: train on some models, judge on others
+# ---------------------------------------------------------------- experiment: train on some models, test on others
 
 @dataclass
 class Labelled:
     dm: DeviceModel
     coarse: SolveResult    # nside 1
-    fine: SolveResult      # nside 8 (the label, and the plain method the closure is judged against)
+    fine: SolveResult      # nside 8 (the label, and the plain method the closure is compared with)
 
 
 def label(dm: DeviceModel, coarse_set, fine_set, verbose: bool = False) -> Labelled:

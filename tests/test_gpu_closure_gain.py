@@ -3,7 +3,7 @@ over the coarse solve alone, that its predicted deviation ranks its errors, and
 the fallback rule's two limits.
 
 Training and test models use different seeds.  The plain nside-8 solve is the
-judge.  Bound 0 (every point falls back) must reproduce the plain solve bit for
+reference.  Bound 0 (every point falls back) must reproduce the plain solve bit for
 bit; an infinite bound must leave every point to the network.
 """
 import math
