@@ -288,6 +288,8 @@ def evaluate(net: ClosureNet, lab: Labelled, coarse_set, fine_set, flag_fraction
         del res
     out["closure"] = runs
     if e_net is not None:
+        if verbose:
+            print(f"  [{dm.name}] fallback fraction for the target median ...", flush=True)
         out["fallback_for_target"] = fallback_curve(e_net, sd, runs, lab.fine.ms)
     return out
 
@@ -302,21 +304,36 @@ def fallback_curve(e_net, sd, runs, plain_ms, target: float = 1e-3) -> dict:
     P, F = e_net.shape
     order = np.argsort(-sd, kind="stable")
     qs = np.linspace(0.0, 1.0, 201)
-    med, med_unflagged = [], []
-    for q in qs:
-        k = int(round(q * P))
-        e = e_net.copy()
-        e[order[:k]] = 0.0
-        med.append(float(np.median(e)))
-        rest = e_net[order[k:]]
-        med_unflagged.append(float(np.median(rest)) if rest.size else 0.0)
-    med = np.array(med)
-    hit = np.nonzero(med <= target)[0]
-    q_star = float(qs[hit[0]]) if hit.size else None
+    med = {}
+
+    def median_at(i):  # the median over every (point, frequency) with the first round(q_i P) points fallen back
+        if i not in med:
+            e = e_net.copy()
+            e[order[:int(round(qs[i] * P))]] = 0.0
+            med[i] = float(np.median(e))
+        return med[i]
+
+    # A fallen-back entry becomes 0, at or below every error, so no order statistic rises with q and
+    # the median is non-increasing along the grid: the first grid point reaching the target is found
+    # by bisection instead of evaluating all 201 (each median runs over P F values).
+    hit = None
+    if median_at(len(qs) - 1) <= target:
+        lo, hi = 0, len(qs) - 1
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if median_at(mid) <= target:
+                hi = mid
+            else:
+                lo = mid + 1
+        hit = lo
+    q_star = float(qs[hit]) if hit is not None else None
+    med_unflagged = None
+    if hit is not None:
+        rest = e_net[order[int(round(qs[hit] * P)):]]
+        med_unflagged = float(np.median(rest)) if rest.size else 0.0
     pts = sorted((r["flagged_fraction"], r["total_ms"]) for r in runs)
     t_star = float(np.interp(q_star, [p for p, _ in pts], [t for _, t in pts])) if q_star is not None else None
-    return dict(target=target, fraction=q_star,
-                median_unflagged_at_fraction=med_unflagged[int(hit[0])] if hit.size else None,
+    return dict(target=target, fraction=q_star, median_unflagged_at_fraction=med_unflagged,
                 closure_ms_interpolated=t_star, plain_ms=plain_ms,
                 speedup_vs_plain=plain_ms / t_star if t_star else None,
-                curve={f"{q:.2f}": m for q, m in zip(qs[::10], med[::10])})
+                curve={f"{qs[i]:.2f}": median_at(i) for i in range(0, len(qs), 10)})
